@@ -1,0 +1,131 @@
+"""Gaussian-Polynomial Approximation of the bilateral filter (Sec. 2-3), in
+float64.
+
+Two independent evaluations of the same filter are given:
+
+* ``gpa_pairwise`` evaluates eq. (GPA) directly: eq. (BF) with the range
+  kernel replaced by the Gaussian-polynomial of eq. (GaussPolynomial),
+  pair by pair, O(W^2 N) per pixel.  The arguments of phi_N are
+  (t, tau) = (h(i-j), h(i)) on the centred image h = f - c (Sec. 2:
+  t = f(i-j), tau = f(i); Sec. 3, eq. shift: the intensities are centred
+  before the expansion, and the centre is added back at the end).
+* ``gpa_alg2`` follows Algorithm 2 (Sec. 3) step by step: the N+1
+  auxiliary images F_n = exp(-h^2/2 sigma_r^2) (h/sigma_r)^n of
+  eq. (intImg) are produced recursively, each is filtered with the spatial
+  kernel (eq. spatialFiltering), and the numerator P and denominator Q of
+  eqs. (P), (Q) are accumulated with the recursively updated G_n/n!.
+
+Appendix B shows the two agree in exact arithmetic; the tests pin that.
+"Order N" is the number of Taylor terms n = 0..N-1 of eq. (approx), so
+Algorithm 2 performs N+1 spatial filterings (of F_0..F_N).
+
+Border: zero extension of the auxiliary images (equivalently, Omega is
+truncated to the image in eq. BF / eq. GPA), as in ``oracle.bf``.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+
+def phi(t: np.ndarray, tau: np.ndarray, sigma_r: float, N: int) -> np.ndarray:
+    """Gaussian-polynomial phi_{N, sigma_r}(t, tau), eq. (GaussPolynomial):
+    exp(-(t^2 + tau^2) / (2 sigma_r^2)) * sum_{n=0}^{N-1} (tau t / sigma_r^2)^n / n!"""
+    t = np.asarray(t, dtype=np.float64)
+    tau = np.asarray(tau, dtype=np.float64)
+    s = tau * t / (sigma_r * sigma_r)
+    term = np.ones(np.broadcast(t, tau).shape)
+    acc = np.zeros_like(term)
+    for n in range(N):
+        if n > 0:
+            term = term * s / n
+        acc = acc + term
+    return np.exp(-(t * t + tau * tau) / (2.0 * sigma_r * sigma_r)) * acc
+
+
+def kernel_error(t, tau, sigma_r: float, N: int) -> np.ndarray:
+    """E_{N, sigma_r}(t, tau) = g(t - tau) - phi_N(t, tau), eq. (error)."""
+    t = np.asarray(t, dtype=np.float64)
+    tau = np.asarray(tau, dtype=np.float64)
+    g = np.exp(-((t - tau) ** 2) / (2.0 * sigma_r * sigma_r))
+    return g - phi(t, tau, sigma_r, N)
+
+
+def gpa_pairwise(f: np.ndarray, w2: np.ndarray, sigma_r: float, N: int,
+                 center: float) -> np.ndarray:
+    """eq. (GPA) on the centred image h = f - center, plus center (Prop. centering)."""
+    h = np.asarray(f, dtype=np.float64) - center
+    H, Wd = h.shape
+    W = w2.shape[0] // 2
+    num = np.zeros_like(h)
+    den = np.zeros_like(h)
+    pad = np.zeros((H + 2 * W, Wd + 2 * W))
+    valid = np.zeros_like(pad)
+    pad[W:W + H, W:W + Wd] = h
+    valid[W:W + H, W:W + Wd] = 1.0
+    for a in range(-W, W + 1):
+        for b in range(-W, W + 1):
+            sh = pad[W - a:W - a + H, W - b:W - b + Wd]
+            ok = valid[W - a:W - a + H, W - b:W - b + Wd]
+            k = w2[W + a, W + b] * phi(sh, h, sigma_r, N) * ok
+            num += k * sh
+            den += k
+    return num / den + center
+
+
+def gpa_pairwise_at(f: np.ndarray, pixels: np.ndarray, w2: np.ndarray,
+                    sigma_r: float, N: int, center: float) -> np.ndarray:
+    """eq. (GPA) at the listed (row, col) pixels only."""
+    h = np.asarray(f, dtype=np.float64) - center
+    H, Wd = h.shape
+    W = w2.shape[0] // 2
+    out = np.empty(len(pixels))
+    for m, (r, c) in enumerate(pixels):
+        r0, r1 = max(0, r - W), min(H, r + W + 1)
+        c0, c1 = max(0, c - W), min(Wd, c + W + 1)
+        win = h[r0:r1, c0:c1]
+        wj = w2[W + r - np.arange(r0, r1)][:, W + c - np.arange(c0, c1)]
+        k = wj * phi(win, h[r, c], sigma_r, N)
+        out[m] = (k * win).sum() / k.sum() + center
+    return out
+
+
+def spatial_filter(F: np.ndarray, w1: np.ndarray) -> np.ndarray:
+    """F_bar(i) = sum_{j in Omega} w(j) F(i - j), eq. (spatialFiltering), for
+    the separable kernel w(a, b) = w1(a) w1(b), with F zero outside the image."""
+    F = np.asarray(F, dtype=np.float64)
+    W = len(w1) // 2
+    H, Wd = F.shape
+    tmp = np.zeros_like(F)
+    for a in range(-W, W + 1):          # rows: tmp(r, c) = sum_a w1(a) F(r - a, c)
+        lo, hi = max(0, a), min(H, H + a)
+        tmp[lo:hi, :] += w1[W + a] * F[lo - a:hi - a, :]
+    out = np.zeros_like(F)
+    for b in range(-W, W + 1):          # cols: out(r, c) = sum_b w1(b) tmp(r, c - b)
+        lo, hi = max(0, b), min(Wd, Wd + b)
+        out[:, lo:hi] += w1[W + b] * tmp[:, lo - b:hi - b]
+    return out
+
+
+def gpa_alg2(f: np.ndarray, w1: np.ndarray, sigma_r: float, N: int, T: float,
+             return_pq: bool = False):
+    """Algorithm 2 (Sec. 3) in float64.  T is the centre of the dynamic range
+    [0, 2T] (the paper centres with t_c = T)."""
+    f = np.asarray(f, dtype=np.float64)
+    # initialisation loop over pixels
+    h = f - T
+    F = np.exp(-(h * h) / (2.0 * sigma_r * sigma_r))
+    G = np.ones_like(f)
+    P = np.zeros_like(f)
+    Q = np.zeros_like(f)
+    Hh = h / sigma_r
+    Fbar = spatial_filter(F, w1)
+    for n in range(1, N + 1):
+        Q = Q + G * Fbar
+        F = Hh * F
+        Fbar = spatial_filter(F, w1)
+        P = P + G * Fbar
+        G = Hh * G / n
+    out = sigma_r * (P / Q) + T
+    if return_pq:
+        return out, P, Q
+    return out

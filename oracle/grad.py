@@ -1,0 +1,99 @@
+"""Reference gradients of the GPA output, in float64.
+
+The paper does not differentiate the filter; these are test references for
+the adjoint the HIP library adds.  For a loss L with upstream gradient
+gbar = dL/d(out), the quantities checked are the vector-Jacobian products
+
+    dL/df (per pixel),   dL/d sigma_r,   dL/d sigma_s (Gaussian kernel only),
+
+with N and the support W held fixed.
+
+* ``vjp_autograd`` builds the GPA of Algorithm 2 (Sec. 3) from plain torch
+  CPU float64 operations (the separable zero-padded spatial filter is a
+  pair of 1-D convolutions) and lets torch.autograd differentiate it.
+* ``vjp_fd`` takes central finite differences of L = sum(gbar * out) with
+  the numpy Algorithm 2 of ``oracle.gpa`` (a separate code path).
+"""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+from . import gpa as _gpa
+from . import kernels as _k
+
+
+def _taps_torch(kind: str, sigma_s, W: int):
+    a = torch.arange(-W, W + 1, dtype=torch.float64)
+    if kind == _k.BOX:
+        return torch.ones_like(a)
+    return torch.exp(-(a * a) / (2.0 * sigma_s * sigma_s))
+
+
+def _filter_torch(F: torch.Tensor, w1: torch.Tensor) -> torch.Tensor:
+    W = (w1.numel() - 1) // 2
+    x = F[None, None]
+    x = torch.nn.functional.conv2d(x, w1.view(1, 1, -1, 1), padding=(W, 0))
+    x = torch.nn.functional.conv2d(x, w1.view(1, 1, 1, -1), padding=(0, W))
+    return x[0, 0]
+
+
+def gpa_torch(f: torch.Tensor, sigma_r: torch.Tensor, sigma_s, kind: str, W: int,
+              N: int, T: float) -> torch.Tensor:
+    """Algorithm 2 (Sec. 3) in differentiable torch float64."""
+    w1 = _taps_torch(kind, sigma_s, W)
+    h = f - T
+    F = torch.exp(-(h * h) / (2.0 * sigma_r * sigma_r))
+    G = torch.ones_like(f)
+    P = torch.zeros_like(f)
+    Q = torch.zeros_like(f)
+    Hh = h / sigma_r
+    Fbar = _filter_torch(F, w1)
+    for n in range(1, N + 1):
+        Q = Q + G * Fbar
+        F = Hh * F
+        Fbar = _filter_torch(F, w1)
+        P = P + G * Fbar
+        G = Hh * G / n
+    return sigma_r * (P / Q) + T
+
+
+def vjp_autograd(f: np.ndarray, gbar: np.ndarray, kind: str, sigma_s, W: int,
+                 sigma_r: float, N: int, T: float):
+    """(dL/df, dL/dsigma_r, dL/dsigma_s) by float64 autograd; dsigma_s is NaN for box."""
+    ft = torch.tensor(np.asarray(f, np.float64), requires_grad=True)
+    sr = torch.tensor(float(sigma_r), dtype=torch.float64, requires_grad=True)
+    ss = None
+    if kind == _k.GAUSS:
+        ss = torch.tensor(float(sigma_s), dtype=torch.float64, requires_grad=True)
+    out = gpa_torch(ft, sr, ss, kind, W, N, T)
+    L = (out * torch.tensor(np.asarray(gbar, np.float64))).sum()
+    inputs = [ft, sr] + ([ss] if ss is not None else [])
+    grads = torch.autograd.grad(L, inputs)
+    dss = float(grads[2]) if ss is not None else float("nan")
+    return grads[0].numpy(), float(grads[1]), dss
+
+
+def _loss_np(f, gbar, kind, sigma_s, W, sigma_r, N, T):
+    w1 = _k.taps1d(kind, sigma_s, W)
+    return float((np.asarray(gbar) * _gpa.gpa_alg2(f, w1, sigma_r, N, T)).sum())
+
+
+def vjp_fd(f: np.ndarray, gbar: np.ndarray, kind: str, sigma_s, W: int,
+           sigma_r: float, N: int, T: float, pixels, h: float = 1e-3):
+    """Central differences (step h) of L = sum(gbar * out) with respect to
+    f at the listed pixels, sigma_r, and sigma_s (Gaussian; W fixed)."""
+    f = np.asarray(f, np.float64)
+    args = (kind, sigma_s, W, sigma_r, N, T)
+    df = []
+    for (r, c) in pixels:
+        fp = f.copy(); fp[r, c] += h
+        fm = f.copy(); fm[r, c] -= h
+        df.append((_loss_np(fp, gbar, *args) - _loss_np(fm, gbar, *args)) / (2 * h))
+    dsr = (_loss_np(f, gbar, kind, sigma_s, W, sigma_r + h, N, T)
+           - _loss_np(f, gbar, kind, sigma_s, W, sigma_r - h, N, T)) / (2 * h)
+    dss = float("nan")
+    if kind == _k.GAUSS:
+        dss = (_loss_np(f, gbar, kind, sigma_s + h, W, sigma_r, N, T)
+               - _loss_np(f, gbar, kind, sigma_s - h, W, sigma_r, N, T)) / (2 * h)
+    return np.array(df), dsr, dss

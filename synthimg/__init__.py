@@ -1,0 +1,106 @@
+"""Seeded synthetic inputs shared by the HIP path's tests and the CPU oracle.
+
+The paper evaluates on a set of eight 512x512 8-bit grayscale photographs
+(Sec. 4, Fig. "dataset"); that set is not available here, so every workload
+is synthetic.  This module only draws pixels and per-image parameters: it
+holds none of the bilateral-filter arithmetic, and neither the oracle nor
+the product package is imported from here.
+
+Generators
+----------
+gen1(H, W, seed)
+    Piecewise-constant 16x16 blocks with levels ~ U[0, 255], plus i.i.d.
+    Gaussian noise of standard deviation 20, clipped to [0, 255] (float64).
+    Draw order with ``numpy.random.default_rng(seed)``: block levels first,
+    then the noise field.
+gen2(H, W, seed)
+    gen1 plus a smooth ramp 40*sin(2*pi*(i/H + j/W)) added to the blocks
+    before the noise, then clipped.
+batch_params(count, seed)
+    Per-image sizes and filter parameters of the uneven batch workload:
+    width ~ U{64..1024}, height ~ U{64..768}, sigma_s ~ U[2, 15],
+    sigma_r ~ U[10, 60].
+clean_blocks(H, W, seed)
+    The noise-free block image that gen1(H, W, seed) starts from (the
+    regression target of the differentiable workload).
+
+Seeds: workload k, image b uses ``seed = 1000*k + b``.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+BLOCK = 16
+NOISE_SD = 20.0
+RAMP_AMPLITUDE = 40.0
+
+
+def _levels(rng: np.random.Generator, H: int, W: int) -> np.ndarray:
+    gh = -(-H // BLOCK)
+    gw = -(-W // BLOCK)
+    lv = rng.uniform(0.0, 255.0, size=(gh, gw))
+    return np.kron(lv, np.ones((BLOCK, BLOCK)))[:H, :W]
+
+
+def clean_blocks(H: int, W: int, seed: int) -> np.ndarray:
+    """Noise-free piecewise-constant image underlying gen1(H, W, seed)."""
+    rng = np.random.default_rng(seed)
+    return _levels(rng, H, W)
+
+
+def gen1(H: int, W: int, seed: int) -> np.ndarray:
+    rng = np.random.default_rng(seed)
+    base = _levels(rng, H, W)
+    noise = rng.normal(0.0, NOISE_SD, size=(H, W))
+    return np.clip(base + noise, 0.0, 255.0)
+
+
+def ramp(H: int, W: int) -> np.ndarray:
+    i = np.arange(H, dtype=np.float64)[:, None]
+    j = np.arange(W, dtype=np.float64)[None, :]
+    return RAMP_AMPLITUDE * np.sin(2.0 * np.pi * (i / H + j / W))
+
+
+def gen2(H: int, W: int, seed: int) -> np.ndarray:
+    rng = np.random.default_rng(seed)
+    base = _levels(rng, H, W) + ramp(H, W)
+    noise = rng.normal(0.0, NOISE_SD, size=(H, W))
+    return np.clip(base + noise, 0.0, 255.0)
+
+
+def batch_params(count: int, seed: int):
+    """List of dicts {height, width, sigma_s, sigma_r, seed} for an uneven batch."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for b in range(count):
+        w = int(rng.integers(64, 1025))
+        h = int(rng.integers(64, 769))
+        ss = float(rng.uniform(2.0, 15.0))
+        sr = float(rng.uniform(10.0, 60.0))
+        out.append(dict(height=h, width=w, sigma_s=ss, sigma_r=sr, seed=seed + 1 + b))
+    return out
+
+
+def sample_pixels(H: int, W: int, count: int, border: int, border_count: int,
+                  seed: int) -> np.ndarray:
+    """Seeded pixel sample used to check full-size results pixel by pixel.
+
+    `count` uniform pixels, `border_count` uniform pixels from the band of
+    width `border` along the image edge, and the four corners; deduplicated,
+    returned as an (M, 2) int64 array of (row, col) in raster order."""
+    rng = np.random.default_rng(seed)
+    mask = np.zeros((H, W), dtype=bool)
+    mask[rng.integers(0, H, size=count), rng.integers(0, W, size=count)] = True
+    b = max(0, min(border, H, W))
+    if b > 0 and border_count > 0:
+        band = np.zeros((H, W), dtype=bool)
+        band[:b, :] = True
+        band[-b:, :] = True
+        band[:, :b] = True
+        band[:, -b:] = True
+        br, bc = np.nonzero(band)
+        pick = rng.integers(0, br.size, size=border_count)
+        mask[br[pick], bc[pick]] = True
+    mask[0, 0] = mask[0, -1] = mask[-1, 0] = mask[-1, -1] = True
+    rr, cc = np.nonzero(mask)
+    return np.stack([rr, cc], axis=1).astype(np.int64)
