@@ -98,11 +98,13 @@ def spatial_filter(F: np.ndarray, w1: np.ndarray) -> np.ndarray:
     tmp = np.zeros_like(F)
     for a in range(-W, W + 1):          # rows: tmp(r, c) = sum_a w1(a) F(r - a, c)
         lo, hi = max(0, a), min(H, H + a)
-        tmp[lo:hi, :] += w1[W + a] * F[lo - a:hi - a, :]
+        if hi > lo:
+            tmp[lo:hi, :] += w1[W + a] * F[lo - a:hi - a, :]
     out = np.zeros_like(F)
     for b in range(-W, W + 1):          # cols: out(r, c) = sum_b w1(b) tmp(r, c - b)
         lo, hi = max(0, b), min(Wd, Wd + b)
-        out[:, lo:hi] += w1[W + b] * tmp[:, lo - b:hi - b]
+        if hi > lo:
+            out[:, lo:hi] += w1[W + b] * tmp[:, lo - b:hi - b]
     return out
 
 

@@ -105,8 +105,10 @@ def test_order_one_closed_form(kind, kw):
     assert np.allclose(G.gpa_alg2(f, K.taps1d(kind, **kw), sr, 1, c), ref, atol=1e-10)
 
 
-def test_spatial_filter_matches_library():
-    f = synthimg.gen2(17, 26, 9)
+@pytest.mark.parametrize("shape", [(17, 26), (3, 3), (1, 9), (8, 1), (1, 1)])
+def test_spatial_filter_matches_library(shape):
+    # includes images smaller than the kernel support (zero extension)
+    f = synthimg.gen2(*shape, 9)
     for kind, kw in KERNELS:
         w1, w2 = K.taps1d(kind, **kw), K.taps2d(kind, **kw)
         assert np.allclose(G.spatial_filter(f, w1), ndimage.correlate(f, w2, mode="constant"), atol=1e-9)
