@@ -1,0 +1,172 @@
+/*
+ * bf_gpa.h -- C ABI of the MI355X (gfx950) implementation of the
+ * Gaussian-Polynomial Approximation (GPA) of the bilateral filter
+ * (Chaudhury & Dabhade, "Fast and Provably Accurate Bilateral Filtering",
+ * arXiv 1603.08109).
+ *
+ * What is computed
+ * ----------------
+ * The bilateral filter of Sec. 1, eq. (BF), with Gaussian range kernel
+ * g(t) = exp(-t^2 / 2 sigma_r^2) (eq. range_kernel) and a box or Gaussian
+ * spatial kernel on Omega = [-W, W]^2 (eqs. spatial_kernel1/2), is replaced
+ * by eq. (GPA): the range kernel becomes the order-N Gaussian-polynomial of
+ * eq. (GaussPolynomial) on intensities centred at `center` (Sec. 3,
+ * eq. shift and Prop. centering).  Algorithm 2 (Sec. 3) evaluates it with
+ * N+1 spatial filterings of the auxiliary images of eq. (intImg) and the
+ * per-pixel ratio of eqs. (P), (Q), (PbyQ).  N is chosen from the requested
+ * accuracy delta via Cor. (eps) and Prop. (LambW) unless given explicitly.
+ *
+ * Conventions
+ * -----------
+ * - Images are single-channel float32, row-major, `height` x `width`, with a
+ *   row pitch given in ELEMENTS (>= width).  All image pointers are DEVICE
+ *   pointers owned by the caller.  Input values are expected in
+ *   [center - T, center + T] (by default [0, 255]); they are not range
+ *   checked on the device.
+ * - Pixels outside the image contribute nothing (the sums of eq. BF / GPA
+ *   run over the part of Omega inside the image).
+ * - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *   Every device call is asynchronous on that stream.
+ * - Return codes: BF_OK (0) on success, a negative BF_E* code on error,
+ *   a positive BF_W* code for a warning (the call still succeeded).
+ *   bf_last_error_message() gives a thread-local description of the last
+ *   non-zero code.  No C++ exception crosses this interface.
+ * - Plans are immutable after bf_plan; a plan owns its device tables and
+ *   its workspace, all allocated inside bf_plan.  bf_forward/bf_backward
+ *   never allocate.  Calls that share one plan must not overlap in time
+ *   (they share the plan's workspace).
+ */
+#ifndef BF_GPA_H
+#define BF_GPA_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define BF_OK               0
+#define BF_EINVAL          -1  /* bad argument */
+#define BF_ENOMEM          -2  /* device or host allocation failed */
+#define BF_EHIP            -3  /* a HIP runtime call failed */
+#define BF_EUNSUPPORTED    -4  /* valid request outside what the build supports */
+#define BF_WNOGUARANTEE     1  /* N below the order that guarantees +-delta */
+
+/* spatial kernel (Sec. 1) */
+#define BF_BOX    0   /* w = 1/|Omega| on [-W, W]^2, eq. spatial_kernel2 */
+#define BF_GAUSS  1   /* w(i) = exp(-|i|^2 / 2 sigma_s^2), eq. spatial_kernel1 */
+
+/* rule that turns delta into N */
+#define BF_NRULE_LAMBERTW  0  /* Cor. eps + Prop. LambW, exact W0 (default) */
+#define BF_NRULE_ALG1      1  /* Algorithm 1 as printed (sigma_r >= 70 -> N = 10) */
+#define BF_NRULE_POISSON   2  /* smallest N whose Poisson tail (Prop. upperBound) <= eps */
+
+/* flags */
+#define BF_FLAG_FP32_ACCUM   1  /* accumulate P and Q in float32 instead of float64 */
+#define BF_FLAG_GRAD         2  /* reserve the workspace bf_backward needs */
+
+typedef struct bf_params {
+  int32_t kernel;    /* BF_BOX or BF_GAUSS */
+  double  sigma_s;   /* Gaussian spatial scale (ignored for box) */
+  int32_t W;         /* half-width of Omega; 0 with BF_GAUSS means ceil(3 sigma_s) */
+  double  sigma_r;   /* range scale, eq. range_kernel */
+  double  T;         /* half dynamic range: inputs in [center-T, center+T]; 0 -> 127.5 */
+  double  center;    /* centring value t_c of eq. shift; NaN -> T */
+  int32_t N;         /* > 0: explicit order; 0: derive from delta */
+  double  delta;     /* requested max |f_BF - f_GPA|; 0 -> 1e-3 */
+  int32_t n_rule;    /* BF_NRULE_* */
+  int32_t height;    /* image size the plan serves */
+  int32_t width;
+  int32_t flags;     /* BF_FLAG_* */
+} bf_params;
+
+typedef struct bf_plan_info {
+  int32_t N;                 /* order: N+1 spatial filterings */
+  int32_t W;                 /* support half-width */
+  double  w0;                /* normalised centre weight w(0) = 1 / sum_Omega w */
+  double  eps;               /* kernel tolerance of Cor. eps */
+  double  lambda;            /* T^2 / sigma_r^2 */
+  double  kernel_bound;      /* Poisson tail at N, Prop. upperBound */
+  double  guaranteed_delta;  /* 2 T bound / (w0 - bound), Prop. accuracy (inf if none) */
+  int32_t tile_rows;         /* tile height the forward kernel uses */
+  int32_t tile_cols;         /* tile width */
+  int64_t workspace_bytes;   /* device bytes owned by the plan */
+} bf_plan_info;
+
+typedef struct bf_plan bf_plan_t;
+typedef struct bf_batch bf_batch_t;
+
+/* Host-only planning: fills `out` from `p` (N, W, w0, eps, bounds) without
+ * touching the device.  Same rules as bf_plan.  Returns BF_OK,
+ * BF_WNOGUARANTEE (explicit N below the bound, or the Algorithm-1 rule
+ * sigma_r >= 70 -> N = 10), or BF_EINVAL / BF_EUNSUPPORTED. */
+int bf_order(const bf_params* p, bf_plan_info* out);
+
+/* Build a plan for one image size and parameter set: validates `p`,
+ * derives W (Sec. 1: W = ceil(3 sigma_s) for the Gaussian), w0, eps
+ * (Cor. eps) and N (Prop. LambW, or as chosen by n_rule), builds the
+ * float64 recursion tables and uploads them, allocates the workspace
+ * (the backward's when BF_FLAG_GRAD is set).  *out receives the plan
+ * (owned by the caller; free with bf_destroy).  Uses the current HIP device. */
+int bf_plan(const bf_params* p, bf_plan_t** out);
+int bf_plan_get_info(const bf_plan_t* plan, bf_plan_info* out);
+int bf_destroy(bf_plan_t* plan);
+
+/* Forward filter, Algorithm 2 (Sec. 3) fused in one kernel launch.
+ *   in      device, height x width float32, row pitch in_pitch (elements)
+ *   out     device, height x width float32, row pitch out_pitch; must not
+ *           alias `in`
+ *   saved   NULL, or device buffer of 3*height*width float32 that receives
+ *           per-pixel state for bf_backward (layout: three planes of
+ *           height*width, dense pitch = width)
+ * Errors: BF_EINVAL for NULL pointers or pitches < width; BF_EHIP if the
+ * launch fails. */
+int bf_forward(const bf_plan_t* plan, const float* in, int64_t in_pitch,
+               float* out, int64_t out_pitch, float* saved, void* stream);
+
+/* Vector-Jacobian product of the forward filter (an extension: the paper
+ * does not differentiate the filter).  With gbar = dL/d(out):
+ *   grad_in     NULL or device float32 image (pitch gin_pitch): dL/d(in)
+ *   grad_sigma  NULL or device double[2]: {dL/d sigma_r, dL/d sigma_s};
+ *               dL/d sigma_s is NaN for the box kernel (W is discrete), and
+ *               W and N are held fixed for the Gaussian one.
+ *   saved       the buffer filled by bf_forward on the same input, or NULL:
+ *               then the forward state is recomputed into the plan's
+ *               workspace (requires BF_FLAG_GRAD at plan time).
+ * The auxiliary images are recomputed, never stored.  Deterministic: the
+ * sigma gradients are reduced in a fixed order. */
+int bf_backward(const bf_plan_t* plan, const float* in, int64_t in_pitch,
+                const float* grad_out, int64_t gout_pitch, const float* saved,
+                float* grad_in, int64_t gin_pitch, double* grad_sigma, void* stream);
+
+/* Batched forward over many images of uneven size, each with its own
+ * parameters (an extension beyond the paper).  bf_batch_plan builds one plan
+ * per image and a work list of tiles ordered by decreasing cost; the
+ * forward runs as ONE persistent kernel launch whose workgroups claim tiles
+ * from a device counter.  The launch sequence is captured in a hipGraph on
+ * the first bf_batch_forward and replayed afterwards.  Image pointer
+ * arrays are host arrays of `count` DEVICE pointers, copied at call time.
+ * Per-image plan problems are reported by bf_batch_status. */
+int bf_batch_plan(int32_t count, const bf_params* per_image, bf_batch_t** out);
+int bf_batch_forward(bf_batch_t* batch, const float* const* in, const int64_t* in_pitch,
+                     float* const* out, const int64_t* out_pitch, void* stream);
+/* Per-image N and status codes (host arrays of `count`, either may be NULL). */
+int bf_batch_status(const bf_batch_t* batch, int32_t* per_image_status, int32_t* per_image_N);
+/* Time the candidate launch shapes for this batch on `stream` (inputs as
+ * for bf_batch_forward) and keep the fastest; the choice is cached in the
+ * file named by BF_TUNE_CACHE (if set), keyed by the batch's shape summary.
+ * *chosen receives the index of the chosen candidate (may be NULL). */
+int bf_batch_tune(bf_batch_t* batch, const float* const* in, const int64_t* in_pitch,
+                  float* const* out, const int64_t* out_pitch, void* stream, int32_t* chosen);
+int bf_batch_destroy(bf_batch_t* batch);
+
+const char* bf_status_string(int status);
+const char* bf_last_error_message(void);
+/* Library version string. */
+const char* bf_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BF_GPA_H */

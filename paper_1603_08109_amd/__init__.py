@@ -1,0 +1,9 @@
+"""MI355X (gfx950) implementation of the Gaussian-Polynomial Approximation of
+the bilateral filter (Chaudhury & Dabhade, arXiv 1603.08109).
+
+The filter runs in hand-written HIP kernels behind the C ABI of
+include/bf_gpa.h (libbfgpa.so, built in-tree by ``build.py``); this package is
+a thin ctypes binding plus a torch.autograd wrapper.
+"""
+from .api import Batch, Plan, PlanInfo, bf_order, version  # noqa: F401
+from .autograd import BilateralGPA  # noqa: F401

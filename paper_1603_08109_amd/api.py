@@ -1,0 +1,200 @@
+"""Python binding of the C ABI: argument marshalling only.
+
+Every step of the filter runs in the HIP library; torch supplies device
+memory and the current stream.  Names follow the C entry points:
+``bf_order``, ``Plan`` (bf_plan / bf_forward / bf_backward / bf_destroy) and
+``Batch`` (bf_batch_plan / bf_batch_forward / bf_batch_tune / ...).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+from dataclasses import dataclass
+
+import torch
+
+from . import _lib as L
+
+_RULES = {"lambertw": L.BF_NRULE_LAMBERTW, "alg1": L.BF_NRULE_ALG1, "poisson": L.BF_NRULE_POISSON}
+_KERNELS = {"box": L.BF_BOX, "gauss": L.BF_GAUSS, "gaussian": L.BF_GAUSS}
+
+
+@dataclass
+class PlanInfo:
+    N: int
+    W: int
+    w0: float
+    eps: float
+    lam: float
+    kernel_bound: float
+    guaranteed_delta: float
+    tile_rows: int
+    tile_cols: int
+    workspace_bytes: int
+    status: int = 0
+
+
+def make_params(kernel: str, sigma_r: float, *, sigma_s: float | None = None, W: int = 0,
+                T: float = 127.5, center: float | None = None, N: int = 0, delta: float = 1e-3,
+                n_rule: str = "lambertw", height: int = 0, width: int = 0,
+                fp32_accum: bool = False, grad: bool = False) -> L.bf_params:
+    p = L.bf_params()
+    p.kernel = _KERNELS[kernel]
+    p.sigma_s = float(sigma_s) if sigma_s is not None else 0.0
+    p.W = int(W)
+    p.sigma_r = float(sigma_r)
+    p.T = float(T)
+    p.center = float("nan") if center is None else float(center)
+    p.N = int(N)
+    p.delta = float(delta)
+    p.n_rule = _RULES[n_rule]
+    p.height = int(height)
+    p.width = int(width)
+    p.flags = (L.BF_FLAG_FP32_ACCUM if fp32_accum else 0) | (L.BF_FLAG_GRAD if grad else 0)
+    return p
+
+
+def _info(i: L.bf_plan_info, status: int = 0) -> PlanInfo:
+    return PlanInfo(i.N, i.W, i.w0, i.eps, i.lambda_, i.kernel_bound, i.guaranteed_delta,
+                    i.tile_rows, i.tile_cols, i.workspace_bytes, status)
+
+
+def bf_order(kernel: str, sigma_r: float, **kw) -> PlanInfo:
+    """Host-only planning (N, W, w0, eps, bounds); no device access."""
+    lib = L.load()
+    p = make_params(kernel, sigma_r, **kw)
+    info = L.bf_plan_info()
+    st = L.check(lib.bf_order(C.byref(p), C.byref(info)), "bf_order")
+    return _info(info, st)
+
+
+def _stream_handle(stream) -> C.c_void_p:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(int(stream.cuda_stream))
+
+
+def _check_image(t: torch.Tensor, H: int, W: int, name: str):
+    if not isinstance(t, torch.Tensor) or t.device.type != "cuda" or t.dtype != torch.float32:
+        raise TypeError(f"{name} must be a float32 CUDA (HIP) tensor")
+    if t.dim() != 2 or t.shape[0] != H or t.shape[1] != W:
+        raise ValueError(f"{name} must have shape ({H}, {W}), got {tuple(t.shape)}")
+    if t.stride(1) != 1:
+        raise ValueError(f"{name} rows must be contiguous")
+
+
+class Plan:
+    """One image size and parameter set (bf_plan)."""
+
+    def __init__(self, kernel: str, sigma_r: float, height: int, width: int, **kw):
+        self._lib = L.load()
+        self.kernel = kernel
+        self.height, self.width = int(height), int(width)
+        self.params = make_params(kernel, sigma_r, height=height, width=width, **kw)
+        h = C.c_void_p()
+        st = L.check(self._lib.bf_plan(C.byref(self.params), C.byref(h)), "bf_plan")
+        self._h = h
+        info = L.bf_plan_info()
+        L.check(self._lib.bf_plan_get_info(self._h, C.byref(info)), "bf_plan_get_info")
+        self.info = _info(info, st)
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            self._lib.bf_destroy(h)
+            self._h = None
+
+    def new_saved(self) -> torch.Tensor:
+        return torch.empty(3 * self.height * self.width, dtype=torch.float32, device="cuda")
+
+    def forward(self, inp: torch.Tensor, out: torch.Tensor | None = None,
+                saved: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+        _check_image(inp, self.height, self.width, "input")
+        if out is None:
+            out = torch.empty_like(inp)
+        _check_image(out, self.height, self.width, "output")
+        sp = C.c_void_p(saved.data_ptr()) if saved is not None else C.c_void_p(0)
+        L.check(self._lib.bf_forward(self._h, C.c_void_p(inp.data_ptr()), inp.stride(0),
+                                     C.c_void_p(out.data_ptr()), out.stride(0), sp,
+                                     _stream_handle(stream)), "bf_forward")
+        return out
+
+    def backward(self, inp: torch.Tensor, grad_out: torch.Tensor, saved: torch.Tensor | None = None,
+                 grad_in: torch.Tensor | None = None, want_sigma: bool = True, stream=None):
+        """Returns (dL/din, tensor([dL/dsigma_r, dL/dsigma_s]) float64 or None)."""
+        _check_image(inp, self.height, self.width, "input")
+        _check_image(grad_out, self.height, self.width, "grad_out")
+        if grad_in is None:
+            grad_in = torch.empty_like(inp)
+        gs = torch.empty(2, dtype=torch.float64, device=inp.device) if want_sigma else None
+        L.check(self._lib.bf_backward(
+            self._h, C.c_void_p(inp.data_ptr()), inp.stride(0), C.c_void_p(grad_out.data_ptr()),
+            grad_out.stride(0), C.c_void_p(saved.data_ptr() if saved is not None else 0),
+            C.c_void_p(grad_in.data_ptr()), grad_in.stride(0),
+            C.c_void_p(gs.data_ptr() if gs is not None else 0), _stream_handle(stream)), "bf_backward")
+        return grad_in, gs
+
+
+class Batch:
+    """Many images of uneven size in one persistent launch (bf_batch_*)."""
+
+    def __init__(self, per_image: list[dict]):
+        self._lib = L.load()
+        self.count = len(per_image)
+        arr = (L.bf_params * self.count)()
+        self.shapes = []
+        for i, d in enumerate(per_image):
+            d = dict(d)
+            kernel = d.pop("kernel")
+            sigma_r = d.pop("sigma_r")
+            arr[i] = make_params(kernel, sigma_r, **d)
+            self.shapes.append((int(d["height"]), int(d["width"])))
+        h = C.c_void_p()
+        self.status = L.check(self._lib.bf_batch_plan(self.count, arr, C.byref(h)), "bf_batch_plan")
+        self._h = h
+        st = (C.c_int32 * self.count)()
+        ns = (C.c_int32 * self.count)()
+        L.check(self._lib.bf_batch_status(self._h, st, ns), "bf_batch_status")
+        self.image_status = list(st)
+        self.N = list(ns)
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            self._lib.bf_batch_destroy(h)
+            self._h = None
+
+    def _arrays(self, inputs, outputs):
+        n = self.count
+        if len(inputs) != n or len(outputs) != n:
+            raise ValueError("one input and one output per image")
+        ip = (C.c_void_p * n)()
+        op = (C.c_void_p * n)()
+        ipt = (C.c_int64 * n)()
+        opt = (C.c_int64 * n)()
+        for i, (a, b) in enumerate(zip(inputs, outputs)):
+            H, W = self.shapes[i]
+            _check_image(a, H, W, f"input[{i}]")
+            _check_image(b, H, W, f"output[{i}]")
+            ip[i], op[i] = a.data_ptr(), b.data_ptr()
+            ipt[i], opt[i] = a.stride(0), b.stride(0)
+        return ip, ipt, op, opt
+
+    def forward(self, inputs, outputs=None, stream=None):
+        if outputs is None:
+            outputs = [torch.empty_like(x) for x in inputs]
+        ip, ipt, op, opt = self._arrays(inputs, outputs)
+        L.check(self._lib.bf_batch_forward(self._h, ip, ipt, op, opt, _stream_handle(stream)),
+                "bf_batch_forward")
+        return outputs
+
+    def tune(self, inputs, outputs, stream=None) -> int:
+        ip, ipt, op, opt = self._arrays(inputs, outputs)
+        ch = C.c_int32(-1)
+        L.check(self._lib.bf_batch_tune(self._h, ip, ipt, op, opt, _stream_handle(stream), C.byref(ch)),
+                "bf_batch_tune")
+        return ch.value
+
+
+def version() -> str:
+    return L.load().bf_version().decode()

@@ -1,0 +1,472 @@
+// Host-side planning and the single-image entry points of the C ABI.
+//
+// Planning follows Sec. 2-3 of the paper:
+//   * support W: given (box) or ceil(3 sigma_s) (Gaussian, Sec. 1);
+//   * w(0) of the kernel normalised to sum 1 over Omega (Prop. accuracy);
+//   * eps = w(0) delta / (2T + delta)                         (Cor. eps);
+//   * N = ceil(q / W0(q e^{-p})), p = 1 + log lambda, q = -lambda - log eps,
+//     lambda = T^2 / sigma_r^2                                 (Prop. LambW),
+//     or Algorithm 1 as printed, or the exact Poisson tail of Prop. upperBound.
+// The float64 tables of the range-safe recursion (see gpa_tables) are built
+// here and uploaded once.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <limits>
+#include <string>
+#include <vector>
+
+#include "bf_internal.h"
+
+namespace bfgpa {
+
+static thread_local std::string g_err;
+
+void set_error(const std::string& msg) { g_err = msg; }
+
+int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+// Principal branch of the Lambert W function on [-1/e, inf): the inverse of
+// w -> w e^w, by Halley iterations from a branch-point / asymptotic start.
+double lambert_w0(double z) {
+  const double em1 = 1.0 / M_E;
+  if (!(z >= -em1)) return std::numeric_limits<double>::quiet_NaN();
+  if (z == 0.0) return 0.0;
+  double w;
+  if (z < -0.25) {
+    double p = std::sqrt(2.0 * (M_E * z + 1.0));
+    w = -1.0 + p - p * p / 3.0 + 11.0 / 72.0 * p * p * p;
+  } else if (z < 3.0) {
+    w = std::log1p(z) * (1.0 - 0.25 * std::log1p(z) / (1.0 + std::log1p(z)));
+  } else {
+    double l1 = std::log(z), l2 = std::log(l1);
+    w = l1 - l2 + l2 / l1;
+  }
+  for (int it = 0; it < 64; ++it) {
+    double ew = std::exp(w);
+    double f = w * ew - z;
+    double wp1 = w + 1.0;
+    if (wp1 == 0.0) break;
+    double den = ew * wp1 - (w + 2.0) * f / (2.0 * wp1);
+    double dw = f / den;
+    w -= dw;
+    if (std::fabs(dw) <= 1e-15 * (1.0 + std::fabs(w))) break;
+  }
+  return w;
+}
+
+// sum_{n >= N} e^{-lam} lam^n / n!  (Prop. upperBound).  Summed directly
+// from the tail side when N > lam (terms then decrease), else as one minus
+// the head (the tail is then at least about one half, so no cancellation).
+double poisson_tail(int N, double lam) {
+  if (N <= 0) return 1.0;
+  if (lam <= 0.0) return 0.0;
+  auto logpmf = [lam](double n) { return -lam + n * std::log(lam) - std::lgamma(n + 1.0); };
+  if ((double)N > lam) {
+    double s = 0.0;
+    for (int n = N; n < N + 100000; ++n) {
+      double t = std::exp(logpmf(n));
+      s += t;
+      if (t <= 1e-18 * s || (t == 0.0 && n > lam)) break;
+    }
+    return s;
+  }
+  double head = 0.0;
+  for (int n = 0; n < N; ++n) head += std::exp(logpmf(n));
+  return std::max(0.0, 1.0 - head);
+}
+
+static int chernoff_order(double lam, double eps) {
+  double p = 1.0 + std::log(lam);
+  double q = -lam - std::log(eps);
+  double w = lambert_w0(q * std::exp(-p));
+  double theta = q / w;
+  return (int)std::ceil(theta - 1e-12);
+}
+
+static int alg1_order(double sigma_r, double eps, double T) {
+  if (sigma_r >= 70.0) return 10;
+  double lam = (T / sigma_r) * (T / sigma_r);
+  double p = 1.0 + std::log(lam);
+  double q = -lam - std::log(eps);
+  double t = q / (M_E * lam);
+  double w = t - t * t + 1.5 * t * t * t - (8.0 / 3.0) * t * t * t * t;
+  double x = q / w;
+  if (sigma_r < 30.0)
+    for (int k = 0; k < 3; ++k) x = x - (x * std::log(x) - p * x - q) / (std::log(x) + 1.0 - p);
+  if (!std::isfinite(x)) return -1;
+  return (int)std::ceil(x - 1e-12);
+}
+
+static int poisson_order(double lam, double eps) {
+  int N = 1;
+  while (poisson_tail(N, lam) > eps && N < 1000000) ++N;
+  return N;
+}
+
+// 1-D kernel factor w1(a), a = -W..W, unnormalised.
+static std::vector<double> taps1d(int kind, double sigma_s, int W) {
+  std::vector<double> t(2 * W + 1);
+  for (int a = -W; a <= W; ++a)
+    t[a + W] = (kind == BF_BOX) ? 1.0 : std::exp(-(double)a * a / (2.0 * sigma_s * sigma_s));
+  return t;
+}
+
+// Fill defaults and check ranges.  Returns BF_OK or a negative code.
+static int normalise(const bf_params* in, bf_params* p) {
+  if (!in) return fail(BF_EINVAL, "params is NULL");
+  *p = *in;
+  if (p->kernel != BF_BOX && p->kernel != BF_GAUSS) return fail(BF_EINVAL, "kernel must be BF_BOX or BF_GAUSS");
+  if (p->kernel == BF_GAUSS) {
+    if (!(p->sigma_s > 0.0) || !std::isfinite(p->sigma_s)) return fail(BF_EINVAL, "sigma_s must be > 0");
+    if (p->W <= 0) p->W = (int)std::ceil(3.0 * p->sigma_s - 1e-12);
+  }
+  if (p->W < 0) return fail(BF_EINVAL, "W must be >= 0");
+  if (!(p->sigma_r > 0.0) || !std::isfinite(p->sigma_r)) return fail(BF_EINVAL, "sigma_r must be > 0");
+  if (p->T == 0.0) p->T = 127.5;
+  if (!(p->T > 0.0) || !std::isfinite(p->T)) return fail(BF_EINVAL, "T must be > 0");
+  if (std::isnan(p->center)) p->center = p->T;
+  if (p->delta == 0.0) p->delta = 1e-3;
+  if (!(p->delta > 0.0)) return fail(BF_EINVAL, "delta must be > 0");
+  if (p->N < 0) return fail(BF_EINVAL, "N must be >= 0");
+  if (p->n_rule < BF_NRULE_LAMBERTW || p->n_rule > BF_NRULE_POISSON) return fail(BF_EINVAL, "unknown n_rule");
+  if (p->height < 0 || p->width < 0) return fail(BF_EINVAL, "height/width must be >= 0");
+  return BF_OK;
+}
+
+// Order and bounds for normalised parameters.
+static int plan_order(const bf_params* p, bf_plan_info* info) {
+  std::memset(info, 0, sizeof(*info));
+  std::vector<double> t = taps1d(p->kernel, p->sigma_s, p->W);
+  double s = 0.0;
+  for (double v : t) s += v;
+  info->W = p->W;
+  info->w0 = (t[p->W] * t[p->W]) / (s * s);
+  info->eps = info->w0 * p->delta / (2.0 * p->T + p->delta);
+  info->lambda = (p->T / p->sigma_r) * (p->T / p->sigma_r);
+  // float32 range: exp(-x^2/2) must stay a normal float for |x| <= T/sigma_r
+  if (info->lambda > 170.0)
+    return fail(BF_EUNSUPPORTED, "sigma_r too small for float32: need T/sigma_r <= 13 (exp(-x^2/2) underflows)");
+  int need = chernoff_order(info->lambda, info->eps);
+  int status = BF_OK;
+  int N;
+  if (p->N > 0) {
+    N = p->N;
+    if (N < need) status = BF_WNOGUARANTEE;
+  } else if (p->n_rule == BF_NRULE_ALG1) {
+    N = alg1_order(p->sigma_r, info->eps, p->T);
+    if (N <= 0) return fail(BF_EUNSUPPORTED, "Algorithm 1 series gives a non-positive order at this eps");
+    if (p->sigma_r >= 70.0 || poisson_tail(N, info->lambda) > info->eps) status = BF_WNOGUARANTEE;
+  } else if (p->n_rule == BF_NRULE_POISSON) {
+    N = poisson_order(info->lambda, info->eps);
+  } else {
+    N = need;
+  }
+  if (N < 1) N = 1;
+  if (N > 4096) return fail(BF_EUNSUPPORTED, "order N above 4096");
+  info->N = N;
+  info->kernel_bound = poisson_tail(N, info->lambda);
+  info->guaranteed_delta = (info->kernel_bound < info->w0)
+      ? 2.0 * p->T * info->kernel_bound / (info->w0 - info->kernel_bound)
+      : std::numeric_limits<double>::infinity();
+  if (status == BF_WNOGUARANTEE) set_error("order below the bound: no +-delta guarantee");
+  return status;
+}
+
+// Tables of the range-safe form of Algorithm 2 (float64, stored float32).
+// With X = T / sigma_r, M_n = max_{|x| <= X} e^{-x^2/2} |x|^n, i.e.
+// (n/e)^{n/2} for n <= X^2 and e^{-X^2/2} X^n beyond; r_n = M_n / M_{n-1}.
+// The kernels keep F~_n = F_n / M_n (|F~_n| <= 1) and the coefficient
+// a_n = e^{-x_i^2/2} x_i^n M_n / n! (|a_n| <= 1); their products equal the
+// terms of eqs. (P), (Q) times e^{-x_i^2/2}, which cancels in P/Q.
+static void gpa_tables(double lam, int N, std::vector<double>& s, std::vector<double>& r,
+                       std::vector<double>& inv) {
+  const double X = std::sqrt(lam);
+  auto logM = [&](int n) -> double {
+    if (n == 0) return 0.0;
+    if ((double)n <= lam) return 0.5 * n * (std::log((double)n) - 1.0);
+    return -0.5 * lam + n * std::log(X);
+  };
+  s.assign(N + 2, 0.0);
+  r.assign(N + 2, 0.0);
+  inv.assign(N + 2, 0.0);
+  for (int n = 1; n <= N + 1; ++n) {
+    r[n] = std::exp(logM(n) - logM(n - 1));
+    s[n] = 1.0 / r[n];
+    inv[n] = 1.0 / n;
+  }
+}
+
+static int choose_forward_tile(int W, int H, int Wd, int* variant, int* TY) {
+  const int nv = forward_variant_count();
+  for (int want : {64, 32, 16, 8, 4}) {
+    for (int v = 0; v < nv; ++v) {
+      Variant vv = forward_variant(v);
+      if (want > 4 * vv.opt) continue;
+      if (region_floats(want, W) > (int64_t)kThreads * vv.mreg) continue;
+      if (forward_lds_bytes(want, W) > max_lds_bytes()) continue;
+      // keep at least ~2 workgroups per CU when the image allows it
+      int64_t tiles = (int64_t)((H + want - 1) / want) * ((Wd + kTileCols - 1) / kTileCols);
+      if (want > 16 && tiles < 512 && H > 0) continue;
+      *variant = v;
+      *TY = want;
+      return BF_OK;
+    }
+  }
+  return fail(BF_EUNSUPPORTED, "support W too large for the fused tile kernels");
+}
+
+static int choose_backward_tile(int W, bool sigs, int* variant, int* TY) {
+  const int nv = backward_variant_count();
+  for (int want : {32, 16, 8, 4}) {
+    for (int v = 0; v < nv; ++v) {
+      Variant vv = backward_variant(v);
+      if (want > 4 * vv.opt) continue;
+      if (region_floats(want, W) > (int64_t)kThreads * vv.mreg) continue;
+      if (backward_lds_bytes(want, W, sigs) + 2 * kThreads * 8 > max_lds_bytes()) continue;
+      *variant = v;
+      *TY = want;
+      return BF_OK;
+    }
+  }
+  return fail(BF_EUNSUPPORTED, "support W too large for the adjoint tile kernels");
+}
+
+static int hip_fail(hipError_t e, const char* what) {
+  return fail(BF_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+}  // namespace bfgpa
+
+using namespace bfgpa;
+
+extern "C" {
+
+const char* bf_version(void) { return "bf_gpa 0.1 (gfx950)"; }
+
+const char* bf_status_string(int status) {
+  switch (status) {
+    case BF_OK: return "ok";
+    case BF_EINVAL: return "invalid argument";
+    case BF_ENOMEM: return "out of memory";
+    case BF_EHIP: return "HIP runtime error";
+    case BF_EUNSUPPORTED: return "unsupported";
+    case BF_WNOGUARANTEE: return "warning: order below the accuracy guarantee";
+    default: return "unknown status";
+  }
+}
+
+const char* bf_last_error_message(void) { return g_err.c_str(); }
+
+int bf_order(const bf_params* in, bf_plan_info* out) {
+  if (!out) return fail(BF_EINVAL, "info is NULL");
+  bf_params p;
+  int st = normalise(in, &p);
+  if (st < 0) return st;
+  st = plan_order(&p, out);
+  if (st < 0) return st;
+  int v, ty;
+  if (p.height > 0 && p.width > 0 && choose_forward_tile(p.W, p.height, p.width, &v, &ty) == BF_OK) {
+    out->tile_rows = ty;
+    out->tile_cols = kTileCols;
+  }
+  return st;
+}
+
+int bf_plan(const bf_params* in, bf_plan_t** out) {
+  if (!out) return fail(BF_EINVAL, "out is NULL");
+  *out = nullptr;
+  bf_params p;
+  int st = normalise(in, &p);
+  if (st < 0) return st;
+  if (p.height <= 0 || p.width <= 0) return fail(BF_EINVAL, "height and width must be > 0");
+  bf_plan_info info;
+  int ost = plan_order(&p, &info);
+  if (ost < 0) return ost;
+  int variant = 0, TY = 0;
+  st = choose_forward_tile(p.W, p.height, p.width, &variant, &TY);
+  if (st < 0) return st;
+  const bool grad = (p.flags & BF_FLAG_GRAD) != 0;
+  const bool sigs = p.kernel == BF_GAUSS;
+  int bvariant = -1, bTY = 0;
+  if (grad) {
+    st = choose_backward_tile(p.W, sigs, &bvariant, &bTY);
+    if (st < 0) return st;
+  }
+
+  bf_plan_t* pl = new (std::nothrow) bf_plan_t();
+  if (!pl) return fail(BF_ENOMEM, "host allocation failed");
+  pl->p = p;
+  pl->info = info;
+  pl->info.tile_rows = TY;
+  pl->info.tile_cols = kTileCols;
+  pl->variant = variant;
+  pl->TY = TY;
+  pl->bvariant = bvariant;
+  pl->bTY = bTY;
+  hipGetDevice(&pl->device);
+
+  // constant tables: s, r, inv (N+2 each), taps and d^2 taps (padded)
+  std::vector<double> s, r, inv;
+  gpa_tables(info.lambda, info.N, s, r, inv);
+  const int N = info.N, W = p.W;
+  const int64_t stride = ((N + 2 + 63) / 64) * 64;
+  const int64_t ntap = 2 * W + 1 + 2 * kTapPad;
+  const int64_t ntapr = ((ntap + 63) / 64) * 64;
+  std::vector<float> h(3 * stride + 2 * ntapr, 0.0f);
+  for (int n = 0; n <= N + 1; ++n) {
+    h[n] = (float)s[n];
+    h[stride + n] = (float)r[n];
+    h[2 * stride + n] = (float)inv[n];
+  }
+  std::vector<double> t = taps1d(p.kernel, p.sigma_s, W);
+  for (int a = -W; a <= W; ++a) {
+    h[3 * stride + kTapPad + a + W] = (float)t[a + W];
+    h[3 * stride + ntapr + kTapPad + a + W] = (float)((double)a * a * t[a + W]);
+  }
+  pl->tab_stride = stride;
+  size_t bytes = h.size() * sizeof(float);
+  hipError_t e = hipMalloc(&pl->d_const, bytes);
+  if (e != hipSuccess) { delete pl; return fail(BF_ENOMEM, "hipMalloc tables failed"); }
+  e = hipMemcpy(pl->d_const, h.data(), bytes, hipMemcpyHostToDevice);
+  if (e != hipSuccess) { hipFree(pl->d_const); delete pl; return hip_fail(e, "hipMemcpy tables"); }
+  int64_t ws = (int64_t)bytes;
+  pl->d_work = nullptr;
+  pl->d_partials = nullptr;
+  pl->ntiles_b = 0;
+  if (grad) {
+    int64_t plane = (int64_t)p.height * p.width;
+    e = hipMalloc(&pl->d_work, 3 * plane * sizeof(float));
+    if (e != hipSuccess) { hipFree(pl->d_const); delete pl; return fail(BF_ENOMEM, "hipMalloc adjoint workspace failed"); }
+    ws += 3 * plane * sizeof(float);
+    pl->ntiles_b = ((p.height + bTY - 1) / bTY) * ((p.width + kTileCols - 1) / kTileCols);
+    e = hipMalloc(&pl->d_partials, 2 * (size_t)pl->ntiles_b * sizeof(double));
+    if (e != hipSuccess) {
+      hipFree(pl->d_work); hipFree(pl->d_const); delete pl;
+      return fail(BF_ENOMEM, "hipMalloc partials failed");
+    }
+    ws += 2 * (int64_t)pl->ntiles_b * sizeof(double);
+  }
+  pl->info.workspace_bytes = ws;
+  *out = pl;
+  if (ost == BF_WNOGUARANTEE) set_error("order below the bound: no +-delta guarantee");
+  return ost;
+}
+
+int bf_plan_get_info(const bf_plan_t* plan, bf_plan_info* out) {
+  if (!plan || !out) return fail(BF_EINVAL, "NULL argument");
+  *out = plan->info;
+  return BF_OK;
+}
+
+int bf_destroy(bf_plan_t* plan) {
+  if (!plan) return BF_OK;
+  int dev = 0;
+  hipGetDevice(&dev);
+  hipSetDevice(plan->device);
+  if (plan->d_const) hipFree(plan->d_const);
+  if (plan->d_work) hipFree(plan->d_work);
+  if (plan->d_partials) hipFree(plan->d_partials);
+  hipSetDevice(dev);
+  delete plan;
+  return BF_OK;
+}
+
+}  // extern "C"
+
+namespace bfgpa {
+static void fill_common(const bf_plan_t* pl, TileParams& tp) {
+  const bf_params& p = pl->p;
+  tp.H = p.height;
+  tp.Wd = p.width;
+  tp.W = p.W;
+  tp.N = pl->info.N;
+  tp.kt = p.kernel;
+  tp.sigma_r = (float)p.sigma_r;
+  tp.inv_sigma_r = (float)(1.0 / p.sigma_r);
+  tp.center = (float)p.center;
+  tp.inv_sigma_s3 = p.kernel == BF_GAUSS ? (float)(1.0 / (p.sigma_s * p.sigma_s * p.sigma_s)) : 0.0f;
+  const int64_t st = pl->tab_stride;
+  tp.s_tab = pl->d_const;
+  tp.r_tab = pl->d_const + st;
+  tp.inv_tab = pl->d_const + 2 * st;
+  const int64_t ntap = 2 * p.W + 1 + 2 * kTapPad;
+  const int64_t ntapr = ((ntap + 63) / 64) * 64;
+  tp.taps = pl->d_const + 3 * st;
+  tp.taps2 = pl->d_const + 3 * st + ntapr;
+  tp.saved_plane = (int64_t)p.height * p.width;
+}
+}  // namespace bfgpa
+
+extern "C" {
+
+int bf_forward(const bf_plan_t* pl, const float* in, int64_t in_pitch, float* out,
+               int64_t out_pitch, float* saved, void* stream) {
+  if (!pl || !in || !out) return fail(BF_EINVAL, "NULL plan or image pointer");
+  if (in_pitch < pl->p.width || out_pitch < pl->p.width) return fail(BF_EINVAL, "pitch smaller than width");
+  if ((const void*)in == (const void*)out) return fail(BF_EINVAL, "in and out must not alias");
+  TileParams tp;
+  std::memset(&tp, 0, sizeof(tp));
+  fill_common(pl, tp);
+  tp.in = in;
+  tp.in_pitch = in_pitch;
+  tp.out = out;
+  tp.out_pitch = out_pitch;
+  tp.saved = saved;
+  tp.TY = pl->TY;
+  tp.tiles_x = (pl->p.width + kTileCols - 1) / kTileCols;
+  const bool acc64 = (pl->p.flags & BF_FLAG_FP32_ACCUM) == 0;
+  hipError_t e = launch_forward(tp, pl->variant, acc64, saved != nullptr, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "forward launch");
+  return BF_OK;
+}
+
+int bf_backward(const bf_plan_t* pl, const float* in, int64_t in_pitch, const float* grad_out,
+                int64_t gout_pitch, const float* saved, float* grad_in, int64_t gin_pitch,
+                double* grad_sigma, void* stream) {
+  if (!pl || !in || !grad_out) return fail(BF_EINVAL, "NULL plan or image pointer");
+  if (!(pl->p.flags & BF_FLAG_GRAD) || pl->bvariant < 0)
+    return fail(BF_EINVAL, "plan was built without BF_FLAG_GRAD");
+  if (in_pitch < pl->p.width || gout_pitch < pl->p.width || (grad_in && gin_pitch < pl->p.width))
+    return fail(BF_EINVAL, "pitch smaller than width");
+  hipStream_t s = (hipStream_t)stream;
+  TileParams tp;
+  std::memset(&tp, 0, sizeof(tp));
+  fill_common(pl, tp);
+  const bool acc64 = (pl->p.flags & BF_FLAG_FP32_ACCUM) == 0;
+  if (!saved) {
+    // recompute the forward state into the plan's workspace
+    TileParams fp = tp;
+    fp.in = in;
+    fp.in_pitch = in_pitch;
+    fp.out = nullptr;
+    fp.out_pitch = 0;
+    fp.saved = pl->d_work;
+    fp.TY = pl->TY;
+    fp.tiles_x = (pl->p.width + kTileCols - 1) / kTileCols;
+    hipError_t e = launch_forward(fp, pl->variant, acc64, true, s);
+    if (e != hipSuccess) return hip_fail(e, "forward (recompute) launch");
+    saved = pl->d_work;
+  }
+  tp.in = in;
+  tp.in_pitch = in_pitch;
+  tp.gout = grad_out;
+  tp.gout_pitch = gout_pitch;
+  tp.saved = const_cast<float*>(saved);
+  tp.out = grad_in;
+  tp.out_pitch = grad_in ? gin_pitch : 0;
+  tp.TY = pl->bTY;
+  tp.tiles_x = (pl->p.width + kTileCols - 1) / kTileCols;
+  const bool sigs = pl->p.kernel == BF_GAUSS && grad_sigma != nullptr;
+  hipError_t e = launch_backward(tp, pl->bvariant, sigs, pl->d_partials, grad_sigma, s);
+  if (e != hipSuccess) return hip_fail(e, "adjoint launch");
+  return BF_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,98 @@
+"""CPU checks of the C ABI: the library loads, exports every entry point the
+header declares, and its host-only planning (bf_order) agrees with the
+oracle's order rules and reports status codes as documented."""
+import math
+import os
+import re
+
+import pytest
+
+from oracle import kernels as K
+from oracle import order as O
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _lib():
+    from paper_1603_08109_amd import _lib as L
+    return L, L.load()
+
+
+def test_exports_every_declared_symbol():
+    L, lib = _lib()
+    header = open(os.path.join(ROOT, "include", "bf_gpa.h")).read()
+    names = set(re.findall(r"^\s*(?:int|const char\*)\s+(bf_\w+)\s*\(", header, re.M))
+    assert {"bf_plan", "bf_forward", "bf_backward", "bf_batch_plan", "bf_batch_forward"} <= names
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(L.SIGNATURES) == names
+
+
+def test_version_and_status_strings():
+    import paper_1603_08109_amd as P
+    L, lib = _lib()
+    assert "gfx950" in P.version()
+    for code in (0, -1, -2, -3, -4, 1):
+        assert lib.bf_status_string(code)
+
+
+@pytest.mark.parametrize("kind,kw", [("box", dict(W=4)), ("box", dict(W=30)),
+                                     ("gauss", dict(sigma_s=3.0)), ("gauss", dict(sigma_s=5.0)),
+                                     ("gauss", dict(sigma_s=25.0))])
+def test_order_matches_oracle(kind, kw):
+    import paper_1603_08109_amd as P
+    w0 = K.w0(kind, **kw)
+    for sr in (10.0, 12.5, 20.0, 30.0, 47.0, 60.0, 90.0):
+        for d in (1e-3, 1e-2, 0.1, 1.0, 3.0):
+            info = P.bf_order(kind, sr, delta=d, **kw)
+            assert info.N == O.order_for_delta(d, w0, 127.5, sr), (sr, d)
+            assert info.w0 == pytest.approx(w0, rel=1e-12)
+            assert info.eps == pytest.approx(O.eps_from_delta(d, w0, 127.5), rel=1e-12)
+            lam = O.lam_of(127.5, sr)
+            assert info.kernel_bound == pytest.approx(O.poisson_tail(info.N, lam), rel=1e-6, abs=1e-300)
+            assert info.guaranteed_delta <= d * (1 + 1e-9)
+
+
+def test_poisson_and_alg1_rules():
+    import paper_1603_08109_amd as P
+    for sr in (15.0, 30.0, 50.0):
+        lam = O.lam_of(127.5, sr)
+        w0 = K.w0("box", W=4)
+        eps = O.eps_from_delta(0.1, w0, 127.5)
+        pi = P.bf_order("box", sr, W=4, delta=0.1, n_rule="poisson")
+        assert pi.N == O.poisson_order(lam, eps)
+        assert pi.N <= P.bf_order("box", sr, W=4, delta=0.1).N
+    a = P.bf_order("box", 80.0, W=4, n_rule="alg1")
+    assert a.N == 10 and a.status == 1  # sigma_r >= 70: no guarantee
+    # Table 1 setting through Algorithm 1 (T = 128, eps = 1e-3 <=> delta with w0 = 1)
+    for sr, n in [(20.0, 67), (30.0, 37), (50.0, 19)]:
+        d = 1e-3 * 2 * 128.0 / (1.0 - 1e-3)
+        got = P.bf_order("box", sr, W=0, T=128.0, delta=d, n_rule="alg1")
+        assert got.N == n
+
+
+def test_status_codes():
+    import paper_1603_08109_amd as P
+    from paper_1603_08109_amd import _lib as L
+    with pytest.raises(L.BFError) as e:
+        P.bf_order("box", -1.0, W=3)
+    assert e.value.code == L.BF_EINVAL
+    with pytest.raises(L.BFError) as e:
+        P.bf_order("box", 30.0, W=-2)
+    assert e.value.code == L.BF_EINVAL
+    with pytest.raises(L.BFError) as e:
+        P.bf_order("gauss", 30.0, sigma_s=0.0)
+    assert e.value.code == L.BF_EINVAL
+    with pytest.raises(L.BFError) as e:
+        P.bf_order("box", 5.0, W=3)          # exp(-x^2/2) would underflow float32
+    assert e.value.code == L.BF_EUNSUPPORTED
+    w = P.bf_order("box", 30.0, W=3, N=5)
+    assert w.status == L.BF_WNOGUARANTEE and w.N == 5
+    assert math.isinf(w.guaranteed_delta) or w.guaranteed_delta > 1e-3
+
+
+def test_gaussian_support_rule():
+    import paper_1603_08109_amd as P
+    for ss, W in [(3.0, 9), (5.0, 15), (25.0, 75), (2.2, 7), (1.0 / 3.0, 1)]:
+        assert P.bf_order("gauss", 30.0, sigma_s=ss).W == W
+    assert P.bf_order("gauss", 30.0, sigma_s=5.0, W=4).W == 4

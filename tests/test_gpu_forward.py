@@ -1,0 +1,161 @@
+"""GPU parity of the fused forward (bf_forward) against the FP64 CPU oracle.
+
+Tolerance: max |GPU - oracle| <= 1e-3 on the 0-255 intensity scale (the
+accuracy target of the workloads), with the oracle evaluated in float64 on
+the float32-rounded input the GPU sees and at the same order N.
+"""
+import numpy as np
+import pytest
+
+import synthimg
+from oracle import bf as B
+from oracle import gpa as G
+from oracle import kernels as K
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-3
+
+
+def _mods():
+    import torch
+    import paper_1603_08109_amd as P
+    assert torch.cuda.is_available()
+    return torch, P
+
+
+def _taps(kind, kw):
+    return K.taps1d(kind, kw.get("sigma_s"), kw.get("W") if kind == "box" else None), \
+        K.taps2d(kind, kw.get("sigma_s"), kw.get("W") if kind == "box" else None)
+
+
+def _gpu_forward(f, kind, sr, **kw):
+    torch, P = _mods()
+    H, Wd = f.shape
+    x = torch.tensor(f, dtype=torch.float32, device="cuda")
+    plan = P.Plan(kind, sr, H, Wd, **kw)
+    out = plan.forward(x)
+    torch.cuda.synchronize()
+    return out.cpu().numpy().astype(np.float64), plan, x.cpu().numpy().astype(np.float64)
+
+
+def _report(name, d):
+    print(f"{name}: max {np.abs(d).max():.3e} rms {np.sqrt(np.mean(d * d)):.3e}", flush=True)
+
+
+CASES = [
+    ("box", dict(W=1), 30.0, (37, 45), 1),
+    ("box", dict(W=5), 20.0, (150, 133), 2),
+    ("box", dict(W=10), 30.0, (100, 200), 3),
+    ("box", dict(W=30), 30.0, (130, 150), 4),
+    ("box", dict(W=5), 10.0, (70, 80), 5),
+    ("gauss", dict(sigma_s=1.0), 30.0, (40, 70), 6),
+    ("gauss", dict(sigma_s=3.0), 30.0, (96, 130), 7),
+    ("gauss", dict(sigma_s=5.0), 40.0, (80, 100), 8),
+    ("gauss", dict(sigma_s=10.0), 50.0, (90, 90), 9),
+    ("gauss", dict(sigma_s=2.0), 12.0, (66, 67), 10),
+]
+
+
+@pytest.mark.parametrize("kind,kw,sr,shape,seed", CASES)
+def test_forward_matches_alg2(kind, kw, sr, shape, seed):
+    f = synthimg.gen2(*shape, seed)
+    out, plan, f32 = _gpu_forward(f, kind, sr, **kw)
+    w1, _ = _taps(kind, kw)
+    ref = G.gpa_alg2(f32, w1, sr, plan.info.N, 127.5)
+    print(f"{kind} {kw} sr={sr} {shape}: N={plan.info.N} tile={plan.info.tile_rows}", flush=True)
+    _report("gpu-alg2", out - ref)
+    assert np.abs(out - ref).max() <= TOL
+
+
+@pytest.mark.parametrize("fp32", [False, True])
+def test_workload1_vs_oracles(fp32):
+    # 256^2 gen1, Gaussian sigma_s = 3 (W = 9), sigma_r = 30, N from delta = 1e-3
+    f = synthimg.gen1(256, 256, 1000)
+    out, plan, f32 = _gpu_forward(f, "gauss", 30.0, sigma_s=3.0, fp32_accum=fp32)
+    assert plan.info.N == 48 and plan.info.W == 9
+    w1, w2 = K.taps1d("gauss", 3.0), K.taps2d("gauss", 3.0)
+    o3 = G.gpa_alg2(f32, w1, 30.0, 48, 127.5)
+    o1 = B.direct_bf(f32, w2, 30.0)
+    _report("gpu-O3", out - o3)
+    _report("gpu-O1", out - o1)
+    assert np.abs(out - o3).max() <= TOL
+    assert np.abs(out - o1).max() <= TOL
+
+
+@pytest.mark.parametrize("kind,kw,sr", [("box", dict(W=5), 20.0), ("box", dict(W=5), 40.0),
+                                        ("gauss", dict(sigma_s=5.0), 20.0),
+                                        ("gauss", dict(sigma_s=5.0), 40.0)])
+def test_workload2_sampled(kind, kw, sr):
+    # 1024^2 gen2 (blocks + ramp + noise): checked pixel by pixel on a sample
+    f = synthimg.gen2(1024, 1024, 2000)
+    out, plan, f32 = _gpu_forward(f, kind, sr, **kw)
+    _, w2 = _taps(kind, kw)
+    W = plan.info.W
+    px = synthimg.sample_pixels(1024, 1024, 1500, W, 500, 2001)
+    o2 = G.gpa_pairwise_at(f32, px, w2, sr, plan.info.N, 127.5)
+    o1 = B.direct_bf_at(f32, px, w2, sr)
+    got = out[px[:, 0], px[:, 1]]
+    print(f"N={plan.info.N} pixels={len(px)}", flush=True)
+    _report("gpu-O2", got - o2)
+    _report("gpu-O1", got - o1)
+    assert np.abs(got - o2).max() <= TOL
+    assert np.abs(got - o1).max() <= TOL
+
+
+@pytest.mark.parametrize("shape", [(1, 1), (1, 200), (200, 1), (3, 3), (5, 64), (64, 5), (65, 129)])
+def test_ragged_and_tiny(shape):
+    f = synthimg.gen1(*shape, 31)
+    for kind, kw in [("box", dict(W=3)), ("gauss", dict(sigma_s=2.0))]:
+        out, plan, f32 = _gpu_forward(f, kind, 25.0, **kw)
+        w1, _ = _taps(kind, kw)
+        ref = G.gpa_alg2(f32, w1, 25.0, plan.info.N, 127.5)
+        assert np.abs(out - ref).max() <= TOL, (kind, shape)
+
+
+def test_support_zero_is_identity():
+    f = synthimg.gen2(50, 70, 41)
+    out, plan, f32 = _gpu_forward(f, "box", 30.0, W=0)
+    assert np.abs(out - f32).max() <= TOL
+
+
+def test_constant_image():
+    f = np.full((77, 91), 203.5)
+    for kind, kw in [("box", dict(W=7)), ("gauss", dict(sigma_s=4.0))]:
+        out, plan, _ = _gpu_forward(f, kind, 30.0, **kw)
+        assert np.abs(out - 203.5).max() <= TOL
+
+
+def test_pitched_buffers():
+    torch, P = _mods()
+    f = synthimg.gen2(90, 100, 51)
+    big_in = torch.zeros(90, 128, dtype=torch.float32, device="cuda")
+    big_in[:, :100] = torch.tensor(f, dtype=torch.float32, device="cuda")
+    big_out = torch.full((90, 160), -7.0, dtype=torch.float32, device="cuda")
+    plan = P.Plan("gauss", 30.0, 90, 100, sigma_s=2.5)
+    plan.forward(big_in[:, :100], out=big_out[:, :100])
+    torch.cuda.synchronize()
+    o = big_out.cpu().numpy().astype(np.float64)
+    ref = G.gpa_alg2(big_in[:, :100].cpu().numpy().astype(np.float64), K.taps1d("gauss", 2.5), 30.0,
+                     plan.info.N, 127.5)
+    assert np.abs(o[:, :100] - ref).max() <= TOL
+    assert np.all(o[:, 100:] == -7.0)  # nothing written past the width
+
+
+def test_deterministic():
+    torch, P = _mods()
+    f = synthimg.gen2(300, 257, 61)
+    x = torch.tensor(f, dtype=torch.float32, device="cuda")
+    plan = P.Plan("box", 30.0, 300, 257, W=9)
+    a = plan.forward(x).clone()
+    b = plan.forward(x)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+
+
+def test_explicit_order_and_rules():
+    torch, P = _mods()
+    f = synthimg.gen1(60, 60, 71)
+    out, plan, f32 = _gpu_forward(f, "box", 30.0, W=4, N=20)
+    assert plan.info.N == 20 and plan.info.status == 1  # BF_WNOGUARANTEE
+    ref = G.gpa_alg2(f32, K.taps1d("box", W=4), 30.0, 20, 127.5)
+    assert np.abs(out - ref).max() <= TOL
