@@ -1,0 +1,255 @@
+"""Throughput benchmark of the GPA bilateral filter on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
+
+Workload (the large-support configuration): one 4096x4096 float32 image
+(synthimg.gen2, seed 3000) filtered with every setting of the sweep
+    Gaussian sigma_s in {3, 10, 25}  x  sigma_r in {10, 30, 50}
+    box W in {10, 30, 75}            x  sigma_r in {10, 30, 50}
+with N from the accuracy bound for delta = 1e-3.  One step = one forward
+pass per setting; `value` = total pixels filtered / total kernel time
+(Mpix/s), inputs resident in HBM.  Also reported: per-setting results, the
+differentiable fwd+bwd workload (32 x 512^2, Gaussian sigma_s = 5,
+sigma_r = 30, N = 49) and the batched workload (256 uneven images, one
+persistent launch) against per-image launches.
+
+The cpu_baseline leg times the FP64 numpy oracle (Algorithm 2) on a
+256x256 crop of the same image for every setting, on this host, and
+reports the GPU's max error against it on that crop.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+# Plain (non-packed) FP32 FMA rate: 256 CUs x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz.
+ALU_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
+
+SWEEP = ([("gauss", dict(sigma_s=s), r) for s in (3.0, 10.0, 25.0) for r in (10.0, 30.0, 50.0)]
+         + [("box", dict(W=w), r) for w in (10, 30, 75) for r in (10.0, 30.0, 50.0)])
+
+
+def setting_name(kind, kw, sr):
+    k = f"sigma_s={kw['sigma_s']:g}" if kind == "gauss" else f"W={kw['W']}"
+    return f"{kind}({k},sigma_r={sr:g})"
+
+
+def alg_flops_per_px_n(kind, W):
+    """Algorithmic flops of Algorithm 2 per pixel per filtering: F <- H F (1),
+    spatial filter (box: two O(1) running sums, 2 adds each = 4; Gaussian:
+    two separable passes of 2W+1 multiply-adds = 4(2W+1)), Q and P updates
+    (2 FMA = 4) and G <- H G / n (2)."""
+    filt = 4.0 if kind == "box" else 4.0 * (2 * W + 1)
+    return 1.0 + filt + 4.0 + 2.0
+
+
+def time_launches(fn, stream, warmup, steps, torch):
+    for _ in range(warmup):
+        fn()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(steps):
+        fn()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps  # ms per launch
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extra", action="store_true", help="skip the fwd+bwd and batch legs")
+    ap.add_argument("--only", default="", help="comma list of sweep indices to run")
+    a = ap.parse_args()
+    if a.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        sys.exit(2)
+
+    import torch
+    import paper_1603_08109_amd as P
+    import synthimg
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    H = Wd = 4096
+    f = synthimg.gen2(H, Wd, 3000)
+    x = torch.tensor(f, dtype=torch.float32, device=dev)
+    out = torch.empty_like(x)
+
+    sweep = list(enumerate(SWEEP))
+    if a.only:
+        keep = {int(i) for i in a.only.split(",")}
+        sweep = [s for s in sweep if s[0] in keep]
+
+    results, skipped = [], []
+    plans = {}
+    for idx, (kind, kw, sr) in sweep:
+        try:
+            plans[idx] = P.Plan(kind, sr, H, Wd, **kw)
+        except Exception as e:  # unsupported support width etc.
+            skipped.append({"setting": setting_name(kind, kw, sr), "reason": str(e).splitlines()[0]})
+    print(f"# bench: {len(plans)} settings on {H}x{Wd}, skipped {len(skipped)}", file=sys.stderr, flush=True)
+
+    torch.cuda.synchronize()
+    total_ms = 0.0
+    total_px = 0.0
+    for idx, (kind, kw, sr) in sweep:
+        if idx not in plans:
+            continue
+        plan = plans[idx]
+        ms = time_launches(lambda: plan.forward(x, out=out), stream, a.warmup, a.steps, torch)
+        N, W = plan.info.N, plan.info.W
+        flops = H * Wd * (N + 1) * alg_flops_per_px_n(kind, W)
+        r = dict(setting=setting_name(kind, kw, sr), N=N, W=W, tile_rows=plan.info.tile_rows,
+                 ms=round(ms, 4), mpix_s=round(H * Wd / ms / 1e3, 1),
+                 alg_tflops=round(flops / ms / 1e9, 2),
+                 hbm_gbs=round(8.0 * H * Wd / ms / 1e6, 1))
+        results.append(r)
+        total_ms += ms
+        total_px += H * Wd
+        print(f"# {r}", file=sys.stderr, flush=True)
+
+    dom = max(results, key=lambda r: r["ms"])
+    dom_kind = "box" if dom["setting"].startswith("box") else "gauss"
+    dom_flops = H * Wd * (dom["N"] + 1) * alg_flops_per_px_n(dom_kind, dom["W"])
+    achieved = dom_flops / (dom["ms"] * 1e-3) / 1e12
+    roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(ALU_PEAK_TFLOPS, 1),
+                "unit": "TFLOP/s", "frac": round(achieved / ALU_PEAK_TFLOPS, 4), "traffic": None,
+                "kernel": "gpa_forward_kernel " + dom["setting"],
+                "hbm_frac": round(dom["hbm_gbs"] / HBM_PEAK_GBS, 5)}
+
+    extra = {}
+    if not a.no_extra:
+        # differentiable workload: 32 x 512^2, Gaussian sigma_s = 5, sigma_r = 30
+        imgs = [torch.tensor(synthimg.gen1(512, 512, 5000 + b), dtype=torch.float32, device=dev)
+                for b in range(32)]
+        tgts = [torch.tensor(synthimg.clean_blocks(512, 512, 5000 + b), dtype=torch.float32, device=dev)
+                for b in range(32)]
+        plan5 = P.Plan("gauss", 30.0, 512, 512, sigma_s=5.0, grad=True)
+        saved = [plan5.new_saved() for _ in range(32)]
+        outs = [torch.empty_like(imgs[0]) for _ in range(32)]
+        gins = [torch.empty_like(imgs[0]) for _ in range(32)]
+        gs = torch.empty(2, dtype=torch.float64, device=dev)
+
+        def fwd_bwd():
+            for b in range(32):
+                plan5.forward(imgs[b], out=outs[b], saved=saved[b])
+                g = (outs[b] - tgts[b]) * (2.0 / outs[b].numel())
+                plan5.backward(imgs[b], g, saved=saved[b], grad_in=gins[b])
+
+        def fwd_only():
+            for b in range(32):
+                plan5.forward(imgs[b], out=outs[b])
+
+        ms_fb = time_launches(fwd_bwd, stream, 1, max(1, a.steps // 2), torch)
+        ms_f = time_launches(fwd_only, stream, 1, max(1, a.steps // 2), torch)
+        px5 = 32 * 512 * 512
+        extra["fwd_bwd"] = {"workload": "32x512^2 gauss(sigma_s=5,sigma_r=30) N=%d, MSE loss" % plan5.info.N,
+                            "ms": round(ms_fb, 3), "mpix_s": round(px5 / ms_fb / 1e3, 1),
+                            "fwd_ms": round(ms_f, 3), "fwd_mpix_s": round(px5 / ms_f / 1e3, 1)}
+        print(f"# fwd_bwd {extra['fwd_bwd']}", file=sys.stderr, flush=True)
+        del imgs, tgts, saved, outs, gins
+
+        # batched workload: 256 uneven images, one persistent launch vs per-image launches
+        specs = synthimg.batch_params(256, 4000)
+        per = [dict(kernel="gauss", sigma_s=s["sigma_s"], sigma_r=s["sigma_r"], height=s["height"],
+                    width=s["width"]) for s in specs]
+        bimgs = [torch.tensor(synthimg.gen2(s["height"], s["width"], s["seed"]), dtype=torch.float32,
+                              device=dev) for s in specs]
+        bouts = [torch.empty_like(t) for t in bimgs]
+        batch = P.Batch(per)
+        chosen = batch.tune(bimgs, bouts)
+        ms_b = time_launches(lambda: batch.forward(bimgs, bouts), stream, 1, a.steps, torch)
+        plans4 = []
+        for s in per:
+            d = dict(s)
+            plans4.append(P.Plan(d.pop("kernel"), d.pop("sigma_r"), **d))
+
+        def per_image():
+            for pl, i, o in zip(plans4, bimgs, bouts):
+                pl.forward(i, out=o)
+
+        ms_p = time_launches(per_image, stream, 1, a.steps, torch)
+        bpx = sum(s["height"] * s["width"] for s in specs)
+        extra["batch"] = {"workload": "256 gen2 images 64..1024 x 64..768, gauss sigma_s U[2,15], "
+                                      "sigma_r U[10,60]", "mpx": round(bpx / 1e6, 2),
+                          "batched_ms": round(ms_b, 3), "per_image_ms": round(ms_p, 3),
+                          "batched_mpix_s": round(bpx / ms_b / 1e3, 1),
+                          "speedup": round(ms_p / ms_b, 3), "tuned_candidate": chosen}
+        print(f"# batch {extra['batch']}", file=sys.stderr, flush=True)
+        del bimgs, bouts, batch, plans4
+
+    cpu = None
+    if not a.no_cpu_baseline:
+        from oracle import gpa as G
+        from oracle import kernels as K
+        crop = 256
+        fc = x[:crop, :crop].double().cpu().numpy()
+        t_cpu = 0.0
+        n_set = 0
+        worst = 0.0
+        for idx, (kind, kw, sr) in sweep:
+            if idx not in plans:
+                continue
+            plan = plans[idx]
+            sub = P.Plan(kind, sr, crop, crop, **kw)
+            gpu_crop = sub.forward(x[:crop, :crop].contiguous())
+            w1 = K.taps1d(kind, kw.get("sigma_s"), kw.get("W"))
+            t0 = time.perf_counter()
+            ref = G.gpa_alg2(fc, w1, sr, plan.info.N, 127.5)
+            t_cpu += time.perf_counter() - t0
+            n_set += 1
+            torch.cuda.synchronize()
+            worst = max(worst, float(np.abs(gpu_crop.cpu().numpy().astype(np.float64) - ref).max()))
+        cpu = {"value": round(n_set * crop * crop / t_cpu / 1e6, 4), "unit": "Mpix/s", "cores": 1,
+               "kind": "oracle",
+               "sample": f"numpy float64 Algorithm 2 on the {crop}x{crop} top-left crop, each of the "
+                         f"{n_set} settings once ({t_cpu:.1f} s)",
+               "gpu_max_err_on_sample": worst}
+        print(f"# cpu {cpu}", file=sys.stderr, flush=True)
+
+    value = total_px / (total_ms * 1e-3) / 1e6
+    line = {
+        "metric": "Mpix/s (fwd, fwd+bwd) at max err <=1e-3 vs FP64 oracle; % HBM roofline",
+        "value": round(value, 1),
+        "unit": "Mpix/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": round(total_ms, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "4096x4096 float32 gen2; forward over the sweep gauss sigma_s{3,10,25} "
+                               "x box W{10,30,75} x sigma_r{10,30,50}, N from delta=1e-3",
+                   "settings_run": len(results), "settings_skipped": skipped,
+                   "accumulation": "float64 P/Q"},
+        "per_setting": results,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    line.update(extra)
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()
