@@ -65,6 +65,9 @@ extern "C" {
 /* flags */
 #define BF_FLAG_FP32_ACCUM   1  /* accumulate P and Q in float32 instead of float64 */
 #define BF_FLAG_GRAD         2  /* reserve the workspace bf_backward needs */
+#define BF_FLAG_STREAMED     4  /* run the orders in blocks through device memory (the
+                                   path taken automatically when W is too wide for the
+                                   fused on-chip tiles); allocates about 64 bytes per pixel */
 
 typedef struct bf_params {
   int32_t kernel;    /* BF_BOX or BF_GAUSS */

@@ -29,6 +29,7 @@ BF_NRULE_POISSON = 2
 
 BF_FLAG_FP32_ACCUM = 1
 BF_FLAG_GRAD = 2
+BF_FLAG_STREAMED = 4
 
 
 class bf_params(C.Structure):

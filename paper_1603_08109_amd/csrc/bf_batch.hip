@@ -22,7 +22,7 @@
 
 namespace bfgpa {
 
-template <int OPT, int MREG, typename Acc>
+template <int OPT, int MREG, bool ACC64>
 __global__ __launch_bounds__(kThreads) void gpa_batch_kernel(const TileParams* __restrict__ params,
                                                              const BatchTile* __restrict__ tiles,
                                                              int ntiles, int* counter) {
@@ -37,9 +37,9 @@ __global__ __launch_bounds__(kThreads) void gpa_batch_kernel(const TileParams* _
     const BatchTile bt = tiles[idx];
     const TileParams p = params[bt.image];
     if (p.kt == BF_BOX)
-      forward_tile<BF_BOX, OPT, MREG, Acc, false>(p, bt.r0, bt.c0, lds);
+      forward_tile<BF_BOX, OPT, MREG, ACC64, false>(p, bt.r0, bt.c0, lds);
     else
-      forward_tile<BF_GAUSS, OPT, MREG, Acc, false>(p, bt.r0, bt.c0, lds);
+      forward_tile<BF_GAUSS, OPT, MREG, ACC64, false>(p, bt.r0, bt.c0, lds);
   }
 }
 
@@ -48,18 +48,18 @@ __global__ void batch_reset_kernel(int* counter) {
 }
 
 // Shapes the batch kernel is built in (opt, mreg); index = candidate variant.
-static const Variant kBatchVariants[] = {{16, 40}, {16, 72}, {8, 40}};
-static constexpr int kNumBatchVariants = 3;
+static const Variant kBatchVariants[] = {{8, 20}, {8, 32}, {4, 48}, {4, 72}};
+static constexpr int kNumBatchVariants = sizeof(kBatchVariants) / sizeof(kBatchVariants[0]);
 
 template <int OPT, int MREG>
 static hipError_t launch_batch_t(const TileParams* d_params, const BatchTile* d_tiles, int ntiles,
                                  int* counter, int grid, size_t lds, bool acc64, hipStream_t s) {
   if (acc64) {
-    auto k = gpa_batch_kernel<OPT, MREG, double>;
+    auto k = gpa_batch_kernel<OPT, MREG, true>;
     hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, max_lds_bytes() - 64);
     hipLaunchKernelGGL(k, dim3(grid), dim3(kThreads), lds, s, d_params, d_tiles, ntiles, counter);
   } else {
-    auto k = gpa_batch_kernel<OPT, MREG, float>;
+    auto k = gpa_batch_kernel<OPT, MREG, false>;
     hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, max_lds_bytes() - 64);
     hipLaunchKernelGGL(k, dim3(grid), dim3(kThreads), lds, s, d_params, d_tiles, ntiles, counter);
   }
@@ -70,9 +70,10 @@ static hipError_t launch_batch_v(int v, const TileParams* d_params, const BatchT
                                  int ntiles, int* counter, int grid, size_t lds, bool acc64,
                                  hipStream_t s) {
   switch (v) {
-    case 0: return launch_batch_t<16, 40>(d_params, d_tiles, ntiles, counter, grid, lds, acc64, s);
-    case 1: return launch_batch_t<16, 72>(d_params, d_tiles, ntiles, counter, grid, lds, acc64, s);
-    default: return launch_batch_t<8, 40>(d_params, d_tiles, ntiles, counter, grid, lds, acc64, s);
+    case 0: return launch_batch_t<8, 20>(d_params, d_tiles, ntiles, counter, grid, lds, acc64, s);
+    case 1: return launch_batch_t<8, 32>(d_params, d_tiles, ntiles, counter, grid, lds, acc64, s);
+    case 2: return launch_batch_t<4, 48>(d_params, d_tiles, ntiles, counter, grid, lds, acc64, s);
+    default: return launch_batch_t<4, 72>(d_params, d_tiles, ntiles, counter, grid, lds, acc64, s);
   }
 }
 
@@ -134,15 +135,9 @@ static bool build_shape(bf_batch* b, int v, int wg_per_cu, BatchShape* out) {
   for (int i = 0; i < b->count; ++i) {
     if (b->status[i] < 0) continue;
     const bf_params& p = b->prm[i];
-    int TY = 0;
-    for (int want : {64, 32, 16, 8, 4}) {
-      if (want > 4 * vv.opt) continue;
-      if (region_floats(want, p.W) > (int64_t)kThreads * vv.mreg) continue;
-      if (forward_lds_bytes(want, p.W) > max_lds_bytes() - 64) continue;
-      TY = want;
-      break;
-    }
-    if (TY == 0) return false;
+    const int TY = 4 * vv.opt;
+    if (region_floats(TY, p.W) > (int64_t)kThreads * vv.mreg) return false;
+    if (forward_lds_bytes(TY, p.W) > max_lds_bytes() - 64) return false;
     out->TY[i] = TY;
     lds = std::max(lds, forward_lds_bytes(TY, p.W));
     const double c = tile_cost(p, b->info[i], TY);
@@ -336,6 +331,8 @@ int bf_batch_plan(int32_t count, const bf_params* per_image, bf_batch_t** out) {
     t.sigma_r = (float)pi.sigma_r;
     t.inv_sigma_r = (float)(1.0 / pi.sigma_r);
     t.center = (float)pi.center;
+    t.inv_T = (float)(1.0 / pi.T);
+    t.X = (float)(pi.T / pi.sigma_r);
     (void)stride;
   }
   if (hipMalloc(&b->d_const, std::max<int64_t>(total, 1) * sizeof(float)) != hipSuccess) {

@@ -1,20 +1,23 @@
 // Device code shared by the forward, adjoint and batched kernels.
 //
 // One workgroup (256 threads, four wave64 waves) owns an output tile of
-// 64 columns x TY rows.  The tile grown by W on every side is the region
-// whose pixels enter its sums.  For every n = 0..N (Algorithm 2, Sec. 3):
-//   1. each thread advances the auxiliary-image values of the region pixels
-//      it owns (registers) by one power, eq. (intImg), and stores them in LDS;
-//   2. the row pass filters every region row onto the 64 tile columns;
-//   3. the column pass filters those onto the tile rows, giving the
-//      filtered image F_bar_n of eq. (spatialFiltering) at the thread's own
-//      output pixels;
+// 64 columns x TY rows (TY = 4 * OPT: each wave owns OPT consecutive rows,
+// lane = column).  The tile grown by W on every side is the region whose
+// pixels enter its sums.  For every n = 0..N (Algorithm 2, Sec. 3):
+//   1. the row pass filters every region row onto the 64 tile columns
+//      (region values in LDS -> row-pass buffer in LDS);
+//   2. each thread advances the auxiliary-image values of the region pixels
+//      it owns (registers) by one power, eq. (intImg), and stores them for
+//      the next n;
+//   3. the column pass filters the row-pass buffer onto the thread's OPT
+//      output pixels, giving F_bar_n of eq. (spatialFiltering) there;
 //   4. the thread folds F_bar_n into its numerator / denominator sums,
 //      eqs. (P), (Q).
 // The auxiliary images never leave the chip.  Box rows and columns are
 // summed with a prefix-difference over a register block (O(1) in W per
 // output); Gaussian ones with a register-blocked FIR whose taps are
-// wave-uniform scalar loads.
+// wave-uniform scalar loads.  Runtime-length loops are unrolled by four so
+// that several LDS reads are in flight per wait.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -35,158 +38,156 @@ __device__ __forceinline__ int xcd_remap(int b, int nblk) {
 
 __device__ __forceinline__ int align4(int n) { return (n + 3) & ~3; }
 
+// Sum of p[k * STRIDE] for k in [k0, k1), four loads in flight per step.
+__device__ __forceinline__ float strided_sum(const float* __restrict__ p, int STRIDE, int k0, int k1) {
+  float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f;
+  int k = k0;
+  for (; k + 4 <= k1; k += 4) {
+    a0 += p[k * STRIDE];
+    a1 += p[(k + 1) * STRIDE];
+    a2 += p[(k + 2) * STRIDE];
+    a3 += p[(k + 3) * STRIDE];
+  }
+  for (; k < k1; ++k) a0 += p[k * STRIDE];
+  return (a0 + a1) + (a2 + a3);
+}
+
+// ---------------------------------------------------------------------------
+// 1-D box and FIR over a strided LDS vector.  `src` points at the first
+// input; output j (0 <= j < S) sums inputs j .. j + 2W (weights tz[0..2W]).
+// ---------------------------------------------------------------------------
+
+// Box: with s(k) the sum of the first k inputs, out[j] = s(j + L) - s(j),
+// L = 2W + 1.  s(j) for j < S comes from the first S inputs (registers);
+// the leading sum s(j + L) advances by one input per output.
+template <int S>
+__device__ __forceinline__ void box1d(const float* __restrict__ src, int STRIDE, int L, float (&out)[S]) {
+  float a[S], b[S];
+#pragma unroll
+  for (int s = 0; s < S; ++s) a[s] = src[s * STRIDE];
+#pragma unroll
+  for (int s = 0; s < S - 1; ++s) b[s] = src[(L + s) * STRIDE];
+  float start[S];
+  float acc = 0.f;
+#pragma unroll
+  for (int s = 0; s < S; ++s) {
+    start[s] = acc;
+    acc += a[s];
+  }
+  float lead = (L >= S) ? acc + strided_sum(src, STRIDE, S, L) : strided_sum(src, STRIDE, 0, L);
+#pragma unroll
+  for (int s = 0; s < S; ++s) {
+    out[s] = lead - start[s];
+    if (s + 1 < S) lead += b[s];
+  }
+}
+
+// FIR: out[j] = sum_k tz[k - j] src[k], k = 0 .. S + 2W - 1, tz zero outside
+// [0, 2W].  Input k feeds outputs max(0, k - 2W) .. min(S - 1, k): the first
+// and last S - 1 inputs (compile-time loops) touch only the accumulators
+// whose taps are non-zero, the middle ones (runtime loop, unrolled by four)
+// touch all S, so exactly S (2W + 1) multiply-adds are issued.  For L < S - 1
+// the padded form (zero taps kTapPad deep) is used.
+template <int S>
+__device__ __forceinline__ void fir1d(const float* __restrict__ src, int STRIDE, int L,
+                                      const float* __restrict__ tz, float (&out)[S]) {
+  constexpr int U = 4;
+#pragma unroll
+  for (int s = 0; s < S; ++s) out[s] = 0.f;
+  if (L >= S - 1) {
+#pragma unroll
+    for (int k = 0; k < S - 1; ++k) {  // head
+      const float v = src[k * STRIDE];
+#pragma unroll
+      for (int s = 0; s <= k; ++s) out[s] = fmaf(tz[k - s], v, out[s]);
+    }
+    int k = S - 1;
+    for (; k + U <= L; k += U) {  // body
+      float v[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) v[u] = src[(k + u) * STRIDE];
+      float tw[S + U - 1];
+#pragma unroll
+      for (int i = 0; i < S + U - 1; ++i) tw[i] = tz[k - (S - 1) + i];
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+#pragma unroll
+        for (int s = 0; s < S; ++s) out[s] = fmaf(tw[u - s + S - 1], v[u], out[s]);
+    }
+    for (; k < L; ++k) {
+      const float v = src[k * STRIDE];
+#pragma unroll
+      for (int s = 0; s < S; ++s) out[s] = fmaf(tz[k - s], v, out[s]);
+    }
+    const float* tl = tz + L;
+#pragma unroll
+    for (int j = 0; j < S - 1; ++j) {  // tail: input L + j feeds outputs j+1 .. S-1
+      const float v = src[(L + j) * STRIDE];
+#pragma unroll
+      for (int s = j + 1; s < S; ++s) out[s] = fmaf(tl[j - s], v, out[s]);
+    }
+  } else {
+    const int K = L + S - 1;
+    for (int k = 0; k < K; ++k) {
+      const float v = src[k * STRIDE];
+#pragma unroll
+      for (int s = 0; s < S; ++s) out[s] = fmaf(tz[k - s], v, out[s]);
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Row pass: region rows (RH of them, pitch RWp) -> Hs rows (pitch kHPitch),
 // 64 outputs per row.  Output column c sums region columns c .. c + 2W.
+// Work items are (row, segment of S outputs); consecutive lanes take
+// consecutive rows, so with the odd pitches every LDS access is conflict-free.
 // ---------------------------------------------------------------------------
-
-// Box: each work item covers S consecutive outputs of one row.  With the
-// running prefix s(k) = sum of the first k region values of the segment,
-// out[j] = s(j + 2W + 1) - s(j); s(j) for j < S is kept in registers and the
-// leading prefix advances one value per output.
-template <int S>
-__device__ __forceinline__ void rowpass_box(const float* __restrict__ Fs, int RWp,
-                                            float* __restrict__ Hs, int RH, int W) {
-  constexpr int nseg = kTileCols / S;
-  const int L = 2 * W + 1;
-  const int items = RH * nseg;
-  for (int it = threadIdx.x; it < items; it += kThreads) {
-    const int seg = it / RH;
-    const int r = it - seg * RH;
-    const float* row = Fs + r * RWp + seg * S;
-    float start[S];
-    float acc = 0.f;
-#pragma unroll
-    for (int s = 0; s < S; ++s) {
-      start[s] = acc;
-      acc += row[s];
-    }
-    float lead;
-    if (L >= S) {
-      lead = acc;
-      for (int k = S; k < L; ++k) lead += row[k];
-    } else {
-      lead = 0.f;
-      for (int k = 0; k < L; ++k) lead += row[k];
-    }
-    float* h = Hs + r * kHPitch + seg * S;
-#pragma unroll
-    for (int s = 0; s < S; ++s) {
-      h[s] = lead - start[s];
-      if (s + 1 < S) lead += row[L + s];
-    }
-  }
-}
-
-// Gaussian: out[j] = sum_d tap[d] F[j + d]; loop over the inputs of the
-// segment, each contributing to all S register accumulators.  tz points at
-// the tap array with kTapPad zeros in front, so tz[k - s] is tap[k - s] or
-// zero outside [0, 2W].
-template <int S>
-__device__ __forceinline__ void rowpass_fir(const float* __restrict__ Fs, int RWp,
-                                            float* __restrict__ Hs, int RH, int W,
-                                            const float* __restrict__ tz) {
-  constexpr int nseg = kTileCols / S;
-  const int L = 2 * W + 1;
-  const int items = RH * nseg;
-  for (int it = threadIdx.x; it < items; it += kThreads) {
-    const int seg = it / RH;
-    const int r = it - seg * RH;
-    const float* row = Fs + r * RWp + seg * S;
-    float acc[S];
-#pragma unroll
-    for (int s = 0; s < S; ++s) acc[s] = 0.f;
-    const int K = L + S - 1;
-    for (int k = 0; k < K; ++k) {
-      const float v = row[k];
-#pragma unroll
-      for (int s = 0; s < S; ++s) acc[s] = fmaf(tz[k - s], v, acc[s]);
-    }
-    float* h = Hs + r * kHPitch + seg * S;
-#pragma unroll
-    for (int s = 0; s < S; ++s) h[s] = acc[s];
-  }
-}
-
-// ---------------------------------------------------------------------------
-// Column pass: the thread owns column `lane` of the tile and output rows
-// orow0 .. orow0 + opt - 1 (opt <= OPT); it reads Hs rows orow0 .. orow0 +
-// opt - 1 + 2W and writes its opt filtered values to v[].
-// ---------------------------------------------------------------------------
-template <int OPT>
-__device__ __forceinline__ void colpass_box(const float* __restrict__ Hs, int orow0, int lane,
-                                            int opt, int W, float (&v)[OPT]) {
-  const float* col = Hs + orow0 * kHPitch + lane;
-  const int L = 2 * W + 1;
-  float start[OPT];
-  float acc = 0.f;
-#pragma unroll
-  for (int s = 0; s < OPT; ++s) {
-    if (s < opt) {
-      start[s] = acc;
-      acc += col[s * kHPitch];
-    }
-  }
-  float lead;
-  if (L >= opt) {
-    lead = acc;
-    for (int k = opt; k < L; ++k) lead += col[k * kHPitch];
-  } else {
-    lead = 0.f;
-    for (int k = 0; k < L; ++k) lead += col[k * kHPitch];
-  }
-#pragma unroll
-  for (int s = 0; s < OPT; ++s) {
-    if (s < opt) {
-      v[s] = lead - start[s];
-      if (s + 1 < opt) lead += col[(L + s) * kHPitch];
-    }
-  }
-}
-
-template <int OPT>
-__device__ __forceinline__ void colpass_fir(const float* __restrict__ Hs, int orow0, int lane,
-                                            int opt, int W, const float* __restrict__ tz,
-                                            float (&v)[OPT]) {
-  const float* col = Hs + orow0 * kHPitch + lane;
-  const int L = 2 * W + 1;
-#pragma unroll
-  for (int s = 0; s < OPT; ++s) v[s] = 0.f;
-  const int K = L + opt - 1;
-  for (int k = 0; k < K; ++k) {
-    const float x = col[k * kHPitch];
-#pragma unroll
-    for (int s = 0; s < OPT; ++s) v[s] = fmaf(tz[k - s], x, v[s]);
-  }
-}
-
-// Row S for the box (prefix trick) and for the FIR (register block).
-constexpr int kRowSegBox = 16;
-constexpr int kRowSegFir = 8;
+constexpr int kRowSegBox = kRowSegBoxHost;
+constexpr int kRowSegFir = kRowSegFirHost;
 
 template <int KT>
-__device__ __forceinline__ void rowpass(const float* Fs, int RWp, float* Hs, int RH, int W,
-                                        const float* tz) {
-  if (KT == BF_BOX)
-    rowpass_box<kRowSegBox>(Fs, RWp, Hs, RH, W);
-  else
-    rowpass_fir<kRowSegFir>(Fs, RWp, Hs, RH, W, tz);
+__device__ __forceinline__ void rowpass(const float* __restrict__ Fs, int RWp, float* __restrict__ Hs,
+                                        int RH, int W, const float* __restrict__ tz) {
+  constexpr int S = (KT == BF_BOX) ? kRowSegBox : kRowSegFir;
+  constexpr int nseg = kTileCols / S;
+  const int L = 2 * W + 1;
+  const int items = RH * nseg;
+  for (int it = threadIdx.x; it < items; it += kThreads) {
+    const int seg = it / RH;
+    const int r = it - seg * RH;
+    float o[S];
+    if (KT == BF_BOX)
+      box1d<S>(Fs + r * RWp + seg * S, 1, L, o);
+    else
+      fir1d<S>(Fs + r * RWp + seg * S, 1, L, tz, o);
+    float* h = Hs + r * kHPitch + seg * S;
+#pragma unroll
+    for (int s = 0; s < S; ++s) h[s] = o[s];
+  }
 }
 
+// Row pass with the FIR regardless of the tile's kernel (adjoint's sigma_s term).
+__device__ __forceinline__ void rowpass_fir_any(const float* __restrict__ Fs, int RWp,
+                                                float* __restrict__ Hs, int RH, int W,
+                                                const float* __restrict__ tz) {
+  rowpass<BF_GAUSS>(Fs, RWp, Hs, RH, W, tz);
+}
+
+// Column pass: the thread owns column `lane` and output rows orow0 ..
+// orow0 + OPT - 1; it reads Hs rows orow0 .. orow0 + OPT - 1 + 2W.
 template <int KT, int OPT>
-__device__ __forceinline__ void colpass(const float* Hs, int orow0, int lane, int opt, int W,
-                                        const float* tz, float (&v)[OPT]) {
+__device__ __forceinline__ void colpass(const float* __restrict__ Hs, int orow0, int lane, int W,
+                                        const float* __restrict__ tz, float (&v)[OPT]) {
+  const float* col = Hs + orow0 * kHPitch + lane;
   if (KT == BF_BOX)
-    colpass_box<OPT>(Hs, orow0, lane, opt, W, v);
+    box1d<OPT>(col, kHPitch, 2 * W + 1, v);
   else
-    colpass_fir<OPT>(Hs, orow0, lane, opt, W, tz, v);
+    fir1d<OPT>(col, kHPitch, 2 * W + 1, tz, v);
 }
 
 // ---------------------------------------------------------------------------
-// Region set-up: the thread owns region pixels q = t + 256 m (row-major over
-// the padded region, pitch RWp).  x = (f - center) / sigma_r, F~_0 = e^{-x^2/2};
-// pixels outside the image (and the pad column) hold x = F = 0 and so never
-// contribute (zero extension).
+// Region ownership: the thread owns region pixels q = t + 256 m (row-major
+// over the padded region, pitch RWp).
 // ---------------------------------------------------------------------------
 struct RegionGeom {
   int RH, RW, RWp, npx;
@@ -196,7 +197,7 @@ __device__ __forceinline__ RegionGeom region_geom(int TY, int W) {
   RegionGeom g;
   g.RH = TY + 2 * W;
   g.RW = kTileCols + 2 * W;
-  g.RWp = g.RW | 1;
+  g.RWp = region_pitch(W);
   g.npx = g.RH * g.RWp;
   return g;
 }
@@ -224,103 +225,143 @@ __device__ __forceinline__ void for_region(const RegionGeom& g, int r0, int c0, 
 }
 
 // ---------------------------------------------------------------------------
-// Fused forward tile body (Algorithm 2 with the range-safe scaling).
+// Fused forward tile body.
+//
+// Range-safe form of Algorithm 2.  With X = T / sigma_r and y = x / X =
+// (f - center) / T (|y| <= 1 on the dynamic range), the kernels keep
+//     F^_n(j) = e^{-x_j^2/2} y_j^n                 (region, one multiply per n)
+//     a_n(i)  = e^{-x_i^2/2} x_i^n X^n / n!        (coefficient, per output)
+// so that a_n(i) F^_n(j) = e^{-x_i^2/2} e^{-x_j^2/2} (x_i x_j)^n / n!: the
+// terms of eq. (Q) times e^{-x_i^2/2}, which cancels in eq. (PbyQ).  For
+// T / sigma_r <= 13 every factor stays in the float32 range (the plan
+// rejects smaller sigma_r).  With F_bar^_n the filtered F^_n:
+//     Q = sum_{n<N} a_n F_bar^_n,   P = X sum_{n<N} a_n F_bar^_{n+1},
+//     out = sigma_r P / Q + center.
+// Products are formed in float32; with ACC64 the running sums are float32
+// partials over blocks of 8 orders folded into float64 totals.
+// SAVE additionally stores, per pixel, Q, P/Q and the coefficient-side
+// derivative D_P - (P/Q) D_Q used by the adjoint, with
+//     D_Q = X sum_{n=1}^{N-1} a_{n-1} F_bar^_n,
+//     D_P = X^2 sum_{n=1}^{N-1} a_{n-1} F_bar^_{n+1}.
 // ---------------------------------------------------------------------------
-template <typename Acc>
-struct AccOps;
-template <>
-struct AccOps<double> {
-  static __device__ __forceinline__ double fma_(float a, float b, double c) {
-    return fma((double)a, (double)b, c);
-  }
+template <bool ACC64>
+struct Accum {
+  float part;
+  double tot;
+  __device__ __forceinline__ void zero() { part = 0.f; tot = 0.0; }
+  __device__ __forceinline__ void add(float a, float b) { part = fmaf(a, b, part); }
+  __device__ __forceinline__ void fold() { tot += (double)part; part = 0.f; }
+  __device__ __forceinline__ double value() const { return tot + (double)part; }
 };
 template <>
-struct AccOps<float> {
-  static __device__ __forceinline__ float fma_(float a, float b, float c) { return fmaf(a, b, c); }
+struct Accum<false> {
+  float part;
+  __device__ __forceinline__ void zero() { part = 0.f; }
+  __device__ __forceinline__ void add(float a, float b) { part = fmaf(a, b, part); }
+  __device__ __forceinline__ void fold() {}
+  __device__ __forceinline__ double value() const { return (double)part; }
 };
 
-template <int KT, int OPT, int MREG, typename Acc, bool SAVE>
+template <int KT, int OPT, int MREG, bool ACC64, bool SAVE>
 __device__ __forceinline__ void forward_tile(const TileParams& p, int r0, int c0, float* lds) {
   const int W = p.W;
   const int N = p.N;
-  const RegionGeom g = region_geom(p.TY, W);
+  const RegionGeom g = region_geom(4 * OPT, W);
   float* Fs = lds;
   float* Hs = lds + align4(g.npx);
   const float* tz = p.taps + kTapPad;
 
-  float Fr[MREG], xr[MREG];
+  // region: F^_0 = e^{-x^2/2} into LDS, y kept in registers
+  float Fr[MREG], yr[MREG];
   for_region<MREG>(g, r0, c0, W, p.H, p.Wd, [&](int m, int q, bool inside, int gr, int gc) {
-    float x = 0.f, F = 0.f;
+    float y = 0.f, F = 0.f;
     if (inside) {
       const float f = p.in[(int64_t)gr * p.in_pitch + gc];
-      x = (f - p.center) / p.sigma_r;
+      const float x = (f - p.center) / p.sigma_r;
+      y = (f - p.center) * p.inv_T;
       F = expf(-0.5f * x * x);
     }
     Fr[m] = F;
-    xr[m] = x;
+    yr[m] = y;
+    if (q < g.npx) Fs[q] = F;
   });
 
   const int lane = threadIdx.x & 63;
-  const int wv = threadIdx.x >> 6;
-  const int opt = p.TY >> 2;
-  const int orow0 = wv * opt;
+  const int orow0 = (threadIdx.x >> 6) * OPT;
   const int gc = c0 + lane;
-  float xo[OPT], ao[OPT], bo[OPT], bp[OPT];
-  Acc P[OPT], Q[OPT], DP[OPT], DQ[OPT];
+  float z[OPT], a[OPT], ap[OPT], app[OPT];
+  Accum<ACC64> P[OPT], Q[OPT], DP[OPT], DQ[OPT];
 #pragma unroll
   for (int s = 0; s < OPT; ++s) {
     const int gr = r0 + orow0 + s;
     float x = 0.f;
-    if (s < opt && gr < p.H && gc < p.Wd) x = (p.in[(int64_t)gr * p.in_pitch + gc] - p.center) / p.sigma_r;
-    xo[s] = x;
-    ao[s] = expf(-0.5f * x * x);  // a_0 = e^{-x^2/2} M_0 / 0!
-    bo[s] = 0.f;                  // b_n = a_{n-1} r_n (none at n = 0)
-    bp[s] = 0.f;
-    P[s] = Q[s] = DP[s] = DQ[s] = Acc(0);
+    if (gr < p.H && gc < p.Wd) x = (p.in[(int64_t)gr * p.in_pitch + gc] - p.center) / p.sigma_r;
+    z[s] = x * p.X;                // a_{n+1} = a_n x X / (n+1)
+    a[s] = expf(-0.5f * x * x);    // a_0
+    ap[s] = 0.f;                   // a_{n-1}
+    app[s] = 0.f;                  // a_{n-2}
+    P[s].zero();
+    Q[s].zero();
+    if (SAVE) {
+      DP[s].zero();
+      DQ[s].zero();
+    }
   }
+  __syncthreads();
 
   for (int n = 0; n <= N; ++n) {
-    const float sn = p.s_tab[n];
-#pragma unroll
-    for (int m = 0; m < MREG; ++m) {
-      if (n > 0) Fr[m] *= xr[m] * sn;  // F~_n = F~_{n-1} x / r_n
-      const int q = threadIdx.x + kThreads * m;
-      if (q < g.npx) Fs[q] = Fr[m];
-    }
-    __syncthreads();
     rowpass<KT>(Fs, g.RWp, Hs, g.RH, W, tz);
     __syncthreads();
+    if (n < N) {
+#pragma unroll
+      for (int m = 0; m < MREG; ++m) {
+        Fr[m] *= yr[m];  // F^_{n+1} = F^_n y
+        const int q = threadIdx.x + kThreads * m;
+        if (q < g.npx) Fs[q] = Fr[m];
+      }
+    }
     float v[OPT];
-    colpass<KT, OPT>(Hs, orow0, lane, opt, W, tz, v);
-    const float rn = p.r_tab[n];
-    const float rn1 = p.r_tab[n + 1];
+    colpass<KT, OPT>(Hs, orow0, lane, W, tz, v);
     const float in1 = p.inv_tab[n + 1];
 #pragma unroll
     for (int s = 0; s < OPT; ++s) {
-      if (n >= 1) P[s] = AccOps<Acc>::fma_(bo[s], v[s], P[s]);  // eq. (P): F_bar_{n} term
-      if (n < N) Q[s] = AccOps<Acc>::fma_(ao[s], v[s], Q[s]);   // eq. (Q): F_bar_{n} term
+      if (n < N) Q[s].add(a[s], v[s]);      // eq. (Q)
+      if (n >= 1) P[s].add(ap[s], v[s]);    // eq. (P), term of F_bar_n
       if (SAVE) {
-        if (n >= 1 && n < N) DQ[s] = AccOps<Acc>::fma_(bo[s], v[s], DQ[s]);
-        if (n >= 2) DP[s] = AccOps<Acc>::fma_(bp[s] * rn, v[s], DP[s]);
-        bp[s] = bo[s];
+        if (n >= 1 && n < N) DQ[s].add(ap[s], v[s]);
+        if (n >= 2) DP[s].add(app[s], v[s]);
+        app[s] = ap[s];
       }
-      const float bn = ao[s] * rn1;  // b_{n+1} = a_n r_{n+1}
-      ao[s] = bn * (xo[s] * in1);    // a_{n+1} = b_{n+1} x / (n+1)
-      bo[s] = bn;
+      ap[s] = a[s];
+      a[s] *= z[s] * in1;
     }
+    if (ACC64 && ((n & 7) == 7)) {
+#pragma unroll
+      for (int s = 0; s < OPT; ++s) {
+        P[s].fold();
+        Q[s].fold();
+        if (SAVE) {
+          DP[s].fold();
+          DQ[s].fold();
+        }
+      }
+    }
+    __syncthreads();
   }
 
+  const double X = (double)p.X;
 #pragma unroll
   for (int s = 0; s < OPT; ++s) {
     const int gr = r0 + orow0 + s;
-    if (s < opt && gr < p.H && gc < p.Wd) {
-      const double ratio = (double)P[s] / (double)Q[s];
+    if (gr < p.H && gc < p.Wd) {
+      const double q = Q[s].value();
+      const double ratio = X * P[s].value() / q;
       if (p.out) p.out[(int64_t)gr * p.out_pitch + gc] = (float)((double)p.sigma_r * ratio + (double)p.center);
       if (SAVE && p.saved) {
         const int64_t idx = (int64_t)gr * p.Wd + gc;
-        p.saved[idx] = (float)Q[s];
+        p.saved[idx] = (float)q;
         p.saved[p.saved_plane + idx] = (float)ratio;
-        p.saved[2 * p.saved_plane + idx] = (float)((double)DP[s] - ratio * (double)DQ[s]);
+        p.saved[2 * p.saved_plane + idx] = (float)(X * X * DP[s].value() - ratio * X * DQ[s].value());
       }
     }
   }

@@ -18,9 +18,14 @@ constexpr int kTileCols = 64;
 // Zero padding on both sides of the tap array, so that the register-blocked
 // FIR loops can index taps without bounds tests (>= largest block - 1).
 constexpr int kTapPad = 16;
-// Row pitch (floats) of the LDS buffer holding the first (row) pass: odd,
-// so column-wise lane access and row-wise lane access are bank-conflict free.
-constexpr int kHPitch = kTileCols + 1;
+// Row pitch (floats) of the LDS buffer holding the row-pass output.  The
+// row pass writes it with lanes on consecutive rows and pairs of adjacent
+// columns (64-bit accesses): a pitch of twice an odd number puts the 16
+// lanes of one LDS cycle on 32 distinct banks.
+constexpr int kHPitch = kTileCols + 2;
+// Row-pass register blocks (outputs per work item) for the box and the FIR.
+constexpr int kRowSegBoxHost = 16;
+constexpr int kRowSegFirHost = 8;
 
 // Everything one tile of the fused forward / adjoint needs for one image.
 struct TileParams {
@@ -37,6 +42,8 @@ struct TileParams {
   int TY;               // tile rows (multiple of 4)
   int tiles_x;          // tiles per image row
   float sigma_r, inv_sigma_r, center;
+  float inv_T;          // 1 / T: y = (f - center) / T, so |y| <= 1 on [center - T, center + T]
+  float X;              // T / sigma_r
   float inv_sigma_s3;   // 1 / sigma_s^3 (Gaussian sigma_s gradient)
   const float* s_tab;   // s_n = 1/r_n, n = 0..N+1 (s_0 = 0)
   const float* r_tab;   // r_n = M_n / M_{n-1}, n = 0..N+1 (r_0 = 0)
@@ -45,14 +52,31 @@ struct TileParams {
   const float* taps2;   // same layout, d^2 * tap (Gaussian sigma_s gradient)
 };
 
+// Large-support path: orders per block and its device state.
+constexpr int kLsBlock = 8;
+struct LsState {
+  int64_t pitch;            // row pitch (floats) of the image-shaped buffers
+  float* F[2];              // F^ state images (double-buffered)
+  float* Y;                 // y = (f - center) / T
+  float* H[kLsBlock];       // row-filtered images, W zero rows above and below
+  float *a, *ap, *app, *z;  // per-pixel coefficient recursion
+  double *P, *Q, *DP, *DQ;  // per-pixel sums
+  int64_t hbytes;           // bytes of one row-filtered image
+};
+
 // Kernel-shape variants (compile-time register budgets).
 struct Variant {
   int opt;    // max output rows per thread (tile rows = 4 * opt)
   int mreg;   // max region pixels per thread
 };
 
-// Region (tile grown by W on every side) in LDS, in floats.
-inline int region_pitch(int W) { return (kTileCols + 2 * W) | 1; }
+// Region (tile grown by W on every side) in LDS, in floats.  Row pitch is
+// twice an odd number for the same reason as kHPitch (the row pass reads
+// pairs of adjacent columns with lanes on consecutive rows).
+__host__ __device__ inline int region_pitch(int W) {
+  const int rw = kTileCols + 2 * W;
+  return (rw % 4 == 2) ? rw : rw + 2;
+}
 inline int64_t region_floats(int TY, int W) {
   return (int64_t)(TY + 2 * W) * region_pitch(W);
 }
@@ -69,6 +93,11 @@ Variant backward_variant(int v);
 int64_t forward_lds_bytes(int TY, int W);
 int64_t backward_lds_bytes(int TY, int W, bool sigs);
 int max_lds_bytes();
+// large-support path (bf_large.hip)
+bool ls_supported(int W);
+int64_t ls_state_bytes(int H, int Wd, int W, bool save);
+LsState ls_layout(void* base, int H, int Wd, int W, bool save);
+hipError_t launch_forward_ls(const TileParams& p, const LsState& st, bool save, hipStream_t s);
 
 // Batch (bf_batch.hip)
 struct BatchTile {
@@ -106,4 +135,7 @@ struct bf_plan {
   float* d_work;        // recompute buffer for the adjoint (3 planes) or null
   double* d_partials;   // per-workgroup sigma-gradient partials
   int ntiles_b;         // backward tiles
+  bool ls;              // large-support path (support too wide for the fused tiles)
+  void* d_ls;           // its device state
+  bfgpa::LsState ls_state;
 };

@@ -12,17 +12,19 @@ namespace bfgpa {
 // ---------------------------------------------------------------------------
 // Forward
 // ---------------------------------------------------------------------------
-template <int KT, int OPT, int MREG, typename Acc, bool SAVE>
+template <int KT, int OPT, int MREG, bool ACC64, bool SAVE>
 __global__ __launch_bounds__(kThreads) void gpa_forward_kernel(TileParams p) {
   extern __shared__ float lds[];
   const int tile = xcd_remap(blockIdx.x, gridDim.x);
   const int ty = tile / p.tiles_x;
   const int tx = tile - ty * p.tiles_x;
-  forward_tile<KT, OPT, MREG, Acc, SAVE>(p, ty * p.TY, tx * kTileCols, lds);
+  forward_tile<KT, OPT, MREG, ACC64, SAVE>(p, ty * 4 * OPT, tx * kTileCols, lds);
 }
 
-static const Variant kFwdVariants[] = {{16, 40}, {16, 72}, {8, 40}};
-int forward_variant_count() { return 3; }
+// (output rows per thread, region pixels per thread); tile rows = 4 * OPT.
+static const Variant kFwdVariants[] = {{8, 12}, {8, 20}, {8, 32}, {16, 40}, {4, 32}, {4, 48}, {4, 72}};
+static constexpr int kNumFwdVariants = sizeof(kFwdVariants) / sizeof(kFwdVariants[0]);
+int forward_variant_count() { return kNumFwdVariants; }
 Variant forward_variant(int v) { return kFwdVariants[v]; }
 
 int64_t forward_lds_bytes(int TY, int W) {
@@ -32,10 +34,10 @@ int64_t forward_lds_bytes(int TY, int W) {
 
 int max_lds_bytes() { return 160 * 1024; }
 
-template <int KT, int OPT, int MREG, typename Acc, bool SAVE>
+template <int KT, int OPT, int MREG, bool ACC64, bool SAVE>
 static hipError_t launch_fwd_t(const TileParams& p, hipStream_t s) {
-  auto kern = gpa_forward_kernel<KT, OPT, MREG, Acc, SAVE>;
-  const int64_t lds = forward_lds_bytes(p.TY, p.W);
+  auto kern = gpa_forward_kernel<KT, OPT, MREG, ACC64, SAVE>;
+  const int64_t lds = forward_lds_bytes(4 * OPT, p.W);
   static bool attr_set = false;
   if (!attr_set) {
     hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -43,7 +45,7 @@ static hipError_t launch_fwd_t(const TileParams& p, hipStream_t s) {
     if (e != hipSuccess) return e;
     attr_set = true;
   }
-  const int tiles = ((p.H + p.TY - 1) / p.TY) * p.tiles_x;
+  const int tiles = ((p.H + 4 * OPT - 1) / (4 * OPT)) * p.tiles_x;
   hipLaunchKernelGGL(kern, dim3(tiles), dim3(kThreads), (size_t)lds, s, p);
   return hipGetLastError();
 }
@@ -51,26 +53,31 @@ static hipError_t launch_fwd_t(const TileParams& p, hipStream_t s) {
 template <int KT, int OPT, int MREG>
 static hipError_t launch_fwd_v(const TileParams& p, bool acc64, bool save, hipStream_t s) {
   if (acc64)
-    return save ? launch_fwd_t<KT, OPT, MREG, double, true>(p, s)
-                : launch_fwd_t<KT, OPT, MREG, double, false>(p, s);
-  return save ? launch_fwd_t<KT, OPT, MREG, float, true>(p, s)
-              : launch_fwd_t<KT, OPT, MREG, float, false>(p, s);
+    return save ? launch_fwd_t<KT, OPT, MREG, true, true>(p, s)
+                : launch_fwd_t<KT, OPT, MREG, true, false>(p, s);
+  return save ? launch_fwd_t<KT, OPT, MREG, false, true>(p, s)
+              : launch_fwd_t<KT, OPT, MREG, false, false>(p, s);
 }
 
 template <int KT>
 static hipError_t launch_fwd_k(const TileParams& p, int variant, bool acc64, bool save,
                                hipStream_t s) {
   switch (variant) {
-    case 0: return launch_fwd_v<KT, 16, 40>(p, acc64, save, s);
-    case 1: return launch_fwd_v<KT, 16, 72>(p, acc64, save, s);
-    default: return launch_fwd_v<KT, 8, 40>(p, acc64, save, s);
+    case 0: return launch_fwd_v<KT, 8, 12>(p, acc64, save, s);
+    case 1: return launch_fwd_v<KT, 8, 20>(p, acc64, save, s);
+    case 2: return launch_fwd_v<KT, 8, 32>(p, acc64, save, s);
+    case 3: return launch_fwd_v<KT, 16, 40>(p, acc64, save, s);
+    case 4: return launch_fwd_v<KT, 4, 32>(p, acc64, save, s);
+    case 5: return launch_fwd_v<KT, 4, 48>(p, acc64, save, s);
+    default: return launch_fwd_v<KT, 4, 72>(p, acc64, save, s);
   }
 }
 
 hipError_t launch_forward(const TileParams& p, int variant, bool acc64, bool save,
                           hipStream_t s) {
+  if (variant < 0 || variant >= kNumFwdVariants) return hipErrorInvalidValue;
   const Variant v = forward_variant(variant);
-  if (p.TY <= 0 || p.TY % 4 != 0 || p.TY > 4 * v.opt) return hipErrorInvalidValue;
+  if (p.TY != 4 * v.opt) return hipErrorInvalidValue;
   if (region_floats(p.TY, p.W) > (int64_t)kThreads * v.mreg) return hipErrorInvalidValue;
   if (forward_lds_bytes(p.TY, p.W) > max_lds_bytes()) return hipErrorInvalidValue;
   if (p.H <= 0 || p.Wd <= 0) return hipSuccess;
@@ -100,7 +107,7 @@ __global__ __launch_bounds__(kThreads) void gpa_backward_kernel(TileParams p, do
   const int txi = tile - tyi * p.tiles_x;
   const int r0 = tyi * p.TY, c0 = txi * kTileCols;
   const int W = p.W, N = p.N;
-  const RegionGeom g = region_geom(p.TY, W);
+  const RegionGeom g = region_geom(4 * OPT, W);
   const int np4 = align4(g.npx);
   float* As = lds;
   float* Hs = As + np4;
@@ -131,9 +138,7 @@ __global__ __launch_bounds__(kThreads) void gpa_backward_kernel(TileParams p, do
   });
 
   const int lane = threadIdx.x & 63;
-  const int wv = threadIdx.x >> 6;
-  const int opt = p.TY >> 2;
-  const int orow0 = wv * opt;
+  const int orow0 = (threadIdx.x >> 6) * OPT;
   const int gc = c0 + lane;
   float xo[OPT], fp[OPT], fc[OPT];
   double dx[OPT], dss[OPT];
@@ -141,7 +146,7 @@ __global__ __launch_bounds__(kThreads) void gpa_backward_kernel(TileParams p, do
   for (int s = 0; s < OPT; ++s) {
     const int gr = r0 + orow0 + s;
     float x = 0.f, F = 0.f;
-    if (s < opt && gr < p.H && gc < p.Wd) {
+    if (gr < p.H && gc < p.Wd) {
       x = (p.in[(int64_t)gr * p.in_pitch + gc] - p.center) / p.sigma_r;
       F = expf(-0.5f * x * x);
     }
@@ -174,22 +179,20 @@ __global__ __launch_bounds__(kThreads) void gpa_backward_kernel(TileParams p, do
     __syncthreads();
     rowpass<KT>(As, g.RWp, Hs, g.RH, W, tz);
     if (SIGS) {
-      rowpass_fir<kRowSegFir>(Fs2, g.RWp, Hg, g.RH, W, tz);
-      rowpass_fir<kRowSegFir>(Fs2, g.RWp, Hg2, g.RH, W, tz2);
+      rowpass_fir_any(Fs2, g.RWp, Hg, g.RH, W, tz);
+      rowpass_fir_any(Fs2, g.RWp, Hg2, g.RH, W, tz2);
     }
     __syncthreads();
     float fa[OPT];
-    colpass<KT, OPT>(Hs, orow0, lane, opt, W, tz, fa);
+    colpass<KT, OPT>(Hs, orow0, lane, W, tz, fa);
     if (SIGS) {
       float u[OPT], u2[OPT];
-      colpass_fir<OPT>(Hg, orow0, lane, opt, W, tz2, u);   // d^2 g along rows of g-filtered
-      colpass_fir<OPT>(Hg2, orow0, lane, opt, W, tz, u2);  // g along rows of d^2 g-filtered
+      colpass<BF_GAUSS, OPT>(Hg, orow0, lane, W, tz2, u);   // d^2 g along rows of g-filtered
+      colpass<BF_GAUSS, OPT>(Hg2, orow0, lane, W, tz, u2);  // g along rows of d^2 g-filtered
 #pragma unroll
       for (int s = 0; s < OPT; ++s) {
-        if (s < opt) {
-          const float adj_i = As[(orow0 + s + W) * g.RWp + lane + W];
-          dss[s] = fma((double)adj_i, (double)(u[s] + u2[s]), dss[s]);
-        }
+        const float adj_i = As[(orow0 + s + W) * g.RWp + lane + W];
+        dss[s] = fma((double)adj_i, (double)(u[s] + u2[s]), dss[s]);
       }
     }
     const float fm = (float)m * sm;
@@ -207,7 +210,7 @@ __global__ __launch_bounds__(kThreads) void gpa_backward_kernel(TileParams p, do
 #pragma unroll
   for (int s = 0; s < OPT; ++s) {
     const int gr = r0 + orow0 + s;
-    if (s < opt && gr < p.H && gc < p.Wd) {
+    if (gr < p.H && gc < p.Wd) {
       const int64_t idx = (int64_t)gr * p.Wd + gc;
       const float gb = p.gout[(int64_t)gr * p.gout_pitch + gc];
       const double Qs = p.saved[idx];
@@ -282,8 +285,8 @@ static hipError_t launch_bwd_t(const TileParams& p, double* partials, hipStream_
     if (e != hipSuccess) return e;
     attr_set = true;
   }
-  const int tiles = ((p.H + p.TY - 1) / p.TY) * p.tiles_x;
-  hipLaunchKernelGGL(kern, dim3(tiles), dim3(kThreads), (size_t)backward_lds_bytes(p.TY, p.W, SIGS),
+  const int tiles = ((p.H + 4 * OPT - 1) / (4 * OPT)) * p.tiles_x;
+  hipLaunchKernelGGL(kern, dim3(tiles), dim3(kThreads), (size_t)backward_lds_bytes(4 * OPT, p.W, SIGS),
                      s, p, partials);
   return hipGetLastError();
 }
@@ -297,7 +300,7 @@ static hipError_t launch_bwd_k(const TileParams& p, int variant, double* partial
 hipError_t launch_backward(const TileParams& p, int variant, bool sigs, double* partials,
                            double* grad_sigma, hipStream_t s) {
   const Variant v = backward_variant(variant);
-  if (p.TY <= 0 || p.TY % 4 != 0 || p.TY > 4 * v.opt) return hipErrorInvalidValue;
+  if (p.TY != 4 * v.opt) return hipErrorInvalidValue;
   if (region_floats(p.TY, p.W) > (int64_t)kThreads * v.mreg) return hipErrorInvalidValue;
   if (backward_lds_bytes(p.TY, p.W, sigs) + 2 * kThreads * 8 > max_lds_bytes()) return hipErrorInvalidValue;
   if (p.H <= 0 || p.Wd <= 0) return hipSuccess;

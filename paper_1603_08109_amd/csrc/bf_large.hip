@@ -1,0 +1,300 @@
+// Large-support forward: Algorithm 2 for supports W too wide for one tile's
+// region to stay on chip (the fused kernels hold (TY + 2W) x (64 + 2W) region
+// values per workgroup).  The N+1 filterings run in blocks of up to kLsBlock
+// orders through device memory:
+//   ls_init  : F^_0 = e^{-x^2/2}, y, and the per-pixel coefficient state;
+//   ls_rows  : per block, F^_n for the block's orders and the row pass of
+//              each (rows staged in LDS with their W-column halo), written to
+//              kLsBlock row-filtered images; the state image advances by the
+//              block length (double-buffered);
+//   ls_cols  : the column pass of each row-filtered image (read straight
+//              from device memory, coalesced along rows) folded into the
+//              per-pixel sums of eqs. (P), (Q) held in registers for the block;
+//   ls_final : eq. (PbyQ) and the optional adjoint state.
+// The range-safe scaling is the same as in the fused kernels (bf_device.h).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdint>
+
+#include "bf_device.h"
+#include "bf_internal.h"
+
+namespace bfgpa {
+
+constexpr int kLsRows = 16;       // image rows per ls_rows workgroup
+constexpr int kLsCols = 256;      // output columns per ls_rows workgroup
+constexpr int kLsOpt = 16;        // output rows per thread in ls_cols
+
+__global__ __launch_bounds__(kThreads) void ls_init_kernel(TileParams p, LsState st) {
+  const int64_t npx = (int64_t)p.H * p.Wd;
+  for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < npx;
+       i += (int64_t)gridDim.x * kThreads) {
+    const int r = (int)(i / p.Wd), c = (int)(i - (int64_t)r * p.Wd);
+    const float f = p.in[(int64_t)r * p.in_pitch + c];
+    const float x = (f - p.center) / p.sigma_r;
+    const float E = expf(-0.5f * x * x);
+    const int64_t j = (int64_t)r * st.pitch + c;
+    st.F[0][j] = E;
+    st.Y[j] = (f - p.center) * p.inv_T;
+    st.a[i] = E;
+    st.ap[i] = 0.f;
+    st.z[i] = x * p.X;
+    st.P[i] = 0.0;
+    st.Q[i] = 0.0;
+    if (st.DP) {
+      st.app[i] = 0.f;
+      st.DP[i] = 0.0;
+      st.DQ[i] = 0.0;
+    }
+  }
+}
+
+// Row pass for orders n0 .. n0 + K - 1.  LDS: F^ and y for kLsRows rows x
+// (kLsCols + 2W) columns (pitch = region_pitch-style), and the row-pass
+// output of one order (kLsRows x kLsCols) staged for a coalesced store.
+template <int KT>
+__global__ __launch_bounds__(kThreads) void ls_rows_kernel(TileParams p, LsState st, int n0, int K,
+                                                           int src) {
+  extern __shared__ float lds[];
+  const int W = p.W;
+  const int RW = kLsCols + 2 * W;
+  const int RWp = (RW % 4 == 2) ? RW : RW + 2;
+  const int HP = kLsCols + 2;
+  const int npx = kLsRows * RWp;
+  float* Fl = lds;
+  float* Yl = lds + align4(npx);
+  float* Hl = Yl + align4(npx);
+  const int tiles_x = (p.Wd + kLsCols - 1) / kLsCols;
+  const int tile = blockIdx.x;
+  const int ty = tile / tiles_x, tx = tile - (tile / tiles_x) * tiles_x;
+  const int r0 = ty * kLsRows, c0 = tx * kLsCols;
+  const float* Fin = st.F[src];
+  float* Fout = st.F[src ^ 1];
+  for (int q = threadIdx.x; q < npx; q += kThreads) {
+    const int row = q / RWp, col = q - row * RWp;
+    const int gr = r0 + row, gc = c0 - W + col;
+    float F = 0.f, y = 0.f;
+    if (col < RW && gr < p.H && gc >= 0 && gc < p.Wd) {
+      const int64_t j = (int64_t)gr * st.pitch + gc;
+      F = Fin[j];
+      y = st.Y[j];
+    }
+    Fl[q] = F;
+    Yl[q] = y;
+  }
+  const float* tz = p.taps + kTapPad;
+  constexpr int S = (KT == BF_BOX) ? kRowSegBox : kRowSegFir;
+  constexpr int nseg = kLsCols / S;
+  for (int k = 0; k < K; ++k) {
+    __syncthreads();
+    for (int it = threadIdx.x; it < kLsRows * nseg; it += kThreads) {
+      const int seg = it / kLsRows;
+      const int r = it - seg * kLsRows;
+      float o[S];
+      if (KT == BF_BOX)
+        box1d<S>(Fl + r * RWp + seg * S, 1, 2 * W + 1, o);
+      else
+        fir1d<S>(Fl + r * RWp + seg * S, 1, 2 * W + 1, tz, o);
+#pragma unroll
+      for (int s = 0; s < S; ++s) Hl[r * HP + seg * S + s] = o[s];
+    }
+    __syncthreads();
+    // coalesced store of this order's row-filtered rows; advance F^ by one power
+    float* Hk = st.H[k] + (int64_t)W * st.pitch;  // W zero rows above the image
+    for (int q = threadIdx.x; q < kLsRows * kLsCols; q += kThreads) {
+      const int row = q / kLsCols, col = q - row * kLsCols;
+      const int gr = r0 + row, gc = c0 + col;
+      if (gr < p.H && gc < p.Wd) Hk[(int64_t)gr * st.pitch + gc] = Hl[row * HP + col];
+    }
+    for (int q = threadIdx.x; q < npx; q += kThreads) Fl[q] *= Yl[q];
+  }
+  __syncthreads();
+  for (int q = threadIdx.x; q < kLsRows * kLsCols; q += kThreads) {
+    const int row = q / kLsCols, col = q - row * kLsCols;
+    const int gr = r0 + row, gc = c0 + col;
+    if (gr < p.H && gc < p.Wd) Fout[(int64_t)gr * st.pitch + gc] = Fl[row * RWp + col + W];
+  }
+}
+
+// Column pass + accumulation for orders n0 .. n0 + K - 1.  The thread owns
+// column c and kLsOpt consecutive rows; row-filtered images carry W zero rows
+// above and below the image, so the column window never leaves the buffer.
+template <int KT, bool SAVE>
+__global__ __launch_bounds__(kThreads) void ls_cols_kernel(TileParams p, LsState st, int n0, int K) {
+  const int tiles_x = (p.Wd + kTileCols - 1) / kTileCols;
+  const int tile = xcd_remap(blockIdx.x, gridDim.x);
+  const int ty = tile / tiles_x, tx = tile - (tile / tiles_x) * tiles_x;
+  const int lane = threadIdx.x & 63;
+  const int r0 = ty * 4 * kLsOpt + (threadIdx.x >> 6) * kLsOpt;
+  const int c = tx * kTileCols + lane;
+  const int W = p.W, N = p.N;
+  const float* tz = p.taps + kTapPad;
+  float a[kLsOpt], ap[kLsOpt], app[kLsOpt], z[kLsOpt];
+  double P[kLsOpt], Q[kLsOpt], DP[kLsOpt], DQ[kLsOpt];
+#pragma unroll
+  for (int s = 0; s < kLsOpt; ++s) {
+    const int r = r0 + s;
+    const bool ok = r < p.H && c < p.Wd;
+    const int64_t i = (int64_t)r * p.Wd + c;
+    a[s] = ok ? st.a[i] : 0.f;
+    ap[s] = ok ? st.ap[i] : 0.f;
+    z[s] = ok ? st.z[i] : 0.f;
+    P[s] = ok ? st.P[i] : 0.0;
+    Q[s] = ok ? st.Q[i] : 0.0;
+    if (SAVE) {
+      app[s] = ok ? st.app[i] : 0.f;
+      DP[s] = ok ? st.DP[i] : 0.0;
+      DQ[s] = ok ? st.DQ[i] : 0.0;
+    }
+  }
+  const int cc = c < p.Wd ? c : p.Wd - 1;  // lanes past the width read a valid column
+  for (int k = 0; k < K; ++k) {
+    const int n = n0 + k;
+    // rows r0 - W .. r0 + kLsOpt - 1 + W of the image = rows r0 .. of the padded buffer
+    const float* col = st.H[k] + (int64_t)r0 * st.pitch + cc;
+    float v[kLsOpt];
+    if (KT == BF_BOX)
+      box1d<kLsOpt>(col, (int)st.pitch, 2 * W + 1, v);
+    else
+      fir1d<kLsOpt>(col, (int)st.pitch, 2 * W + 1, tz, v);
+    const float in1 = p.inv_tab[n + 1];
+#pragma unroll
+    for (int s = 0; s < kLsOpt; ++s) {
+      if (n < N) Q[s] = fma((double)a[s], (double)v[s], Q[s]);
+      if (n >= 1) P[s] = fma((double)ap[s], (double)v[s], P[s]);
+      if (SAVE) {
+        if (n >= 1 && n < N) DQ[s] = fma((double)ap[s], (double)v[s], DQ[s]);
+        if (n >= 2) DP[s] = fma((double)app[s], (double)v[s], DP[s]);
+        app[s] = ap[s];
+      }
+      ap[s] = a[s];
+      a[s] *= z[s] * in1;
+    }
+  }
+#pragma unroll
+  for (int s = 0; s < kLsOpt; ++s) {
+    const int r = r0 + s;
+    if (r < p.H && c < p.Wd) {
+      const int64_t i = (int64_t)r * p.Wd + c;
+      st.a[i] = a[s];
+      st.ap[i] = ap[s];
+      st.P[i] = P[s];
+      st.Q[i] = Q[s];
+      if (SAVE) {
+        st.app[i] = app[s];
+        st.DP[i] = DP[s];
+        st.DQ[i] = DQ[s];
+      }
+    }
+  }
+}
+
+__global__ __launch_bounds__(kThreads) void ls_final_kernel(TileParams p, LsState st) {
+  const int64_t npx = (int64_t)p.H * p.Wd;
+  const double X = (double)p.X;
+  for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < npx;
+       i += (int64_t)gridDim.x * kThreads) {
+    const int r = (int)(i / p.Wd), c = (int)(i - (int64_t)r * p.Wd);
+    const double q = st.Q[i];
+    const double ratio = X * st.P[i] / q;
+    if (p.out) p.out[(int64_t)r * p.out_pitch + c] = (float)((double)p.sigma_r * ratio + (double)p.center);
+    if (p.saved && st.DP) {
+      p.saved[i] = (float)q;
+      p.saved[p.saved_plane + i] = (float)ratio;
+      p.saved[2 * p.saved_plane + i] = (float)(X * X * st.DP[i] - ratio * X * st.DQ[i]);
+    }
+  }
+}
+
+int64_t ls_rows_lds_bytes(int W) {
+  const int RW = kLsCols + 2 * W;
+  const int RWp = (RW % 4 == 2) ? RW : RW + 2;
+  const int64_t npx = (int64_t)kLsRows * RWp;
+  return 4 * (2 * ((npx + 3) & ~3LL) + (int64_t)kLsRows * (kLsCols + 2));
+}
+
+bool ls_supported(int W) { return ls_rows_lds_bytes(W) <= max_lds_bytes(); }
+
+int64_t ls_state_bytes(int H, int Wd, int W, bool save) {
+  const int64_t pitch = ((Wd + 63) / 64) * 64;
+  const int64_t img = pitch * H;
+  const int64_t himg = pitch * (((H + 4 * kLsOpt - 1) / (4 * kLsOpt)) * (4 * kLsOpt) + 2 * W);
+  const int64_t npx = (int64_t)H * Wd;
+  int64_t b = 3 * img * 4 + (int64_t)kLsBlock * himg * 4 + 3 * npx * 4 + 2 * npx * 8;
+  if (save) b += npx * 4 + 2 * npx * 8;
+  return b + 256 * 32;
+}
+
+// Carve the state buffers out of one allocation.
+LsState ls_layout(void* base, int H, int Wd, int W, bool save) {
+  LsState st;
+  const int64_t pitch = ((Wd + 63) / 64) * 64;
+  const int64_t img = pitch * H;
+  const int64_t himg = pitch * (((H + 4 * kLsOpt - 1) / (4 * kLsOpt)) * (4 * kLsOpt) + 2 * W);
+  const int64_t npx = (int64_t)H * Wd;
+  char* q = (char*)base;
+  auto take = [&](int64_t bytes) {
+    char* r = q;
+    q += (bytes + 255) & ~255LL;
+    return (void*)r;
+  };
+  st.pitch = pitch;
+  st.F[0] = (float*)take(img * 4);
+  st.F[1] = (float*)take(img * 4);
+  st.Y = (float*)take(img * 4);
+  for (int k = 0; k < kLsBlock; ++k) st.H[k] = (float*)take(himg * 4);
+  st.a = (float*)take(npx * 4);
+  st.ap = (float*)take(npx * 4);
+  st.z = (float*)take(npx * 4);
+  st.P = (double*)take(npx * 8);
+  st.Q = (double*)take(npx * 8);
+  st.app = nullptr;
+  st.DP = st.DQ = nullptr;
+  if (save) {
+    st.app = (float*)take(npx * 4);
+    st.DP = (double*)take(npx * 8);
+    st.DQ = (double*)take(npx * 8);
+  }
+  st.hbytes = himg * 4;
+  return st;
+}
+
+hipError_t launch_forward_ls(const TileParams& p, const LsState& st, bool save, hipStream_t s) {
+  if (p.H <= 0 || p.Wd <= 0) return hipSuccess;
+  if (save != (st.DP != nullptr)) return hipErrorInvalidValue;
+  const int64_t npx = (int64_t)p.H * p.Wd;
+  const int g1 = (int)std::min<int64_t>((npx + kThreads - 1) / kThreads, 4096);
+  hipLaunchKernelGGL(ls_init_kernel, dim3(g1), dim3(kThreads), 0, s, p, st);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int64_t rl = ls_rows_lds_bytes(p.W);
+  auto rk = p.kt == BF_BOX ? ls_rows_kernel<BF_BOX> : ls_rows_kernel<BF_GAUSS>;
+  e = hipFuncSetAttribute((const void*)rk, hipFuncAttributeMaxDynamicSharedMemorySize, max_lds_bytes());
+  if (e != hipSuccess) return e;
+  const int grow = ((p.H + kLsRows - 1) / kLsRows) * ((p.Wd + kLsCols - 1) / kLsCols);
+  const int gcol = ((p.H + 4 * kLsOpt - 1) / (4 * kLsOpt)) * ((p.Wd + kTileCols - 1) / kTileCols);
+  int src = 0;
+  for (int n0 = 0; n0 <= p.N; n0 += kLsBlock) {
+    const int K = std::min(kLsBlock, p.N + 1 - n0);
+    hipLaunchKernelGGL(rk, dim3(grow), dim3(kThreads), (size_t)rl, s, p, st, n0, K, src);
+    if (p.kt == BF_BOX) {
+      if (save)
+        hipLaunchKernelGGL((ls_cols_kernel<BF_BOX, true>), dim3(gcol), dim3(kThreads), 0, s, p, st, n0, K);
+      else
+        hipLaunchKernelGGL((ls_cols_kernel<BF_BOX, false>), dim3(gcol), dim3(kThreads), 0, s, p, st, n0, K);
+    } else {
+      if (save)
+        hipLaunchKernelGGL((ls_cols_kernel<BF_GAUSS, true>), dim3(gcol), dim3(kThreads), 0, s, p, st, n0, K);
+      else
+        hipLaunchKernelGGL((ls_cols_kernel<BF_GAUSS, false>), dim3(gcol), dim3(kThreads), 0, s, p, st, n0, K);
+    }
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    src ^= 1;
+  }
+  hipLaunchKernelGGL(ls_final_kernel, dim3(g1), dim3(kThreads), 0, s, p, st);
+  return hipGetLastError();
+}
+
+}  // namespace bfgpa

@@ -203,37 +203,63 @@ static void gpa_tables(double lam, int N, std::vector<double>& s, std::vector<do
   }
 }
 
-static int choose_forward_tile(int W, int H, int Wd, int* variant, int* TY) {
+// Rough per-output cost of a tile shape (VALU instructions per order n),
+// scaled up when the register footprint limits waves per SIMD.
+static double tile_cost(int kernel, int W, int opt, int mreg) {
+  const int TY = 4 * opt;
+  const double area = (double)TY * kTileCols;
+  const double L = 2.0 * W + 1.0;
+  const double rows = (double)(TY + 2 * W);
+  const double npx = (double)region_floats(TY, W);
+  double row, col;
+  if (kernel == BF_BOX) {
+    row = rows * kTileCols * (2.0 + L / kRowSegBoxHost);
+    col = area * (2.0 + L / opt);
+  } else {
+    row = rows * kTileCols * (L + 4.0);
+    col = area * (L + 4.0);
+  }
+  const double upd = 2.0 * npx;
+  const double acc = 5.0 * area;
+  const double regs = 2.0 * mreg + 9.0 * opt + 40.0;
+  const double occ = regs <= 128 ? 1.0 : regs <= 168 ? 1.1 : regs <= 256 ? 1.3 : 1.8;
+  return (row + col + upd + acc) / area * occ;
+}
+
+static int choose_forward_tile(int kernel, int W, int H, int Wd, int* variant, int* TY) {
   const int nv = forward_variant_count();
-  for (int want : {64, 32, 16, 8, 4}) {
-    for (int v = 0; v < nv; ++v) {
-      Variant vv = forward_variant(v);
-      if (want > 4 * vv.opt) continue;
-      if (region_floats(want, W) > (int64_t)kThreads * vv.mreg) continue;
-      if (forward_lds_bytes(want, W) > max_lds_bytes()) continue;
-      // keep at least ~2 workgroups per CU when the image allows it
-      int64_t tiles = (int64_t)((H + want - 1) / want) * ((Wd + kTileCols - 1) / kTileCols);
-      if (want > 16 && tiles < 512 && H > 0) continue;
-      *variant = v;
-      *TY = want;
-      return BF_OK;
+  int best = -1;
+  double bestc = 0.0;
+  for (int v = 0; v < nv; ++v) {
+    Variant vv = forward_variant(v);
+    const int ty = 4 * vv.opt;
+    if (region_floats(ty, W) > (int64_t)kThreads * vv.mreg) continue;
+    if (forward_lds_bytes(ty, W) > max_lds_bytes()) continue;
+    double c = tile_cost(kernel, W, vv.opt, vv.mreg);
+    // small images: prefer shapes that give every CU at least one tile
+    const int64_t tiles = (int64_t)((H + ty - 1) / ty) * ((Wd + kTileCols - 1) / kTileCols);
+    if (tiles < 256) c *= 1.0 + (256.0 - tiles) / 256.0;
+    if (best < 0 || c < bestc) {
+      best = v;
+      bestc = c;
     }
   }
-  return fail(BF_EUNSUPPORTED, "support W too large for the fused tile kernels");
+  if (best < 0) return fail(BF_EUNSUPPORTED, "support W too large for the fused tile kernels");
+  *variant = best;
+  *TY = 4 * forward_variant(best).opt;
+  return BF_OK;
 }
 
 static int choose_backward_tile(int W, bool sigs, int* variant, int* TY) {
   const int nv = backward_variant_count();
-  for (int want : {32, 16, 8, 4}) {
-    for (int v = 0; v < nv; ++v) {
-      Variant vv = backward_variant(v);
-      if (want > 4 * vv.opt) continue;
-      if (region_floats(want, W) > (int64_t)kThreads * vv.mreg) continue;
-      if (backward_lds_bytes(want, W, sigs) + 2 * kThreads * 8 > max_lds_bytes()) continue;
-      *variant = v;
-      *TY = want;
-      return BF_OK;
-    }
+  for (int v = 0; v < nv; ++v) {
+    Variant vv = backward_variant(v);
+    const int ty = 4 * vv.opt;
+    if (region_floats(ty, W) > (int64_t)kThreads * vv.mreg) continue;
+    if (backward_lds_bytes(ty, W, sigs) + 2 * kThreads * 8 > max_lds_bytes()) continue;
+    *variant = v;
+    *TY = ty;
+    return BF_OK;
   }
   return fail(BF_EUNSUPPORTED, "support W too large for the adjoint tile kernels");
 }
@@ -272,9 +298,13 @@ int bf_order(const bf_params* in, bf_plan_info* out) {
   st = plan_order(&p, out);
   if (st < 0) return st;
   int v, ty;
-  if (p.height > 0 && p.width > 0 && choose_forward_tile(p.W, p.height, p.width, &v, &ty) == BF_OK) {
-    out->tile_rows = ty;
-    out->tile_cols = kTileCols;
+  if (p.height > 0 && p.width > 0) {
+    if (choose_forward_tile(p.kernel, p.W, p.height, p.width, &v, &ty) == BF_OK) {
+      out->tile_rows = ty;
+      out->tile_cols = kTileCols;
+    } else if (!ls_supported(p.W)) {
+      return fail(BF_EUNSUPPORTED, "support W too large");
+    }
   }
   return st;
 }
@@ -290,8 +320,15 @@ int bf_plan(const bf_params* in, bf_plan_t** out) {
   int ost = plan_order(&p, &info);
   if (ost < 0) return ost;
   int variant = 0, TY = 0;
-  st = choose_forward_tile(p.W, p.height, p.width, &variant, &TY);
-  if (st < 0) return st;
+  bool ls = false;
+  st = (p.flags & BF_FLAG_STREAMED) ? BF_EUNSUPPORTED
+                                      : choose_forward_tile(p.kernel, p.W, p.height, p.width, &variant, &TY);
+  if (st < 0) {
+    if (!ls_supported(p.W)) return fail(BF_EUNSUPPORTED, "support W too large");
+    ls = true;  // large-support path through device memory
+    variant = -1;
+    TY = 0;
+  }
   const bool grad = (p.flags & BF_FLAG_GRAD) != 0;
   const bool sigs = p.kernel == BF_GAUSS;
   int bvariant = -1, bTY = 0;
@@ -310,6 +347,9 @@ int bf_plan(const bf_params* in, bf_plan_t** out) {
   pl->TY = TY;
   pl->bvariant = bvariant;
   pl->bTY = bTY;
+  pl->ls = ls;
+  pl->d_ls = nullptr;
+  std::memset(&pl->ls_state, 0, sizeof(pl->ls_state));
   hipGetDevice(&pl->device);
 
   // constant tables: s, r, inv (N+2 each), taps and d^2 taps (padded)
@@ -353,6 +393,26 @@ int bf_plan(const bf_params* in, bf_plan_t** out) {
     }
     ws += 2 * (int64_t)pl->ntiles_b * sizeof(double);
   }
+  if (ls) {
+    const int64_t lb = ls_state_bytes(p.height, p.width, p.W, grad);
+    e = hipMalloc(&pl->d_ls, lb);
+    if (e != hipSuccess) {
+      if (pl->d_work) hipFree(pl->d_work);
+      if (pl->d_partials) hipFree(pl->d_partials);
+      hipFree(pl->d_const);
+      delete pl;
+      return fail(BF_ENOMEM, "hipMalloc large-support state failed");
+    }
+    e = hipMemset(pl->d_ls, 0, lb);  // zero rows around the row-filtered images
+    if (e != hipSuccess) {
+      hipFree(pl->d_ls);
+      hipFree(pl->d_const);
+      delete pl;
+      return hip_fail(e, "hipMemset large-support state");
+    }
+    pl->ls_state = ls_layout(pl->d_ls, p.height, p.width, p.W, grad);
+    ws += lb;
+  }
   pl->info.workspace_bytes = ws;
   *out = pl;
   if (ost == BF_WNOGUARANTEE) set_error("order below the bound: no +-delta guarantee");
@@ -373,6 +433,7 @@ int bf_destroy(bf_plan_t* plan) {
   if (plan->d_const) hipFree(plan->d_const);
   if (plan->d_work) hipFree(plan->d_work);
   if (plan->d_partials) hipFree(plan->d_partials);
+  if (plan->d_ls) hipFree(plan->d_ls);
   hipSetDevice(dev);
   delete plan;
   return BF_OK;
@@ -391,6 +452,8 @@ static void fill_common(const bf_plan_t* pl, TileParams& tp) {
   tp.sigma_r = (float)p.sigma_r;
   tp.inv_sigma_r = (float)(1.0 / p.sigma_r);
   tp.center = (float)p.center;
+  tp.inv_T = (float)(1.0 / p.T);
+  tp.X = (float)(p.T / p.sigma_r);
   tp.inv_sigma_s3 = p.kernel == BF_GAUSS ? (float)(1.0 / (p.sigma_s * p.sigma_s * p.sigma_s)) : 0.0f;
   const int64_t st = pl->tab_stride;
   tp.s_tab = pl->d_const;
@@ -422,7 +485,14 @@ int bf_forward(const bf_plan_t* pl, const float* in, int64_t in_pitch, float* ou
   tp.TY = pl->TY;
   tp.tiles_x = (pl->p.width + kTileCols - 1) / kTileCols;
   const bool acc64 = (pl->p.flags & BF_FLAG_FP32_ACCUM) == 0;
-  hipError_t e = launch_forward(tp, pl->variant, acc64, saved != nullptr, (hipStream_t)stream);
+  hipError_t e;
+  if (pl->ls) {
+    if (saved && !pl->ls_state.DP)
+      return fail(BF_EINVAL, "saved state needs a plan built with BF_FLAG_GRAD");
+    e = launch_forward_ls(tp, pl->ls_state, saved != nullptr, (hipStream_t)stream);
+  } else {
+    e = launch_forward(tp, pl->variant, acc64, saved != nullptr, (hipStream_t)stream);
+  }
   if (e != hipSuccess) return hip_fail(e, "forward launch");
   return BF_OK;
 }

@@ -159,3 +159,55 @@ def test_explicit_order_and_rules():
     assert plan.info.N == 20 and plan.info.status == 1  # BF_WNOGUARANTEE
     ref = G.gpa_alg2(f32, K.taps1d("box", W=4), 30.0, 20, 127.5)
     assert np.abs(out - ref).max() <= TOL
+
+
+# --- large supports: the blocked path through device memory ---------------
+
+@pytest.mark.parametrize("kind,kw,sr,shape", [("box", dict(W=75), 50.0, (200, 330)),
+                                              ("box", dict(W=75), 10.0, (90, 170)),
+                                              ("gauss", dict(sigma_s=25.0), 30.0, (170, 260)),
+                                              ("gauss", dict(sigma_s=16.0, streamed=True), 12.0, (100, 140)),
+                                              ("box", dict(W=60), 30.0, (40, 50))])
+def test_large_support(kind, kw, sr, shape):
+    f = synthimg.gen2(*shape, 77)
+    out, plan, f32 = _gpu_forward(f, kind, sr, **kw)
+    assert plan.info.tile_rows == 0  # streamed path
+    kw = {k: v for k, v in kw.items() if k != "streamed"}
+    w1, _ = _taps(kind, kw)
+    ref = G.gpa_alg2(f32, w1, sr, plan.info.N, 127.5)
+    print(f"{kind} {kw} sr={sr} N={plan.info.N}", flush=True)
+    _report("gpu-alg2", out - ref)
+    assert np.abs(out - ref).max() <= TOL
+
+
+@pytest.mark.parametrize("kind,kw,sr", [("box", dict(W=7), 30.0), ("gauss", dict(sigma_s=3.0), 20.0)])
+def test_streamed_matches_fused(kind, kw, sr):
+    torch, P = _mods()
+    f = synthimg.gen2(150, 210, 78)
+    x = torch.tensor(f, dtype=torch.float32, device="cuda")
+    a = P.Plan(kind, sr, 150, 210, **kw).forward(x)
+    ps = P.Plan(kind, sr, 150, 210, streamed=True, **kw)
+    b = ps.forward(x)
+    torch.cuda.synchronize()
+    assert ps.info.tile_rows == 0
+    assert (a - b).abs().max().item() <= 1e-4
+    w1, _ = _taps(kind, kw)
+    ref = G.gpa_alg2(x.cpu().numpy().astype(np.float64), w1, sr, ps.info.N, 127.5)
+    assert np.abs(b.cpu().numpy() - ref).max() <= TOL
+
+
+@pytest.mark.parametrize("kind,kw,sr", [("box", dict(W=75), 30.0), ("gauss", dict(sigma_s=25.0), 50.0),
+                                        ("box", dict(W=30), 10.0), ("gauss", dict(sigma_s=10.0), 30.0)])
+def test_workload3_sampled(kind, kw, sr):
+    # 4096^2 gen2, checked pixel by pixel on a sample (incl. the border band)
+    f = synthimg.gen2(4096, 4096, 3000)
+    out, plan, f32 = _gpu_forward(f, kind, sr, **kw)
+    _, w2 = _taps(kind, kw)
+    W = plan.info.W
+    n = 60 if W > 40 else 300
+    px = synthimg.sample_pixels(4096, 4096, n, W, n // 3, 3001)
+    o2 = G.gpa_pairwise_at(f32, px, w2, sr, plan.info.N, 127.5)
+    got = out[px[:, 0], px[:, 1]]
+    print(f"N={plan.info.N} pixels={len(px)} tile_rows={plan.info.tile_rows}", flush=True)
+    _report("gpu-O2", got - o2)
+    assert np.abs(got - o2).max() <= TOL
