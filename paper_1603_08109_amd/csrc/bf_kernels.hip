@@ -22,7 +22,7 @@ __global__ __launch_bounds__(kThreads) void gpa_forward_kernel(TileParams p) {
 }
 
 // (output rows per thread, region pixels per thread); tile rows = 4 * OPT.
-static const Variant kFwdVariants[] = {{8, 12}, {8, 20}, {8, 32}, {16, 40}, {4, 32}, {4, 48}, {4, 72}};
+static const Variant kFwdVariants[] = {{8, 12}, {8, 20}, {8, 32}, {16, 40}, {4, 32}, {4, 48}, {4, 72}, {8, 48}};
 static constexpr int kNumFwdVariants = sizeof(kFwdVariants) / sizeof(kFwdVariants[0]);
 int forward_variant_count() { return kNumFwdVariants; }
 Variant forward_variant(int v) { return kFwdVariants[v]; }
@@ -69,7 +69,8 @@ static hipError_t launch_fwd_k(const TileParams& p, int variant, bool acc64, boo
     case 3: return launch_fwd_v<KT, 16, 40>(p, acc64, save, s);
     case 4: return launch_fwd_v<KT, 4, 32>(p, acc64, save, s);
     case 5: return launch_fwd_v<KT, 4, 48>(p, acc64, save, s);
-    default: return launch_fwd_v<KT, 4, 72>(p, acc64, save, s);
+    case 6: return launch_fwd_v<KT, 4, 72>(p, acc64, save, s);
+    default: return launch_fwd_v<KT, 8, 48>(p, acc64, save, s);
   }
 }
 

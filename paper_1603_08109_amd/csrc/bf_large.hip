@@ -117,77 +117,147 @@ __global__ __launch_bounds__(kThreads) void ls_rows_kernel(TileParams p, LsState
   }
 }
 
-// Column pass + accumulation for orders n0 .. n0 + K - 1.  The thread owns
-// column c and kLsOpt consecutive rows; row-filtered images carry W zero rows
-// above and below the image, so the column window never leaves the buffer.
-template <int KT, bool SAVE>
-__global__ __launch_bounds__(kThreads) void ls_cols_kernel(TileParams p, LsState st, int n0, int K) {
+// Per-pixel coefficient state of the streamed path, held in registers for
+// CH pixels while the orders of one block are folded in.
+template <int CH, bool SAVE>
+struct LsPix {
+  float a[CH], ap[CH], app[CH], z[CH];
+  double P[CH], Q[CH], DP[CH], DQ[CH];
+
+  __device__ __forceinline__ void load(const LsState& st, int64_t i0, int64_t stride, int n_ok) {
+#pragma unroll
+    for (int s = 0; s < CH; ++s) {
+      const bool ok = s < n_ok;
+      const int64_t i = i0 + s * stride;
+      a[s] = ok ? st.a[i] : 0.f;
+      ap[s] = ok ? st.ap[i] : 0.f;
+      z[s] = ok ? st.z[i] : 0.f;
+      P[s] = ok ? st.P[i] : 0.0;
+      Q[s] = ok ? st.Q[i] : 0.0;
+      if (SAVE) {
+        app[s] = ok ? st.app[i] : 0.f;
+        DP[s] = ok ? st.DP[i] : 0.0;
+        DQ[s] = ok ? st.DQ[i] : 0.0;
+      }
+    }
+  }
+  __device__ __forceinline__ void store(const LsState& st, int64_t i0, int64_t stride, int n_ok) const {
+#pragma unroll
+    for (int s = 0; s < CH; ++s) {
+      if (s < n_ok) {
+        const int64_t i = i0 + s * stride;
+        st.a[i] = a[s];
+        st.ap[i] = ap[s];
+        st.P[i] = P[s];
+        st.Q[i] = Q[s];
+        if (SAVE) {
+          st.app[i] = app[s];
+          st.DP[i] = DP[s];
+          st.DQ[i] = DQ[s];
+        }
+      }
+    }
+  }
+  // fold F_bar_n (value v at pixel s) into eqs. (P), (Q) and advance a_n
+  __device__ __forceinline__ void fold(int s, int n, int N, float v, float in1) {
+    if (n < N) Q[s] = fma((double)a[s], (double)v, Q[s]);
+    if (n >= 1) P[s] = fma((double)ap[s], (double)v, P[s]);
+    if (SAVE) {
+      if (n >= 1 && n < N) DQ[s] = fma((double)ap[s], (double)v, DQ[s]);
+      if (n >= 2) DP[s] = fma((double)app[s], (double)v, DP[s]);
+      app[s] = ap[s];
+    }
+    ap[s] = a[s];
+    a[s] *= z[s] * in1;
+  }
+};
+
+// Box column pass: each thread walks a column segment of `seg_rows` rows
+// with one running window sum per order of the block (two reads per output),
+// CH pixels at a time.  Row-filtered images carry W zero rows above and
+// below the image, so the window never leaves the buffer.
+template <bool SAVE>
+__global__ __launch_bounds__(kThreads) void ls_cols_box_kernel(TileParams p, LsState st, int n0, int K,
+                                                               int seg_rows) {
+  constexpr int CH = 8;
+  const int c = blockIdx.x * kTileCols + (threadIdx.x & 63);
+  const int rs = (blockIdx.y * 4 + (threadIdx.x >> 6)) * seg_rows;
+  if (c >= p.Wd || rs >= p.H) return;  // no barriers in this kernel
+  const int re = min(rs + seg_rows, p.H);
+  const int L = 2 * p.W + 1;
+  const int64_t pitch = st.pitch;
+  float V[kLsBlock];
+#pragma unroll
+  for (int k = 0; k < kLsBlock; ++k)
+    V[k] = (k < K) ? strided_sum(st.H[k] + (int64_t)rs * pitch + c, (int)pitch, 0, L) : 0.f;
+  LsPix<CH, SAVE> px;
+  for (int r = rs; r < re; r += CH) {
+    const int nr = min(CH, re - r);
+    px.load(st, (int64_t)r * p.Wd + c, p.Wd, nr);
+#pragma unroll
+    for (int k = 0; k < kLsBlock; ++k) {
+      if (k < K) {
+        const int n = n0 + k;
+        const float in1 = p.inv_tab[n + 1];
+        const float* hk = st.H[k] + c;
+        float enter[CH], leave[CH];
+#pragma unroll
+        for (int s = 0; s < CH; ++s) {
+          enter[s] = s < nr ? hk[(int64_t)(r + s + L) * pitch] : 0.f;
+          leave[s] = s < nr ? hk[(int64_t)(r + s) * pitch] : 0.f;
+        }
+#pragma unroll
+        for (int s = 0; s < CH; ++s) {
+          if (s < nr) {
+            px.fold(s, n, p.N, V[k], in1);
+            V[k] += enter[s] - leave[s];
+          }
+        }
+      }
+    }
+    px.store(st, (int64_t)r * p.Wd + c, p.Wd, nr);
+  }
+}
+
+// FIR column pass: the workgroup stages the column window of one order's
+// row-filtered image (4*OPT + 2W rows x 64 columns) in LDS; each thread
+// filters its column over OPT output rows.  LDS pitch 80 keeps the paired
+// reads of adjacent rows conflict-free.
+constexpr int kLsColPitch = 80;
+
+template <int OPT, bool SAVE>
+__global__ __launch_bounds__(kThreads) void ls_cols_fir_kernel(TileParams p, LsState st, int n0, int K) {
+  extern __shared__ float lds[];
   const int tiles_x = (p.Wd + kTileCols - 1) / kTileCols;
   const int tile = xcd_remap(blockIdx.x, gridDim.x);
   const int ty = tile / tiles_x, tx = tile - (tile / tiles_x) * tiles_x;
   const int lane = threadIdx.x & 63;
-  const int r0 = ty * 4 * kLsOpt + (threadIdx.x >> 6) * kLsOpt;
-  const int c = tx * kTileCols + lane;
-  const int W = p.W, N = p.N;
+  const int tr0 = ty * 4 * OPT;
+  const int orow = (threadIdx.x >> 6) * OPT;
+  const int c0 = tx * kTileCols;
+  const int c = c0 + lane;
+  const int W = p.W;
+  const int rows = 4 * OPT + 2 * W;
   const float* tz = p.taps + kTapPad;
-  float a[kLsOpt], ap[kLsOpt], app[kLsOpt], z[kLsOpt];
-  double P[kLsOpt], Q[kLsOpt], DP[kLsOpt], DQ[kLsOpt];
-#pragma unroll
-  for (int s = 0; s < kLsOpt; ++s) {
-    const int r = r0 + s;
-    const bool ok = r < p.H && c < p.Wd;
-    const int64_t i = (int64_t)r * p.Wd + c;
-    a[s] = ok ? st.a[i] : 0.f;
-    ap[s] = ok ? st.ap[i] : 0.f;
-    z[s] = ok ? st.z[i] : 0.f;
-    P[s] = ok ? st.P[i] : 0.0;
-    Q[s] = ok ? st.Q[i] : 0.0;
-    if (SAVE) {
-      app[s] = ok ? st.app[i] : 0.f;
-      DP[s] = ok ? st.DP[i] : 0.0;
-      DQ[s] = ok ? st.DQ[i] : 0.0;
-    }
-  }
-  const int cc = c < p.Wd ? c : p.Wd - 1;  // lanes past the width read a valid column
+  const int nr = max(0, min(OPT, p.H - (tr0 + orow)));
+  LsPix<OPT, SAVE> px;
+  if (c < p.Wd) px.load(st, (int64_t)(tr0 + orow) * p.Wd + c, p.Wd, nr);
   for (int k = 0; k < K; ++k) {
     const int n = n0 + k;
-    // rows r0 - W .. r0 + kLsOpt - 1 + W of the image = rows r0 .. of the padded buffer
-    const float* col = st.H[k] + (int64_t)r0 * st.pitch + cc;
-    float v[kLsOpt];
-    if (KT == BF_BOX)
-      box1d<kLsOpt>(col, (int)st.pitch, 2 * W + 1, v);
-    else
-      fir1d<kLsOpt>(col, (int)st.pitch, 2 * W + 1, tz, v);
+    __syncthreads();
+    const float* hk = st.H[k] + (int64_t)tr0 * st.pitch + c0;  // padded row tr0 = image row tr0 - W
+    for (int q = threadIdx.x; q < rows * kTileCols; q += kThreads) {
+      const int rr = q >> 6, cc = q & 63;
+      lds[rr * kLsColPitch + cc] = (c0 + cc < p.Wd) ? hk[(int64_t)rr * st.pitch + cc] : 0.f;
+    }
+    __syncthreads();
+    float v[OPT];
+    fir1d<OPT>(lds + orow * kLsColPitch + lane, kLsColPitch, 2 * W + 1, tz, v);
     const float in1 = p.inv_tab[n + 1];
 #pragma unroll
-    for (int s = 0; s < kLsOpt; ++s) {
-      if (n < N) Q[s] = fma((double)a[s], (double)v[s], Q[s]);
-      if (n >= 1) P[s] = fma((double)ap[s], (double)v[s], P[s]);
-      if (SAVE) {
-        if (n >= 1 && n < N) DQ[s] = fma((double)ap[s], (double)v[s], DQ[s]);
-        if (n >= 2) DP[s] = fma((double)app[s], (double)v[s], DP[s]);
-        app[s] = ap[s];
-      }
-      ap[s] = a[s];
-      a[s] *= z[s] * in1;
-    }
+    for (int s = 0; s < OPT; ++s) px.fold(s, n, p.N, v[s], in1);
   }
-#pragma unroll
-  for (int s = 0; s < kLsOpt; ++s) {
-    const int r = r0 + s;
-    if (r < p.H && c < p.Wd) {
-      const int64_t i = (int64_t)r * p.Wd + c;
-      st.a[i] = a[s];
-      st.ap[i] = ap[s];
-      st.P[i] = P[s];
-      st.Q[i] = Q[s];
-      if (SAVE) {
-        st.app[i] = app[s];
-        st.DP[i] = DP[s];
-        st.DQ[i] = DQ[s];
-      }
-    }
-  }
+  if (c < p.Wd) px.store(st, (int64_t)(tr0 + orow) * p.Wd + c, p.Wd, nr);
 }
 
 __global__ __launch_bounds__(kThreads) void ls_final_kernel(TileParams p, LsState st) {
@@ -214,12 +284,16 @@ int64_t ls_rows_lds_bytes(int W) {
   return 4 * (2 * ((npx + 3) & ~3LL) + (int64_t)kLsRows * (kLsCols + 2));
 }
 
-bool ls_supported(int W) { return ls_rows_lds_bytes(W) <= max_lds_bytes(); }
+bool ls_supported(int W) {
+  return ls_rows_lds_bytes(W) <= max_lds_bytes() &&
+         (int64_t)(64 + 2 * W) * kLsColPitch * 4 <= max_lds_bytes();
+}
 
 int64_t ls_state_bytes(int H, int Wd, int W, bool save) {
   const int64_t pitch = ((Wd + 63) / 64) * 64;
   const int64_t img = pitch * H;
-  const int64_t himg = pitch * (((H + 4 * kLsOpt - 1) / (4 * kLsOpt)) * (4 * kLsOpt) + 2 * W);
+  // image rows padded to a multiple of 64, plus W zero rows above and W + 1 below
+  const int64_t himg = pitch * (((H + 4 * kLsOpt - 1) / (4 * kLsOpt)) * (4 * kLsOpt) + 2 * W + 1);
   const int64_t npx = (int64_t)H * Wd;
   int64_t b = 3 * img * 4 + (int64_t)kLsBlock * himg * 4 + 3 * npx * 4 + 2 * npx * 8;
   if (save) b += npx * 4 + 2 * npx * 8;
@@ -231,7 +305,8 @@ LsState ls_layout(void* base, int H, int Wd, int W, bool save) {
   LsState st;
   const int64_t pitch = ((Wd + 63) / 64) * 64;
   const int64_t img = pitch * H;
-  const int64_t himg = pitch * (((H + 4 * kLsOpt - 1) / (4 * kLsOpt)) * (4 * kLsOpt) + 2 * W);
+  // image rows padded to a multiple of 64, plus W zero rows above and W + 1 below
+  const int64_t himg = pitch * (((H + 4 * kLsOpt - 1) / (4 * kLsOpt)) * (4 * kLsOpt) + 2 * W + 1);
   const int64_t npx = (int64_t)H * Wd;
   char* q = (char*)base;
   auto take = [&](int64_t bytes) {
@@ -273,21 +348,38 @@ hipError_t launch_forward_ls(const TileParams& p, const LsState& st, bool save, 
   e = hipFuncSetAttribute((const void*)rk, hipFuncAttributeMaxDynamicSharedMemorySize, max_lds_bytes());
   if (e != hipSuccess) return e;
   const int grow = ((p.H + kLsRows - 1) / kLsRows) * ((p.Wd + kLsCols - 1) / kLsCols);
-  const int gcol = ((p.H + 4 * kLsOpt - 1) / (4 * kLsOpt)) * ((p.Wd + kTileCols - 1) / kTileCols);
+  const int tiles_x = (p.Wd + kTileCols - 1) / kTileCols;
+  // box: column segments long enough that the window set-up (2W + 1 reads) is
+  // amortised, short enough to give every CU several waves
+  int seg_rows = 256;
+  while (seg_rows > 16 && (int64_t)tiles_x * 4 * ((p.H + 4 * seg_rows - 1) / (4 * seg_rows)) < 2048) seg_rows /= 2;
+  const dim3 gbox(tiles_x, (p.H + 4 * seg_rows - 1) / (4 * seg_rows));
+  const int gfir8 = ((p.H + 31) / 32) * tiles_x;
+  const int gfir16 = ((p.H + 63) / 64) * tiles_x;
+  const size_t fl8 = (size_t)(32 + 2 * p.W) * kLsColPitch * 4;
+  const size_t fl16 = (size_t)(64 + 2 * p.W) * kLsColPitch * 4;
+  if (p.kt != BF_BOX) {
+    auto k8 = ls_cols_fir_kernel<8, true>;
+    auto k16 = ls_cols_fir_kernel<16, false>;
+    e = hipFuncSetAttribute((const void*)k8, hipFuncAttributeMaxDynamicSharedMemorySize, max_lds_bytes());
+    if (e == hipSuccess)
+      e = hipFuncSetAttribute((const void*)k16, hipFuncAttributeMaxDynamicSharedMemorySize, max_lds_bytes());
+    if (e != hipSuccess) return e;
+  }
   int src = 0;
   for (int n0 = 0; n0 <= p.N; n0 += kLsBlock) {
     const int K = std::min(kLsBlock, p.N + 1 - n0);
     hipLaunchKernelGGL(rk, dim3(grow), dim3(kThreads), (size_t)rl, s, p, st, n0, K, src);
     if (p.kt == BF_BOX) {
       if (save)
-        hipLaunchKernelGGL((ls_cols_kernel<BF_BOX, true>), dim3(gcol), dim3(kThreads), 0, s, p, st, n0, K);
+        hipLaunchKernelGGL((ls_cols_box_kernel<true>), gbox, dim3(kThreads), 0, s, p, st, n0, K, seg_rows);
       else
-        hipLaunchKernelGGL((ls_cols_kernel<BF_BOX, false>), dim3(gcol), dim3(kThreads), 0, s, p, st, n0, K);
+        hipLaunchKernelGGL((ls_cols_box_kernel<false>), gbox, dim3(kThreads), 0, s, p, st, n0, K, seg_rows);
     } else {
       if (save)
-        hipLaunchKernelGGL((ls_cols_kernel<BF_GAUSS, true>), dim3(gcol), dim3(kThreads), 0, s, p, st, n0, K);
+        hipLaunchKernelGGL((ls_cols_fir_kernel<8, true>), dim3(gfir8), dim3(kThreads), fl8, s, p, st, n0, K);
       else
-        hipLaunchKernelGGL((ls_cols_kernel<BF_GAUSS, false>), dim3(gcol), dim3(kThreads), 0, s, p, st, n0, K);
+        hipLaunchKernelGGL((ls_cols_fir_kernel<16, false>), dim3(gfir16), dim3(kThreads), fl16, s, p, st, n0, K);
     }
     e = hipGetLastError();
     if (e != hipSuccess) return e;

@@ -226,6 +226,15 @@ static double tile_cost(int kernel, int W, int opt, int mreg) {
   return (row + col + upd + acc) / area * occ;
 }
 
+// Same units for the streamed path: rows staged 256 wide, exact column pass,
+// plus about 20 bytes of device-memory traffic per pixel and order (~100
+// instruction slots at the chip's VALU : HBM balance).
+static double streamed_cost(int kernel, int W) {
+  const double L = 2.0 * W + 1.0;
+  if (kernel == BF_BOX) return (256.0 + 2 * W) / 256.0 * (2.0 + L / 16.0) + 2.0 + 5.0 + 100.0;
+  return (256.0 + 2 * W) / 256.0 * (L + 4.0) + (L + 4.0) + 5.0 + 100.0;
+}
+
 static int choose_forward_tile(int kernel, int W, int H, int Wd, int* variant, int* TY) {
   const int nv = forward_variant_count();
   int best = -1;
@@ -245,6 +254,10 @@ static int choose_forward_tile(int kernel, int W, int H, int Wd, int* variant, i
     }
   }
   if (best < 0) return fail(BF_EUNSUPPORTED, "support W too large for the fused tile kernels");
+  // the streamed path launches two kernels per block of 8 orders: only worth
+  // it when the image is large enough to hide those launches
+  if ((int64_t)H * Wd >= (1 << 20) && bestc > streamed_cost(kernel, W) && ls_supported(W))
+    return fail(BF_EUNSUPPORTED, "streamed path is cheaper at this support");
   *variant = best;
   *TY = 4 * forward_variant(best).opt;
   return BF_OK;
