@@ -54,6 +54,45 @@ def alg_flops_per_px_n(kind, W):
     return 1.0 + filt + 4.0 + 2.0
 
 
+def source_sha():
+    """sha256 over the HIP sources: measured HBM traffic is only reported for
+    the kernels it was measured on."""
+    import hashlib
+    h = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_1603_08109_amd", "csrc")
+    for name in sorted(os.listdir(d)):
+        with open(os.path.join(d, name), "rb") as fh:
+            h.update(name.encode() + fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(setting):
+    """HBM bytes per forward call from profiles/traffic.json (rocprofv3
+    FETCH_SIZE + WRITE_SIZE, scaled by a copy kernel of known size), or None
+    when absent or taken on other kernel sources."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        with open(path) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if t.get("source_sha") != source_sha():
+        return None
+    e = t.get("settings", {}).get(setting)
+    return None if e is None else e.get("bytes_per_call")
+
+
+def copy_probe(mb, torch):
+    """Plain device copy of `mb` MiB (calibrates the HBM byte counters)."""
+    n = mb * (1 << 20) // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes_read": n * 4, "copy_probe_bytes_written": n * 4}))
+
+
 def time_launches(fn, stream, warmup, steps, torch):
     for _ in range(warmup):
         fn()
@@ -76,6 +115,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true", help="skip the fwd+bwd and batch legs")
     ap.add_argument("--only", default="", help="comma list of sweep indices to run")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB (counter calibration)")
     a = ap.parse_args()
     if a.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
@@ -86,6 +127,9 @@ def main():
     import synthimg
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if a.copy_probe:
+        copy_probe(a.copy_probe, torch)
+        return
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream()
     H = Wd = 4096
@@ -126,14 +170,22 @@ def main():
         total_px += H * Wd
         print(f"# {r}", file=sys.stderr, flush=True)
 
+    def roof(r):
+        kind = "box" if r["setting"].startswith("box") else "gauss"
+        flops = H * Wd * (r["N"] + 1) * alg_flops_per_px_n(kind, r["W"])
+        achieved = flops / (r["ms"] * 1e-3) / 1e12
+        kern = ("gpa_forward_kernel (one launch)" if r["tile_rows"] > 0 else
+                "ls_rows_kernel + ls_cols_%s_kernel per block of 8 orders" % ("box" if kind == "box" else "fir"))
+        return {"bound": "alu", "achieved": round(achieved, 3), "peak": round(ALU_PEAK_TFLOPS, 1),
+                "unit": "TFLOP/s", "frac": round(achieved / ALU_PEAK_TFLOPS, 4),
+                "traffic": measured_traffic(r["setting"]),
+                "kernel": kern, "setting": r["setting"], "ms_per_call": r["ms"],
+                "alg_flops_per_call": flops, "hbm_frac_alg_bytes": round(r["hbm_gbs"] / HBM_PEAK_GBS, 5)}
+
     dom = max(results, key=lambda r: r["ms"])
-    dom_kind = "box" if dom["setting"].startswith("box") else "gauss"
-    dom_flops = H * Wd * (dom["N"] + 1) * alg_flops_per_px_n(dom_kind, dom["W"])
-    achieved = dom_flops / (dom["ms"] * 1e-3) / 1e12
-    roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(ALU_PEAK_TFLOPS, 1),
-                "unit": "TFLOP/s", "frac": round(achieved / ALU_PEAK_TFLOPS, 4), "traffic": None,
-                "kernel": "gpa_forward_kernel " + dom["setting"],
-                "hbm_frac": round(dom["hbm_gbs"] / HBM_PEAK_GBS, 5)}
+    roofline = roof(dom)
+    fused = [r for r in results if r["tile_rows"] > 0]
+    roofline_fused = roof(max(fused, key=lambda r: r["ms"])) if fused else None
 
     extra = {}
     if not a.no_extra:
@@ -245,6 +297,8 @@ def main():
                    "accumulation": "float64 P/Q"},
         "per_setting": results,
         "roofline": roofline,
+        "roofline_fused": roofline_fused,
+        "source_sha": source_sha(),
         "cpu_baseline": cpu,
     }
     line.update(extra)
