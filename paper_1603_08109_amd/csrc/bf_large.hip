@@ -71,17 +71,29 @@ __global__ __launch_bounds__(kThreads) void ls_rows_kernel(TileParams p, LsState
   const int r0 = ty * kLsRows, c0 = tx * kLsCols;
   const float* Fin = st.F[src];
   float* Fout = st.F[src ^ 1];
-  for (int q = threadIdx.x; q < npx; q += kThreads) {
-    const int row = q / RWp, col = q - row * RWp;
-    const int gr = r0 + row, gc = c0 - W + col;
-    float F = 0.f, y = 0.f;
-    if (col < RW && gr < p.H && gc >= 0 && gc < p.Wd) {
-      const int64_t j = (int64_t)gr * st.pitch + gc;
-      F = Fin[j];
-      y = st.Y[j];
+  for (int q0 = threadIdx.x; q0 < npx; q0 += 4 * kThreads) {
+    float F[4], y[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int q = q0 + u * kThreads;
+      const int row = q / RWp, col = q - row * RWp;
+      const int gr = r0 + row, gc = c0 - W + col;
+      F[u] = 0.f;
+      y[u] = 0.f;
+      if (q < npx && col < RW && gr < p.H && gc >= 0 && gc < p.Wd) {
+        const int64_t j = (int64_t)gr * st.pitch + gc;
+        F[u] = Fin[j];
+        y[u] = st.Y[j];
+      }
     }
-    Fl[q] = F;
-    Yl[q] = y;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int q = q0 + u * kThreads;
+      if (q < npx) {
+        Fl[q] = F[u];
+        Yl[q] = y[u];
+      }
+    }
   }
   const float* tz = p.taps + kTapPad;
   constexpr int S = (KT == BF_BOX) ? kRowSegBox : kRowSegFir;
@@ -246,9 +258,21 @@ __global__ __launch_bounds__(kThreads) void ls_cols_fir_kernel(TileParams p, LsS
     const int n = n0 + k;
     __syncthreads();
     const float* hk = st.H[k] + (int64_t)tr0 * st.pitch + c0;  // padded row tr0 = image row tr0 - W
-    for (int q = threadIdx.x; q < rows * kTileCols; q += kThreads) {
-      const int rr = q >> 6, cc = q & 63;
-      lds[rr * kLsColPitch + cc] = (c0 + cc < p.Wd) ? hk[(int64_t)rr * st.pitch + cc] : 0.f;
+    // eight loads in flight per thread before any LDS store
+    const int total = rows * kTileCols;
+    const bool col_ok = (c0 + (threadIdx.x & 63)) < p.Wd;  // q & 63 == threadIdx.x & 63 below
+    for (int q0 = threadIdx.x; q0 < total; q0 += 8 * kThreads) {
+      float v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int q = q0 + u * kThreads;
+        v[u] = (q < total && col_ok) ? hk[(int64_t)(q >> 6) * st.pitch + (q & 63)] : 0.f;
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int q = q0 + u * kThreads;
+        if (q < total) lds[(q >> 6) * kLsColPitch + (q & 63)] = v[u];
+      }
     }
     __syncthreads();
     float v[OPT];
