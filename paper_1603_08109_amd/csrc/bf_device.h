@@ -272,30 +272,36 @@ __device__ __forceinline__ void forward_tile(const TileParams& p, int r0, int c0
   const float* tz = p.taps + kTapPad;
 
   // region: F^_0 = e^{-x^2/2} into LDS, y kept in registers
+  // region: F^_0 = e^{-x^2/2} into LDS, y kept in registers.  Loads use
+  // clamped (always valid) addresses and no branches, so all MREG are in flight.
   float Fr[MREG], yr[MREG];
   for_region<MREG>(g, r0, c0, W, p.H, p.Wd, [&](int m, int q, bool inside, int gr, int gc) {
-    float y = 0.f, F = 0.f;
-    if (inside) {
-      const float f = p.in[(int64_t)gr * p.in_pitch + gc];
-      const float x = (f - p.center) / p.sigma_r;
-      y = (f - p.center) * p.inv_T;
-      F = expf(-0.5f * x * x);
-    }
-    Fr[m] = F;
-    yr[m] = y;
-    if (q < g.npx) Fs[q] = F;
+    const int cr = min(max(gr, 0), p.H - 1), cc = min(max(gc, 0), p.Wd - 1);
+    Fr[m] = p.in[(int64_t)cr * p.in_pitch + cc];
+    yr[m] = inside ? 1.f : 0.f;
   });
+#pragma unroll
+  for (int m = 0; m < MREG; ++m) {
+    const float f = Fr[m];
+    const bool inside = yr[m] != 0.f;
+    const float x = (f - p.center) / p.sigma_r;
+    yr[m] = inside ? (f - p.center) * p.inv_T : 0.f;
+    Fr[m] = inside ? expf(-0.5f * x * x) : 0.f;
+    const int q = threadIdx.x + kThreads * m;
+    if (q < g.npx) Fs[q] = Fr[m];
+  }
 
   const int lane = threadIdx.x & 63;
   const int orow0 = (threadIdx.x >> 6) * OPT;
   const int gc = c0 + lane;
   float z[OPT], a[OPT], ap[OPT], app[OPT];
   Accum<ACC64> P[OPT], Q[OPT], DP[OPT], DQ[OPT];
+  const int gcc = min(gc, p.Wd - 1);
+#pragma unroll
+  for (int s = 0; s < OPT; ++s) z[s] = p.in[(int64_t)min(r0 + orow0 + s, p.H - 1) * p.in_pitch + gcc];
 #pragma unroll
   for (int s = 0; s < OPT; ++s) {
-    const int gr = r0 + orow0 + s;
-    float x = 0.f;
-    if (gr < p.H && gc < p.Wd) x = (p.in[(int64_t)gr * p.in_pitch + gc] - p.center) / p.sigma_r;
+    const float x = (z[s] - p.center) / p.sigma_r;  // pixels past the image: harmless, never stored
     z[s] = x * p.X;                // a_{n+1} = a_n x X / (n+1)
     a[s] = expf(-0.5f * x * x);    // a_0
     ap[s] = 0.f;                   // a_{n-1}

@@ -62,6 +62,7 @@ struct LsState {
   float *a, *ap, *app, *z;  // per-pixel coefficient recursion
   double *P, *Q, *DP, *DQ;  // per-pixel sums
   int64_t hbytes;           // bytes of one row-filtered image
+  int64_t hrows;            // rows of one row-filtered image (with the zero rows)
 };
 
 // Kernel-shape variants (compile-time register budgets).
