@@ -175,7 +175,7 @@ def main():
         flops = H * Wd * (r["N"] + 1) * alg_flops_per_px_n(kind, r["W"])
         achieved = flops / (r["ms"] * 1e-3) / 1e12
         kern = ("gpa_forward_kernel (one launch)" if r["tile_rows"] > 0 else
-                "ls_rows_kernel + ls_cols_%s_kernel per block of 8 orders" % ("box" if kind == "box" else "fir"))
+                "ls_rows + ls_cols_%s per block of 16 orders" % ("box" if kind == "box" else "mfma"))
         return {"bound": "alu", "achieved": round(achieved, 3), "peak": round(ALU_PEAK_TFLOPS, 1),
                 "unit": "TFLOP/s", "frac": round(achieved / ALU_PEAK_TFLOPS, 4),
                 "traffic": measured_traffic(r["setting"]),

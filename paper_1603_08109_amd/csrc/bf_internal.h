@@ -53,7 +53,7 @@ struct TileParams {
 };
 
 // Large-support path: orders per block and its device state.
-constexpr int kLsBlock = 8;
+constexpr int kLsBlock = 16;
 struct LsState {
   int64_t pitch;            // row pitch (floats) of the image-shaped buffers
   float* F[2];              // F^ state images (double-buffered)
@@ -62,7 +62,6 @@ struct LsState {
   float *a, *ap, *app, *z;  // per-pixel coefficient recursion
   double *P, *Q, *DP, *DQ;  // per-pixel sums
   int64_t hbytes;           // bytes of one row-filtered image
-  int64_t hrows;            // rows of one row-filtered image (with the zero rows)
 };
 
 // Kernel-shape variants (compile-time register budgets).

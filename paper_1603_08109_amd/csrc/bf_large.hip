@@ -130,247 +130,6 @@ __global__ __launch_bounds__(kThreads) void ls_rows_kernel(TileParams p, LsState
   }
 }
 
-// ---------------------------------------------------------------------------
-// Gaussian passes on the matrix cores.  A 1-D FIR over 16 consecutive
-// outputs is a banded Toeplitz product: out[j] = sum_m x[m] tap[m - j],
-// m = 0 .. 15 + 2W.  v_mfma_f32_16x16x4f32 multiplies a 16x4 by a 4x16
-// float32 block (lane l holds A[l%16][l/16], B[l/16][l%16]; the result
-// D[4(l/16)+v][l%16] sits in accumulator v), so ceil((16 + 2W)/4) of them
-// give a 16x16 block of outputs.  The Toeplitz operand, the same for every
-// block, is one per-lane table in LDS: Tt[kk*64 + l] = tap[4kk + l/16 - l%16]
-// (zero outside [0, 2W]).
-// ---------------------------------------------------------------------------
-typedef float mf4 __attribute__((ext_vector_type(4)));
-
-__device__ __forceinline__ int ls_kk(int W) { return (16 + 2 * W + 3) / 4; }
-
-__device__ __forceinline__ void fill_toeplitz(float* Tt, int W, const float* __restrict__ tz) {
-  const int KK = ls_kk(W);
-  for (int i = threadIdx.x; i < KK * 64; i += kThreads) {
-    const int kk = i >> 6, l = i & 63;
-    const int d = 4 * kk + (l >> 4) - (l & 15);
-    Tt[i] = (d >= 0 && d <= 2 * W) ? tz[d] : 0.f;
-  }
-}
-
-// Row pitch of the staged rows for the matrix-core row pass: the last
-// block reads 4*ceil((16+2W)/4) columns, up to 258 + 2W; keep the pitch
-// twice an odd number (conflict-free column reads).
-__host__ __device__ inline int ls_rows_pitch_mfma(int W) {
-  const int need = kLsCols + 2 * W + 4;
-  return (need % 4 == 2) ? need : need + 2;
-}
-
-__global__ __launch_bounds__(kThreads) void ls_rows_mfma_kernel(TileParams p, LsState st, int n0, int K,
-                                                                int src) {
-  extern __shared__ float lds[];
-  const int W = p.W;
-  const int RW = kLsCols + 2 * W;
-  const int RWp = ls_rows_pitch_mfma(W);
-  const int HP = kLsCols + 2;
-  const int KK = ls_kk(W);
-  const int npx = kLsRows * RWp;
-  float* Fl = lds;
-  float* Yl = lds + align4(npx);
-  float* Hl = Yl + align4(npx);
-  float* Tt = Hl + align4(kLsRows * HP);
-  const int tiles_x = (p.Wd + kLsCols - 1) / kLsCols;
-  const int tile = blockIdx.x;
-  const int ty = tile / tiles_x, tx = tile - (tile / tiles_x) * tiles_x;
-  const int r0 = ty * kLsRows, c0 = tx * kLsCols;
-  const float* Fin = st.F[src];
-  float* Fout = st.F[src ^ 1];
-  fill_toeplitz(Tt, W, p.taps + kTapPad);
-  for (int q0 = threadIdx.x; q0 < npx; q0 += 4 * kThreads) {
-    float F[4], y[4];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int q = q0 + u * kThreads;
-      const int row = q / RWp, col = q - row * RWp;
-      const int gr = r0 + row, gc = c0 - W + col;
-      F[u] = 0.f;
-      y[u] = 0.f;
-      if (q < npx && col < RW && gr < p.H && gc >= 0 && gc < p.Wd) {
-        const int64_t j = (int64_t)gr * st.pitch + gc;
-        F[u] = Fin[j];
-        y[u] = st.Y[j];
-      }
-    }
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int q = q0 + u * kThreads;
-      if (q < npx) {
-        Fl[q] = F[u];
-        Yl[q] = y[u];
-      }
-    }
-  }
-  const int lane = threadIdx.x & 63;
-  const int wv = threadIdx.x >> 6;
-  const int arow = (lane & 15) * RWp + (lane >> 4);  // A[l%16][l/16] inside a block
-  for (int k = 0; k < K; ++k) {
-    __syncthreads();
-    mf4 acc[4];
-#pragma unroll
-    for (int bb = 0; bb < 4; ++bb) acc[bb] = mf4{0.f, 0.f, 0.f, 0.f};
-    const int cbase = wv * 64;  // this wave's four 16-column blocks
-    for (int kk = 0; kk < KK; ++kk) {
-      const float b = Tt[kk * 64 + lane];
-#pragma unroll
-      for (int bb = 0; bb < 4; ++bb) {
-        const float a = Fl[arow + cbase + bb * 16 + 4 * kk];
-        acc[bb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc[bb], 0, 0, 0);
-      }
-    }
-#pragma unroll
-    for (int bb = 0; bb < 4; ++bb)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) Hl[(4 * (lane >> 4) + v) * HP + cbase + bb * 16 + (lane & 15)] = acc[bb][v];
-    __syncthreads();
-    float* Hk = st.H[k] + (int64_t)W * st.pitch;
-    for (int q = threadIdx.x; q < kLsRows * kLsCols; q += kThreads) {
-      const int row = q / kLsCols, col = q - row * kLsCols;
-      const int gr = r0 + row, gc = c0 + col;
-      if (gr < p.H && gc < p.Wd) Hk[(int64_t)gr * st.pitch + gc] = Hl[row * HP + col];
-    }
-    for (int q = threadIdx.x; q < npx; q += kThreads) Fl[q] *= Yl[q];
-  }
-  __syncthreads();
-  for (int q = threadIdx.x; q < kLsRows * kLsCols; q += kThreads) {
-    const int row = q / kLsCols, col = q - row * kLsCols;
-    const int gr = r0 + row, gc = c0 + col;
-    if (gr < p.H && gc < p.Wd) Fout[(int64_t)gr * st.pitch + gc] = Fl[row * RWp + col + W];
-  }
-}
-
-int64_t ls_rows_mfma_lds_bytes(int W) {
-  const int64_t npx = (int64_t)kLsRows * ls_rows_pitch_mfma(W);
-  const int64_t KK = (16 + 2 * W + 3) / 4;
-  return 4 * (2 * ((npx + 3) & ~3LL) + (((int64_t)kLsRows * (kLsCols + 2) + 3) & ~3LL) + KK * 64);
-}
-
-// Column pass on the matrix cores: the workgroup stages 64 + 2W + 4 rows
-// x 64 columns of one order's row-filtered image; wave w computes output
-// rows 16w .. 16w+15 as four 16x16 blocks (Toeplitz table as A, staged
-// columns as B) and folds them into its 16 pixels per lane.
-constexpr int kLsMfmaStage = 4;  // extra staged rows read by the last k-step
-
-template <bool SAVE>
-__global__ __launch_bounds__(kThreads) void ls_cols_mfma_kernel(TileParams p, LsState st, int n0, int K,
-                                                                int hrows) {
-  extern __shared__ float lds[];
-  const int tiles_x = (p.Wd + kTileCols - 1) / kTileCols;
-  const int tile = xcd_remap(blockIdx.x, gridDim.x);
-  const int ty = tile / tiles_x, tx = tile - (tile / tiles_x) * tiles_x;
-  const int lane = threadIdx.x & 63;
-  const int wv = threadIdx.x >> 6;
-  const int tr0 = ty * 64, c0 = tx * kTileCols;
-  const int W = p.W;
-  const int KK = ls_kk(W);
-  const int rows = 64 + 2 * W + kLsMfmaStage;
-  float* Sl = lds;
-  float* Tt = lds + rows * kLsColPitch;
-  fill_toeplitz(Tt, W, p.taps + kTapPad);
-  // this lane's 16 pixels: block bb (columns 16bb..), accumulator v (row 4(l/16)+v)
-  float a[16], ap[16], app[16], z[16];
-  double P[16], Q[16], DP[16], DQ[16];
-  const int pr0 = tr0 + wv * 16 + 4 * (lane >> 4);  // pixel row of accumulator v = pr0 + v
-  const int pc0 = c0 + (lane & 15);                  // pixel column of block bb = pc0 + 16 bb
-#pragma unroll
-  for (int bb = 0; bb < 4; ++bb)
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int s = bb * 4 + v;
-      const bool ok = pr0 + v < p.H && pc0 + 16 * bb < p.Wd;
-      const int64_t i = ok ? (int64_t)(pr0 + v) * p.Wd + pc0 + 16 * bb : 0;
-      a[s] = ok ? st.a[i] : 0.f;
-      ap[s] = ok ? st.ap[i] : 0.f;
-      z[s] = ok ? st.z[i] : 0.f;
-      P[s] = ok ? st.P[i] : 0.0;
-      Q[s] = ok ? st.Q[i] : 0.0;
-      if (SAVE) {
-        app[s] = ok ? st.app[i] : 0.f;
-        DP[s] = ok ? st.DP[i] : 0.0;
-        DQ[s] = ok ? st.DQ[i] : 0.0;
-      }
-    }
-  const int bcol = (lane >> 4) * kLsColPitch + (lane & 15);  // B[l/16][l%16] inside a block
-  for (int k = 0; k < K; ++k) {
-    const int n = n0 + k;
-    __syncthreads();
-    const float* hk = st.H[k] + c0;
-    const int total = rows * kTileCols;
-    const bool col_ok = (c0 + (threadIdx.x & 63)) < p.Wd;
-    for (int q0 = threadIdx.x; q0 < total; q0 += 8 * kThreads) {
-      float v[8];
-#pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const int q = q0 + u * kThreads;
-        const int rr = tr0 + (q >> 6);  // padded row
-        v[u] = (q < total && col_ok && rr < hrows) ? hk[(int64_t)rr * st.pitch + (q & 63)] : 0.f;
-      }
-#pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const int q = q0 + u * kThreads;
-        if (q < total) Sl[(q >> 6) * kLsColPitch + (q & 63)] = v[u];
-      }
-    }
-    __syncthreads();
-    mf4 acc[4];
-#pragma unroll
-    for (int bb = 0; bb < 4; ++bb) acc[bb] = mf4{0.f, 0.f, 0.f, 0.f};
-    const float* sb = Sl + (wv * 16) * kLsColPitch + bcol;
-    for (int kk = 0; kk < KK; ++kk) {
-      const float ta = Tt[kk * 64 + lane];
-#pragma unroll
-      for (int bb = 0; bb < 4; ++bb) {
-        const float b = sb[4 * kk * kLsColPitch + bb * 16];
-        acc[bb] = __builtin_amdgcn_mfma_f32_16x16x4f32(ta, b, acc[bb], 0, 0, 0);
-      }
-    }
-    const float in1 = p.inv_tab[n + 1];
-#pragma unroll
-    for (int bb = 0; bb < 4; ++bb)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int s = bb * 4 + v;
-        const float val = acc[bb][v];
-        if (n < p.N) Q[s] = fma((double)a[s], (double)val, Q[s]);
-        if (n >= 1) P[s] = fma((double)ap[s], (double)val, P[s]);
-        if (SAVE) {
-          if (n >= 1 && n < p.N) DQ[s] = fma((double)ap[s], (double)val, DQ[s]);
-          if (n >= 2) DP[s] = fma((double)app[s], (double)val, DP[s]);
-          app[s] = ap[s];
-        }
-        ap[s] = a[s];
-        a[s] *= z[s] * in1;
-      }
-  }
-#pragma unroll
-  for (int bb = 0; bb < 4; ++bb)
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int s = bb * 4 + v;
-      if (pr0 + v < p.H && pc0 + 16 * bb < p.Wd) {
-        const int64_t i = (int64_t)(pr0 + v) * p.Wd + pc0 + 16 * bb;
-        st.a[i] = a[s];
-        st.ap[i] = ap[s];
-        st.P[i] = P[s];
-        st.Q[i] = Q[s];
-        if (SAVE) {
-          st.app[i] = app[s];
-          st.DP[i] = DP[s];
-          st.DQ[i] = DQ[s];
-        }
-      }
-    }
-}
-
-int64_t ls_cols_mfma_lds_bytes(int W) {
-  const int64_t KK = (16 + 2 * W + 3) / 4;
-  return 4 * ((int64_t)(64 + 2 * W + kLsMfmaStage) * kLsColPitch + KK * 64);
-}
-
 // Per-pixel coefficient state of the streamed path, held in registers for
 // CH pixels while the orders of one block are folded in.
 template <int CH, bool SAVE>
@@ -392,6 +151,46 @@ struct LsPix {
         app[s] = ok ? st.app[i] : 0.f;
         DP[s] = ok ? st.DP[i] : 0.0;
         DQ[s] = ok ? st.DQ[i] : 0.0;
+      }
+    }
+  }
+  // pixels s0 .. s0 + M - 1 at i0 + (s - s0) * stride, the first n_ok of them inside the image
+  template <int M>
+  __device__ __forceinline__ void load_part(const LsState& st, int s0, int64_t i0, int64_t stride, int n_ok) {
+#pragma unroll
+    for (int u = 0; u < M; ++u) {
+      const int s = s0 + u;
+      const bool ok = u < n_ok;
+      const int64_t i = ok ? i0 + u * stride : 0;
+      a[s] = ok ? st.a[i] : 0.f;
+      ap[s] = ok ? st.ap[i] : 0.f;
+      z[s] = ok ? st.z[i] : 0.f;
+      P[s] = ok ? st.P[i] : 0.0;
+      Q[s] = ok ? st.Q[i] : 0.0;
+      if (SAVE) {
+        app[s] = ok ? st.app[i] : 0.f;
+        DP[s] = ok ? st.DP[i] : 0.0;
+        DQ[s] = ok ? st.DQ[i] : 0.0;
+      }
+    }
+  }
+  template <int M>
+  __device__ __forceinline__ void store_part(const LsState& st, int s0, int64_t i0, int64_t stride,
+                                             int n_ok) const {
+#pragma unroll
+    for (int u = 0; u < M; ++u) {
+      const int s = s0 + u;
+      if (u < n_ok) {
+        const int64_t i = i0 + u * stride;
+        st.a[i] = a[s];
+        st.ap[i] = ap[s];
+        st.P[i] = P[s];
+        st.Q[i] = Q[s];
+        if (SAVE) {
+          st.app[i] = app[s];
+          st.DP[i] = DP[s];
+          st.DQ[i] = DQ[s];
+        }
       }
     }
   }
@@ -425,6 +224,238 @@ struct LsPix {
     a[s] *= z[s] * in1;
   }
 };
+
+// ---------------------------------------------------------------------------
+// Gaussian passes on the matrix cores.  A 1-D FIR over 16 consecutive
+// outputs is a banded Toeplitz product: out[j] = sum_m x[m] tap[m - j],
+// m = 0 .. 15 + 2W.  v_mfma_f32_16x16x4f32 multiplies a 16x4 by a 4x16
+// float32 block (lane l holds A[l%16][l/16], B[l/16][l%16]; the result
+// D[4(l/16)+v][l%16] sits in accumulator v), so ceil((16 + 2W)/4) of them
+// give a 16x16 block of outputs.  The Toeplitz operand, the same for every
+// block, is one per-lane table in LDS: Tt[kk*64 + l] = tap[4kk + l/16 - l%16]
+// (zero outside [0, 2W]).
+// ---------------------------------------------------------------------------
+typedef float mf4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ int ls_kk(int W) { return (16 + 2 * W + 3) / 4; }
+
+template <int NT>
+__device__ __forceinline__ void fill_toeplitz(float* Tt, int W, const float* __restrict__ tz) {
+  const int KK = ls_kk(W);
+  for (int i = threadIdx.x; i < KK * 64; i += NT) {
+    const int kk = i >> 6, l = i & 63;
+    const int d = 4 * kk + (l >> 4) - (l & 15);
+    Tt[i] = (d >= 0 && d <= 2 * W) ? tz[d] : 0.f;
+  }
+}
+
+// Row pitch of the staged rows for the matrix-core row pass: the last
+// block reads 4*ceil((16+2W)/4) columns, up to 258 + 2W; keep the pitch
+// twice an odd number (conflict-free column reads).
+__host__ __device__ inline int ls_rows_pitch_mfma(int W) {
+  const int need = kLsCols + 2 * W + 4;
+  return (need % 4 == 2) ? need : need + 2;
+}
+
+// Row pass on the matrix cores.  Each thread owns the staged values
+// q = threadIdx.x + 256 j of the workgroup's kLsRows x (256 + 2W) window and
+// keeps F^_n and y for them in registers; per order it writes F^_n to one of
+// two LDS buffers (so one barrier per order suffices), the four waves each
+// compute 16 rows x 64 columns of the row-filtered image as four 16x16
+// products and store them straight from the accumulators, and F^ advances
+// by one power in registers.
+constexpr int kLsRowsRegs = 32;  // staged values per thread: 16 (256 + 2W) <= 32 x 256
+
+bool ls_rows_mfma_fits(int W) { return kLsRows * ls_rows_pitch_mfma(W) <= kLsRowsRegs * kThreads; }
+
+__global__ __launch_bounds__(kThreads) void ls_rows_mfma_kernel(TileParams p, LsState st, int n0, int K,
+                                                                int src) {
+  extern __shared__ float lds[];
+  const int W = p.W;
+  const int RW = kLsCols + 2 * W;
+  const int RWp = ls_rows_pitch_mfma(W);
+  const int KK = ls_kk(W);
+  const int npx = kLsRows * RWp;
+  const int fls = align4(npx);
+  float* Fl = lds;  // two buffers of fls
+  float* Tt = lds + 2 * fls;
+  const int tiles_x = (p.Wd + kLsCols - 1) / kLsCols;
+  const int tile = blockIdx.x;
+  const int ty = tile / tiles_x, tx = tile - (tile / tiles_x) * tiles_x;
+  const int r0 = ty * kLsRows, c0 = tx * kLsCols;
+  const float* Fin = st.F[src];
+  float* Fout = st.F[src ^ 1];
+  fill_toeplitz<kThreads>(Tt, W, p.taps + kTapPad);
+  float F[kLsRowsRegs], Y[kLsRowsRegs];
+#pragma unroll
+  for (int j = 0; j < kLsRowsRegs; ++j) {
+    const int q = threadIdx.x + j * kThreads;
+    const int row = q / RWp, col = q - row * RWp;
+    const int gr = r0 + row, gc = c0 - W + col;
+    const bool ok = q < npx && col < RW && gr < p.H && gc >= 0 && gc < p.Wd;
+    const int64_t i = ok ? (int64_t)gr * st.pitch + gc : 0;
+    F[j] = ok ? Fin[i] : 0.f;
+    Y[j] = ok ? st.Y[i] : 0.f;
+  }
+  const int lane = threadIdx.x & 63;
+  const int wv = threadIdx.x >> 6;
+  const int cbase = wv * 64;                         // this wave's four 16-column blocks
+  const int arow = (lane & 15) * RWp + (lane >> 4);  // A[l%16][l/16] inside a block
+  const int orow = r0 + 4 * (lane >> 4);             // output row of accumulator v: orow + v
+  const int ocol = c0 + cbase + (lane & 15);         // output column of block bb: ocol + 16 bb
+  for (int k = 0; k < K; ++k) {
+    float* Fc = Fl + (k & 1) * fls;
+#pragma unroll
+    for (int j = 0; j < kLsRowsRegs; ++j) {
+      const int q = threadIdx.x + j * kThreads;
+      if (q < npx) Fc[q] = F[j];
+    }
+    __syncthreads();
+    mf4 acc[4];
+#pragma unroll
+    for (int bb = 0; bb < 4; ++bb) acc[bb] = mf4{0.f, 0.f, 0.f, 0.f};
+    // operands of step kk + 1 are read from LDS while step kk's products run
+    const float* sa = Fc + arow + cbase;
+    float tb = Tt[lane], a[4];
+#pragma unroll
+    for (int bb = 0; bb < 4; ++bb) a[bb] = sa[bb * 16];
+    for (int kk = 0; kk < KK; ++kk) {
+      const int kn = min(kk + 1, KK - 1);
+      const float tn = Tt[kn * 64 + lane];
+      float an[4];
+#pragma unroll
+      for (int bb = 0; bb < 4; ++bb) an[bb] = sa[bb * 16 + 4 * kn];
+#pragma unroll
+      for (int bb = 0; bb < 4; ++bb) acc[bb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[bb], tb, acc[bb], 0, 0, 0);
+      tb = tn;
+#pragma unroll
+      for (int bb = 0; bb < 4; ++bb) a[bb] = an[bb];
+    }
+    float* Hk = st.H[k] + (int64_t)W * st.pitch;  // W zero rows above the image
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      if (orow + v < p.H) {
+#pragma unroll
+        for (int bb = 0; bb < 4; ++bb)
+          if (ocol + 16 * bb < p.Wd) Hk[(int64_t)(orow + v) * st.pitch + ocol + 16 * bb] = acc[bb][v];
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < kLsRowsRegs; ++j) F[j] *= Y[j];
+  }
+#pragma unroll
+  for (int j = 0; j < kLsRowsRegs; ++j) {
+    const int q = threadIdx.x + j * kThreads;
+    const int row = q / RWp, col = q - row * RWp;
+    const int gr = r0 + row, gc = c0 - W + col;
+    if (q < npx && col >= W && col < W + kLsCols && gr < p.H && gc < p.Wd)
+      Fout[(int64_t)gr * st.pitch + gc] = F[j];
+  }
+}
+
+int64_t ls_rows_mfma_lds_bytes(int W) {
+  const int64_t npx = (int64_t)kLsRows * ls_rows_pitch_mfma(W);
+  const int64_t KK = (16 + 2 * W + 3) / 4;
+  return 4 * (2 * ((npx + 3) & ~3LL) + KK * 64);
+}
+
+// Column pass on the matrix cores: a workgroup of eight waves stages
+// ls_cols_rows(W) rows x 64 columns of one order's row-filtered image
+// (64 output rows, the 2W halo, the overhang of the last k-step) with
+// direct-to-LDS loads; wave w computes output rows 16 (w % 4) .. + 15 and
+// columns 32 (w / 4) .. + 31 as two 16x16 blocks (Toeplitz table as A,
+// staged columns as B) and folds them into its 8 pixels per lane.  The
+// staged window never leaves the row-filtered image: it carries W zero
+// rows above and W + 8 below a height padded to a multiple of 64.
+constexpr int kColsThreads = 512;
+
+__host__ __device__ inline int ls_cols_rows(int W) { return (64 + 2 * W + 4 + 3) & ~3; }
+
+// Tile order for the column pass: column bands four tiles wide, row-major
+// inside a band, so the tiles resident on one XCD at a time form a tall
+// block whose overlapping halos are served from its L2.
+__device__ __forceinline__ void band_tile(int t, int tiles_x, int tiles_y, int& ty, int& tx) {
+  constexpr int BW = 4;
+  const int band = t / (BW * tiles_y);
+  const int bx0 = band * BW;
+  const int bw = min(BW, tiles_x - bx0);
+  const int idx = t - band * BW * tiles_y;
+  ty = idx / bw;
+  tx = bx0 + (idx - ty * bw);
+}
+
+template <bool SAVE>
+__global__ __launch_bounds__(kColsThreads) void ls_cols_mfma_kernel(TileParams p, LsState st, int n0, int K) {
+  extern __shared__ float lds[];
+  const int tiles_x = (p.Wd + kTileCols - 1) / kTileCols;
+  const int tiles_y = (p.H + 63) / 64;
+  int ty, tx;
+  band_tile(xcd_remap(blockIdx.x, gridDim.x), tiles_x, tiles_y, ty, tx);
+  const int lane = threadIdx.x & 63;
+  const int wv = threadIdx.x >> 6;
+  const int rb = wv & 3, ch = wv >> 2;  // row block, column half
+  const int tr0 = ty * 64, c0 = tx * kTileCols;
+  const int W = p.W;
+  const int KK = ls_kk(W);
+  const int rows = ls_cols_rows(W);
+  float* Sl = lds;  // rows x 64, pitch 64
+  float* Tt = lds + rows * 64;
+  fill_toeplitz<kColsThreads>(Tt, W, p.taps + kTapPad);
+  // this lane's 8 pixels: block j (columns 32 ch + 16 j ..), accumulator v (row 4(l/16)+v)
+  const int pr0 = tr0 + rb * 16 + 4 * (lane >> 4);  // pixel row of accumulator v = pr0 + v
+  const int pc0 = c0 + ch * 32 + (lane & 15);       // pixel column of block j = pc0 + 16 j
+  LsPix<8, SAVE> px;
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    const int nr = (pc0 + 16 * j < p.Wd) ? max(0, min(4, p.H - pr0)) : 0;
+    px.template load_part<4>(st, j * 4, (int64_t)pr0 * p.Wd + pc0 + 16 * j, p.Wd, nr);
+  }
+  const float* sb = Sl + (rb * 16 + (lane >> 4)) * 64 + ch * 32 + (lane & 15);  // B[l/16][l%16]
+  for (int k = 0; k < K; ++k) {
+    const int n = n0 + k;
+    __syncthreads();
+    // one wave instruction moves 4 staged rows (64 lanes x 16 bytes)
+    const float* hk = st.H[k] + (int64_t)(tr0 + (lane >> 4)) * st.pitch + c0 + (lane & 15) * 4;
+    for (int g = wv; g < rows / 4; g += kColsThreads / 64)
+      __builtin_amdgcn_global_load_lds(hk + (int64_t)(4 * g) * st.pitch,
+                                       (__attribute__((address_space(3))) void*)(Sl + g * 256), 16, 0, 0);
+    __syncthreads();
+    mf4 acc[2];
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[j] = mf4{0.f, 0.f, 0.f, 0.f};
+    // operands of step kk + 1 are read from LDS while step kk's products run
+    float ta = Tt[lane], b[2];
+#pragma unroll
+    for (int j = 0; j < 2; ++j) b[j] = sb[j * 16];
+    for (int kk = 0; kk < KK; ++kk) {
+      const int kn = min(kk + 1, KK - 1);
+      const float tn = Tt[kn * 64 + lane];
+      float bn[2];
+#pragma unroll
+      for (int j = 0; j < 2; ++j) bn[j] = sb[4 * kn * 64 + j * 16];
+#pragma unroll
+      for (int j = 0; j < 2; ++j) acc[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(ta, b[j], acc[j], 0, 0, 0);
+      ta = tn;
+#pragma unroll
+      for (int j = 0; j < 2; ++j) b[j] = bn[j];
+    }
+    const float in1 = p.inv_tab[n + 1];
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) px.fold(j * 4 + v, n, p.N, acc[j][v], in1);
+  }
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    const int nr = (pc0 + 16 * j < p.Wd) ? max(0, min(4, p.H - pr0)) : 0;
+    px.template store_part<4>(st, j * 4, (int64_t)pr0 * p.Wd + pc0 + 16 * j, p.Wd, nr);
+  }
+}
+
+int64_t ls_cols_mfma_lds_bytes(int W) {
+  const int64_t KK = (16 + 2 * W + 3) / 4;
+  return 4 * ((int64_t)ls_cols_rows(W) * 64 + KK * 64);
+}
 
 // Box column pass: each thread walks a column segment of `seg_rows` rows
 // with one running window sum per order of the block (two reads per output),
@@ -554,11 +585,15 @@ bool ls_supported(int W) {
          (int64_t)(64 + 2 * W) * kLsColPitch * 4 <= max_lds_bytes();
 }
 
+// Rows of one row-filtered image: the height padded to a multiple of 64,
+// W zero rows above, and W + 8 zero rows below (the box window's entering
+// row, and the overhang of the matrix-core column pass's staged window).
+static int64_t ls_hrows(int H, int W) { return (int64_t)((H + 63) / 64) * 64 + 2 * W + 8; }
+
 int64_t ls_state_bytes(int H, int Wd, int W, bool save) {
   const int64_t pitch = ((Wd + 63) / 64) * 64;
   const int64_t img = pitch * H;
-  // image rows padded to a multiple of 64, plus W zero rows above and W + 1 below
-  const int64_t himg = pitch * (((H + 4 * kLsOpt - 1) / (4 * kLsOpt)) * (4 * kLsOpt) + 2 * W + 1);
+  const int64_t himg = pitch * ls_hrows(H, W);
   const int64_t npx = (int64_t)H * Wd;
   int64_t b = 3 * img * 4 + (int64_t)kLsBlock * himg * 4 + 3 * npx * 4 + 2 * npx * 8;
   if (save) b += npx * 4 + 2 * npx * 8;
@@ -570,8 +605,7 @@ LsState ls_layout(void* base, int H, int Wd, int W, bool save) {
   LsState st;
   const int64_t pitch = ((Wd + 63) / 64) * 64;
   const int64_t img = pitch * H;
-  // image rows padded to a multiple of 64, plus W zero rows above and W + 1 below
-  const int64_t himg = pitch * (((H + 4 * kLsOpt - 1) / (4 * kLsOpt)) * (4 * kLsOpt) + 2 * W + 1);
+  const int64_t himg = pitch * ls_hrows(H, W);
   const int64_t npx = (int64_t)H * Wd;
   char* q = (char*)base;
   auto take = [&](int64_t bytes) {
@@ -597,7 +631,6 @@ LsState ls_layout(void* base, int H, int Wd, int W, bool save) {
     st.DQ = (double*)take(npx * 8);
   }
   st.hbytes = himg * 4;
-  st.hrows = himg / pitch;
   return st;
 }
 
@@ -624,16 +657,21 @@ hipError_t launch_forward_ls(const TileParams& p, const LsState& st, bool save, 
   const int gfir16 = ((p.H + 63) / 64) * tiles_x;
   const size_t fl8 = (size_t)(32 + 2 * p.W) * kLsColPitch * 4;
   const size_t fl16 = (size_t)(64 + 2 * p.W) * kLsColPitch * 4;
-  // Gaussian without the adjoint state: FIR passes on the matrix cores
+  // Gaussian: FIR passes on the matrix cores where the staged windows fit
   const size_t rlm = (size_t)ls_rows_mfma_lds_bytes(p.W);
   const size_t clm = (size_t)ls_cols_mfma_lds_bytes(p.W);
-  const bool use_mfma = p.kt != BF_BOX && !save && rlm <= (size_t)max_lds_bytes() &&
-                        clm <= (size_t)max_lds_bytes();
-  if (use_mfma) {
+  const bool rows_mfma = p.kt != BF_BOX && ls_rows_mfma_fits(p.W) && rlm <= (size_t)max_lds_bytes();
+  const bool cols_mfma = p.kt != BF_BOX && clm <= (size_t)max_lds_bytes();
+  if (rows_mfma) {
     e = hipFuncSetAttribute((const void*)ls_rows_mfma_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
                             max_lds_bytes());
+    if (e != hipSuccess) return e;
+  }
+  if (cols_mfma) {
+    e = hipFuncSetAttribute((const void*)ls_cols_mfma_kernel<false>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            max_lds_bytes());
     if (e == hipSuccess)
-      e = hipFuncSetAttribute((const void*)ls_cols_mfma_kernel<false>,
+      e = hipFuncSetAttribute((const void*)ls_cols_mfma_kernel<true>,
                               hipFuncAttributeMaxDynamicSharedMemorySize, max_lds_bytes());
     if (e != hipSuccess) return e;
   }
@@ -648,7 +686,7 @@ hipError_t launch_forward_ls(const TileParams& p, const LsState& st, bool save, 
   int src = 0;
   for (int n0 = 0; n0 <= p.N; n0 += kLsBlock) {
     const int K = std::min(kLsBlock, p.N + 1 - n0);
-    if (use_mfma)
+    if (rows_mfma)
       hipLaunchKernelGGL(ls_rows_mfma_kernel, dim3(grow), dim3(kThreads), (size_t)rlm, s, p, st, n0, K, src);
     else
       hipLaunchKernelGGL(rk, dim3(grow), dim3(kThreads), (size_t)rl, s, p, st, n0, K, src);
@@ -657,9 +695,11 @@ hipError_t launch_forward_ls(const TileParams& p, const LsState& st, bool save, 
         hipLaunchKernelGGL((ls_cols_box_kernel<true>), gbox, dim3(kThreads), 0, s, p, st, n0, K, seg_rows);
       else
         hipLaunchKernelGGL((ls_cols_box_kernel<false>), gbox, dim3(kThreads), 0, s, p, st, n0, K, seg_rows);
-    } else if (use_mfma) {
-      hipLaunchKernelGGL((ls_cols_mfma_kernel<false>), dim3(gfir16), dim3(kThreads), clm, s, p, st, n0, K,
-                         (int)st.hrows);
+    } else if (cols_mfma) {
+      if (save)
+        hipLaunchKernelGGL((ls_cols_mfma_kernel<true>), dim3(gfir16), dim3(kColsThreads), clm, s, p, st, n0, K);
+      else
+        hipLaunchKernelGGL((ls_cols_mfma_kernel<false>), dim3(gfir16), dim3(kColsThreads), clm, s, p, st, n0, K);
     } else {
       if (save)
         hipLaunchKernelGGL((ls_cols_fir_kernel<8, true>), dim3(gfir8), dim3(kThreads), fl8, s, p, st, n0, K);

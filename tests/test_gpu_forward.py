@@ -211,3 +211,22 @@ def test_workload3_sampled(kind, kw, sr):
     print(f"N={plan.info.N} pixels={len(px)} tile_rows={plan.info.tile_rows}", flush=True)
     _report("gpu-O2", got - o2)
     assert np.abs(got - o2).max() <= TOL
+
+
+@pytest.mark.parametrize("kind,kw,sr", [("box", dict(W=6), 25.0), ("gauss", dict(sigma_s=3.0), 30.0)])
+def test_streamed_saved_state_matches_fused(kind, kw, sr):
+    # the forward's saved planes (for the adjoint) agree between the two paths
+    torch, P = _mods()
+    f = synthimg.gen2(140, 200, 79)
+    x = torch.tensor(f, dtype=torch.float32, device="cuda")
+    pf = P.Plan(kind, sr, 140, 200, grad=True, **kw)
+    ps = P.Plan(kind, sr, 140, 200, grad=True, streamed=True, **kw)
+    assert ps.info.tile_rows == 0 and pf.info.tile_rows > 0
+    sf, ss = pf.new_saved(), ps.new_saved()
+    a = pf.forward(x, saved=sf)
+    b = ps.forward(x, saved=ss)
+    torch.cuda.synchronize()
+    assert (a - b).abs().max().item() <= 1e-4
+    for i, (u, v) in enumerate(zip(sf.view(3, -1), ss.view(3, -1))):
+        scale = u.abs().max().item()
+        assert (u - v).abs().max().item() <= 1e-4 * scale + 1e-12, i
