@@ -20,8 +20,8 @@ CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libbfgpa.so")
 
-SOURCES = ["bf_plan.cpp", "bf_kernels.hip", "bf_batch.hip", "bf_large.hip"]
-HEADERS = ["bf_internal.h", "bf_device.h", os.path.join("..", "..", "include", "bf_gpa.h")]
+SOURCES = ["bf_plan.cpp", "bf_kernels.hip", "bf_batch.hip", "bf_large.hip", "bf_large_bwd.hip"]
+HEADERS = ["bf_internal.h", "bf_device.h", "bf_toeplitz.h", os.path.join("..", "..", "include", "bf_gpa.h")]
 
 
 def hipcc() -> str:

@@ -64,6 +64,24 @@ struct LsState {
   int64_t hbytes;           // bytes of one row-filtered image
 };
 
+// Rows of one row-filtered image of the streamed passes: the height padded
+// to a multiple of 64, W zero rows above, and W + 8 zero rows below (a box
+// window's entering row, and the overhang of a staged column window).
+inline int64_t ls_hrows(int H, int W) { return (int64_t)((H + 63) / 64) * 64 + 2 * W + 8; }
+
+// Streamed adjoint (supports too wide for the fused adjoint tiles): orders
+// per block and its device state.
+constexpr int kBlsBlock = 8;
+constexpr int kBlsPartials = 1024;  // workgroups of the final reduction pass
+struct BlsState {
+  int64_t pitch;               // row pitch (floats) of the image-shaped buffers
+  float* A[2];                 // scaled coefficients a_m (double-buffered)
+  float* B[2];                 // b_m = a_{m-1} r_m (double-buffered)
+  float* R[2 * kBlsBlock];     // row-filtered adjoint images: taps, then d^2 taps
+  float *fc, *fp;              // F~_m and F~_{m-1} at each pixel
+  double *dx, *dss;            // per-pixel sums of the image and sigma_s gradients
+};
+
 // Kernel-shape variants (compile-time register budgets).
 struct Variant {
   int opt;    // max output rows per thread (tile rows = 4 * opt)
@@ -98,6 +116,13 @@ bool ls_supported(int W);
 int64_t ls_state_bytes(int H, int Wd, int W, bool save);
 LsState ls_layout(void* base, int H, int Wd, int W, bool save);
 hipError_t launch_forward_ls(const TileParams& p, const LsState& st, bool save, hipStream_t s);
+// streamed adjoint (bf_large_bwd.hip)
+bool bls_supported(int W, bool sigs);
+int64_t bls_state_bytes(int H, int Wd, int W, bool sigs);
+BlsState bls_layout(void* base, int H, int Wd, int W, bool sigs);
+hipError_t launch_backward_ls(const TileParams& p, const BlsState& st, bool sigs, double* partials,
+                              double* grad_sigma, hipStream_t s);
+hipError_t launch_sigma_reduce(const double* partials, int n, bool has_ss, double* out, hipStream_t s);
 
 // Batch (bf_batch.hip)
 struct BatchTile {
@@ -138,4 +163,7 @@ struct bf_plan {
   bool ls;              // large-support path (support too wide for the fused tiles)
   void* d_ls;           // its device state
   bfgpa::LsState ls_state;
+  bool bls;             // streamed adjoint
+  void* d_bls;          // its device state
+  bfgpa::BlsState bls_state;
 };

@@ -266,6 +266,11 @@ __global__ __launch_bounds__(kThreads) void sigma_reduce_kernel(const double* pa
   }
 }
 
+hipError_t launch_sigma_reduce(const double* partials, int n, bool has_ss, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(sigma_reduce_kernel, dim3(1), dim3(kThreads), 0, s, partials, n, has_ss ? 1 : 0, out);
+  return hipGetLastError();
+}
+
 static const Variant kBwdVariants[] = {{8, 24}, {4, 32}};
 int backward_variant_count() { return 2; }
 Variant backward_variant(int v) { return kBwdVariants[v]; }

@@ -19,6 +19,7 @@
 
 #include "bf_device.h"
 #include "bf_internal.h"
+#include "bf_toeplitz.h"
 
 namespace bfgpa {
 
@@ -226,36 +227,8 @@ struct LsPix {
 };
 
 // ---------------------------------------------------------------------------
-// Gaussian passes on the matrix cores.  A 1-D FIR over 16 consecutive
-// outputs is a banded Toeplitz product: out[j] = sum_m x[m] tap[m - j],
-// m = 0 .. 15 + 2W.  v_mfma_f32_16x16x4f32 multiplies a 16x4 by a 4x16
-// float32 block (lane l holds A[l%16][l/16], B[l/16][l%16]; the result
-// D[4(l/16)+v][l%16] sits in accumulator v), so ceil((16 + 2W)/4) of them
-// give a 16x16 block of outputs.  The Toeplitz operand, the same for every
-// block, is one per-lane table in LDS: Tt[kk*64 + l] = tap[4kk + l/16 - l%16]
-// (zero outside [0, 2W]).
+// Gaussian passes on the matrix cores (Toeplitz products, bf_toeplitz.h).
 // ---------------------------------------------------------------------------
-typedef float mf4 __attribute__((ext_vector_type(4)));
-
-__device__ __forceinline__ int ls_kk(int W) { return (16 + 2 * W + 3) / 4; }
-
-template <int NT>
-__device__ __forceinline__ void fill_toeplitz(float* Tt, int W, const float* __restrict__ tz) {
-  const int KK = ls_kk(W);
-  for (int i = threadIdx.x; i < KK * 64; i += NT) {
-    const int kk = i >> 6, l = i & 63;
-    const int d = 4 * kk + (l >> 4) - (l & 15);
-    Tt[i] = (d >= 0 && d <= 2 * W) ? tz[d] : 0.f;
-  }
-}
-
-// Row pitch of the staged rows for the matrix-core row pass: the last
-// block reads 4*ceil((16+2W)/4) columns, up to 258 + 2W; keep the pitch
-// twice an odd number (conflict-free column reads).
-__host__ __device__ inline int ls_rows_pitch_mfma(int W) {
-  const int need = kLsCols + 2 * W + 4;
-  return (need % 4 == 2) ? need : need + 2;
-}
 
 // Row pass on the matrix cores.  Each thread owns the staged values
 // q = threadIdx.x + 256 j of the workgroup's kLsRows x (256 + 2W) window and
@@ -300,7 +273,6 @@ __global__ __launch_bounds__(kThreads) void ls_rows_mfma_kernel(TileParams p, Ls
   const int lane = threadIdx.x & 63;
   const int wv = threadIdx.x >> 6;
   const int cbase = wv * 64;                         // this wave's four 16-column blocks
-  const int arow = (lane & 15) * RWp + (lane >> 4);  // A[l%16][l/16] inside a block
   const int orow = r0 + 4 * (lane >> 4);             // output row of accumulator v: orow + v
   const int ocol = c0 + cbase + (lane & 15);         // output column of block bb: ocol + 16 bb
   for (int k = 0; k < K; ++k) {
@@ -314,23 +286,7 @@ __global__ __launch_bounds__(kThreads) void ls_rows_mfma_kernel(TileParams p, Ls
     mf4 acc[4];
 #pragma unroll
     for (int bb = 0; bb < 4; ++bb) acc[bb] = mf4{0.f, 0.f, 0.f, 0.f};
-    // operands of step kk + 1 are read from LDS while step kk's products run
-    const float* sa = Fc + arow + cbase;
-    float tb = Tt[lane], a[4];
-#pragma unroll
-    for (int bb = 0; bb < 4; ++bb) a[bb] = sa[bb * 16];
-    for (int kk = 0; kk < KK; ++kk) {
-      const int kn = min(kk + 1, KK - 1);
-      const float tn = Tt[kn * 64 + lane];
-      float an[4];
-#pragma unroll
-      for (int bb = 0; bb < 4; ++bb) an[bb] = sa[bb * 16 + 4 * kn];
-#pragma unroll
-      for (int bb = 0; bb < 4; ++bb) acc[bb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[bb], tb, acc[bb], 0, 0, 0);
-      tb = tn;
-#pragma unroll
-      for (int bb = 0; bb < 4; ++bb) a[bb] = an[bb];
-    }
+    toeplitz_rows<4>(Fc, RWp, cbase, Tt, KK, acc);
     float* Hk = st.H[k] + (int64_t)W * st.pitch;  // W zero rows above the image
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
@@ -360,29 +316,13 @@ int64_t ls_rows_mfma_lds_bytes(int W) {
 }
 
 // Column pass on the matrix cores: a workgroup of eight waves stages
-// ls_cols_rows(W) rows x 64 columns of one order's row-filtered image
-// (64 output rows, the 2W halo, the overhang of the last k-step) with
+// ls_cols_rows(W) rows x 64 columns of one order's row-filtered image with
 // direct-to-LDS loads; wave w computes output rows 16 (w % 4) .. + 15 and
-// columns 32 (w / 4) .. + 31 as two 16x16 blocks (Toeplitz table as A,
-// staged columns as B) and folds them into its 8 pixels per lane.  The
-// staged window never leaves the row-filtered image: it carries W zero
-// rows above and W + 8 below a height padded to a multiple of 64.
+// columns 32 (w / 4) .. + 31 as two 16x16 blocks and folds them into its 8
+// pixels per lane.  The staged window never leaves the row-filtered image:
+// it carries W zero rows above and W + 8 below a height padded to a
+// multiple of 64.
 constexpr int kColsThreads = 512;
-
-__host__ __device__ inline int ls_cols_rows(int W) { return (64 + 2 * W + 4 + 3) & ~3; }
-
-// Tile order for the column pass: column bands four tiles wide, row-major
-// inside a band, so the tiles resident on one XCD at a time form a tall
-// block whose overlapping halos are served from its L2.
-__device__ __forceinline__ void band_tile(int t, int tiles_x, int tiles_y, int& ty, int& tx) {
-  constexpr int BW = 4;
-  const int band = t / (BW * tiles_y);
-  const int bx0 = band * BW;
-  const int bw = min(BW, tiles_x - bx0);
-  const int idx = t - band * BW * tiles_y;
-  ty = idx / bw;
-  tx = bx0 + (idx - ty * bw);
-}
 
 template <bool SAVE>
 __global__ __launch_bounds__(kColsThreads) void ls_cols_mfma_kernel(TileParams p, LsState st, int n0, int K) {
@@ -410,35 +350,15 @@ __global__ __launch_bounds__(kColsThreads) void ls_cols_mfma_kernel(TileParams p
     const int nr = (pc0 + 16 * j < p.Wd) ? max(0, min(4, p.H - pr0)) : 0;
     px.template load_part<4>(st, j * 4, (int64_t)pr0 * p.Wd + pc0 + 16 * j, p.Wd, nr);
   }
-  const float* sb = Sl + (rb * 16 + (lane >> 4)) * 64 + ch * 32 + (lane & 15);  // B[l/16][l%16]
   for (int k = 0; k < K; ++k) {
     const int n = n0 + k;
     __syncthreads();
-    // one wave instruction moves 4 staged rows (64 lanes x 16 bytes)
-    const float* hk = st.H[k] + (int64_t)(tr0 + (lane >> 4)) * st.pitch + c0 + (lane & 15) * 4;
-    for (int g = wv; g < rows / 4; g += kColsThreads / 64)
-      __builtin_amdgcn_global_load_lds(hk + (int64_t)(4 * g) * st.pitch,
-                                       (__attribute__((address_space(3))) void*)(Sl + g * 256), 16, 0, 0);
+    stage_rows_lds<kColsThreads>(st.H[k] + (int64_t)tr0 * st.pitch + c0, st.pitch, Sl, rows);
     __syncthreads();
     mf4 acc[2];
 #pragma unroll
     for (int j = 0; j < 2; ++j) acc[j] = mf4{0.f, 0.f, 0.f, 0.f};
-    // operands of step kk + 1 are read from LDS while step kk's products run
-    float ta = Tt[lane], b[2];
-#pragma unroll
-    for (int j = 0; j < 2; ++j) b[j] = sb[j * 16];
-    for (int kk = 0; kk < KK; ++kk) {
-      const int kn = min(kk + 1, KK - 1);
-      const float tn = Tt[kn * 64 + lane];
-      float bn[2];
-#pragma unroll
-      for (int j = 0; j < 2; ++j) bn[j] = sb[4 * kn * 64 + j * 16];
-#pragma unroll
-      for (int j = 0; j < 2; ++j) acc[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(ta, b[j], acc[j], 0, 0, 0);
-      ta = tn;
-#pragma unroll
-      for (int j = 0; j < 2; ++j) b[j] = bn[j];
-    }
+    toeplitz_cols<2>(Sl, rb * 16, ch * 32, Tt, KK, acc);
     const float in1 = p.inv_tab[n + 1];
 #pragma unroll
     for (int j = 0; j < 2; ++j)
@@ -585,11 +505,6 @@ bool ls_supported(int W) {
          (int64_t)(64 + 2 * W) * kLsColPitch * 4 <= max_lds_bytes();
 }
 
-// Rows of one row-filtered image: the height padded to a multiple of 64,
-// W zero rows above, and W + 8 zero rows below (the box window's entering
-// row, and the overhang of the matrix-core column pass's staged window).
-static int64_t ls_hrows(int H, int W) { return (int64_t)((H + 63) / 64) * 64 + 2 * W + 8; }
-
 int64_t ls_state_bytes(int H, int Wd, int W, bool save) {
   const int64_t pitch = ((Wd + 63) / 64) * 64;
   const int64_t img = pitch * H;
@@ -636,7 +551,7 @@ LsState ls_layout(void* base, int H, int Wd, int W, bool save) {
 
 hipError_t launch_forward_ls(const TileParams& p, const LsState& st, bool save, hipStream_t s) {
   if (p.H <= 0 || p.Wd <= 0) return hipSuccess;
-  if (save != (st.DP != nullptr)) return hipErrorInvalidValue;
+  if (save && !st.DP) return hipErrorInvalidValue;  // saved planes need the adjoint sums
   const int64_t npx = (int64_t)p.H * p.Wd;
   const int g1 = (int)std::min<int64_t>((npx + kThreads - 1) / kThreads, 4096);
   hipLaunchKernelGGL(ls_init_kernel, dim3(g1), dim3(kThreads), 0, s, p, st);

@@ -345,9 +345,15 @@ int bf_plan(const bf_params* in, bf_plan_t** out) {
   const bool grad = (p.flags & BF_FLAG_GRAD) != 0;
   const bool sigs = p.kernel == BF_GAUSS;
   int bvariant = -1, bTY = 0;
+  bool bls = false;
   if (grad) {
-    st = choose_backward_tile(p.W, sigs, &bvariant, &bTY);
-    if (st < 0) return st;
+    st = (p.flags & BF_FLAG_STREAMED) ? BF_EUNSUPPORTED : choose_backward_tile(p.W, sigs, &bvariant, &bTY);
+    if (st < 0) {
+      if (!bls_supported(p.W, sigs)) return fail(BF_EUNSUPPORTED, "support W too large for the adjoint");
+      bls = true;  // streamed adjoint
+      bvariant = -1;
+      bTY = 0;
+    }
   }
 
   bf_plan_t* pl = new (std::nothrow) bf_plan_t();
@@ -362,6 +368,9 @@ int bf_plan(const bf_params* in, bf_plan_t** out) {
   pl->bTY = bTY;
   pl->ls = ls;
   pl->d_ls = nullptr;
+  pl->bls = bls;
+  pl->d_bls = nullptr;
+  std::memset(&pl->bls_state, 0, sizeof(pl->bls_state));
   std::memset(&pl->ls_state, 0, sizeof(pl->ls_state));
   hipGetDevice(&pl->device);
 
@@ -398,7 +407,7 @@ int bf_plan(const bf_params* in, bf_plan_t** out) {
     e = hipMalloc(&pl->d_work, 3 * plane * sizeof(float));
     if (e != hipSuccess) { hipFree(pl->d_const); delete pl; return fail(BF_ENOMEM, "hipMalloc adjoint workspace failed"); }
     ws += 3 * plane * sizeof(float);
-    pl->ntiles_b = ((p.height + bTY - 1) / bTY) * ((p.width + kTileCols - 1) / kTileCols);
+    pl->ntiles_b = bls ? kBlsPartials : ((p.height + bTY - 1) / bTY) * ((p.width + kTileCols - 1) / kTileCols);
     e = hipMalloc(&pl->d_partials, 2 * (size_t)pl->ntiles_b * sizeof(double));
     if (e != hipSuccess) {
       hipFree(pl->d_work); hipFree(pl->d_const); delete pl;
@@ -426,6 +435,25 @@ int bf_plan(const bf_params* in, bf_plan_t** out) {
     pl->ls_state = ls_layout(pl->d_ls, p.height, p.width, p.W, grad);
     ws += lb;
   }
+  if (bls) {
+    const int64_t bb = bls_state_bytes(p.height, p.width, p.W, sigs);
+    e = hipMalloc(&pl->d_bls, bb);
+    if (e == hipSuccess) {
+      e = hipMemset(pl->d_bls, 0, bb);  // zero rows around the row-filtered images
+      if (e != hipSuccess) hipFree(pl->d_bls);
+    }
+    if (e != hipSuccess) {
+      if (pl->d_ls) hipFree(pl->d_ls);
+      hipFree(pl->d_work);
+      hipFree(pl->d_partials);
+      hipFree(pl->d_const);
+      delete pl;
+      return e == hipErrorOutOfMemory ? fail(BF_ENOMEM, "hipMalloc streamed adjoint state failed")
+                                      : hip_fail(e, "streamed adjoint state");
+    }
+    pl->bls_state = bls_layout(pl->d_bls, p.height, p.width, p.W, sigs);
+    ws += bb;
+  }
   pl->info.workspace_bytes = ws;
   *out = pl;
   if (ost == BF_WNOGUARANTEE) set_error("order below the bound: no +-delta guarantee");
@@ -447,6 +475,7 @@ int bf_destroy(bf_plan_t* plan) {
   if (plan->d_work) hipFree(plan->d_work);
   if (plan->d_partials) hipFree(plan->d_partials);
   if (plan->d_ls) hipFree(plan->d_ls);
+  if (plan->d_bls) hipFree(plan->d_bls);
   hipSetDevice(dev);
   delete plan;
   return BF_OK;
@@ -514,7 +543,7 @@ int bf_backward(const bf_plan_t* pl, const float* in, int64_t in_pitch, const fl
                 int64_t gout_pitch, const float* saved, float* grad_in, int64_t gin_pitch,
                 double* grad_sigma, void* stream) {
   if (!pl || !in || !grad_out) return fail(BF_EINVAL, "NULL plan or image pointer");
-  if (!(pl->p.flags & BF_FLAG_GRAD) || pl->bvariant < 0)
+  if (!(pl->p.flags & BF_FLAG_GRAD) || (pl->bvariant < 0 && !pl->bls))
     return fail(BF_EINVAL, "plan was built without BF_FLAG_GRAD");
   if (in_pitch < pl->p.width || gout_pitch < pl->p.width || (grad_in && gin_pitch < pl->p.width))
     return fail(BF_EINVAL, "pitch smaller than width");
@@ -533,7 +562,8 @@ int bf_backward(const bf_plan_t* pl, const float* in, int64_t in_pitch, const fl
     fp.saved = pl->d_work;
     fp.TY = pl->TY;
     fp.tiles_x = (pl->p.width + kTileCols - 1) / kTileCols;
-    hipError_t e = launch_forward(fp, pl->variant, acc64, true, s);
+    hipError_t e = pl->ls ? launch_forward_ls(fp, pl->ls_state, true, s)
+                          : launch_forward(fp, pl->variant, acc64, true, s);
     if (e != hipSuccess) return hip_fail(e, "forward (recompute) launch");
     saved = pl->d_work;
   }
@@ -547,7 +577,8 @@ int bf_backward(const bf_plan_t* pl, const float* in, int64_t in_pitch, const fl
   tp.TY = pl->bTY;
   tp.tiles_x = (pl->p.width + kTileCols - 1) / kTileCols;
   const bool sigs = pl->p.kernel == BF_GAUSS && grad_sigma != nullptr;
-  hipError_t e = launch_backward(tp, pl->bvariant, sigs, pl->d_partials, grad_sigma, s);
+  hipError_t e = pl->bls ? launch_backward_ls(tp, pl->bls_state, sigs, pl->d_partials, grad_sigma, s)
+                         : launch_backward(tp, pl->bvariant, sigs, pl->d_partials, grad_sigma, s);
   if (e != hipSuccess) return hip_fail(e, "adjoint launch");
   return BF_OK;
 }

@@ -138,3 +138,59 @@ def test_autograd_module():
     assert np.abs(x.grad.cpu().numpy() - df).max() <= RTOL * np.abs(df).max()
     assert abs(m.sigma_r.grad.item() - dsr) <= RTOL * abs(dsr)
     assert abs(m.sigma_s.grad.item() - dss) <= RTOL * abs(dss)
+
+
+# --- streamed adjoint (supports wider than the fused adjoint tiles) --------
+
+@pytest.mark.parametrize("kind,kw,sr,shape,seed", [
+    ("gauss", dict(sigma_s=12.0), 30.0, (60, 90), 11),   # W = 36: streamed adjoint by size
+    ("box", dict(W=40), 25.0, (70, 100), 12),
+    ("gauss", dict(sigma_s=2.0, streamed=True), 30.0, (45, 71), 13),
+    ("box", dict(W=4, streamed=True), 20.0, (50, 66), 14),
+])
+def test_streamed_adjoint_matches_autograd(kind, kw, sr, shape, seed):
+    f = synthimg.gen1(*shape, seed)
+    gbar = synthimg.gen2(*shape, seed + 100) / 255.0 - 0.5
+    for use_saved in (True, False):
+        gin, gs, plan, f32, g32 = _run(f, gbar, kind, sr, use_saved=use_saved, **kw)
+        W = plan.info.W
+        df, dsr, dss = GR.vjp_autograd(f32, g32, kind, kw.get("sigma_s"), W, sr, plan.info.N, 127.5)
+        err = np.abs(gin - df).max() / np.abs(df).max()
+        print(f"{kind} {kw} saved={use_saved} N={plan.info.N}: df rel {err:.2e}  dsr {gs[0]:.6e} vs "
+              f"{dsr:.6e}  dss {gs[1]:.6e} vs {dss:.6e}", flush=True)
+        assert err <= RTOL
+        assert abs(gs[0] - dsr) <= RTOL * abs(dsr)
+        if kind == "gauss":
+            assert abs(gs[1] - dss) <= RTOL * abs(dss)
+        else:
+            assert np.isnan(gs[1])
+
+
+@pytest.mark.parametrize("kind,kw,sr", [("box", dict(W=6), 30.0), ("gauss", dict(sigma_s=3.0), 20.0)])
+def test_streamed_adjoint_matches_fused(kind, kw, sr):
+    torch, P = _mods()
+    f = synthimg.gen2(130, 190, 15)
+    gbar = synthimg.gen1(130, 190, 16) / 255.0 - 0.5
+    x = torch.tensor(f, dtype=torch.float32, device="cuda")
+    g = torch.tensor(gbar, dtype=torch.float32, device="cuda")
+    res = []
+    for streamed in (False, True):
+        plan = P.Plan(kind, sr, 130, 190, grad=True, streamed=streamed, **kw)
+        gin, gs = plan.backward(x, g)  # recomputes the forward state
+        torch.cuda.synchronize()
+        res.append((gin.cpu().numpy().astype(np.float64), gs.cpu().numpy()))
+    (a, sa), (b, sb) = res
+    # both compute the filters in float32 in different summation orders (VALU
+    # tiles vs matrix-core Toeplitz blocks); the float64 reference decides
+    W = P.Plan(kind, sr, 130, 190, **kw).info.W
+    N = P.Plan(kind, sr, 130, 190, **kw).info.N
+    df, dsr, dss = GR.vjp_autograd(x.cpu().numpy().astype(np.float64), g.cpu().numpy().astype(np.float64),
+                                   kind, kw.get("sigma_s"), W, sr, N, 127.5)
+    print(f"dsr fused {sa[0]:.9e} streamed {sb[0]:.9e} fp64 {dsr:.9e}; "
+          f"dss fused {sa[1]:.9e} streamed {sb[1]:.9e} fp64 {dss:.9e}", flush=True)
+    assert np.abs(a - b).max() <= 1e-4 * np.abs(a).max()
+    assert abs(sa[0] - sb[0]) <= 1e-4 * abs(dsr)
+    assert abs(sb[0] - dsr) <= RTOL * abs(dsr)
+    if kind == "gauss":
+        assert abs(sa[1] - sb[1]) <= 1e-4 * abs(dss)
+        assert abs(sb[1] - dss) <= RTOL * abs(dss)
