@@ -116,7 +116,19 @@ int bf_plan(const bf_params* p, bf_plan_t** out);
 int bf_plan_get_info(const bf_plan_t* plan, bf_plan_info* out);
 int bf_destroy(bf_plan_t* plan);
 
-/* Forward filter, Algorithm 2 (Sec. 3) fused in one kernel launch.
+/* A second plan with the same parameters and its own device workspace.  A
+ * plan's parameters never change after bf_plan, but bf_forward and
+ * bf_backward use its workspace (the adjoint's recompute buffer and
+ * partial sums, the streamed paths' state), so calls that may overlap, e.g.
+ * on two streams, need one plan each.  *out is owned by the caller (free
+ * with bf_destroy); the clone lives on the current HIP device.  Errors as
+ * for bf_plan. */
+int bf_plan_clone_workspace(const bf_plan_t* plan, bf_plan_t** out);
+
+/* Forward filter, Algorithm 2 (Sec. 3): one fused kernel launch, or, for
+ * supports too wide for a tile's region to stay on chip (and with
+ * BF_FLAG_STREAMED), the streamed sequence that filters blocks of orders
+ * through the plan's device workspace.
  *   in      device, height x width float32, row pitch in_pitch (elements)
  *   out     device, height x width float32, row pitch out_pitch; must not
  *           alias `in`
@@ -137,8 +149,10 @@ int bf_forward(const bf_plan_t* plan, const float* in, int64_t in_pitch,
  *   saved       the buffer filled by bf_forward on the same input, or NULL:
  *               then the forward state is recomputed into the plan's
  *               workspace (requires BF_FLAG_GRAD at plan time).
- * The auxiliary images are recomputed, never stored.  Deterministic: the
- * sigma gradients are reduced in a fixed order. */
+ * The auxiliary images are recomputed, never stored (supports wider than the
+ * fused adjoint tiles stream blocks of filtered adjoint images through the
+ * plan's workspace).  Deterministic: the sigma gradients are reduced in a
+ * fixed order. */
 int bf_backward(const bf_plan_t* plan, const float* in, int64_t in_pitch,
                 const float* grad_out, int64_t gout_pitch, const float* saved,
                 float* grad_in, int64_t gin_pitch, double* grad_sigma, void* stream);
@@ -162,6 +176,27 @@ int bf_batch_status(const bf_batch_t* batch, int32_t* per_image_status, int32_t*
  * *chosen receives the index of the chosen candidate (may be NULL). */
 int bf_batch_tune(bf_batch_t* batch, const float* const* in, const int64_t* in_pitch,
                   float* const* out, const int64_t* out_pitch, void* stream, int32_t* chosen);
+/* Batched vector-Jacobian product (an extension beyond the paper), for a
+ * batch planned with BF_FLAG_GRAD on at least one image.  Per image i, as
+ * bf_backward with saved = NULL: the forward state is recomputed by one
+ * persistent batch launch; the adjoint tiles of all images whose support
+ * fits the fused adjoint run as one more persistent launch over a
+ * cost-ordered work list, and wider supports run the streamed adjoint image
+ * by image.  Arguments are host arrays of `count` entries:
+ *   in, in_pitch          the images and row pitches (device pointers)
+ *   grad_out, gout_pitch  dL/d(out_i)
+ *   grad_in, gin_pitch    NULL, or receives dL/d(in_i) (an entry may be NULL)
+ *   grad_sigma            NULL or DEVICE double[2 * count]: per image
+ *                         {dL/d sigma_r, dL/d sigma_s}, NaN for the box
+ *                         kernel's sigma_s; entries of images whose plan
+ *                         failed (bf_batch_status < 0) are left untouched.
+ * Returns BF_EINVAL for NULL arrays, pitches < width, or a batch planned
+ * without BF_FLAG_GRAD; BF_EHIP if a launch fails.  The batch's device
+ * workspace is shared by its calls: calls on one batch are serialised
+ * (each waits for the previous call's host-side staging). */
+int bf_batch_backward(bf_batch_t* batch, const float* const* in, const int64_t* in_pitch,
+                      const float* const* grad_out, const int64_t* gout_pitch, float* const* grad_in,
+                      const int64_t* gin_pitch, double* grad_sigma, void* stream);
 int bf_batch_destroy(bf_batch_t* batch);
 
 const char* bf_status_string(int status);

@@ -70,6 +70,7 @@ SIGNATURES = {
     "bf_plan": (C.c_int, [C.POINTER(bf_params), C.POINTER(C.c_void_p)]),
     "bf_plan_get_info": (C.c_int, [C.c_void_p, C.POINTER(bf_plan_info)]),
     "bf_destroy": (C.c_int, [C.c_void_p]),
+    "bf_plan_clone_workspace": (C.c_int, [C.c_void_p, C.POINTER(C.c_void_p)]),
     "bf_forward": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_int64, C.c_void_p,
                              C.c_void_p]),
     "bf_backward": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_int64, C.c_void_p,
@@ -81,6 +82,9 @@ SIGNATURES = {
     "bf_batch_tune": (C.c_int, [C.c_void_p, C.POINTER(C.c_void_p), C.POINTER(C.c_int64),
                                 C.POINTER(C.c_void_p), C.POINTER(C.c_int64), C.c_void_p,
                                 C.POINTER(C.c_int32)]),
+    "bf_batch_backward": (C.c_int, [C.c_void_p, C.POINTER(C.c_void_p), C.POINTER(C.c_int64),
+                                    C.POINTER(C.c_void_p), C.POINTER(C.c_int64), C.POINTER(C.c_void_p),
+                                    C.POINTER(C.c_int64), C.c_void_p, C.c_void_p]),
     "bf_batch_destroy": (C.c_int, [C.c_void_p]),
     "bf_status_string": (C.c_char_p, [C.c_int]),
     "bf_last_error_message": (C.c_char_p, []),

@@ -105,6 +105,21 @@ class Plan:
             self._lib.bf_destroy(h)
             self._h = None
 
+    def clone(self) -> "Plan":
+        """Same parameters, separate device workspace (bf_plan_clone_workspace)."""
+        c = Plan.__new__(Plan)
+        c._lib = self._lib
+        c.kernel = self.kernel
+        c.height, c.width = self.height, self.width
+        c.params = self.params
+        h = C.c_void_p()
+        st = L.check(self._lib.bf_plan_clone_workspace(self._h, C.byref(h)), "bf_plan_clone_workspace")
+        c._h = h
+        info = L.bf_plan_info()
+        L.check(self._lib.bf_plan_get_info(c._h, C.byref(info)), "bf_plan_get_info")
+        c.info = _info(info, st)
+        return c
+
     def new_saved(self) -> torch.Tensor:
         return torch.empty(3 * self.height * self.width, dtype=torch.float32, device="cuda")
 
@@ -188,6 +203,34 @@ class Batch:
         L.check(self._lib.bf_batch_forward(self._h, ip, ipt, op, opt, _stream_handle(stream)),
                 "bf_batch_forward")
         return outputs
+
+    def backward(self, inputs, grad_outs, grad_ins=None, want_sigma: bool = True, stream=None):
+        """Returns (list of dL/din_i, float64 tensor (count, 2) of [dL/dsigma_r, dL/dsigma_s] or None)."""
+        n = self.count
+        if len(inputs) != n or len(grad_outs) != n:
+            raise ValueError("one input and one output gradient per image")
+        if grad_ins is None:
+            grad_ins = [torch.empty_like(x) for x in inputs]
+        ip = (C.c_void_p * n)()
+        ipt = (C.c_int64 * n)()
+        gp = (C.c_void_p * n)()
+        gpt = (C.c_int64 * n)()
+        op = (C.c_void_p * n)()
+        opt = (C.c_int64 * n)()
+        for i, (a, g, o) in enumerate(zip(inputs, grad_outs, grad_ins)):
+            H, W = self.shapes[i]
+            _check_image(a, H, W, f"input[{i}]")
+            _check_image(g, H, W, f"grad_out[{i}]")
+            _check_image(o, H, W, f"grad_in[{i}]")
+            ip[i], ipt[i] = a.data_ptr(), a.stride(0)
+            gp[i], gpt[i] = g.data_ptr(), g.stride(0)
+            op[i], opt[i] = o.data_ptr(), o.stride(0)
+        dev = inputs[0].device
+        gs = torch.empty(n, 2, dtype=torch.float64, device=dev) if want_sigma else None
+        L.check(self._lib.bf_batch_backward(self._h, ip, ipt, gp, gpt, op, opt,
+                                            C.c_void_p(gs.data_ptr() if gs is not None else 0),
+                                            _stream_handle(stream)), "bf_batch_backward")
+        return grad_ins, gs
 
     def tune(self, inputs, outputs, stream=None) -> int:
         ip, ipt, op, opt = self._arrays(inputs, outputs)

@@ -22,59 +22,152 @@
 
 namespace bfgpa {
 
-template <int OPT, int MREG, bool ACC64>
+template <int OPT, int MREG, bool ACC64, bool SAVE>
 __global__ __launch_bounds__(kThreads) void gpa_batch_kernel(const TileParams* __restrict__ params,
                                                              const BatchTile* __restrict__ tiles,
                                                              int ntiles, int* counter) {
   extern __shared__ float lds[];
   __shared__ int s_idx;
   for (;;) {
+    // The barrier in front of the claim keeps the compiler from merging this
+    // thread-0 branch with one at the end of the previous tile across the
+    // loop latch (which would leave the claim outside the loop that holds
+    // the barriers).  The claimed index is made wave-uniform, so the exit
+    // test and the tile's parameters are scalar.
+    __syncthreads();
     if (threadIdx.x == 0) s_idx = atomicAdd(counter, 1);
     __syncthreads();
-    const int idx = s_idx;
-    __syncthreads();
+    const int idx = __builtin_amdgcn_readfirstlane(s_idx);
     if (idx >= ntiles) break;  // every workgroup ends here once the list is drained
     const BatchTile bt = tiles[idx];
-    const TileParams p = params[bt.image];
+    const TileParams p = params[__builtin_amdgcn_readfirstlane(bt.image)];
     if (p.kt == BF_BOX)
-      forward_tile<BF_BOX, OPT, MREG, ACC64, false>(p, bt.r0, bt.c0, lds);
+      forward_tile<BF_BOX, OPT, MREG, ACC64, SAVE>(p, bt.r0, bt.c0, lds);
     else
-      forward_tile<BF_GAUSS, OPT, MREG, ACC64, false>(p, bt.r0, bt.c0, lds);
+      forward_tile<BF_GAUSS, OPT, MREG, ACC64, SAVE>(p, bt.r0, bt.c0, lds);
+  }
+}
+
+// Batched adjoint: the same persistent scheme over adjoint tiles.  Each
+// tile writes its two sigma-gradient sums to its own slot (BatchTile::pad),
+// so the per-image sums below run in a fixed order.
+template <int OPT, int MREG>
+__global__ __launch_bounds__(kThreads) void gpa_batch_backward_kernel(const TileParams* __restrict__ params,
+                                                                      const BatchTile* __restrict__ tiles,
+                                                                      int ntiles, int* counter,
+                                                                      double* partials) {
+  extern __shared__ float lds[];
+  __shared__ double red[2 * kThreads];
+  __shared__ int s_idx;
+  for (;;) {
+    // as in gpa_batch_kernel: barrier before the claim, wave-uniform index
+    __syncthreads();
+    if (threadIdx.x == 0) s_idx = atomicAdd(counter, 1);
+    __syncthreads();
+    const int idx = __builtin_amdgcn_readfirstlane(s_idx);
+    if (idx >= ntiles) break;  // every workgroup ends here once the list is drained
+    const BatchTile bt = tiles[idx];
+    const TileParams p = params[__builtin_amdgcn_readfirstlane(bt.image)];
+    double* part = partials + 2 * (int64_t)__builtin_amdgcn_readfirstlane(bt.pad);
+    if (p.kt == BF_BOX)
+      backward_tile<BF_BOX, OPT, MREG, false>(p, bt.r0, bt.c0, lds, red, part);
+    else
+      backward_tile<BF_GAUSS, OPT, MREG, true>(p, bt.r0, bt.c0, lds, red, part);
+  }
+}
+
+// Per-image sums of the adjoint tiles' partials (one workgroup per image;
+// n < 0 marks an image whose gradients are produced elsewhere).
+struct BatchRed {
+  int32_t off, n, has_ss, pad;
+};
+
+__global__ __launch_bounds__(kThreads) void batch_sigma_reduce_kernel(const double* partials,
+                                                                      const BatchRed* info, double* out) {
+  __shared__ double red[2][kThreads];
+  const BatchRed bi = info[blockIdx.x];
+  if (bi.n < 0) return;  // uniform per workgroup
+  double a = 0.0, b = 0.0;
+  for (int i = threadIdx.x; i < bi.n; i += kThreads) {
+    a += partials[2 * (int64_t)(bi.off + i)];
+    b += partials[2 * (int64_t)(bi.off + i) + 1];
+  }
+  red[0][threadIdx.x] = a;
+  red[1][threadIdx.x] = b;
+  __syncthreads();
+  for (int w = kThreads / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) {
+      red[0][threadIdx.x] += red[0][threadIdx.x + w];
+      red[1][threadIdx.x] += red[1][threadIdx.x + w];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    out[2 * blockIdx.x] = red[0][0];
+    out[2 * blockIdx.x + 1] = bi.has_ss ? red[1][0] : __builtin_nan("");
   }
 }
 
 __global__ void batch_reset_kernel(int* counter) {
-  if (threadIdx.x == 0) counter[0] = 0;
+  if (threadIdx.x < 2) counter[threadIdx.x] = 0;
 }
 
 // Shapes the batch kernel is built in (opt, mreg); index = candidate variant.
 static const Variant kBatchVariants[] = {{8, 20}, {8, 32}, {4, 48}, {4, 72}};
 static constexpr int kNumBatchVariants = sizeof(kBatchVariants) / sizeof(kBatchVariants[0]);
 
-template <int OPT, int MREG>
-static hipError_t launch_batch_t(const TileParams* d_params, const BatchTile* d_tiles, int ntiles,
-                                 int* counter, int grid, size_t lds, bool acc64, hipStream_t s) {
-  if (acc64) {
-    auto k = gpa_batch_kernel<OPT, MREG, true>;
-    hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, max_lds_bytes() - 64);
-    hipLaunchKernelGGL(k, dim3(grid), dim3(kThreads), lds, s, d_params, d_tiles, ntiles, counter);
-  } else {
-    auto k = gpa_batch_kernel<OPT, MREG, false>;
-    hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, max_lds_bytes() - 64);
-    hipLaunchKernelGGL(k, dim3(grid), dim3(kThreads), lds, s, d_params, d_tiles, ntiles, counter);
-  }
+template <int OPT, int MREG, bool ACC64, bool SAVE>
+static hipError_t launch_batch_k(const TileParams* d_params, const BatchTile* d_tiles, int ntiles,
+                                 int* counter, int grid, size_t lds, hipStream_t s) {
+  auto k = gpa_batch_kernel<OPT, MREG, ACC64, SAVE>;
+  hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     max_lds_bytes() - 64);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k, dim3(grid), dim3(kThreads), lds, s, d_params, d_tiles, ntiles, counter);
   return hipGetLastError();
 }
 
+template <int OPT, int MREG>
+static hipError_t launch_batch_t(const TileParams* d_params, const BatchTile* d_tiles, int ntiles,
+                                 int* counter, int grid, size_t lds, bool acc64, bool save, hipStream_t s) {
+  if (acc64)
+    return save ? launch_batch_k<OPT, MREG, true, true>(d_params, d_tiles, ntiles, counter, grid, lds, s)
+                : launch_batch_k<OPT, MREG, true, false>(d_params, d_tiles, ntiles, counter, grid, lds, s);
+  return save ? launch_batch_k<OPT, MREG, false, true>(d_params, d_tiles, ntiles, counter, grid, lds, s)
+              : launch_batch_k<OPT, MREG, false, false>(d_params, d_tiles, ntiles, counter, grid, lds, s);
+}
+
 static hipError_t launch_batch_v(int v, const TileParams* d_params, const BatchTile* d_tiles,
-                                 int ntiles, int* counter, int grid, size_t lds, bool acc64,
+                                 int ntiles, int* counter, int grid, size_t lds, bool acc64, bool save,
                                  hipStream_t s) {
   switch (v) {
-    case 0: return launch_batch_t<8, 20>(d_params, d_tiles, ntiles, counter, grid, lds, acc64, s);
-    case 1: return launch_batch_t<8, 32>(d_params, d_tiles, ntiles, counter, grid, lds, acc64, s);
-    case 2: return launch_batch_t<4, 48>(d_params, d_tiles, ntiles, counter, grid, lds, acc64, s);
-    default: return launch_batch_t<4, 72>(d_params, d_tiles, ntiles, counter, grid, lds, acc64, s);
+    case 0: return launch_batch_t<8, 20>(d_params, d_tiles, ntiles, counter, grid, lds, acc64, save, s);
+    case 1: return launch_batch_t<8, 32>(d_params, d_tiles, ntiles, counter, grid, lds, acc64, save, s);
+    case 2: return launch_batch_t<4, 48>(d_params, d_tiles, ntiles, counter, grid, lds, acc64, save, s);
+    default: return launch_batch_t<4, 72>(d_params, d_tiles, ntiles, counter, grid, lds, acc64, save, s);
   }
+}
+
+// Adjoint tile shapes: the single-image adjoint's variants (backward_variant).
+template <int OPT, int MREG>
+static hipError_t launch_batch_bwd_t(const TileParams* d_params, const BatchTile* d_tiles, int ntiles,
+                                     int* counter, double* partials, int grid, size_t lds, hipStream_t s) {
+  auto k = gpa_batch_backward_kernel<OPT, MREG>;
+  hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     max_lds_bytes() - 2 * kThreads * 8 - 64);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k, dim3(grid), dim3(kThreads), lds, s, d_params, d_tiles, ntiles, counter, partials);
+  return hipGetLastError();
+}
+
+static hipError_t launch_batch_bwd(int v, const TileParams* d_params, const BatchTile* d_tiles, int ntiles,
+                                   int* counter, double* partials, int grid, size_t lds, hipStream_t s) {
+  const Variant vv = backward_variant(v);
+  if (vv.opt == 8 && vv.mreg == 24)
+    return launch_batch_bwd_t<8, 24>(d_params, d_tiles, ntiles, counter, partials, grid, lds, s);
+  if (vv.opt == 4 && vv.mreg == 32)
+    return launch_batch_bwd_t<4, 32>(d_params, d_tiles, ntiles, counter, partials, grid, lds, s);
+  return hipErrorInvalidValue;
 }
 
 }  // namespace bfgpa
@@ -112,6 +205,24 @@ struct bf_batch {
   hipGraphExec_t gexec[2] = {nullptr, nullptr};
   int slot = 0;
   std::string key;
+  // adjoint (planned when an image asks for BF_FLAG_GRAD)
+  bool grad = false;
+  int bvariant = -1;                  // adjoint tile variant of the fused images
+  size_t blds = 0;                    // its dynamic LDS bytes
+  std::vector<int> bTY;               // per-image adjoint tile rows (0: streamed adjoint)
+  std::vector<int> streamed;          // images on the streamed adjoint
+  BatchTile* d_btiles = nullptr;      // adjoint tiles, cost-ordered
+  int nbtiles = 0;
+  double* d_bpartials = nullptr;      // two sums per adjoint tile
+  BatchRed* d_bred = nullptr;         // per-image partial ranges
+  float* d_saved = nullptr;           // forward state (3 planes per image)
+  std::vector<int64_t> saved_off;
+  TileParams* d_bparams = nullptr;    // forward-with-state params, then adjoint params
+  TileParams* h_bstage = nullptr;     // pinned staging of d_bparams
+  hipEvent_t bev = nullptr;
+  bool bev_used = false;
+  void* d_bls = nullptr;              // streamed adjoint state, reused image by image
+  double* d_bls_partials = nullptr;
 };
 
 namespace bfgpa {
@@ -246,8 +357,95 @@ static int run_direct(bf_batch* b, int k, hipStream_t s, int grid) {
     return fail(BF_EHIP, "hipMemcpyAsync batch params");
   hipLaunchKernelGGL(batch_reset_kernel, dim3(1), dim3(64), 0, s, b->d_counter);
   hipError_t e = launch_batch_v(sh.variant, b->d_params, b->d_tiles, b->ntiles, b->d_counter, grid,
-                                sh.lds, b->acc64, s);
+                                sh.lds, b->acc64, false, s);
   if (e != hipSuccess) return fail(BF_EHIP, std::string("batch launch: ") + hipGetErrorString(e));
+  return BF_OK;
+}
+
+// Adjoint planning: images whose support fits the fused adjoint tiles get
+// adjoint tiles in one persistent work list (the shape that fits the most
+// images); the others run the streamed adjoint one after another on a
+// shared state buffer.  The forward state the adjoint reads (3 planes per
+// image) is recomputed by the batch forward kernel at each call.
+static int plan_batch_adjoint(bf_batch* b) {
+  const int count = b->count;
+  int best = -1, best_n = -1;
+  for (int v = 0; v < backward_variant_count(); ++v) {
+    const Variant vv = backward_variant(v);
+    int n = 0;
+    for (int i = 0; i < count; ++i) {
+      if (b->status[i] < 0) continue;
+      const int TY = 4 * vv.opt, W = b->prm[i].W;
+      const bool sigs = b->prm[i].kernel == BF_GAUSS;
+      if (region_floats(TY, W) <= (int64_t)kThreads * vv.mreg &&
+          backward_lds_bytes(TY, W, sigs) + 2 * kThreads * 8 + 64 <= max_lds_bytes())
+        ++n;
+    }
+    if (n > best_n) {
+      best_n = n;
+      best = v;
+    }
+  }
+  b->bvariant = best;
+  const Variant vv = backward_variant(best);
+  b->bTY.assign(count, 0);
+  std::vector<std::pair<double, BatchTile>> list;
+  std::vector<BatchRed> red(count, BatchRed{0, -1, 0, 0});
+  int slots = 0;
+  int64_t lds = 0, bls_bytes = 0, saved = 0;
+  b->saved_off.assign(count, 0);
+  for (int i = 0; i < count; ++i) {
+    if (b->status[i] < 0) continue;
+    const bf_params& p = b->prm[i];
+    const bool sigs = p.kernel == BF_GAUSS;
+    b->saved_off[i] = saved;
+    saved += 3 * (int64_t)p.height * p.width;
+    const int TY = 4 * vv.opt;
+    if (region_floats(TY, p.W) <= (int64_t)kThreads * vv.mreg &&
+        backward_lds_bytes(TY, p.W, sigs) + 2 * kThreads * 8 + 64 <= max_lds_bytes()) {
+      b->bTY[i] = TY;
+      lds = std::max(lds, backward_lds_bytes(TY, p.W, sigs));
+      const double c = 2.5 * tile_cost(p, b->info[i], TY);
+      red[i] = BatchRed{slots, 0, sigs ? 1 : 0, 0};
+      for (int r0 = 0; r0 < p.height; r0 += TY)
+        for (int c0 = 0; c0 < p.width; c0 += kTileCols) {
+          list.push_back({c, BatchTile{i, r0, c0, slots++}});
+          red[i].n++;
+        }
+    } else {
+      if (!bls_supported(p.W, sigs)) return fail(BF_EUNSUPPORTED, "a batch image's support W is too large for the adjoint");
+      b->streamed.push_back(i);
+      bls_bytes = std::max(bls_bytes, bls_state_bytes(p.height, p.width, p.W, sigs));
+    }
+  }
+  std::stable_sort(list.begin(), list.end(),
+                   [](const std::pair<double, BatchTile>& a, const std::pair<double, BatchTile>& c) {
+                     return a.first > c.first;
+                   });
+  std::vector<BatchTile> tiles;
+  for (auto& e : list) tiles.push_back(e.second);
+  b->nbtiles = (int)tiles.size();
+  b->blds = (size_t)lds;
+  auto dev_alloc = [&](void** ptr, size_t bytes) { return hipMalloc(ptr, std::max<size_t>(bytes, 16)) == hipSuccess; };
+  if (!dev_alloc((void**)&b->d_btiles, tiles.size() * sizeof(BatchTile)) ||
+      !dev_alloc((void**)&b->d_bpartials, 2 * (size_t)slots * sizeof(double)) ||
+      !dev_alloc((void**)&b->d_bred, count * sizeof(BatchRed)) ||
+      !dev_alloc((void**)&b->d_saved, (size_t)saved * sizeof(float)) ||
+      !dev_alloc((void**)&b->d_bparams, 2 * (size_t)count * sizeof(TileParams)) ||
+      !dev_alloc((void**)&b->d_bls_partials, 2 * (size_t)kBlsPartials * sizeof(double)))
+    return fail(BF_ENOMEM, "hipMalloc batch adjoint buffers failed");
+  if (bls_bytes > 0 && !dev_alloc(&b->d_bls, (size_t)bls_bytes))
+    return fail(BF_ENOMEM, "hipMalloc batch streamed adjoint state failed");
+  if (!tiles.empty() && hipMemcpy(b->d_btiles, tiles.data(), tiles.size() * sizeof(BatchTile),
+                                  hipMemcpyHostToDevice) != hipSuccess)
+    return fail(BF_EHIP, "hipMemcpy batch adjoint tiles failed");
+  if (hipMemcpy(b->d_bred, red.data(), count * sizeof(BatchRed), hipMemcpyHostToDevice) != hipSuccess)
+    return fail(BF_EHIP, "hipMemcpy batch reduction table failed");
+  if (hipHostMalloc((void**)&b->h_bstage, 2 * (size_t)count * sizeof(TileParams), hipHostMallocDefault) !=
+      hipSuccess)
+    return fail(BF_ENOMEM, "hipHostMalloc batch adjoint staging failed");
+  if (hipEventCreateWithFlags(&b->bev, hipEventDisableTiming) != hipSuccess)
+    return fail(BF_EHIP, "hipEventCreate failed");
   return BF_OK;
 }
 
@@ -282,9 +480,11 @@ int bf_batch_plan(int32_t count, const bf_params* per_image, bf_batch_t** out) {
   std::vector<std::vector<float>> tabs(count);
   std::vector<int64_t> offs(count, 0);
   int64_t total = 0;
+  std::vector<int64_t> strides(count, 0), ntaps(count, 0);
   for (int i = 0; i < count; ++i) {
     bf_params pi = per_image[i];
-    pi.flags &= ~BF_FLAG_GRAD;
+    if (pi.flags & BF_FLAG_GRAD) b->grad = true;
+    pi.flags &= ~(BF_FLAG_GRAD | BF_FLAG_STREAMED);
     int st = bf_order(&pi, &b->info[i]);
     b->status[i] = st;
     if (st < 0) continue;
@@ -298,42 +498,23 @@ int bf_batch_plan(int32_t count, const bf_params* per_image, bf_batch_t** out) {
       delete b;
       return fail(BF_EINVAL, "all images of a batch must use the same accumulation precision");
     }
-    // tables: s, r, inv (N+2), taps (padded)
-    const int N = b->info[i].N, W = pi.W;
-    const double lam = b->info[i].lambda, X = std::sqrt(lam);
-    auto logM = [&](int n) -> double {
-      if (n == 0) return 0.0;
-      if ((double)n <= lam) return 0.5 * n * (std::log((double)n) - 1.0);
-      return -0.5 * lam + n * std::log(X);
-    };
-    const int64_t stride = ((N + 2 + 63) / 64) * 64;
-    const int64_t ntap = ((2 * W + 1 + 2 * kTapPad + 63) / 64) * 64;
-    std::vector<float>& h = tabs[i];
-    h.assign(3 * stride + ntap, 0.0f);
-    for (int n = 1; n <= N + 1; ++n) {
-      const double r = std::exp(logM(n) - logM(n - 1));
-      h[n] = (float)(1.0 / r);
-      h[stride + n] = (float)r;
-      h[2 * stride + n] = (float)(1.0 / n);
-    }
-    for (int a = -W; a <= W; ++a)
-      h[3 * stride + kTapPad + a + W] =
-          pi.kernel == BF_BOX ? 1.0f : (float)std::exp(-(double)a * a / (2.0 * pi.sigma_s * pi.sigma_s));
+    tabs[i] = const_tables(pi, b->info[i], &strides[i], &ntaps[i]);
     offs[i] = total;
-    total += (int64_t)h.size();
+    total += (int64_t)tabs[i].size();
     TileParams& t = b->hp[i];
     std::memset(&t, 0, sizeof(t));
     t.H = pi.height;
     t.Wd = pi.width;
-    t.W = W;
-    t.N = N;
+    t.W = pi.W;
+    t.N = b->info[i].N;
     t.kt = pi.kernel;
     t.sigma_r = (float)pi.sigma_r;
     t.inv_sigma_r = (float)(1.0 / pi.sigma_r);
     t.center = (float)pi.center;
     t.inv_T = (float)(1.0 / pi.T);
     t.X = (float)(pi.T / pi.sigma_r);
-    (void)stride;
+    t.inv_sigma_s3 = pi.kernel == BF_GAUSS ? (float)(1.0 / (pi.sigma_s * pi.sigma_s * pi.sigma_s)) : 0.0f;
+    t.saved_plane = (int64_t)pi.height * pi.width;
   }
   if (hipMalloc(&b->d_const, std::max<int64_t>(total, 1) * sizeof(float)) != hipSuccess) {
     delete b;
@@ -342,14 +523,7 @@ int bf_batch_plan(int32_t count, const bf_params* per_image, bf_batch_t** out) {
   for (int i = 0; i < count; ++i) {
     if (b->status[i] < 0) continue;
     hipMemcpy(b->d_const + offs[i], tabs[i].data(), tabs[i].size() * sizeof(float), hipMemcpyHostToDevice);
-    const int N = b->info[i].N;
-    const int64_t stride = ((N + 2 + 63) / 64) * 64;
-    TileParams& t = b->hp[i];
-    t.s_tab = b->d_const + offs[i];
-    t.r_tab = t.s_tab + stride;
-    t.inv_tab = t.s_tab + 2 * stride;
-    t.taps = t.s_tab + 3 * stride;
-    t.taps2 = t.taps;
+    bind_tables(b->hp[i], b->d_const + offs[i], strides[i], ntaps[i]);
   }
   // candidate launch shapes
   for (int v = 0; v < kNumBatchVariants; ++v)
@@ -363,7 +537,7 @@ int bf_batch_plan(int32_t count, const bf_params* per_image, bf_batch_t** out) {
     return fail(BF_EUNSUPPORTED, "a batch image's support W is too large for the batch kernel");
   }
   if (hipMalloc(&b->d_params, count * sizeof(TileParams)) != hipSuccess ||
-      hipMalloc(&b->d_counter, sizeof(int)) != hipSuccess) {
+      hipMalloc(&b->d_counter, 2 * sizeof(int)) != hipSuccess) {
     hipFree(b->d_const);
     delete b;
     return fail(BF_ENOMEM, "hipMalloc batch buffers failed");
@@ -383,6 +557,13 @@ int bf_batch_plan(int32_t count, const bf_params* per_image, bf_batch_t** out) {
   }
   int st = select_shape(b, c);
   if (st < 0) return st;
+  if (b->grad) {
+    st = plan_batch_adjoint(b);
+    if (st < 0) {
+      bf_batch_destroy(b);
+      return st;
+    }
+  }
   *out = b;
   return warn;
 }
@@ -472,10 +653,82 @@ int bf_batch_tune(bf_batch_t* b, const float* const* in, const int64_t* in_pitch
   return BF_OK;
 }
 
+int bf_batch_backward(bf_batch_t* b, const float* const* in, const int64_t* in_pitch,
+                      const float* const* grad_out, const int64_t* gout_pitch, float* const* grad_in,
+                      const int64_t* gin_pitch, double* grad_sigma, void* stream) {
+  if (!b || !in || !in_pitch || !grad_out || !gout_pitch) return fail(BF_EINVAL, "NULL argument");
+  if (!b->grad) return fail(BF_EINVAL, "batch was planned without BF_FLAG_GRAD");
+  if (grad_in && !gin_pitch) return fail(BF_EINVAL, "grad_in without gin_pitch");
+  hipStream_t s = (hipStream_t)stream;
+  if (b->bev_used && hipEventSynchronize(b->bev) != hipSuccess) return fail(BF_EHIP, "hipEventSynchronize");
+  const int n = b->count;
+  const BatchShape& sh = b->cands[b->chosen];
+  for (int i = 0; i < n; ++i) {
+    TileParams f = b->hp[i];  // forward with state
+    TileParams g = b->hp[i];  // adjoint
+    if (b->status[i] >= 0) {
+      const int Wd = b->prm[i].width;
+      if (!in[i] || !grad_out[i]) return fail(BF_EINVAL, "NULL image pointer in batch");
+      if (in_pitch[i] < Wd || gout_pitch[i] < Wd || (grad_in && grad_in[i] && gin_pitch[i] < Wd))
+        return fail(BF_EINVAL, "pitch smaller than width in batch");
+      f.in = g.in = in[i];
+      f.in_pitch = g.in_pitch = in_pitch[i];
+      f.out = nullptr;
+      f.saved = g.saved = b->d_saved + b->saved_off[i];
+      g.gout = grad_out[i];
+      g.gout_pitch = gout_pitch[i];
+      g.out = grad_in ? grad_in[i] : nullptr;
+      g.out_pitch = (grad_in && grad_in[i]) ? gin_pitch[i] : 0;
+      g.TY = b->bTY[i];
+    }
+    b->h_bstage[i] = f;
+    b->h_bstage[n + i] = g;
+  }
+  if (hipMemcpyAsync(b->d_bparams, b->h_bstage, 2 * (size_t)n * sizeof(TileParams), hipMemcpyHostToDevice, s) !=
+      hipSuccess)
+    return fail(BF_EHIP, "hipMemcpyAsync batch adjoint params");
+  hipLaunchKernelGGL(batch_reset_kernel, dim3(1), dim3(64), 0, s, b->d_counter);
+  hipError_t e = launch_batch_v(sh.variant, b->d_bparams, b->d_tiles, b->ntiles, b->d_counter, grid_of(b), sh.lds,
+                                b->acc64, true, s);
+  if (e != hipSuccess) return fail(BF_EHIP, std::string("batch forward-state launch: ") + hipGetErrorString(e));
+  if (b->nbtiles > 0) {
+    const int grid = std::max(1, std::min(2 * b->num_cu, b->nbtiles));
+    e = launch_batch_bwd(b->bvariant, b->d_bparams + n, b->d_btiles, b->nbtiles, b->d_counter + 1,
+                         b->d_bpartials, grid, b->blds, s);
+    if (e != hipSuccess) return fail(BF_EHIP, std::string("batch adjoint launch: ") + hipGetErrorString(e));
+  }
+  if (grad_sigma) {
+    hipLaunchKernelGGL(batch_sigma_reduce_kernel, dim3(n), dim3(kThreads), 0, s, (const double*)b->d_bpartials,
+                       (const BatchRed*)b->d_bred, grad_sigma);
+    e = hipGetLastError();
+    if (e != hipSuccess) return fail(BF_EHIP, std::string("batch sigma reduction: ") + hipGetErrorString(e));
+  }
+  for (int i : b->streamed) {
+    const bf_params& p = b->prm[i];
+    const bool sigs = p.kernel == BF_GAUSS && grad_sigma != nullptr;
+    const bool gauss = p.kernel == BF_GAUSS;
+    // the zero rows of this image's layout must be zero: clear the shared state
+    e = hipMemsetAsync(b->d_bls, 0, (size_t)bls_state_bytes(p.height, p.width, p.W, gauss), s);
+    if (e != hipSuccess) return fail(BF_EHIP, "hipMemsetAsync streamed adjoint state");
+    const BlsState st = bls_layout(b->d_bls, p.height, p.width, p.W, gauss);
+    e = launch_backward_ls(b->h_bstage[n + i], st, sigs, b->d_bls_partials, grad_sigma ? grad_sigma + 2 * i : nullptr, s);
+    if (e != hipSuccess) return fail(BF_EHIP, std::string("batch streamed adjoint: ") + hipGetErrorString(e));
+  }
+  hipEventRecord(b->bev, s);
+  b->bev_used = true;
+  return BF_OK;
+}
+
 int bf_batch_destroy(bf_batch_t* b) {
   if (!b) return BF_OK;
   for (int k = 0; k < 2; ++k)
     if (b->ev_used[k]) hipEventSynchronize(b->ev[k]);
+  if (b->bev_used) hipEventSynchronize(b->bev);
+  if (b->bev) hipEventDestroy(b->bev);
+  if (b->h_bstage) hipHostFree(b->h_bstage);
+  for (void* ptr : {(void*)b->d_btiles, (void*)b->d_bpartials, (void*)b->d_bred, (void*)b->d_saved,
+                    (void*)b->d_bparams, b->d_bls, (void*)b->d_bls_partials})
+    if (ptr) hipFree(ptr);
   destroy_graphs(b);
   for (int k = 0; k < 2; ++k) {
     if (b->ev[k]) hipEventDestroy(b->ev[k]);

@@ -144,6 +144,10 @@ int fail(int code, const std::string& msg);
 // planning helpers (bf_plan.cpp)
 double lambert_w0(double z);
 double poisson_tail(int N, double lam);
+std::vector<double> taps1d(int kind, double sigma_s, int W);
+void gpa_tables(double lam, int N, std::vector<double>& s, std::vector<double>& r, std::vector<double>& inv);
+std::vector<float> const_tables(const bf_params& p, const bf_plan_info& info, int64_t* stride, int64_t* ntapr);
+void bind_tables(TileParams& tp, const float* d, int64_t stride, int64_t ntapr);
 
 }  // namespace bfgpa
 

@@ -111,7 +111,7 @@ static int poisson_order(double lam, double eps) {
 }
 
 // 1-D kernel factor w1(a), a = -W..W, unnormalised.
-static std::vector<double> taps1d(int kind, double sigma_s, int W) {
+std::vector<double> taps1d(int kind, double sigma_s, int W) {
   std::vector<double> t(2 * W + 1);
   for (int a = -W; a <= W; ++a)
     t[a + W] = (kind == BF_BOX) ? 1.0 : std::exp(-(double)a * a / (2.0 * sigma_s * sigma_s));
@@ -185,8 +185,8 @@ static int plan_order(const bf_params* p, bf_plan_info* info) {
 // The kernels keep F~_n = F_n / M_n (|F~_n| <= 1) and the coefficient
 // a_n = e^{-x_i^2/2} x_i^n M_n / n! (|a_n| <= 1); their products equal the
 // terms of eqs. (P), (Q) times e^{-x_i^2/2}, which cancels in P/Q.
-static void gpa_tables(double lam, int N, std::vector<double>& s, std::vector<double>& r,
-                       std::vector<double>& inv) {
+void gpa_tables(double lam, int N, std::vector<double>& s, std::vector<double>& r,
+                std::vector<double>& inv) {
   const double X = std::sqrt(lam);
   auto logM = [&](int n) -> double {
     if (n == 0) return 0.0;
@@ -201,6 +201,38 @@ static void gpa_tables(double lam, int N, std::vector<double>& s, std::vector<do
     s[n] = 1.0 / r[n];
     inv[n] = 1.0 / n;
   }
+}
+
+// Device constant tables of one image, as one float array: s_n, r_n, 1/n
+// (n = 0 .. N+1, rows of *stride floats), then the taps and the d^2 taps
+// (kTapPad zeros on each side, rows of *ntapr floats).
+std::vector<float> const_tables(const bf_params& p, const bf_plan_info& info, int64_t* stride,
+                                int64_t* ntapr) {
+  std::vector<double> s, r, inv;
+  gpa_tables(info.lambda, info.N, s, r, inv);
+  const int N = info.N, W = p.W;
+  *stride = ((N + 2 + 63) / 64) * 64;
+  *ntapr = ((2 * W + 1 + 2 * kTapPad + 63) / 64) * 64;
+  std::vector<float> h(3 * *stride + 2 * *ntapr, 0.0f);
+  for (int n = 0; n <= N + 1; ++n) {
+    h[n] = (float)s[n];
+    h[*stride + n] = (float)r[n];
+    h[2 * *stride + n] = (float)inv[n];
+  }
+  std::vector<double> t = taps1d(p.kernel, p.sigma_s, W);
+  for (int a = -W; a <= W; ++a) {
+    h[3 * *stride + kTapPad + a + W] = (float)t[a + W];
+    h[3 * *stride + *ntapr + kTapPad + a + W] = (float)((double)a * a * t[a + W]);
+  }
+  return h;
+}
+
+void bind_tables(TileParams& tp, const float* d, int64_t stride, int64_t ntapr) {
+  tp.s_tab = d;
+  tp.r_tab = d + stride;
+  tp.inv_tab = d + 2 * stride;
+  tp.taps = d + 3 * stride;
+  tp.taps2 = d + 3 * stride + ntapr;
 }
 
 // Rough per-output cost of a tile shape (VALU instructions per order n),
@@ -375,23 +407,8 @@ int bf_plan(const bf_params* in, bf_plan_t** out) {
   hipGetDevice(&pl->device);
 
   // constant tables: s, r, inv (N+2 each), taps and d^2 taps (padded)
-  std::vector<double> s, r, inv;
-  gpa_tables(info.lambda, info.N, s, r, inv);
-  const int N = info.N, W = p.W;
-  const int64_t stride = ((N + 2 + 63) / 64) * 64;
-  const int64_t ntap = 2 * W + 1 + 2 * kTapPad;
-  const int64_t ntapr = ((ntap + 63) / 64) * 64;
-  std::vector<float> h(3 * stride + 2 * ntapr, 0.0f);
-  for (int n = 0; n <= N + 1; ++n) {
-    h[n] = (float)s[n];
-    h[stride + n] = (float)r[n];
-    h[2 * stride + n] = (float)inv[n];
-  }
-  std::vector<double> t = taps1d(p.kernel, p.sigma_s, W);
-  for (int a = -W; a <= W; ++a) {
-    h[3 * stride + kTapPad + a + W] = (float)t[a + W];
-    h[3 * stride + ntapr + kTapPad + a + W] = (float)((double)a * a * t[a + W]);
-  }
+  int64_t stride = 0, ntapr = 0;
+  std::vector<float> h = const_tables(p, info, &stride, &ntapr);
   pl->tab_stride = stride;
   size_t bytes = h.size() * sizeof(float);
   hipError_t e = hipMalloc(&pl->d_const, bytes);
@@ -460,6 +477,13 @@ int bf_plan(const bf_params* in, bf_plan_t** out) {
   return ost;
 }
 
+int bf_plan_clone_workspace(const bf_plan_t* plan, bf_plan_t** out) {
+  if (!plan || !out) return fail(BF_EINVAL, "NULL argument");
+  *out = nullptr;
+  bf_params p = plan->p;  // normalised parameters: the same N, W and tables
+  return bf_plan(&p, out);
+}
+
 int bf_plan_get_info(const bf_plan_t* plan, bf_plan_info* out) {
   if (!plan || !out) return fail(BF_EINVAL, "NULL argument");
   *out = plan->info;
@@ -497,14 +521,8 @@ static void fill_common(const bf_plan_t* pl, TileParams& tp) {
   tp.inv_T = (float)(1.0 / p.T);
   tp.X = (float)(p.T / p.sigma_r);
   tp.inv_sigma_s3 = p.kernel == BF_GAUSS ? (float)(1.0 / (p.sigma_s * p.sigma_s * p.sigma_s)) : 0.0f;
-  const int64_t st = pl->tab_stride;
-  tp.s_tab = pl->d_const;
-  tp.r_tab = pl->d_const + st;
-  tp.inv_tab = pl->d_const + 2 * st;
-  const int64_t ntap = 2 * p.W + 1 + 2 * kTapPad;
-  const int64_t ntapr = ((ntap + 63) / 64) * 64;
-  tp.taps = pl->d_const + 3 * st;
-  tp.taps2 = pl->d_const + 3 * st + ntapr;
+  const int64_t ntapr = ((2 * p.W + 1 + 2 * kTapPad + 63) / 64) * 64;
+  bind_tables(tp, pl->d_const, pl->tab_stride, ntapr);
   tp.saved_plane = (int64_t)p.height * p.width;
 }
 }  // namespace bfgpa

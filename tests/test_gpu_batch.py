@@ -116,3 +116,75 @@ def test_workload4_batch():
         worst = max(worst, np.abs(got - ref).max())
     print(f"workload-4 sampled max err {worst:.3e}", flush=True)
     assert worst <= TOL
+
+
+# --- batched adjoint ---------------------------------------------------------
+
+def _grad_batch(seed):
+    rng = np.random.default_rng(seed)
+    specs = []
+    kinds = [("box", dict(W=3)), ("gauss", dict(sigma_s=2.5)), ("box", dict(W=30)),   # W = 30: streamed adjoint
+             ("gauss", dict(sigma_s=10.0)), ("gauss", dict(sigma_s=1.2)), ("box", dict(W=9)),
+             ("gauss", dict(sigma_s=4.0))]
+    for b, (kind, kw) in enumerate(kinds):
+        H, Wd = int(rng.integers(20, 130)), int(rng.integers(20, 170))
+        specs.append(dict(kernel=kind, sigma_r=float(rng.uniform(15, 60)), height=H, width=Wd, grad=True, **kw))
+    return specs
+
+
+def test_batch_backward_matches_per_image():
+    torch, P = _mods()
+    specs = _grad_batch(21)
+    batch = P.Batch(specs)
+    assert all(s >= 0 for s in batch.image_status)
+    imgs = [torch.tensor(synthimg.gen2(s["height"], s["width"], 500 + i), dtype=torch.float32, device="cuda")
+            for i, s in enumerate(specs)]
+    for rep in range(2):
+        gouts = [torch.tensor(synthimg.gen1(s["height"], s["width"], 600 + 10 * rep + i) / 255.0 - 0.5,
+                              dtype=torch.float32, device="cuda") for i, s in enumerate(specs)]
+        gins, gs = batch.backward(imgs, gouts)
+        torch.cuda.synchronize()
+        gs = gs.cpu().numpy()
+        for i, s in enumerate(specs):
+            kw = {k: v for k, v in s.items() if k not in ("kernel", "sigma_r", "height", "width")}
+            plan = P.Plan(s["kernel"], s["sigma_r"], s["height"], s["width"], **kw)
+            ref, rs = plan.backward(imgs[i], gouts[i])
+            torch.cuda.synchronize()
+            ref, rs = ref.cpu().numpy().astype(np.float64), rs.cpu().numpy()
+            got = gins[i].cpu().numpy().astype(np.float64)
+            err = np.abs(got - ref).max() / np.abs(ref).max()
+            print(f"rep {rep} image {i} {s['kernel']} W={plan.info.W} N={plan.info.N}: df rel {err:.2e} "
+                  f"dsr {gs[i, 0]:.6e} vs {rs[0]:.6e} dss {gs[i, 1]:.6e} vs {rs[1]:.6e}", flush=True)
+            assert err <= 1e-4, (rep, i)
+            assert abs(gs[i, 0] - rs[0]) <= 1e-4 * abs(rs[0]), (rep, i)
+            if s["kernel"] == "gauss":
+                assert abs(gs[i, 1] - rs[1]) <= 1e-4 * abs(rs[1]), (rep, i)
+            else:
+                assert np.isnan(gs[i, 1])
+
+
+def test_batch_backward_matches_autograd():
+    from oracle import grad as GR
+    torch, P = _mods()
+    specs = [dict(kernel="gauss", sigma_s=2.0, sigma_r=30.0, height=40, width=52, grad=True),
+             dict(kernel="box", W=4, sigma_r=25.0, height=33, width=45, grad=True),
+             dict(kernel="gauss", sigma_s=9.0, sigma_r=40.0, height=50, width=61, grad=True)]  # W = 27
+    batch = P.Batch(specs)
+    imgs = [torch.tensor(synthimg.gen1(s["height"], s["width"], 700 + i), dtype=torch.float32, device="cuda")
+            for i, s in enumerate(specs)]
+    gouts = [torch.tensor(synthimg.gen2(s["height"], s["width"], 800 + i) / 255.0 - 0.5, dtype=torch.float32,
+                          device="cuda") for i, s in enumerate(specs)]
+    gins, gs = batch.backward(imgs, gouts)
+    torch.cuda.synchronize()
+    gs = gs.cpu().numpy()
+    for i, s in enumerate(specs):
+        kind = s["kernel"]
+        W = s["W"] if kind == "box" else P.bf_order("gauss", 30.0, sigma_s=s["sigma_s"]).W
+        df, dsr, dss = GR.vjp_autograd(imgs[i].cpu().numpy().astype(np.float64),
+                                       gouts[i].cpu().numpy().astype(np.float64), kind, s.get("sigma_s"), W,
+                                       s["sigma_r"], batch.N[i], 127.5)
+        got = gins[i].cpu().numpy().astype(np.float64)
+        assert np.abs(got - df).max() <= 1e-3 * np.abs(df).max(), i
+        assert abs(gs[i, 0] - dsr) <= 1e-3 * abs(dsr), i
+        if kind == "gauss":
+            assert abs(gs[i, 1] - dss) <= 1e-3 * abs(dss), i

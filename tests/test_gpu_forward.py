@@ -230,3 +230,24 @@ def test_streamed_saved_state_matches_fused(kind, kw, sr):
     for i, (u, v) in enumerate(zip(sf.view(3, -1), ss.view(3, -1))):
         scale = u.abs().max().item()
         assert (u - v).abs().max().item() <= 1e-4 * scale + 1e-12, i
+
+
+def test_clone_workspace_on_two_streams():
+    # a clone has its own workspace: both plans run at once on two streams
+    torch, P = _mods()
+    f = synthimg.gen2(300, 280, 81)
+    x = torch.tensor(f, dtype=torch.float32, device="cuda")
+    for kind, kw in [("gauss", dict(sigma_s=25.0)), ("box", dict(W=5))]:
+        a = P.Plan(kind, 20.0, 300, 280, **kw)
+        b = a.clone()
+        assert b.info.N == a.info.N and b.info.W == a.info.W and b.info.tile_rows == a.info.tile_rows
+        ref = a.forward(x)
+        torch.cuda.synchronize()
+        s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+        o1, o2 = torch.empty_like(x), torch.empty_like(x)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            a.forward(x, out=o1, stream=s1)
+            b.forward(x, out=o2, stream=s2)
+        torch.cuda.synchronize()
+        assert torch.equal(o1, ref) and torch.equal(o2, ref)
