@@ -38,6 +38,15 @@ __device__ __forceinline__ int xcd_remap(int b, int nblk) {
 
 __device__ __forceinline__ int align4(int n) { return (n + 3) & ~3; }
 
+// Workgroup barrier that orders LDS accesses only: global loads and stores
+// issued before it stay in flight (a full __syncthreads waits for them).
+// For kernels whose waves exchange data through LDS alone.
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 // Sum of p[k * STRIDE] for k in [k0, k1), four loads in flight per step.
 __device__ __forceinline__ float strided_sum(const float* __restrict__ p, int STRIDE, int k0, int k1) {
   float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f;

@@ -113,6 +113,7 @@ int64_t backward_lds_bytes(int TY, int W, bool sigs);
 int max_lds_bytes();
 // large-support path (bf_large.hip)
 bool ls_supported(int W);
+bool ls_box_strip_supported(int W);
 int64_t ls_state_bytes(int H, int Wd, int W, bool save);
 LsState ls_layout(void* base, int H, int Wd, int W, bool save);
 hipError_t launch_forward_ls(const TileParams& p, const LsState& st, bool save, hipStream_t s);

@@ -28,6 +28,19 @@ constexpr int kLsCols = 256;      // output columns per ls_rows workgroup
 constexpr int kLsOpt = 16;        // output rows per thread in ls_cols
 constexpr int kLsColPitch = 80;   // LDS pitch of staged column windows (paired reads conflict-free)
 
+// Compute units of the current device (queried once per process and device).
+static int num_cus() {
+  static int cached[64] = {0};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+  if (cached[dev] == 0) {
+    int n = 0;
+    if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0) n = 256;
+    cached[dev] = n;
+  }
+  return cached[dev];
+}
+
 __global__ __launch_bounds__(kThreads) void ls_init_kernel(TileParams p, LsState st) {
   const int64_t npx = (int64_t)p.H * p.Wd;
   for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < npx;
@@ -476,6 +489,161 @@ __global__ __launch_bounds__(kThreads) void ls_cols_fir_kernel(TileParams p, LsS
   if (c < p.Wd) px.store(st, (int64_t)(tr0 + orow) * p.Wd + c, p.Wd, nr);
 }
 
+// ---------------------------------------------------------------------------
+// Box kernel in column strips.  With C_n(r, c) = sum_{|dr| <= W} F^_n(r + dr, c)
+// (zero outside the image), the box sum is F_bar_n(r, c) = sum_{|dc| <= W}
+// C_n(r, c + dc).  A workgroup owns a strip of OC = 256 - 2W output columns
+// (one strip column per thread, halo included) and a segment of rows.  It
+// keeps C_n for the block's orders in float64 registers and slides them down
+// the segment (add the entering row, subtract the leaving one; each row's
+// F^_n follow from F^_{n0} and y by the power recursion), takes each order's
+// row window as a difference of float64 prefix sums (one wave scan per
+// order), and folds the K values of every output pixel into eqs. (P), (Q).
+// The segment's rows advance the F^ state image as they enter.  Waves share
+// only LDS, so the barriers leave global loads and stores in flight.
+// ---------------------------------------------------------------------------
+// Inclusive prefix sum of a double over the 64 lanes of a wave: row_shr
+// steps inside each 16-lane row, then row_bcast:15 and row_bcast:31 carry the
+// row totals (DPP moves of both 32-bit halves; no LDS traffic).
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ double dpp_d(double v) {
+  const int lo = __double2loint(v), hi = __double2hiint(v);
+  const int l2 = __builtin_amdgcn_update_dpp(0, lo, CTRL, ROW_MASK, 0xF, true);
+  const int h2 = __builtin_amdgcn_update_dpp(0, hi, CTRL, ROW_MASK, 0xF, true);
+  return __hiloint2double(h2, l2);
+}
+__device__ __forceinline__ double wave_scan_incl(double v) {
+  v += dpp_d<0x111, 0xF>(v);  // row_shr:1
+  v += dpp_d<0x112, 0xF>(v);  // row_shr:2
+  v += dpp_d<0x114, 0xF>(v);  // row_shr:4
+  v += dpp_d<0x118, 0xF>(v);  // row_shr:8
+  v += dpp_d<0x142, 0xA>(v);  // row_bcast:15 into rows 1, 3
+  v += dpp_d<0x143, 0xC>(v);  // row_bcast:31 into rows 2, 3
+  return v;
+}
+
+constexpr int kStripThreads = 256;
+constexpr int kStripPitch = 260;  // doubles per order in the prefix buffer (256 columns + total)
+
+__host__ __device__ inline int strip_cols(int W) { return kStripThreads - 2 * W; }
+
+template <bool SAVE>
+__global__ __launch_bounds__(kStripThreads) void ls_box_strip_kernel(TileParams p, LsState st, int n0, int K,
+                                                                     int src, int seg_rows) {
+  extern __shared__ double dlds[];
+  double* Cs = dlds;  // kLsBlock x kStripPitch; order k's window sums then overwrite its row
+  const int W = p.W, L = 2 * W + 1;
+  const int OC = strip_cols(W);
+  const int nstrips = (p.Wd + OC - 1) / OC;
+  const int strip = blockIdx.x % nstrips, seg = blockIdx.x / nstrips;
+  const int c0 = strip * OC;
+  const int r_lo = seg * seg_rows, r_hi = min(r_lo + seg_rows, p.H);
+  const int t = threadIdx.x;
+  const int gc = c0 - W + t;
+  const bool col_ok = gc >= 0 && gc < p.Wd;
+  const bool central = t >= W && t < W + OC && gc < p.Wd;
+  const bool pix = t < OC && c0 + t < p.Wd;  // output column c0 + t
+  const float* Fin = st.F[src];
+  float* Fout = st.F[src ^ 1];
+  const int lane = t & 63, wv = t >> 6;
+  double C[kLsBlock];
+  float in1[kLsBlock];  // 1/(n+1) of the block's orders, read once
+#pragma unroll
+  for (int k = 0; k < kLsBlock; ++k) {
+    C[k] = 0.0;
+    in1[k] = p.inv_tab[n0 + min(k, K - 1) + 1];
+  }
+  // row q of F^_{n0 .. n0+K-1} at this column enters (+) or leaves (-) the window
+  auto load_row = [&](int q, float& f, float& y) {
+    f = 0.f;
+    y = 0.f;
+    if (col_ok && q >= 0 && q < p.H) {
+      const int64_t j = (int64_t)q * st.pitch + gc;
+      f = Fin[j];
+      y = st.Y[j];
+    }
+  };
+  for (int q = r_lo - W; q <= r_lo + W; ++q) {
+    float f, y;
+    load_row(q, f, y);
+#pragma unroll
+    for (int k = 0; k < kLsBlock; ++k)
+      if (k < K) {
+        C[k] += (double)f;
+        f *= y;
+      }
+    if (central && q >= r_lo && q < r_hi) Fout[(int64_t)q * st.pitch + gc] = f;
+  }
+  for (int r = r_lo; r < r_hi; ++r) {
+#pragma unroll
+    for (int k = 0; k < kLsBlock; ++k)
+      if (k < K) Cs[k * kStripPitch + t] = C[k];
+    LsPix<1, SAVE> px;
+    const int64_t pi = (int64_t)r * p.Wd + c0 + t;
+    px.load(st, pi, 0, pix ? 1 : 0);
+    float fe, ye, fl, yl;  // rows entering and leaving after this output row
+    load_row(r + W + 1, fe, ye);
+    load_row(r - W, fl, yl);
+    lds_barrier();
+    // per order: prefix S over the 256 strip columns (float64), then the
+    // window sums S(c + 2W + 1) - S(c) of the OC output columns.  Wave w
+    // takes orders w, w+4, w+8, w+12 (straight-line, so the four scans
+    // interleave; rows past K hold stale values that nobody reads).  Lane l
+    // scans columns 4l .. 4l+3 (DPP across lanes), writes S back in place,
+    // then reads S at columns l + 64i and l + 64i + L (conflict-free).
+#pragma unroll
+    for (int j = 0; j < kLsBlock / 4; ++j) {
+      double* row = Cs + (wv + 4 * j) * kStripPitch;
+      const double2 u = *(const double2*)(row + 4 * lane);
+      const double2 w = *(const double2*)(row + 4 * lane + 2);
+      const double s1 = u.x + u.y, s2 = s1 + w.x, s3 = s2 + w.y;
+      const double incl = wave_scan_incl(s3);
+      const double ex = incl - s3;
+      *(double2*)(row + 4 * lane) = make_double2(ex, ex + u.x);
+      *(double2*)(row + 4 * lane + 2) = make_double2(ex + s1, ex + s2);
+      if (lane == 63) row[256] = incl;
+      float ov[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int c = lane + 64 * i;
+        ov[i] = (float)(row[min(c + L, 256)] - row[c]);
+      }
+      // all of the wave's reads of S precede these writes into the same row
+      float* o = (float*)row;
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+        if (lane + 64 * i < OC) o[lane + 64 * i] = ov[i];
+    }
+    lds_barrier();
+    // this pixel's window sums, then a barrier: the next row's column sums
+    // overwrite the rows they sit in
+    float v[kLsBlock];
+#pragma unroll
+    for (int k = 0; k < kLsBlock; ++k) v[k] = ((const float*)(Cs + k * kStripPitch))[t];
+    lds_barrier();
+    if (pix) {
+#pragma unroll
+      for (int k = 0; k < kLsBlock; ++k)
+        if (k < K) px.fold(0, n0 + k, p.N, v[k], in1[k]);
+      px.store(st, pi, 0, 1);
+    }
+    // slide the window to r + 1
+#pragma unroll
+    for (int k = 0; k < kLsBlock; ++k)
+      if (k < K) {
+        C[k] += (double)fe - (double)fl;
+        fe *= ye;
+        fl *= yl;
+      }
+    const int qe = r + W + 1;
+    if (central && qe >= r_lo && qe < r_hi) Fout[(int64_t)qe * st.pitch + gc] = fe;
+  }
+}
+
+int64_t ls_box_strip_lds_bytes() { return (int64_t)kLsBlock * kStripPitch * 8; }
+
+bool ls_box_strip_supported(int W) { return strip_cols(W) >= 64; }
+
 __global__ __launch_bounds__(kThreads) void ls_final_kernel(TileParams p, LsState st) {
   const int64_t npx = (int64_t)p.H * p.Wd;
   const double X = (double)p.X;
@@ -572,6 +740,23 @@ hipError_t launch_forward_ls(const TileParams& p, const LsState& st, bool save, 
   const int gfir16 = ((p.H + 63) / 64) * tiles_x;
   const size_t fl8 = (size_t)(32 + 2 * p.W) * kLsColPitch * 4;
   const size_t fl16 = (size_t)(64 + 2 * p.W) * kLsColPitch * 4;
+  // box: column strips (running float64 column sums, prefix-sum row windows)
+  const bool box_strip = p.kt == BF_BOX && ls_box_strip_supported(p.W);
+  const int nstrips = box_strip ? (p.Wd + strip_cols(p.W) - 1) / strip_cols(p.W) : 1;
+  // segments: one wave of workgroups (as many as fit on the chip at once, so
+  // none trails); each segment pays a 2W + 1 row warm-up
+  const int slots = num_cus() * (int)std::max<int64_t>(1, max_lds_bytes() / ls_box_strip_lds_bytes());
+  const int nseg = std::max(1, std::min((p.H + 31) / 32, slots / nstrips));
+  const int strip_seg = (p.H + nseg - 1) / nseg;
+  const int gstrip = nstrips * ((p.H + strip_seg - 1) / strip_seg);
+  if (box_strip) {
+    e = hipFuncSetAttribute((const void*)ls_box_strip_kernel<false>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)ls_box_strip_lds_bytes());
+    if (e == hipSuccess)
+      e = hipFuncSetAttribute((const void*)ls_box_strip_kernel<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)ls_box_strip_lds_bytes());
+    if (e != hipSuccess) return e;
+  }
   // Gaussian: FIR passes on the matrix cores where the staged windows fit
   const size_t rlm = (size_t)ls_rows_mfma_lds_bytes(p.W);
   const size_t clm = (size_t)ls_cols_mfma_lds_bytes(p.W);
@@ -601,6 +786,18 @@ hipError_t launch_forward_ls(const TileParams& p, const LsState& st, bool save, 
   int src = 0;
   for (int n0 = 0; n0 <= p.N; n0 += kLsBlock) {
     const int K = std::min(kLsBlock, p.N + 1 - n0);
+    if (box_strip) {
+      if (save)
+        hipLaunchKernelGGL((ls_box_strip_kernel<true>), dim3(gstrip), dim3(kStripThreads), (size_t)ls_box_strip_lds_bytes(),
+                           s, p, st, n0, K, src, strip_seg);
+      else
+        hipLaunchKernelGGL((ls_box_strip_kernel<false>), dim3(gstrip), dim3(kStripThreads), (size_t)ls_box_strip_lds_bytes(),
+                           s, p, st, n0, K, src, strip_seg);
+      e = hipGetLastError();
+      if (e != hipSuccess) return e;
+      src ^= 1;
+      continue;
+    }
     if (rows_mfma)
       hipLaunchKernelGGL(ls_rows_mfma_kernel, dim3(grow), dim3(kThreads), (size_t)rlm, s, p, st, n0, K, src);
     else

@@ -286,10 +286,14 @@ static int choose_forward_tile(int kernel, int W, int H, int Wd, int* variant, i
     }
   }
   if (best < 0) return fail(BF_EUNSUPPORTED, "support W too large for the fused tile kernels");
-  // the streamed path launches two kernels per block of 8 orders: only worth
-  // it when the image is large enough to hide those launches
-  if ((int64_t)H * Wd >= (1 << 20) && bestc > streamed_cost(kernel, W) && ls_supported(W))
-    return fail(BF_EUNSUPPORTED, "streamed path is cheaper at this support");
+  // the streamed path launches kernels per block of 16 orders: only worth it
+  // when the image is large enough to hide those launches.  Box: the column
+  // strips beat the fused tiles from W = 16 on (measured on 4096^2: W = 10
+  // fused 1.7 vs strips 1.9 ps per pixel and order, W = 30 4.4 vs 2.2).
+  if ((int64_t)H * Wd >= (1 << 20) && ls_supported(W)) {
+    if (kernel == BF_BOX ? (W >= 16 && ls_box_strip_supported(W)) : bestc > streamed_cost(kernel, W))
+      return fail(BF_EUNSUPPORTED, "streamed path is cheaper at this support");
+  }
   *variant = best;
   *TY = 4 * forward_variant(best).opt;
   return BF_OK;
