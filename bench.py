@@ -109,6 +109,136 @@ def time_launches(fn, stream, warmup, steps, torch):
     return e0.elapsed_time(e1) / steps  # ms per launch
 
 
+# rocprofv3 runs whose summaries are committed under profiles/ (run from the
+# repository root; DIR is the output folder, then `bench.py --summarize DIR`).
+PROFILE_RUNS = {
+    "trace": "rocprofv3 --kernel-trace --stats --output-format csv -d DIR/trace -o t -- "
+             "python3 bench.py --steps 2 --warmup 1 --no-cpu-baseline --no-extra",
+    "fetch": "rocprofv3 --pmc FETCH_SIZE --output-format csv -d DIR/fetch -o c -- "
+             "python3 bench.py --only 0,6 --steps 1 --warmup 0 --no-cpu-baseline --no-extra",
+    "write": "rocprofv3 --pmc WRITE_SIZE --output-format csv -d DIR/write -o c -- "
+             "python3 bench.py --only 0,6 --steps 1 --warmup 0 --no-cpu-baseline --no-extra",
+    "fetch_copy": "rocprofv3 --pmc FETCH_SIZE --output-format csv -d DIR/fetch_copy -o c -- "
+                  "python3 bench.py --copy-probe 512",
+    "write_copy": "rocprofv3 --pmc WRITE_SIZE --output-format csv -d DIR/write_copy -o c -- "
+                  "python3 bench.py --copy-probe 512",
+}
+COPY_PROBE_MIB = 512
+
+
+def _csv_rows(path):
+    import csv
+    with open(path, newline="") as fh:
+        return list(csv.DictReader(fh))
+
+
+def _short(name):
+    n = name.replace("bfgpa::", "").replace("void ", "")
+    return n.split("(")[0] if "(" in n else n
+
+
+def _calls(dispatches):
+    """Group time-ordered library dispatches into forward calls: one fused
+    launch, or the streamed sequence from ls_init to ls_final."""
+    calls, cur = [], None
+    for d in dispatches:
+        n = _short(d["name"])
+        if n.startswith("__amd_rocclr") or not n.replace("<", " ").split()[0].endswith("kernel"):
+            continue
+        if n.startswith("gpa_forward_kernel"):
+            calls.append([d])
+        elif n.startswith("ls_init_kernel"):
+            cur = [d]
+        elif cur is not None:
+            cur.append(d)
+            if n.startswith("ls_final_kernel"):
+                calls.append(cur)
+                cur = None
+    return calls
+
+
+def summarize(dirpath, sweep_settings):
+    """Write profiles/forward_sweep_4096_kernel_stats.md and profiles/traffic.json
+    from the outputs of PROFILE_RUNS in `dirpath`."""
+    import glob
+    import collections
+    trace = _csv_rows(glob.glob(os.path.join(dirpath, "trace", "*_kernel_trace.csv"))[0])
+    disp = sorted(({"name": r["Kernel_Name"], "t0": int(r["Start_Timestamp"]), "t1": int(r["End_Timestamp"])}
+                   for r in trace), key=lambda d: d["t0"])
+    per_kernel = collections.OrderedDict()
+    for d in disp:
+        per_kernel.setdefault(_short(d["name"]), []).append((d["t1"] - d["t0"]) / 1e3)
+    total = sum(sum(v) for v in per_kernel.values())
+    calls = _calls(disp)
+    per_call = 3  # --warmup 1 --steps 2
+    lines = ["# Kernel time, 4096x4096 forward sweep (18 settings)", "",
+             "Command (from the repository root, DIR = an output folder):", "", "```",
+             PROFILE_RUNS["trace"], "python3 bench.py --summarize DIR", "```", "",
+             f"Each setting runs {per_call} forward calls (1 warm-up + 2 timed). A call is one fused "
+             "`gpa_forward_kernel` launch, or the streamed sequence `ls_init`, per block of 16 orders "
+             "(`ls_rows_mfma` + `ls_cols_mfma` for the Gaussian, `ls_box_strip` for the box), `ls_final`.",
+             "", "| kernel | calls | total ms | avg us | % |", "|---|---|---|---|---|"]
+    for k, v in sorted(per_kernel.items(), key=lambda kv: -sum(kv[1])):
+        lines.append(f"| `{k}` | {len(v)} | {sum(v) / 1e3:.2f} | {sum(v) / len(v):.1f} | "
+                     f"{100 * sum(v) / total:.2f} |")
+    lines += ["", "Per-setting forward-call time (sum of the call's kernel durations, mean of its calls):", "",
+              "| setting | kernels per call | mean ms per call |", "|---|---|---|"]
+    if len(calls) == per_call * len(sweep_settings):
+        for i, s in enumerate(sweep_settings):
+            cs = calls[per_call * i: per_call * (i + 1)]
+            ms = sum(sum(d["t1"] - d["t0"] for d in c) for c in cs) / len(cs) / 1e6
+            lines.append(f"| {s} | {len(cs[0])} | {ms:.3f} |")
+    else:
+        lines.append(f"| (calls found: {len(calls)}, expected {per_call * len(sweep_settings)}) | | |")
+    out_md = os.path.join(ROOT, "profiles", "forward_sweep_4096_kernel_stats.md")
+    with open(out_md, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+
+    def counter_calls(sub):
+        rows = _csv_rows(glob.glob(os.path.join(dirpath, sub, "*_counter_collection.csv"))[0])
+        byd = collections.OrderedDict()
+        for r in rows:
+            byd.setdefault(int(r["Dispatch_Id"]), {"name": r["Kernel_Name"], "t0": int(r["Start_Timestamp"]),
+                                                   "t1": int(r["End_Timestamp"]), "v": 0.0})
+            byd[int(r["Dispatch_Id"])]["v"] += float(r["Counter_Value"])
+        return _calls(sorted(byd.values(), key=lambda d: d["t0"])), byd
+
+    def copy_kib(sub):
+        rows = _csv_rows(glob.glob(os.path.join(dirpath, sub, "*_counter_collection.csv"))[0])
+        return max(float(r["Counter_Value"]) for r in rows if "copyBuffer" in r["Kernel_Name"])
+
+    probe = COPY_PROBE_MIB * (1 << 20)
+    fscale = probe / (copy_kib("fetch_copy") * 1024.0)
+    wscale = probe / (copy_kib("write_copy") * 1024.0)
+    fcalls, _ = counter_calls("fetch")
+    wcalls, _ = counter_calls("write")
+    names = [sweep_settings[0], sweep_settings[6]]
+    settings = {}
+    for s, fc, wc in zip(names, fcalls, wcalls):
+        kern = collections.OrderedDict()
+        for d in fc:
+            e = kern.setdefault(_short(d["name"]), {"dispatches": 0, "fetch_bytes": 0, "write_bytes": 0})
+            e["dispatches"] += 1
+            e["fetch_bytes"] += int(d["v"] * 1024 * fscale)
+        for d in wc:
+            kern.setdefault(_short(d["name"]), {"dispatches": 0, "fetch_bytes": 0, "write_bytes": 0})
+            kern[_short(d["name"])]["write_bytes"] += int(d["v"] * 1024 * wscale)
+        fb = sum(e["fetch_bytes"] for e in kern.values())
+        wb = sum(e["write_bytes"] for e in kern.values())
+        settings[s] = {"bytes_per_call": fb + wb, "fetch_bytes": fb, "write_bytes": wb,
+                       "alg_bytes": 8 * 4096 * 4096, "kernels": kern}
+    doc = {"source_sha": source_sha(), "image": "4096x4096 float32 gen2 seed 3000",
+           "fetch_scale": fscale, "write_scale": wscale,
+           "calibration": f"plain {COPY_PROBE_MIB} MiB device copy (bench.py --copy-probe {COPY_PROBE_MIB}): "
+                          f"FETCH_SIZE read {probe / fscale / 2**20:.0f} MiB, WRITE_SIZE {probe / wscale / 2**20:.0f} MiB",
+           "commands": [PROFILE_RUNS[k] for k in ("fetch", "write", "fetch_copy", "write_copy")]
+           + ["python3 bench.py --summarize DIR"],
+           "settings": settings}
+    with open(os.path.join(ROOT, "profiles", "traffic.json"), "w") as fh:
+        json.dump(doc, fh, indent=1)
+    print(f"wrote {out_md} and profiles/traffic.json")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -119,7 +249,12 @@ def main():
     ap.add_argument("--only", default="", help="comma list of sweep indices to run")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (counter calibration)")
+    ap.add_argument("--summarize", default="", metavar="DIR",
+                    help="write profiles/ summaries from the rocprofv3 outputs of PROFILE_RUNS in DIR")
     a = ap.parse_args()
+    if a.summarize:
+        summarize(a.summarize, [setting_name(k, kw, sr) for k, kw, sr in SWEEP])
+        return
     if a.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
