@@ -506,17 +506,24 @@ __global__ __launch_bounds__(kThreads) void ls_cols_fir_kernel(TileParams p, LsS
 // steps inside each 16-lane row, then row_bcast:15 and row_bcast:31 carry the
 // row totals (DPP moves of both 32-bit halves; no LDS traffic).
 template <int CTRL, int ROW_MASK>
-__device__ __forceinline__ double dpp_d(double v) {
+__device__ __forceinline__ double dpp_d(double v) {  // lanes of disabled rows read 0
   const int lo = __double2loint(v), hi = __double2hiint(v);
   const int l2 = __builtin_amdgcn_update_dpp(0, lo, CTRL, ROW_MASK, 0xF, true);
   const int h2 = __builtin_amdgcn_update_dpp(0, hi, CTRL, ROW_MASK, 0xF, true);
   return __hiloint2double(h2, l2);
 }
+template <int CTRL>
+__device__ __forceinline__ double dpp_shr(double v) {  // all rows; lanes shifted in from outside the row read 0
+  const int lo = __double2loint(v), hi = __double2hiint(v);
+  const int l2 = __builtin_amdgcn_mov_dpp(lo, CTRL, 0xF, 0xF, true);
+  const int h2 = __builtin_amdgcn_mov_dpp(hi, CTRL, 0xF, 0xF, true);
+  return __hiloint2double(h2, l2);
+}
 __device__ __forceinline__ double wave_scan_incl(double v) {
-  v += dpp_d<0x111, 0xF>(v);  // row_shr:1
-  v += dpp_d<0x112, 0xF>(v);  // row_shr:2
-  v += dpp_d<0x114, 0xF>(v);  // row_shr:4
-  v += dpp_d<0x118, 0xF>(v);  // row_shr:8
+  v += dpp_shr<0x111>(v);     // row_shr:1
+  v += dpp_shr<0x112>(v);     // row_shr:2
+  v += dpp_shr<0x114>(v);     // row_shr:4
+  v += dpp_shr<0x118>(v);     // row_shr:8
   v += dpp_d<0x142, 0xA>(v);  // row_bcast:15 into rows 1, 3
   v += dpp_d<0x143, 0xC>(v);  // row_bcast:31 into rows 2, 3
   return v;
@@ -542,10 +549,11 @@ __global__ __launch_bounds__(kStripThreads) void ls_box_strip_kernel(TileParams 
   const int gc = c0 - W + t;
   const bool col_ok = gc >= 0 && gc < p.Wd;
   const bool central = t >= W && t < W + OC && gc < p.Wd;
-  const bool pix = t < OC && c0 + t < p.Wd;  // output column c0 + t
+  const int lane = t & 63, wv = t >> 6;
+  const int oc = t;  // output column c0 + oc (idle lanes cost nothing once a wave has none)
+  const bool pix = oc < OC && c0 + oc < p.Wd;
   const float* Fin = st.F[src];
   float* Fout = st.F[src ^ 1];
-  const int lane = t & 63, wv = t >> 6;
   double C[kLsBlock];
   float in1[kLsBlock];  // 1/(n+1) of the block's orders, read once
 #pragma unroll
@@ -579,7 +587,7 @@ __global__ __launch_bounds__(kStripThreads) void ls_box_strip_kernel(TileParams 
     for (int k = 0; k < kLsBlock; ++k)
       if (k < K) Cs[k * kStripPitch + t] = C[k];
     LsPix<1, SAVE> px;
-    const int64_t pi = (int64_t)r * p.Wd + c0 + t;
+    const int64_t pi = (int64_t)r * p.Wd + c0 + oc;
     px.load(st, pi, 0, pix ? 1 : 0);
     float fe, ye, fl, yl;  // rows entering and leaving after this output row
     load_row(r + W + 1, fe, ye);
@@ -619,7 +627,7 @@ __global__ __launch_bounds__(kStripThreads) void ls_box_strip_kernel(TileParams 
     // overwrite the rows they sit in
     float v[kLsBlock];
 #pragma unroll
-    for (int k = 0; k < kLsBlock; ++k) v[k] = ((const float*)(Cs + k * kStripPitch))[t];
+    for (int k = 0; k < kLsBlock; ++k) v[k] = ((const float*)(Cs + k * kStripPitch))[oc];
     lds_barrier();
     if (pix) {
 #pragma unroll
