@@ -68,6 +68,8 @@ extern "C" {
 #define BF_FLAG_STREAMED     4  /* run the orders in blocks through device memory (the
                                    path taken automatically when W is too wide for the
                                    fused on-chip tiles); allocates about 64 bytes per pixel */
+#define BF_FLAG_JOINT        8  /* cross (joint) filter: the range kernel acts on a guide
+                                   image (bf_forward_joint); fused tiles only, no adjoint */
 
 typedef struct bf_params {
   int32_t kernel;    /* BF_BOX or BF_GAUSS */
@@ -139,6 +141,20 @@ int bf_plan_clone_workspace(const bf_plan_t* plan, bf_plan_t** out);
  * launch fails. */
 int bf_forward(const bf_plan_t* plan, const float* in, int64_t in_pitch,
                float* out, int64_t out_pitch, float* saved, void* stream);
+
+/* Cross (joint) bilateral filter, the extension named in Sec. 1 and Sec. 5:
+ * out(i) = sum_j w(j) g(h(i-j) - h(i)) f(i-j) / sum_j w(j) g(h(i-j) - h(i)),
+ * with the range kernel g replaced by phi_N on the centred guide h (T, center
+ * and N refer to the guide's range).  The plan must have been built with
+ * BF_FLAG_JOINT; it runs in one fused launch with two spatial filterings per
+ * order (F_n of the guide, and F_n f), N orders.
+ *   in      device, height x width float32 (f), pitch in_pitch
+ *   guide   device, height x width float32 (h), pitch guide_pitch
+ *   out     device, height x width float32, pitch out_pitch; aliases neither
+ * Errors: BF_EINVAL for NULL pointers, pitches < width, aliasing, or a plan
+ * without BF_FLAG_JOINT; BF_EHIP if the launch fails. */
+int bf_forward_joint(const bf_plan_t* plan, const float* in, int64_t in_pitch, const float* guide,
+                     int64_t guide_pitch, float* out, int64_t out_pitch, void* stream);
 
 /* Vector-Jacobian product of the forward filter (an extension: the paper
  * does not differentiate the filter).  With gbar = dL/d(out):

@@ -30,6 +30,7 @@ BF_NRULE_POISSON = 2
 BF_FLAG_FP32_ACCUM = 1
 BF_FLAG_GRAD = 2
 BF_FLAG_STREAMED = 4
+BF_FLAG_JOINT = 8
 
 
 class bf_params(C.Structure):
@@ -73,6 +74,8 @@ SIGNATURES = {
     "bf_plan_clone_workspace": (C.c_int, [C.c_void_p, C.POINTER(C.c_void_p)]),
     "bf_forward": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_int64, C.c_void_p,
                              C.c_void_p]),
+    "bf_forward_joint": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_int64, C.c_void_p,
+                                   C.c_int64, C.c_void_p]),
     "bf_backward": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_int64, C.c_void_p,
                               C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p]),
     "bf_batch_plan": (C.c_int, [C.c_int32, C.POINTER(bf_params), C.POINTER(C.c_void_p)]),

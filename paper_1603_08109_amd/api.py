@@ -37,7 +37,8 @@ class PlanInfo:
 def make_params(kernel: str, sigma_r: float, *, sigma_s: float | None = None, W: int = 0,
                 T: float = 127.5, center: float | None = None, N: int = 0, delta: float = 1e-3,
                 n_rule: str = "lambertw", height: int = 0, width: int = 0,
-                fp32_accum: bool = False, grad: bool = False, streamed: bool = False) -> L.bf_params:
+                fp32_accum: bool = False, grad: bool = False, streamed: bool = False,
+                joint: bool = False) -> L.bf_params:
     p = L.bf_params()
     p.kernel = _KERNELS[kernel]
     p.sigma_s = float(sigma_s) if sigma_s is not None else 0.0
@@ -51,7 +52,7 @@ def make_params(kernel: str, sigma_r: float, *, sigma_s: float | None = None, W:
     p.height = int(height)
     p.width = int(width)
     p.flags = ((L.BF_FLAG_FP32_ACCUM if fp32_accum else 0) | (L.BF_FLAG_GRAD if grad else 0)
-               | (L.BF_FLAG_STREAMED if streamed else 0))
+               | (L.BF_FLAG_STREAMED if streamed else 0) | (L.BF_FLAG_JOINT if joint else 0))
     return p
 
 
@@ -133,6 +134,20 @@ class Plan:
         L.check(self._lib.bf_forward(self._h, C.c_void_p(inp.data_ptr()), inp.stride(0),
                                      C.c_void_p(out.data_ptr()), out.stride(0), sp,
                                      _stream_handle(stream)), "bf_forward")
+        return out
+
+    def forward_joint(self, inp: torch.Tensor, guide: torch.Tensor, out: torch.Tensor | None = None,
+                      stream=None) -> torch.Tensor:
+        """Cross (joint) filter of `inp` with the range kernel on `guide` (plan built with joint=True)."""
+        _check_image(inp, self.height, self.width, "input")
+        _check_image(guide, self.height, self.width, "guide")
+        if out is None:
+            out = torch.empty_like(inp)
+        _check_image(out, self.height, self.width, "output")
+        L.check(self._lib.bf_forward_joint(self._h, C.c_void_p(inp.data_ptr()), inp.stride(0),
+                                           C.c_void_p(guide.data_ptr()), guide.stride(0),
+                                           C.c_void_p(out.data_ptr()), out.stride(0), _stream_handle(stream)),
+                "bf_forward_joint")
         return out
 
     def backward(self, inp: torch.Tensor, grad_out: torch.Tensor, saved: torch.Tensor | None = None,

@@ -383,6 +383,108 @@ __device__ __forceinline__ void forward_tile(const TileParams& p, int r0, int c0
 }
 
 // ---------------------------------------------------------------------------
+// Cross (joint) filter, one 64 x 4*OPT tile: the range kernel acts on the
+// guide h, the averaged values come from f (named as an extension in Sec. 1
+// and Sec. 5).  With F^_n = e^{-x^2/2} y^n from the guide and a_n as in
+// forward_tile (guide value at the output pixel),
+//   Q = sum_{n<N} a_n (w * F^_n),  P = sum_{n<N} a_n (w * (F^_n f)),
+//   out = P / Q:
+// N orders, two filterings each (no order shift, the numerator is f).
+// ---------------------------------------------------------------------------
+template <int KT, int OPT, int MREG>
+__device__ __forceinline__ void joint_tile(const TileParams& p, int r0, int c0, float* lds) {
+  const int W = p.W;
+  const int N = p.N;
+  const RegionGeom g = region_geom(4 * OPT, W);
+  const int np4 = align4(g.npx);
+  float* Fs = lds;                  // F^_n
+  float* Gs = lds + np4;            // F^_n f
+  float* Hs = Gs + np4;             // row pass of F^_n
+  float* Hg = Hs + g.RH * kHPitch;  // row pass of F^_n f
+  const float* tz = p.taps + kTapPad;
+
+  float Fr[MREG], yr[MREG], fr[MREG];
+  for_region<MREG>(g, r0, c0, W, p.H, p.Wd, [&](int m, int q, bool inside, int gr, int gc) {
+    const int cr = min(max(gr, 0), p.H - 1), cc = min(max(gc, 0), p.Wd - 1);
+    Fr[m] = p.guide[(int64_t)cr * p.guide_pitch + cc];
+    fr[m] = p.in[(int64_t)cr * p.in_pitch + cc];
+    yr[m] = inside ? 1.f : 0.f;
+  });
+#pragma unroll
+  for (int m = 0; m < MREG; ++m) {
+    const float h = Fr[m];
+    const bool inside = yr[m] != 0.f;
+    const float x = (h - p.center) / p.sigma_r;
+    yr[m] = inside ? (h - p.center) * p.inv_T : 0.f;
+    Fr[m] = inside ? expf(-0.5f * x * x) : 0.f;
+    fr[m] = inside ? fr[m] : 0.f;
+    const int q = threadIdx.x + kThreads * m;
+    if (q < g.npx) {
+      Fs[q] = Fr[m];
+      Gs[q] = Fr[m] * fr[m];
+    }
+  }
+
+  const int lane = threadIdx.x & 63;
+  const int orow0 = (threadIdx.x >> 6) * OPT;
+  const int gc = c0 + lane;
+  const int gcc = min(gc, p.Wd - 1);
+  float z[OPT], a[OPT];
+  Accum<true> P[OPT], Q[OPT];
+#pragma unroll
+  for (int s = 0; s < OPT; ++s) {
+    const float h = p.guide[(int64_t)min(r0 + orow0 + s, p.H - 1) * p.guide_pitch + gcc];
+    const float x = (h - p.center) / p.sigma_r;  // pixels past the image: harmless, never stored
+    z[s] = x * p.X;
+    a[s] = expf(-0.5f * x * x);
+    P[s].zero();
+    Q[s].zero();
+  }
+  __syncthreads();
+
+  for (int n = 0; n < N; ++n) {
+    rowpass<KT>(Fs, g.RWp, Hs, g.RH, W, tz);
+    rowpass<KT>(Gs, g.RWp, Hg, g.RH, W, tz);
+    __syncthreads();
+    if (n + 1 < N) {
+#pragma unroll
+      for (int m = 0; m < MREG; ++m) {
+        Fr[m] *= yr[m];
+        const int q = threadIdx.x + kThreads * m;
+        if (q < g.npx) {
+          Fs[q] = Fr[m];
+          Gs[q] = Fr[m] * fr[m];
+        }
+      }
+    }
+    float v[OPT], u[OPT];
+    colpass<KT, OPT>(Hs, orow0, lane, W, tz, v);
+    colpass<KT, OPT>(Hg, orow0, lane, W, tz, u);
+    const float in1 = p.inv_tab[n + 1];
+#pragma unroll
+    for (int s = 0; s < OPT; ++s) {
+      Q[s].add(a[s], v[s]);
+      P[s].add(a[s], u[s]);
+      a[s] *= z[s] * in1;
+    }
+    if ((n & 7) == 7) {
+#pragma unroll
+      for (int s = 0; s < OPT; ++s) {
+        P[s].fold();
+        Q[s].fold();
+      }
+    }
+    __syncthreads();
+  }
+
+#pragma unroll
+  for (int s = 0; s < OPT; ++s) {
+    const int gr = r0 + orow0 + s;
+    if (gr < p.H && gc < p.Wd) p.out[(int64_t)gr * p.out_pitch + gc] = (float)(P[s].value() / Q[s].value());
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Adjoint.  With gbar = dL/dout, p_i = gbar sigma_r / Q~_i and
 // rho_i = P~_i / Q~_i (saved by the forward), the scaled adjoint image of
 // F~_m is  adj_m(i) = p_i (b_m(i) [m >= 1] - rho_i a_m(i) [m <= N-1])

@@ -50,6 +50,8 @@ struct TileParams {
   const float* inv_tab; // 1/n, n = 0..N+1 (inv_0 = 0)
   const float* taps;    // kTapPad zeros, 2W+1 taps, kTapPad zeros
   const float* taps2;   // same layout, d^2 * tap (Gaussian sigma_s gradient)
+  const float* guide;   // cross filter: the image the range kernel acts on (else null)
+  int64_t guide_pitch;
 };
 
 // Large-support path: orders per block and its device state.
@@ -104,6 +106,10 @@ hipError_t launch_forward(const TileParams& p, int variant, bool acc64, bool sav
                           hipStream_t s);
 hipError_t launch_backward(const TileParams& p, int variant, bool sigs, double* partials,
                            double* grad_sigma, hipStream_t s);
+hipError_t launch_joint(const TileParams& p, int variant, hipStream_t s);
+int joint_variant_count();
+Variant joint_variant(int v);
+int64_t joint_lds_bytes(int TY, int W);
 int forward_variant_count();
 Variant forward_variant(int v);
 int backward_variant_count();

@@ -87,6 +87,58 @@ hipError_t launch_forward(const TileParams& p, int variant, bool acc64, bool sav
 }
 
 // ---------------------------------------------------------------------------
+// Cross (joint) filter: fused tiles only (joint_tile, bf_device.h).
+// ---------------------------------------------------------------------------
+template <int KT, int OPT, int MREG>
+__global__ __launch_bounds__(kThreads) void gpa_joint_kernel(TileParams p) {
+  extern __shared__ float lds[];
+  const int tile = xcd_remap(blockIdx.x, gridDim.x);
+  const int ty = tile / p.tiles_x;
+  const int tx = tile - ty * p.tiles_x;
+  joint_tile<KT, OPT, MREG>(p, ty * 4 * OPT, tx * kTileCols, lds);
+}
+
+// three region arrays per thread (F^, y, f): the smaller register budgets only
+static const Variant kJointVariants[] = {{8, 12}, {8, 20}, {8, 32}, {4, 32}};
+int joint_variant_count() { return 4; }
+Variant joint_variant(int v) { return kJointVariants[v]; }
+
+int64_t joint_lds_bytes(int TY, int W) {
+  const int64_t npx = region_floats(TY, W);
+  return 4 * (2 * ((npx + 3) & ~3LL) + 2 * (int64_t)(TY + 2 * W) * kHPitch);
+}
+
+template <int KT, int OPT, int MREG>
+static hipError_t launch_joint_t(const TileParams& p, hipStream_t s) {
+  auto kern = gpa_joint_kernel<KT, OPT, MREG>;
+  hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, max_lds_bytes());
+  if (e != hipSuccess) return e;
+  const int tiles = ((p.H + 4 * OPT - 1) / (4 * OPT)) * p.tiles_x;
+  hipLaunchKernelGGL(kern, dim3(tiles), dim3(kThreads), (size_t)joint_lds_bytes(4 * OPT, p.W), s, p);
+  return hipGetLastError();
+}
+
+template <int KT>
+static hipError_t launch_joint_k(const TileParams& p, int variant, hipStream_t s) {
+  switch (variant) {
+    case 0: return launch_joint_t<KT, 8, 12>(p, s);
+    case 1: return launch_joint_t<KT, 8, 20>(p, s);
+    case 2: return launch_joint_t<KT, 8, 32>(p, s);
+    default: return launch_joint_t<KT, 4, 32>(p, s);
+  }
+}
+
+hipError_t launch_joint(const TileParams& p, int variant, hipStream_t s) {
+  if (variant < 0 || variant >= joint_variant_count() || !p.guide) return hipErrorInvalidValue;
+  const Variant v = joint_variant(variant);
+  if (p.TY != 4 * v.opt) return hipErrorInvalidValue;
+  if (region_floats(p.TY, p.W) > (int64_t)kThreads * v.mreg) return hipErrorInvalidValue;
+  if (joint_lds_bytes(p.TY, p.W) > max_lds_bytes()) return hipErrorInvalidValue;
+  if (p.H <= 0 || p.Wd <= 0) return hipSuccess;
+  return p.kt == BF_BOX ? launch_joint_k<BF_BOX>(p, variant, s) : launch_joint_k<BF_GAUSS>(p, variant, s);
+}
+
+// ---------------------------------------------------------------------------
 // Adjoint kernels (the per-tile arithmetic, backward_tile, is in bf_device.h).
 // ---------------------------------------------------------------------------
 template <int KT, int OPT, int MREG, bool SIGS>

@@ -299,6 +299,29 @@ static int choose_forward_tile(int kernel, int W, int H, int Wd, int* variant, i
   return BF_OK;
 }
 
+// Cross filter: the fused tile variants with room for two region images.
+static int choose_joint_tile(int kernel, int W, int H, int Wd, int* variant, int* TY) {
+  int best = -1;
+  double bestc = 0.0;
+  for (int v = 0; v < joint_variant_count(); ++v) {
+    const Variant vv = joint_variant(v);
+    const int ty = 4 * vv.opt;
+    if (region_floats(ty, W) > (int64_t)kThreads * vv.mreg) continue;
+    if (joint_lds_bytes(ty, W) > max_lds_bytes()) continue;
+    double c = tile_cost(kernel, W, vv.opt, vv.mreg);
+    const int64_t tiles = (int64_t)((H + ty - 1) / ty) * ((Wd + kTileCols - 1) / kTileCols);
+    if (tiles < 256) c *= 1.0 + (256.0 - tiles) / 256.0;
+    if (best < 0 || c < bestc) {
+      best = v;
+      bestc = c;
+    }
+  }
+  if (best < 0) return fail(BF_EUNSUPPORTED, "support W too large for the cross-filter tiles");
+  *variant = best;
+  *TY = 4 * joint_variant(best).opt;
+  return BF_OK;
+}
+
 static int choose_backward_tile(int W, bool sigs, int* variant, int* TY) {
   const int nv = backward_variant_count();
   for (int v = 0; v < nv; ++v) {
@@ -370,8 +393,15 @@ int bf_plan(const bf_params* in, bf_plan_t** out) {
   if (ost < 0) return ost;
   int variant = 0, TY = 0;
   bool ls = false;
-  st = (p.flags & BF_FLAG_STREAMED) ? BF_EUNSUPPORTED
+  if (p.flags & BF_FLAG_JOINT) {
+    if (p.flags & (BF_FLAG_GRAD | BF_FLAG_STREAMED))
+      return fail(BF_EUNSUPPORTED, "the cross filter has no adjoint or streamed path");
+    st = choose_joint_tile(p.kernel, p.W, p.height, p.width, &variant, &TY);
+    if (st < 0) return st;
+  } else {
+    st = (p.flags & BF_FLAG_STREAMED) ? BF_EUNSUPPORTED
                                       : choose_forward_tile(p.kernel, p.W, p.height, p.width, &variant, &TY);
+  }
   if (st < 0) {
     if (!ls_supported(p.W)) return fail(BF_EUNSUPPORTED, "support W too large");
     ls = true;  // large-support path through device memory
@@ -538,6 +568,7 @@ int bf_forward(const bf_plan_t* pl, const float* in, int64_t in_pitch, float* ou
   if (!pl || !in || !out) return fail(BF_EINVAL, "NULL plan or image pointer");
   if (in_pitch < pl->p.width || out_pitch < pl->p.width) return fail(BF_EINVAL, "pitch smaller than width");
   if ((const void*)in == (const void*)out) return fail(BF_EINVAL, "in and out must not alias");
+  if (pl->p.flags & BF_FLAG_JOINT) return fail(BF_EINVAL, "a cross-filter plan runs with bf_forward_joint");
   TileParams tp;
   std::memset(&tp, 0, sizeof(tp));
   fill_common(pl, tp);
@@ -558,6 +589,30 @@ int bf_forward(const bf_plan_t* pl, const float* in, int64_t in_pitch, float* ou
     e = launch_forward(tp, pl->variant, acc64, saved != nullptr, (hipStream_t)stream);
   }
   if (e != hipSuccess) return hip_fail(e, "forward launch");
+  return BF_OK;
+}
+
+int bf_forward_joint(const bf_plan_t* pl, const float* in, int64_t in_pitch, const float* guide,
+                     int64_t guide_pitch, float* out, int64_t out_pitch, void* stream) {
+  if (!pl || !in || !guide || !out) return fail(BF_EINVAL, "NULL plan or image pointer");
+  if (!(pl->p.flags & BF_FLAG_JOINT)) return fail(BF_EINVAL, "plan was built without BF_FLAG_JOINT");
+  if (in_pitch < pl->p.width || guide_pitch < pl->p.width || out_pitch < pl->p.width)
+    return fail(BF_EINVAL, "pitch smaller than width");
+  if ((const void*)in == (const void*)out || (const void*)guide == (const void*)out)
+    return fail(BF_EINVAL, "out must not alias in or guide");
+  TileParams tp;
+  std::memset(&tp, 0, sizeof(tp));
+  fill_common(pl, tp);
+  tp.in = in;
+  tp.in_pitch = in_pitch;
+  tp.guide = guide;
+  tp.guide_pitch = guide_pitch;
+  tp.out = out;
+  tp.out_pitch = out_pitch;
+  tp.TY = pl->TY;
+  tp.tiles_x = (pl->p.width + kTileCols - 1) / kTileCols;
+  hipError_t e = launch_joint(tp, pl->variant, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "cross-filter launch");
   return BF_OK;
 }
 
