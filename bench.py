@@ -389,6 +389,19 @@ def main():
         print(f"# batch {extra['batch']}", file=sys.stderr, flush=True)
         del bimgs, bouts, batch, plans4
 
+        # cross (joint) filter on the sweep image with a second synthetic image as guide
+        guide = torch.tensor(synthimg.gen1(H, Wd, 3100), dtype=torch.float32, device=dev)
+        jl = {}
+        for kind, kw, sr in [("gauss", dict(sigma_s=3.0), 30.0), ("box", dict(W=10), 30.0)]:
+            jp = P.Plan(kind, sr, H, Wd, joint=True, **kw)
+            ms_j = time_launches(lambda: jp.forward_joint(x, guide, out=out), stream, a.warmup, a.steps, torch)
+            jl[setting_name(kind, kw, sr)] = {"N": jp.info.N, "ms": round(ms_j, 4),
+                                              "mpix_s": round(H * Wd / ms_j / 1e3, 1)}
+        extra["joint"] = {"workload": "4096x4096 gen2 filtered with a gen1 guide (range kernel on the guide)",
+                          "per_setting": jl}
+        print(f"# joint {extra['joint']}", file=sys.stderr, flush=True)
+        del guide
+
     cpu = None
     if not a.no_cpu_baseline:
         from oracle import gpa as G
