@@ -156,6 +156,19 @@ int bf_forward(const bf_plan_t* plan, const float* in, int64_t in_pitch,
 int bf_forward_joint(const bf_plan_t* plan, const float* in, int64_t in_pitch, const float* guide,
                      int64_t guide_pitch, float* out, int64_t out_pitch, void* stream);
 
+/* Data range of an image, for planning with the centre and half-range taken
+ * from the data (data-driven range): writes {min, max} of the
+ * height x width float32 image `in` (device, row pitch `pitch`) to the DEVICE
+ * array minmax[2], skipping NaNs ({+inf, -inf} if there is no number).  Plan
+ * with center = (min + max)/2 and T = (max - min)/2: every |f - center| <= T,
+ * so the accuracy guarantee of Prop. (accuracy) still holds, and a range
+ * narrower than [0, 255] lowers lambda = T^2/sigma_r^2 and with it N (and
+ * admits a smaller sigma_r in float32).  Two kernel launches on `stream`, no
+ * allocation.  Errors: BF_EINVAL for NULL pointers, sizes < 0 or a pitch <
+ * width; BF_EHIP if a launch fails. */
+int bf_image_range(const float* in, int64_t pitch, int32_t height, int32_t width, float* minmax,
+                   void* stream);
+
 /* Vector-Jacobian product of the forward filter (an extension: the paper
  * does not differentiate the filter).  With gbar = dL/d(out):
  *   grad_in     NULL or device float32 image (pitch gin_pitch): dL/d(in)

@@ -76,6 +76,7 @@ SIGNATURES = {
                              C.c_void_p]),
     "bf_forward_joint": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_int64, C.c_void_p,
                                    C.c_int64, C.c_void_p]),
+    "bf_image_range": (C.c_int, [C.c_void_p, C.c_int64, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p]),
     "bf_backward": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_int64, C.c_void_p,
                               C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p]),
     "bf_batch_plan": (C.c_int, [C.c_int32, C.POINTER(bf_params), C.POINTER(C.c_void_p)]),

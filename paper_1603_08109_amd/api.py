@@ -255,5 +255,24 @@ class Batch:
         return ch.value
 
 
+def image_range(img: torch.Tensor, stream=None) -> torch.Tensor:
+    """Device float32 tensor [min, max] of a 2-D float32 image (bf_image_range)."""
+    if not isinstance(img, torch.Tensor) or img.device.type != "cuda" or img.dtype != torch.float32:
+        raise TypeError("image must be a float32 CUDA (HIP) tensor")
+    if img.dim() != 2 or img.stride(1) != 1:
+        raise ValueError("image must be 2-D with contiguous rows")
+    mm = torch.empty(2, dtype=torch.float32, device=img.device)
+    lib = L.load()
+    L.check(lib.bf_image_range(C.c_void_p(img.data_ptr()), img.stride(0), img.shape[0], img.shape[1],
+                               C.c_void_p(mm.data_ptr()), _stream_handle(stream)), "bf_image_range")
+    return mm
+
+
+def range_params(vmin: float, vmax: float) -> dict:
+    """center and T for a plan from a data range (keeps |f - center| <= T)."""
+    T = max(0.5 * (float(vmax) - float(vmin)), 1e-6)
+    return {"center": 0.5 * (float(vmax) + float(vmin)), "T": T}
+
+
 def version() -> str:
     return L.load().bf_version().decode()

@@ -107,6 +107,7 @@ hipError_t launch_forward(const TileParams& p, int variant, bool acc64, bool sav
 hipError_t launch_backward(const TileParams& p, int variant, bool sigs, double* partials,
                            double* grad_sigma, hipStream_t s);
 hipError_t launch_joint(const TileParams& p, int variant, hipStream_t s);
+hipError_t launch_range(const float* in, int64_t pitch, int H, int Wd, float* mm, hipStream_t s);
 int joint_variant_count();
 Variant joint_variant(int v);
 int64_t joint_lds_bytes(int TY, int W);

@@ -1,6 +1,8 @@
 // Single-image kernels: fused forward (Algorithm 2) and its adjoint.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include <cmath>
 #include <cstdint>
 
@@ -84,6 +86,75 @@ hipError_t launch_forward(const TileParams& p, int variant, bool acc64, bool sav
   if (p.H <= 0 || p.Wd <= 0) return hipSuccess;
   return p.kt == BF_BOX ? launch_fwd_k<BF_BOX>(p, variant, acc64, save, s)
                         : launch_fwd_k<BF_GAUSS>(p, variant, acc64, save, s);
+}
+
+// ---------------------------------------------------------------------------
+// Data range of an image (min and max), for planning with T and c taken from
+// the data: with c = (min + max)/2 and T = (max - min)/2 every |f - c| <= T,
+// so Prop. (accuracy) still holds, and a narrower range lowers lambda and N.
+// NaNs are skipped.  Two launches: the output pair is set to (+inf, -inf),
+// then every workgroup folds its share in with compare-and-swap loops.
+// ---------------------------------------------------------------------------
+__global__ void range_init_kernel(float* mm) {
+  if (threadIdx.x == 0) {
+    mm[0] = __builtin_huge_valf();
+    mm[1] = -__builtin_huge_valf();
+  }
+}
+
+__device__ __forceinline__ void atomic_fmin(float* a, float v) {
+  int* ai = (int*)a;
+  int old = __float_as_int(*(volatile float*)a);
+  while (v < __int_as_float(old)) {
+    const int assumed = old;
+    old = atomicCAS(ai, assumed, __float_as_int(v));
+    if (old == assumed) break;
+  }
+}
+
+__device__ __forceinline__ void atomic_fmax(float* a, float v) {
+  int* ai = (int*)a;
+  int old = __float_as_int(*(volatile float*)a);
+  while (v > __int_as_float(old)) {
+    const int assumed = old;
+    old = atomicCAS(ai, assumed, __float_as_int(v));
+    if (old == assumed) break;
+  }
+}
+
+__global__ __launch_bounds__(kThreads) void range_kernel(const float* __restrict__ in, int64_t pitch, int H, int Wd,
+                                                         float* mm) {
+  __shared__ float smin[kThreads], smax[kThreads];
+  float lo = __builtin_huge_valf(), hi = -__builtin_huge_valf();
+  const int64_t npx = (int64_t)H * Wd;
+  for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < npx; i += (int64_t)gridDim.x * kThreads) {
+    const int r = (int)(i / Wd), c = (int)(i - (int64_t)r * Wd);
+    const float v = in[(int64_t)r * pitch + c];
+    lo = fminf(lo, v);  // fminf/fmaxf return the other operand for a NaN
+    hi = fmaxf(hi, v);
+  }
+  smin[threadIdx.x] = lo;
+  smax[threadIdx.x] = hi;
+  __syncthreads();
+  for (int w = kThreads / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) {
+      smin[threadIdx.x] = fminf(smin[threadIdx.x], smin[threadIdx.x + w]);
+      smax[threadIdx.x] = fmaxf(smax[threadIdx.x], smax[threadIdx.x + w]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    atomic_fmin(mm, smin[0]);
+    atomic_fmax(mm + 1, smax[0]);
+  }
+}
+
+hipError_t launch_range(const float* in, int64_t pitch, int H, int Wd, float* mm, hipStream_t s) {
+  hipLaunchKernelGGL(range_init_kernel, dim3(1), dim3(64), 0, s, mm);
+  const int64_t npx = (int64_t)H * Wd;
+  const int g = (int)std::max<int64_t>(1, std::min<int64_t>((npx + kThreads - 1) / kThreads, 1024));
+  hipLaunchKernelGGL(range_kernel, dim3(g), dim3(kThreads), 0, s, in, pitch, H, Wd, mm);
+  return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------

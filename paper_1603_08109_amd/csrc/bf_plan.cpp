@@ -592,6 +592,15 @@ int bf_forward(const bf_plan_t* pl, const float* in, int64_t in_pitch, float* ou
   return BF_OK;
 }
 
+int bf_image_range(const float* in, int64_t pitch, int32_t height, int32_t width, float* minmax,
+                   void* stream) {
+  if (!in || !minmax) return fail(BF_EINVAL, "NULL image or output pointer");
+  if (height < 0 || width < 0 || pitch < width) return fail(BF_EINVAL, "bad size or pitch");
+  hipError_t e = launch_range(in, pitch, height, width, minmax, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "range launch");
+  return BF_OK;
+}
+
 int bf_forward_joint(const bf_plan_t* pl, const float* in, int64_t in_pitch, const float* guide,
                      int64_t guide_pitch, float* out, int64_t out_pitch, void* stream) {
   if (!pl || !in || !guide || !out) return fail(BF_EINVAL, "NULL plan or image pointer");
