@@ -70,6 +70,9 @@ extern "C" {
                                    fused on-chip tiles); allocates about 64 bytes per pixel */
 #define BF_FLAG_JOINT        8  /* cross (joint) filter: the range kernel acts on a guide
                                    image (bf_forward_joint); fused tiles only, no adjoint */
+#define BF_FLAG_MIRROR      16  /* reflecting border (edge samples repeated) instead of zero
+                                   extension; forward only (no adjoint), and on the streamed
+                                   path only for box W <= 96 and Gaussian W <= 124 */
 
 typedef struct bf_params {
   int32_t kernel;    /* BF_BOX or BF_GAUSS */

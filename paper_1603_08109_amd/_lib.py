@@ -31,6 +31,7 @@ BF_FLAG_FP32_ACCUM = 1
 BF_FLAG_GRAD = 2
 BF_FLAG_STREAMED = 4
 BF_FLAG_JOINT = 8
+BF_FLAG_MIRROR = 16
 
 
 class bf_params(C.Structure):

@@ -38,7 +38,7 @@ def make_params(kernel: str, sigma_r: float, *, sigma_s: float | None = None, W:
                 T: float = 127.5, center: float | None = None, N: int = 0, delta: float = 1e-3,
                 n_rule: str = "lambertw", height: int = 0, width: int = 0,
                 fp32_accum: bool = False, grad: bool = False, streamed: bool = False,
-                joint: bool = False) -> L.bf_params:
+                joint: bool = False, mirror: bool = False) -> L.bf_params:
     p = L.bf_params()
     p.kernel = _KERNELS[kernel]
     p.sigma_s = float(sigma_s) if sigma_s is not None else 0.0
@@ -52,7 +52,8 @@ def make_params(kernel: str, sigma_r: float, *, sigma_s: float | None = None, W:
     p.height = int(height)
     p.width = int(width)
     p.flags = ((L.BF_FLAG_FP32_ACCUM if fp32_accum else 0) | (L.BF_FLAG_GRAD if grad else 0)
-               | (L.BF_FLAG_STREAMED if streamed else 0) | (L.BF_FLAG_JOINT if joint else 0))
+               | (L.BF_FLAG_STREAMED if streamed else 0) | (L.BF_FLAG_JOINT if joint else 0)
+               | (L.BF_FLAG_MIRROR if mirror else 0))
     return p
 
 

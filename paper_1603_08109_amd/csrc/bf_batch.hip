@@ -369,6 +369,8 @@ static int run_direct(bf_batch* b, int k, hipStream_t s, int grid) {
 // image) is recomputed by the batch forward kernel at each call.
 static int plan_batch_adjoint(bf_batch* b) {
   const int count = b->count;
+  for (int i = 0; i < count; ++i)
+    if (b->status[i] >= 0 && b->hp[i].mirror) return fail(BF_EUNSUPPORTED, "the mirror border has no adjoint");
   int best = -1, best_n = -1;
   for (int v = 0; v < backward_variant_count(); ++v) {
     const Variant vv = backward_variant(v);
@@ -516,6 +518,7 @@ int bf_batch_plan(int32_t count, const bf_params* per_image, bf_batch_t** out) {
     t.X = (float)(pi.T / pi.sigma_r);
     t.inv_sigma_s3 = pi.kernel == BF_GAUSS ? (float)(1.0 / (pi.sigma_s * pi.sigma_s * pi.sigma_s)) : 0.0f;
     t.saved_plane = (int64_t)pi.height * pi.width;
+    t.mirror = (pi.flags & BF_FLAG_MIRROR) ? 1 : 0;
   }
   if (hipMalloc(&b->d_const, std::max<int64_t>(total, 1) * sizeof(float)) != hipSuccess) {
     delete b;

@@ -212,17 +212,34 @@ __device__ __forceinline__ RegionGeom region_geom(int TY, int W) {
 }
 
 // Visit the thread's region pixels: fn(m, q, inside, gr, gc).
+// Index into the reflected extension of [0, n) (edge samples repeated,
+// period 2n): the mirror-border reading of the image outside its domain.
+__host__ __device__ __forceinline__ int reflect_index(int i, int n) {
+  int m = i % (2 * n);
+  if (m < 0) m += 2 * n;
+  return m < n ? m : 2 * n - 1 - m;
+}
+
+// Visit this thread's MREG region slots: fn(slot, q, inside, gr, gc).  With
+// zero extension, `inside` marks slots on the image; with `mirror` every slot
+// of the region is inside and (gr, gc) are reflected onto the image.
 template <int MREG, typename Fn>
 __device__ __forceinline__ void for_region(const RegionGeom& g, int r0, int c0, int W, int H,
-                                           int Wd, Fn&& fn) {
+                                           int Wd, Fn&& fn, bool mirror = false) {
   const int t = threadIdx.x;
   int row = t / g.RWp, col = t - row * g.RWp;
   const int srow = kThreads / g.RWp, scol = kThreads - srow * g.RWp;
 #pragma unroll
   for (int m = 0; m < MREG; ++m) {
     const int q = t + kThreads * m;
-    const int gr = r0 - W + row, gc = c0 - W + col;
-    const bool inside = q < g.npx && col < g.RW && gr >= 0 && gr < H && gc >= 0 && gc < Wd;
+    int gr = r0 - W + row, gc = c0 - W + col;
+    bool inside = q < g.npx && col < g.RW;
+    if (mirror) {
+      gr = reflect_index(gr, H);
+      gc = reflect_index(gc, Wd);
+    } else {
+      inside = inside && gr >= 0 && gr < H && gc >= 0 && gc < Wd;
+    }
     fn(m, q, inside, gr, gc);
     col += scol;
     row += srow;
@@ -288,7 +305,7 @@ __device__ __forceinline__ void forward_tile(const TileParams& p, int r0, int c0
     const int cr = min(max(gr, 0), p.H - 1), cc = min(max(gc, 0), p.Wd - 1);
     Fr[m] = p.in[(int64_t)cr * p.in_pitch + cc];
     yr[m] = inside ? 1.f : 0.f;
-  });
+  }, p.mirror != 0);
 #pragma unroll
   for (int m = 0; m < MREG; ++m) {
     const float f = Fr[m];
@@ -409,7 +426,7 @@ __device__ __forceinline__ void joint_tile(const TileParams& p, int r0, int c0, 
     Fr[m] = p.guide[(int64_t)cr * p.guide_pitch + cc];
     fr[m] = p.in[(int64_t)cr * p.in_pitch + cc];
     yr[m] = inside ? 1.f : 0.f;
-  });
+  }, p.mirror != 0);
 #pragma unroll
   for (int m = 0; m < MREG; ++m) {
     const float h = Fr[m];

@@ -52,6 +52,7 @@ struct TileParams {
   const float* taps2;   // same layout, d^2 * tap (Gaussian sigma_s gradient)
   const float* guide;   // cross filter: the image the range kernel acts on (else null)
   int64_t guide_pitch;
+  int mirror;           // 1: reflecting border (BF_FLAG_MIRROR), 0: zero extension
 };
 
 // Large-support path: orders per block and its device state.
@@ -121,6 +122,7 @@ int max_lds_bytes();
 // large-support path (bf_large.hip)
 bool ls_supported(int W);
 bool ls_box_strip_supported(int W);
+bool ls_mirror_supported(int kernel, int W);
 int64_t ls_state_bytes(int H, int Wd, int W, bool save);
 LsState ls_layout(void* base, int H, int Wd, int W, bool save);
 hipError_t launch_forward_ls(const TileParams& p, const LsState& st, bool save, hipStream_t s);

@@ -277,8 +277,13 @@ __global__ __launch_bounds__(kThreads) void ls_rows_mfma_kernel(TileParams p, Ls
   for (int j = 0; j < kLsRowsRegs; ++j) {
     const int q = threadIdx.x + j * kThreads;
     const int row = q / RWp, col = q - row * RWp;
-    const int gr = r0 + row, gc = c0 - W + col;
-    const bool ok = q < npx && col < RW && gr < p.H && gc >= 0 && gc < p.Wd;
+    const int gr = r0 + row;
+    int gc = c0 - W + col;
+    bool ok = q < npx && col < RW && gr < p.H;
+    if (p.mirror)
+      gc = reflect_index(gc, p.Wd);
+    else
+      ok = ok && gc >= 0 && gc < p.Wd;
     const int64_t i = ok ? (int64_t)gr * st.pitch + gc : 0;
     F[j] = ok ? Fin[i] : 0.f;
     Y[j] = ok ? st.Y[i] : 0.f;
@@ -366,7 +371,10 @@ __global__ __launch_bounds__(kColsThreads) void ls_cols_mfma_kernel(TileParams p
   for (int k = 0; k < K; ++k) {
     const int n = n0 + k;
     __syncthreads();
-    stage_rows_lds<kColsThreads>(st.H[k] + (int64_t)tr0 * st.pitch + c0, st.pitch, Sl, rows);
+    if (p.mirror)
+      stage_rows_lds_mirror<kColsThreads>(st.H[k], st.pitch, tr0, c0, W, p.H, Sl, rows);
+    else
+      stage_rows_lds<kColsThreads>(st.H[k] + (int64_t)tr0 * st.pitch + c0, st.pitch, Sl, rows);
     __syncthreads();
     mf4 acc[2];
 #pragma unroll
@@ -547,7 +555,9 @@ __global__ __launch_bounds__(kStripThreads) void ls_box_strip_kernel(TileParams 
   const int r_lo = seg * seg_rows, r_hi = min(r_lo + seg_rows, p.H);
   const int t = threadIdx.x;
   const int gc = c0 - W + t;
-  const bool col_ok = gc >= 0 && gc < p.Wd;
+  // mirror border: strip columns and rows outside the image read their reflections
+  const bool col_ok = p.mirror || (gc >= 0 && gc < p.Wd);
+  const int gcs = p.mirror ? reflect_index(gc, p.Wd) : gc;
   const bool central = t >= W && t < W + OC && gc < p.Wd;
   const int lane = t & 63, wv = t >> 6;
   const int oc = t;  // output column c0 + oc (idle lanes cost nothing once a wave has none)
@@ -565,8 +575,9 @@ __global__ __launch_bounds__(kStripThreads) void ls_box_strip_kernel(TileParams 
   auto load_row = [&](int q, float& f, float& y) {
     f = 0.f;
     y = 0.f;
+    if (p.mirror) q = reflect_index(q, p.H);
     if (col_ok && q >= 0 && q < p.H) {
-      const int64_t j = (int64_t)q * st.pitch + gc;
+      const int64_t j = (int64_t)q * st.pitch + gcs;
       f = Fin[j];
       y = st.Y[j];
     }
@@ -652,6 +663,14 @@ int64_t ls_box_strip_lds_bytes() { return (int64_t)kLsBlock * kStripPitch * 8; }
 
 bool ls_box_strip_supported(int W) { return strip_cols(W) >= 64; }
 
+// The streamed kernels that implement the mirror border: box strips, and the
+// matrix-core row and column passes of the Gaussian.
+bool ls_mirror_supported(int kernel, int W) {
+  if (kernel == BF_BOX) return ls_box_strip_supported(W);
+  return ls_rows_mfma_fits(W) && ls_rows_mfma_lds_bytes(W) <= max_lds_bytes() &&
+         ls_cols_mfma_lds_bytes(W) <= max_lds_bytes();
+}
+
 __global__ __launch_bounds__(kThreads) void ls_final_kernel(TileParams p, LsState st) {
   const int64_t npx = (int64_t)p.H * p.Wd;
   const double X = (double)p.X;
@@ -727,6 +746,7 @@ LsState ls_layout(void* base, int H, int Wd, int W, bool save) {
 
 hipError_t launch_forward_ls(const TileParams& p, const LsState& st, bool save, hipStream_t s) {
   if (p.H <= 0 || p.Wd <= 0) return hipSuccess;
+  if (p.mirror && !ls_mirror_supported(p.kt, p.W)) return hipErrorInvalidValue;
   if (save && !st.DP) return hipErrorInvalidValue;  // saved planes need the adjoint sums
   const int64_t npx = (int64_t)p.H * p.Wd;
   const int g1 = (int)std::min<int64_t>((npx + kThreads - 1) / kThreads, 4096);

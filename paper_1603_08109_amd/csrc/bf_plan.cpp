@@ -393,6 +393,8 @@ int bf_plan(const bf_params* in, bf_plan_t** out) {
   if (ost < 0) return ost;
   int variant = 0, TY = 0;
   bool ls = false;
+  if ((p.flags & BF_FLAG_MIRROR) && (p.flags & BF_FLAG_GRAD))
+    return fail(BF_EUNSUPPORTED, "the mirror border has no adjoint");
   if (p.flags & BF_FLAG_JOINT) {
     if (p.flags & (BF_FLAG_GRAD | BF_FLAG_STREAMED))
       return fail(BF_EUNSUPPORTED, "the cross filter has no adjoint or streamed path");
@@ -404,6 +406,8 @@ int bf_plan(const bf_params* in, bf_plan_t** out) {
   }
   if (st < 0) {
     if (!ls_supported(p.W)) return fail(BF_EUNSUPPORTED, "support W too large");
+    if ((p.flags & BF_FLAG_MIRROR) && !ls_mirror_supported(p.kernel, p.W))
+      return fail(BF_EUNSUPPORTED, "support W too large for the mirror border");
     ls = true;  // large-support path through device memory
     variant = -1;
     TY = 0;
@@ -558,6 +562,7 @@ static void fill_common(const bf_plan_t* pl, TileParams& tp) {
   const int64_t ntapr = ((2 * p.W + 1 + 2 * kTapPad + 63) / 64) * 64;
   bind_tables(tp, pl->d_const, pl->tab_stride, ntapr);
   tp.saved_plane = (int64_t)p.height * p.width;
+  tp.mirror = (p.flags & BF_FLAG_MIRROR) ? 1 : 0;
 }
 }  // namespace bfgpa
 

@@ -12,6 +12,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include "bf_device.h"
 #include "bf_internal.h"
 
 namespace bfgpa {
@@ -104,6 +105,22 @@ __device__ __forceinline__ void stage_rows_lds(const float* src, int64_t pitch, 
   for (int g = wv; g < rows / 4; g += NT / 64)
     __builtin_amdgcn_global_load_lds(h + (int64_t)(4 * g) * pitch,
                                      (__attribute__((address_space(3))) void*)(S + g * 256), 16, 0, 0);
+}
+
+// As stage_rows_lds for a window of a row-filtered image laid out with W
+// rows above the image (padded row R holds image row R - W), but with the
+// rows outside the image taken from their reflections (mirror border).
+template <int NT>
+__device__ __forceinline__ void stage_rows_lds_mirror(const float* img, int64_t pitch, int R0, int c0, int W,
+                                                      int H, float* S, int rows) {
+  const int lane = threadIdx.x & 63;
+  const int wv = threadIdx.x >> 6;
+  for (int g = wv; g < rows / 4; g += NT / 64) {
+    const int R = R0 + 4 * g + (lane >> 4);
+    const int Rs = reflect_index(R - W, H) + W;
+    __builtin_amdgcn_global_load_lds(img + (int64_t)Rs * pitch + c0 + (lane & 15) * 4,
+                                     (__attribute__((address_space(3))) void*)(S + g * 256), 16, 0, 0);
+  }
 }
 
 // Tile order for column passes: column bands four tiles wide, row-major
