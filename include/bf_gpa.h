@@ -73,6 +73,17 @@ extern "C" {
 #define BF_FLAG_MIRROR      16  /* reflecting border (edge samples repeated) instead of zero
                                    extension; forward only (no adjoint), and on the streamed
                                    path only for box W <= 96 and Gaussian W <= 124 */
+#define BF_FLAG_TILE_VALU   32  /* force the fused tile on the vector ALUs (the planner's
+                                   choice otherwise); BF_EUNSUPPORTED if W does not fit */
+#define BF_FLAG_TILE_MFMA   64  /* force the fused 64 x 64 tile with both FIR passes on the
+                                   matrix cores (Gaussian, W <= 45, float64 sums whatever
+                                   BF_FLAG_FP32_ACCUM says); at most one of STREAMED,
+                                   TILE_VALU, TILE_MFMA may be set */
+
+/* forward engines (bf_plan_info.path) */
+#define BF_PATH_TILE       0  /* one fused launch, tile on the vector ALUs */
+#define BF_PATH_STREAMED   1  /* blocks of orders through device memory */
+#define BF_PATH_TILE_MFMA  2  /* one fused launch, FIR passes on the matrix cores */
 
 typedef struct bf_params {
   int32_t kernel;    /* BF_BOX or BF_GAUSS */
@@ -100,6 +111,7 @@ typedef struct bf_plan_info {
   int32_t tile_rows;         /* tile height the forward kernel uses */
   int32_t tile_cols;         /* tile width */
   int64_t workspace_bytes;   /* device bytes owned by the plan */
+  int32_t path;              /* BF_PATH_* the forward runs (bf_order: the one it would run) */
 } bf_plan_info;
 
 typedef struct bf_plan bf_plan_t;

@@ -32,6 +32,11 @@ BF_FLAG_GRAD = 2
 BF_FLAG_STREAMED = 4
 BF_FLAG_JOINT = 8
 BF_FLAG_MIRROR = 16
+BF_FLAG_TILE_VALU = 32
+BF_FLAG_TILE_MFMA = 64
+BF_PATH_TILE = 0
+BF_PATH_STREAMED = 1
+BF_PATH_TILE_MFMA = 2
 
 
 class bf_params(C.Structure):
@@ -63,6 +68,7 @@ class bf_plan_info(C.Structure):
         ("tile_rows", C.c_int32),
         ("tile_cols", C.c_int32),
         ("workspace_bytes", C.c_int64),
+        ("path", C.c_int32),
     ]
 
 

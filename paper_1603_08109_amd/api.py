@@ -17,6 +17,9 @@ from . import _lib as L
 
 _RULES = {"lambertw": L.BF_NRULE_LAMBERTW, "alg1": L.BF_NRULE_ALG1, "poisson": L.BF_NRULE_POISSON}
 _KERNELS = {"box": L.BF_BOX, "gauss": L.BF_GAUSS, "gaussian": L.BF_GAUSS}
+_ENGINES = {None: 0, "auto": 0, "valu": L.BF_FLAG_TILE_VALU, "mfma": L.BF_FLAG_TILE_MFMA,
+            "streamed": L.BF_FLAG_STREAMED}
+PATHS = {L.BF_PATH_TILE: "valu", L.BF_PATH_STREAMED: "streamed", L.BF_PATH_TILE_MFMA: "mfma"}
 
 
 @dataclass
@@ -31,6 +34,7 @@ class PlanInfo:
     tile_rows: int
     tile_cols: int
     workspace_bytes: int
+    path: int = 0
     status: int = 0
 
 
@@ -38,7 +42,9 @@ def make_params(kernel: str, sigma_r: float, *, sigma_s: float | None = None, W:
                 T: float = 127.5, center: float | None = None, N: int = 0, delta: float = 1e-3,
                 n_rule: str = "lambertw", height: int = 0, width: int = 0,
                 fp32_accum: bool = False, grad: bool = False, streamed: bool = False,
-                joint: bool = False, mirror: bool = False) -> L.bf_params:
+                joint: bool = False, mirror: bool = False, engine: str | None = None) -> L.bf_params:
+    """bf_params; `engine` forces the forward engine: "valu" (fused tile on the
+    vector ALUs), "mfma" (fused tile on the matrix cores) or "streamed"."""
     p = L.bf_params()
     p.kernel = _KERNELS[kernel]
     p.sigma_s = float(sigma_s) if sigma_s is not None else 0.0
@@ -53,13 +59,13 @@ def make_params(kernel: str, sigma_r: float, *, sigma_s: float | None = None, W:
     p.width = int(width)
     p.flags = ((L.BF_FLAG_FP32_ACCUM if fp32_accum else 0) | (L.BF_FLAG_GRAD if grad else 0)
                | (L.BF_FLAG_STREAMED if streamed else 0) | (L.BF_FLAG_JOINT if joint else 0)
-               | (L.BF_FLAG_MIRROR if mirror else 0))
+               | (L.BF_FLAG_MIRROR if mirror else 0) | _ENGINES[engine])
     return p
 
 
 def _info(i: L.bf_plan_info, status: int = 0) -> PlanInfo:
     return PlanInfo(i.N, i.W, i.w0, i.eps, i.lambda_, i.kernel_bound, i.guaranteed_delta,
-                    i.tile_rows, i.tile_cols, i.workspace_bytes, status)
+                    i.tile_rows, i.tile_cols, i.workspace_bytes, i.path, status)
 
 
 def bf_order(kernel: str, sigma_r: float, **kw) -> PlanInfo:

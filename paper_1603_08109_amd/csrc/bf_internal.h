@@ -108,6 +108,10 @@ hipError_t launch_forward(const TileParams& p, int variant, bool acc64, bool sav
 hipError_t launch_backward(const TileParams& p, int variant, bool sigs, double* partials,
                            double* grad_sigma, hipStream_t s);
 hipError_t launch_joint(const TileParams& p, int variant, hipStream_t s);
+// fused Gaussian tile with both FIR passes on the matrix cores (W <= 45)
+hipError_t launch_fused_mfma(const TileParams& p, bool save, hipStream_t s);
+bool fused_mfma_supported(int W);
+int64_t fused_mfma_lds_bytes(int W);
 hipError_t launch_range(const float* in, int64_t pitch, int H, int Wd, float* mm, hipStream_t s);
 int joint_variant_count();
 Variant joint_variant(int v);
@@ -175,6 +179,7 @@ struct bf_plan {
   double* d_partials;   // per-workgroup sigma-gradient partials
   int ntiles_b;         // backward tiles
   bool ls;              // large-support path (support too wide for the fused tiles)
+  bool mfma;            // fused matrix-core tile (Gaussian)
   void* d_ls;           // its device state
   bfgpa::LsState ls_state;
   bool bls;             // streamed adjoint

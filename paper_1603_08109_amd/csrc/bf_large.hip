@@ -144,101 +144,6 @@ __global__ __launch_bounds__(kThreads) void ls_rows_kernel(TileParams p, LsState
   }
 }
 
-// Per-pixel coefficient state of the streamed path, held in registers for
-// CH pixels while the orders of one block are folded in.
-template <int CH, bool SAVE>
-struct LsPix {
-  float a[CH], ap[CH], app[CH], z[CH];
-  double P[CH], Q[CH], DP[CH], DQ[CH];
-
-  __device__ __forceinline__ void load(const LsState& st, int64_t i0, int64_t stride, int n_ok) {
-#pragma unroll
-    for (int s = 0; s < CH; ++s) {
-      const bool ok = s < n_ok;
-      const int64_t i = i0 + s * stride;
-      a[s] = ok ? st.a[i] : 0.f;
-      ap[s] = ok ? st.ap[i] : 0.f;
-      z[s] = ok ? st.z[i] : 0.f;
-      P[s] = ok ? st.P[i] : 0.0;
-      Q[s] = ok ? st.Q[i] : 0.0;
-      if (SAVE) {
-        app[s] = ok ? st.app[i] : 0.f;
-        DP[s] = ok ? st.DP[i] : 0.0;
-        DQ[s] = ok ? st.DQ[i] : 0.0;
-      }
-    }
-  }
-  // pixels s0 .. s0 + M - 1 at i0 + (s - s0) * stride, the first n_ok of them inside the image
-  template <int M>
-  __device__ __forceinline__ void load_part(const LsState& st, int s0, int64_t i0, int64_t stride, int n_ok) {
-#pragma unroll
-    for (int u = 0; u < M; ++u) {
-      const int s = s0 + u;
-      const bool ok = u < n_ok;
-      const int64_t i = ok ? i0 + u * stride : 0;
-      a[s] = ok ? st.a[i] : 0.f;
-      ap[s] = ok ? st.ap[i] : 0.f;
-      z[s] = ok ? st.z[i] : 0.f;
-      P[s] = ok ? st.P[i] : 0.0;
-      Q[s] = ok ? st.Q[i] : 0.0;
-      if (SAVE) {
-        app[s] = ok ? st.app[i] : 0.f;
-        DP[s] = ok ? st.DP[i] : 0.0;
-        DQ[s] = ok ? st.DQ[i] : 0.0;
-      }
-    }
-  }
-  template <int M>
-  __device__ __forceinline__ void store_part(const LsState& st, int s0, int64_t i0, int64_t stride,
-                                             int n_ok) const {
-#pragma unroll
-    for (int u = 0; u < M; ++u) {
-      const int s = s0 + u;
-      if (u < n_ok) {
-        const int64_t i = i0 + u * stride;
-        st.a[i] = a[s];
-        st.ap[i] = ap[s];
-        st.P[i] = P[s];
-        st.Q[i] = Q[s];
-        if (SAVE) {
-          st.app[i] = app[s];
-          st.DP[i] = DP[s];
-          st.DQ[i] = DQ[s];
-        }
-      }
-    }
-  }
-  __device__ __forceinline__ void store(const LsState& st, int64_t i0, int64_t stride, int n_ok) const {
-#pragma unroll
-    for (int s = 0; s < CH; ++s) {
-      if (s < n_ok) {
-        const int64_t i = i0 + s * stride;
-        st.a[i] = a[s];
-        st.ap[i] = ap[s];
-        st.P[i] = P[s];
-        st.Q[i] = Q[s];
-        if (SAVE) {
-          st.app[i] = app[s];
-          st.DP[i] = DP[s];
-          st.DQ[i] = DQ[s];
-        }
-      }
-    }
-  }
-  // fold F_bar_n (value v at pixel s) into eqs. (P), (Q) and advance a_n
-  __device__ __forceinline__ void fold(int s, int n, int N, float v, float in1) {
-    if (n < N) Q[s] = fma((double)a[s], (double)v, Q[s]);
-    if (n >= 1) P[s] = fma((double)ap[s], (double)v, P[s]);
-    if (SAVE) {
-      if (n >= 1 && n < N) DQ[s] = fma((double)ap[s], (double)v, DQ[s]);
-      if (n >= 2) DP[s] = fma((double)app[s], (double)v, DP[s]);
-      app[s] = ap[s];
-    }
-    ap[s] = a[s];
-    a[s] *= z[s] * in1;
-  }
-};
-
 // ---------------------------------------------------------------------------
 // Gaussian passes on the matrix cores (Toeplitz products, bf_toeplitz.h).
 // ---------------------------------------------------------------------------

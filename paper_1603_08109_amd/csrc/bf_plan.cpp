@@ -267,7 +267,8 @@ static double streamed_cost(int kernel, int W) {
   return (256.0 + 2 * W) / 256.0 * (L + 4.0) + (L + 4.0) + 5.0 + 100.0;
 }
 
-static int choose_forward_tile(int kernel, int W, int H, int Wd, int* variant, int* TY) {
+static int choose_forward_tile(int kernel, int W, int H, int Wd, bool allow_streamed, int* variant, int* TY,
+                               double* cost = nullptr) {
   const int nv = forward_variant_count();
   int best = -1;
   double bestc = 0.0;
@@ -290,12 +291,18 @@ static int choose_forward_tile(int kernel, int W, int H, int Wd, int* variant, i
   // when the image is large enough to hide those launches.  Box: the column
   // strips beat the fused tiles from W = 16 on (measured on 4096^2: W = 10
   // fused 1.7 vs strips 1.9 ps per pixel and order, W = 30 4.4 vs 2.2).
-  if ((int64_t)H * Wd >= (1 << 20) && ls_supported(W)) {
-    if (kernel == BF_BOX ? (W >= 16 && ls_box_strip_supported(W)) : bestc > streamed_cost(kernel, W))
+  // Gaussian on images of 2^22 pixels and more: the streamed passes win from
+  // W = 13 on (measured on 4096^2: W = 9 tile 9.4 vs streamed 14.0 ms, W = 15
+  // 18.5 vs 15.6 ms, sigma_r = 10), earlier than the cost model says.
+  const int64_t npx = (int64_t)H * Wd;
+  if (allow_streamed && npx >= (1 << 20) && ls_supported(W)) {
+    const bool gauss_wide = bestc > streamed_cost(kernel, W) || (npx >= (1 << 22) && W >= 13);
+    if (kernel == BF_BOX ? (W >= 16 && ls_box_strip_supported(W)) : gauss_wide)
       return fail(BF_EUNSUPPORTED, "streamed path is cheaper at this support");
   }
   *variant = best;
   *TY = 4 * forward_variant(best).opt;
+  if (cost) *cost = bestc;
   return BF_OK;
 }
 
@@ -319,6 +326,53 @@ static int choose_joint_tile(int kernel, int W, int H, int Wd, int* variant, int
   if (best < 0) return fail(BF_EUNSUPPORTED, "support W too large for the cross-filter tiles");
   *variant = best;
   *TY = 4 * joint_variant(best).opt;
+  return BF_OK;
+}
+
+// The forward engine of a plan: the fused VALU tile (variant, TY), the
+// fused matrix-core tile (Gaussian only), or the streamed sequence.
+struct ForwardPath {
+  int engine;   // BF_PATH_*
+  int variant;  // VALU tile variant, or -1
+  int TY;       // tile rows (0 on the streamed path)
+};
+
+static int choose_forward_path(const bf_params& p, ForwardPath* fp) {
+  const int force = p.flags & (BF_FLAG_STREAMED | BF_FLAG_TILE_VALU | BF_FLAG_TILE_MFMA);
+  if (force & (force - 1)) return fail(BF_EINVAL, "at most one of the STREAMED / TILE_VALU / TILE_MFMA flags");
+  const bool mirror = (p.flags & BF_FLAG_MIRROR) != 0;
+  fp->variant = -1;
+  fp->TY = 0;
+  if (p.flags & BF_FLAG_JOINT) {
+    if (p.flags & (BF_FLAG_GRAD | BF_FLAG_STREAMED | BF_FLAG_TILE_MFMA))
+      return fail(BF_EUNSUPPORTED, "the cross filter has no adjoint, streamed or matrix-core path");
+    fp->engine = BF_PATH_TILE;
+    return choose_joint_tile(p.kernel, p.W, p.height, p.width, &fp->variant, &fp->TY);
+  }
+  if (p.flags & BF_FLAG_TILE_MFMA) {
+    if (p.kernel != BF_GAUSS) return fail(BF_EUNSUPPORTED, "the matrix-core tile serves the Gaussian kernel only");
+    if (!fused_mfma_supported(p.W)) return fail(BF_EUNSUPPORTED, "support W too large for the matrix-core tile");
+    fp->engine = BF_PATH_TILE_MFMA;
+    fp->TY = 64;
+    return BF_OK;
+  }
+  if (p.flags & BF_FLAG_TILE_VALU) {
+    fp->engine = BF_PATH_TILE;
+    return choose_forward_tile(p.kernel, p.W, p.height, p.width, false, &fp->variant, &fp->TY);
+  }
+  if (!(p.flags & BF_FLAG_STREAMED)) {
+    double c = 0.0;
+    if (choose_forward_tile(p.kernel, p.W, p.height, p.width, true, &fp->variant, &fp->TY, &c) == BF_OK) {
+      fp->engine = BF_PATH_TILE;
+      return BF_OK;
+    }
+  }
+  if (!ls_supported(p.W)) return fail(BF_EUNSUPPORTED, "support W too large");
+  if (mirror && !ls_mirror_supported(p.kernel, p.W))
+    return fail(BF_EUNSUPPORTED, "support W too large for the mirror border");
+  fp->engine = BF_PATH_STREAMED;
+  fp->variant = -1;
+  fp->TY = 0;
   return BF_OK;
 }
 
@@ -369,14 +423,13 @@ int bf_order(const bf_params* in, bf_plan_info* out) {
   if (st < 0) return st;
   st = plan_order(&p, out);
   if (st < 0) return st;
-  int v, ty;
   if (p.height > 0 && p.width > 0) {
-    if (choose_forward_tile(p.kernel, p.W, p.height, p.width, &v, &ty) == BF_OK) {
-      out->tile_rows = ty;
-      out->tile_cols = kTileCols;
-    } else if (!ls_supported(p.W)) {
-      return fail(BF_EUNSUPPORTED, "support W too large");
-    }
+    ForwardPath fp;
+    const int pst = choose_forward_path(p, &fp);
+    if (pst < 0) return pst;
+    out->path = fp.engine;
+    out->tile_rows = fp.TY;
+    out->tile_cols = fp.engine == BF_PATH_STREAMED ? 0 : fp.engine == BF_PATH_TILE_MFMA ? 64 : kTileCols;
   }
   return st;
 }
@@ -391,27 +444,13 @@ int bf_plan(const bf_params* in, bf_plan_t** out) {
   bf_plan_info info;
   int ost = plan_order(&p, &info);
   if (ost < 0) return ost;
-  int variant = 0, TY = 0;
-  bool ls = false;
   if ((p.flags & BF_FLAG_MIRROR) && (p.flags & BF_FLAG_GRAD))
     return fail(BF_EUNSUPPORTED, "the mirror border has no adjoint");
-  if (p.flags & BF_FLAG_JOINT) {
-    if (p.flags & (BF_FLAG_GRAD | BF_FLAG_STREAMED))
-      return fail(BF_EUNSUPPORTED, "the cross filter has no adjoint or streamed path");
-    st = choose_joint_tile(p.kernel, p.W, p.height, p.width, &variant, &TY);
-    if (st < 0) return st;
-  } else {
-    st = (p.flags & BF_FLAG_STREAMED) ? BF_EUNSUPPORTED
-                                      : choose_forward_tile(p.kernel, p.W, p.height, p.width, &variant, &TY);
-  }
-  if (st < 0) {
-    if (!ls_supported(p.W)) return fail(BF_EUNSUPPORTED, "support W too large");
-    if ((p.flags & BF_FLAG_MIRROR) && !ls_mirror_supported(p.kernel, p.W))
-      return fail(BF_EUNSUPPORTED, "support W too large for the mirror border");
-    ls = true;  // large-support path through device memory
-    variant = -1;
-    TY = 0;
-  }
+  ForwardPath fpath;
+  st = choose_forward_path(p, &fpath);
+  if (st < 0) return st;
+  const bool ls = fpath.engine == BF_PATH_STREAMED;  // large-support path through device memory
+  const int variant = fpath.variant, TY = fpath.TY;
   const bool grad = (p.flags & BF_FLAG_GRAD) != 0;
   const bool sigs = p.kernel == BF_GAUSS;
   int bvariant = -1, bTY = 0;
@@ -430,8 +469,10 @@ int bf_plan(const bf_params* in, bf_plan_t** out) {
   if (!pl) return fail(BF_ENOMEM, "host allocation failed");
   pl->p = p;
   pl->info = info;
+  pl->info.path = fpath.engine;
   pl->info.tile_rows = TY;
-  pl->info.tile_cols = kTileCols;
+  pl->info.tile_cols = ls ? 0 : fpath.engine == BF_PATH_TILE_MFMA ? 64 : kTileCols;
+  pl->mfma = fpath.engine == BF_PATH_TILE_MFMA;
   pl->variant = variant;
   pl->TY = TY;
   pl->bvariant = bvariant;
@@ -590,6 +631,8 @@ int bf_forward(const bf_plan_t* pl, const float* in, int64_t in_pitch, float* ou
     if (saved && !pl->ls_state.DP)
       return fail(BF_EINVAL, "saved state needs a plan built with BF_FLAG_GRAD");
     e = launch_forward_ls(tp, pl->ls_state, saved != nullptr, (hipStream_t)stream);
+  } else if (pl->mfma) {
+    e = launch_fused_mfma(tp, saved != nullptr, (hipStream_t)stream);
   } else {
     e = launch_forward(tp, pl->variant, acc64, saved != nullptr, (hipStream_t)stream);
   }
@@ -653,8 +696,9 @@ int bf_backward(const bf_plan_t* pl, const float* in, int64_t in_pitch, const fl
     fp.saved = pl->d_work;
     fp.TY = pl->TY;
     fp.tiles_x = (pl->p.width + kTileCols - 1) / kTileCols;
-    hipError_t e = pl->ls ? launch_forward_ls(fp, pl->ls_state, true, s)
-                          : launch_forward(fp, pl->variant, acc64, true, s);
+    hipError_t e = pl->ls     ? launch_forward_ls(fp, pl->ls_state, true, s)
+                   : pl->mfma ? launch_fused_mfma(fp, true, s)
+                              : launch_forward(fp, pl->variant, acc64, true, s);
     if (e != hipSuccess) return hip_fail(e, "forward (recompute) launch");
     saved = pl->d_work;
   }

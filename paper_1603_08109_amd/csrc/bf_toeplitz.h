@@ -59,13 +59,13 @@ __device__ __forceinline__ void toeplitz_rows(const float* L, int pitch, int cba
 }
 
 // Column products: NB blocks of 16 outputs at columns cbase + 16 bb and
-// rows r0 .. r0 + 15 of a staged window S (pitch 64; output row r reads
-// staged rows r .. r + 2W).
+// rows r0 .. r0 + 15 of a staged window S (row pitch `pitch`; output row r
+// reads staged rows r .. r + 2W).
 template <int NB>
 __device__ __forceinline__ void toeplitz_cols(const float* S, int r0, int cbase, const float* Tt, int KK,
-                                              mf4 (&acc)[NB]) {
+                                              mf4 (&acc)[NB], int pitch = 64) {
   const int lane = threadIdx.x & 63;
-  const float* sb = S + (r0 + (lane >> 4)) * 64 + cbase + (lane & 15);  // B[l/16][l%16]
+  const float* sb = S + (r0 + (lane >> 4)) * pitch + cbase + (lane & 15);  // B[l/16][l%16]
   float ta = Tt[lane], b[NB];
 #pragma unroll
   for (int bb = 0; bb < NB; ++bb) b[bb] = sb[bb * 16];
@@ -74,7 +74,7 @@ __device__ __forceinline__ void toeplitz_cols(const float* S, int r0, int cbase,
     const float tn = Tt[kn * 64 + lane];
     float bn[NB];
 #pragma unroll
-    for (int bb = 0; bb < NB; ++bb) bn[bb] = sb[4 * kn * 64 + bb * 16];
+    for (int bb = 0; bb < NB; ++bb) bn[bb] = sb[4 * kn * pitch + bb * 16];
 #pragma unroll
     for (int bb = 0; bb < NB; ++bb) acc[bb] = __builtin_amdgcn_mfma_f32_16x16x4f32(ta, b[bb], acc[bb], 0, 0, 0);
     ta = tn;

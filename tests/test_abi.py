@@ -96,3 +96,28 @@ def test_gaussian_support_rule():
     for ss, W in [(3.0, 9), (5.0, 15), (25.0, 75), (2.2, 7), (1.0 / 3.0, 1)]:
         assert P.bf_order("gauss", 30.0, sigma_s=ss).W == W
     assert P.bf_order("gauss", 30.0, sigma_s=5.0, W=4).W == 4
+
+
+def test_engine_selection():
+    # host-only: which forward engine a plan would run, and the forcing flags' limits
+    import paper_1603_08109_amd as P
+    from paper_1603_08109_amd import _lib as L
+    kw = dict(height=512, width=512)
+    a = P.bf_order("gauss", 30.0, sigma_s=3.0, engine="mfma", **kw)
+    assert a.path == L.BF_PATH_TILE_MFMA and (a.tile_rows, a.tile_cols) == (64, 64)
+    assert P.bf_order("gauss", 30.0, sigma_s=15.0, engine="mfma", **kw).W == 45
+    v = P.bf_order("gauss", 30.0, sigma_s=3.0, engine="valu", **kw)
+    assert v.path == L.BF_PATH_TILE and v.tile_rows > 0
+    s = P.bf_order("gauss", 30.0, sigma_s=3.0, engine="streamed", **kw)
+    assert s.path == L.BF_PATH_STREAMED
+    assert P.bf_order("gauss", 30.0, sigma_s=25.0, **kw).path == L.BF_PATH_STREAMED  # W = 75
+    for bad, code in [(dict(kernel="box", W=3), L.BF_EUNSUPPORTED),             # Gaussian only
+                      (dict(kernel="gauss", sigma_s=15.4), L.BF_EUNSUPPORTED),  # W = 47 > 45
+                      (dict(kernel="gauss", sigma_s=3.0, joint=True), L.BF_EUNSUPPORTED)]:
+        k = bad.pop("kernel")
+        with pytest.raises(L.BFError) as e:
+            P.bf_order(k, 30.0, engine="mfma", **bad, **kw)
+        assert e.value.code == code, bad
+    with pytest.raises(L.BFError) as e:
+        P.bf_order("gauss", 30.0, sigma_s=3.0, engine="mfma", streamed=True, **kw)
+    assert e.value.code == L.BF_EINVAL
