@@ -56,6 +56,9 @@ extern "C" {
 /* spatial kernel (Sec. 1) */
 #define BF_BOX    0   /* w = 1/|Omega| on [-W, W]^2, eq. spatial_kernel2 */
 #define BF_GAUSS  1   /* w(i) = exp(-|i|^2 / 2 sigma_s^2), eq. spatial_kernel1 */
+#define BF_GAUSS_REC 2 /* the recursive Gaussian Sec. 1 and Sec. 3 cite (Deriche's fit
+                          of exp(-x^2/2) by two damped oscillations), unbounded support,
+                          O(1) per pixel and order whatever sigma_s; W is ignored */
 
 /* rule that turns delta into N */
 #define BF_NRULE_LAMBERTW  0  /* Cor. eps + Prop. LambW, exact W0 (default) */
@@ -84,9 +87,10 @@ extern "C" {
 #define BF_PATH_TILE       0  /* one fused launch, tile on the vector ALUs */
 #define BF_PATH_STREAMED   1  /* blocks of orders through device memory */
 #define BF_PATH_TILE_MFMA  2  /* one fused launch, FIR passes on the matrix cores */
+#define BF_PATH_RECURSIVE  3  /* BF_GAUSS_REC: row and column recursions per block of orders */
 
 typedef struct bf_params {
-  int32_t kernel;    /* BF_BOX or BF_GAUSS */
+  int32_t kernel;    /* BF_BOX, BF_GAUSS or BF_GAUSS_REC */
   double  sigma_s;   /* Gaussian spatial scale (ignored for box) */
   int32_t W;         /* half-width of Omega; 0 with BF_GAUSS means ceil(3 sigma_s) */
   double  sigma_r;   /* range scale, eq. range_kernel */

@@ -31,6 +31,8 @@ the order rule is w(0) = (h(0) / sum_n h(|n|))^2.
 """
 from __future__ import annotations
 
+from functools import lru_cache
+
 import numpy as np
 
 from . import bf as _bf
@@ -60,10 +62,17 @@ def w0(sigma_s: float) -> float:
     return (float(kernel(0, sigma_s)) / kernel_sum(sigma_s)) ** 2
 
 
-def toeplitz(L: int, sigma_s: float) -> np.ndarray:
-    """K[i, j] = h(|i - j|) for a line of L samples."""
+@lru_cache(maxsize=8)
+def _toeplitz(L: int, sigma_s: float) -> np.ndarray:
     i = np.arange(L)
-    return kernel(i[:, None] - i[None, :], sigma_s)
+    K = kernel(i[:, None] - i[None, :], sigma_s)
+    K.setflags(write=False)
+    return K
+
+
+def toeplitz(L: int, sigma_s: float) -> np.ndarray:
+    """K[i, j] = h(|i - j|) for a line of L samples (cached, read-only)."""
+    return _toeplitz(int(L), float(sigma_s))
 
 
 def spatial_filter(F: np.ndarray, sigma_s: float) -> np.ndarray:
@@ -109,6 +118,37 @@ def gpa_alg2(f: np.ndarray, sigma_s: float, sigma_r: float, N: int, T: float) ->
         Fbar = spatial_filter(F, sigma_s)
         P = P + G * Fbar
         G = Hh * G / n
+    return sigma_r * (P / Q) + T
+
+
+def gpa_alg2_at(f: np.ndarray, pixels: np.ndarray, sigma_s: float, sigma_r: float, N: int,
+                T: float) -> np.ndarray:
+    """``gpa_alg2`` at the listed (row, col) pixels only: F_bar_n there is
+    k_r^T F_n k_c with the rows k_r = h(|r - i|), k_c = h(|c - j|)."""
+    f = np.asarray(f, dtype=np.float64)
+    H, Wd = f.shape
+    px = np.asarray(pixels)
+    rr, cc = px[:, 0], px[:, 1]
+    Kr = kernel(rr[:, None] - np.arange(H)[None, :], sigma_s)
+    Kc = kernel(cc[:, None] - np.arange(Wd)[None, :], sigma_s)
+    h = f - T
+    Hh = h / sigma_r
+    F = np.exp(-(h * h) / (2.0 * sigma_r * sigma_r))
+    hp = Hh[rr, cc]
+    G = np.ones(len(px))
+    P = np.zeros(len(px))
+    Q = np.zeros(len(px))
+
+    def at(F):
+        return ((Kr @ F) * Kc).sum(axis=1)
+
+    Fbar = at(F)
+    for n in range(1, N + 1):
+        Q = Q + G * Fbar
+        F = Hh * F
+        Fbar = at(F)
+        P = P + G * Fbar
+        G = hp * G / n
     return sigma_r * (P / Q) + T
 
 

@@ -22,6 +22,7 @@ BF_WNOGUARANTEE = 1
 
 BF_BOX = 0
 BF_GAUSS = 1
+BF_GAUSS_REC = 2
 
 BF_NRULE_LAMBERTW = 0
 BF_NRULE_ALG1 = 1
@@ -37,6 +38,7 @@ BF_FLAG_TILE_MFMA = 64
 BF_PATH_TILE = 0
 BF_PATH_STREAMED = 1
 BF_PATH_TILE_MFMA = 2
+BF_PATH_RECURSIVE = 3
 
 
 class bf_params(C.Structure):

@@ -16,10 +16,11 @@ import torch
 from . import _lib as L
 
 _RULES = {"lambertw": L.BF_NRULE_LAMBERTW, "alg1": L.BF_NRULE_ALG1, "poisson": L.BF_NRULE_POISSON}
-_KERNELS = {"box": L.BF_BOX, "gauss": L.BF_GAUSS, "gaussian": L.BF_GAUSS}
+_KERNELS = {"box": L.BF_BOX, "gauss": L.BF_GAUSS, "gaussian": L.BF_GAUSS, "gauss_rec": L.BF_GAUSS_REC}
 _ENGINES = {None: 0, "auto": 0, "valu": L.BF_FLAG_TILE_VALU, "mfma": L.BF_FLAG_TILE_MFMA,
             "streamed": L.BF_FLAG_STREAMED}
-PATHS = {L.BF_PATH_TILE: "valu", L.BF_PATH_STREAMED: "streamed", L.BF_PATH_TILE_MFMA: "mfma"}
+PATHS = {L.BF_PATH_TILE: "valu", L.BF_PATH_STREAMED: "streamed", L.BF_PATH_TILE_MFMA: "mfma",
+         L.BF_PATH_RECURSIVE: "recursive"}
 
 
 @dataclass

@@ -487,8 +487,9 @@ int bf_batch_plan(int32_t count, const bf_params* per_image, bf_batch_t** out) {
     bf_params pi = per_image[i];
     if (pi.flags & BF_FLAG_GRAD) b->grad = true;
     pi.flags &= ~(BF_FLAG_GRAD | BF_FLAG_STREAMED);
-    int st = (pi.flags & BF_FLAG_JOINT) ? fail(BF_EUNSUPPORTED, "the batch runs the plain filter only")
-                                        : bf_order(&pi, &b->info[i]);
+    int st = (pi.flags & BF_FLAG_JOINT)  ? fail(BF_EUNSUPPORTED, "the batch runs the plain filter only")
+             : pi.kernel == BF_GAUSS_REC ? fail(BF_EUNSUPPORTED, "the batch has no recursive Gaussian")
+                                         : bf_order(&pi, &b->info[i]);
     b->status[i] = st;
     if (st < 0) continue;
     if (st > 0) warn = st;

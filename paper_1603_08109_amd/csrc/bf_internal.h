@@ -53,6 +53,7 @@ struct TileParams {
   const float* guide;   // cross filter: the image the range kernel acts on (else null)
   int64_t guide_pitch;
   int mirror;           // 1: reflecting border (BF_FLAG_MIRROR), 0: zero extension
+  const float* rg_tab;  // recursive Gaussian: recursion coefficients and scan matrices (else null)
 };
 
 // Large-support path: orders per block and its device state.
@@ -65,6 +66,8 @@ struct LsState {
   float *a, *ap, *app, *z;  // per-pixel coefficient recursion
   double *P, *Q, *DP, *DQ;  // per-pixel sums
   int64_t hbytes;           // bytes of one row-filtered image
+  int64_t tpitch;           // recursive Gaussian: row pitch of the column-major filtered images
+  float* HT[kLsBlock];      // recursive Gaussian: the row-filtered images, column-major
 };
 
 // Rows of one row-filtered image of the streamed passes: the height padded
@@ -108,6 +111,18 @@ hipError_t launch_forward(const TileParams& p, int variant, bool acc64, bool sav
 hipError_t launch_backward(const TileParams& p, int variant, bool sigs, double* partials,
                            double* grad_sigma, hipStream_t s);
 hipError_t launch_joint(const TileParams& p, int variant, hipStream_t s);
+// Recursive Gaussian (BF_GAUSS_REC).  Table (floats): per oscillation j of
+// the fit, at 8 j: a, a' (weights), Re q, Im q (pole q = rho e^{i theta});
+// from 16: q_j^(8 m), m = 1 .. kRgPow, as (re, im) at 16 + 2 (kRgPow j + m - 1).
+constexpr int kRgPow = 128;
+constexpr int kRgTabFloats = 16 + 4 * kRgPow;
+hipError_t launch_forward_rg(const TileParams& p, const LsState& st, hipStream_t s);
+bool rg_supported(int H, int Wd);
+int64_t rg_state_bytes(int H, int Wd);
+LsState rg_layout(void* base, int H, int Wd);
+void rg_table(double sigma_s, float* out);
+double rg_w0(double sigma_s);
+
 // fused Gaussian tile with both FIR passes on the matrix cores (W <= 45)
 hipError_t launch_fused_mfma(const TileParams& p, bool save, hipStream_t s);
 bool fused_mfma_supported(int W);
@@ -180,6 +195,7 @@ struct bf_plan {
   int ntiles_b;         // backward tiles
   bool ls;              // large-support path (support too wide for the fused tiles)
   bool mfma;            // fused matrix-core tile (Gaussian)
+  bool rec;             // recursive Gaussian (its state in d_ls / ls_state)
   void* d_ls;           // its device state
   bfgpa::LsState ls_state;
   bool bls;             // streamed adjoint

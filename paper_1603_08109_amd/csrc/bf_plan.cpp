@@ -13,6 +13,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <complex>
 #include <cstdio>
 #include <cstring>
 #include <limits>
@@ -122,10 +123,16 @@ std::vector<double> taps1d(int kind, double sigma_s, int W) {
 static int normalise(const bf_params* in, bf_params* p) {
   if (!in) return fail(BF_EINVAL, "params is NULL");
   *p = *in;
-  if (p->kernel != BF_BOX && p->kernel != BF_GAUSS) return fail(BF_EINVAL, "kernel must be BF_BOX or BF_GAUSS");
+  if (p->kernel != BF_BOX && p->kernel != BF_GAUSS && p->kernel != BF_GAUSS_REC)
+    return fail(BF_EINVAL, "kernel must be BF_BOX, BF_GAUSS or BF_GAUSS_REC");
   if (p->kernel == BF_GAUSS) {
     if (!(p->sigma_s > 0.0) || !std::isfinite(p->sigma_s)) return fail(BF_EINVAL, "sigma_s must be > 0");
     if (p->W <= 0) p->W = (int)std::ceil(3.0 * p->sigma_s - 1e-12);
+  }
+  if (p->kernel == BF_GAUSS_REC) {
+    // the fit's recursions stay well conditioned in float32 over this range
+    if (!(p->sigma_s >= 0.5 && p->sigma_s <= 100.0)) return fail(BF_EINVAL, "recursive Gaussian: sigma_s in [0.5, 100]");
+    p->W = 0;  // unbounded support
   }
   if (p->W < 0) return fail(BF_EINVAL, "W must be >= 0");
   if (!(p->sigma_r > 0.0) || !std::isfinite(p->sigma_r)) return fail(BF_EINVAL, "sigma_r must be > 0");
@@ -147,7 +154,7 @@ static int plan_order(const bf_params* p, bf_plan_info* info) {
   double s = 0.0;
   for (double v : t) s += v;
   info->W = p->W;
-  info->w0 = (t[p->W] * t[p->W]) / (s * s);
+  info->w0 = p->kernel == BF_GAUSS_REC ? rg_w0(p->sigma_s) : (t[p->W] * t[p->W]) / (s * s);
   info->eps = info->w0 * p->delta / (2.0 * p->T + p->delta);
   info->lambda = (p->T / p->sigma_r) * (p->T / p->sigma_r);
   // float32 range: exp(-x^2/2) must stay a normal float for |x| <= T/sigma_r
@@ -203,6 +210,48 @@ void gpa_tables(double lam, int N, std::vector<double>& s, std::vector<double>& 
   }
 }
 
+// Deriche's fit of the sampled Gaussian exp(-x^2/2), x = n / sigma_s, by two
+// damped oscillations (a, a', b, omega):
+// h(n) = sum_j (a_j cos(omega_j x) + a'_j sin(omega_j x)) e^{-b_j x}, x = |n| / sigma_s.
+static const double kDericheFit[2][4] = {{1.680, 3.735, 1.783, 0.6318}, {-0.6803, -0.2598, 1.723, 1.997}};
+
+// Normalised centre weight (h(0) / sum_n h(|n|))^2 of the 2-D kernel; with
+// q = rho e^{i theta} per oscillation, sum_{m >= 1} h_j(m) = Re[(a - i a') q / (1 - q)].
+double rg_w0(double sigma_s) {
+  double h0 = 0.0, tail = 0.0;
+  for (const auto& f : kDericheFit) {
+    const std::complex<double> q = std::polar(std::exp(-f[2] / sigma_s), f[3] / sigma_s);
+    h0 += f[0];
+    tail += std::real(std::complex<double>(f[0], -f[1]) * q / (1.0 - q));
+  }
+  const double S = h0 + 2.0 * tail;
+  return (h0 / S) * (h0 / S);
+}
+
+// Per oscillation, the pole q = rho e^{i theta}, rho = e^{-b/sigma_s},
+// theta = omega/sigma_s: h_j(n) = Re[(a - i a') q^n], so the causal part is
+// Re[(a - i a') w] with w[i] = q w[i-1] + x[i] and the anticausal part the
+// same with w'[i] = q (w'[i+1] + x[i+1]).  The scans over chunks of 16 or 8
+// samples move states by q^16 or q^8 per chunk: the table holds q^(8 m),
+// m = 1 .. 128.
+void rg_table(double sigma_s, float* out) {
+  for (int j = 0; j < 2; ++j) {
+    const std::complex<double> q = std::polar(std::exp(-kDericheFit[j][2] / sigma_s), kDericheFit[j][3] / sigma_s);
+    out[8 * j + 0] = (float)kDericheFit[j][0];
+    out[8 * j + 1] = (float)kDericheFit[j][1];
+    out[8 * j + 2] = (float)q.real();
+    out[8 * j + 3] = (float)q.imag();
+    std::complex<double> q8 = q;
+    for (int i = 0; i < 3; ++i) q8 *= q8;  // q^8
+    std::complex<double> z = q8;
+    for (int m = 1; m <= kRgPow; ++m) {
+      out[16 + 2 * (kRgPow * j + m - 1)] = (float)z.real();
+      out[17 + 2 * (kRgPow * j + m - 1)] = (float)z.imag();
+      z *= q8;
+    }
+  }
+}
+
 // Device constant tables of one image, as one float array: s_n, r_n, 1/n
 // (n = 0 .. N+1, rows of *stride floats), then the taps and the d^2 taps
 // (kTapPad zeros on each side, rows of *ntapr floats).
@@ -213,7 +262,9 @@ std::vector<float> const_tables(const bf_params& p, const bf_plan_info& info, in
   const int N = info.N, W = p.W;
   *stride = ((N + 2 + 63) / 64) * 64;
   *ntapr = ((2 * W + 1 + 2 * kTapPad + 63) / 64) * 64;
-  std::vector<float> h(3 * *stride + 2 * *ntapr, 0.0f);
+  const int64_t nrg = p.kernel == BF_GAUSS_REC ? kRgTabFloats : 0;
+  std::vector<float> h(3 * *stride + 2 * *ntapr + nrg, 0.0f);
+  if (nrg) rg_table(p.sigma_s, h.data() + 3 * *stride + 2 * *ntapr);
   for (int n = 0; n <= N + 1; ++n) {
     h[n] = (float)s[n];
     h[*stride + n] = (float)r[n];
@@ -343,6 +394,14 @@ static int choose_forward_path(const bf_params& p, ForwardPath* fp) {
   const bool mirror = (p.flags & BF_FLAG_MIRROR) != 0;
   fp->variant = -1;
   fp->TY = 0;
+  if (p.kernel == BF_GAUSS_REC) {
+    if (p.flags & (BF_FLAG_JOINT | BF_FLAG_MIRROR | BF_FLAG_TILE_VALU | BF_FLAG_TILE_MFMA))
+      return fail(BF_EUNSUPPORTED, "the recursive Gaussian runs the plain filter, zero border, own engine");
+    if (p.height > 0 && p.width > 0 && !rg_supported(p.height, p.width))
+      return fail(BF_EUNSUPPORTED, "recursive Gaussian: width and height <= 8192");
+    fp->engine = BF_PATH_RECURSIVE;
+    return BF_OK;
+  }
   if (p.flags & BF_FLAG_JOINT) {
     if (p.flags & (BF_FLAG_GRAD | BF_FLAG_STREAMED | BF_FLAG_TILE_MFMA))
       return fail(BF_EUNSUPPORTED, "the cross filter has no adjoint, streamed or matrix-core path");
@@ -429,7 +488,9 @@ int bf_order(const bf_params* in, bf_plan_info* out) {
     if (pst < 0) return pst;
     out->path = fp.engine;
     out->tile_rows = fp.TY;
-    out->tile_cols = fp.engine == BF_PATH_STREAMED ? 0 : fp.engine == BF_PATH_TILE_MFMA ? 64 : kTileCols;
+    out->tile_cols = (fp.engine == BF_PATH_STREAMED || fp.engine == BF_PATH_RECURSIVE) ? 0
+                     : fp.engine == BF_PATH_TILE_MFMA                                  ? 64
+                                                                                       : kTileCols;
   }
   return st;
 }
@@ -446,6 +507,8 @@ int bf_plan(const bf_params* in, bf_plan_t** out) {
   if (ost < 0) return ost;
   if ((p.flags & BF_FLAG_MIRROR) && (p.flags & BF_FLAG_GRAD))
     return fail(BF_EUNSUPPORTED, "the mirror border has no adjoint");
+  if (p.kernel == BF_GAUSS_REC && (p.flags & BF_FLAG_GRAD))
+    return fail(BF_EUNSUPPORTED, "the recursive Gaussian has no adjoint");
   ForwardPath fpath;
   st = choose_forward_path(p, &fpath);
   if (st < 0) return st;
@@ -471,8 +534,9 @@ int bf_plan(const bf_params* in, bf_plan_t** out) {
   pl->info = info;
   pl->info.path = fpath.engine;
   pl->info.tile_rows = TY;
-  pl->info.tile_cols = ls ? 0 : fpath.engine == BF_PATH_TILE_MFMA ? 64 : kTileCols;
+  pl->info.tile_cols = (ls || fpath.engine == BF_PATH_RECURSIVE) ? 0 : fpath.engine == BF_PATH_TILE_MFMA ? 64 : kTileCols;
   pl->mfma = fpath.engine == BF_PATH_TILE_MFMA;
+  pl->rec = fpath.engine == BF_PATH_RECURSIVE;
   pl->variant = variant;
   pl->TY = TY;
   pl->bvariant = bvariant;
@@ -530,6 +594,17 @@ int bf_plan(const bf_params* in, bf_plan_t** out) {
     }
     pl->ls_state = ls_layout(pl->d_ls, p.height, p.width, p.W, grad);
     ws += lb;
+  }
+  if (pl->rec) {
+    const int64_t rb = rg_state_bytes(p.height, p.width);
+    e = hipMalloc(&pl->d_ls, rb);
+    if (e != hipSuccess) {
+      hipFree(pl->d_const);
+      delete pl;
+      return fail(BF_ENOMEM, "hipMalloc recursive-Gaussian state failed");
+    }
+    pl->ls_state = rg_layout(pl->d_ls, p.height, p.width);
+    ws += rb;
   }
   if (bls) {
     const int64_t bb = bls_state_bytes(p.height, p.width, p.W, sigs);
@@ -602,6 +677,7 @@ static void fill_common(const bf_plan_t* pl, TileParams& tp) {
   tp.inv_sigma_s3 = p.kernel == BF_GAUSS ? (float)(1.0 / (p.sigma_s * p.sigma_s * p.sigma_s)) : 0.0f;
   const int64_t ntapr = ((2 * p.W + 1 + 2 * kTapPad + 63) / 64) * 64;
   bind_tables(tp, pl->d_const, pl->tab_stride, ntapr);
+  tp.rg_tab = p.kernel == BF_GAUSS_REC ? pl->d_const + 3 * pl->tab_stride + 2 * ntapr : nullptr;
   tp.saved_plane = (int64_t)p.height * p.width;
   tp.mirror = (p.flags & BF_FLAG_MIRROR) ? 1 : 0;
 }
@@ -633,6 +709,9 @@ int bf_forward(const bf_plan_t* pl, const float* in, int64_t in_pitch, float* ou
     e = launch_forward_ls(tp, pl->ls_state, saved != nullptr, (hipStream_t)stream);
   } else if (pl->mfma) {
     e = launch_fused_mfma(tp, saved != nullptr, (hipStream_t)stream);
+  } else if (pl->rec) {
+    if (saved) return fail(BF_EINVAL, "the recursive Gaussian keeps no adjoint state");
+    e = launch_forward_rg(tp, pl->ls_state, (hipStream_t)stream);
   } else {
     e = launch_forward(tp, pl->variant, acc64, saved != nullptr, (hipStream_t)stream);
   }

@@ -121,3 +121,25 @@ def test_engine_selection():
     with pytest.raises(L.BFError) as e:
         P.bf_order("gauss", 30.0, sigma_s=3.0, engine="mfma", streamed=True, **kw)
     assert e.value.code == L.BF_EINVAL
+
+
+def test_recursive_gaussian_planning():
+    # host-only: w0 from the fit's closed-form sum, N from the same rule, engine and limits
+    import paper_1603_08109_amd as P
+    from oracle import recursive as R
+    from paper_1603_08109_amd import _lib as L
+    for ss in (0.5, 3.0, 25.0, 100.0):
+        w0 = R.w0(ss)
+        for sr in (10.0, 30.0, 60.0):
+            info = P.bf_order("gauss_rec", sr, sigma_s=ss, height=512, width=512)
+            assert info.w0 == pytest.approx(w0, rel=1e-10)
+            assert info.N == O.order_for_delta(1e-3, w0, 127.5, sr)
+            assert info.path == L.BF_PATH_RECURSIVE and info.W == 0
+    for bad in (dict(sigma_s=0.3), dict(sigma_s=150.0)):
+        with pytest.raises(L.BFError) as e:
+            P.bf_order("gauss_rec", 30.0, **bad)
+        assert e.value.code == L.BF_EINVAL
+    with pytest.raises(L.BFError) as e:
+        P.bf_order("gauss_rec", 30.0, sigma_s=3.0, height=9000, width=64)   # lines longer than 8192
+    assert e.value.code == L.BF_EUNSUPPORTED
+    assert P.bf_order("gauss_rec", 30.0, sigma_s=3.0, height=64, width=8192).path == L.BF_PATH_RECURSIVE

@@ -103,3 +103,10 @@ def test_deviation_from_truncated_gaussian(sigma_s, sigma_r):
     d = np.abs(rec - ex)
     print(f"sigma_s={sigma_s} sigma_r={sigma_r}: max {d.max():.3e} mean {d.mean():.3e}")
     assert d.max() < 1.5 and d.mean() < 0.2
+
+
+def test_pointwise_matches_full():
+    f = synthimg.gen1(19, 23, 9)
+    px = np.array([[0, 0], [18, 22], [7, 11], [0, 22], [12, 3]])
+    full = R.gpa_alg2(f, 2.5, 25.0, 12, 127.5)
+    assert np.allclose(R.gpa_alg2_at(f, px, 2.5, 25.0, 12, 127.5), full[px[:, 0], px[:, 1]], rtol=0, atol=1e-10)
