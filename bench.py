@@ -402,6 +402,18 @@ def main():
         print(f"# joint {extra['joint']}", file=sys.stderr, flush=True)
         del guide
 
+        # recursive (Deriche) Gaussian: cost flat in sigma_s, next to the exact FIR of the sweep
+        rl = {}
+        for ss, sr in [(3.0, 30.0), (10.0, 30.0), (25.0, 30.0), (25.0, 10.0), (60.0, 30.0)]:
+            rp = P.Plan("gauss_rec", sr, H, Wd, sigma_s=ss)
+            ms_r = time_launches(lambda: rp.forward(x, out=out), stream, 1, max(1, a.steps // 2), torch)
+            rl[f"sigma_s={ss:g},sigma_r={sr:g}"] = {"N": rp.info.N, "ms": round(ms_r, 4),
+                                                   "us_per_order": round(1e3 * ms_r / (rp.info.N + 1), 2),
+                                                   "mpix_s": round(H * Wd / ms_r / 1e3, 1)}
+        extra["recursive"] = {"workload": "4096x4096 gen2, BF_GAUSS_REC (Deriche's fit, unbounded support)",
+                              "per_setting": rl}
+        print(f"# recursive {extra['recursive']}", file=sys.stderr, flush=True)
+
     cpu = None
     if not a.no_cpu_baseline:
         from oracle import gpa as G
