@@ -37,6 +37,12 @@ HBM_PEAK_GBS = 8000.0
 ALU_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 # Dense FP32 matrix-core rate (v_mfma_f32_16x16x4f32), MI355X published figure.
 MFMA_F32_PEAK_TFLOPS = 157.3
+# Dense BF16 matrix-core rate, MI355X published figure; the streamed Gaussian
+# passes spend six BF16 products per FP32 product (three-way splits), so the
+# FP32-product ceiling of that arithmetic is a sixth of it.
+MFMA_BF16_PEAK_TFLOPS = 2500.0
+SPLIT_PRODUCTS = 6
+SPLIT_MIN_W = 40  # from this support both streamed passes use the split arithmetic
 
 SWEEP = ([("gauss", dict(sigma_s=s), r) for s in (3.0, 10.0, 25.0) for r in (10.0, 30.0, 50.0)]
          + [("box", dict(W=w), r) for w in (10, 30, 75) for r in (10.0, 30.0, 50.0)])
@@ -176,7 +182,8 @@ def summarize(dirpath, sweep_settings):
              PROFILE_RUNS["trace"], "python3 bench.py --summarize DIR", "```", "",
              f"Each setting runs {per_call} forward calls (1 warm-up + 2 timed). A call is one fused "
              "`gpa_forward_kernel` launch, or the streamed sequence `ls_init`, per block of 16 orders "
-             "(`ls_rows_mfma` + `ls_cols_mfma` for the Gaussian, `ls_box_strip` for the box), `ls_final`.",
+             "(`ls_rows_x3` + `ls_cols_x3` for the Gaussian from W = 40, `ls_rows_x3` + `ls_cols_mfma` below, "
+             "`ls_box_strip` for the box), `ls_final`.",
              "", "| kernel | calls | total ms | avg us | % |", "|---|---|---|---|---|"]
     for k, v in sorted(per_kernel.items(), key=lambda kv: -sum(kv[1])):
         lines.append(f"| `{k}` | {len(v)} | {sum(v) / 1e3:.2f} | {sum(v) / len(v):.1f} | "
@@ -312,16 +319,29 @@ def main():
         flops = H * Wd * (r["N"] + 1) * alg_flops_per_px_n(kind, r["W"])
         achieved = flops / (r["ms"] * 1e-3) / 1e12
         streamed_fir = r["tile_rows"] == 0 and kind == "gauss"
+        split = streamed_fir and r["W"] >= SPLIT_MIN_W
         kern = ("gpa_forward_kernel (one launch)" if r["tile_rows"] > 0 else
-                "ls_rows_mfma + ls_cols_mfma per block of 16 orders" if streamed_fir else
-                "ls_rows + ls_cols_box per block of 16 orders")
-        # the streamed Gaussian filters run on the matrix cores: priced at their FP32 peak
-        bound, peak = ("mfma", MFMA_F32_PEAK_TFLOPS) if streamed_fir else ("alu", ALU_PEAK_TFLOPS)
+                "ls_rows_x3 + ls_cols_x3 per block of 16 orders" if split else
+                "ls_rows_x3 + ls_cols_mfma per block of 16 orders" if streamed_fir else
+                "ls_box_strip per block of 16 orders")
+        extra = {}
+        if split:
+            # the FIR products run as split-BF16 matrix-core products: priced at the
+            # FP32-product ceiling of that arithmetic, with the FP32 matrix-core ratio beside
+            bound, peak = "mfma", MFMA_BF16_PEAK_TFLOPS / SPLIT_PRODUCTS
+            extra = {"peak_basis": f"BF16 dense {MFMA_BF16_PEAK_TFLOPS:g} TFLOP/s / {SPLIT_PRODUCTS} products "
+                                   "per FP32 product",
+                     "frac_of_fp32_mfma_peak": round(achieved / MFMA_F32_PEAK_TFLOPS, 4)}
+        elif streamed_fir:
+            bound, peak = "mfma", MFMA_F32_PEAK_TFLOPS
+        else:
+            bound, peak = "alu", ALU_PEAK_TFLOPS
         return {"bound": bound, "achieved": round(achieved, 3), "peak": round(peak, 1),
                 "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
                 "traffic": measured_traffic(r["setting"]),
                 "kernel": kern, "setting": r["setting"], "ms_per_call": r["ms"],
-                "alg_flops_per_call": flops, "hbm_frac_alg_bytes": round(r["hbm_gbs"] / HBM_PEAK_GBS, 5)}
+                "alg_flops_per_call": flops, "hbm_frac_alg_bytes": round(r["hbm_gbs"] / HBM_PEAK_GBS, 5),
+                **extra}
 
     dom = max(results, key=lambda r: r["ms"])
     roofline = roof(dom)

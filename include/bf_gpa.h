@@ -82,6 +82,10 @@ extern "C" {
                                    matrix cores (Gaussian, W <= 45, float64 sums whatever
                                    BF_FLAG_FP32_ACCUM says); at most one of STREAMED,
                                    TILE_VALU, TILE_MFMA may be set */
+#define BF_FLAG_MFMA_FP32  128  /* streamed Gaussian passes: plain float32 matrix-core products
+                                   instead of float32 emulated by three-way bfloat16 splits
+                                   (six bf16 products per float32 product, about 2.3x fewer
+                                   matrix-core cycles, same rounding level) */
 
 /* forward engines (bf_plan_info.path) */
 #define BF_PATH_TILE       0  /* one fused launch, tile on the vector ALUs */

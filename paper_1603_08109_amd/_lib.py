@@ -35,6 +35,7 @@ BF_FLAG_JOINT = 8
 BF_FLAG_MIRROR = 16
 BF_FLAG_TILE_VALU = 32
 BF_FLAG_TILE_MFMA = 64
+BF_FLAG_MFMA_FP32 = 128
 BF_PATH_TILE = 0
 BF_PATH_STREAMED = 1
 BF_PATH_TILE_MFMA = 2

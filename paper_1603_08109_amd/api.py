@@ -43,9 +43,11 @@ def make_params(kernel: str, sigma_r: float, *, sigma_s: float | None = None, W:
                 T: float = 127.5, center: float | None = None, N: int = 0, delta: float = 1e-3,
                 n_rule: str = "lambertw", height: int = 0, width: int = 0,
                 fp32_accum: bool = False, grad: bool = False, streamed: bool = False,
-                joint: bool = False, mirror: bool = False, engine: str | None = None) -> L.bf_params:
+                joint: bool = False, mirror: bool = False, engine: str | None = None,
+                mfma_fp32: bool = False) -> L.bf_params:
     """bf_params; `engine` forces the forward engine: "valu" (fused tile on the
-    vector ALUs), "mfma" (fused tile on the matrix cores) or "streamed"."""
+    vector ALUs), "mfma" (fused tile on the matrix cores) or "streamed"; `mfma_fp32`
+    keeps the streamed Gaussian passes on plain float32 matrix-core products."""
     p = L.bf_params()
     p.kernel = _KERNELS[kernel]
     p.sigma_s = float(sigma_s) if sigma_s is not None else 0.0
@@ -60,7 +62,8 @@ def make_params(kernel: str, sigma_r: float, *, sigma_s: float | None = None, W:
     p.width = int(width)
     p.flags = ((L.BF_FLAG_FP32_ACCUM if fp32_accum else 0) | (L.BF_FLAG_GRAD if grad else 0)
                | (L.BF_FLAG_STREAMED if streamed else 0) | (L.BF_FLAG_JOINT if joint else 0)
-               | (L.BF_FLAG_MIRROR if mirror else 0) | _ENGINES[engine])
+               | (L.BF_FLAG_MIRROR if mirror else 0) | _ENGINES[engine]
+               | (L.BF_FLAG_MFMA_FP32 if mfma_fp32 else 0))
     return p
 
 

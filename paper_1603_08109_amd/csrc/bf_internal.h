@@ -54,10 +54,13 @@ struct TileParams {
   int64_t guide_pitch;
   int mirror;           // 1: reflecting border (BF_FLAG_MIRROR), 0: zero extension
   const float* rg_tab;  // recursive Gaussian: recursion coefficients and scan matrices (else null)
+  int mfma_x3;          // streamed Gaussian: float32 products as split-bfloat16 matrix-core products
 };
 
 // Large-support path: orders per block and its device state.
 constexpr int kLsBlock = 16;
+constexpr int kLsRows = 16;   // image rows per streamed row-pass workgroup
+constexpr int kLsCols = 256;  // output columns per streamed row-pass workgroup
 struct LsState {
   int64_t pitch;            // row pitch (floats) of the image-shaped buffers
   float* F[2];              // F^ state images (double-buffered)
@@ -71,9 +74,10 @@ struct LsState {
 };
 
 // Rows of one row-filtered image of the streamed passes: the height padded
-// to a multiple of 64, W zero rows above, and W + 8 zero rows below (a box
-// window's entering row, and the overhang of a staged column window).
-inline int64_t ls_hrows(int H, int W) { return (int64_t)((H + 63) / 64) * 64 + 2 * W + 8; }
+// to a multiple of 64, W zero rows above, and W + 40 zero rows below (a box
+// window's entering row, and the overhang of a staged column window: the
+// split-bfloat16 column pass stages up to 2W + 95 rows from a tile's first).
+__host__ __device__ inline int64_t ls_hrows(int H, int W) { return (int64_t)((H + 63) / 64) * 64 + 2 * W + 40; }
 
 // Streamed adjoint (supports too wide for the fused adjoint tiles): orders
 // per block and its device state.
@@ -122,6 +126,13 @@ int64_t rg_state_bytes(int H, int Wd);
 LsState rg_layout(void* base, int H, int Wd);
 void rg_table(double sigma_s, float* out);
 double rg_w0(double sigma_s);
+
+// streamed Gaussian passes with float32 emulated on the bfloat16 matrix cores (W <= 120)
+bool ls_x3_supported(int W);
+int64_t ls_rows_x3_lds_bytes(int W);
+int64_t ls_cols_x3_lds_bytes(int W);
+hipError_t launch_rows_x3(const TileParams& p, const LsState& st, int n0, int K, int src, int grid, hipStream_t s);
+hipError_t launch_cols_x3(const TileParams& p, const LsState& st, int n0, int K, bool save, int grid, hipStream_t s);
 
 // fused Gaussian tile with both FIR passes on the matrix cores (W <= 45)
 hipError_t launch_fused_mfma(const TileParams& p, bool save, hipStream_t s);

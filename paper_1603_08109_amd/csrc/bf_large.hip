@@ -23,8 +23,6 @@
 
 namespace bfgpa {
 
-constexpr int kLsRows = 16;       // image rows per ls_rows workgroup
-constexpr int kLsCols = 256;      // output columns per ls_rows workgroup
 constexpr int kLsOpt = 16;        // output rows per thread in ls_cols
 constexpr int kLsColPitch = 80;   // LDS pitch of staged column windows (paired reads conflict-free)
 
@@ -695,6 +693,9 @@ hipError_t launch_forward_ls(const TileParams& p, const LsState& st, bool save, 
   const size_t clm = (size_t)ls_cols_mfma_lds_bytes(p.W);
   const bool rows_mfma = p.kt != BF_BOX && ls_rows_mfma_fits(p.W) && rlm <= (size_t)max_lds_bytes();
   const bool cols_mfma = p.kt != BF_BOX && clm <= (size_t)max_lds_bytes();
+  // split-bfloat16 passes (float32 products at about 2.3x the float32 matrix-core rate)
+  const bool x3 = p.kt != BF_BOX && p.mfma_x3 && ls_x3_supported(p.W) &&
+                  ls_rows_x3_lds_bytes(p.W) <= max_lds_bytes() && ls_cols_x3_lds_bytes(p.W) <= max_lds_bytes();
   if (rows_mfma) {
     e = hipFuncSetAttribute((const void*)ls_rows_mfma_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
                             max_lds_bytes());
@@ -727,6 +728,26 @@ hipError_t launch_forward_ls(const TileParams& p, const LsState& st, bool save, 
         hipLaunchKernelGGL((ls_box_strip_kernel<false>), dim3(gstrip), dim3(kStripThreads), (size_t)ls_box_strip_lds_bytes(),
                            s, p, st, n0, K, src, strip_seg);
       e = hipGetLastError();
+      if (e != hipSuccess) return e;
+      src ^= 1;
+      continue;
+    }
+    if (x3) {
+      // split row pass always; split column pass from W = 40 (4096^2, sigma_r = 30,
+      // ms per call, rows+cols float32 / split rows / both split: W = 30 4.40 / 4.00 /
+      // 4.14, W = 51 5.82 / 4.95 / 4.78, W = 75 7.40 / 6.09 / 5.93)
+      e = launch_rows_x3(p, st, n0, K, src, grow, s);
+      if (e == hipSuccess) {
+        if (p.W >= 40) {
+          e = launch_cols_x3(p, st, n0, K, save, gfir16, s);
+        } else {
+          if (save)
+            hipLaunchKernelGGL((ls_cols_mfma_kernel<true>), dim3(gfir16), dim3(kColsThreads), clm, s, p, st, n0, K);
+          else
+            hipLaunchKernelGGL((ls_cols_mfma_kernel<false>), dim3(gfir16), dim3(kColsThreads), clm, s, p, st, n0, K);
+          e = hipGetLastError();
+        }
+      }
       if (e != hipSuccess) return e;
       src ^= 1;
       continue;

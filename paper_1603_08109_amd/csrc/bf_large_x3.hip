@@ -1,0 +1,378 @@
+// Streamed Gaussian passes with float32 products emulated on the bfloat16
+// matrix cores.  Every float32 operand is split exactly into three bfloat16
+// terms, f = f_hi + f_mid + f_lo (each the round-to-nearest of what the
+// previous ones leave, 8 significant bits apiece).  A product a t is then
+// the six terms whose weights reach 2^-16 of it (hi hi, hi mid, mid hi,
+// hi lo, mid mid, lo hi), each exact in float32 and accumulated in float32,
+// which drops at most about 2^-23 of |a t|: the float32 product's own
+// rounding.  v_mfma_f32_16x16x32_bf16 takes 16 cycles for a 16x16x32 block,
+// against 32 for 16x16x4 in float32, so the six of them do the banded
+// Toeplitz product of bf_toeplitz.h with about 2.3x fewer matrix-core cycles
+// (k-steps of 32 instead of 4).
+//
+// Lane layout (checked on the GPU): lane l holds A[l%16][8(l/16) + i] and
+// B[8(l/16) + i][l%16], i = 0..7; the result D[4(l/16) + v][l%16] sits in
+// accumulator v.  The Toeplitz operand of k-step s, lane l, element i is
+// tap[32 s + 8(l/16) + i - l%16] (zero outside [0, 2W]) in both passes (B of
+// the row pass, A of the column pass); it is split once per workgroup into
+// LDS as [s][plane][lane] groups of 8, then held in registers (up to 8
+// k-steps x 3 planes x 4 VGPRs), so the only LDS reads per MFMA group are
+// the data slices.
+//
+// Row pass: a workgroup (eight waves) owns 16 rows x 256 columns as in
+// ls_rows_mfma; each order's F^_n is split into three bfloat16 planes in
+// LDS (row pitch 8 mod 16 elements: the 16-byte reads of the 16 rows are
+// conflict-free).
+// Column pass: 64 x 64 tiles; the float32 window of order k + 1 is staged
+// by direct-to-LDS loads while order k multiplies, and each lane splits its
+// 8 rows of one column in registers.  In both passes a wave's blocks that
+// read the same data slice one k-step apart share its reads.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdint>
+
+#include "bf_device.h"
+#include "bf_internal.h"
+#include "bf_toeplitz.h"
+
+namespace bfgpa {
+
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+
+__host__ __device__ inline int x3_steps(int W) { return (16 + 2 * W + 31) / 32; }
+
+// row pitch (bfloat16 elements) of a row-pass plane: the last slice reads
+// column 239 + 32 S; 8 mod 16 keeps the 16-row reads conflict-free
+__host__ __device__ inline int x3_rows_pitch(int W) {
+  const int need = 240 + 32 * x3_steps(W);
+  return ((need + 7) / 16) * 16 + 8;
+}
+
+// rows of a column-pass window: block pair rb, rb + 2 reads rows up to
+// 16 rb + 32 S + 31 with rb <= 1
+__host__ __device__ inline int x3_cols_rows(int W) { return 32 * x3_steps(W) + 48; }
+
+constexpr int kX3RowsThreads = 512;
+constexpr int kX3RowsRegs = 16;        // fp32 slots per thread in the row pass (8 pairs)
+constexpr int kX3ColsThreads = 512;
+constexpr int kX3MaxSteps = 8;             // k-steps of the widest support (W = 120)
+
+__device__ __forceinline__ void split3(float f, __bf16& h, __bf16& m, __bf16& l) {
+  h = (__bf16)f;
+  const float r = f - (float)h;
+  m = (__bf16)r;
+  l = (__bf16)(r - (float)m);
+}
+
+// the three planes of the Toeplitz operand, [s][plane][lane] x 8
+template <int NT>
+__device__ __forceinline__ void fill_toeplitz_x3(__bf16* Tb, int W, const float* __restrict__ tz) {
+  const int S = x3_steps(W);
+  for (int u = threadIdx.x; u < S * 64; u += NT) {
+    const int s = u >> 6, l = u & 63;
+    bf8 ph, pm, pl;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const int d = 32 * s + 8 * (l >> 4) + i - (l & 15);
+      const float t = (d >= 0 && d <= 2 * W) ? tz[d] : 0.f;
+      __bf16 h, m, lo;
+      split3(t, h, m, lo);
+      ph[i] = h;
+      pm[i] = m;
+      pl[i] = lo;
+    }
+    bf8* T = (bf8*)Tb;
+    T[(s * 3 + 0) * 64 + l] = ph;
+    T[(s * 3 + 1) * 64 + l] = pm;
+    T[(s * 3 + 2) * 64 + l] = pl;
+  }
+}
+
+struct X3 {
+  bf8 h, m, l;
+};
+
+__device__ __forceinline__ X3 x3_table(const __bf16* Tb, int s, int lane) {
+  const bf8* T = (const bf8*)Tb;
+  X3 r;
+  r.h = T[(s * 3 + 0) * 64 + lane];
+  r.m = T[(s * 3 + 1) * 64 + lane];
+  r.l = T[(s * 3 + 2) * 64 + lane];
+  return r;
+}
+
+// acc += a b with both operands split (six bf16 products, smallest first)
+__device__ __forceinline__ mf4 mfma_x3(const X3& a, const X3& b, mf4 acc) {
+  acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.l, b.h, acc, 0, 0, 0);
+  acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.m, b.m, acc, 0, 0, 0);
+  acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.h, b.l, acc, 0, 0, 0);
+  acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.m, b.h, acc, 0, 0, 0);
+  acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.h, b.m, acc, 0, 0, 0);
+  acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.h, b.h, acc, 0, 0, 0);
+  return acc;
+}
+
+bool ls_x3_supported(int W) {
+  return kLsRows * x3_rows_pitch(W) <= kX3RowsRegs * kX3RowsThreads;  // W <= 120
+}
+
+int64_t ls_rows_x3_lds_bytes(int W) {
+  return 2 * 3 * (int64_t)kLsRows * x3_rows_pitch(W) + (int64_t)x3_steps(W) * 3 * 64 * 16;
+}
+
+int64_t ls_cols_x3_lds_bytes(int W) {
+  // two float32 windows; the first order's Toeplitz split passes through the second
+  const int64_t win = 4 * (int64_t)(x3_cols_rows(W) / 4) * (4 * 64 + 8);
+  return 2 * win;
+}
+
+// Row pass for orders n0 .. n0 + K - 1 (see ls_rows_mfma_kernel for the tile
+// and the F^ / y slots; here a thread owns pairs of adjacent columns).  Wave
+// w takes the 16-column blocks par = w & 1 and par + 2 of column group
+// w >> 1 (64 columns); they read the same slice one k-step apart.
+template <int MAXS>
+__global__ __launch_bounds__(kX3RowsThreads) void ls_rows_x3_kernel(TileParams p, LsState st, int n0, int K,
+                                                                    int src) {
+  extern __shared__ float lds[];
+  const int W = p.W;
+  const int RW = kLsCols + 2 * W;
+  const int RWb = x3_rows_pitch(W);
+  const int S = x3_steps(W);
+  const int plane = kLsRows * RWb;  // bf16 per plane
+  __bf16* Pl = (__bf16*)lds;        // 3 planes
+  __bf16* Tb = Pl + 3 * plane;
+  const int tiles_x = (p.Wd + kLsCols - 1) / kLsCols;
+  const int tile = blockIdx.x;
+  const int ty = tile / tiles_x, tx = tile - (tile / tiles_x) * tiles_x;
+  const int r0 = ty * kLsRows, c0 = tx * kLsCols;
+  const float* Fin = st.F[src];
+  float* Fout = st.F[src ^ 1];
+  fill_toeplitz_x3<kX3RowsThreads>(Tb, W, p.taps + kTapPad);
+  __syncthreads();
+  X3 T[MAXS];  // this lane's Toeplitz operands, in registers for the whole kernel
+#pragma unroll
+  for (int q = 0; q < MAXS; ++q)
+    if (q < S) T[q] = x3_table(Tb, q, threadIdx.x & 63);
+  float F[kX3RowsRegs], Y[kX3RowsRegs];
+#pragma unroll
+  for (int j = 0; j < kX3RowsRegs; ++j) {
+    const int q = 2 * (threadIdx.x + (j >> 1) * kX3RowsThreads) + (j & 1);
+    const int row = q / RWb, col = q - (q / RWb) * RWb;
+    const int gr = r0 + row;
+    int gc = c0 - W + col;
+    bool ok = row < kLsRows && col < RW && gr < p.H;
+    if (p.mirror)
+      gc = reflect_index(gc, p.Wd);
+    else
+      ok = ok && gc >= 0 && gc < p.Wd;
+    const int64_t i = ok ? (int64_t)gr * st.pitch + gc : 0;
+    F[j] = ok ? Fin[i] : 0.f;
+    Y[j] = ok ? st.Y[i] : 0.f;
+  }
+  const int lane = threadIdx.x & 63;
+  const int wv = threadIdx.x >> 6;
+  const int cbase = 64 * (wv >> 1) + 16 * (wv & 1);  // block par; block par + 2 is 32 columns on
+  const int orow = r0 + 4 * (lane >> 4);
+  const int ocol = c0 + cbase + (lane & 15);
+  // A reads: row l%16, columns cbase + 32 s + 8 (l/16) .. + 7
+  const int abase = (lane & 15) * RWb + cbase + 8 * (lane >> 4);
+  for (int k = 0; k < K; ++k) {
+    __syncthreads();  // the previous order's reads are done
+#pragma unroll
+    for (int j = 0; j < kX3RowsRegs; j += 2) {
+      const int q = 2 * (threadIdx.x + (j >> 1) * kX3RowsThreads);
+      if (q < plane) {
+        __bf16 h0, m0, l0, h1, m1, l1;
+        split3(F[j], h0, m0, l0);
+        split3(F[j + 1], h1, m1, l1);
+        typedef __bf16 bf2 __attribute__((ext_vector_type(2)));
+        *(bf2*)(Pl + q) = bf2{h0, h1};
+        *(bf2*)(Pl + plane + q) = bf2{m0, m1};
+        *(bf2*)(Pl + 2 * plane + q) = bf2{l0, l1};
+      }
+    }
+    __syncthreads();
+    mf4 acc[2] = {mf4{0.f, 0.f, 0.f, 0.f}, mf4{0.f, 0.f, 0.f, 0.f}};
+#pragma unroll
+    for (int q = 0; q <= MAXS; ++q) {
+      if (q <= S) {
+        const int a = abase + 32 * q;
+        X3 av;
+        av.h = *(const bf8*)(Pl + a);
+        av.m = *(const bf8*)(Pl + plane + a);
+        av.l = *(const bf8*)(Pl + 2 * plane + a);
+        if (q < S) acc[0] = mfma_x3(av, T[q < MAXS ? q : 0], acc[0]);  // block par at step q
+        if (q >= 1) acc[1] = mfma_x3(av, T[q >= 1 ? q - 1 : 0], acc[1]);    // block par + 2 at step q - 1
+      }
+    }
+    float* Hk = st.H[k] + (int64_t)W * st.pitch;  // W zero rows above the image
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      if (orow + v < p.H) {
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+          if (ocol + 32 * b < p.Wd) Hk[(int64_t)(orow + v) * st.pitch + ocol + 32 * b] = acc[b][v];
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < kX3RowsRegs; ++j) F[j] *= Y[j];
+  }
+#pragma unroll
+  for (int j = 0; j < kX3RowsRegs; ++j) {
+    const int q = 2 * (threadIdx.x + (j >> 1) * kX3RowsThreads) + (j & 1);
+    const int row = q / RWb, col = q - (q / RWb) * RWb;
+    const int gr = r0 + row, gc = c0 - W + col;
+    if (row < kLsRows && col >= W && col < W + kLsCols && gr < p.H && gc < p.Wd)
+      Fout[(int64_t)gr * st.pitch + gc] = F[j];
+  }
+}
+
+// Column pass: wave w takes the row blocks rb = w & 1 and rb + 2 of column
+// block cb = w >> 1 (16 columns); they read the same window slice one k-step
+// apart.  Lane pixels: accumulator v of block b at row 16 (rb + 2b) +
+// 4 (l/16) + v, column 16 cb + l%16.  The window of order k + 1 is staged
+// in float32 by direct-to-LDS loads (groups of 4 rows, group pitch 264
+// floats so the 8-row reads of the four lane groups fall on distinct banks)
+// while order k multiplies; a lane splits its 8 rows of one column into the
+// three bfloat16 planes in registers.
+constexpr int kX3GroupFloats = 4 * 64 + 8;
+
+__host__ __device__ inline int64_t x3_cols_buffer_floats(int W) {
+  return (int64_t)(x3_cols_rows(W) / 4) * kX3GroupFloats;
+}
+
+template <bool MIRROR>
+__device__ __forceinline__ void x3_stage(const float* __restrict__ Hk, int64_t pitch, int tr0, int c0, int W, int H,
+                                         int groups, float* buf) {
+  const int lane = threadIdx.x & 63;
+  const int wv = threadIdx.x >> 6;
+  for (int g = wv; g < groups; g += kX3ColsThreads / 64) {
+    int R = tr0 + 4 * g + (lane >> 4);  // padded row: image row R - W
+    if (MIRROR) R = reflect_index(R - W, H) + W;
+    __builtin_amdgcn_global_load_lds(Hk + (int64_t)R * pitch + c0 + (lane & 15) * 4,
+                                     (__attribute__((address_space(3))) void*)(buf + g * kX3GroupFloats), 16, 0, 0);
+  }
+}
+
+template <int MAXS, bool SAVE>
+__global__ __launch_bounds__(kX3ColsThreads) void ls_cols_x3_kernel(TileParams p, LsState st, int n0, int K) {
+  extern __shared__ float lds[];
+  const int tiles_x = (p.Wd + kTileCols - 1) / kTileCols;
+  const int tiles_y = (p.H + 63) / 64;
+  int ty, tx;
+  band_tile(xcd_remap(blockIdx.x, gridDim.x), tiles_x, tiles_y, ty, tx);
+  const int lane = threadIdx.x & 63;
+  const int wv = threadIdx.x >> 6;
+  const int rb = wv & 1, cb = wv >> 1;
+  const int tr0 = ty * 64, c0 = tx * kTileCols;
+  const int W = p.W;
+  const int S = x3_steps(W);
+  const int groups = x3_cols_rows(W) / 4;
+  const int64_t bfl = x3_cols_buffer_floats(W);
+  float* buf0 = lds;
+  // the Toeplitz operands pass through the second buffer into registers
+  fill_toeplitz_x3<kX3ColsThreads>((__bf16*)(lds + bfl), W, p.taps + kTapPad);
+  __syncthreads();
+  X3 T[MAXS];
+#pragma unroll
+  for (int q = 0; q < MAXS; ++q)
+    if (q < S) T[q] = x3_table((const __bf16*)(lds + bfl), q, lane);
+  const int pr0 = tr0 + 16 * rb + 4 * (lane >> 4);
+  const int pc = c0 + 16 * cb + (lane & 15);
+  LsPix<8, SAVE> px;
+#pragma unroll
+  for (int b = 0; b < 2; ++b) {
+    const int nr = pc < p.Wd ? max(0, min(4, p.H - (pr0 + 32 * b))) : 0;
+    px.template load_part<4>(st, 4 * b, (int64_t)(pr0 + 32 * b) * p.Wd + pc, p.Wd, nr);
+  }
+  if (p.mirror)
+    x3_stage<true>(st.H[0], st.pitch, tr0, c0, W, p.H, groups, buf0);
+  else
+    x3_stage<false>(st.H[0], st.pitch, tr0, c0, W, p.H, groups, buf0);
+  // this lane's column and first row of slice 0 (16 rb + 8 (l/16), a multiple
+  // of 4: row r of a slice sits at group r / 4, offsets are compile-time)
+  const int lbase = (4 * rb + 2 * (lane >> 4)) * kX3GroupFloats + 16 * cb + (lane & 15);
+  for (int k = 0; k < K; ++k) {
+    const int n = n0 + k;
+    __syncthreads();  // order k staged (each thread waits for its loads); order k - 1 read
+    float* cur = lds + (k & 1) * bfl;
+    if (k + 1 < K) {
+      float* nxt = lds + ((k + 1) & 1) * bfl;
+      if (p.mirror)
+        x3_stage<true>(st.H[k + 1], st.pitch, tr0, c0, W, p.H, groups, nxt);
+      else
+        x3_stage<false>(st.H[k + 1], st.pitch, tr0, c0, W, p.H, groups, nxt);
+    }
+    mf4 acc[2] = {mf4{0.f, 0.f, 0.f, 0.f}, mf4{0.f, 0.f, 0.f, 0.f}};
+#pragma unroll
+    for (int q = 0; q <= MAXS; ++q) {
+      if (q <= S) {
+        X3 bv;
+        const float* src = cur + lbase + 8 * q * kX3GroupFloats;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+          const float f = src[(i >> 2) * kX3GroupFloats + (i & 3) * 64];
+          __bf16 h, m, l;
+          split3(f, h, m, l);
+          bv.h[i] = h;
+          bv.m[i] = m;
+          bv.l[i] = l;
+        }
+        if (q < S) acc[0] = mfma_x3(T[q < MAXS ? q : 0], bv, acc[0]);  // block rb at step q
+        if (q >= 1) acc[1] = mfma_x3(T[q >= 1 ? q - 1 : 0], bv, acc[1]);    // block rb + 2 at step q - 1
+      }
+    }
+    const float in1 = p.inv_tab[n + 1];
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) px.fold(4 * b + v, n, p.N, acc[b][v], in1);
+  }
+#pragma unroll
+  for (int b = 0; b < 2; ++b) {
+    const int nr = pc < p.Wd ? max(0, min(4, p.H - (pr0 + 32 * b))) : 0;
+    px.template store_part<4>(st, 4 * b, (int64_t)(pr0 + 32 * b) * p.Wd + pc, p.Wd, nr);
+  }
+}
+
+template <int MAXS>
+static hipError_t rows_x3_t(const TileParams& p, const LsState& st, int n0, int K, int src, int grid, hipStream_t s) {
+  static bool attr = false;
+  if (!attr) {
+    hipError_t e = hipFuncSetAttribute((const void*)ls_rows_x3_kernel<MAXS>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       max_lds_bytes());
+    if (e != hipSuccess) return e;
+    attr = true;
+  }
+  hipLaunchKernelGGL(ls_rows_x3_kernel<MAXS>, dim3(grid), dim3(kX3RowsThreads), (size_t)ls_rows_x3_lds_bytes(p.W), s,
+                     p, st, n0, K, src);
+  return hipGetLastError();
+}
+
+template <int MAXS, bool SAVE>
+static hipError_t cols_x3_t(const TileParams& p, const LsState& st, int n0, int K, int grid, hipStream_t s) {
+  static bool attr = false;
+  if (!attr) {
+    hipError_t e = hipFuncSetAttribute((const void*)ls_cols_x3_kernel<MAXS, SAVE>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, max_lds_bytes());
+    if (e != hipSuccess) return e;
+    attr = true;
+  }
+  hipLaunchKernelGGL((ls_cols_x3_kernel<MAXS, SAVE>), dim3(grid), dim3(kX3ColsThreads),
+                     (size_t)ls_cols_x3_lds_bytes(p.W), s, p, st, n0, K);
+  return hipGetLastError();
+}
+
+// Toeplitz operands in registers: 6 k-steps cover W <= 88, 8 cover W <= 120
+hipError_t launch_rows_x3(const TileParams& p, const LsState& st, int n0, int K, int src, int grid, hipStream_t s) {
+  return x3_steps(p.W) <= 6 ? rows_x3_t<6>(p, st, n0, K, src, grid, s) : rows_x3_t<8>(p, st, n0, K, src, grid, s);
+}
+
+hipError_t launch_cols_x3(const TileParams& p, const LsState& st, int n0, int K, bool save, int grid, hipStream_t s) {
+  if (x3_steps(p.W) <= 6)
+    return save ? cols_x3_t<6, true>(p, st, n0, K, grid, s) : cols_x3_t<6, false>(p, st, n0, K, grid, s);
+  return save ? cols_x3_t<8, true>(p, st, n0, K, grid, s) : cols_x3_t<8, false>(p, st, n0, K, grid, s);
+}
+
+}  // namespace bfgpa

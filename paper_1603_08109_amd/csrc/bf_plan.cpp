@@ -680,6 +680,7 @@ static void fill_common(const bf_plan_t* pl, TileParams& tp) {
   tp.rg_tab = p.kernel == BF_GAUSS_REC ? pl->d_const + 3 * pl->tab_stride + 2 * ntapr : nullptr;
   tp.saved_plane = (int64_t)p.height * p.width;
   tp.mirror = (p.flags & BF_FLAG_MIRROR) ? 1 : 0;
+  tp.mfma_x3 = (p.flags & BF_FLAG_MFMA_FP32) ? 0 : 1;
 }
 }  // namespace bfgpa
 
