@@ -1,0 +1,111 @@
+"""The bilateral filter and its Gaussian-polynomial approximation on video
+and volume data, in float64.  Test infrastructure only.
+
+Sec. 1 and Sec. 5 note that the filter extends directly to video and volume
+data: the domain becomes I in Z^3 and the spatial kernel w lives on a cube
+Omega = [-W, W]^3.  With the same separable kernels, w(a, b, c) =
+w1(a) w1(b) w1(c) (the box of eq. spatial_kernel2 or the Gaussian of eq.
+spatial_kernel1 along each axis), eq. (BF), eq. (GPA) and Algorithm 2 keep
+their form; only the spatial filtering of eq. (spatialFiltering) runs over
+three axes.  The normalised centre weight of Prop. (accuracy) becomes
+w(0) = (w1(0) / sum_a w1(a))^3.
+
+Volumes are (D, H, W) arrays (slice, row, column); the border reading is
+the zero extension of ``oracle.bf``.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from .bf import range_kernel
+from .gpa import phi
+
+
+def _shifted(pad: np.ndarray, W: int, a: int, b: int, c: int, shape) -> np.ndarray:
+    D, H, Wd = shape
+    return pad[W - a:W - a + D, W - b:W - b + H, W - c:W - c + Wd]
+
+
+def direct_bf(f: np.ndarray, w1: np.ndarray, sigma_r: float) -> np.ndarray:
+    """eq. (BF) on a volume with w = w1 x w1 x w1."""
+    f = np.asarray(f, dtype=np.float64)
+    W = len(w1) // 2
+    pad = np.pad(f, W)
+    valid = np.pad(np.ones_like(f), W)
+    num = np.zeros_like(f)
+    den = np.zeros_like(f)
+    for a in range(-W, W + 1):
+        for b in range(-W, W + 1):
+            for c in range(-W, W + 1):
+                sh = _shifted(pad, W, a, b, c, f.shape)
+                ok = _shifted(valid, W, a, b, c, f.shape)
+                k = w1[W + a] * w1[W + b] * w1[W + c] * range_kernel(sh - f, sigma_r) * ok
+                num += k * sh
+                den += k
+    return num / den
+
+
+def gpa_pairwise(f: np.ndarray, w1: np.ndarray, sigma_r: float, N: int, center: float) -> np.ndarray:
+    """eq. (GPA) on the centred volume, pair by pair."""
+    h = np.asarray(f, dtype=np.float64) - center
+    W = len(w1) // 2
+    pad = np.pad(h, W)
+    valid = np.pad(np.ones_like(h), W)
+    num = np.zeros_like(h)
+    den = np.zeros_like(h)
+    for a in range(-W, W + 1):
+        for b in range(-W, W + 1):
+            for c in range(-W, W + 1):
+                sh = _shifted(pad, W, a, b, c, h.shape)
+                ok = _shifted(valid, W, a, b, c, h.shape)
+                k = w1[W + a] * w1[W + b] * w1[W + c] * phi(sh, h, sigma_r, N) * ok
+                num += k * sh
+                den += k
+    return num / den + center
+
+
+def spatial_filter(F: np.ndarray, w1: np.ndarray) -> np.ndarray:
+    """eq. (spatialFiltering) with w = w1 x w1 x w1 over the zero-extended
+    volume: one shifted sum per axis."""
+    out = np.asarray(F, dtype=np.float64)
+    W = len(w1) // 2
+    for axis in range(3):
+        L = out.shape[axis]
+        acc = np.zeros_like(out)
+        for a in range(-W, W + 1):
+            lo, hi = max(0, a), min(L, L + a)
+            if hi <= lo:
+                continue
+            dst = [slice(None)] * 3
+            src = [slice(None)] * 3
+            dst[axis] = slice(lo, hi)
+            src[axis] = slice(lo - a, hi - a)
+            acc[tuple(dst)] += w1[W + a] * out[tuple(src)]
+        out = acc
+    return out
+
+
+def gpa_alg2(f: np.ndarray, w1: np.ndarray, sigma_r: float, N: int, T: float) -> np.ndarray:
+    """Algorithm 2 (Sec. 3) on a volume: the same recursions, filtering over
+    three axes."""
+    f = np.asarray(f, dtype=np.float64)
+    h = f - T
+    F = np.exp(-(h * h) / (2.0 * sigma_r * sigma_r))
+    G = np.ones_like(f)
+    P = np.zeros_like(f)
+    Q = np.zeros_like(f)
+    Hh = h / sigma_r
+    Fbar = spatial_filter(F, w1)
+    for n in range(1, N + 1):
+        Q = Q + G * Fbar
+        F = Hh * F
+        Fbar = spatial_filter(F, w1)
+        P = P + G * Fbar
+        G = Hh * G / n
+    return sigma_r * (P / Q) + T
+
+
+def w0(w1: np.ndarray) -> float:
+    """Normalised centre weight of w1 x w1 x w1."""
+    w1 = np.asarray(w1, dtype=np.float64)
+    return float((w1[len(w1) // 2] / w1.sum()) ** 3)
