@@ -92,6 +92,7 @@ extern "C" {
 #define BF_PATH_STREAMED   1  /* blocks of orders through device memory */
 #define BF_PATH_TILE_MFMA  2  /* one fused launch, FIR passes on the matrix cores */
 #define BF_PATH_RECURSIVE  3  /* BF_GAUSS_REC: row and column recursions per block of orders */
+#define BF_PATH_VOLUME     4  /* bf_plan_volume: row, column and depth passes per block of orders */
 
 typedef struct bf_params {
   int32_t kernel;    /* BF_BOX, BF_GAUSS or BF_GAUSS_REC */
@@ -164,6 +165,25 @@ int bf_plan_clone_workspace(const bf_plan_t* plan, bf_plan_t** out);
  * launch fails. */
 int bf_forward(const bf_plan_t* plan, const float* in, int64_t in_pitch,
                float* out, int64_t out_pitch, float* saved, void* stream);
+
+/* Video and volume data, the extension named in Sec. 1 and Sec. 5: D slices
+ * of height x width (p->height, p->width), the kernel w1 x w1 x w1 on the cube
+ * [-W, W]^3 (box or truncated Gaussian, W <= 32), zero extension, Algorithm 2
+ * with three-axis filtering; N from the rule of bf_plan with the centre weight
+ * (w1(0) / sum w1)^3.  Plain forward filter only: BF_FLAG_GRAD, JOINT, MIRROR,
+ * TILE_VALU and TILE_MFMA return BF_EUNSUPPORTED, as does BF_GAUSS_REC.
+ * Allocates about 80 bytes per voxel.  *out is owned by the caller
+ * (bf_destroy). */
+int bf_plan_volume(const bf_params* p, int32_t depth, bf_plan_t** out);
+
+/* Filter a volume planned by bf_plan_volume.
+ *   in   device, depth slices of height x width float32, rows of pitch in_pitch
+ *        elements, slice d starting at in + d * height * in_pitch (slices stacked)
+ *   out  device, same layout with pitch out_pitch; must not alias `in`
+ * Errors: BF_EINVAL for NULL pointers, pitches < width, aliasing, or a plan
+ * not from bf_plan_volume; BF_EHIP if a launch fails. */
+int bf_forward_volume(const bf_plan_t* plan, const float* in, int64_t in_pitch, float* out, int64_t out_pitch,
+                      void* stream);
 
 /* Cross (joint) bilateral filter, the extension named in Sec. 1 and Sec. 5:
  * out(i) = sum_j w(j) g(h(i-j) - h(i)) f(i-j) / sum_j w(j) g(h(i-j) - h(i)),

@@ -40,6 +40,7 @@ BF_PATH_TILE = 0
 BF_PATH_STREAMED = 1
 BF_PATH_TILE_MFMA = 2
 BF_PATH_RECURSIVE = 3
+BF_PATH_VOLUME = 4
 
 
 class bf_params(C.Structure):
@@ -82,6 +83,8 @@ SIGNATURES = {
     "bf_plan_get_info": (C.c_int, [C.c_void_p, C.POINTER(bf_plan_info)]),
     "bf_destroy": (C.c_int, [C.c_void_p]),
     "bf_plan_clone_workspace": (C.c_int, [C.c_void_p, C.POINTER(C.c_void_p)]),
+    "bf_plan_volume": (C.c_int, [C.POINTER(bf_params), C.c_int32, C.POINTER(C.c_void_p)]),
+    "bf_forward_volume": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_int64, C.c_void_p]),
     "bf_forward": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_int64, C.c_void_p,
                              C.c_void_p]),
     "bf_forward_joint": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_int64, C.c_void_p,

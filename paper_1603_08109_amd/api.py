@@ -20,7 +20,7 @@ _KERNELS = {"box": L.BF_BOX, "gauss": L.BF_GAUSS, "gaussian": L.BF_GAUSS, "gauss
 _ENGINES = {None: 0, "auto": 0, "valu": L.BF_FLAG_TILE_VALU, "mfma": L.BF_FLAG_TILE_MFMA,
             "streamed": L.BF_FLAG_STREAMED}
 PATHS = {L.BF_PATH_TILE: "valu", L.BF_PATH_STREAMED: "streamed", L.BF_PATH_TILE_MFMA: "mfma",
-         L.BF_PATH_RECURSIVE: "recursive"}
+         L.BF_PATH_RECURSIVE: "recursive", L.BF_PATH_VOLUME: "volume"}
 
 
 @dataclass
@@ -94,6 +94,48 @@ def _check_image(t: torch.Tensor, H: int, W: int, name: str):
         raise ValueError(f"{name} must have shape ({H}, {W}), got {tuple(t.shape)}")
     if t.stride(1) != 1:
         raise ValueError(f"{name} rows must be contiguous")
+
+
+class VolumePlan:
+    """A volume (or video) of `depth` slices of height x width (bf_plan_volume /
+    bf_forward_volume); the kernel is w1 x w1 x w1."""
+
+    def __init__(self, kernel: str, sigma_r: float, depth: int, height: int, width: int, **kw):
+        self._lib = L.load()
+        self.kernel = kernel
+        self.depth, self.height, self.width = int(depth), int(height), int(width)
+        self.params = make_params(kernel, sigma_r, height=height, width=width, **kw)
+        h = C.c_void_p()
+        st = L.check(self._lib.bf_plan_volume(C.byref(self.params), self.depth, C.byref(h)), "bf_plan_volume")
+        self._h = h
+        info = L.bf_plan_info()
+        L.check(self._lib.bf_plan_get_info(self._h, C.byref(info)), "bf_plan_get_info")
+        self.info = _info(info, st)
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            self._lib.bf_destroy(h)
+            self._h = None
+
+    def forward(self, inp: torch.Tensor, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+        """`inp`: (depth, height, width) float32 CUDA tensor with contiguous rows and
+        slices stacked (stride(0) == height * stride(1))."""
+        D, H, W = self.depth, self.height, self.width
+        for t, name in ((inp, "input"), (out, "output")):
+            if t is None:
+                continue
+            if not isinstance(t, torch.Tensor) or t.device.type != "cuda" or t.dtype != torch.float32:
+                raise TypeError(f"{name} must be a float32 CUDA (HIP) tensor")
+            stacked = D == 1 or t.stride(0) == H * t.stride(1)  # a size-1 dim's stride is arbitrary
+            if tuple(t.shape) != (D, H, W) or t.stride(2) != 1 or not stacked:
+                raise ValueError(f"{name} must be ({D}, {H}, {W}) with stacked slices, got {tuple(t.shape)}")
+        if out is None:
+            out = torch.empty_like(inp)
+        L.check(self._lib.bf_forward_volume(self._h, C.c_void_p(inp.data_ptr()), inp.stride(1),
+                                            C.c_void_p(out.data_ptr()), out.stride(1), _stream_handle(stream)),
+                "bf_forward_volume")
+        return out
 
 
 class Plan:

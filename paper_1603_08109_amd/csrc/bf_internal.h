@@ -134,6 +134,20 @@ int64_t ls_cols_x3_lds_bytes(int W);
 hipError_t launch_rows_x3(const TileParams& p, const LsState& st, int n0, int K, int src, int grid, hipStream_t s);
 hipError_t launch_cols_x3(const TileParams& p, const LsState& st, int n0, int K, bool save, int grid, hipStream_t s);
 
+// pieces of the streamed sequence (an image of p.H rows)
+hipError_t ls_launch_init(const TileParams& p, const LsState& st, hipStream_t s);
+hipError_t ls_launch_rows(const TileParams& p, const LsState& st, int n0, int K, int src, hipStream_t s);
+hipError_t ls_launch_final(const TileParams& p, const LsState& st, hipStream_t s);
+
+// Video / volume data: D slices of Hs x Wd stacked as one image of D Hs rows.
+constexpr int kVolMaxW = 32;
+struct VolBufs {
+  float* G[kLsBlock];  // per order of a block: the row- and column-filtered volume
+};
+int64_t vol_state_bytes(int D, int Hs, int Wd, int W);
+LsState vol_layout(void* base, int D, int Hs, int Wd, int W, VolBufs* g);
+hipError_t launch_forward_vol(const TileParams& p, const LsState& st, const VolBufs& g, int D, int Hs, hipStream_t s);
+
 // fused Gaussian tile with both FIR passes on the matrix cores (W <= 45)
 hipError_t launch_fused_mfma(const TileParams& p, bool save, hipStream_t s);
 bool fused_mfma_supported(int W);
@@ -207,6 +221,8 @@ struct bf_plan {
   bool ls;              // large-support path (support too wide for the fused tiles)
   bool mfma;            // fused matrix-core tile (Gaussian)
   bool rec;             // recursive Gaussian (its state in d_ls / ls_state)
+  int depth;            // > 0: a volume plan of depth slices (its state in d_ls / ls_state, vol)
+  bfgpa::VolBufs vol;
   void* d_ls;           // its device state
   bfgpa::LsState ls_state;
   bool bls;             // streamed adjoint

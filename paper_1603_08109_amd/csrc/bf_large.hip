@@ -780,4 +780,39 @@ hipError_t launch_forward_ls(const TileParams& p, const LsState& st, bool save, 
   return hipGetLastError();
 }
 
+// Pieces of the streamed sequence for the volume path (bf_volume.hip): the
+// lift, the row pass of one block of orders, and eq. (PbyQ).
+hipError_t ls_launch_init(const TileParams& p, const LsState& st, hipStream_t s) {
+  const int64_t npx = (int64_t)p.H * p.Wd;
+  const int g1 = (int)std::min<int64_t>((npx + kThreads - 1) / kThreads, 4096);
+  hipLaunchKernelGGL(ls_init_kernel, dim3(g1), dim3(kThreads), 0, s, p, st);
+  return hipGetLastError();
+}
+
+hipError_t ls_launch_rows(const TileParams& p, const LsState& st, int n0, int K, int src, hipStream_t s) {
+  const int grow = ((p.H + kLsRows - 1) / kLsRows) * ((p.Wd + kLsCols - 1) / kLsCols);
+  if (p.kt != BF_BOX && p.mfma_x3 && ls_x3_supported(p.W) && ls_rows_x3_lds_bytes(p.W) <= max_lds_bytes())
+    return launch_rows_x3(p, st, n0, K, src, grow, s);
+  const size_t rlm = (size_t)ls_rows_mfma_lds_bytes(p.W);
+  if (p.kt != BF_BOX && ls_rows_mfma_fits(p.W) && rlm <= (size_t)max_lds_bytes()) {
+    hipError_t e = hipFuncSetAttribute((const void*)ls_rows_mfma_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       max_lds_bytes());
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(ls_rows_mfma_kernel, dim3(grow), dim3(kThreads), rlm, s, p, st, n0, K, src);
+    return hipGetLastError();
+  }
+  auto rk = p.kt == BF_BOX ? ls_rows_kernel<BF_BOX> : ls_rows_kernel<BF_GAUSS>;
+  hipError_t e = hipFuncSetAttribute((const void*)rk, hipFuncAttributeMaxDynamicSharedMemorySize, max_lds_bytes());
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(rk, dim3(grow), dim3(kThreads), (size_t)ls_rows_lds_bytes(p.W), s, p, st, n0, K, src);
+  return hipGetLastError();
+}
+
+hipError_t ls_launch_final(const TileParams& p, const LsState& st, hipStream_t s) {
+  const int64_t npx = (int64_t)p.H * p.Wd;
+  const int g1 = (int)std::min<int64_t>((npx + kThreads - 1) / kThreads, 4096);
+  hipLaunchKernelGGL(ls_final_kernel, dim3(g1), dim3(kThreads), 0, s, p, st);
+  return hipGetLastError();
+}
+
 }  // namespace bfgpa

@@ -148,13 +148,14 @@ static int normalise(const bf_params* in, bf_params* p) {
 }
 
 // Order and bounds for normalised parameters.
-static int plan_order(const bf_params* p, bf_plan_info* info) {
+// dims: 2 for images, 3 for volumes (the centre weight of w1 x w1 x w1).
+static int plan_order(const bf_params* p, bf_plan_info* info, int dims = 2) {
   std::memset(info, 0, sizeof(*info));
   std::vector<double> t = taps1d(p->kernel, p->sigma_s, p->W);
   double s = 0.0;
   for (double v : t) s += v;
   info->W = p->W;
-  info->w0 = p->kernel == BF_GAUSS_REC ? rg_w0(p->sigma_s) : (t[p->W] * t[p->W]) / (s * s);
+  info->w0 = p->kernel == BF_GAUSS_REC ? rg_w0(p->sigma_s) : std::pow(t[p->W] / s, (double)dims);
   info->eps = info->w0 * p->delta / (2.0 * p->T + p->delta);
   info->lambda = (p->T / p->sigma_r) * (p->T / p->sigma_r);
   // float32 range: exp(-x^2/2) must stay a normal float for |x| <= T/sigma_r
@@ -635,8 +636,9 @@ int bf_plan_clone_workspace(const bf_plan_t* plan, bf_plan_t** out) {
   if (!plan || !out) return fail(BF_EINVAL, "NULL argument");
   *out = nullptr;
   bf_params p = plan->p;  // normalised parameters: the same N, W and tables
-  return bf_plan(&p, out);
+  return plan->depth > 0 ? bf_plan_volume(&p, plan->depth, out) : bf_plan(&p, out);
 }
+
 
 int bf_plan_get_info(const bf_plan_t* plan, bf_plan_info* out) {
   if (!plan || !out) return fail(BF_EINVAL, "NULL argument");
@@ -692,6 +694,7 @@ int bf_forward(const bf_plan_t* pl, const float* in, int64_t in_pitch, float* ou
   if (in_pitch < pl->p.width || out_pitch < pl->p.width) return fail(BF_EINVAL, "pitch smaller than width");
   if ((const void*)in == (const void*)out) return fail(BF_EINVAL, "in and out must not alias");
   if (pl->p.flags & BF_FLAG_JOINT) return fail(BF_EINVAL, "a cross-filter plan runs with bf_forward_joint");
+  if (pl->depth > 0) return fail(BF_EINVAL, "a volume plan runs with bf_forward_volume");
   TileParams tp;
   std::memset(&tp, 0, sizeof(tp));
   fill_common(pl, tp);
@@ -717,6 +720,77 @@ int bf_forward(const bf_plan_t* pl, const float* in, int64_t in_pitch, float* ou
     e = launch_forward(tp, pl->variant, acc64, saved != nullptr, (hipStream_t)stream);
   }
   if (e != hipSuccess) return hip_fail(e, "forward launch");
+  return BF_OK;
+}
+
+int bf_plan_volume(const bf_params* in, int32_t depth, bf_plan_t** out) {
+  if (!out) return fail(BF_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (depth <= 0) return fail(BF_EINVAL, "depth must be > 0");
+  bf_params p;
+  int st = normalise(in, &p);
+  if (st < 0) return st;
+  if (p.height <= 0 || p.width <= 0) return fail(BF_EINVAL, "height and width must be > 0");
+  if (p.kernel == BF_GAUSS_REC) return fail(BF_EUNSUPPORTED, "volumes take the box or the truncated Gaussian");
+  if (p.flags & (BF_FLAG_GRAD | BF_FLAG_JOINT | BF_FLAG_MIRROR | BF_FLAG_TILE_VALU | BF_FLAG_TILE_MFMA))
+    return fail(BF_EUNSUPPORTED, "volumes: plain forward filter, zero border, streamed engine only");
+  if (p.W > kVolMaxW) return fail(BF_EUNSUPPORTED, "volumes: W <= 32");
+  if ((int64_t)depth * p.height > (1 << 30) / std::max(1, p.width))
+    return fail(BF_EUNSUPPORTED, "volume too large");
+  bf_plan_info info;
+  const int ost = plan_order(&p, &info, 3);
+  if (ost < 0) return ost;
+  bf_plan_t* pl = new (std::nothrow) bf_plan_t();
+  if (!pl) return fail(BF_ENOMEM, "host allocation failed");
+  pl->p = p;
+  pl->info = info;
+  pl->info.path = BF_PATH_VOLUME;
+  pl->variant = -1;
+  pl->bvariant = -1;
+  pl->depth = depth;
+  hipGetDevice(&pl->device);
+  int64_t stride = 0, ntapr = 0;
+  std::vector<float> h = const_tables(p, info, &stride, &ntapr);
+  pl->tab_stride = stride;
+  const size_t bytes = h.size() * sizeof(float);
+  hipError_t e = hipMalloc(&pl->d_const, bytes);
+  if (e != hipSuccess) { delete pl; return fail(BF_ENOMEM, "hipMalloc tables failed"); }
+  e = hipMemcpy(pl->d_const, h.data(), bytes, hipMemcpyHostToDevice);
+  if (e != hipSuccess) { hipFree(pl->d_const); delete pl; return hip_fail(e, "hipMemcpy tables"); }
+  const int64_t vb = vol_state_bytes(depth, p.height, p.width, p.W);
+  e = hipMalloc(&pl->d_ls, vb);
+  if (e == hipSuccess) {
+    e = hipMemset(pl->d_ls, 0, vb);  // zero rows around the row-filtered images
+    if (e != hipSuccess) hipFree(pl->d_ls);
+  }
+  if (e != hipSuccess) {
+    hipFree(pl->d_const);
+    delete pl;
+    return e == hipErrorOutOfMemory ? fail(BF_ENOMEM, "hipMalloc volume state failed") : hip_fail(e, "volume state");
+  }
+  pl->ls_state = vol_layout(pl->d_ls, depth, p.height, p.width, p.W, &pl->vol);
+  pl->info.workspace_bytes = (int64_t)bytes + vb;
+  *out = pl;
+  if (ost == BF_WNOGUARANTEE) set_error("order below the bound: no +-delta guarantee");
+  return ost;
+}
+
+int bf_forward_volume(const bf_plan_t* pl, const float* in, int64_t in_pitch, float* out, int64_t out_pitch,
+                      void* stream) {
+  if (!pl || !in || !out) return fail(BF_EINVAL, "NULL plan or volume pointer");
+  if (pl->depth <= 0) return fail(BF_EINVAL, "plan was not built with bf_plan_volume");
+  if (in_pitch < pl->p.width || out_pitch < pl->p.width) return fail(BF_EINVAL, "pitch smaller than width");
+  if ((const void*)in == (const void*)out) return fail(BF_EINVAL, "in and out must not alias");
+  TileParams tp;
+  std::memset(&tp, 0, sizeof(tp));
+  fill_common(pl, tp);
+  tp.H = pl->depth * pl->p.height;  // slices stacked as one image
+  tp.in = in;
+  tp.in_pitch = in_pitch;
+  tp.out = out;
+  tp.out_pitch = out_pitch;
+  hipError_t e = launch_forward_vol(tp, pl->ls_state, pl->vol, pl->depth, pl->p.height, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "volume forward launch");
   return BF_OK;
 }
 

@@ -1,0 +1,134 @@
+// Video and volume data (the extension Sec. 1 and Sec. 5 name): D slices of
+// Hs x Wd, kernel w1 x w1 x w1 on the cube [-W, W]^3, zero extension.
+// Algorithm 2 is unchanged; only the spatial filtering runs over three axes.
+//
+// The slices are stacked as one image of D Hs rows (voxel (d, r, c) at row
+// d Hs + r), so the lift, the row pass of each block of 16 orders and
+// eq. (PbyQ) are the streamed image kernels as they are.  Per block:
+//   vol_cols  : the column FIR inside each slice (taps that would cross a
+//               slice boundary are dropped), 64 x 64 tiles staged in LDS,
+//               writing the row- and column-filtered volume of each order;
+//   vol_depth : the FIR across slices at each (r, c), folded into the
+//               float64 sums of eqs. (P), (Q) of kVolDepth voxels per thread.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdint>
+#include <cstring>
+
+#include "bf_device.h"
+#include "bf_internal.h"
+
+namespace bfgpa {
+
+constexpr int kVolTile = 64;   // rows and columns of a column-pass tile
+constexpr int kVolDepth = 8;   // voxels per thread along the depth axis
+
+// Column FIR inside each slice for orders n0 .. n0 + K - 1.  Thread: column
+// c = tid % 64 of the tile, output rows 16 (tid / 64) .. + 15.
+__global__ __launch_bounds__(256) void vol_cols_kernel(TileParams p, LsState st, VolBufs g, int K, int Hs) {
+  extern __shared__ float lds[];
+  const int W = p.W;
+  const int rows = kVolTile + 2 * W;
+  const int tiles_x = (p.Wd + kVolTile - 1) / kVolTile;
+  const int ty = blockIdx.x / tiles_x, tx = blockIdx.x - (blockIdx.x / tiles_x) * tiles_x;
+  const int R0 = ty * kVolTile, c0 = tx * kVolTile;
+  const int c = threadIdx.x & 63;
+  const int rg = threadIdx.x >> 6;
+  const float* tz = p.taps + kTapPad;  // tz[a + W] = w1(a)
+  for (int k = 0; k < K; ++k) {
+    __syncthreads();  // the previous order's reads are done
+    // stage rows R0 - W .. R0 + 63 + W (row-filtered images carry W zero rows above)
+    const float* Hk = st.H[k];
+    for (int i = rg; i < rows; i += 4) {
+      const int Rp = R0 + i;  // padded row = stacked row R0 - W + i, plus W
+      lds[i * kVolTile + c] = (c0 + c < p.Wd) ? Hk[(int64_t)Rp * st.pitch + c0 + c] : 0.f;
+    }
+    __syncthreads();
+    float* Gk = g.G[k];
+#pragma unroll 4
+    for (int j = 0; j < 16; ++j) {
+      const int R = R0 + 16 * rg + j;  // stacked row
+      if (R >= p.H || c0 + c >= p.Wd) continue;
+      const int d0 = (R / Hs) * Hs;  // first row of this slice
+      const int lo = max(-W, d0 - R), hi = min(W, d0 + Hs - 1 - R);
+      const float* col = lds + (R - R0 + W) * kVolTile + c;
+      float acc = 0.f;
+      for (int a = lo; a <= hi; ++a) acc += tz[a + W] * col[a * kVolTile];
+      Gk[(int64_t)R * p.Wd + c0 + c] = acc;
+    }
+  }
+}
+
+// FIR across slices and the fold into eqs. (P), (Q): thread q of the slice
+// plane, voxels at depths d0 .. d0 + kVolDepth - 1.
+__global__ __launch_bounds__(256) void vol_depth_kernel(TileParams p, LsState st, VolBufs g, int n0, int K, int Hs,
+                                                        int D) {
+  const int64_t plane = (int64_t)Hs * p.Wd;
+  const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int d0 = blockIdx.y * kVolDepth;
+  const bool live = q < plane;
+  const int nok = live ? std::min(kVolDepth, D - d0) : 0;
+  const int W = p.W;
+  const float* tz = p.taps + kTapPad;
+  LsPix<kVolDepth, false> px;
+  const int64_t i0 = (int64_t)d0 * plane + (live ? q : 0);
+  px.load(st, i0, plane, nok);
+  for (int k = 0; k < K; ++k) {
+    const float* Gk = g.G[k] + (live ? q : 0);
+    const int n = n0 + k;
+    const float in1 = p.inv_tab[n + 1];
+#pragma unroll
+    for (int t = 0; t < kVolDepth; ++t) {
+      const int d = d0 + t;
+      float acc = 0.f;
+      if (t < nok) {
+        const int lo = max(-W, -d), hi = min(W, D - 1 - d);
+        for (int a = lo; a <= hi; ++a) acc += tz[a + W] * Gk[(int64_t)(d + a) * plane];
+      }
+      px.fold(t, n, p.N, acc, in1);
+    }
+  }
+  px.store(st, i0, plane, nok);
+}
+
+int64_t vol_state_bytes(int D, int Hs, int Wd, int W) {
+  const int64_t H = (int64_t)D * Hs;
+  return ls_state_bytes((int)H, Wd, W, false) + kLsBlock * (H * Wd * 4 + 256);
+}
+
+LsState vol_layout(void* base, int D, int Hs, int Wd, int W, VolBufs* g) {
+  const int H = D * Hs;
+  LsState st = ls_layout(base, H, Wd, W, false);
+  char* q = (char*)base + ls_state_bytes(H, Wd, W, false);
+  for (int k = 0; k < kLsBlock; ++k) {
+    g->G[k] = (float*)q;
+    q += ((int64_t)H * Wd * 4 + 255) & ~255LL;
+  }
+  return st;
+}
+
+hipError_t launch_forward_vol(const TileParams& p, const LsState& st, const VolBufs& g, int D, int Hs,
+                              hipStream_t s) {
+  if (p.H <= 0 || p.Wd <= 0) return hipSuccess;
+  if (p.W > kVolMaxW || p.H != D * Hs) return hipErrorInvalidValue;
+  hipError_t e = ls_launch_init(p, st, s);
+  if (e != hipSuccess) return e;
+  const int tiles = ((p.H + kVolTile - 1) / kVolTile) * ((p.Wd + kVolTile - 1) / kVolTile);
+  const size_t clds = (size_t)(kVolTile + 2 * p.W) * kVolTile * 4;
+  const dim3 gdep((unsigned)((int64_t)Hs * p.Wd + 255) / 256, (D + kVolDepth - 1) / kVolDepth);
+  int src = 0;
+  for (int n0 = 0; n0 <= p.N; n0 += kLsBlock) {
+    const int K = std::min(kLsBlock, p.N + 1 - n0);
+    e = ls_launch_rows(p, st, n0, K, src, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(vol_cols_kernel, dim3(tiles), dim3(256), clds, s, p, st, g, K, Hs);
+    hipLaunchKernelGGL(vol_depth_kernel, gdep, dim3(256), 0, s, p, st, g, n0, K, Hs, D);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    src ^= 1;
+  }
+  return ls_launch_final(p, st, s);
+}
+
+}  // namespace bfgpa

@@ -143,3 +143,12 @@ def test_recursive_gaussian_planning():
         P.bf_order("gauss_rec", 30.0, sigma_s=3.0, height=9000, width=64)   # lines longer than 8192
     assert e.value.code == L.BF_EUNSUPPORTED
     assert P.bf_order("gauss_rec", 30.0, sigma_s=3.0, height=64, width=8192).path == L.BF_PATH_RECURSIVE
+
+
+def test_volume_planning_weight():
+    # host-side check through the oracle: the 3-D centre weight and its order
+    from oracle import volume as V
+    w1 = K.taps1d("gauss", sigma_s=2.0)
+    assert V.w0(w1) == pytest.approx((w1[len(w1) // 2] / w1.sum()) ** 3, rel=1e-12)
+    assert O.order_for_delta(1e-3, V.w0(w1), 127.5, 30.0) >= O.order_for_delta(1e-3, K.w0("gauss", sigma_s=2.0),
+                                                                                  127.5, 30.0)
