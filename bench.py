@@ -434,6 +434,21 @@ def main():
                               "per_setting": rl}
         print(f"# recursive {extra['recursive']}", file=sys.stderr, flush=True)
 
+        # video/volume extension: 64 frames of 1024^2 (67 Mvoxels), box W = 3 and Gaussian sigma_s = 1.5
+        vd, vh, vw = 64, 1024, 1024
+        vx = torch.tensor(np.stack([synthimg.gen2(vh, vw, 3200 + d) for d in range(vd)]), dtype=torch.float32,
+                          device=dev)
+        vout = torch.empty_like(vx)
+        vl = {}
+        for kind, kw, sr in [("box", dict(W=3), 30.0), ("gauss", dict(sigma_s=1.5), 30.0)]:
+            vp = P.VolumePlan(kind, sr, vd, vh, vw, **kw)
+            ms_v = time_launches(lambda: vp.forward(vx, out=vout), stream, 1, max(1, a.steps // 2), torch)
+            vl[setting_name(kind, kw, sr)] = {"N": vp.info.N, "ms": round(ms_v, 3),
+                                              "mvox_s": round(vd * vh * vw / ms_v / 1e3, 1)}
+        extra["volume"] = {"workload": f"{vd}x{vh}x{vw} gen2 frames, kernel w1 x w1 x w1", "per_setting": vl}
+        print(f"# volume {extra['volume']}", file=sys.stderr, flush=True)
+        del vx, vout
+
     cpu = None
     if not a.no_cpu_baseline:
         from oracle import gpa as G

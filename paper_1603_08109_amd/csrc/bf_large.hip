@@ -562,6 +562,187 @@ __global__ __launch_bounds__(kStripThreads) void ls_box_strip_kernel(TileParams 
   }
 }
 
+// Wider strips for the forward without saved state: 512 strip columns, two
+// per thread, so the 2W halo columns are shared by 512 - 2W outputs instead
+// of 256 - 2W.  The same float64 column sums and prefix windows; the fold
+// keeps float32 partial sums of eqs. (P), (Q) and adds them into the float64
+// totals every 8 orders, as the fused tiles do.
+constexpr int kStrip2Cols = 512;
+constexpr int kStrip2Pitch = 548;  // doubles per order: 512 columns swizzled, the total, 16-byte rows
+
+__host__ __device__ inline int strip2_cols(int W) { return kStrip2Cols - 2 * W; }
+
+// Column s of a prefix row sits at s + 2 (s / 32): a lane's 8 consecutive
+// columns stay contiguous, and the 16 lanes of a 16-byte read phase land on
+// distinct banks.
+__device__ __forceinline__ int sw2(int s) { return s + 2 * (s >> 5); }
+
+__global__ __launch_bounds__(kStripThreads) void ls_box_strip2_kernel(TileParams p, LsState st, int n0, int K,
+                                                                      int src, int seg_rows) {
+  extern __shared__ double dlds[];
+  double* Cs = dlds;  // kLsBlock x kStrip2Pitch; order k's window sums then overwrite its row
+  const int W = p.W, L = 2 * W + 1;
+  const int OC = strip2_cols(W);
+  const int nstrips = (p.Wd + OC - 1) / OC;
+  const int strip = blockIdx.x % nstrips, seg = blockIdx.x / nstrips;
+  const int c0 = strip * OC;
+  const int r_lo = seg * seg_rows, r_hi = min(r_lo + seg_rows, p.H);
+  const int t = threadIdx.x;
+  const int lane = t & 63, wv = t >> 6;
+  // this thread's strip columns 2t, 2t + 1 (image columns c0 - W + 2t + j)
+  int gcs[2];
+  bool col_ok[2], central[2], pix[2];
+  int64_t pio[2];
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    const int sc = 2 * t + j, gc = c0 - W + sc;
+    col_ok[j] = p.mirror || (gc >= 0 && gc < p.Wd);
+    gcs[j] = p.mirror ? reflect_index(gc, p.Wd) : gc;
+    central[j] = sc >= W && sc < W + OC && gc < p.Wd;
+    pix[j] = central[j];
+    pio[j] = gc;  // output column of this strip column when central
+  }
+  const float* Fin = st.F[src];
+  float* Fout = st.F[src ^ 1];
+  double C[kLsBlock][2];
+  float in1[kLsBlock];
+#pragma unroll
+  for (int k = 0; k < kLsBlock; ++k) {
+    C[k][0] = C[k][1] = 0.0;
+    in1[k] = p.inv_tab[n0 + min(k, K - 1) + 1];
+  }
+  auto load_row = [&](int q, float (&f)[2], float (&y)[2]) {
+    if (p.mirror) q = reflect_index(q, p.H);
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      f[j] = 0.f;
+      y[j] = 0.f;
+      if (col_ok[j] && q >= 0 && q < p.H) {
+        const int64_t i = (int64_t)q * st.pitch + gcs[j];
+        f[j] = Fin[i];
+        y[j] = st.Y[i];
+      }
+    }
+  };
+  for (int q = r_lo - W; q <= r_lo + W; ++q) {
+    float f[2], y[2];
+    load_row(q, f, y);
+#pragma unroll
+    for (int k = 0; k < kLsBlock; ++k)
+      if (k < K) {
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          C[k][j] += (double)f[j];
+          f[j] *= y[j];
+        }
+      }
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+      if (central[j] && q >= r_lo && q < r_hi) Fout[(int64_t)q * st.pitch + pio[j]] = f[j];
+  }
+  for (int r = r_lo; r < r_hi; ++r) {
+#pragma unroll
+    for (int k = 0; k < kLsBlock; ++k)
+      if (k < K) *(double2*)(Cs + k * kStrip2Pitch + sw2(2 * t)) = make_double2(C[k][0], C[k][1]);
+    float fe[2], ye[2], fl[2], yl[2];  // rows entering and leaving after this output row
+    load_row(r + W + 1, fe, ye);
+    load_row(r - W, fl, yl);
+    lds_barrier();
+    // per order: float64 prefix over the 512 strip columns (lane l scans
+    // columns 8l .. 8l + 7, a DPP wave scan joins the lanes), then the window
+    // sums S(c + 2W + 1) - S(c) of the OC output columns; wave w takes orders
+    // w, w + 4, w + 8, w + 12
+#pragma unroll
+    for (int jj = 0; jj < kLsBlock / 4; ++jj) {
+      double* row = Cs + (wv + 4 * jj) * kStrip2Pitch;
+      double x[8];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const double2 v2 = *(const double2*)(row + sw2(8 * lane) + 2 * u);
+        x[2 * u] = v2.x;
+        x[2 * u + 1] = v2.y;
+      }
+      double pre[8];
+      pre[0] = 0.0;
+#pragma unroll
+      for (int u = 1; u < 8; ++u) pre[u] = pre[u - 1] + x[u - 1];
+      const double tot = pre[7] + x[7];
+      const double incl = wave_scan_incl(tot);
+      const double ex = incl - tot;
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        *(double2*)(row + sw2(8 * lane) + 2 * u) = make_double2(ex + pre[2 * u], ex + pre[2 * u + 1]);
+      if (lane == 63) row[sw2(kStrip2Cols)] = incl;
+      float ov[8];
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        const int c = lane + 64 * i;
+        ov[i] = (float)(row[sw2(min(c + L, kStrip2Cols))] - row[sw2(c)]);
+      }
+      // all of the wave's reads of S precede these writes into the same row
+      float* o = (float*)row;
+#pragma unroll
+      for (int i = 0; i < 8; ++i)
+        if (lane + 64 * i < OC) o[lane + 64 * i] = ov[i];
+    }
+    lds_barrier();
+    // this thread's pixels: output columns 2t + j - W
+    float v[kLsBlock][2];
+#pragma unroll
+    for (int k = 0; k < kLsBlock; ++k)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) v[k][j] = pix[j] ? ((const float*)(Cs + k * kStrip2Pitch))[2 * t + j - W] : 0.f;
+    lds_barrier();
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      if (!pix[j]) continue;
+      const int64_t pi = (int64_t)r * p.Wd + pio[j];
+      float a = st.a[pi], ap = st.ap[pi];
+      const float z = st.z[pi];
+      double P = st.P[pi], Q = st.Q[pi];
+      float p32 = 0.f, q32 = 0.f;
+#pragma unroll
+      for (int k = 0; k < kLsBlock; ++k) {
+        if (k < K) {
+          const int n = n0 + k;
+          if (n < p.N) q32 = fmaf(a, v[k][j], q32);
+          if (n >= 1) p32 = fmaf(ap, v[k][j], p32);
+          ap = a;
+          a *= z * in1[k];
+        }
+        if ((k & 7) == 7) {
+          Q += (double)q32;
+          P += (double)p32;
+          q32 = p32 = 0.f;
+        }
+      }
+      st.a[pi] = a;
+      st.ap[pi] = ap;
+      st.P[pi] = P;
+      st.Q[pi] = Q;
+    }
+    // slide the window to r + 1
+#pragma unroll
+    for (int k = 0; k < kLsBlock; ++k)
+      if (k < K) {
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          C[k][j] += (double)fe[j] - (double)fl[j];
+          fe[j] *= ye[j];
+          fl[j] *= yl[j];
+        }
+      }
+    const int qe = r + W + 1;
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+      if (central[j] && qe >= r_lo && qe < r_hi) Fout[(int64_t)qe * st.pitch + pio[j]] = fe[j];
+  }
+}
+
+int64_t ls_box_strip2_lds_bytes() { return (int64_t)kLsBlock * kStrip2Pitch * 8; }
+
+bool ls_box_strip2_supported(int W) { return strip2_cols(W) >= 128; }
+
 int64_t ls_box_strip_lds_bytes() { return (int64_t)kLsBlock * kStripPitch * 8; }
 
 bool ls_box_strip_supported(int W) { return strip_cols(W) >= 64; }
@@ -680,6 +861,20 @@ hipError_t launch_forward_ls(const TileParams& p, const LsState& st, bool save, 
   const int nseg = std::max(1, std::min((p.H + 31) / 32, slots / nstrips));
   const int strip_seg = (p.H + nseg - 1) / nseg;
   const int gstrip = nstrips * ((p.H + strip_seg - 1) / strip_seg);
+  // forward without saved state and W >= 56: the 512-column strips (the halo
+  // is shared by more outputs, at half the occupancy; 4096^2, sigma_r = 10:
+  // W = 75 15.7 -> 14.4 ms, W = 30 9.3 -> 10.9 ms, crossover near W = 54)
+  const bool strip2 = box_strip && !save && p.W >= 56 && ls_box_strip2_supported(p.W);
+  const int nstrips2 = strip2 ? (p.Wd + strip2_cols(p.W) - 1) / strip2_cols(p.W) : 1;
+  const int slots2 = num_cus() * (int)std::max<int64_t>(1, max_lds_bytes() / ls_box_strip2_lds_bytes());
+  const int nseg2 = std::max(1, std::min((p.H + 31) / 32, slots2 / nstrips2));
+  const int strip2_seg = (p.H + nseg2 - 1) / nseg2;
+  const int gstrip2 = nstrips2 * ((p.H + strip2_seg - 1) / strip2_seg);
+  if (strip2) {
+    e = hipFuncSetAttribute((const void*)ls_box_strip2_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)ls_box_strip2_lds_bytes());
+    if (e != hipSuccess) return e;
+  }
   if (box_strip) {
     e = hipFuncSetAttribute((const void*)ls_box_strip_kernel<false>, hipFuncAttributeMaxDynamicSharedMemorySize,
                             (int)ls_box_strip_lds_bytes());
@@ -720,6 +915,14 @@ hipError_t launch_forward_ls(const TileParams& p, const LsState& st, bool save, 
   int src = 0;
   for (int n0 = 0; n0 <= p.N; n0 += kLsBlock) {
     const int K = std::min(kLsBlock, p.N + 1 - n0);
+    if (strip2) {
+      hipLaunchKernelGGL(ls_box_strip2_kernel, dim3(gstrip2), dim3(kStripThreads), (size_t)ls_box_strip2_lds_bytes(),
+                         s, p, st, n0, K, src, strip2_seg);
+      e = hipGetLastError();
+      if (e != hipSuccess) return e;
+      src ^= 1;
+      continue;
+    }
     if (box_strip) {
       if (save)
         hipLaunchKernelGGL((ls_box_strip_kernel<true>), dim3(gstrip), dim3(kStripThreads), (size_t)ls_box_strip_lds_bytes(),

@@ -113,6 +113,24 @@ __device__ __forceinline__ mf4 mfma_x3(const X3& a, const X3& b, mf4 acc) {
   return acc;
 }
 
+// two independent sums, their six products interleaved so consecutive
+// matrix-core instructions never wait on each other's result
+__device__ __forceinline__ void mfma_x3_pair(const X3& a0, const X3& b0, mf4& acc0, const X3& a1, const X3& b1,
+                                             mf4& acc1) {
+  acc0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0.l, b0.h, acc0, 0, 0, 0);
+  acc1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1.l, b1.h, acc1, 0, 0, 0);
+  acc0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0.m, b0.m, acc0, 0, 0, 0);
+  acc1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1.m, b1.m, acc1, 0, 0, 0);
+  acc0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0.h, b0.l, acc0, 0, 0, 0);
+  acc1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1.h, b1.l, acc1, 0, 0, 0);
+  acc0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0.m, b0.h, acc0, 0, 0, 0);
+  acc1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1.m, b1.h, acc1, 0, 0, 0);
+  acc0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0.h, b0.m, acc0, 0, 0, 0);
+  acc1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1.h, b1.m, acc1, 0, 0, 0);
+  acc0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0.h, b0.h, acc0, 0, 0, 0);
+  acc1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1.h, b1.h, acc1, 0, 0, 0);
+}
+
 bool ls_x3_supported(int W) {
   return kLsRows * x3_rows_pitch(W) <= kX3RowsRegs * kX3RowsThreads;  // W <= 120
 }
@@ -202,8 +220,13 @@ __global__ __launch_bounds__(kX3RowsThreads) void ls_rows_x3_kernel(TileParams p
         av.h = *(const bf8*)(Pl + a);
         av.m = *(const bf8*)(Pl + plane + a);
         av.l = *(const bf8*)(Pl + 2 * plane + a);
-        if (q < S) acc[0] = mfma_x3(av, T[q < MAXS ? q : 0], acc[0]);  // block par at step q
-        if (q >= 1) acc[1] = mfma_x3(av, T[q >= 1 ? q - 1 : 0], acc[1]);    // block par + 2 at step q - 1
+        // block par at step q, block par + 2 at step q - 1
+        if (q >= 1 && q < S)
+          mfma_x3_pair(av, T[q < MAXS ? q : 0], acc[0], av, T[q >= 1 ? q - 1 : 0], acc[1]);
+        else if (q < S)
+          acc[0] = mfma_x3(av, T[q < MAXS ? q : 0], acc[0]);
+        else
+          acc[1] = mfma_x3(av, T[q >= 1 ? q - 1 : 0], acc[1]);
       }
     }
     float* Hk = st.H[k] + (int64_t)W * st.pitch;  // W zero rows above the image
@@ -319,8 +342,13 @@ __global__ __launch_bounds__(kX3ColsThreads) void ls_cols_x3_kernel(TileParams p
           bv.m[i] = m;
           bv.l[i] = l;
         }
-        if (q < S) acc[0] = mfma_x3(T[q < MAXS ? q : 0], bv, acc[0]);  // block rb at step q
-        if (q >= 1) acc[1] = mfma_x3(T[q >= 1 ? q - 1 : 0], bv, acc[1]);    // block rb + 2 at step q - 1
+        // block rb at step q, block rb + 2 at step q - 1
+        if (q >= 1 && q < S)
+          mfma_x3_pair(T[q < MAXS ? q : 0], bv, acc[0], T[q >= 1 ? q - 1 : 0], bv, acc[1]);
+        else if (q < S)
+          acc[0] = mfma_x3(T[q < MAXS ? q : 0], bv, acc[0]);
+        else
+          acc[1] = mfma_x3(T[q >= 1 ? q - 1 : 0], bv, acc[1]);
       }
     }
     const float in1 = p.inv_tab[n + 1];

@@ -251,3 +251,26 @@ def test_clone_workspace_on_two_streams():
             b.forward(x, out=o2, stream=s2)
         torch.cuda.synchronize()
         assert torch.equal(o1, ref) and torch.equal(o2, ref)
+
+
+@pytest.mark.parametrize("W,sr,shape", [(16, 10.0, (150, 700)), (56, 30.0, (120, 1100)), (75, 20.0, (90, 900)),
+                                        (190, 30.0, (60, 500))])
+def test_box_strip_widths_agree(W, sr, shape):
+    # the forward-only strips (512 columns from W = 56, float32 partial sums
+    # flushed every 8 orders) against the 256-column strips that also write the
+    # saved state, and both against the oracle; several strips, a ragged last one
+    torch, P = _mods()
+    f = synthimg.gen2(*shape, 80 + W)
+    x = torch.tensor(f, dtype=torch.float32, device="cuda")
+    pa = P.Plan("box", sr, *shape, W=W, engine="streamed")
+    a = pa.forward(x)
+    ref = G.gpa_alg2(x.cpu().numpy().astype(np.float64), K.taps1d("box", W=W), sr, pa.info.N, 127.5)
+    da = np.abs(a.cpu().numpy() - ref).max()
+    db = 0.0
+    if W <= 120:  # the adjoint's support limit: only then is there a saved-state plan
+        pg = P.Plan("box", sr, *shape, W=W, engine="streamed", grad=True)
+        b = pg.forward(x, saved=pg.new_saved())
+        torch.cuda.synchronize()
+        db = np.abs(b.cpu().numpy() - ref).max()
+    print(f"W={W} N={pa.info.N}: wide {da:.3e} saved {db:.3e}", flush=True)
+    assert da <= TOL and db <= TOL
