@@ -441,7 +441,11 @@ __device__ __forceinline__ double wave_scan_incl(double v) {
 }
 
 constexpr int kStripThreads = 256;
-constexpr int kStripPitch = 260;  // doubles per order in the prefix buffer (256 columns + total)
+constexpr int kStripPitch = 276;  // doubles per order: 256 columns swizzled, the total, 16-byte rows
+
+// Column s of a 256-column prefix row sits at s + 2 (s / 32): the 16-byte
+// reads of lanes 8 apart (32 bytes per lane) no longer share banks.
+__device__ __forceinline__ int sw1(int s) { return s + 2 * (s >> 5); }
 
 __host__ __device__ inline int strip_cols(int W) { return kStripThreads - 2 * W; }
 
@@ -499,7 +503,7 @@ __global__ __launch_bounds__(kStripThreads) void ls_box_strip_kernel(TileParams 
   for (int r = r_lo; r < r_hi; ++r) {
 #pragma unroll
     for (int k = 0; k < kLsBlock; ++k)
-      if (k < K) Cs[k * kStripPitch + t] = C[k];
+      if (k < K) Cs[k * kStripPitch + sw1(t)] = C[k];
     LsPix<1, SAVE> px;
     const int64_t pi = (int64_t)r * p.Wd + c0 + oc;
     px.load(st, pi, 0, pix ? 1 : 0);
@@ -516,19 +520,19 @@ __global__ __launch_bounds__(kStripThreads) void ls_box_strip_kernel(TileParams 
 #pragma unroll
     for (int j = 0; j < kLsBlock / 4; ++j) {
       double* row = Cs + (wv + 4 * j) * kStripPitch;
-      const double2 u = *(const double2*)(row + 4 * lane);
-      const double2 w = *(const double2*)(row + 4 * lane + 2);
+      const double2 u = *(const double2*)(row + sw1(4 * lane));
+      const double2 w = *(const double2*)(row + sw1(4 * lane) + 2);
       const double s1 = u.x + u.y, s2 = s1 + w.x, s3 = s2 + w.y;
       const double incl = wave_scan_incl(s3);
       const double ex = incl - s3;
-      *(double2*)(row + 4 * lane) = make_double2(ex, ex + u.x);
-      *(double2*)(row + 4 * lane + 2) = make_double2(ex + s1, ex + s2);
-      if (lane == 63) row[256] = incl;
+      *(double2*)(row + sw1(4 * lane)) = make_double2(ex, ex + u.x);
+      *(double2*)(row + sw1(4 * lane) + 2) = make_double2(ex + s1, ex + s2);
+      if (lane == 63) row[sw1(256)] = incl;
       float ov[4];
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const int c = lane + 64 * i;
-        ov[i] = (float)(row[min(c + L, 256)] - row[c]);
+        ov[i] = (float)(row[sw1(min(c + L, 256))] - row[sw1(c)]);
       }
       // all of the wave's reads of S precede these writes into the same row
       float* o = (float*)row;
