@@ -434,6 +434,18 @@ def main():
                               "per_setting": rl}
         print(f"# recursive {extra['recursive']}", file=sys.stderr, flush=True)
 
+        # wide range (T / sigma_r above 13): the streamed Gaussian with float64 per-pixel states
+        wl = {}
+        for ss, sr in [(3.0, 8.0), (3.0, 5.0), (25.0, 5.0), (25.0, 3.5)]:
+            wp = P.Plan("gauss", sr, H, Wd, sigma_s=ss)
+            ms_w = time_launches(lambda: wp.forward(x, out=out), stream, 1, max(1, a.steps // 2), torch)
+            wl[f"sigma_s={ss:g},sigma_r={sr:g}"] = {"N": wp.info.N, "W": wp.info.W, "ms": round(ms_w, 3),
+                                                   "us_per_order": round(1e3 * ms_w / (wp.info.N + 1), 2),
+                                                   "mpix_s": round(H * Wd / ms_w / 1e3, 1)}
+        extra["wide_range"] = {"workload": "4096x4096 gen2, gauss, lambda = (127.5 / sigma_r)^2 in (170, 1400]",
+                               "per_setting": wl}
+        print(f"# wide_range {extra['wide_range']}", file=sys.stderr, flush=True)
+
         # video/volume extension: 64 frames of 1024^2 (67 Mvoxels), box W = 3 and Gaussian sigma_s = 1.5
         vd, vh, vw = 64, 1024, 1024
         vx = torch.tensor(np.stack([synthimg.gen2(vh, vw, 3200 + d) for d in range(vd)]), dtype=torch.float32,

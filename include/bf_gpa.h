@@ -93,6 +93,8 @@ extern "C" {
 #define BF_PATH_TILE_MFMA  2  /* one fused launch, FIR passes on the matrix cores */
 #define BF_PATH_RECURSIVE  3  /* BF_GAUSS_REC: row and column recursions per block of orders */
 #define BF_PATH_VOLUME     4  /* bf_plan_volume: row, column and depth passes per block of orders */
+#define BF_PATH_WIDE       5  /* T/sigma_r in (13, 37.4]: the streamed Gaussian with float64
+                                 per-pixel states (plain forward, zero border, W <= 120) */
 
 typedef struct bf_params {
   int32_t kernel;    /* BF_BOX, BF_GAUSS or BF_GAUSS_REC */
@@ -137,7 +139,13 @@ int bf_order(const bf_params* p, bf_plan_info* out);
  * (Cor. eps) and N (Prop. LambW, or as chosen by n_rule), builds the
  * float64 recursion tables and uploads them, allocates the workspace
  * (the backward's when BF_FLAG_GRAD is set).  *out receives the plan
- * (owned by the caller; free with bf_destroy).  Uses the current HIP device. */
+ * (owned by the caller; free with bf_destroy).  Uses the current HIP device.
+ * Range: with lambda = (T / sigma_r)^2, every path serves lambda <= 170
+ * (e^{-x^2/2} a normal float32 for |x| <= T / sigma_r).  For 170 < lambda
+ * <= 1400 (e.g. sigma_r >= 3.41 on [0, 255]) only the plain forward Gaussian
+ * (W <= 120, zero border, no GRAD / JOINT / MIRROR / TILE_* / MFMA_FP32)
+ * runs, on BF_PATH_WIDE; other requests there return BF_EUNSUPPORTED, as
+ * does every lambda above 1400. */
 int bf_plan(const bf_params* p, bf_plan_t** out);
 int bf_plan_get_info(const bf_plan_t* plan, bf_plan_info* out);
 int bf_destroy(bf_plan_t* plan);
@@ -200,7 +208,7 @@ int bf_forward_joint(const bf_plan_t* plan, const float* in, int64_t in_pitch, c
                      int64_t guide_pitch, float* out, int64_t out_pitch, void* stream);
 
 /* Data range of an image, for planning with the centre and half-range taken
- * from the data (data-driven range): writes {min, max} of the
+ * from the data: writes {min, max} of the
  * height x width float32 image `in` (device, row pitch `pitch`) to the DEVICE
  * array minmax[2], skipping NaNs ({+inf, -inf} if there is no number).  Plan
  * with center = (min + max)/2 and T = (max - min)/2: every |f - center| <= T,

@@ -21,8 +21,18 @@ Algorithm 2 performs N+1 spatial filterings (of F_0..F_N).
 
 Border: zero extension of the auxiliary images (equivalently, Omega is
 truncated to the image in eq. BF / eq. GPA), as in ``oracle.bf``.
+
+Small sigma_r: the partial sums of ``phi`` reach e^{|s|} with |s| up to
+lambda = T^2 / sigma_r^2 and overflow float64 beyond lambda ~ 709 (sigma_r
+below about 4.8 on [0, 255]).  ``phi_wide`` evaluates the same sum with
+every term formed in log space, which stays finite to lambda = 1400; the
+pair-by-pair forms take it with ``wide=True``.
+
+Test infrastructure only: the product path never imports this package.
 """
 from __future__ import annotations
+
+import math
 
 import numpy as np
 
@@ -42,6 +52,30 @@ def phi(t: np.ndarray, tau: np.ndarray, sigma_r: float, N: int) -> np.ndarray:
     return np.exp(-(t * t + tau * tau) / (2.0 * sigma_r * sigma_r)) * acc
 
 
+def phi_wide(t: np.ndarray, tau: np.ndarray, sigma_r: float, N: int) -> np.ndarray:
+    """phi_{N, sigma_r}(t, tau) of eq. (GaussPolynomial), each term
+    exp(-(t^2 + tau^2) / (2 sigma_r^2)) s^n / n!, s = tau t / sigma_r^2,
+    taken as sign(s)^n exp(-(t^2 + tau^2) / (2 sigma_r^2) + n log|s| - log n!):
+    every term is at most exp(-(|t| - |tau|)^2 / (2 sigma_r^2)) <= 1."""
+    t = np.asarray(t, dtype=np.float64)
+    tau = np.asarray(tau, dtype=np.float64)
+    s = tau * t / (sigma_r * sigma_r)
+    base = -(t * t + tau * tau) / (2.0 * sigma_r * sigma_r)
+    with np.errstate(divide="ignore"):
+        ls = np.log(np.abs(s))
+    neg = s < 0
+    acc = np.zeros(np.broadcast(t, tau).shape)
+    for n in range(N):
+        if n == 0:
+            term = np.exp(base) * np.ones_like(acc)
+        else:
+            term = np.exp(base + n * ls - math.lgamma(n + 1.0))
+            if n % 2 == 1:
+                term = np.where(neg, -term, term)
+        acc = acc + term
+    return acc
+
+
 def kernel_error(t, tau, sigma_r: float, N: int) -> np.ndarray:
     """E_{N, sigma_r}(t, tau) = g(t - tau) - phi_N(t, tau), eq. (error)."""
     t = np.asarray(t, dtype=np.float64)
@@ -51,8 +85,10 @@ def kernel_error(t, tau, sigma_r: float, N: int) -> np.ndarray:
 
 
 def gpa_pairwise(f: np.ndarray, w2: np.ndarray, sigma_r: float, N: int,
-                 center: float) -> np.ndarray:
-    """eq. (GPA) on the centred image h = f - center, plus center (Prop. centering)."""
+                 center: float, wide: bool = False) -> np.ndarray:
+    """eq. (GPA) on the centred image h = f - center, plus center (Prop. centering).
+    wide: phi evaluated by ``phi_wide``."""
+    ph = phi_wide if wide else phi
     h = np.asarray(f, dtype=np.float64) - center
     H, Wd = h.shape
     W = w2.shape[0] // 2
@@ -66,15 +102,16 @@ def gpa_pairwise(f: np.ndarray, w2: np.ndarray, sigma_r: float, N: int,
         for b in range(-W, W + 1):
             sh = pad[W - a:W - a + H, W - b:W - b + Wd]
             ok = valid[W - a:W - a + H, W - b:W - b + Wd]
-            k = w2[W + a, W + b] * phi(sh, h, sigma_r, N) * ok
+            k = w2[W + a, W + b] * ph(sh, h, sigma_r, N) * ok
             num += k * sh
             den += k
     return num / den + center
 
 
 def gpa_pairwise_at(f: np.ndarray, pixels: np.ndarray, w2: np.ndarray,
-                    sigma_r: float, N: int, center: float) -> np.ndarray:
-    """eq. (GPA) at the listed (row, col) pixels only."""
+                    sigma_r: float, N: int, center: float, wide: bool = False) -> np.ndarray:
+    """eq. (GPA) at the listed (row, col) pixels only (wide: ``phi_wide``)."""
+    ph = phi_wide if wide else phi
     h = np.asarray(f, dtype=np.float64) - center
     H, Wd = h.shape
     W = w2.shape[0] // 2
@@ -84,7 +121,7 @@ def gpa_pairwise_at(f: np.ndarray, pixels: np.ndarray, w2: np.ndarray,
         c0, c1 = max(0, c - W), min(Wd, c + W + 1)
         win = h[r0:r1, c0:c1]
         wj = w2[W + r - np.arange(r0, r1)][:, W + c - np.arange(c0, c1)]
-        k = wj * phi(win, h[r, c], sigma_r, N)
+        k = wj * ph(win, h[r, c], sigma_r, N)
         out[m] = (k * win).sum() / k.sum() + center
     return out
 

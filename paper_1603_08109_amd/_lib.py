@@ -41,6 +41,7 @@ BF_PATH_STREAMED = 1
 BF_PATH_TILE_MFMA = 2
 BF_PATH_RECURSIVE = 3
 BF_PATH_VOLUME = 4
+BF_PATH_WIDE = 5
 
 
 class bf_params(C.Structure):

@@ -20,7 +20,7 @@ _KERNELS = {"box": L.BF_BOX, "gauss": L.BF_GAUSS, "gaussian": L.BF_GAUSS, "gauss
 _ENGINES = {None: 0, "auto": 0, "valu": L.BF_FLAG_TILE_VALU, "mfma": L.BF_FLAG_TILE_MFMA,
             "streamed": L.BF_FLAG_STREAMED}
 PATHS = {L.BF_PATH_TILE: "valu", L.BF_PATH_STREAMED: "streamed", L.BF_PATH_TILE_MFMA: "mfma",
-         L.BF_PATH_RECURSIVE: "recursive", L.BF_PATH_VOLUME: "volume"}
+         L.BF_PATH_RECURSIVE: "recursive", L.BF_PATH_VOLUME: "volume", L.BF_PATH_WIDE: "wide"}
 
 
 @dataclass

@@ -490,6 +490,8 @@ int bf_batch_plan(int32_t count, const bf_params* per_image, bf_batch_t** out) {
     int st = (pi.flags & BF_FLAG_JOINT)  ? fail(BF_EUNSUPPORTED, "the batch runs the plain filter only")
              : pi.kernel == BF_GAUSS_REC ? fail(BF_EUNSUPPORTED, "the batch has no recursive Gaussian")
                                          : bf_order(&pi, &b->info[i]);
+    if (st >= 0 && b->info[i].lambda > kLambdaF32)
+      st = fail(BF_EUNSUPPORTED, "the batch runs float32 ranges only: need T/sigma_r <= 13");
     b->status[i] = st;
     if (st < 0) continue;
     if (st > 0) warn = st;

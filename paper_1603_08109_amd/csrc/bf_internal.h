@@ -55,7 +55,15 @@ struct TileParams {
   int mirror;           // 1: reflecting border (BF_FLAG_MIRROR), 0: zero extension
   const float* rg_tab;  // recursive Gaussian: recursion coefficients and scan matrices (else null)
   int mfma_x3;          // streamed Gaussian: float32 products as split-bfloat16 matrix-core products
+  int wide;             // wide range (T / sigma_r above 13): float64 per-pixel states, out = sigma_r P / Q + c
+  const double* isq;    // 1 / sqrt(n), n = 0 .. N+1 (isq_0 = 0)
+  const double* sq;     // sqrt(n), n = 0 .. N+1
 };
+
+// lambda = (T / sigma_r)^2 limits: exp(-x^2/2) stays a normal float32 for
+// lambda <= 170 and a normal float64 for lambda <= 1400 (x up to 37.4)
+constexpr double kLambdaF32 = 170.0;
+constexpr double kLambdaF64 = 1400.0;
 
 // Large-support path: orders per block and its device state.
 constexpr int kLsBlock = 16;
@@ -71,6 +79,8 @@ struct LsState {
   int64_t hbytes;           // bytes of one row-filtered image
   int64_t tpitch;           // recursive Gaussian: row pitch of the column-major filtered images
   float* HT[kLsBlock];      // recursive Gaussian: the row-filtered images, column-major
+  double* Fd[2];            // wide range: F~_n = e^{-x^2/2} x^n / sqrt(n!) images (double-buffered)
+  double *ad, *apd;         // wide range: per-pixel a~_n, a~_{n-1}
 };
 
 // Rows of one row-filtered image of the streamed passes: the height padded
@@ -129,6 +139,8 @@ double rg_w0(double sigma_s);
 
 // streamed Gaussian passes with float32 emulated on the bfloat16 matrix cores (W <= 120)
 bool ls_x3_supported(int W);
+bool ls_wide_supported(int W);
+hipError_t launch_forward_wide(const TileParams& p, const LsState& st, hipStream_t s);
 int64_t ls_rows_x3_lds_bytes(int W);
 int64_t ls_cols_x3_lds_bytes(int W);
 hipError_t launch_rows_x3(const TileParams& p, const LsState& st, int n0, int K, int src, int grid, hipStream_t s);
@@ -167,8 +179,8 @@ int max_lds_bytes();
 bool ls_supported(int W);
 bool ls_box_strip_supported(int W);
 bool ls_mirror_supported(int kernel, int W);
-int64_t ls_state_bytes(int H, int Wd, int W, bool save);
-LsState ls_layout(void* base, int H, int Wd, int W, bool save);
+int64_t ls_state_bytes(int H, int Wd, int W, bool save, bool wide = false);
+LsState ls_layout(void* base, int H, int Wd, int W, bool save, bool wide = false);
 hipError_t launch_forward_ls(const TileParams& p, const LsState& st, bool save, hipStream_t s);
 // streamed adjoint (bf_large_bwd.hip)
 bool bls_supported(int W, bool sigs);
@@ -221,6 +233,7 @@ struct bf_plan {
   bool ls;              // large-support path (support too wide for the fused tiles)
   bool mfma;            // fused matrix-core tile (Gaussian)
   bool rec;             // recursive Gaussian (its state in d_ls / ls_state)
+  bool wide;            // wide-range streamed Gaussian (its state in d_ls / ls_state)
   int depth;            // > 0: a volume plan of depth slices (its state in d_ls / ls_state, vol)
   bfgpa::VolBufs vol;
   void* d_ls;           // its device state

@@ -761,7 +761,7 @@ bool ls_mirror_supported(int kernel, int W) {
 
 __global__ __launch_bounds__(kThreads) void ls_final_kernel(TileParams p, LsState st) {
   const int64_t npx = (int64_t)p.H * p.Wd;
-  const double X = (double)p.X;
+  const double X = p.wide ? 1.0 : (double)p.X;  // the wide-range sums carry no 1/X
   for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < npx;
        i += (int64_t)gridDim.x * kThreads) {
     const int r = (int)(i / p.Wd), c = (int)(i - (int64_t)r * p.Wd);
@@ -788,19 +788,21 @@ bool ls_supported(int W) {
          (int64_t)(64 + 2 * W) * kLsColPitch * 4 <= max_lds_bytes();
 }
 
-int64_t ls_state_bytes(int H, int Wd, int W, bool save) {
+// wide range: the F~ images and the coefficients in float64 instead of float32
+int64_t ls_state_bytes(int H, int Wd, int W, bool save, bool wide) {
   const int64_t pitch = ((Wd + 63) / 64) * 64;
   const int64_t img = pitch * H;
   const int64_t himg = pitch * ls_hrows(H, W);
   const int64_t npx = (int64_t)H * Wd;
-  int64_t b = 3 * img * 4 + (int64_t)kLsBlock * himg * 4 + 3 * npx * 4 + 2 * npx * 8;
+  int64_t b = (wide ? 2 * img * 8 + img * 4 : 3 * img * 4) + (int64_t)kLsBlock * himg * 4 +
+              (wide ? 2 * npx * 8 + npx * 4 : 3 * npx * 4) + 2 * npx * 8;
   if (save) b += npx * 4 + 2 * npx * 8;
   return b + 256 * 32;
 }
 
 // Carve the state buffers out of one allocation.
-LsState ls_layout(void* base, int H, int Wd, int W, bool save) {
-  LsState st;
+LsState ls_layout(void* base, int H, int Wd, int W, bool save, bool wide) {
+  LsState st = {};
   const int64_t pitch = ((Wd + 63) / 64) * 64;
   const int64_t img = pitch * H;
   const int64_t himg = pitch * ls_hrows(H, W);
@@ -812,12 +814,22 @@ LsState ls_layout(void* base, int H, int Wd, int W, bool save) {
     return (void*)r;
   };
   st.pitch = pitch;
-  st.F[0] = (float*)take(img * 4);
-  st.F[1] = (float*)take(img * 4);
+  if (wide) {
+    st.Fd[0] = (double*)take(img * 8);
+    st.Fd[1] = (double*)take(img * 8);
+  } else {
+    st.F[0] = (float*)take(img * 4);
+    st.F[1] = (float*)take(img * 4);
+  }
   st.Y = (float*)take(img * 4);
   for (int k = 0; k < kLsBlock; ++k) st.H[k] = (float*)take(himg * 4);
-  st.a = (float*)take(npx * 4);
-  st.ap = (float*)take(npx * 4);
+  if (wide) {
+    st.ad = (double*)take(npx * 8);
+    st.apd = (double*)take(npx * 8);
+  } else {
+    st.a = (float*)take(npx * 4);
+    st.ap = (float*)take(npx * 4);
+  }
   st.z = (float*)take(npx * 4);
   st.P = (double*)take(npx * 8);
   st.Q = (double*)take(npx * 8);

@@ -31,6 +31,7 @@
 
 #include <algorithm>
 #include <cstdint>
+#include <type_traits>
 
 #include "bf_device.h"
 #include "bf_internal.h"
@@ -149,9 +150,12 @@ int64_t ls_cols_x3_lds_bytes(int W) {
 // and the F^ / y slots; here a thread owns pairs of adjacent columns).  Wave
 // w takes the 16-column blocks par = w & 1 and par + 2 of column group
 // w >> 1 (64 columns); they read the same slice one k-step apart.
-template <int MAXS>
+// WIDE: F~_n = e^{-x^2/2} x^n / sqrt(n!) in float64 (state images st.Fd),
+// advanced by x / sqrt(n + 1); the matrix cores see it rounded to float32.
+template <int MAXS, bool WIDE>
 __global__ __launch_bounds__(kX3RowsThreads) void ls_rows_x3_kernel(TileParams p, LsState st, int n0, int K,
                                                                     int src) {
+  using FT = typename std::conditional<WIDE, double, float>::type;
   extern __shared__ float lds[];
   const int W = p.W;
   const int RW = kLsCols + 2 * W;
@@ -164,15 +168,16 @@ __global__ __launch_bounds__(kX3RowsThreads) void ls_rows_x3_kernel(TileParams p
   const int tile = blockIdx.x;
   const int ty = tile / tiles_x, tx = tile - (tile / tiles_x) * tiles_x;
   const int r0 = ty * kLsRows, c0 = tx * kLsCols;
-  const float* Fin = st.F[src];
-  float* Fout = st.F[src ^ 1];
+  const FT* Fin = (const FT*)(WIDE ? (const void*)st.Fd[src] : (const void*)st.F[src]);
+  FT* Fout = (FT*)(WIDE ? (void*)st.Fd[src ^ 1] : (void*)st.F[src ^ 1]);
   fill_toeplitz_x3<kX3RowsThreads>(Tb, W, p.taps + kTapPad);
   __syncthreads();
   X3 T[MAXS];  // this lane's Toeplitz operands, in registers for the whole kernel
 #pragma unroll
   for (int q = 0; q < MAXS; ++q)
     if (q < S) T[q] = x3_table(Tb, q, threadIdx.x & 63);
-  float F[kX3RowsRegs], Y[kX3RowsRegs];
+  FT F[kX3RowsRegs];
+  float Y[kX3RowsRegs];
 #pragma unroll
   for (int j = 0; j < kX3RowsRegs; ++j) {
     const int q = 2 * (threadIdx.x + (j >> 1) * kX3RowsThreads) + (j & 1);
@@ -185,7 +190,7 @@ __global__ __launch_bounds__(kX3RowsThreads) void ls_rows_x3_kernel(TileParams p
     else
       ok = ok && gc >= 0 && gc < p.Wd;
     const int64_t i = ok ? (int64_t)gr * st.pitch + gc : 0;
-    F[j] = ok ? Fin[i] : 0.f;
+    F[j] = ok ? Fin[i] : (FT)0;
     Y[j] = ok ? st.Y[i] : 0.f;
   }
   const int lane = threadIdx.x & 63;
@@ -202,8 +207,8 @@ __global__ __launch_bounds__(kX3RowsThreads) void ls_rows_x3_kernel(TileParams p
       const int q = 2 * (threadIdx.x + (j >> 1) * kX3RowsThreads);
       if (q < plane) {
         __bf16 h0, m0, l0, h1, m1, l1;
-        split3(F[j], h0, m0, l0);
-        split3(F[j + 1], h1, m1, l1);
+        split3((float)F[j], h0, m0, l0);
+        split3((float)F[j + 1], h1, m1, l1);
         typedef __bf16 bf2 __attribute__((ext_vector_type(2)));
         *(bf2*)(Pl + q) = bf2{h0, h1};
         *(bf2*)(Pl + plane + q) = bf2{m0, m1};
@@ -238,8 +243,14 @@ __global__ __launch_bounds__(kX3RowsThreads) void ls_rows_x3_kernel(TileParams p
           if (ocol + 32 * b < p.Wd) Hk[(int64_t)(orow + v) * st.pitch + ocol + 32 * b] = acc[b][v];
       }
     }
+    if constexpr (WIDE) {
+      const double g = p.isq[n0 + k + 1];
 #pragma unroll
-    for (int j = 0; j < kX3RowsRegs; ++j) F[j] *= Y[j];
+      for (int j = 0; j < kX3RowsRegs; ++j) F[j] = F[j] * (double)Y[j] * g;
+    } else {
+#pragma unroll
+      for (int j = 0; j < kX3RowsRegs; ++j) F[j] *= Y[j];
+    }
   }
 #pragma unroll
   for (int j = 0; j < kX3RowsRegs; ++j) {
@@ -278,7 +289,52 @@ __device__ __forceinline__ void x3_stage(const float* __restrict__ Hk, int64_t p
   }
 }
 
-template <int MAXS, bool SAVE>
+// Wide range: per-pixel a~_n = e^{-x_i^2/2} x_i^n / sqrt(n!) in float64, so
+// a~_n F~_n is the term of eq. (Q) and sqrt(n) a~_{n-1} F~_n that of eq. (P)
+// (without the X of the range-safe form); every factor is at most 1.
+template <int CH>
+struct WidePix {
+  double a[CH], ap[CH], P[CH], Q[CH];
+  float z[CH];
+  template <int M>
+  __device__ __forceinline__ void load_part(const LsState& st, int s0, int64_t i0, int64_t stride, int n_ok) {
+#pragma unroll
+    for (int u = 0; u < M; ++u) {
+      const int s = s0 + u;
+      const bool ok = u < n_ok;
+      const int64_t i = ok ? i0 + u * stride : 0;
+      a[s] = ok ? st.ad[i] : 0.0;
+      ap[s] = ok ? st.apd[i] : 0.0;
+      z[s] = ok ? st.z[i] : 0.f;
+      P[s] = ok ? st.P[i] : 0.0;
+      Q[s] = ok ? st.Q[i] : 0.0;
+    }
+  }
+  template <int M>
+  __device__ __forceinline__ void store_part(const LsState& st, int s0, int64_t i0, int64_t stride,
+                                             int n_ok) const {
+#pragma unroll
+    for (int u = 0; u < M; ++u) {
+      const int s = s0 + u;
+      if (u < n_ok) {
+        const int64_t i = i0 + u * stride;
+        st.ad[i] = a[s];
+        st.apd[i] = ap[s];
+        st.P[i] = P[s];
+        st.Q[i] = Q[s];
+      }
+    }
+  }
+  // fold F~_bar_n (value v at pixel s); g1 = 1 / sqrt(n + 1), sn = sqrt(n)
+  __device__ __forceinline__ void fold(int s, int n, int N, float v, double g1, double sn) {
+    if (n < N) Q[s] = fma(a[s], (double)v, Q[s]);
+    if (n >= 1) P[s] = fma(ap[s] * sn, (double)v, P[s]);
+    ap[s] = a[s];
+    a[s] = a[s] * (double)z[s] * g1;
+  }
+};
+
+template <int MAXS, bool SAVE, bool WIDE>
 __global__ __launch_bounds__(kX3ColsThreads) void ls_cols_x3_kernel(TileParams p, LsState st, int n0, int K) {
   extern __shared__ float lds[];
   const int tiles_x = (p.Wd + kTileCols - 1) / kTileCols;
@@ -303,7 +359,7 @@ __global__ __launch_bounds__(kX3ColsThreads) void ls_cols_x3_kernel(TileParams p
     if (q < S) T[q] = x3_table((const __bf16*)(lds + bfl), q, lane);
   const int pr0 = tr0 + 16 * rb + 4 * (lane >> 4);
   const int pc = c0 + 16 * cb + (lane & 15);
-  LsPix<8, SAVE> px;
+  typename std::conditional<WIDE, WidePix<8>, LsPix<8, SAVE>>::type px;
 #pragma unroll
   for (int b = 0; b < 2; ++b) {
     const int nr = pc < p.Wd ? max(0, min(4, p.H - (pr0 + 32 * b))) : 0;
@@ -351,11 +407,19 @@ __global__ __launch_bounds__(kX3ColsThreads) void ls_cols_x3_kernel(TileParams p
           acc[1] = mfma_x3(T[q >= 1 ? q - 1 : 0], bv, acc[1]);
       }
     }
-    const float in1 = p.inv_tab[n + 1];
+    if constexpr (WIDE) {
+      const double g1 = p.isq[n + 1], sn = p.sq[n];
 #pragma unroll
-    for (int b = 0; b < 2; ++b)
+      for (int b = 0; b < 2; ++b)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) px.fold(4 * b + v, n, p.N, acc[b][v], in1);
+        for (int v = 0; v < 4; ++v) px.fold(4 * b + v, n, p.N, acc[b][v], g1, sn);
+    } else {
+      const float in1 = p.inv_tab[n + 1];
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) px.fold(4 * b + v, n, p.N, acc[b][v], in1);
+    }
   }
 #pragma unroll
   for (int b = 0; b < 2; ++b) {
@@ -364,43 +428,93 @@ __global__ __launch_bounds__(kX3ColsThreads) void ls_cols_x3_kernel(TileParams p
   }
 }
 
-template <int MAXS>
+template <int MAXS, bool WIDE>
 static hipError_t rows_x3_t(const TileParams& p, const LsState& st, int n0, int K, int src, int grid, hipStream_t s) {
   static bool attr = false;
   if (!attr) {
-    hipError_t e = hipFuncSetAttribute((const void*)ls_rows_x3_kernel<MAXS>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       max_lds_bytes());
-    if (e != hipSuccess) return e;
-    attr = true;
-  }
-  hipLaunchKernelGGL(ls_rows_x3_kernel<MAXS>, dim3(grid), dim3(kX3RowsThreads), (size_t)ls_rows_x3_lds_bytes(p.W), s,
-                     p, st, n0, K, src);
-  return hipGetLastError();
-}
-
-template <int MAXS, bool SAVE>
-static hipError_t cols_x3_t(const TileParams& p, const LsState& st, int n0, int K, int grid, hipStream_t s) {
-  static bool attr = false;
-  if (!attr) {
-    hipError_t e = hipFuncSetAttribute((const void*)ls_cols_x3_kernel<MAXS, SAVE>,
+    hipError_t e = hipFuncSetAttribute((const void*)ls_rows_x3_kernel<MAXS, WIDE>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, max_lds_bytes());
     if (e != hipSuccess) return e;
     attr = true;
   }
-  hipLaunchKernelGGL((ls_cols_x3_kernel<MAXS, SAVE>), dim3(grid), dim3(kX3ColsThreads),
+  hipLaunchKernelGGL((ls_rows_x3_kernel<MAXS, WIDE>), dim3(grid), dim3(kX3RowsThreads),
+                     (size_t)ls_rows_x3_lds_bytes(p.W), s, p, st, n0, K, src);
+  return hipGetLastError();
+}
+
+template <int MAXS, bool SAVE, bool WIDE>
+static hipError_t cols_x3_t(const TileParams& p, const LsState& st, int n0, int K, int grid, hipStream_t s) {
+  static bool attr = false;
+  if (!attr) {
+    hipError_t e = hipFuncSetAttribute((const void*)ls_cols_x3_kernel<MAXS, SAVE, WIDE>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, max_lds_bytes());
+    if (e != hipSuccess) return e;
+    attr = true;
+  }
+  hipLaunchKernelGGL((ls_cols_x3_kernel<MAXS, SAVE, WIDE>), dim3(grid), dim3(kX3ColsThreads),
                      (size_t)ls_cols_x3_lds_bytes(p.W), s, p, st, n0, K);
   return hipGetLastError();
 }
 
 // Toeplitz operands in registers: 6 k-steps cover W <= 88, 8 cover W <= 120
 hipError_t launch_rows_x3(const TileParams& p, const LsState& st, int n0, int K, int src, int grid, hipStream_t s) {
-  return x3_steps(p.W) <= 6 ? rows_x3_t<6>(p, st, n0, K, src, grid, s) : rows_x3_t<8>(p, st, n0, K, src, grid, s);
+  return x3_steps(p.W) <= 6 ? rows_x3_t<6, false>(p, st, n0, K, src, grid, s)
+                            : rows_x3_t<8, false>(p, st, n0, K, src, grid, s);
 }
 
 hipError_t launch_cols_x3(const TileParams& p, const LsState& st, int n0, int K, bool save, int grid, hipStream_t s) {
   if (x3_steps(p.W) <= 6)
-    return save ? cols_x3_t<6, true>(p, st, n0, K, grid, s) : cols_x3_t<6, false>(p, st, n0, K, grid, s);
-  return save ? cols_x3_t<8, true>(p, st, n0, K, grid, s) : cols_x3_t<8, false>(p, st, n0, K, grid, s);
+    return save ? cols_x3_t<6, true, false>(p, st, n0, K, grid, s) : cols_x3_t<6, false, false>(p, st, n0, K, grid, s);
+  return save ? cols_x3_t<8, true, false>(p, st, n0, K, grid, s) : cols_x3_t<8, false, false>(p, st, n0, K, grid, s);
+}
+
+// Wide range (lambda = (T / sigma_r)^2 in (170, 1400]): the lift in float64
+// (F~_0 = a~_0 = e^{-x^2/2}, x = (f - center) / sigma_r as in float32), the
+// split passes with float64 states, and eq. (PbyQ) without the factor X.
+__global__ __launch_bounds__(256) void wide_init_kernel(TileParams p, LsState st) {
+  const int64_t npx = (int64_t)p.H * p.Wd;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < npx; i += (int64_t)gridDim.x * 256) {
+    const int r = (int)(i / p.Wd), c = (int)(i - (int64_t)r * p.Wd);
+    const float f = p.in[(int64_t)r * p.in_pitch + c];
+    const float x = (f - p.center) / p.sigma_r;
+    const double E = exp(-0.5 * (double)x * (double)x);
+    const int64_t j = (int64_t)r * st.pitch + c;
+    st.Fd[0][j] = E;
+    st.Y[j] = x;
+    st.ad[i] = E;
+    st.apd[i] = 0.0;
+    st.z[i] = x;
+    st.P[i] = 0.0;
+    st.Q[i] = 0.0;
+  }
+}
+
+bool ls_wide_supported(int W) {
+  return ls_x3_supported(W) && ls_rows_x3_lds_bytes(W) <= max_lds_bytes() && ls_cols_x3_lds_bytes(W) <= max_lds_bytes();
+}
+
+hipError_t launch_forward_wide(const TileParams& p, const LsState& st, hipStream_t s) {
+  if (p.H <= 0 || p.Wd <= 0) return hipSuccess;
+  if (!p.wide || p.kt != BF_GAUSS || p.mirror || !ls_wide_supported(p.W) || !st.Fd[0] || !st.ad)
+    return hipErrorInvalidValue;
+  const int64_t npx = (int64_t)p.H * p.Wd;
+  const int g1 = (int)std::min<int64_t>((npx + 255) / 256, 4096);
+  hipLaunchKernelGGL(wide_init_kernel, dim3(g1), dim3(256), 0, s, p, st);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int grow = ((p.H + kLsRows - 1) / kLsRows) * ((p.Wd + kLsCols - 1) / kLsCols);
+  const int gcols = ((p.H + 63) / 64) * ((p.Wd + kTileCols - 1) / kTileCols);
+  const bool six = x3_steps(p.W) <= 6;
+  int src = 0;
+  for (int n0 = 0; n0 <= p.N; n0 += kLsBlock) {
+    const int K = std::min(kLsBlock, p.N + 1 - n0);
+    e = six ? rows_x3_t<6, true>(p, st, n0, K, src, grow, s) : rows_x3_t<8, true>(p, st, n0, K, src, grow, s);
+    if (e == hipSuccess)
+      e = six ? cols_x3_t<6, false, true>(p, st, n0, K, gcols, s) : cols_x3_t<8, false, true>(p, st, n0, K, gcols, s);
+    if (e != hipSuccess) return e;
+    src ^= 1;
+  }
+  return ls_launch_final(p, st, s);
 }
 
 }  // namespace bfgpa

@@ -158,9 +158,10 @@ static int plan_order(const bf_params* p, bf_plan_info* info, int dims = 2) {
   info->w0 = p->kernel == BF_GAUSS_REC ? rg_w0(p->sigma_s) : std::pow(t[p->W] / s, (double)dims);
   info->eps = info->w0 * p->delta / (2.0 * p->T + p->delta);
   info->lambda = (p->T / p->sigma_r) * (p->T / p->sigma_r);
-  // float32 range: exp(-x^2/2) must stay a normal float for |x| <= T/sigma_r
-  if (info->lambda > 170.0)
-    return fail(BF_EUNSUPPORTED, "sigma_r too small for float32: need T/sigma_r <= 13 (exp(-x^2/2) underflows)");
+  // exp(-x^2/2) must stay a normal float64 for |x| <= T/sigma_r (float32 up to
+  // lambda = 170; beyond, only the wide-range streamed Gaussian runs)
+  if (info->lambda > kLambdaF64)
+    return fail(BF_EUNSUPPORTED, "sigma_r too small: need T/sigma_r <= 37 (exp(-x^2/2) underflows float64)");
   int need = chernoff_order(info->lambda, info->eps);
   int status = BF_OK;
   int N;
@@ -254,27 +255,36 @@ void rg_table(double sigma_s, float* out) {
 }
 
 // Device constant tables of one image, as one float array: s_n, r_n, 1/n
-// (n = 0 .. N+1, rows of *stride floats), then the taps and the d^2 taps
-// (kTapPad zeros on each side, rows of *ntapr floats).
+// (n = 0 .. N+1, rows of *stride floats); 1/sqrt(n) and sqrt(n) as float64
+// (two rows of *stride doubles, the wide-range path); the taps and the d^2
+// taps (kTapPad zeros on each side, rows of *ntapr floats); the recursive-
+// Gaussian table.  Every offset is even, so the doubles stay aligned.
 std::vector<float> const_tables(const bf_params& p, const bf_plan_info& info, int64_t* stride,
                                 int64_t* ntapr) {
   std::vector<double> s, r, inv;
-  gpa_tables(info.lambda, info.N, s, r, inv);
+  // the range-safe tables serve lambda <= 170 (the wide-range path reads none of them)
+  gpa_tables(std::min(info.lambda, kLambdaF32), info.N, s, r, inv);
   const int N = info.N, W = p.W;
   *stride = ((N + 2 + 63) / 64) * 64;
   *ntapr = ((2 * W + 1 + 2 * kTapPad + 63) / 64) * 64;
   const int64_t nrg = p.kernel == BF_GAUSS_REC ? kRgTabFloats : 0;
-  std::vector<float> h(3 * *stride + 2 * *ntapr + nrg, 0.0f);
-  if (nrg) rg_table(p.sigma_s, h.data() + 3 * *stride + 2 * *ntapr);
+  const int64_t taps0 = 7 * *stride;
+  std::vector<float> h(taps0 + 2 * *ntapr + nrg, 0.0f);
+  if (nrg) rg_table(p.sigma_s, h.data() + taps0 + 2 * *ntapr);
+  std::vector<double> isq(*stride, 0.0), sq(*stride, 0.0);
   for (int n = 0; n <= N + 1; ++n) {
     h[n] = (float)s[n];
     h[*stride + n] = (float)r[n];
     h[2 * *stride + n] = (float)inv[n];
+    sq[n] = std::sqrt((double)n);
+    isq[n] = n > 0 ? 1.0 / sq[n] : 0.0;
   }
+  std::memcpy(h.data() + 3 * *stride, isq.data(), *stride * sizeof(double));
+  std::memcpy(h.data() + 5 * *stride, sq.data(), *stride * sizeof(double));
   std::vector<double> t = taps1d(p.kernel, p.sigma_s, W);
   for (int a = -W; a <= W; ++a) {
-    h[3 * *stride + kTapPad + a + W] = (float)t[a + W];
-    h[3 * *stride + *ntapr + kTapPad + a + W] = (float)((double)a * a * t[a + W]);
+    h[taps0 + kTapPad + a + W] = (float)t[a + W];
+    h[taps0 + *ntapr + kTapPad + a + W] = (float)((double)a * a * t[a + W]);
   }
   return h;
 }
@@ -283,8 +293,10 @@ void bind_tables(TileParams& tp, const float* d, int64_t stride, int64_t ntapr) 
   tp.s_tab = d;
   tp.r_tab = d + stride;
   tp.inv_tab = d + 2 * stride;
-  tp.taps = d + 3 * stride;
-  tp.taps2 = d + 3 * stride + ntapr;
+  tp.isq = (const double*)(d + 3 * stride);
+  tp.sq = (const double*)(d + 5 * stride);
+  tp.taps = d + 7 * stride;
+  tp.taps2 = d + 7 * stride + ntapr;
 }
 
 // Rough per-output cost of a tile shape (VALU instructions per order n),
@@ -395,6 +407,18 @@ static int choose_forward_path(const bf_params& p, ForwardPath* fp) {
   const bool mirror = (p.flags & BF_FLAG_MIRROR) != 0;
   fp->variant = -1;
   fp->TY = 0;
+  if ((p.T / p.sigma_r) * (p.T / p.sigma_r) > kLambdaF32) {
+    // float32 exp(-x^2/2) underflows: the streamed Gaussian with float64 states
+    if (p.kernel != BF_GAUSS ||
+        (p.flags & (BF_FLAG_JOINT | BF_FLAG_GRAD | BF_FLAG_MIRROR | BF_FLAG_TILE_VALU | BF_FLAG_TILE_MFMA |
+                    BF_FLAG_MFMA_FP32)))
+      return fail(BF_EUNSUPPORTED,
+                  "sigma_r too small for float32: T/sigma_r above 13 runs only the plain forward Gaussian "
+                  "(zero border, no adjoint, split-bfloat16 streamed passes)");
+    if (!ls_wide_supported(p.W)) return fail(BF_EUNSUPPORTED, "T/sigma_r above 13: Gaussian W <= 120");
+    fp->engine = BF_PATH_WIDE;
+    return BF_OK;
+  }
   if (p.kernel == BF_GAUSS_REC) {
     if (p.flags & (BF_FLAG_JOINT | BF_FLAG_MIRROR | BF_FLAG_TILE_VALU | BF_FLAG_TILE_MFMA))
       return fail(BF_EUNSUPPORTED, "the recursive Gaussian runs the plain filter, zero border, own engine");
@@ -483,13 +507,14 @@ int bf_order(const bf_params* in, bf_plan_info* out) {
   if (st < 0) return st;
   st = plan_order(&p, out);
   if (st < 0) return st;
-  if (p.height > 0 && p.width > 0) {
+  // the engine needs the image size, except that lambda above 170 admits one engine whatever the size
+  if ((p.height > 0 && p.width > 0) || out->lambda > kLambdaF32) {
     ForwardPath fp;
     const int pst = choose_forward_path(p, &fp);
     if (pst < 0) return pst;
     out->path = fp.engine;
     out->tile_rows = fp.TY;
-    out->tile_cols = (fp.engine == BF_PATH_STREAMED || fp.engine == BF_PATH_RECURSIVE) ? 0
+    out->tile_cols = (fp.engine == BF_PATH_STREAMED || fp.engine == BF_PATH_RECURSIVE || fp.engine == BF_PATH_WIDE) ? 0
                      : fp.engine == BF_PATH_TILE_MFMA                                  ? 64
                                                                                        : kTileCols;
   }
@@ -513,7 +538,8 @@ int bf_plan(const bf_params* in, bf_plan_t** out) {
   ForwardPath fpath;
   st = choose_forward_path(p, &fpath);
   if (st < 0) return st;
-  const bool ls = fpath.engine == BF_PATH_STREAMED;  // large-support path through device memory
+  const bool wide = fpath.engine == BF_PATH_WIDE;
+  const bool ls = fpath.engine == BF_PATH_STREAMED || wide;  // streamed orders through device memory
   const int variant = fpath.variant, TY = fpath.TY;
   const bool grad = (p.flags & BF_FLAG_GRAD) != 0;
   const bool sigs = p.kernel == BF_GAUSS;
@@ -538,6 +564,7 @@ int bf_plan(const bf_params* in, bf_plan_t** out) {
   pl->info.tile_cols = (ls || fpath.engine == BF_PATH_RECURSIVE) ? 0 : fpath.engine == BF_PATH_TILE_MFMA ? 64 : kTileCols;
   pl->mfma = fpath.engine == BF_PATH_TILE_MFMA;
   pl->rec = fpath.engine == BF_PATH_RECURSIVE;
+  pl->wide = wide;
   pl->variant = variant;
   pl->TY = TY;
   pl->bvariant = bvariant;
@@ -577,7 +604,7 @@ int bf_plan(const bf_params* in, bf_plan_t** out) {
     ws += 2 * (int64_t)pl->ntiles_b * sizeof(double);
   }
   if (ls) {
-    const int64_t lb = ls_state_bytes(p.height, p.width, p.W, grad);
+    const int64_t lb = ls_state_bytes(p.height, p.width, p.W, grad, wide);
     e = hipMalloc(&pl->d_ls, lb);
     if (e != hipSuccess) {
       if (pl->d_work) hipFree(pl->d_work);
@@ -593,7 +620,7 @@ int bf_plan(const bf_params* in, bf_plan_t** out) {
       delete pl;
       return hip_fail(e, "hipMemset large-support state");
     }
-    pl->ls_state = ls_layout(pl->d_ls, p.height, p.width, p.W, grad);
+    pl->ls_state = ls_layout(pl->d_ls, p.height, p.width, p.W, grad, wide);
     ws += lb;
   }
   if (pl->rec) {
@@ -679,10 +706,11 @@ static void fill_common(const bf_plan_t* pl, TileParams& tp) {
   tp.inv_sigma_s3 = p.kernel == BF_GAUSS ? (float)(1.0 / (p.sigma_s * p.sigma_s * p.sigma_s)) : 0.0f;
   const int64_t ntapr = ((2 * p.W + 1 + 2 * kTapPad + 63) / 64) * 64;
   bind_tables(tp, pl->d_const, pl->tab_stride, ntapr);
-  tp.rg_tab = p.kernel == BF_GAUSS_REC ? pl->d_const + 3 * pl->tab_stride + 2 * ntapr : nullptr;
+  tp.rg_tab = p.kernel == BF_GAUSS_REC ? pl->d_const + 7 * pl->tab_stride + 2 * ntapr : nullptr;
   tp.saved_plane = (int64_t)p.height * p.width;
   tp.mirror = (p.flags & BF_FLAG_MIRROR) ? 1 : 0;
   tp.mfma_x3 = (p.flags & BF_FLAG_MFMA_FP32) ? 0 : 1;
+  tp.wide = pl->wide ? 1 : 0;
 }
 }  // namespace bfgpa
 
@@ -710,7 +738,8 @@ int bf_forward(const bf_plan_t* pl, const float* in, int64_t in_pitch, float* ou
   if (pl->ls) {
     if (saved && !pl->ls_state.DP)
       return fail(BF_EINVAL, "saved state needs a plan built with BF_FLAG_GRAD");
-    e = launch_forward_ls(tp, pl->ls_state, saved != nullptr, (hipStream_t)stream);
+    e = pl->wide ? launch_forward_wide(tp, pl->ls_state, (hipStream_t)stream)
+                 : launch_forward_ls(tp, pl->ls_state, saved != nullptr, (hipStream_t)stream);
   } else if (pl->mfma) {
     e = launch_fused_mfma(tp, saved != nullptr, (hipStream_t)stream);
   } else if (pl->rec) {
@@ -740,6 +769,8 @@ int bf_plan_volume(const bf_params* in, int32_t depth, bf_plan_t** out) {
   bf_plan_info info;
   const int ost = plan_order(&p, &info, 3);
   if (ost < 0) return ost;
+  if (info.lambda > kLambdaF32)
+    return fail(BF_EUNSUPPORTED, "sigma_r too small for float32 volumes: need T/sigma_r <= 13");
   bf_plan_t* pl = new (std::nothrow) bf_plan_t();
   if (!pl) return fail(BF_ENOMEM, "host allocation failed");
   pl->p = p;

@@ -145,6 +145,39 @@ def test_recursive_gaussian_planning():
     assert P.bf_order("gauss_rec", 30.0, sigma_s=3.0, height=64, width=8192).path == L.BF_PATH_RECURSIVE
 
 
+def test_wide_range_planning():
+    # host-only: lambda = (T / sigma_r)^2 in (170, 1400] runs the Gaussian on
+    # the wide-range streamed path only; every other request there, and any
+    # lambda above 1400, is unsupported
+    import paper_1603_08109_amd as P
+    from paper_1603_08109_amd import _lib as L
+    kw = dict(height=256, width=300)
+    for sr, ss in [(9.7, 2.0), (6.0, 3.0), (3.41, 1.0), (5.0, 40.0)]:
+        info = P.bf_order("gauss", sr, sigma_s=ss, **kw)
+        assert info.path == L.BF_PATH_WIDE and info.tile_cols == 0, (sr, ss)
+        assert info.lam == pytest.approx((127.5 / sr) ** 2)
+        assert info.N == O.order_for_delta(1e-3, K.w0("gauss", sigma_s=ss), 127.5, sr)
+        assert P.bf_order("gauss", sr, sigma_s=ss).path == L.BF_PATH_WIDE  # no size needed
+    assert P.bf_order("gauss", 9.8, sigma_s=2.0, **kw).path != L.BF_PATH_WIDE      # lambda 169.3
+    assert P.bf_order("gauss", 5.0, sigma_s=2.0, T=60.0, **kw).path != L.BF_PATH_WIDE  # data range
+    bad = [dict(kernel="box", W=3), dict(kernel="gauss", sigma_s=2.0, grad=True),
+           dict(kernel="gauss", sigma_s=2.0, mirror=True), dict(kernel="gauss", sigma_s=2.0, joint=True),
+           dict(kernel="gauss", sigma_s=2.0, engine="valu"), dict(kernel="gauss", sigma_s=2.0, engine="mfma"),
+           dict(kernel="gauss", sigma_s=2.0, mfma_fp32=True), dict(kernel="gauss", sigma_s=41.0),
+           dict(kernel="gauss_rec", sigma_s=2.0)]
+    for b in bad:
+        k = b.pop("kernel")
+        with pytest.raises(L.BFError) as e:
+            P.bf_order(k, 6.0, **b, **kw)
+        assert e.value.code == L.BF_EUNSUPPORTED, (k, b)
+    with pytest.raises(L.BFError) as e:
+        P.bf_order("gauss", 3.4, sigma_s=2.0, **kw)                    # lambda 1406
+    assert e.value.code == L.BF_EUNSUPPORTED
+    with pytest.raises(L.BFError) as e:
+        P.VolumePlan("gauss", 6.0, 4, 32, 32, sigma_s=1.0)             # volumes: float32 range
+    assert e.value.code == L.BF_EUNSUPPORTED
+
+
 def test_volume_planning_weight():
     # host-side check through the oracle: the 3-D centre weight and its order
     from oracle import volume as V

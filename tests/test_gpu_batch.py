@@ -188,3 +188,13 @@ def test_batch_backward_matches_autograd():
         assert abs(gs[i, 0] - dsr) <= 1e-3 * abs(dsr), i
         if kind == "gauss":
             assert abs(gs[i, 1] - dss) <= 1e-3 * abs(dss), i
+
+
+def test_wide_range_image_reported():
+    # lambda above 170 runs only on the single-image wide-range path: the batch
+    # reports that image as unsupported and keeps the others
+    torch, P = _mods()
+    from paper_1603_08109_amd import _lib as L
+    batch = P.Batch([dict(kernel="gauss", sigma_s=2.0, sigma_r=30.0, height=40, width=50),
+                     dict(kernel="gauss", sigma_s=2.0, sigma_r=6.0, height=40, width=50)])
+    assert batch.image_status[0] >= 0 and batch.image_status[1] == L.BF_EUNSUPPORTED

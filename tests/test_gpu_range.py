@@ -66,16 +66,20 @@ def test_data_range_plan_meets_delta(kind, kw, sr):
 
 
 def test_small_sigma_r_with_data_range():
-    # sigma_r = 5 is outside the float32 domain for T = 127.5 (lambda = 650) but
-    # fine for a data range of width 80 (lambda = 64)
+    # sigma_r = 5 is outside the float32 domain for T = 127.5 (lambda = 650:
+    # only the wide-range float64-state path, N = 796) but a float32 path with a
+    # far lower order for a data range of width 80 (lambda = 64)
     torch, P = _mods()
+    full = P.Plan("gauss", 5.0, 40, 40, sigma_s=1.5)
+    assert full.info.path == P.BF_PATH_WIDE
     with pytest.raises(P.BFError):
-        P.Plan("gauss", 5.0, 40, 40, sigma_s=1.5)
+        P.Plan("box", 5.0, 40, 40, W=2)
     f = _narrow((40, 40), 12, 100.0, 180.0)
     x = torch.tensor(f, dtype=torch.float32, device="cuda")
     mm = P.image_range(x).cpu().numpy()
     rp = P.range_params(mm[0], mm[1])
     plan = P.Plan("gauss", 5.0, 40, 40, sigma_s=1.5, **rp)
+    assert plan.info.path != P.BF_PATH_WIDE and plan.info.N < full.info.N // 4
     out = plan.forward(x)
     torch.cuda.synchronize()
     f32 = x.cpu().numpy().astype(np.float64)
