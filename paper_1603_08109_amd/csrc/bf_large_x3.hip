@@ -22,7 +22,12 @@
 // Row pass: a workgroup (eight waves) owns 16 rows x 256 columns as in
 // ls_rows_mfma; each order's F^_n is split into three bfloat16 planes in
 // LDS (row pitch 8 mod 16 elements: the 16-byte reads of the 16 rows are
-// conflict-free).
+// conflict-free).  Two sets of planes: while the matrix cores multiply order
+// k from one, each thread splits order k + 1 into the other, a slot pair per
+// k-step; the number of k-steps is a template parameter, so one order is a
+// single block of straight-line code the compiler can software-pipeline
+// (operand reads of step q + 1 under the products of step q), with one
+// barrier per order.
 // Column pass: 64 x 64 tiles; the float32 window of order k + 1 is staged
 // by direct-to-LDS loads while order k multiplies, and each lane splits its
 // 8 rows of one column in registers.  In both passes a wave's blocks that
@@ -58,6 +63,14 @@ constexpr int kX3RowsThreads = 512;
 constexpr int kX3RowsRegs = 16;        // fp32 slots per thread in the row pass (8 pairs)
 constexpr int kX3ColsThreads = 512;
 constexpr int kX3MaxSteps = 8;             // k-steps of the widest support (W = 120)
+
+// elements per bfloat16 plane of the row pass: 16 rows at x3_rows_pitch(W),
+// padded so that each of a thread's slot pairs (elements below
+// kX3RowsRegs * kX3RowsThreads) has a place without a bounds test
+__host__ __device__ inline int x3_plane_elems(int W) {
+  const int rows = kLsRows * x3_rows_pitch(W);
+  return rows > kX3RowsRegs * kX3RowsThreads ? rows : kX3RowsRegs * kX3RowsThreads;
+}
 
 __device__ __forceinline__ void split3(float f, __bf16& h, __bf16& m, __bf16& l) {
   h = (__bf16)f;
@@ -136,8 +149,9 @@ bool ls_x3_supported(int W) {
   return kLsRows * x3_rows_pitch(W) <= kX3RowsRegs * kX3RowsThreads;  // W <= 120
 }
 
+// two sets of three bfloat16 planes, then the Toeplitz split table
 int64_t ls_rows_x3_lds_bytes(int W) {
-  return 2 * 3 * (int64_t)kLsRows * x3_rows_pitch(W) + (int64_t)x3_steps(W) * 3 * 64 * 16;
+  return 2 * 2 * 3 * (int64_t)x3_plane_elems(W) + (int64_t)x3_steps(W) * 3 * 64 * 16;
 }
 
 int64_t ls_cols_x3_lds_bytes(int W) {
@@ -146,13 +160,41 @@ int64_t ls_cols_x3_lds_bytes(int W) {
   return 2 * win;
 }
 
+// slot pair jj of a thread (plane elements 2 (tid + jj 512) and + 1) into
+// the three planes at P
+template <typename FT>
+__device__ __forceinline__ void x3_split_pair(FT f0, FT f1, __bf16* P, int plane, int jj) {
+  const int q = 2 * (threadIdx.x + jj * kX3RowsThreads);
+  __bf16 h0, m0, l0, h1, m1, l1;
+  split3((float)f0, h0, m0, l0);
+  split3((float)f1, h1, m1, l1);
+  typedef __bf16 bf2 __attribute__((ext_vector_type(2)));
+  *(bf2*)(P + q) = bf2{h0, h1};
+  *(bf2*)(P + plane + q) = bf2{m0, m1};
+  *(bf2*)(P + 2 * plane + q) = bf2{l0, l1};
+}
+
+// F^_n -> F^_{n+1} = F^_n y; wide range: F~_n -> F~_{n+1} = F~_n x / sqrt(n + 1)
+template <bool WIDE, typename FT>
+__device__ __forceinline__ void x3_advance(FT* F, const float* Y, const TileParams& p, int n) {
+  if constexpr (WIDE) {
+    const double g = p.isq[n + 1];
+#pragma unroll
+    for (int j = 0; j < kX3RowsRegs; ++j) F[j] = F[j] * (double)Y[j] * g;
+  } else {
+#pragma unroll
+    for (int j = 0; j < kX3RowsRegs; ++j) F[j] *= Y[j];
+  }
+}
+
 // Row pass for orders n0 .. n0 + K - 1 (see ls_rows_mfma_kernel for the tile
 // and the F^ / y slots; here a thread owns pairs of adjacent columns).  Wave
 // w takes the 16-column blocks par = w & 1 and par + 2 of column group
-// w >> 1 (64 columns); they read the same slice one k-step apart.
+// w >> 1 (64 columns); they read the same slice one k-step apart.  S =
+// x3_steps(W).
 // WIDE: F~_n = e^{-x^2/2} x^n / sqrt(n!) in float64 (state images st.Fd),
 // advanced by x / sqrt(n + 1); the matrix cores see it rounded to float32.
-template <int MAXS, bool WIDE>
+template <int S, bool WIDE>
 __global__ __launch_bounds__(kX3RowsThreads) void ls_rows_x3_kernel(TileParams p, LsState st, int n0, int K,
                                                                     int src) {
   using FT = typename std::conditional<WIDE, double, float>::type;
@@ -160,10 +202,9 @@ __global__ __launch_bounds__(kX3RowsThreads) void ls_rows_x3_kernel(TileParams p
   const int W = p.W;
   const int RW = kLsCols + 2 * W;
   const int RWb = x3_rows_pitch(W);
-  const int S = x3_steps(W);
-  const int plane = kLsRows * RWb;  // bf16 per plane
-  __bf16* Pl = (__bf16*)lds;        // 3 planes
-  __bf16* Tb = Pl + 3 * plane;
+  const int plane = x3_plane_elems(W);
+  __bf16* Pl = (__bf16*)lds;  // two sets of 3 planes (orders k and k + 1)
+  __bf16* Tb = Pl + 6 * plane;
   const int tiles_x = (p.Wd + kLsCols - 1) / kLsCols;
   const int tile = blockIdx.x;
   const int ty = tile / tiles_x, tx = tile - (tile / tiles_x) * tiles_x;
@@ -171,11 +212,6 @@ __global__ __launch_bounds__(kX3RowsThreads) void ls_rows_x3_kernel(TileParams p
   const FT* Fin = (const FT*)(WIDE ? (const void*)st.Fd[src] : (const void*)st.F[src]);
   FT* Fout = (FT*)(WIDE ? (void*)st.Fd[src ^ 1] : (void*)st.F[src ^ 1]);
   fill_toeplitz_x3<kX3RowsThreads>(Tb, W, p.taps + kTapPad);
-  __syncthreads();
-  X3 T[MAXS];  // this lane's Toeplitz operands, in registers for the whole kernel
-#pragma unroll
-  for (int q = 0; q < MAXS; ++q)
-    if (q < S) T[q] = x3_table(Tb, q, threadIdx.x & 63);
   FT F[kX3RowsRegs];
   float Y[kX3RowsRegs];
 #pragma unroll
@@ -193,6 +229,14 @@ __global__ __launch_bounds__(kX3RowsThreads) void ls_rows_x3_kernel(TileParams p
     F[j] = ok ? Fin[i] : (FT)0;
     Y[j] = ok ? st.Y[i] : 0.f;
   }
+  // order n0 into the first set; F advances to order n0 + 1
+#pragma unroll
+  for (int jj = 0; jj < kX3RowsRegs / 2; ++jj) x3_split_pair(F[2 * jj], F[2 * jj + 1], Pl, plane, jj);
+  x3_advance<WIDE>(F, Y, p, n0);
+  __syncthreads();  // the table and the first set are written
+  X3 T[S];  // this lane's Toeplitz operands, in registers for the whole kernel
+#pragma unroll
+  for (int q = 0; q < S; ++q) T[q] = x3_table(Tb, q, threadIdx.x & 63);
   const int lane = threadIdx.x & 63;
   const int wv = threadIdx.x >> 6;
   const int cbase = 64 * (wv >> 1) + 16 * (wv & 1);  // block par; block par + 2 is 32 columns on
@@ -201,39 +245,31 @@ __global__ __launch_bounds__(kX3RowsThreads) void ls_rows_x3_kernel(TileParams p
   // A reads: row l%16, columns cbase + 32 s + 8 (l/16) .. + 7
   const int abase = (lane & 15) * RWb + cbase + 8 * (lane >> 4);
   for (int k = 0; k < K; ++k) {
-    __syncthreads();  // the previous order's reads are done
-#pragma unroll
-    for (int j = 0; j < kX3RowsRegs; j += 2) {
-      const int q = 2 * (threadIdx.x + (j >> 1) * kX3RowsThreads);
-      if (q < plane) {
-        __bf16 h0, m0, l0, h1, m1, l1;
-        split3((float)F[j], h0, m0, l0);
-        split3((float)F[j + 1], h1, m1, l1);
-        typedef __bf16 bf2 __attribute__((ext_vector_type(2)));
-        *(bf2*)(Pl + q) = bf2{h0, h1};
-        *(bf2*)(Pl + plane + q) = bf2{m0, m1};
-        *(bf2*)(Pl + 2 * plane + q) = bf2{l0, l1};
-      }
-    }
-    __syncthreads();
+    if (k > 0) __syncthreads();  // order k's set is written; order k - 1's reads of the other set are done
+    const __bf16* cur = Pl + (k & 1) * 3 * plane;
+    __bf16* nxt = Pl + ((k + 1) & 1) * 3 * plane;
     mf4 acc[2] = {mf4{0.f, 0.f, 0.f, 0.f}, mf4{0.f, 0.f, 0.f, 0.f}};
 #pragma unroll
-    for (int q = 0; q <= MAXS; ++q) {
-      if (q <= S) {
-        const int a = abase + 32 * q;
-        X3 av;
-        av.h = *(const bf8*)(Pl + a);
-        av.m = *(const bf8*)(Pl + plane + a);
-        av.l = *(const bf8*)(Pl + 2 * plane + a);
-        // block par at step q, block par + 2 at step q - 1
-        if (q >= 1 && q < S)
-          mfma_x3_pair(av, T[q < MAXS ? q : 0], acc[0], av, T[q >= 1 ? q - 1 : 0], acc[1]);
-        else if (q < S)
-          acc[0] = mfma_x3(av, T[q < MAXS ? q : 0], acc[0]);
-        else
-          acc[1] = mfma_x3(av, T[q >= 1 ? q - 1 : 0], acc[1]);
-      }
+    for (int q = 0; q <= S; ++q) {
+      const int a = abase + 32 * q;
+      X3 av;
+      av.h = *(const bf8*)(cur + a);
+      av.m = *(const bf8*)(cur + plane + a);
+      av.l = *(const bf8*)(cur + 2 * plane + a);
+      // block par at step q, block par + 2 at step q - 1
+      if (q >= 1 && q < S)
+        mfma_x3_pair(av, T[q < S ? q : 0], acc[0], av, T[q >= 1 ? q - 1 : 0], acc[1]);
+      else if (q < S)
+        acc[0] = mfma_x3(av, T[q], acc[0]);
+      else
+        acc[1] = mfma_x3(av, T[q >= 1 ? q - 1 : 0], acc[1]);
+      // the next order's split under the matrix-core work (after the last
+      // order it fills the idle set and is never read)
+      if (q < kX3RowsRegs / 2) x3_split_pair(F[2 * q], F[2 * q + 1], nxt, plane, q);
     }
+#pragma unroll
+    for (int jj = S + 1; jj < kX3RowsRegs / 2; ++jj) x3_split_pair(F[2 * jj], F[2 * jj + 1], nxt, plane, jj);
+    if (k + 1 < K) x3_advance<WIDE>(F, Y, p, n0 + k + 1);
     float* Hk = st.H[k] + (int64_t)W * st.pitch;  // W zero rows above the image
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
@@ -243,15 +279,8 @@ __global__ __launch_bounds__(kX3RowsThreads) void ls_rows_x3_kernel(TileParams p
           if (ocol + 32 * b < p.Wd) Hk[(int64_t)(orow + v) * st.pitch + ocol + 32 * b] = acc[b][v];
       }
     }
-    if constexpr (WIDE) {
-      const double g = p.isq[n0 + k + 1];
-#pragma unroll
-      for (int j = 0; j < kX3RowsRegs; ++j) F[j] = F[j] * (double)Y[j] * g;
-    } else {
-#pragma unroll
-      for (int j = 0; j < kX3RowsRegs; ++j) F[j] *= Y[j];
-    }
   }
+  // F holds order n0 + K
 #pragma unroll
   for (int j = 0; j < kX3RowsRegs; ++j) {
     const int q = 2 * (threadIdx.x + (j >> 1) * kX3RowsThreads) + (j & 1);
@@ -334,7 +363,7 @@ struct WidePix {
   }
 };
 
-template <int MAXS, bool SAVE, bool WIDE>
+template <int S, bool SAVE, bool WIDE>
 __global__ __launch_bounds__(kX3ColsThreads) void ls_cols_x3_kernel(TileParams p, LsState st, int n0, int K) {
   extern __shared__ float lds[];
   const int tiles_x = (p.Wd + kTileCols - 1) / kTileCols;
@@ -346,17 +375,15 @@ __global__ __launch_bounds__(kX3ColsThreads) void ls_cols_x3_kernel(TileParams p
   const int rb = wv & 1, cb = wv >> 1;
   const int tr0 = ty * 64, c0 = tx * kTileCols;
   const int W = p.W;
-  const int S = x3_steps(W);
   const int groups = x3_cols_rows(W) / 4;
   const int64_t bfl = x3_cols_buffer_floats(W);
   float* buf0 = lds;
   // the Toeplitz operands pass through the second buffer into registers
   fill_toeplitz_x3<kX3ColsThreads>((__bf16*)(lds + bfl), W, p.taps + kTapPad);
   __syncthreads();
-  X3 T[MAXS];
+  X3 T[S];
 #pragma unroll
-  for (int q = 0; q < MAXS; ++q)
-    if (q < S) T[q] = x3_table((const __bf16*)(lds + bfl), q, lane);
+  for (int q = 0; q < S; ++q) T[q] = x3_table((const __bf16*)(lds + bfl), q, lane);
   const int pr0 = tr0 + 16 * rb + 4 * (lane >> 4);
   const int pc = c0 + 16 * cb + (lane & 15);
   typename std::conditional<WIDE, WidePix<8>, LsPix<8, SAVE>>::type px;
@@ -385,27 +412,25 @@ __global__ __launch_bounds__(kX3ColsThreads) void ls_cols_x3_kernel(TileParams p
     }
     mf4 acc[2] = {mf4{0.f, 0.f, 0.f, 0.f}, mf4{0.f, 0.f, 0.f, 0.f}};
 #pragma unroll
-    for (int q = 0; q <= MAXS; ++q) {
-      if (q <= S) {
-        X3 bv;
-        const float* src = cur + lbase + 8 * q * kX3GroupFloats;
+    for (int q = 0; q <= S; ++q) {
+      X3 bv;
+      const float* src = cur + lbase + 8 * q * kX3GroupFloats;
 #pragma unroll
-        for (int i = 0; i < 8; ++i) {
-          const float f = src[(i >> 2) * kX3GroupFloats + (i & 3) * 64];
-          __bf16 h, m, l;
-          split3(f, h, m, l);
-          bv.h[i] = h;
-          bv.m[i] = m;
-          bv.l[i] = l;
-        }
-        // block rb at step q, block rb + 2 at step q - 1
-        if (q >= 1 && q < S)
-          mfma_x3_pair(T[q < MAXS ? q : 0], bv, acc[0], T[q >= 1 ? q - 1 : 0], bv, acc[1]);
-        else if (q < S)
-          acc[0] = mfma_x3(T[q < MAXS ? q : 0], bv, acc[0]);
-        else
-          acc[1] = mfma_x3(T[q >= 1 ? q - 1 : 0], bv, acc[1]);
+      for (int i = 0; i < 8; ++i) {
+        const float f = src[(i >> 2) * kX3GroupFloats + (i & 3) * 64];
+        __bf16 h, m, l;
+        split3(f, h, m, l);
+        bv.h[i] = h;
+        bv.m[i] = m;
+        bv.l[i] = l;
       }
+      // block rb at step q, block rb + 2 at step q - 1
+      if (q >= 1 && q < S)
+        mfma_x3_pair(T[q < S ? q : 0], bv, acc[0], T[q >= 1 ? q - 1 : 0], bv, acc[1]);
+      else if (q < S)
+        acc[0] = mfma_x3(T[q], bv, acc[0]);
+      else
+        acc[1] = mfma_x3(T[q >= 1 ? q - 1 : 0], bv, acc[1]);
     }
     if constexpr (WIDE) {
       const double g1 = p.isq[n + 1], sn = p.sq[n];
@@ -428,44 +453,71 @@ __global__ __launch_bounds__(kX3ColsThreads) void ls_cols_x3_kernel(TileParams p
   }
 }
 
-template <int MAXS, bool WIDE>
-static hipError_t rows_x3_t(const TileParams& p, const LsState& st, int n0, int K, int src, int grid, hipStream_t s) {
+template <int S, bool WIDE>
+static hipError_t rows_x3_s(const TileParams& p, const LsState& st, int n0, int K, int src, int grid, hipStream_t s) {
   static bool attr = false;
   if (!attr) {
-    hipError_t e = hipFuncSetAttribute((const void*)ls_rows_x3_kernel<MAXS, WIDE>,
+    hipError_t e = hipFuncSetAttribute((const void*)ls_rows_x3_kernel<S, WIDE>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, max_lds_bytes());
     if (e != hipSuccess) return e;
     attr = true;
   }
-  hipLaunchKernelGGL((ls_rows_x3_kernel<MAXS, WIDE>), dim3(grid), dim3(kX3RowsThreads),
+  hipLaunchKernelGGL((ls_rows_x3_kernel<S, WIDE>), dim3(grid), dim3(kX3RowsThreads),
                      (size_t)ls_rows_x3_lds_bytes(p.W), s, p, st, n0, K, src);
   return hipGetLastError();
 }
 
-template <int MAXS, bool SAVE, bool WIDE>
-static hipError_t cols_x3_t(const TileParams& p, const LsState& st, int n0, int K, int grid, hipStream_t s) {
+template <bool WIDE>
+static hipError_t rows_x3_t(const TileParams& p, const LsState& st, int n0, int K, int src, int grid, hipStream_t s) {
+  switch (x3_steps(p.W)) {
+    case 1: return rows_x3_s<1, WIDE>(p, st, n0, K, src, grid, s);
+    case 2: return rows_x3_s<2, WIDE>(p, st, n0, K, src, grid, s);
+    case 3: return rows_x3_s<3, WIDE>(p, st, n0, K, src, grid, s);
+    case 4: return rows_x3_s<4, WIDE>(p, st, n0, K, src, grid, s);
+    case 5: return rows_x3_s<5, WIDE>(p, st, n0, K, src, grid, s);
+    case 6: return rows_x3_s<6, WIDE>(p, st, n0, K, src, grid, s);
+    case 7: return rows_x3_s<7, WIDE>(p, st, n0, K, src, grid, s);
+    case 8: return rows_x3_s<8, WIDE>(p, st, n0, K, src, grid, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <int S, bool SAVE, bool WIDE>
+static hipError_t cols_x3_s(const TileParams& p, const LsState& st, int n0, int K, int grid, hipStream_t s) {
   static bool attr = false;
   if (!attr) {
-    hipError_t e = hipFuncSetAttribute((const void*)ls_cols_x3_kernel<MAXS, SAVE, WIDE>,
+    hipError_t e = hipFuncSetAttribute((const void*)ls_cols_x3_kernel<S, SAVE, WIDE>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, max_lds_bytes());
     if (e != hipSuccess) return e;
     attr = true;
   }
-  hipLaunchKernelGGL((ls_cols_x3_kernel<MAXS, SAVE, WIDE>), dim3(grid), dim3(kX3ColsThreads),
+  hipLaunchKernelGGL((ls_cols_x3_kernel<S, SAVE, WIDE>), dim3(grid), dim3(kX3ColsThreads),
                      (size_t)ls_cols_x3_lds_bytes(p.W), s, p, st, n0, K);
   return hipGetLastError();
 }
 
-// Toeplitz operands in registers: 6 k-steps cover W <= 88, 8 cover W <= 120
+template <bool SAVE, bool WIDE>
+static hipError_t cols_x3_t(const TileParams& p, const LsState& st, int n0, int K, int grid, hipStream_t s) {
+  switch (x3_steps(p.W)) {
+    case 1: return cols_x3_s<1, SAVE, WIDE>(p, st, n0, K, grid, s);
+    case 2: return cols_x3_s<2, SAVE, WIDE>(p, st, n0, K, grid, s);
+    case 3: return cols_x3_s<3, SAVE, WIDE>(p, st, n0, K, grid, s);
+    case 4: return cols_x3_s<4, SAVE, WIDE>(p, st, n0, K, grid, s);
+    case 5: return cols_x3_s<5, SAVE, WIDE>(p, st, n0, K, grid, s);
+    case 6: return cols_x3_s<6, SAVE, WIDE>(p, st, n0, K, grid, s);
+    case 7: return cols_x3_s<7, SAVE, WIDE>(p, st, n0, K, grid, s);
+    case 8: return cols_x3_s<8, SAVE, WIDE>(p, st, n0, K, grid, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+// one kernel per k-step count S = x3_steps(W) (W <= 120: S <= 8), the Toeplitz operands in registers
 hipError_t launch_rows_x3(const TileParams& p, const LsState& st, int n0, int K, int src, int grid, hipStream_t s) {
-  return x3_steps(p.W) <= 6 ? rows_x3_t<6, false>(p, st, n0, K, src, grid, s)
-                            : rows_x3_t<8, false>(p, st, n0, K, src, grid, s);
+  return rows_x3_t<false>(p, st, n0, K, src, grid, s);
 }
 
 hipError_t launch_cols_x3(const TileParams& p, const LsState& st, int n0, int K, bool save, int grid, hipStream_t s) {
-  if (x3_steps(p.W) <= 6)
-    return save ? cols_x3_t<6, true, false>(p, st, n0, K, grid, s) : cols_x3_t<6, false, false>(p, st, n0, K, grid, s);
-  return save ? cols_x3_t<8, true, false>(p, st, n0, K, grid, s) : cols_x3_t<8, false, false>(p, st, n0, K, grid, s);
+  return save ? cols_x3_t<true, false>(p, st, n0, K, grid, s) : cols_x3_t<false, false>(p, st, n0, K, grid, s);
 }
 
 // Wide range (lambda = (T / sigma_r)^2 in (170, 1400]): the lift in float64
@@ -504,13 +556,12 @@ hipError_t launch_forward_wide(const TileParams& p, const LsState& st, hipStream
   if (e != hipSuccess) return e;
   const int grow = ((p.H + kLsRows - 1) / kLsRows) * ((p.Wd + kLsCols - 1) / kLsCols);
   const int gcols = ((p.H + 63) / 64) * ((p.Wd + kTileCols - 1) / kTileCols);
-  const bool six = x3_steps(p.W) <= 6;
   int src = 0;
   for (int n0 = 0; n0 <= p.N; n0 += kLsBlock) {
     const int K = std::min(kLsBlock, p.N + 1 - n0);
-    e = six ? rows_x3_t<6, true>(p, st, n0, K, src, grow, s) : rows_x3_t<8, true>(p, st, n0, K, src, grow, s);
+    e = rows_x3_t<true>(p, st, n0, K, src, grow, s);
     if (e == hipSuccess)
-      e = six ? cols_x3_t<6, false, true>(p, st, n0, K, gcols, s) : cols_x3_t<8, false, true>(p, st, n0, K, gcols, s);
+      e = cols_x3_t<false, true>(p, st, n0, K, gcols, s);
     if (e != hipSuccess) return e;
     src ^= 1;
   }
