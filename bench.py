@@ -373,12 +373,30 @@ def main():
 
         ms_fb = time_launches(fwd_bwd, stream, 1, max(1, a.steps // 2), torch)
         ms_f = time_launches(fwd_only, stream, 1, max(1, a.steps // 2), torch)
+        ref_gins = [g.clone() for g in gins]
+
+        # the same 32 images through the batch entry points: one persistent forward launch and
+        # one persistent adjoint launch (forward state recomputed inside), sigma gradients included
+        gbatch = P.Batch([dict(kernel="gauss", sigma_s=5.0, sigma_r=30.0, height=512, width=512, grad=True)
+                          for _ in range(32)])
+        bgins = [torch.empty_like(imgs[0]) for _ in range(32)]
+
+        def fwd_bwd_batched():
+            gbatch.forward(imgs, outs)
+            gouts = [(outs[b] - tgts[b]) * (2.0 / outs[b].numel()) for b in range(32)]
+            gbatch.backward(imgs, gouts, grad_ins=bgins)
+
+        ms_fbb = time_launches(fwd_bwd_batched, stream, 1, max(1, a.steps // 2), torch)
+        torch.cuda.synchronize()
+        rel = max(float((bgins[b] - ref_gins[b]).abs().max() / ref_gins[b].abs().max()) for b in range(32))
         px5 = 32 * 512 * 512
         extra["fwd_bwd"] = {"workload": "32x512^2 gauss(sigma_s=5,sigma_r=30) N=%d, MSE loss" % plan5.info.N,
                             "ms": round(ms_fb, 3), "mpix_s": round(px5 / ms_fb / 1e3, 1),
-                            "fwd_ms": round(ms_f, 3), "fwd_mpix_s": round(px5 / ms_f / 1e3, 1)}
+                            "fwd_ms": round(ms_f, 3), "fwd_mpix_s": round(px5 / ms_f / 1e3, 1),
+                            "batched_ms": round(ms_fbb, 3), "batched_mpix_s": round(px5 / ms_fbb / 1e3, 1),
+                            "batched_vs_per_image_max_rel_dfdin": rel}
         print(f"# fwd_bwd {extra['fwd_bwd']}", file=sys.stderr, flush=True)
-        del imgs, tgts, saved, outs, gins
+        del imgs, tgts, saved, outs, gins, bgins, ref_gins, gbatch
 
         # batched workload: 256 uneven images, one persistent launch vs per-image launches
         specs = synthimg.batch_params(256, 4000)
