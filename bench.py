@@ -389,14 +389,27 @@ def main():
         ms_fbb = time_launches(fwd_bwd_batched, stream, 1, max(1, a.steps // 2), torch)
         torch.cuda.synchronize()
         rel = max(float((bgins[b] - ref_gins[b]).abs().max() / ref_gins[b].abs().max()) for b in range(32))
+        bsaved = gbatch.new_saved()
+
+        def fwd_bwd_batched_saved():
+            # the forward keeps its per-image state; the adjoint skips its recompute launch
+            gbatch.forward(imgs, outs, saved=bsaved)
+            gouts = [(outs[b] - tgts[b]) * (2.0 / outs[b].numel()) for b in range(32)]
+            gbatch.backward(imgs, gouts, grad_ins=bgins, saved=bsaved)
+
+        ms_fbs = time_launches(fwd_bwd_batched_saved, stream, 1, max(1, a.steps // 2), torch)
+        torch.cuda.synchronize()
+        rel_s = max(float((bgins[b] - ref_gins[b]).abs().max() / ref_gins[b].abs().max()) for b in range(32))
         px5 = 32 * 512 * 512
         extra["fwd_bwd"] = {"workload": "32x512^2 gauss(sigma_s=5,sigma_r=30) N=%d, MSE loss" % plan5.info.N,
                             "ms": round(ms_fb, 3), "mpix_s": round(px5 / ms_fb / 1e3, 1),
                             "fwd_ms": round(ms_f, 3), "fwd_mpix_s": round(px5 / ms_f / 1e3, 1),
                             "batched_ms": round(ms_fbb, 3), "batched_mpix_s": round(px5 / ms_fbb / 1e3, 1),
-                            "batched_vs_per_image_max_rel_dfdin": rel}
+                            "batched_vs_per_image_max_rel_dfdin": rel,
+                            "batched_saved_ms": round(ms_fbs, 3), "batched_saved_mpix_s": round(px5 / ms_fbs / 1e3, 1),
+                            "batched_saved_vs_per_image_max_rel_dfdin": rel_s}
         print(f"# fwd_bwd {extra['fwd_bwd']}", file=sys.stderr, flush=True)
-        del imgs, tgts, saved, outs, gins, bgins, ref_gins, gbatch
+        del imgs, tgts, saved, outs, gins, bgins, ref_gins, gbatch, bsaved
 
         # batched workload: 256 uneven images, one persistent launch vs per-image launches
         specs = synthimg.batch_params(256, 4000)

@@ -277,6 +277,23 @@ int bf_batch_tune(bf_batch_t* batch, const float* const* in, const int64_t* in_p
 int bf_batch_backward(bf_batch_t* batch, const float* const* in, const int64_t* in_pitch,
                       const float* const* grad_out, const int64_t* gout_pitch, float* const* grad_in,
                       const int64_t* gin_pitch, double* grad_sigma, void* stream);
+/* The batch pair with the forward state kept by the caller (as bf_forward /
+ * bf_backward with `saved`), so the adjoint skips its recompute launch.
+ * bf_batch_forward_saved runs the persistent forward directly (not from the
+ * captured graph) and also writes, for image i, three planes of
+ * height*width float32 (dense pitch = width) to the DEVICE buffer saved[i];
+ * bf_batch_backward_saved takes the same arrays and reads them.  `saved` is
+ * a host array of `count` device pointers; entries of images whose plan
+ * failed are ignored, every other one must be non-NULL.  The planes belong to
+ * the inputs the forward saw: passing other inputs gives the gradient at the
+ * saved state.  Errors as for bf_batch_forward / bf_batch_backward, plus
+ * BF_EINVAL for a NULL `saved` array or entry, or a batch planned without
+ * BF_FLAG_GRAD. */
+int bf_batch_forward_saved(bf_batch_t* batch, const float* const* in, const int64_t* in_pitch,
+                           float* const* out, const int64_t* out_pitch, float* const* saved, void* stream);
+int bf_batch_backward_saved(bf_batch_t* batch, const float* const* in, const int64_t* in_pitch,
+                            const float* const* grad_out, const int64_t* gout_pitch, const float* const* saved,
+                            float* const* grad_in, const int64_t* gin_pitch, double* grad_sigma, void* stream);
 int bf_batch_destroy(bf_batch_t* batch);
 
 const char* bf_status_string(int status);

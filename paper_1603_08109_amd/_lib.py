@@ -103,6 +103,12 @@ SIGNATURES = {
     "bf_batch_backward": (C.c_int, [C.c_void_p, C.POINTER(C.c_void_p), C.POINTER(C.c_int64),
                                     C.POINTER(C.c_void_p), C.POINTER(C.c_int64), C.POINTER(C.c_void_p),
                                     C.POINTER(C.c_int64), C.c_void_p, C.c_void_p]),
+    "bf_batch_forward_saved": (C.c_int, [C.c_void_p, C.POINTER(C.c_void_p), C.POINTER(C.c_int64),
+                                         C.POINTER(C.c_void_p), C.POINTER(C.c_int64), C.POINTER(C.c_void_p),
+                                         C.c_void_p]),
+    "bf_batch_backward_saved": (C.c_int, [C.c_void_p, C.POINTER(C.c_void_p), C.POINTER(C.c_int64),
+                                          C.POINTER(C.c_void_p), C.POINTER(C.c_int64), C.POINTER(C.c_void_p),
+                                          C.POINTER(C.c_void_p), C.POINTER(C.c_int64), C.c_void_p, C.c_void_p]),
     "bf_batch_destroy": (C.c_int, [C.c_void_p]),
     "bf_status_string": (C.c_char_p, [C.c_int]),
     "bf_last_error_message": (C.c_char_p, []),

@@ -264,16 +264,38 @@ class Batch:
             ipt[i], opt[i] = a.stride(0), b.stride(0)
         return ip, ipt, op, opt
 
-    def forward(self, inputs, outputs=None, stream=None):
+    def new_saved(self) -> list:
+        """Per-image forward-state buffers (3 * height * width float32) for forward/backward(saved=...)."""
+        return [torch.empty(3 * H * W, dtype=torch.float32, device="cuda") for H, W in self.shapes]
+
+    def _saved_array(self, saved):
+        n = self.count
+        if len(saved) != n:
+            raise ValueError("one saved buffer per image")
+        arr = (C.c_void_p * n)()
+        for i, t in enumerate(saved):
+            H, W = self.shapes[i]
+            if t.dtype != torch.float32 or not t.is_cuda or not t.is_contiguous() or t.numel() < 3 * H * W:
+                raise ValueError(f"saved[{i}] must be a contiguous CUDA float32 tensor of 3*{H}*{W} elements")
+            arr[i] = t.data_ptr()
+        return arr
+
+    def forward(self, inputs, outputs=None, saved=None, stream=None):
+        """saved: None, or new_saved() buffers that receive each image's forward state."""
         if outputs is None:
             outputs = [torch.empty_like(x) for x in inputs]
         ip, ipt, op, opt = self._arrays(inputs, outputs)
-        L.check(self._lib.bf_batch_forward(self._h, ip, ipt, op, opt, _stream_handle(stream)),
-                "bf_batch_forward")
+        if saved is None:
+            L.check(self._lib.bf_batch_forward(self._h, ip, ipt, op, opt, _stream_handle(stream)),
+                    "bf_batch_forward")
+        else:
+            L.check(self._lib.bf_batch_forward_saved(self._h, ip, ipt, op, opt, self._saved_array(saved),
+                                                     _stream_handle(stream)), "bf_batch_forward_saved")
         return outputs
 
-    def backward(self, inputs, grad_outs, grad_ins=None, want_sigma: bool = True, stream=None):
-        """Returns (list of dL/din_i, float64 tensor (count, 2) of [dL/dsigma_r, dL/dsigma_s] or None)."""
+    def backward(self, inputs, grad_outs, grad_ins=None, want_sigma: bool = True, saved=None, stream=None):
+        """Returns (list of dL/din_i, float64 tensor (count, 2) of [dL/dsigma_r, dL/dsigma_s] or None).
+        saved: None (the forward state is recomputed) or the buffers forward(saved=...) filled."""
         n = self.count
         if len(inputs) != n or len(grad_outs) != n:
             raise ValueError("one input and one output gradient per image")
@@ -295,9 +317,13 @@ class Batch:
             op[i], opt[i] = o.data_ptr(), o.stride(0)
         dev = inputs[0].device
         gs = torch.empty(n, 2, dtype=torch.float64, device=dev) if want_sigma else None
-        L.check(self._lib.bf_batch_backward(self._h, ip, ipt, gp, gpt, op, opt,
-                                            C.c_void_p(gs.data_ptr() if gs is not None else 0),
-                                            _stream_handle(stream)), "bf_batch_backward")
+        gsp = C.c_void_p(gs.data_ptr() if gs is not None else 0)
+        if saved is None:
+            L.check(self._lib.bf_batch_backward(self._h, ip, ipt, gp, gpt, op, opt, gsp, _stream_handle(stream)),
+                    "bf_batch_backward")
+        else:
+            L.check(self._lib.bf_batch_backward_saved(self._h, ip, ipt, gp, gpt, self._saved_array(saved), op, opt,
+                                                      gsp, _stream_handle(stream)), "bf_batch_backward_saved")
         return grad_ins, gs
 
     def tune(self, inputs, outputs, stream=None) -> int:

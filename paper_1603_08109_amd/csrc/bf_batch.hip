@@ -350,14 +350,15 @@ static int stage(bf_batch* b, int k, const float* const* in, const int64_t* in_p
   return BF_OK;
 }
 
-static int run_direct(bf_batch* b, int k, hipStream_t s, int grid) {
+// save: the staged params carry per-image saved planes, written as well
+static int run_direct(bf_batch* b, int k, hipStream_t s, int grid, bool save = false) {
   const BatchShape& sh = b->cands[b->chosen];
   if (hipMemcpyAsync(b->d_params, b->h_stage[k], b->count * sizeof(TileParams), hipMemcpyHostToDevice,
                      s) != hipSuccess)
     return fail(BF_EHIP, "hipMemcpyAsync batch params");
   hipLaunchKernelGGL(batch_reset_kernel, dim3(1), dim3(64), 0, s, b->d_counter);
   hipError_t e = launch_batch_v(sh.variant, b->d_params, b->d_tiles, b->ntiles, b->d_counter, grid,
-                                sh.lds, b->acc64, false, s);
+                                sh.lds, b->acc64, save, s);
   if (e != hipSuccess) return fail(BF_EHIP, std::string("batch launch: ") + hipGetErrorString(e));
   return BF_OK;
 }
@@ -660,9 +661,34 @@ int bf_batch_tune(bf_batch_t* b, const float* const* in, const int64_t* in_pitch
   return BF_OK;
 }
 
-int bf_batch_backward(bf_batch_t* b, const float* const* in, const int64_t* in_pitch,
-                      const float* const* grad_out, const int64_t* gout_pitch, float* const* grad_in,
-                      const int64_t* gin_pitch, double* grad_sigma, void* stream) {
+int bf_batch_forward_saved(bf_batch_t* b, const float* const* in, const int64_t* in_pitch,
+                           float* const* out, const int64_t* out_pitch, float* const* saved, void* stream) {
+  if (!b || !in || !out || !in_pitch || !out_pitch || !saved) return fail(BF_EINVAL, "NULL argument");
+  if (!b->grad) return fail(BF_EINVAL, "saved state needs a batch planned with BF_FLAG_GRAD");
+  hipStream_t s = (hipStream_t)stream;
+  const int k = b->slot;
+  b->slot ^= 1;
+  int st = stage(b, k, in, in_pitch, out, out_pitch);
+  if (st < 0) return st;
+  for (int i = 0; i < b->count; ++i) {
+    if (b->status[i] < 0) continue;
+    if (!saved[i]) return fail(BF_EINVAL, "NULL saved pointer in batch");
+    b->h_stage[k][i].saved = saved[i];
+  }
+  st = run_direct(b, k, s, grid_of(b), true);
+  if (st < 0) return st;
+  hipEventRecord(b->ev[k], s);
+  b->ev_used[k] = true;
+  return BF_OK;
+}
+
+}  // extern "C"
+
+// saved: NULL (recompute the forward state into the batch workspace) or the
+// per-image planes bf_batch_forward_saved wrote
+static int batch_backward(bf_batch_t* b, const float* const* in, const int64_t* in_pitch,
+                          const float* const* grad_out, const int64_t* gout_pitch, const float* const* saved,
+                          float* const* grad_in, const int64_t* gin_pitch, double* grad_sigma, void* stream) {
   if (!b || !in || !in_pitch || !grad_out || !gout_pitch) return fail(BF_EINVAL, "NULL argument");
   if (!b->grad) return fail(BF_EINVAL, "batch was planned without BF_FLAG_GRAD");
   if (grad_in && !gin_pitch) return fail(BF_EINVAL, "grad_in without gin_pitch");
@@ -681,7 +707,8 @@ int bf_batch_backward(bf_batch_t* b, const float* const* in, const int64_t* in_p
       f.in = g.in = in[i];
       f.in_pitch = g.in_pitch = in_pitch[i];
       f.out = nullptr;
-      f.saved = g.saved = b->d_saved + b->saved_off[i];
+      if (saved && !saved[i]) return fail(BF_EINVAL, "NULL saved pointer in batch");
+      f.saved = g.saved = saved ? const_cast<float*>(saved[i]) : b->d_saved + b->saved_off[i];
       g.gout = grad_out[i];
       g.gout_pitch = gout_pitch[i];
       g.out = grad_in ? grad_in[i] : nullptr;
@@ -695,9 +722,12 @@ int bf_batch_backward(bf_batch_t* b, const float* const* in, const int64_t* in_p
       hipSuccess)
     return fail(BF_EHIP, "hipMemcpyAsync batch adjoint params");
   hipLaunchKernelGGL(batch_reset_kernel, dim3(1), dim3(64), 0, s, b->d_counter);
-  hipError_t e = launch_batch_v(sh.variant, b->d_bparams, b->d_tiles, b->ntiles, b->d_counter, grid_of(b), sh.lds,
-                                b->acc64, true, s);
-  if (e != hipSuccess) return fail(BF_EHIP, std::string("batch forward-state launch: ") + hipGetErrorString(e));
+  hipError_t e = hipSuccess;
+  if (!saved) {
+    e = launch_batch_v(sh.variant, b->d_bparams, b->d_tiles, b->ntiles, b->d_counter, grid_of(b), sh.lds, b->acc64,
+                       true, s);
+    if (e != hipSuccess) return fail(BF_EHIP, std::string("batch forward-state launch: ") + hipGetErrorString(e));
+  }
   if (b->nbtiles > 0) {
     const int grid = std::max(1, std::min(2 * b->num_cu, b->nbtiles));
     e = launch_batch_bwd(b->bvariant, b->d_bparams + n, b->d_btiles, b->nbtiles, b->d_counter + 1,
@@ -724,6 +754,21 @@ int bf_batch_backward(bf_batch_t* b, const float* const* in, const int64_t* in_p
   hipEventRecord(b->bev, s);
   b->bev_used = true;
   return BF_OK;
+}
+
+extern "C" {
+
+int bf_batch_backward(bf_batch_t* b, const float* const* in, const int64_t* in_pitch,
+                      const float* const* grad_out, const int64_t* gout_pitch, float* const* grad_in,
+                      const int64_t* gin_pitch, double* grad_sigma, void* stream) {
+  return batch_backward(b, in, in_pitch, grad_out, gout_pitch, nullptr, grad_in, gin_pitch, grad_sigma, stream);
+}
+
+int bf_batch_backward_saved(bf_batch_t* b, const float* const* in, const int64_t* in_pitch,
+                            const float* const* grad_out, const int64_t* gout_pitch, const float* const* saved,
+                            float* const* grad_in, const int64_t* gin_pitch, double* grad_sigma, void* stream) {
+  if (!saved) return fail(BF_EINVAL, "NULL saved array");
+  return batch_backward(b, in, in_pitch, grad_out, gout_pitch, saved, grad_in, gin_pitch, grad_sigma, stream);
 }
 
 int bf_batch_destroy(bf_batch_t* b) {

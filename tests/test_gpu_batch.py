@@ -198,3 +198,42 @@ def test_wide_range_image_reported():
     batch = P.Batch([dict(kernel="gauss", sigma_s=2.0, sigma_r=30.0, height=40, width=50),
                      dict(kernel="gauss", sigma_s=2.0, sigma_r=6.0, height=40, width=50)])
     assert batch.image_status[0] >= 0 and batch.image_status[1] == L.BF_EUNSUPPORTED
+
+
+def test_batch_saved_state_pair():
+    # bf_batch_forward_saved / bf_batch_backward_saved: the same outputs as the
+    # graphed forward and, from the same forward state (the same kernel writes
+    # it), exactly the recomputing adjoint's gradients; the W = 30 box image
+    # takes the streamed adjoint from the saved planes as well
+    torch, P = _mods()
+    specs = _grad_batch(33)
+    batch = P.Batch(specs)
+    assert all(s >= 0 for s in batch.image_status)
+    imgs = [torch.tensor(synthimg.gen2(s["height"], s["width"], 900 + i), dtype=torch.float32, device="cuda")
+            for i, s in enumerate(specs)]
+    gouts = [torch.tensor(synthimg.gen1(s["height"], s["width"], 950 + i) / 255.0 - 0.5, dtype=torch.float32,
+                          device="cuda") for i, s in enumerate(specs)]
+    ref_out = [o.clone() for o in batch.forward(imgs)]
+    ref_gin, ref_gs = batch.backward(imgs, gouts)
+    ref_gin = [g.clone() for g in ref_gin]
+    ref_gs = ref_gs.clone()
+    saved = batch.new_saved()
+    for rep in range(2):
+        out = batch.forward(imgs, saved=saved)
+        gin, gs = batch.backward(imgs, gouts, saved=saved)
+        torch.cuda.synchronize()
+        for i in range(len(specs)):
+            assert torch.abs(out[i] - ref_out[i]).max().item() <= 1e-5, (rep, i)
+            assert torch.equal(gin[i], ref_gin[i]), (rep, i)
+        assert torch.equal(torch.nan_to_num(gs, nan=7.0), torch.nan_to_num(ref_gs, nan=7.0)), rep
+
+
+def test_batch_saved_state_errors():
+    torch, P = _mods()
+    plain = P.Batch([dict(kernel="gauss", sigma_s=2.0, sigma_r=30.0, height=20, width=30)])
+    x = [torch.zeros(20, 30, device="cuda")]
+    with pytest.raises(P.BFError):
+        plain.forward(x, saved=plain.new_saved())                      # planned without BF_FLAG_GRAD
+    g = P.Batch([dict(kernel="gauss", sigma_s=2.0, sigma_r=30.0, height=20, width=30, grad=True)])
+    with pytest.raises(ValueError):
+        g.forward(x, saved=[torch.empty(10, device="cuda")])           # too small
