@@ -89,3 +89,33 @@ def test_split_saved_state():
     torch.cuda.synchronize()
     for i, (u, v) in enumerate(zip(sa.view(3, -1), sb.view(3, -1))):
         assert (u - v).abs().max().item() <= 1e-4 * u.abs().max().item() + 1e-12, i
+
+
+@pytest.mark.parametrize("ss,shape", [(2.0, (70, 300)), (15.0, (130, 270)), (21.3, (140, 200)),
+                                      (33.3, (230, 150))])
+def test_split_every_step_count(ss, shape):
+    # the passes are compiled per k-step count S = ceil((16 + 2W) / 32): W = 6 (S = 1), 45 (S = 4,
+    # split columns), 64 (S = 5), 100 (S = 7); the other counts are covered above
+    f = synthimg.gen1(*shape, 94)
+    x3, f32, plan, fx = _pair(f, ss, 30.0)
+    ref = G.gpa_alg2(fx, K.taps1d("gauss", ss), 30.0, plan.info.N, 127.5)
+    d3 = np.abs(x3 - ref).max()
+    print(f"sigma_s={ss} W={plan.info.W} N={plan.info.N}: split {d3:.3e}", flush=True)
+    assert d3 <= TOL
+    assert np.abs(x3 - f32).max() <= BETWEEN
+
+
+def test_split_saved_state_split_columns():
+    # W = 45: the split column pass with the adjoint's sums (SAVE), against the float32 passes
+    torch, P = _mods()
+    f = synthimg.gen2(150, 180, 95)
+    x = torch.tensor(f, dtype=torch.float32, device="cuda")
+    a = P.Plan("gauss", 25.0, 150, 180, sigma_s=15.0, grad=True, engine="streamed")
+    b = P.Plan("gauss", 25.0, 150, 180, sigma_s=15.0, grad=True, engine="streamed", mfma_fp32=True)
+    assert a.info.W == 45
+    sa, sb = a.new_saved(), b.new_saved()
+    ya, yb = a.forward(x, saved=sa), b.forward(x, saved=sb)
+    torch.cuda.synchronize()
+    assert (ya - yb).abs().max().item() <= BETWEEN
+    for i, (u, v) in enumerate(zip(sa.view(3, -1), sb.view(3, -1))):
+        assert (u - v).abs().max().item() <= 1e-4 * u.abs().max().item() + 1e-12, i
