@@ -19,10 +19,10 @@ constexpr int kTileCols = 64;
 // FIR loops can index taps without bounds tests (>= largest block - 1).
 constexpr int kTapPad = 16;
 // Row pitch (floats) of the LDS buffer holding the row-pass output.  The
-// row pass writes it with lanes on consecutive rows and pairs of adjacent
-// columns (64-bit accesses): a pitch of twice an odd number puts the 16
-// lanes of one LDS cycle on 32 distinct banks.
-constexpr int kHPitch = kTileCols + 2;
+// row pass writes it with lanes on consecutive rows, each lane a run of
+// adjacent columns as pairs of dword accesses at any alignment: an odd pitch
+// puts every dword of the wave's access on a distinct bank.
+constexpr int kHPitch = kTileCols + 1;
 // Row-pass register blocks (outputs per work item) for the box and the FIR.
 constexpr int kRowSegBoxHost = 16;
 constexpr int kRowSegFirHost = 8;
@@ -109,11 +109,11 @@ struct Variant {
 };
 
 // Region (tile grown by W on every side) in LDS, in floats.  Row pitch is
-// twice an odd number for the same reason as kHPitch (the row pass reads
-// pairs of adjacent columns with lanes on consecutive rows).
+// odd for the same reason as kHPitch (the row pass reads runs of adjacent
+// columns with lanes on consecutive rows).
 __host__ __device__ inline int region_pitch(int W) {
-  const int rw = kTileCols + 2 * W;
-  return (rw % 4 == 2) ? rw : rw + 2;
+  const int rw = kTileCols + 2 * W;  // even
+  return rw + 1;
 }
 inline int64_t region_floats(int TY, int W) {
   return (int64_t)(TY + 2 * W) * region_pitch(W);
