@@ -380,7 +380,7 @@ static int plan_batch_adjoint(bf_batch* b) {
       if (b->status[i] < 0) continue;
       const int TY = 4 * vv.opt, W = b->prm[i].W;
       const bool sigs = b->prm[i].kernel == BF_GAUSS;
-      if (region_floats(TY, W) <= (int64_t)kThreads * vv.mreg &&
+      if (region_floats_bwd(TY, W) <= (int64_t)kThreads * vv.mreg &&
           backward_lds_bytes(TY, W, sigs) + 2 * kThreads * 8 + 64 <= max_lds_bytes())
         ++n;
     }
@@ -404,7 +404,7 @@ static int plan_batch_adjoint(bf_batch* b) {
     b->saved_off[i] = saved;
     saved += 3 * (int64_t)p.height * p.width;
     const int TY = 4 * vv.opt;
-    if (region_floats(TY, p.W) <= (int64_t)kThreads * vv.mreg &&
+    if (region_floats_bwd(TY, p.W) <= (int64_t)kThreads * vv.mreg &&
         backward_lds_bytes(TY, p.W, sigs) + 2 * kThreads * 8 + 64 <= max_lds_bytes()) {
       b->bTY[i] = TY;
       lds = std::max(lds, backward_lds_bytes(TY, p.W, sigs));

@@ -154,7 +154,7 @@ __device__ __forceinline__ void fir1d(const float* __restrict__ src, int STRIDE,
 constexpr int kRowSegBox = kRowSegBoxHost;
 constexpr int kRowSegFir = kRowSegFirHost;
 
-template <int KT>
+template <int KT, int HP = kHPitch>
 __device__ __forceinline__ void rowpass(const float* __restrict__ Fs, int RWp, float* __restrict__ Hs,
                                         int RH, int W, const float* __restrict__ tz) {
   constexpr int S = (KT == BF_BOX) ? kRowSegBox : kRowSegFir;
@@ -169,29 +169,30 @@ __device__ __forceinline__ void rowpass(const float* __restrict__ Fs, int RWp, f
       box1d<S>(Fs + r * RWp + seg * S, 1, L, o);
     else
       fir1d<S>(Fs + r * RWp + seg * S, 1, L, tz, o);
-    float* h = Hs + r * kHPitch + seg * S;
+    float* h = Hs + r * HP + seg * S;
 #pragma unroll
     for (int s = 0; s < S; ++s) h[s] = o[s];
   }
 }
 
 // Row pass with the FIR regardless of the tile's kernel (adjoint's sigma_s term).
+template <int HP>
 __device__ __forceinline__ void rowpass_fir_any(const float* __restrict__ Fs, int RWp,
                                                 float* __restrict__ Hs, int RH, int W,
                                                 const float* __restrict__ tz) {
-  rowpass<BF_GAUSS>(Fs, RWp, Hs, RH, W, tz);
+  rowpass<BF_GAUSS, HP>(Fs, RWp, Hs, RH, W, tz);
 }
 
 // Column pass: the thread owns column `lane` and output rows orow0 ..
 // orow0 + OPT - 1; it reads Hs rows orow0 .. orow0 + OPT - 1 + 2W.
-template <int KT, int OPT>
+template <int KT, int OPT, int HP = kHPitch>
 __device__ __forceinline__ void colpass(const float* __restrict__ Hs, int orow0, int lane, int W,
                                         const float* __restrict__ tz, float (&v)[OPT]) {
-  const float* col = Hs + orow0 * kHPitch + lane;
+  const float* col = Hs + orow0 * HP + lane;
   if (KT == BF_BOX)
-    box1d<OPT>(col, kHPitch, 2 * W + 1, v);
+    box1d<OPT>(col, HP, 2 * W + 1, v);
   else
-    fir1d<OPT>(col, kHPitch, 2 * W + 1, tz, v);
+    fir1d<OPT>(col, HP, 2 * W + 1, tz, v);
 }
 
 // ---------------------------------------------------------------------------
@@ -202,11 +203,12 @@ struct RegionGeom {
   int RH, RW, RWp, npx;
 };
 
-__device__ __forceinline__ RegionGeom region_geom(int TY, int W) {
+// bwd: the adjoint tile's pitch (region_pitch_bwd)
+__device__ __forceinline__ RegionGeom region_geom(int TY, int W, bool bwd = false) {
   RegionGeom g;
   g.RH = TY + 2 * W;
   g.RW = kTileCols + 2 * W;
-  g.RWp = region_pitch(W);
+  g.RWp = bwd ? region_pitch_bwd(W) : region_pitch(W);
   g.npx = g.RH * g.RWp;
   return g;
 }
@@ -521,13 +523,13 @@ template <int KT, int OPT, int MREG, bool SIGS>
 __device__ __forceinline__ void backward_tile(const TileParams& p, int r0, int c0, float* lds, double* red,
                                               double* part) {
   const int W = p.W, N = p.N;
-  const RegionGeom g = region_geom(4 * OPT, W);
+  const RegionGeom g = region_geom(4 * OPT, W, true);
   const int np4 = align4(g.npx);
   float* As = lds;
   float* Hs = As + np4;
-  float* Fs2 = Hs + g.RH * kHPitch;
+  float* Fs2 = Hs + g.RH * kHPitchBwd;
   float* Hg = Fs2 + np4;
-  float* Hg2 = Hg + g.RH * kHPitch;
+  float* Hg2 = Hg + g.RH * kHPitchBwd;
   const float* tz = p.taps + kTapPad;
   const float* tz2 = p.taps2 + kTapPad;
 
@@ -591,18 +593,18 @@ __device__ __forceinline__ void backward_tile(const TileParams& p, int r0, int c
       br[k] = bn;
     }
     __syncthreads();
-    rowpass<KT>(As, g.RWp, Hs, g.RH, W, tz);
+    rowpass<KT, kHPitchBwd>(As, g.RWp, Hs, g.RH, W, tz);
     if (SIGS) {
-      rowpass_fir_any(Fs2, g.RWp, Hg, g.RH, W, tz);
-      rowpass_fir_any(Fs2, g.RWp, Hg2, g.RH, W, tz2);
+      rowpass_fir_any<kHPitchBwd>(Fs2, g.RWp, Hg, g.RH, W, tz);
+      rowpass_fir_any<kHPitchBwd>(Fs2, g.RWp, Hg2, g.RH, W, tz2);
     }
     __syncthreads();
     float fa[OPT];
-    colpass<KT, OPT>(Hs, orow0, lane, W, tz, fa);
+    colpass<KT, OPT, kHPitchBwd>(Hs, orow0, lane, W, tz, fa);
     if (SIGS) {
       float u[OPT], u2[OPT];
-      colpass<BF_GAUSS, OPT>(Hg, orow0, lane, W, tz2, u);   // d^2 g along rows of g-filtered
-      colpass<BF_GAUSS, OPT>(Hg2, orow0, lane, W, tz, u2);  // g along rows of d^2 g-filtered
+      colpass<BF_GAUSS, OPT, kHPitchBwd>(Hg, orow0, lane, W, tz2, u);   // d^2 g along rows of g-filtered
+      colpass<BF_GAUSS, OPT, kHPitchBwd>(Hg2, orow0, lane, W, tz, u2);  // g along rows of d^2 g-filtered
 #pragma unroll
       for (int s = 0; s < OPT; ++s) {
         const float adj_i = As[(orow0 + s + W) * g.RWp + lane + W];

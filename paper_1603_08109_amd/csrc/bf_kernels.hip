@@ -257,8 +257,8 @@ int backward_variant_count() { return 2; }
 Variant backward_variant(int v) { return kBwdVariants[v]; }
 
 int64_t backward_lds_bytes(int TY, int W, bool sigs) {
-  const int64_t np4 = (region_floats(TY, W) + 3) & ~3LL;
-  const int64_t hs = (int64_t)(TY + 2 * W) * kHPitch;
+  const int64_t np4 = (region_floats_bwd(TY, W) + 3) & ~3LL;
+  const int64_t hs = (int64_t)(TY + 2 * W) * kHPitchBwd;
   return 4 * (np4 + hs + (sigs ? np4 + 2 * hs : 0));
 }
 
@@ -288,7 +288,7 @@ hipError_t launch_backward(const TileParams& p, int variant, bool sigs, double* 
                            double* grad_sigma, hipStream_t s) {
   const Variant v = backward_variant(variant);
   if (p.TY != 4 * v.opt) return hipErrorInvalidValue;
-  if (region_floats(p.TY, p.W) > (int64_t)kThreads * v.mreg) return hipErrorInvalidValue;
+  if (region_floats_bwd(p.TY, p.W) > (int64_t)kThreads * v.mreg) return hipErrorInvalidValue;
   if (backward_lds_bytes(p.TY, p.W, sigs) + 2 * kThreads * 8 > max_lds_bytes()) return hipErrorInvalidValue;
   if (p.H <= 0 || p.Wd <= 0) return hipSuccess;
   hipError_t e;

@@ -465,7 +465,7 @@ static int choose_backward_tile(int W, bool sigs, int* variant, int* TY) {
   for (int v = 0; v < nv; ++v) {
     Variant vv = backward_variant(v);
     const int ty = 4 * vv.opt;
-    if (region_floats(ty, W) > (int64_t)kThreads * vv.mreg) continue;
+    if (region_floats_bwd(ty, W) > (int64_t)kThreads * vv.mreg) continue;
     if (backward_lds_bytes(ty, W, sigs) + 2 * kThreads * 8 > max_lds_bytes()) continue;
     *variant = v;
     *TY = ty;
