@@ -163,6 +163,8 @@ static hipError_t launch_batch_bwd_t(const TileParams* d_params, const BatchTile
 static hipError_t launch_batch_bwd(int v, const TileParams* d_params, const BatchTile* d_tiles, int ntiles,
                                    int* counter, double* partials, int grid, size_t lds, hipStream_t s) {
   const Variant vv = backward_variant(v);
+  if (vv.opt == 4 && vv.mreg == 20)
+    return launch_batch_bwd_t<4, 20>(d_params, d_tiles, ntiles, counter, partials, grid, lds, s);
   if (vv.opt == 8 && vv.mreg == 24)
     return launch_batch_bwd_t<8, 24>(d_params, d_tiles, ntiles, counter, partials, grid, lds, s);
   if (vv.opt == 4 && vv.mreg == 32)

@@ -252,8 +252,10 @@ hipError_t launch_sigma_reduce(const double* partials, int n, bool has_ss, doubl
   return hipGetLastError();
 }
 
-static const Variant kBwdVariants[] = {{8, 24}, {4, 32}};
-int backward_variant_count() { return 2; }
+// {4, 20} first: its LDS (about 75 KB at W = 15) lets two workgroups share a
+// CU, where the 32-row tiles' 100 KB allow one
+static const Variant kBwdVariants[] = {{4, 20}, {8, 24}, {4, 32}};
+int backward_variant_count() { return 3; }
 Variant backward_variant(int v) { return kBwdVariants[v]; }
 
 int64_t backward_lds_bytes(int TY, int W, bool sigs) {
@@ -280,8 +282,9 @@ static hipError_t launch_bwd_t(const TileParams& p, double* partials, hipStream_
 
 template <int KT, bool SIGS>
 static hipError_t launch_bwd_k(const TileParams& p, int variant, double* partials, hipStream_t s) {
-  return variant == 0 ? launch_bwd_t<KT, 8, 24, SIGS>(p, partials, s)
-                      : launch_bwd_t<KT, 4, 32, SIGS>(p, partials, s);
+  return variant == 0   ? launch_bwd_t<KT, 4, 20, SIGS>(p, partials, s)
+         : variant == 1 ? launch_bwd_t<KT, 8, 24, SIGS>(p, partials, s)
+                        : launch_bwd_t<KT, 4, 32, SIGS>(p, partials, s);
 }
 
 hipError_t launch_backward(const TileParams& p, int variant, bool sigs, double* partials,
