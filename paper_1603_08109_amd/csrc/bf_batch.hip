@@ -23,7 +23,7 @@
 namespace bfgpa {
 
 template <int OPT, int MREG, bool ACC64, bool SAVE>
-__global__ __launch_bounds__(kThreads) void gpa_batch_kernel(const TileParams* __restrict__ params,
+__global__ __launch_bounds__(kThreads, (OPT * MREG <= 256 ? 2 : 1)) void gpa_batch_kernel(const TileParams* __restrict__ params,
                                                              const BatchTile* __restrict__ tiles,
                                                              int ntiles, int* counter) {
   extern __shared__ float lds[];

@@ -15,7 +15,7 @@ namespace bfgpa {
 // Forward
 // ---------------------------------------------------------------------------
 template <int KT, int OPT, int MREG, bool ACC64, bool SAVE>
-__global__ __launch_bounds__(kThreads) void gpa_forward_kernel(TileParams p) {
+__global__ __launch_bounds__(kThreads, (OPT * MREG <= 256 ? 2 : 1)) void gpa_forward_kernel(TileParams p) {
   extern __shared__ float lds[];
   const int tile = xcd_remap(blockIdx.x, gridDim.x);
   const int ty = tile / p.tiles_x;
@@ -213,7 +213,7 @@ hipError_t launch_joint(const TileParams& p, int variant, hipStream_t s) {
 // Adjoint kernels (the per-tile arithmetic, backward_tile, is in bf_device.h).
 // ---------------------------------------------------------------------------
 template <int KT, int OPT, int MREG, bool SIGS>
-__global__ __launch_bounds__(kThreads) void gpa_backward_kernel(TileParams p, double* partials) {
+__global__ __launch_bounds__(kThreads, (OPT * MREG <= 256 ? 2 : 1)) void gpa_backward_kernel(TileParams p, double* partials) {
   extern __shared__ float lds[];
   __shared__ double red[2 * kThreads];
   const int tile = xcd_remap(blockIdx.x, gridDim.x);
