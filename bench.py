@@ -263,7 +263,7 @@ def main():
         summarize(a.summarize, [setting_name(k, kw, sr) for k, kw, sr in SWEEP])
         return
     if a.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        print(json.dumps({"error": "this benchmark measures one GPU (the sharding design is documented, not run); --gpus must be 1"}))
         sys.exit(2)
 
     import torch
