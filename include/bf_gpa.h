@@ -94,7 +94,7 @@ extern "C" {
 #define BF_PATH_RECURSIVE  3  /* BF_GAUSS_REC: row and column recursions per block of orders */
 #define BF_PATH_VOLUME     4  /* bf_plan_volume: row, column and depth passes per block of orders */
 #define BF_PATH_WIDE       5  /* T/sigma_r in (13, 37.4]: the streamed Gaussian with float64
-                                 per-pixel states (plain forward, zero border, W <= 120) */
+                                 per-pixel states (forward only, zero or mirror border, W <= 120) */
 
 typedef struct bf_params {
   int32_t kernel;    /* BF_BOX, BF_GAUSS or BF_GAUSS_REC */
@@ -142,8 +142,8 @@ int bf_order(const bf_params* p, bf_plan_info* out);
  * (owned by the caller; free with bf_destroy).  Uses the current HIP device.
  * Range: with lambda = (T / sigma_r)^2, every path serves lambda <= 170
  * (e^{-x^2/2} a normal float32 for |x| <= T / sigma_r).  For 170 < lambda
- * <= 1400 (e.g. sigma_r >= 3.41 on [0, 255]) only the plain forward Gaussian
- * (W <= 120, zero border, no GRAD / JOINT / MIRROR / TILE_* / MFMA_FP32)
+ * <= 1400 (e.g. sigma_r >= 3.41 on [0, 255]) only the forward Gaussian
+ * (W <= 120, zero or mirror border, no GRAD / JOINT / TILE_* / MFMA_FP32)
  * runs, on BF_PATH_WIDE; other requests there return BF_EUNSUPPORTED, as
  * does every lambda above 1400. */
 int bf_plan(const bf_params* p, bf_plan_t** out);

@@ -55,7 +55,16 @@ def gpa_alg2(f: np.ndarray, w1: np.ndarray, sigma_r: float, N: int, T: float) ->
 
 
 def gpa_pairwise_at(f: np.ndarray, pixels: np.ndarray, w2: np.ndarray, sigma_r: float, N: int,
-                    center: float) -> np.ndarray:
-    """eq. (GPA) with the reflected extension, at the listed (row, col) pixels."""
+                    center: float, wide: bool = False) -> np.ndarray:
+    """eq. (GPA) with the reflected extension, at the listed (row, col) pixels
+    (wide: phi in log space, ``oracle.gpa.phi_wide``)."""
     W = w2.shape[0] // 2
-    return _gpa.gpa_pairwise_at(_pad(f, W), np.asarray(pixels) + W, w2, sigma_r, N, center)
+    return _gpa.gpa_pairwise_at(_pad(f, W), np.asarray(pixels) + W, w2, sigma_r, N, center, wide=wide)
+
+
+def gpa_pairwise(f: np.ndarray, w2: np.ndarray, sigma_r: float, N: int, center: float,
+                 wide: bool = False) -> np.ndarray:
+    """eq. (GPA) pair by pair with the reflected extension (wide: ``phi_wide``)."""
+    W = w2.shape[0] // 2
+    H, Wd = np.shape(f)
+    return _gpa.gpa_pairwise(_pad(f, W), w2, sigma_r, N, center, wide=wide)[W:W + H, W:W + Wd]

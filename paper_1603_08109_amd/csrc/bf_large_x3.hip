@@ -547,7 +547,7 @@ bool ls_wide_supported(int W) {
 
 hipError_t launch_forward_wide(const TileParams& p, const LsState& st, hipStream_t s) {
   if (p.H <= 0 || p.Wd <= 0) return hipSuccess;
-  if (!p.wide || p.kt != BF_GAUSS || p.mirror || !ls_wide_supported(p.W) || !st.Fd[0] || !st.ad)
+  if (!p.wide || p.kt != BF_GAUSS || !ls_wide_supported(p.W) || !st.Fd[0] || !st.ad)
     return hipErrorInvalidValue;
   const int64_t npx = (int64_t)p.H * p.Wd;
   const int g1 = (int)std::min<int64_t>((npx + 255) / 256, 4096);

@@ -410,11 +410,10 @@ static int choose_forward_path(const bf_params& p, ForwardPath* fp) {
   if ((p.T / p.sigma_r) * (p.T / p.sigma_r) > kLambdaF32) {
     // float32 exp(-x^2/2) underflows: the streamed Gaussian with float64 states
     if (p.kernel != BF_GAUSS ||
-        (p.flags & (BF_FLAG_JOINT | BF_FLAG_GRAD | BF_FLAG_MIRROR | BF_FLAG_TILE_VALU | BF_FLAG_TILE_MFMA |
-                    BF_FLAG_MFMA_FP32)))
+        (p.flags & (BF_FLAG_JOINT | BF_FLAG_GRAD | BF_FLAG_TILE_VALU | BF_FLAG_TILE_MFMA | BF_FLAG_MFMA_FP32)))
       return fail(BF_EUNSUPPORTED,
                   "sigma_r too small for float32: T/sigma_r above 13 runs only the plain forward Gaussian "
-                  "(zero border, no adjoint, split-bfloat16 streamed passes)");
+                  "(no adjoint or cross filter, split-bfloat16 streamed passes)");
     if (!ls_wide_supported(p.W)) return fail(BF_EUNSUPPORTED, "T/sigma_r above 13: Gaussian W <= 120");
     fp->engine = BF_PATH_WIDE;
     return BF_OK;

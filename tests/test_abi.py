@@ -159,9 +159,10 @@ def test_wide_range_planning():
         assert info.N == O.order_for_delta(1e-3, K.w0("gauss", sigma_s=ss), 127.5, sr)
         assert P.bf_order("gauss", sr, sigma_s=ss).path == L.BF_PATH_WIDE  # no size needed
     assert P.bf_order("gauss", 9.8, sigma_s=2.0, **kw).path != L.BF_PATH_WIDE      # lambda 169.3
+    assert P.bf_order("gauss", 6.0, sigma_s=2.0, mirror=True, **kw).path == L.BF_PATH_WIDE
     assert P.bf_order("gauss", 5.0, sigma_s=2.0, T=60.0, **kw).path != L.BF_PATH_WIDE  # data range
     bad = [dict(kernel="box", W=3), dict(kernel="gauss", sigma_s=2.0, grad=True),
-           dict(kernel="gauss", sigma_s=2.0, mirror=True), dict(kernel="gauss", sigma_s=2.0, joint=True),
+           dict(kernel="gauss", sigma_s=2.0, joint=True),
            dict(kernel="gauss", sigma_s=2.0, engine="valu"), dict(kernel="gauss", sigma_s=2.0, engine="mfma"),
            dict(kernel="gauss", sigma_s=2.0, mfma_fp32=True), dict(kernel="gauss", sigma_s=41.0),
            dict(kernel="gauss_rec", sigma_s=2.0)]

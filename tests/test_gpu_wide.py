@@ -117,12 +117,31 @@ def test_full_size_sampled(ss, sr):
     assert np.abs(got - ref).max() <= TOL
 
 
+@pytest.mark.parametrize("ss,sr,shape", [(2.0, 5.0, (40, 70)), (12.0, 6.0, (90, 120)), (30.0, 8.0, (150, 170))])
+def test_mirror_border(ss, sr, shape):
+    # the reflecting border on the wide-range passes (W = 6, 36, 90), against eq. (GPA) on the
+    # reflected extension, at every pixel of the small image and sampled ones of the larger
+    from oracle import mirror as M
+    f = synthimg.gen2(*shape, 71)
+    out, plan, fx = _forward(f, sr, ss, mirror=True)
+    w2 = K.taps2d("gauss", sigma_s=ss)
+    if shape[0] * shape[1] <= 4000:
+        ref = M.gpa_pairwise(fx, w2, sr, plan.info.N, 127.5, wide=True)
+        d = out - ref
+    else:
+        px = _sample(*shape, 20, 72)
+        d = out[px[:, 0], px[:, 1]] - M.gpa_pairwise_at(fx, px, w2, sr, plan.info.N, 127.5, wide=True)
+    print(f"sigma_s={ss} sigma_r={sr} W={plan.info.W} N={plan.info.N}", flush=True)
+    _report("gpu-oracle", d)
+    assert np.abs(d).max() <= TOL
+
+
 def test_unsupported_and_saved():
     torch, P = _mods()
     plan = P.Plan("gauss", 6.0, 32, 32, sigma_s=2.0)
     x = torch.zeros(32, 32, device="cuda")
     with pytest.raises(P.BFError):
         plan.forward(x, saved=torch.empty(3 * 32 * 32, device="cuda"))
-    for kw in (dict(grad=True), dict(mirror=True), dict(mfma_fp32=True)):
+    for kw in (dict(grad=True), dict(mfma_fp32=True)):
         with pytest.raises(P.BFError):
             P.Plan("gauss", 6.0, 32, 32, sigma_s=2.0, **kw)

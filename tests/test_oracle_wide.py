@@ -76,3 +76,18 @@ def test_pairwise_wide_meets_accuracy_bound():
     px = np.array([[0, 0], [13, 16], [7, 8], [3, 15]])
     at = G.gpa_pairwise_at(f, px, w2, sr, N, 127.5, wide=True)
     assert np.abs(at - got[px[:, 0], px[:, 1]]).max() <= 1e-9
+
+
+def test_mirror_pairwise_wide_meets_accuracy_bound():
+    # the reflected extension at sigma_r = 3.5: eq. (GPA) in log space against eq. (BF), and the
+    # pixel-sampled form against the full one
+    from oracle import mirror as M
+    f = synthimg.gen1(12, 15, 73)
+    w2 = K.taps2d(K.GAUSS, sigma_s=1.0)
+    sr, T = 3.5, 127.5
+    eps = K.w0(K.GAUSS, sigma_s=1.0) * 1e-3 / (2 * T + 1e-3)
+    N = O.chernoff_order(O.lam_of(T, sr), eps)
+    got = M.gpa_pairwise(f, w2, sr, N, 127.5, wide=True)
+    assert np.abs(got - M.direct_bf(f, w2, sr)).max() <= 1e-3
+    px = np.array([[0, 0], [11, 14], [5, 7]])
+    assert np.abs(M.gpa_pairwise_at(f, px, w2, sr, N, 127.5, wide=True) - got[px[:, 0], px[:, 1]]).max() <= 1e-9
