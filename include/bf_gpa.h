@@ -176,10 +176,11 @@ int bf_forward(const bf_plan_t* plan, const float* in, int64_t in_pitch,
 
 /* Video and volume data, the extension named in Sec. 1 and Sec. 5: D slices
  * of height x width (p->height, p->width), the kernel w1 x w1 x w1 on the cube
- * [-W, W]^3 (box or truncated Gaussian, W <= 32), zero extension, Algorithm 2
- * with three-axis filtering; N from the rule of bf_plan with the centre weight
- * (w1(0) / sum w1)^3.  Plain forward filter only: BF_FLAG_GRAD, JOINT, MIRROR,
- * TILE_VALU and TILE_MFMA return BF_EUNSUPPORTED, as does BF_GAUSS_REC.
+ * [-W, W]^3 (box or truncated Gaussian, W <= 32), zero extension or, with
+ * BF_FLAG_MIRROR, reflection about every face (edge samples repeated), Algorithm
+ * 2 with three-axis filtering; N from the rule of bf_plan with the centre weight
+ * (w1(0) / sum w1)^3.  Forward filter only: BF_FLAG_GRAD, JOINT, TILE_VALU and
+ * TILE_MFMA return BF_EUNSUPPORTED, as does BF_GAUSS_REC.
  * Allocates about 80 bytes per voxel.  *out is owned by the caller
  * (bf_destroy). */
 int bf_plan_volume(const bf_params* p, int32_t depth, bf_plan_t** out);

@@ -11,7 +11,8 @@ three axes.  The normalised centre weight of Prop. (accuracy) becomes
 w(0) = (w1(0) / sum_a w1(a))^3.
 
 Volumes are (D, H, W) arrays (slice, row, column); the border reading is
-the zero extension of ``oracle.bf``.
+the zero extension of ``oracle.bf``, or reflection about every face (the
+``_mirror`` forms, as ``oracle.mirror`` for images).
 """
 from __future__ import annotations
 
@@ -103,6 +104,34 @@ def gpa_alg2(f: np.ndarray, w1: np.ndarray, sigma_r: float, N: int, T: float) ->
         P = P + G * Fbar
         G = Hh * G / n
     return sigma_r * (P / Q) + T
+
+
+def _reflect_pad(f: np.ndarray, W: int) -> np.ndarray:
+    return np.pad(np.asarray(f, dtype=np.float64), W, mode="symmetric")
+
+
+def direct_bf_mirror(f: np.ndarray, w1: np.ndarray, sigma_r: float) -> np.ndarray:
+    """eq. (BF) on the volume extended by reflection about every face (edge
+    samples repeated): the zero-extension filter on the reflect-padded volume,
+    centre crop (every window then lies inside the padding)."""
+    W = len(w1) // 2
+    D, H, Wd = np.shape(f)
+    return direct_bf(_reflect_pad(f, W), w1, sigma_r)[W:W + D, W:W + H, W:W + Wd]
+
+
+def gpa_pairwise_mirror(f: np.ndarray, w1: np.ndarray, sigma_r: float, N: int, center: float) -> np.ndarray:
+    """eq. (GPA) pair by pair on the reflected extension of the volume."""
+    W = len(w1) // 2
+    D, H, Wd = np.shape(f)
+    return gpa_pairwise(_reflect_pad(f, W), w1, sigma_r, N, center)[W:W + D, W:W + H, W:W + Wd]
+
+
+def gpa_alg2_mirror(f: np.ndarray, w1: np.ndarray, sigma_r: float, N: int, T: float) -> np.ndarray:
+    """Algorithm 2 on the reflected extension (the auxiliary images are
+    pointwise in f, so extending f extends them)."""
+    W = len(w1) // 2
+    D, H, Wd = np.shape(f)
+    return gpa_alg2(_reflect_pad(f, W), w1, sigma_r, N, T)[W:W + D, W:W + H, W:W + Wd]
 
 
 def w0(w1: np.ndarray) -> float:

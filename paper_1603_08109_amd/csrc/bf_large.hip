@@ -90,9 +90,11 @@ __global__ __launch_bounds__(kThreads) void ls_rows_kernel(TileParams p, LsState
     for (int u = 0; u < 4; ++u) {
       const int q = q0 + u * kThreads;
       const int row = q / RWp, col = q - row * RWp;
-      const int gr = r0 + row, gc = c0 - W + col;
+      const int gr = r0 + row;
+      int gc = c0 - W + col;
       F[u] = 0.f;
       y[u] = 0.f;
+      if (p.mirror) gc = reflect_index(gc, p.Wd);  // mirror border: halo columns read their reflections
       if (q < npx && col < RW && gr < p.H && gc >= 0 && gc < p.Wd) {
         const int64_t j = (int64_t)gr * st.pitch + gc;
         F[u] = Fin[j];

@@ -760,8 +760,8 @@ int bf_plan_volume(const bf_params* in, int32_t depth, bf_plan_t** out) {
   if (st < 0) return st;
   if (p.height <= 0 || p.width <= 0) return fail(BF_EINVAL, "height and width must be > 0");
   if (p.kernel == BF_GAUSS_REC) return fail(BF_EUNSUPPORTED, "volumes take the box or the truncated Gaussian");
-  if (p.flags & (BF_FLAG_GRAD | BF_FLAG_JOINT | BF_FLAG_MIRROR | BF_FLAG_TILE_VALU | BF_FLAG_TILE_MFMA))
-    return fail(BF_EUNSUPPORTED, "volumes: plain forward filter, zero border, streamed engine only");
+  if (p.flags & (BF_FLAG_GRAD | BF_FLAG_JOINT | BF_FLAG_TILE_VALU | BF_FLAG_TILE_MFMA))
+    return fail(BF_EUNSUPPORTED, "volumes: forward filter (zero or mirror border), streamed engine only");
   if (p.W > kVolMaxW) return fail(BF_EUNSUPPORTED, "volumes: W <= 32");
   if ((int64_t)depth * p.height > (1 << 30) / std::max(1, p.width))
     return fail(BF_EUNSUPPORTED, "volume too large");

@@ -1,5 +1,6 @@
 // Video and volume data (the extension Sec. 1 and Sec. 5 name): D slices of
-// Hs x Wd, kernel w1 x w1 x w1 on the cube [-W, W]^3, zero extension.
+// Hs x Wd, kernel w1 x w1 x w1 on the cube [-W, W]^3, zero extension or (with
+// p.mirror) reflection about every face, edge samples repeated.
 // Algorithm 2 is unchanged; only the spatial filtering runs over three axes.
 //
 // The slices are stacked as one image of D Hs rows (voxel (d, r, c) at row
@@ -51,10 +52,16 @@ __global__ __launch_bounds__(256) void vol_cols_kernel(TileParams p, LsState st,
       const int R = R0 + 16 * rg + j;  // stacked row
       if (R >= p.H || c0 + c >= p.Wd) continue;
       const int d0 = (R / Hs) * Hs;  // first row of this slice
-      const int lo = max(-W, d0 - R), hi = min(W, d0 + Hs - 1 - R);
-      const float* col = lds + (R - R0 + W) * kVolTile + c;
       float acc = 0.f;
-      for (int a = lo; a <= hi; ++a) acc += tz[a + W] * col[a * kVolTile];
+      if (p.mirror) {
+        // reflected rows stay in this slice and within W of R: inside the staged window
+        const float* base = lds + (d0 - R0 + W) * kVolTile + c;
+        for (int a = -W; a <= W; ++a) acc += tz[a + W] * base[reflect_index(R - d0 + a, Hs) * kVolTile];
+      } else {
+        const int lo = max(-W, d0 - R), hi = min(W, d0 + Hs - 1 - R);
+        const float* col = lds + (R - R0 + W) * kVolTile + c;
+        for (int a = lo; a <= hi; ++a) acc += tz[a + W] * col[a * kVolTile];
+      }
       Gk[(int64_t)R * p.Wd + c0 + c] = acc;
     }
   }
@@ -83,8 +90,12 @@ __global__ __launch_bounds__(256) void vol_depth_kernel(TileParams p, LsState st
       const int d = d0 + t;
       float acc = 0.f;
       if (t < nok) {
-        const int lo = max(-W, -d), hi = min(W, D - 1 - d);
-        for (int a = lo; a <= hi; ++a) acc += tz[a + W] * Gk[(int64_t)(d + a) * plane];
+        if (p.mirror) {
+          for (int a = -W; a <= W; ++a) acc += tz[a + W] * Gk[(int64_t)reflect_index(d + a, D) * plane];
+        } else {
+          const int lo = max(-W, -d), hi = min(W, D - 1 - d);
+          for (int a = lo; a <= hi; ++a) acc += tz[a + W] * Gk[(int64_t)(d + a) * plane];
+        }
       }
       px.fold(t, n, p.N, acc, in1);
     }

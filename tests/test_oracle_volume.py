@@ -85,3 +85,54 @@ def test_constants_and_convergence():
 def test_order_weight():
     w1 = K.taps1d(K.GAUSS, sigma_s=2.0)
     assert V.w0(w1) == pytest.approx(K.w0("gauss", sigma_s=2.0) ** 1.5, rel=1e-12)
+
+
+def _reflect(i, n):
+    # reflection about the faces with the edge sample repeated: period 2n
+    m = i % (2 * n)
+    return m if m < n else 2 * n - 1 - m
+
+
+def test_mirror_direct_bruteforce():
+    # D = 2 and H = 3 below W = 2.. so the reflection wraps more than once
+    f = _vol(2, 3, 5, 6)
+    w1 = K.taps1d(K.GAUSS, sigma_s=0.8)
+    W = len(w1) // 2
+    D, H, Wd = f.shape
+    ref = np.empty_like(f)
+    for d in range(D):
+        for r in range(H):
+            for c in range(Wd):
+                num = den = 0.0
+                for a in range(-W, W + 1):
+                    for b in range(-W, W + 1):
+                        for e in range(-W, W + 1):
+                            v = f[_reflect(d - a, D), _reflect(r - b, H), _reflect(c - e, Wd)]
+                            k = w1[W + a] * w1[W + b] * w1[W + e] * np.exp(-(v - f[d, r, c]) ** 2 / (2 * 20.0 ** 2))
+                            num += k * v
+                            den += k
+                ref[d, r, c] = num / den
+    assert np.allclose(V.direct_bf_mirror(f, w1, 20.0), ref, rtol=0, atol=1e-10)
+
+
+@pytest.mark.parametrize("N", [2, 12, 40])
+def test_mirror_alg2_equals_pairwise(N):
+    f = _vol(3, 5, 6, 7)
+    w1 = K.taps1d(K.BOX, W=2)
+    a = V.gpa_alg2_mirror(f, w1, 30.0, N, 127.5)
+    b = V.gpa_pairwise_mirror(f, w1, 30.0, N, 127.5)
+    assert np.abs(a - b).max() < 1e-8 * max(1.0, np.abs(b).max())
+
+
+def test_mirror_single_slice_and_limits():
+    # D = 1: every depth tap reads the same slice, so the weights factor out and
+    # the result is the 2-D mirror filter; constants stay; large N meets eq. (BF)
+    from oracle import mirror as M
+    f = synthimg.gen1(9, 11, 8)
+    w1 = K.taps1d(K.GAUSS, sigma_s=1.2)
+    assert np.allclose(V.direct_bf_mirror(f[None], w1, 25.0)[0], M.direct_bf(f, np.outer(w1, w1), 25.0),
+                       rtol=0, atol=1e-10)
+    assert np.abs(V.gpa_alg2_mirror(np.full((2, 4, 5), 77.0), w1, 10.0, 6, 127.5) - 77.0).max() < 1e-9
+    g = _vol(3, 4, 6, 9)
+    exact = V.direct_bf_mirror(g, w1, 30.0)
+    assert np.abs(V.gpa_alg2_mirror(g, w1, 30.0, 80, 127.5) - exact).max() < 1e-8
