@@ -180,7 +180,9 @@ int bf_forward(const bf_plan_t* plan, const float* in, int64_t in_pitch,
  * BF_FLAG_MIRROR, reflection about every face (edge samples repeated), Algorithm
  * 2 with three-axis filtering; N from the rule of bf_plan with the centre weight
  * (w1(0) / sum w1)^3.  Forward filter only: BF_FLAG_GRAD, JOINT, TILE_VALU and
- * TILE_MFMA return BF_EUNSUPPORTED, as does BF_GAUSS_REC.
+ * TILE_MFMA return BF_EUNSUPPORTED, as does BF_GAUSS_REC.  T/sigma_r above 13
+ * (lambda in (170, 1400]) takes the Gaussian only, on the float64-state passes
+ * of BF_PATH_WIDE (not with BF_FLAG_MFMA_FP32).
  * Allocates about 80 bytes per voxel.  *out is owned by the caller
  * (bf_destroy). */
 int bf_plan_volume(const bf_params* p, int32_t depth, bf_plan_t** out);

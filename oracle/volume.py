@@ -19,7 +19,7 @@ from __future__ import annotations
 import numpy as np
 
 from .bf import range_kernel
-from .gpa import phi
+from .gpa import phi, phi_wide
 
 
 def _shifted(pad: np.ndarray, W: int, a: int, b: int, c: int, shape) -> np.ndarray:
@@ -46,8 +46,11 @@ def direct_bf(f: np.ndarray, w1: np.ndarray, sigma_r: float) -> np.ndarray:
     return num / den
 
 
-def gpa_pairwise(f: np.ndarray, w1: np.ndarray, sigma_r: float, N: int, center: float) -> np.ndarray:
-    """eq. (GPA) on the centred volume, pair by pair."""
+def gpa_pairwise(f: np.ndarray, w1: np.ndarray, sigma_r: float, N: int, center: float,
+                 wide: bool = False) -> np.ndarray:
+    """eq. (GPA) on the centred volume, pair by pair (wide: phi in log space,
+    ``oracle.gpa.phi_wide``, finite for T / sigma_r up to 37.4)."""
+    ph = phi_wide if wide else phi
     h = np.asarray(f, dtype=np.float64) - center
     W = len(w1) // 2
     pad = np.pad(h, W)
@@ -59,7 +62,7 @@ def gpa_pairwise(f: np.ndarray, w1: np.ndarray, sigma_r: float, N: int, center: 
             for c in range(-W, W + 1):
                 sh = _shifted(pad, W, a, b, c, h.shape)
                 ok = _shifted(valid, W, a, b, c, h.shape)
-                k = w1[W + a] * w1[W + b] * w1[W + c] * phi(sh, h, sigma_r, N) * ok
+                k = w1[W + a] * w1[W + b] * w1[W + c] * ph(sh, h, sigma_r, N) * ok
                 num += k * sh
                 den += k
     return num / den + center
@@ -119,11 +122,12 @@ def direct_bf_mirror(f: np.ndarray, w1: np.ndarray, sigma_r: float) -> np.ndarra
     return direct_bf(_reflect_pad(f, W), w1, sigma_r)[W:W + D, W:W + H, W:W + Wd]
 
 
-def gpa_pairwise_mirror(f: np.ndarray, w1: np.ndarray, sigma_r: float, N: int, center: float) -> np.ndarray:
+def gpa_pairwise_mirror(f: np.ndarray, w1: np.ndarray, sigma_r: float, N: int, center: float,
+                        wide: bool = False) -> np.ndarray:
     """eq. (GPA) pair by pair on the reflected extension of the volume."""
     W = len(w1) // 2
     D, H, Wd = np.shape(f)
-    return gpa_pairwise(_reflect_pad(f, W), w1, sigma_r, N, center)[W:W + D, W:W + H, W:W + Wd]
+    return gpa_pairwise(_reflect_pad(f, W), w1, sigma_r, N, center, wide=wide)[W:W + D, W:W + H, W:W + Wd]
 
 
 def gpa_alg2_mirror(f: np.ndarray, w1: np.ndarray, sigma_r: float, N: int, T: float) -> np.ndarray:

@@ -754,4 +754,55 @@ struct LsPix {
   }
 };
 
+// Wide range: per-pixel a~_n = e^{-x_i^2/2} x_i^n / sqrt(n!) in float64, so
+// a~_n F~_n is the term of eq. (Q) and sqrt(n) a~_{n-1} F~_n that of eq. (P)
+// (without the X of the range-safe form); every factor is at most 1.
+template <int CH>
+struct WidePix {
+  double a[CH], ap[CH], P[CH], Q[CH];
+  float z[CH];
+  __device__ __forceinline__ void load(const LsState& st, int64_t i0, int64_t stride, int n_ok) {
+    load_part<CH>(st, 0, i0, stride, n_ok);
+  }
+  __device__ __forceinline__ void store(const LsState& st, int64_t i0, int64_t stride, int n_ok) const {
+    store_part<CH>(st, 0, i0, stride, n_ok);
+  }
+  template <int M>
+  __device__ __forceinline__ void load_part(const LsState& st, int s0, int64_t i0, int64_t stride, int n_ok) {
+#pragma unroll
+    for (int u = 0; u < M; ++u) {
+      const int s = s0 + u;
+      const bool ok = u < n_ok;
+      const int64_t i = ok ? i0 + u * stride : 0;
+      a[s] = ok ? st.ad[i] : 0.0;
+      ap[s] = ok ? st.apd[i] : 0.0;
+      z[s] = ok ? st.z[i] : 0.f;
+      P[s] = ok ? st.P[i] : 0.0;
+      Q[s] = ok ? st.Q[i] : 0.0;
+    }
+  }
+  template <int M>
+  __device__ __forceinline__ void store_part(const LsState& st, int s0, int64_t i0, int64_t stride,
+                                             int n_ok) const {
+#pragma unroll
+    for (int u = 0; u < M; ++u) {
+      const int s = s0 + u;
+      if (u < n_ok) {
+        const int64_t i = i0 + u * stride;
+        st.ad[i] = a[s];
+        st.apd[i] = ap[s];
+        st.P[i] = P[s];
+        st.Q[i] = Q[s];
+      }
+    }
+  }
+  // fold F~_bar_n (value v at pixel s); g1 = 1 / sqrt(n + 1), sn = sqrt(n)
+  __device__ __forceinline__ void fold(int s, int n, int N, float v, double g1, double sn) {
+    if (n < N) Q[s] = fma(a[s], (double)v, Q[s]);
+    if (n >= 1) P[s] = fma(ap[s] * sn, (double)v, P[s]);
+    ap[s] = a[s];
+    a[s] = a[s] * (double)z[s] * g1;
+  }
+};
+
 }  // namespace bfgpa

@@ -152,6 +152,9 @@ double rg_w0(double sigma_s);
 bool ls_x3_supported(int W);
 bool ls_wide_supported(int W);
 hipError_t launch_forward_wide(const TileParams& p, const LsState& st, hipStream_t s);
+// pieces of the wide-range sequence for the volume path: the float64 lift and one block's row pass
+hipError_t wide_launch_init(const TileParams& p, const LsState& st, hipStream_t s);
+hipError_t launch_rows_x3_wide(const TileParams& p, const LsState& st, int n0, int K, int src, hipStream_t s);
 int64_t ls_rows_x3_lds_bytes(int W);
 int64_t ls_cols_x3_lds_bytes(int W);
 hipError_t launch_rows_x3(const TileParams& p, const LsState& st, int n0, int K, int src, int grid, hipStream_t s);
@@ -167,8 +170,8 @@ constexpr int kVolMaxW = 32;
 struct VolBufs {
   float* G[kLsBlock];  // per order of a block: the row- and column-filtered volume
 };
-int64_t vol_state_bytes(int D, int Hs, int Wd, int W);
-LsState vol_layout(void* base, int D, int Hs, int Wd, int W, VolBufs* g);
+int64_t vol_state_bytes(int D, int Hs, int Wd, int W, bool wide = false);
+LsState vol_layout(void* base, int D, int Hs, int Wd, int W, VolBufs* g, bool wide = false);
 hipError_t launch_forward_vol(const TileParams& p, const LsState& st, const VolBufs& g, int D, int Hs, hipStream_t s);
 
 // fused Gaussian tile with both FIR passes on the matrix cores (W <= 45)

@@ -318,50 +318,6 @@ __device__ __forceinline__ void x3_stage(const float* __restrict__ Hk, int64_t p
   }
 }
 
-// Wide range: per-pixel a~_n = e^{-x_i^2/2} x_i^n / sqrt(n!) in float64, so
-// a~_n F~_n is the term of eq. (Q) and sqrt(n) a~_{n-1} F~_n that of eq. (P)
-// (without the X of the range-safe form); every factor is at most 1.
-template <int CH>
-struct WidePix {
-  double a[CH], ap[CH], P[CH], Q[CH];
-  float z[CH];
-  template <int M>
-  __device__ __forceinline__ void load_part(const LsState& st, int s0, int64_t i0, int64_t stride, int n_ok) {
-#pragma unroll
-    for (int u = 0; u < M; ++u) {
-      const int s = s0 + u;
-      const bool ok = u < n_ok;
-      const int64_t i = ok ? i0 + u * stride : 0;
-      a[s] = ok ? st.ad[i] : 0.0;
-      ap[s] = ok ? st.apd[i] : 0.0;
-      z[s] = ok ? st.z[i] : 0.f;
-      P[s] = ok ? st.P[i] : 0.0;
-      Q[s] = ok ? st.Q[i] : 0.0;
-    }
-  }
-  template <int M>
-  __device__ __forceinline__ void store_part(const LsState& st, int s0, int64_t i0, int64_t stride,
-                                             int n_ok) const {
-#pragma unroll
-    for (int u = 0; u < M; ++u) {
-      const int s = s0 + u;
-      if (u < n_ok) {
-        const int64_t i = i0 + u * stride;
-        st.ad[i] = a[s];
-        st.apd[i] = ap[s];
-        st.P[i] = P[s];
-        st.Q[i] = Q[s];
-      }
-    }
-  }
-  // fold F~_bar_n (value v at pixel s); g1 = 1 / sqrt(n + 1), sn = sqrt(n)
-  __device__ __forceinline__ void fold(int s, int n, int N, float v, double g1, double sn) {
-    if (n < N) Q[s] = fma(a[s], (double)v, Q[s]);
-    if (n >= 1) P[s] = fma(ap[s] * sn, (double)v, P[s]);
-    ap[s] = a[s];
-    a[s] = a[s] * (double)z[s] * g1;
-  }
-};
 
 template <int S, bool SAVE, bool WIDE>
 __global__ __launch_bounds__(kX3ColsThreads) void ls_cols_x3_kernel(TileParams p, LsState st, int n0, int K) {
@@ -539,6 +495,18 @@ __global__ __launch_bounds__(256) void wide_init_kernel(TileParams p, LsState st
     st.P[i] = 0.0;
     st.Q[i] = 0.0;
   }
+}
+
+hipError_t wide_launch_init(const TileParams& p, const LsState& st, hipStream_t s) {
+  const int64_t npx = (int64_t)p.H * p.Wd;
+  const int g1 = (int)std::min<int64_t>((npx + 255) / 256, 4096);
+  hipLaunchKernelGGL(wide_init_kernel, dim3(g1), dim3(256), 0, s, p, st);
+  return hipGetLastError();
+}
+
+hipError_t launch_rows_x3_wide(const TileParams& p, const LsState& st, int n0, int K, int src, hipStream_t s) {
+  const int grow = ((p.H + kLsRows - 1) / kLsRows) * ((p.Wd + kLsCols - 1) / kLsCols);
+  return rows_x3_t<true>(p, st, n0, K, src, grow, s);
 }
 
 bool ls_wide_supported(int W) {

@@ -768,13 +768,17 @@ int bf_plan_volume(const bf_params* in, int32_t depth, bf_plan_t** out) {
   bf_plan_info info;
   const int ost = plan_order(&p, &info, 3);
   if (ost < 0) return ost;
-  if (info.lambda > kLambdaF32)
-    return fail(BF_EUNSUPPORTED, "sigma_r too small for float32 volumes: need T/sigma_r <= 13");
+  // T/sigma_r above 13: the Gaussian's float64-state (wide-range) passes
+  const bool wide = info.lambda > kLambdaF32;
+  if (wide && (p.kernel != BF_GAUSS || (p.flags & BF_FLAG_MFMA_FP32)))
+    return fail(BF_EUNSUPPORTED, "sigma_r too small for float32 volumes: T/sigma_r above 13 takes the Gaussian "
+                                 "on its split-bfloat16 passes only");
   bf_plan_t* pl = new (std::nothrow) bf_plan_t();
   if (!pl) return fail(BF_ENOMEM, "host allocation failed");
   pl->p = p;
   pl->info = info;
   pl->info.path = BF_PATH_VOLUME;
+  pl->wide = wide;
   pl->variant = -1;
   pl->bvariant = -1;
   pl->depth = depth;
@@ -787,7 +791,7 @@ int bf_plan_volume(const bf_params* in, int32_t depth, bf_plan_t** out) {
   if (e != hipSuccess) { delete pl; return fail(BF_ENOMEM, "hipMalloc tables failed"); }
   e = hipMemcpy(pl->d_const, h.data(), bytes, hipMemcpyHostToDevice);
   if (e != hipSuccess) { hipFree(pl->d_const); delete pl; return hip_fail(e, "hipMemcpy tables"); }
-  const int64_t vb = vol_state_bytes(depth, p.height, p.width, p.W);
+  const int64_t vb = vol_state_bytes(depth, p.height, p.width, p.W, wide);
   e = hipMalloc(&pl->d_ls, vb);
   if (e == hipSuccess) {
     e = hipMemset(pl->d_ls, 0, vb);  // zero rows around the row-filtered images
@@ -798,7 +802,7 @@ int bf_plan_volume(const bf_params* in, int32_t depth, bf_plan_t** out) {
     delete pl;
     return e == hipErrorOutOfMemory ? fail(BF_ENOMEM, "hipMalloc volume state failed") : hip_fail(e, "volume state");
   }
-  pl->ls_state = vol_layout(pl->d_ls, depth, p.height, p.width, p.W, &pl->vol);
+  pl->ls_state = vol_layout(pl->d_ls, depth, p.height, p.width, p.W, &pl->vol, wide);
   pl->info.workspace_bytes = (int64_t)bytes + vb;
   *out = pl;
   if (ost == BF_WNOGUARANTEE) set_error("order below the bound: no +-delta guarantee");

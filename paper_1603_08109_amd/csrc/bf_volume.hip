@@ -16,6 +16,7 @@
 #include <algorithm>
 #include <cstdint>
 #include <cstring>
+#include <type_traits>
 
 #include "bf_device.h"
 #include "bf_internal.h"
@@ -69,6 +70,8 @@ __global__ __launch_bounds__(256) void vol_cols_kernel(TileParams p, LsState st,
 
 // FIR across slices and the fold into eqs. (P), (Q): thread q of the slice
 // plane, voxels at depths d0 .. d0 + kVolDepth - 1.
+// WIDE: the wide-range float64 states (see ls_rows_x3_kernel), folded without the X of eq. (P)
+template <bool WIDE>
 __global__ __launch_bounds__(256) void vol_depth_kernel(TileParams p, LsState st, VolBufs g, int n0, int K, int Hs,
                                                         int D) {
   const int64_t plane = (int64_t)Hs * p.Wd;
@@ -78,13 +81,14 @@ __global__ __launch_bounds__(256) void vol_depth_kernel(TileParams p, LsState st
   const int nok = live ? std::min(kVolDepth, D - d0) : 0;
   const int W = p.W;
   const float* tz = p.taps + kTapPad;
-  LsPix<kVolDepth, false> px;
+  typename std::conditional<WIDE, WidePix<kVolDepth>, LsPix<kVolDepth, false>>::type px;
   const int64_t i0 = (int64_t)d0 * plane + (live ? q : 0);
   px.load(st, i0, plane, nok);
   for (int k = 0; k < K; ++k) {
     const float* Gk = g.G[k] + (live ? q : 0);
     const int n = n0 + k;
     const float in1 = p.inv_tab[n + 1];
+    const double g1 = WIDE ? p.isq[n + 1] : 0.0, sn = WIDE ? p.sq[n] : 0.0;
 #pragma unroll
     for (int t = 0; t < kVolDepth; ++t) {
       const int d = d0 + t;
@@ -97,21 +101,24 @@ __global__ __launch_bounds__(256) void vol_depth_kernel(TileParams p, LsState st
           for (int a = lo; a <= hi; ++a) acc += tz[a + W] * Gk[(int64_t)(d + a) * plane];
         }
       }
-      px.fold(t, n, p.N, acc, in1);
+      if constexpr (WIDE)
+        px.fold(t, n, p.N, acc, g1, sn);
+      else
+        px.fold(t, n, p.N, acc, in1);
     }
   }
   px.store(st, i0, plane, nok);
 }
 
-int64_t vol_state_bytes(int D, int Hs, int Wd, int W) {
+int64_t vol_state_bytes(int D, int Hs, int Wd, int W, bool wide) {
   const int64_t H = (int64_t)D * Hs;
-  return ls_state_bytes((int)H, Wd, W, false) + kLsBlock * (H * Wd * 4 + 256);
+  return ls_state_bytes((int)H, Wd, W, false, wide) + kLsBlock * (H * Wd * 4 + 256);
 }
 
-LsState vol_layout(void* base, int D, int Hs, int Wd, int W, VolBufs* g) {
+LsState vol_layout(void* base, int D, int Hs, int Wd, int W, VolBufs* g, bool wide) {
   const int H = D * Hs;
-  LsState st = ls_layout(base, H, Wd, W, false);
-  char* q = (char*)base + ls_state_bytes(H, Wd, W, false);
+  LsState st = ls_layout(base, H, Wd, W, false, wide);
+  char* q = (char*)base + ls_state_bytes(H, Wd, W, false, wide);
   for (int k = 0; k < kLsBlock; ++k) {
     g->G[k] = (float*)q;
     q += ((int64_t)H * Wd * 4 + 255) & ~255LL;
@@ -123,7 +130,8 @@ hipError_t launch_forward_vol(const TileParams& p, const LsState& st, const VolB
                               hipStream_t s) {
   if (p.H <= 0 || p.Wd <= 0) return hipSuccess;
   if (p.W > kVolMaxW || p.H != D * Hs) return hipErrorInvalidValue;
-  hipError_t e = ls_launch_init(p, st, s);
+  if (p.wide && (p.kt != BF_GAUSS || !st.Fd[0])) return hipErrorInvalidValue;
+  hipError_t e = p.wide ? wide_launch_init(p, st, s) : ls_launch_init(p, st, s);
   if (e != hipSuccess) return e;
   const int tiles = ((p.H + kVolTile - 1) / kVolTile) * ((p.Wd + kVolTile - 1) / kVolTile);
   const size_t clds = (size_t)(kVolTile + 2 * p.W) * kVolTile * 4;
@@ -131,10 +139,13 @@ hipError_t launch_forward_vol(const TileParams& p, const LsState& st, const VolB
   int src = 0;
   for (int n0 = 0; n0 <= p.N; n0 += kLsBlock) {
     const int K = std::min(kLsBlock, p.N + 1 - n0);
-    e = ls_launch_rows(p, st, n0, K, src, s);
+    e = p.wide ? launch_rows_x3_wide(p, st, n0, K, src, s) : ls_launch_rows(p, st, n0, K, src, s);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(vol_cols_kernel, dim3(tiles), dim3(256), clds, s, p, st, g, K, Hs);
-    hipLaunchKernelGGL(vol_depth_kernel, gdep, dim3(256), 0, s, p, st, g, n0, K, Hs, D);
+    if (p.wide)
+      hipLaunchKernelGGL(vol_depth_kernel<true>, gdep, dim3(256), 0, s, p, st, g, n0, K, Hs, D);
+    else
+      hipLaunchKernelGGL(vol_depth_kernel<false>, gdep, dim3(256), 0, s, p, st, g, n0, K, Hs, D);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     src ^= 1;

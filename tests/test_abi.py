@@ -175,7 +175,7 @@ def test_wide_range_planning():
         P.bf_order("gauss", 3.4, sigma_s=2.0, **kw)                    # lambda 1406
     assert e.value.code == L.BF_EUNSUPPORTED
     with pytest.raises(L.BFError) as e:
-        P.VolumePlan("gauss", 6.0, 4, 32, 32, sigma_s=1.0)             # volumes: float32 range
+        P.VolumePlan("box", 6.0, 4, 32, 32, W=1)                      # volumes: the Gaussian only there
     assert e.value.code == L.BF_EUNSUPPORTED
 
 

@@ -137,6 +137,21 @@ def test_mirror_matches_oracle(kind, kw, sr, shape, seed):
     assert d.max() <= TOL
 
 
+@pytest.mark.parametrize("ss,sr,shape,mirror", [(1.0, 5.0, (4, 20, 30), False), (1.5, 6.0, (3, 16, 20), False),
+                                                (1.0, 4.0, (2, 10, 12), True)])
+def test_wide_range(ss, sr, shape, mirror):
+    # T/sigma_r above 13: the float64-state row pass and depth fold, against eq. (GPA)
+    # pair by pair in log space
+    torch, P = _mods()
+    f = _vol(*shape, 40)
+    out, plan, f32 = _run(f, "gauss", sr, sigma_s=ss, mirror=mirror)
+    w1 = _w1("gauss", dict(sigma_s=ss))
+    ref = (V.gpa_pairwise_mirror if mirror else V.gpa_pairwise)(f32, w1, sr, plan.info.N, 127.5, wide=True)
+    d = np.abs(out - ref)
+    print(f"wide sigma_s={ss} sigma_r={sr} {shape} mirror={mirror}: N={plan.info.N} max {d.max():.3e}", flush=True)
+    assert d.max() <= TOL
+
+
 def test_plan_weight_and_order():
     torch, P = _mods()
     from oracle import order as O

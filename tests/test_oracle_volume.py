@@ -136,3 +136,20 @@ def test_mirror_single_slice_and_limits():
     g = _vol(3, 4, 6, 9)
     exact = V.direct_bf_mirror(g, w1, 30.0)
     assert np.abs(V.gpa_alg2_mirror(g, w1, 30.0, 80, 127.5) - exact).max() < 1e-8
+
+
+def test_pairwise_wide_forms():
+    # phi in log space: the plain pair-by-pair form where that is finite, and the direct
+    # filter within the accuracy bound at sigma_r = 4 (lambda = 1016), on the zero and
+    # the reflected extension
+    f = _vol(3, 5, 6, 10)
+    w1 = K.taps1d(K.GAUSS, sigma_s=0.8)
+    a = V.gpa_pairwise(f, w1, 8.0, 300, 127.5)
+    b = V.gpa_pairwise(f, w1, 8.0, 300, 127.5, wide=True)
+    assert np.abs(a - b).max() < 1e-9
+    from oracle import order as O
+    eps = V.w0(w1) * 1e-3 / (2 * 127.5 + 1e-3)
+    N = O.chernoff_order(O.lam_of(127.5, 4.0), eps)
+    assert np.abs(V.gpa_pairwise(f, w1, 4.0, N, 127.5, wide=True) - V.direct_bf(f, w1, 4.0)).max() <= 1e-3
+    g = _vol(2, 4, 5, 11)
+    assert np.abs(V.gpa_pairwise_mirror(g, w1, 4.0, N, 127.5, wide=True) - V.direct_bf_mirror(g, w1, 4.0)).max() <= 1e-3
