@@ -13,6 +13,10 @@ with N and the support W held fixed.
   pair of 1-D convolutions) and lets torch.autograd differentiate it.
 * ``vjp_fd`` takes central finite differences of L = sum(gbar * out) with
   the numpy Algorithm 2 of ``oracle.gpa`` (a separate code path).
+* ``mirror=True`` on either: the same with the reflecting
+  border (image extended by reflection about its edges, edge samples
+  repeated); autograd differentiates the reflection as the gather it is, the
+  differences use the numpy ``oracle.mirror`` filter.
 """
 from __future__ import annotations
 
@@ -21,6 +25,7 @@ import torch
 
 from . import gpa as _gpa
 from . import kernels as _k
+from . import mirror as _mirror
 
 
 def _taps_torch(kind: str, sigma_s, W: int):
@@ -59,14 +64,22 @@ def gpa_torch(f: torch.Tensor, sigma_r: torch.Tensor, sigma_s, kind: str, W: int
 
 
 def vjp_autograd(f: np.ndarray, gbar: np.ndarray, kind: str, sigma_s, W: int,
-                 sigma_r: float, N: int, T: float):
-    """(dL/df, dL/dsigma_r, dL/dsigma_s) by float64 autograd; dsigma_s is NaN for box."""
+                 sigma_r: float, N: int, T: float, mirror: bool = False):
+    """(dL/df, dL/dsigma_r, dL/dsigma_s) by float64 autograd; dsigma_s is NaN for box.
+    mirror: the image is first extended by W on each side by reflection (a gather
+    with the reflected indices) and the output is the centre crop."""
     ft = torch.tensor(np.asarray(f, np.float64), requires_grad=True)
     sr = torch.tensor(float(sigma_r), dtype=torch.float64, requires_grad=True)
     ss = None
     if kind == _k.GAUSS:
         ss = torch.tensor(float(sigma_s), dtype=torch.float64, requires_grad=True)
-    out = gpa_torch(ft, sr, ss, kind, W, N, T)
+    if mirror:
+        H, Wd = ft.shape
+        ri = torch.as_tensor(_mirror.reflect_index(np.arange(-W, H + W), H))
+        ci = torch.as_tensor(_mirror.reflect_index(np.arange(-W, Wd + W), Wd))
+        out = gpa_torch(ft[ri][:, ci], sr, ss, kind, W, N, T)[W:W + H, W:W + Wd]
+    else:
+        out = gpa_torch(ft, sr, ss, kind, W, N, T)
     L = (out * torch.tensor(np.asarray(gbar, np.float64))).sum()
     inputs = [ft, sr] + ([ss] if ss is not None else [])
     grads = torch.autograd.grad(L, inputs)
@@ -74,26 +87,28 @@ def vjp_autograd(f: np.ndarray, gbar: np.ndarray, kind: str, sigma_s, W: int,
     return grads[0].numpy(), float(grads[1]), dss
 
 
-def _loss_np(f, gbar, kind, sigma_s, W, sigma_r, N, T):
+def _loss_np(f, gbar, kind, sigma_s, W, sigma_r, N, T, mirror=False):
     w1 = _k.taps1d(kind, sigma_s, W)
-    return float((np.asarray(gbar) * _gpa.gpa_alg2(f, w1, sigma_r, N, T)).sum())
+    alg2 = _mirror.gpa_alg2 if mirror else _gpa.gpa_alg2
+    return float((np.asarray(gbar) * alg2(f, w1, sigma_r, N, T)).sum())
 
 
 def vjp_fd(f: np.ndarray, gbar: np.ndarray, kind: str, sigma_s, W: int,
-           sigma_r: float, N: int, T: float, pixels, h: float = 1e-3):
+           sigma_r: float, N: int, T: float, pixels, h: float = 1e-3, mirror: bool = False):
     """Central differences (step h) of L = sum(gbar * out) with respect to
-    f at the listed pixels, sigma_r, and sigma_s (Gaussian; W fixed)."""
+    f at the listed pixels, sigma_r, and sigma_s (Gaussian; W fixed); mirror:
+    the reflecting-border filter of ``oracle.mirror``."""
     f = np.asarray(f, np.float64)
-    args = (kind, sigma_s, W, sigma_r, N, T)
+    args = (kind, sigma_s, W, sigma_r, N, T, mirror)
     df = []
     for (r, c) in pixels:
         fp = f.copy(); fp[r, c] += h
         fm = f.copy(); fm[r, c] -= h
         df.append((_loss_np(fp, gbar, *args) - _loss_np(fm, gbar, *args)) / (2 * h))
-    dsr = (_loss_np(f, gbar, kind, sigma_s, W, sigma_r + h, N, T)
-           - _loss_np(f, gbar, kind, sigma_s, W, sigma_r - h, N, T)) / (2 * h)
+    dsr = (_loss_np(f, gbar, kind, sigma_s, W, sigma_r + h, N, T, mirror)
+           - _loss_np(f, gbar, kind, sigma_s, W, sigma_r - h, N, T, mirror)) / (2 * h)
     dss = float("nan")
     if kind == _k.GAUSS:
-        dss = (_loss_np(f, gbar, kind, sigma_s + h, W, sigma_r, N, T)
-               - _loss_np(f, gbar, kind, sigma_s - h, W, sigma_r, N, T)) / (2 * h)
+        dss = (_loss_np(f, gbar, kind, sigma_s + h, W, sigma_r, N, T, mirror)
+               - _loss_np(f, gbar, kind, sigma_s - h, W, sigma_r, N, T, mirror)) / (2 * h)
     return np.array(df), dsr, dss

@@ -27,3 +27,25 @@ def test_autograd_matches_fd(kind, sigma_s, W):
         assert dss == pytest.approx(fd_ss, rel=1e-5, abs=1e-9)
     else:
         assert np.isnan(dss)
+
+
+@pytest.mark.parametrize("kind,sigma_s,W,shape", [(K.BOX, None, 2, (14, 13)), (K.GAUSS, 1.5, 5, (4, 13))])
+def test_mirror_autograd_matches_fd(kind, sigma_s, W, shape):
+    # the reflecting border: autograd through the reflected gather against central differences
+    # of the numpy mirror filter, at corners, edges and inside; (4, 13) with W = 5 reflects the
+    # rows more than once, so one pixel's value reaches a window through several reflections
+    f = synthimg.gen1(*shape, 5)
+    gbar = synthimg.gen2(*shape, 6) / 255.0 - 0.5
+    N, sr, T = 30, 30.0, 127.5
+    df, dsr, dss = GR.vjp_autograd(f, gbar, kind, sigma_s, W, sr, N, T, mirror=True)
+    H, Wd = shape
+    px = np.array([[0, 0], [H - 1, Wd - 1], [0, Wd // 2], [H // 2, 0], [H // 2, Wd - 2], [H - 1, 3]])
+    fd_f, fd_sr, fd_ss = GR.vjp_fd(f, gbar, kind, sigma_s, W, sr, N, T, px, h=1e-3, mirror=True)
+    scale = np.abs(df).max()
+    assert np.allclose(df[px[:, 0], px[:, 1]], fd_f, rtol=1e-5, atol=1e-7 * scale)
+    assert dsr == pytest.approx(fd_sr, rel=1e-5, abs=1e-9)
+    if kind == K.GAUSS:
+        assert dss == pytest.approx(fd_ss, rel=1e-5, abs=1e-9)
+    # the border changes the gradient: it is not the zero-border one
+    dz = GR.vjp_autograd(f, gbar, kind, sigma_s, W, sr, N, T)[0]
+    assert np.abs(dz - df).max() > 1e-3 * scale
