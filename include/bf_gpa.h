@@ -74,8 +74,9 @@ extern "C" {
 #define BF_FLAG_JOINT        8  /* cross (joint) filter: the range kernel acts on a guide
                                    image (bf_forward_joint); fused tiles only, no adjoint */
 #define BF_FLAG_MIRROR      16  /* reflecting border (edge samples repeated) instead of zero
-                                   extension; forward only (no adjoint), and on the streamed
-                                   path only for box W <= 96 and Gaussian W <= 124 */
+                                   extension; on the streamed path only for box W <= 96 and
+                                   Gaussian W <= 124; with BF_FLAG_GRAD the adjoint runs on
+                                   the image extended by W on each side (see bf_backward) */
 #define BF_FLAG_TILE_VALU   32  /* force the fused tile on the vector ALUs (the planner's
                                    choice otherwise); BF_EUNSUPPORTED if W does not fit */
 #define BF_FLAG_TILE_MFMA   64  /* force the fused 64 x 64 tile with both FIR passes on the
@@ -168,7 +169,8 @@ int bf_plan_clone_workspace(const bf_plan_t* plan, bf_plan_t** out);
  *           alias `in`
  *   saved   NULL, or device buffer of 3*height*width float32 that receives
  *           per-pixel state for bf_backward (layout: three planes of
- *           height*width, dense pitch = width)
+ *           height*width, dense pitch = width); must be NULL with
+ *           BF_FLAG_MIRROR (BF_EUNSUPPORTED)
  * Errors: BF_EINVAL for NULL pointers or pitches < width; BF_EHIP if the
  * launch fails. */
 int bf_forward(const bf_plan_t* plan, const float* in, int64_t in_pitch,
@@ -235,7 +237,14 @@ int bf_image_range(const float* in, int64_t pitch, int32_t height, int32_t width
  * The auxiliary images are recomputed, never stored (supports wider than the
  * fused adjoint tiles stream blocks of filtered adjoint images through the
  * plan's workspace).  Deterministic: the sigma gradients are reduced in a
- * fixed order. */
+ * fixed order.
+ * With BF_FLAG_MIRROR the reflected filter equals the zero-border filter of
+ * the image extended by W on each side by reflection, cropped back; the call
+ * pads the image (and the output gradient, with zeros) into the plan's
+ * workspace, runs the zero-border adjoint there (recomputing its state:
+ * `saved` must be NULL, else BF_EUNSUPPORTED) and adds the gradient of every
+ * extended sample onto the pixel it reflects.  Errors of the inner adjoint
+ * are returned as they are. */
 int bf_backward(const bf_plan_t* plan, const float* in, int64_t in_pitch,
                 const float* grad_out, int64_t gout_pitch, const float* saved,
                 float* grad_in, int64_t gin_pitch, double* grad_sigma, void* stream);

@@ -203,6 +203,11 @@ BlsState bls_layout(void* base, int H, int Wd, int W, bool sigs);
 hipError_t launch_backward_ls(const TileParams& p, const BlsState& st, bool sigs, double* partials,
                               double* grad_sigma, hipStream_t s);
 hipError_t launch_sigma_reduce(const double* partials, int n, bool has_ss, double* out, hipStream_t s);
+// reflecting-border adjoint: extend (image by reflection, output gradient by zeros) by W on each
+// side, and fold the extension's gradient back onto the image (bf_kernels.hip)
+hipError_t launch_mirror_pad(const float* in, int64_t in_pitch, const float* gout, int64_t gout_pitch, int H, int Wd,
+                             int W, float* fpad, float* gpad, hipStream_t s);
+hipError_t launch_mirror_fold(const float* gpad, int H, int Wd, int W, float* gin, int64_t gin_pitch, hipStream_t s);
 
 // Batch (bf_batch.hip)
 struct BatchTile {
@@ -255,4 +260,7 @@ struct bf_plan {
   bool bls;             // streamed adjoint
   void* d_bls;          // its device state
   bfgpa::BlsState bls_state;
+  bf_plan* mirror_adj;  // reflecting border with BF_FLAG_GRAD: zero-border adjoint plan of the extended image
+  float* d_mpad;        // its extended image, output gradient and input gradient (three planes)
+  int64_t mpad_plane;   // floats per plane
 };

@@ -308,3 +308,71 @@ hipError_t launch_backward(const TileParams& p, int variant, bool sigs, double* 
 }
 
 }  // namespace bfgpa
+
+// ---------------------------------------------------------------------------
+// Adjoint with the reflecting border.  With reflection every output pixel's
+// window lies inside the image extended by W on each side, so the forward is
+// the zero-border filter of that extension cropped back to the image.  The
+// adjoint therefore runs the zero-border adjoint on the extension (output
+// gradient zero outside the image) and sums the extension's gradient back
+// onto the pixels each extended sample reflects.
+// ---------------------------------------------------------------------------
+namespace bfgpa {
+
+// fpad: the extension by reflection (period 2n, edge samples repeated);
+// gpad: the output gradient, zero outside the image.  Both (H + 2W) x (Wd + 2W), pitch Wd + 2W.
+__global__ __launch_bounds__(kThreads) void mirror_pad_kernel(const float* in, int64_t in_pitch, const float* gout,
+                                                              int64_t gout_pitch, int H, int Wd, int W, float* fpad,
+                                                              float* gpad) {
+  const int Wp = Wd + 2 * W;
+  const int64_t n = (int64_t)(H + 2 * W) * Wp;
+  for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kThreads) {
+    const int R = (int)(i / Wp);
+    const int r = R - W, c = (int)(i - (int64_t)R * Wp) - W;
+    fpad[i] = in[(int64_t)reflect_index(r, H) * in_pitch + reflect_index(c, Wd)];
+    gpad[i] = (r >= 0 && r < H && c >= 0 && c < Wd) ? gout[(int64_t)r * gout_pitch + c] : 0.f;
+  }
+}
+
+// first offset u >= -W of the extension with u = u0 (mod 2n)
+__device__ __forceinline__ int first_image(int u0, int n, int W) { return u0 - ((u0 + W) / (2 * n)) * (2 * n); }
+
+// gin(r, c) = sum of gpad over the extended samples (u, v) in [-W, H + W) x [-W, Wd + W)
+// that reflect onto (r, c): u = r or 2H - 1 - r modulo 2H, likewise v.
+__global__ __launch_bounds__(kThreads) void mirror_fold_kernel(const float* gpad, int H, int Wd, int W, float* gin,
+                                                               int64_t gin_pitch) {
+  const int Wp = Wd + 2 * W;
+  const int64_t n = (int64_t)H * Wd;
+  for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kThreads) {
+    const int r = (int)(i / Wd), c = (int)(i - (int64_t)r * Wd);
+    float acc = 0.f;
+    for (int a = 0; a < 2; ++a) {
+      for (int u = first_image(a ? 2 * H - 1 - r : r, H, W); u < H + W; u += 2 * H) {
+        const float* row = gpad + (int64_t)(u + W) * Wp + W;
+        for (int b = 0; b < 2; ++b)
+          for (int v = first_image(b ? 2 * Wd - 1 - c : c, Wd, W); v < Wd + W; v += 2 * Wd) acc += row[v];
+      }
+    }
+    gin[(int64_t)r * gin_pitch + c] = acc;
+  }
+}
+
+static int grid_for(int64_t n) {
+  return (int)std::max<int64_t>(1, std::min<int64_t>((n + kThreads - 1) / kThreads, 8192));
+}
+
+hipError_t launch_mirror_pad(const float* in, int64_t in_pitch, const float* gout, int64_t gout_pitch, int H, int Wd,
+                             int W, float* fpad, float* gpad, hipStream_t s) {
+  const int64_t n = (int64_t)(H + 2 * W) * (Wd + 2 * W);
+  hipLaunchKernelGGL(mirror_pad_kernel, dim3(grid_for(n)), dim3(kThreads), 0, s, in, in_pitch, gout, gout_pitch, H, Wd,
+                     W, fpad, gpad);
+  return hipGetLastError();
+}
+
+hipError_t launch_mirror_fold(const float* gpad, int H, int Wd, int W, float* gin, int64_t gin_pitch, hipStream_t s) {
+  hipLaunchKernelGGL(mirror_fold_kernel, dim3(grid_for((int64_t)H * Wd)), dim3(kThreads), 0, s, gpad, H, Wd, W, gin,
+                     gin_pitch);
+  return hipGetLastError();
+}
+
+}  // namespace bfgpa

@@ -520,6 +520,48 @@ int bf_order(const bf_params* in, bf_plan_info* out) {
   return st;
 }
 
+// Reflecting border with BF_FLAG_GRAD: the forward plan of the image (reflecting border, no
+// adjoint workspace of its own) holds a zero-border adjoint plan of the image extended by W on
+// each side, plus the three extended planes bf_backward pads into and folds back from.
+static int plan_mirror_adjoint(const bf_params& p, bf_plan_t** out) {
+  bf_params q = p;
+  q.flags &= ~BF_FLAG_GRAD;
+  bf_plan_t* pl = nullptr;
+  const int wst = bf_plan(&q, &pl);
+  if (wst < 0) return wst;
+  bf_params r = p;
+  r.flags &= ~BF_FLAG_MIRROR;
+  r.height = p.height + 2 * p.W;
+  r.width = p.width + 2 * p.W;
+  bf_plan_t* adj = nullptr;
+  int st = bf_plan(&r, &adj);
+  if (st < 0) {
+    const std::string msg = g_err;
+    bf_destroy(pl);
+    return fail(st, "reflecting-border adjoint: " + msg);
+  }
+  if (adj->info.N != pl->info.N || adj->info.W != pl->info.W) {
+    bf_destroy(adj);
+    bf_destroy(pl);
+    return fail(BF_EINVAL, "reflecting-border adjoint: order or support differs on the extended image");
+  }
+  const int64_t plane = (((int64_t)r.height * r.width + 63) / 64) * 64;  // 256-byte aligned planes
+  hipError_t e = hipMalloc(&pl->d_mpad, 3 * plane * sizeof(float));
+  if (e != hipSuccess) {
+    pl->d_mpad = nullptr;
+    bf_destroy(adj);
+    bf_destroy(pl);
+    return fail(BF_ENOMEM, "hipMalloc reflecting-border adjoint planes failed");
+  }
+  pl->mirror_adj = adj;
+  pl->mpad_plane = plane;
+  pl->p.flags |= BF_FLAG_GRAD;
+  pl->info.workspace_bytes += adj->info.workspace_bytes + 3 * plane * (int64_t)sizeof(float);
+  *out = pl;
+  if (wst == BF_WNOGUARANTEE) set_error("order below the bound: no +-delta guarantee");
+  return wst;
+}
+
 int bf_plan(const bf_params* in, bf_plan_t** out) {
   if (!out) return fail(BF_EINVAL, "out is NULL");
   *out = nullptr;
@@ -530,10 +572,9 @@ int bf_plan(const bf_params* in, bf_plan_t** out) {
   bf_plan_info info;
   int ost = plan_order(&p, &info);
   if (ost < 0) return ost;
-  if ((p.flags & BF_FLAG_MIRROR) && (p.flags & BF_FLAG_GRAD))
-    return fail(BF_EUNSUPPORTED, "the mirror border has no adjoint");
   if (p.kernel == BF_GAUSS_REC && (p.flags & BF_FLAG_GRAD))
     return fail(BF_EUNSUPPORTED, "the recursive Gaussian has no adjoint");
+  if ((p.flags & BF_FLAG_MIRROR) && (p.flags & BF_FLAG_GRAD)) return plan_mirror_adjoint(p, out);
   ForwardPath fpath;
   st = choose_forward_path(p, &fpath);
   if (st < 0) return st;
@@ -682,7 +723,9 @@ int bf_destroy(bf_plan_t* plan) {
   if (plan->d_partials) hipFree(plan->d_partials);
   if (plan->d_ls) hipFree(plan->d_ls);
   if (plan->d_bls) hipFree(plan->d_bls);
+  if (plan->d_mpad) hipFree(plan->d_mpad);
   hipSetDevice(dev);
+  if (plan->mirror_adj) bf_destroy(plan->mirror_adj);
   delete plan;
   return BF_OK;
 }
@@ -722,6 +765,8 @@ int bf_forward(const bf_plan_t* pl, const float* in, int64_t in_pitch, float* ou
   if ((const void*)in == (const void*)out) return fail(BF_EINVAL, "in and out must not alias");
   if (pl->p.flags & BF_FLAG_JOINT) return fail(BF_EINVAL, "a cross-filter plan runs with bf_forward_joint");
   if (pl->depth > 0) return fail(BF_EINVAL, "a volume plan runs with bf_forward_volume");
+  if (saved && (pl->p.flags & BF_FLAG_MIRROR))
+    return fail(BF_EUNSUPPORTED, "the reflecting border keeps no adjoint state (its adjoint recomputes)");
   TileParams tp;
   std::memset(&tp, 0, sizeof(tp));
   fill_common(pl, tp);
@@ -865,11 +910,29 @@ int bf_backward(const bf_plan_t* pl, const float* in, int64_t in_pitch, const fl
                 int64_t gout_pitch, const float* saved, float* grad_in, int64_t gin_pitch,
                 double* grad_sigma, void* stream) {
   if (!pl || !in || !grad_out) return fail(BF_EINVAL, "NULL plan or image pointer");
-  if (!(pl->p.flags & BF_FLAG_GRAD) || (pl->bvariant < 0 && !pl->bls))
+  if (!(pl->p.flags & BF_FLAG_GRAD) || (pl->bvariant < 0 && !pl->bls && !pl->mirror_adj))
     return fail(BF_EINVAL, "plan was built without BF_FLAG_GRAD");
   if (in_pitch < pl->p.width || gout_pitch < pl->p.width || (grad_in && gin_pitch < pl->p.width))
     return fail(BF_EINVAL, "pitch smaller than width");
   hipStream_t s = (hipStream_t)stream;
+  if (pl->mirror_adj) {
+    if (saved) return fail(BF_EUNSUPPORTED, "the reflecting border keeps no adjoint state: saved must be NULL");
+    const int H = pl->p.height, Wd = pl->p.width, W = pl->p.W;
+    const int64_t Wp = Wd + 2 * W;
+    float* fpad = pl->d_mpad;
+    float* gpad = fpad + pl->mpad_plane;
+    float* ipad = gpad + pl->mpad_plane;
+    hipError_t e = launch_mirror_pad(in, in_pitch, grad_out, gout_pitch, H, Wd, W, fpad, gpad, s);
+    if (e != hipSuccess) return hip_fail(e, "reflecting-border pad launch");
+    const int st = bf_backward(pl->mirror_adj, fpad, Wp, gpad, Wp, nullptr, grad_in ? ipad : nullptr, Wp,
+                               grad_sigma, stream);
+    if (st < 0) return st;
+    if (grad_in) {
+      e = launch_mirror_fold(ipad, H, Wd, W, grad_in, gin_pitch, s);
+      if (e != hipSuccess) return hip_fail(e, "reflecting-border fold launch");
+    }
+    return BF_OK;
+  }
   TileParams tp;
   std::memset(&tp, 0, sizeof(tp));
   fill_common(pl, tp);

@@ -1,0 +1,87 @@
+"""GPU parity of the adjoint with the reflecting border (BF_FLAG_MIRROR with
+BF_FLAG_GRAD) against float64 autograd through the reflected gather
+(oracle.grad.vjp_autograd with mirror=True, itself pinned by finite
+differences of the numpy mirror filter).
+
+Tolerance as for the zero-border adjoint: max |GPU - ref| <= 1e-3 * max |ref|
+for dL/df and relative 1e-3 for the sigma gradients.  Cases: fused adjoint
+tiles, several tiles with ragged tails, supports wider than the image (pixels
+reached through several reflections), and a wide support on the streamed
+adjoint; two calls in a row on one plan, the state of the first left in the
+plan's planes."""
+import numpy as np
+import pytest
+
+import synthimg
+from oracle import grad as GR
+from oracle import kernels as K
+from oracle import mirror as M
+
+pytestmark = pytest.mark.gpu
+RTOL = 1e-3
+
+
+def _mods():
+    import torch
+    import paper_1603_08109_amd as P
+    assert torch.cuda.is_available()
+    return torch, P
+
+
+def _check(plan, f, gbar, kind, kw, sr):
+    torch, P = _mods()
+    x = torch.tensor(f, dtype=torch.float32, device="cuda")
+    g = torch.tensor(gbar, dtype=torch.float32, device="cuda")
+    gin, gs = plan.backward(x, g)
+    torch.cuda.synchronize()
+    gin = gin.cpu().numpy().astype(np.float64)
+    gs = gs.cpu().numpy()
+    f32 = x.cpu().numpy().astype(np.float64)
+    g32 = g.cpu().numpy().astype(np.float64)
+    df, dsr, dss = GR.vjp_autograd(f32, g32, kind, kw.get("sigma_s"), plan.info.W, sr, plan.info.N, 127.5,
+                                   mirror=True)
+    err = np.abs(gin - df).max() / np.abs(df).max()
+    print(f"{kind} {kw} {f.shape} W={plan.info.W} N={plan.info.N}: df rel {err:.2e}  dsr {gs[0]:.6e} vs "
+          f"{dsr:.6e}  dss {gs[1]:.6e} vs {dss:.6e}", flush=True)
+    assert err <= RTOL
+    assert abs(gs[0] - dsr) <= RTOL * abs(dsr)
+    if kind == "gauss":
+        assert abs(gs[1] - dss) <= RTOL * abs(dss)
+    return x
+
+
+CASES = [
+    ("box", dict(W=3), 30.0, (40, 50), 1),
+    ("box", dict(W=9), 20.0, (5, 7), 2),             # W > H, W: several reflections
+    ("gauss", dict(sigma_s=2.0), 30.0, (45, 71), 3),
+    ("gauss", dict(sigma_s=1.5), 25.0, (4, 30), 4),  # W = 5 > H
+    ("gauss", dict(sigma_s=3.0), 25.0, (66, 90), 5),
+    ("gauss", dict(sigma_s=15.0), 30.0, (70, 96), 6),  # W = 45
+]
+
+
+@pytest.mark.parametrize("kind,kw,sr,shape,seed", CASES)
+def test_mirror_adjoint_matches_autograd(kind, kw, sr, shape, seed):
+    torch, P = _mods()
+    plan = P.Plan(kind, sr, *shape, grad=True, mirror=True, **kw)
+    f = synthimg.gen1(*shape, seed)
+    gbar = synthimg.gen2(*shape, seed + 100) / 255.0 - 0.5
+    x = _check(plan, f, gbar, kind, kw, sr)
+    # the forward of the same plan is the reflecting-border filter
+    out = plan.forward(x).cpu().numpy().astype(np.float64)
+    ref = M.gpa_alg2(x.cpu().numpy().astype(np.float64), K.taps1d(kind, kw.get("sigma_s"), plan.info.W), sr,
+                     plan.info.N, 127.5)
+    assert np.abs(out - ref).max() <= 1e-3
+    # a second call on new data: the extended planes are written afresh
+    _check(plan, synthimg.gen2(*shape, seed + 7), synthimg.gen1(*shape, seed + 8) / 255.0 - 0.5, kind, kw, sr)
+
+
+def test_mirror_adjoint_saved_rejected():
+    torch, P = _mods()
+    plan = P.Plan("gauss", 30.0, 32, 40, sigma_s=2.0, grad=True, mirror=True)
+    x = torch.zeros(32, 40, device="cuda")
+    saved = plan.new_saved()
+    with pytest.raises(P.BFError):
+        plan.forward(x, saved=saved)
+    with pytest.raises(P.BFError):
+        plan.backward(x, torch.zeros_like(x), saved=saved)
