@@ -274,7 +274,9 @@ int bf_batch_tune(bf_batch_t* batch, const float* const* in, const int64_t* in_p
  * persistent batch launch; the adjoint tiles of all images whose support
  * fits the fused adjoint run as one more persistent launch over a
  * cost-ordered work list, and wider supports run the streamed adjoint image
- * by image.  Arguments are host arrays of `count` entries:
+ * by image.  Images with BF_FLAG_MIRROR run bf_backward of a plan of their
+ * own (built at bf_batch_plan, on the image extended by reflection), image
+ * by image, recomputing their state.  Arguments are host arrays of `count` entries:
  *   in, in_pitch          the images and row pitches (device pointers)
  *   grad_out, gout_pitch  dL/d(out_i)
  *   grad_in, gin_pitch    NULL, or receives dL/d(in_i) (an entry may be NULL)
@@ -296,7 +298,8 @@ int bf_batch_backward(bf_batch_t* batch, const float* const* in, const int64_t* 
  * height*width float32 (dense pitch = width) to the DEVICE buffer saved[i];
  * bf_batch_backward_saved takes the same arrays and reads them.  `saved` is
  * a host array of `count` device pointers; entries of images whose plan
- * failed are ignored, every other one must be non-NULL.  The planes belong to
+ * failed are ignored, every other one must be non-NULL (images with
+ * BF_FLAG_MIRROR recompute their state and leave theirs unread).  The planes belong to
  * the inputs the forward saw: passing other inputs gives the gradient at the
  * saved state.  Errors as for bf_batch_forward / bf_batch_backward, plus
  * BF_EINVAL for a NULL `saved` array or entry, or a batch planned without

@@ -5,7 +5,8 @@ parameters; the order N and support W are fixed at construction (they are
 integers and are held constant when differentiating).  The forward saves
 three per-pixel values (Q, P/Q and the coefficient-derivative term) for the
 adjoint; the N+1 auxiliary images are recomputed inside the adjoint kernel,
-never stored.
+never stored.  With ``mirror=True`` (reflecting border) nothing is saved: the
+adjoint recomputes its state on the image extended by reflection.
 """
 from __future__ import annotations
 
@@ -18,7 +19,7 @@ class _GPAFunction(torch.autograd.Function):
     @staticmethod
     def forward(ctx, image, sigma_r, sigma_s, module):
         plan = module._plan_for(image)
-        saved = plan.new_saved()
+        saved = None if module.mirror else plan.new_saved()
         out = plan.forward(image.detach(), saved=saved)
         ctx.plan = plan
         ctx.save_for_backward(image, saved)
@@ -40,9 +41,10 @@ class BilateralGPA(torch.nn.Module):
 
     def __init__(self, kernel: str, sigma_r: float, sigma_s: float | None = None, W: int = 0,
                  N: int | None = None, delta: float = 1e-3, T: float = 127.5,
-                 center: float | None = None):
+                 center: float | None = None, mirror: bool = False):
         super().__init__()
         self.kernel = kernel
+        self.mirror = mirror
         self.sigma_r = torch.nn.Parameter(torch.tensor(float(sigma_r)))
         self.sigma_s = torch.nn.Parameter(torch.tensor(float(sigma_s))) if kernel != "box" else None
         self.W = W
@@ -56,7 +58,7 @@ class BilateralGPA(torch.nn.Module):
                float(self.sigma_s.detach()) if self.sigma_s is not None else None)
         plan = self._plans.get(key)
         if plan is None:
-            kw = dict(W=self.W, T=self.T, center=self.center, delta=self.delta, grad=True)
+            kw = dict(W=self.W, T=self.T, center=self.center, delta=self.delta, grad=True, mirror=self.mirror)
             if self._N is not None:
                 kw["N"] = self._N
             if self.sigma_s is not None:

@@ -225,6 +225,8 @@ struct bf_batch {
   bool bev_used = false;
   void* d_bls = nullptr;              // streamed adjoint state, reused image by image
   double* d_bls_partials = nullptr;
+  std::vector<int> mirrored;          // images with the reflecting border: adjoint through their own plan
+  std::vector<bf_plan_t*> mplans;     // those plans (per image, null elsewhere)
 };
 
 namespace bfgpa {
@@ -369,17 +371,28 @@ static int run_direct(bf_batch* b, int k, hipStream_t s, int grid, bool save = f
 // adjoint tiles in one persistent work list (the shape that fits the most
 // images); the others run the streamed adjoint one after another on a
 // shared state buffer.  The forward state the adjoint reads (3 planes per
-// image) is recomputed by the batch forward kernel at each call.
+// image) is recomputed by the batch forward kernel at each call.  Images with
+// the reflecting border run the adjoint of their own plan (bf_backward on the
+// image extended by reflection) one after another.
 static int plan_batch_adjoint(bf_batch* b) {
   const int count = b->count;
-  for (int i = 0; i < count; ++i)
-    if (b->status[i] >= 0 && b->hp[i].mirror) return fail(BF_EUNSUPPORTED, "the mirror border has no adjoint");
+  b->mplans.assign(count, nullptr);
+  for (int i = 0; i < count; ++i) {
+    if (b->status[i] < 0 || !b->hp[i].mirror) continue;
+    bf_params q = b->prm[i];
+    q.flags |= BF_FLAG_GRAD;
+    const int st = bf_plan(&q, &b->mplans[i]);
+    if (st < 0) return st;
+    if (b->mplans[i]->info.N != b->info[i].N || b->mplans[i]->info.W != b->prm[i].W)
+      return fail(BF_EINVAL, "batch mirror adjoint: order or support differs from the batch plan");
+    b->mirrored.push_back(i);
+  }
   int best = -1, best_n = -1;
   for (int v = 0; v < backward_variant_count(); ++v) {
     const Variant vv = backward_variant(v);
     int n = 0;
     for (int i = 0; i < count; ++i) {
-      if (b->status[i] < 0) continue;
+      if (b->status[i] < 0 || b->mplans[i]) continue;
       const int TY = 4 * vv.opt, W = b->prm[i].W;
       const bool sigs = b->prm[i].kernel == BF_GAUSS;
       if (region_floats_bwd(TY, W) <= (int64_t)kThreads * vv.mreg &&
@@ -405,6 +418,7 @@ static int plan_batch_adjoint(bf_batch* b) {
     const bool sigs = p.kernel == BF_GAUSS;
     b->saved_off[i] = saved;
     saved += 3 * (int64_t)p.height * p.width;
+    if (b->mplans[i]) continue;
     const int TY = 4 * vv.opt;
     if (region_floats_bwd(TY, p.W) <= (int64_t)kThreads * vv.mreg &&
         backward_lds_bytes(TY, p.W, sigs) + 2 * kThreads * 8 + 64 <= max_lds_bytes()) {
@@ -753,6 +767,13 @@ static int batch_backward(bf_batch_t* b, const float* const* in, const int64_t* 
     e = launch_backward_ls(b->h_bstage[n + i], st, sigs, b->d_bls_partials, grad_sigma ? grad_sigma + 2 * i : nullptr, s);
     if (e != hipSuccess) return fail(BF_EHIP, std::string("batch streamed adjoint: ") + hipGetErrorString(e));
   }
+  for (int i : b->mirrored) {
+    // recomputes its own state (the batch's saved planes of this image go unread)
+    const int st = bf_backward(b->mplans[i], in[i], in_pitch[i], grad_out[i], gout_pitch[i], nullptr,
+                               grad_in ? grad_in[i] : nullptr, grad_in ? gin_pitch[i] : 0,
+                               grad_sigma ? grad_sigma + 2 * i : nullptr, stream);
+    if (st < 0) return st;
+  }
   hipEventRecord(b->bev, s);
   b->bev_used = true;
   return BF_OK;
@@ -792,6 +813,8 @@ int bf_batch_destroy(bf_batch_t* b) {
   if (b->d_params) hipFree(b->d_params);
   if (b->d_tiles) hipFree(b->d_tiles);
   if (b->d_counter) hipFree(b->d_counter);
+  for (bf_plan_t* pl : b->mplans)
+    if (pl) bf_destroy(pl);
   delete b;
   return BF_OK;
 }

@@ -109,5 +109,3 @@ def test_mirror_unsupported():
     torch, P = _mods()
     with pytest.raises(P.BFError):
         P.Plan("box", 30.0, 300, 300, W=120, mirror=True)  # streamed box beyond the strips
-    with pytest.raises(P.BFError):
-        P.Batch([dict(kernel="box", W=3, sigma_r=30.0, height=20, width=20, mirror=True, grad=True)])

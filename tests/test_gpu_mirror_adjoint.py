@@ -85,3 +85,61 @@ def test_mirror_adjoint_saved_rejected():
         plan.forward(x, saved=saved)
     with pytest.raises(P.BFError):
         plan.backward(x, torch.zeros_like(x), saved=saved)
+
+
+def test_autograd_module_mirror():
+    # the torch.autograd wrapper with the reflecting border: output and all three gradients
+    torch, P = _mods()
+    f = synthimg.gen1(40, 56, 31)
+    target = torch.tensor(synthimg.clean_blocks(40, 56, 31), dtype=torch.float32, device="cuda")
+    x = torch.tensor(f, dtype=torch.float32, device="cuda", requires_grad=True)
+    m = P.BilateralGPA("gauss", sigma_r=30.0, sigma_s=2.0, mirror=True).cuda()
+    y = m(x)
+    ((y - target) ** 2).mean().backward()
+    torch.cuda.synchronize()
+    f32 = f.astype(np.float32).astype(np.float64)
+    out = M.gpa_alg2(f32, K.taps1d("gauss", 2.0), 30.0, m._N, 127.5)
+    gbar = 2.0 * (y.detach().double().cpu().numpy() - target.cpu().numpy()) / y.numel()
+    df, dsr, dss = GR.vjp_autograd(f32, gbar, "gauss", 2.0, m.W, 30.0, m._N, 127.5, mirror=True)
+    assert np.abs(y.detach().cpu().numpy() - out).max() <= 1e-3
+    assert np.abs(x.grad.cpu().numpy() - df).max() <= RTOL * np.abs(df).max()
+    assert abs(m.sigma_r.grad.item() - dsr) <= RTOL * abs(dsr)
+    assert abs(m.sigma_s.grad.item() - dss) <= RTOL * abs(dss)
+
+
+def test_batch_mirror_adjoint():
+    # a batch mixing reflecting and zero borders: the mirror images take their own plan's adjoint,
+    # the others the persistent adjoint tiles; each against its own float64 reference, with and
+    # without the saved-state pair
+    torch, P = _mods()
+    specs = [dict(kernel="gauss", sigma_s=2.0, sigma_r=30.0, height=30, width=41, mirror=True, grad=True),
+             dict(kernel="box", W=3, sigma_r=25.0, height=25, width=33, grad=True),
+             dict(kernel="box", W=9, sigma_r=20.0, height=6, width=50, mirror=True, grad=True)]
+    batch = P.Batch(specs)
+    assert all(st >= 0 for st in batch.image_status)
+    xs = [torch.tensor(synthimg.gen1(d["height"], d["width"], 40 + i), dtype=torch.float32, device="cuda")
+          for i, d in enumerate(specs)]
+    gs_ = [torch.tensor(synthimg.gen2(d["height"], d["width"], 50 + i) / 255.0 - 0.5, dtype=torch.float32,
+                        device="cuda") for i, d in enumerate(specs)]
+    gin, gsig = batch.backward(xs, gs_)
+    saved = batch.new_saved()
+    batch.forward(xs, saved=saved)
+    gin2, gsig2 = batch.backward(xs, gs_, saved=saved)
+    torch.cuda.synchronize()
+    for i, d in enumerate(specs):
+        kind, mirror = d["kernel"], d.get("mirror", False)
+        W = d.get("W") or K.support(kind, sigma_s=d.get("sigma_s"))
+        f32 = xs[i].cpu().numpy().astype(np.float64)
+        g32 = gs_[i].cpu().numpy().astype(np.float64)
+        df, dsr, dss = GR.vjp_autograd(f32, g32, kind, d.get("sigma_s"), W, d["sigma_r"], batch.N[i], 127.5,
+                                       mirror=mirror)
+        for a, sg in ((gin[i], gsig[i]), (gin2[i], gsig2[i])):
+            got = a.cpu().numpy().astype(np.float64)
+            sg = sg.cpu().numpy()
+            err = np.abs(got - df).max() / np.abs(df).max()
+            print(f"image {i} {kind} mirror={mirror} W={W} N={batch.N[i]}: df rel {err:.2e} dsr {sg[0]:.6e} vs "
+                  f"{dsr:.6e}", flush=True)
+            assert err <= RTOL
+            assert abs(sg[0] - dsr) <= RTOL * abs(dsr)
+            if kind == "gauss":
+                assert abs(sg[1] - dss) <= RTOL * abs(dss)
