@@ -143,3 +143,25 @@ def test_batch_mirror_adjoint():
             assert abs(sg[0] - dsr) <= RTOL * abs(dsr)
             if kind == "gauss":
                 assert abs(sg[1] - dss) <= RTOL * abs(dss)
+
+
+def test_full_size_512():
+    # one image of the 32 x 512^2 fwd+bwd workload (sigma_s = 5, W = 15, sigma_r = 30), every pixel
+    torch, P = _mods()
+    kw = dict(sigma_s=5.0)
+    plan = P.Plan("gauss", 30.0, 512, 512, grad=True, mirror=True, **kw)
+    _check(plan, synthimg.gen2(512, 512, 90), synthimg.gen1(512, 512, 91) / 255.0 - 0.5, "gauss", kw, 30.0)
+
+
+def test_clone_same_result():
+    # a clone holds its own extended planes and inner adjoint plan, with the same result
+    torch, P = _mods()
+    plan = P.Plan("box", 25.0, 37, 45, W=4, grad=True, mirror=True)
+    other = plan.clone()
+    x = torch.tensor(synthimg.gen1(37, 45, 95), dtype=torch.float32, device="cuda")
+    g = torch.tensor(synthimg.gen2(37, 45, 96) / 255.0 - 0.5, dtype=torch.float32, device="cuda")
+    a, sa = plan.backward(x, g)
+    b, sb = other.backward(x, g)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b) and torch.equal(sa[:1], sb[:1])
+    assert other.info.workspace_bytes == plan.info.workspace_bytes > 0
