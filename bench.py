@@ -375,6 +375,21 @@ def main():
         ms_f = time_launches(fwd_only, stream, 1, max(1, a.steps // 2), torch)
         ref_gins = [g.clone() for g in gins]
 
+        def fwd_bwd_recompute(plan):
+            def run():
+                for b in range(32):
+                    plan.forward(imgs[b], out=outs[b])
+                    g = (outs[b] - tgts[b]) * (2.0 / outs[b].numel())
+                    plan.backward(imgs[b], g, grad_in=gins[b])
+            return run
+
+        # the adjoint recomputing its state, with the zero border and with the reflecting border
+        # (whose adjoint runs on the image extended by W = 15 on each side)
+        ms_fr = time_launches(fwd_bwd_recompute(plan5), stream, 1, max(1, a.steps // 2), torch)
+        plan5m = P.Plan("gauss", 30.0, 512, 512, sigma_s=5.0, grad=True, mirror=True)
+        ms_fm = time_launches(fwd_bwd_recompute(plan5m), stream, 1, max(1, a.steps // 2), torch)
+        del plan5m
+
         # the same 32 images through the batch entry points: one persistent forward launch and
         # one persistent adjoint launch (forward state recomputed inside), sigma gradients included
         gbatch = P.Batch([dict(kernel="gauss", sigma_s=5.0, sigma_r=30.0, height=512, width=512, grad=True)
@@ -407,7 +422,10 @@ def main():
                             "batched_ms": round(ms_fbb, 3), "batched_mpix_s": round(px5 / ms_fbb / 1e3, 1),
                             "batched_vs_per_image_max_rel_dfdin": rel,
                             "batched_saved_ms": round(ms_fbs, 3), "batched_saved_mpix_s": round(px5 / ms_fbs / 1e3, 1),
-                            "batched_saved_vs_per_image_max_rel_dfdin": rel_s}
+                            "batched_saved_vs_per_image_max_rel_dfdin": rel_s,
+                            "recompute_ms": round(ms_fr, 3), "recompute_mpix_s": round(px5 / ms_fr / 1e3, 1),
+                            "mirror_recompute_ms": round(ms_fm, 3),
+                            "mirror_recompute_mpix_s": round(px5 / ms_fm / 1e3, 1)}
         print(f"# fwd_bwd {extra['fwd_bwd']}", file=sys.stderr, flush=True)
         del imgs, tgts, saved, outs, gins, bgins, ref_gins, gbatch, bsaved
 
