@@ -182,6 +182,7 @@ struct BatchShape {
   int wg_per_cu;               // persistent grid = CUs * wg_per_cu
   std::vector<int> TY;         // per-image tile rows
   std::vector<BatchTile> tiles;
+  std::vector<BatchTile> ftiles;  // the plain forward's tiles: those of images not on their own plan
   size_t lds;                  // dynamic LDS bytes
 };
 
@@ -200,6 +201,14 @@ struct bf_batch {
   TileParams* d_params = nullptr;
   BatchTile* d_tiles = nullptr;       // tiles of the chosen shape
   int ntiles = 0;
+  BatchTile* d_ftiles = nullptr;      // its plain-forward subset
+  int nftiles = 0;
+  std::vector<bf_plan_t*> fplans;     // images whose plain forward runs the streamed passes of a plan of their own
+  static constexpr int kAux = 4;      // side streams for those images, concurrent with the persistent launch
+  std::vector<int> aux_imgs[kAux];    // images per side stream (longest first, least-loaded stream)
+  hipStream_t aux[kAux] = {};
+  hipEvent_t fork_ev = nullptr;
+  hipEvent_t join_ev[kAux] = {};
   int* d_counter = nullptr;
   TileParams* h_stage[2] = {nullptr, nullptr};
   hipEvent_t ev[2] = {nullptr, nullptr};
@@ -263,7 +272,10 @@ static bool build_shape(bf_batch* b, int v, int wg_per_cu, BatchShape* out) {
                    [](const std::pair<double, BatchTile>& a, const std::pair<double, BatchTile>& b2) {
                      return a.first > b2.first;
                    });
-  for (auto& e : list) out->tiles.push_back(e.second);
+  for (auto& e : list) {
+    out->tiles.push_back(e.second);
+    if (b->fplans.empty() || !b->fplans[e.second.image]) out->ftiles.push_back(e.second);
+  }
   out->lds = (size_t)lds;
   return true;
 }
@@ -313,13 +325,16 @@ static void destroy_graphs(bf_batch* b) {
 static int select_shape(bf_batch* b, int c) {
   const BatchShape& sh = b->cands[c];
   if (b->d_tiles) hipFree(b->d_tiles);
-  b->d_tiles = nullptr;
+  if (b->d_ftiles) hipFree(b->d_ftiles);
+  b->d_tiles = b->d_ftiles = nullptr;
   b->ntiles = (int)sh.tiles.size();
-  if (b->ntiles > 0) {
-    if (hipMalloc(&b->d_tiles, sh.tiles.size() * sizeof(BatchTile)) != hipSuccess)
-      return fail(BF_ENOMEM, "hipMalloc batch tiles failed");
-    if (hipMemcpy(b->d_tiles, sh.tiles.data(), sh.tiles.size() * sizeof(BatchTile),
-                  hipMemcpyHostToDevice) != hipSuccess)
+  b->nftiles = (int)sh.ftiles.size();
+  for (int f = 0; f < 2; ++f) {
+    const std::vector<BatchTile>& t = f ? sh.ftiles : sh.tiles;
+    BatchTile** d = f ? &b->d_ftiles : &b->d_tiles;
+    if (t.empty()) continue;
+    if (hipMalloc(d, t.size() * sizeof(BatchTile)) != hipSuccess) return fail(BF_ENOMEM, "hipMalloc batch tiles failed");
+    if (hipMemcpy(*d, t.data(), t.size() * sizeof(BatchTile), hipMemcpyHostToDevice) != hipSuccess)
       return fail(BF_EHIP, "hipMemcpy batch tiles failed");
   }
   for (int i = 0; i < b->count; ++i) {
@@ -354,15 +369,16 @@ static int stage(bf_batch* b, int k, const float* const* in, const int64_t* in_p
   return BF_OK;
 }
 
-// save: the staged params carry per-image saved planes, written as well
+// save: the staged params carry per-image saved planes, written as well, for
+// every image; otherwise only the tiles of images without a plan of their own
 static int run_direct(bf_batch* b, int k, hipStream_t s, int grid, bool save = false) {
   const BatchShape& sh = b->cands[b->chosen];
   if (hipMemcpyAsync(b->d_params, b->h_stage[k], b->count * sizeof(TileParams), hipMemcpyHostToDevice,
                      s) != hipSuccess)
     return fail(BF_EHIP, "hipMemcpyAsync batch params");
   hipLaunchKernelGGL(batch_reset_kernel, dim3(1), dim3(64), 0, s, b->d_counter);
-  hipError_t e = launch_batch_v(sh.variant, b->d_params, b->d_tiles, b->ntiles, b->d_counter, grid,
-                                sh.lds, b->acc64, save, s);
+  hipError_t e = launch_batch_v(sh.variant, b->d_params, save ? b->d_tiles : b->d_ftiles,
+                                save ? b->ntiles : b->nftiles, b->d_counter, grid, sh.lds, b->acc64, save, s);
   if (e != hipSuccess) return fail(BF_EHIP, std::string("batch launch: ") + hipGetErrorString(e));
   return BF_OK;
 }
@@ -468,10 +484,10 @@ static int plan_batch_adjoint(bf_batch* b) {
   return BF_OK;
 }
 
-static int grid_of(const bf_batch* b) {
+static int grid_of(const bf_batch* b, bool save = true) {
   const BatchShape& sh = b->cands[b->chosen];
   int g = b->num_cu * sh.wg_per_cu;
-  return std::max(1, std::min(g, std::max(1, b->ntiles)));
+  return std::max(1, std::min(g, std::max(1, save ? b->ntiles : b->nftiles)));
 }
 
 }  // namespace bfgpa
@@ -549,6 +565,40 @@ int bf_batch_plan(int32_t count, const bf_params* per_image, bf_batch_t** out) {
     hipMemcpy(b->d_const + offs[i], tabs[i].data(), tabs[i].size() * sizeof(float), hipMemcpyHostToDevice);
     bind_tables(b->hp[i], b->d_const + offs[i], strides[i], ntaps[i]);
   }
+  // images whose own plan takes the streamed passes (the per-image engine rule) run them
+  b->fplans.assign(count, nullptr);
+  for (int i = 0; i < count; ++i) {
+    if (b->status[i] < 0 || b->info[i].path != BF_PATH_STREAMED) continue;
+    const int st = bf_plan(&b->prm[i], &b->fplans[i]);
+    if (st < 0) {
+      bf_batch_destroy(b);
+      return st;
+    }
+  }
+  {
+    // spread them over the side streams, largest cost first, each to the least-loaded stream
+    std::vector<std::pair<double, int>> cost;
+    for (int i = 0; i < count; ++i)
+      if (b->fplans[i]) cost.push_back({(double)b->prm[i].height * b->prm[i].width * (b->info[i].N + 1), i});
+    std::stable_sort(cost.begin(), cost.end(),
+                     [](const std::pair<double, int>& x, const std::pair<double, int>& y) { return x.first > y.first; });
+    double load[bf_batch::kAux] = {};
+    for (const auto& c : cost) {
+      const int j = (int)(std::min_element(load, load + bf_batch::kAux) - load);
+      load[j] += c.first;
+      b->aux_imgs[j].push_back(c.second);
+    }
+    if (!cost.empty()) {
+      bool ok = hipEventCreateWithFlags(&b->fork_ev, hipEventDisableTiming) == hipSuccess;
+      for (int j = 0; ok && j < bf_batch::kAux; ++j)
+        ok = hipStreamCreateWithFlags(&b->aux[j], hipStreamNonBlocking) == hipSuccess &&
+             hipEventCreateWithFlags(&b->join_ev[j], hipEventDisableTiming) == hipSuccess;
+      if (!ok) {
+        bf_batch_destroy(b);
+        return fail(BF_EHIP, "batch side streams");
+      }
+    }
+  }
   // candidate launch shapes
   for (int v = 0; v < kNumBatchVariants; ++v)
     for (int wg : {1, 2, 4}) {
@@ -556,14 +606,12 @@ int bf_batch_plan(int32_t count, const bf_params* per_image, bf_batch_t** out) {
       if (build_shape(b, v, wg, &sh)) b->cands.push_back(std::move(sh));
     }
   if (b->cands.empty()) {
-    hipFree(b->d_const);
-    delete b;
+    bf_batch_destroy(b);
     return fail(BF_EUNSUPPORTED, "a batch image's support W is too large for the batch kernel");
   }
   if (hipMalloc(&b->d_params, count * sizeof(TileParams)) != hipSuccess ||
       hipMalloc(&b->d_counter, 2 * sizeof(int)) != hipSuccess) {
-    hipFree(b->d_const);
-    delete b;
+    bf_batch_destroy(b);
     return fail(BF_ENOMEM, "hipMalloc batch buffers failed");
   }
   for (int k = 0; k < 2; ++k) {
@@ -617,7 +665,7 @@ int bf_batch_forward(bf_batch_t* b, const float* const* in, const int64_t* in_pi
     hipGraph_t graph = nullptr;
     hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
-      int rs = run_direct(b, k, cap, grid_of(b));
+      int rs = run_direct(b, k, cap, grid_of(b, false));
       e = hipStreamEndCapture(cap, &graph);
       if (rs < 0) {
         if (graph) hipGraphDestroy(graph);
@@ -630,11 +678,28 @@ int bf_batch_forward(bf_batch_t* b, const float* const* in, const int64_t* in_pi
     hipStreamDestroy(cap);
     if (e != hipSuccess) return fail(BF_EHIP, std::string("batch graph capture: ") + hipGetErrorString(e));
   }
+  // images on the streamed passes: their own plan's launches on the side streams, forked from
+  // `s` before the persistent launch and joined back into it
+  const bool side = b->fork_ev != nullptr;
+  if (side) {
+    hipEventRecord(b->fork_ev, s);
+    for (int j = 0; j < bf_batch::kAux; ++j) hipStreamWaitEvent(b->aux[j], b->fork_ev, 0);
+  }
   hipError_t e = hipGraphLaunch(b->gexec[k], s);
   if (e != hipSuccess) return fail(BF_EHIP, std::string("hipGraphLaunch: ") + hipGetErrorString(e));
+  int fst = BF_OK;
+  if (side) {
+    for (int j = 0; j < bf_batch::kAux; ++j) {
+      for (int i : b->aux_imgs[j]) {
+        if (fst >= 0) fst = bf_forward(b->fplans[i], in[i], in_pitch[i], out[i], out_pitch[i], nullptr, b->aux[j]);
+      }
+      hipEventRecord(b->join_ev[j], b->aux[j]);  // joined even after an error, so `s` never waits on a stale fork
+      hipStreamWaitEvent(s, b->join_ev[j], 0);
+    }
+  }
   hipEventRecord(b->ev[k], s);
   b->ev_used[k] = true;
-  return BF_OK;
+  return fst < 0 ? fst : BF_OK;
 }
 
 int bf_batch_tune(bf_batch_t* b, const float* const* in, const int64_t* in_pitch, float* const* out,
@@ -654,9 +719,9 @@ int bf_batch_tune(bf_batch_t* b, const float* const* in, const int64_t* in_pitch
     st = stage(b, k, in, in_pitch, out, out_pitch);
     if (st < 0) return st;
     // one warm-up, then three timed launches (direct, not graphed)
-    run_direct(b, k, s, grid_of(b));
+    run_direct(b, k, s, grid_of(b, false));
     hipEventRecord(e0, s);
-    for (int rep = 0; rep < 3; ++rep) run_direct(b, k, s, grid_of(b));
+    for (int rep = 0; rep < 3; ++rep) run_direct(b, k, s, grid_of(b, false));
     hipEventRecord(e1, s);
     hipEventRecord(b->ev[k], s);
     b->ev_used[k] = true;
@@ -813,7 +878,18 @@ int bf_batch_destroy(bf_batch_t* b) {
   if (b->d_params) hipFree(b->d_params);
   if (b->d_tiles) hipFree(b->d_tiles);
   if (b->d_counter) hipFree(b->d_counter);
+  if (b->d_ftiles) hipFree(b->d_ftiles);
+  for (int j = 0; j < bf_batch::kAux; ++j) {
+    if (b->aux[j]) {
+      hipStreamSynchronize(b->aux[j]);
+      hipStreamDestroy(b->aux[j]);
+    }
+    if (b->join_ev[j]) hipEventDestroy(b->join_ev[j]);
+  }
+  if (b->fork_ev) hipEventDestroy(b->fork_ev);
   for (bf_plan_t* pl : b->mplans)
+    if (pl) bf_destroy(pl);
+  for (bf_plan_t* pl : b->fplans)
     if (pl) bf_destroy(pl);
   delete b;
   return BF_OK;

@@ -351,18 +351,21 @@ static int choose_forward_tile(int kernel, int W, int H, int Wd, bool allow_stre
     }
   }
   if (best < 0) return fail(BF_EUNSUPPORTED, "support W too large for the fused tile kernels");
-  // the streamed path launches kernels per block of 16 orders: only worth it
-  // when the image is large enough to hide those launches.  Box: the column
-  // strips beat the fused tiles from W = 16 on (measured on 4096^2: W = 10
-  // fused 1.7 vs strips 1.9 ps per pixel and order, W = 30 4.4 vs 2.2).
-  // Gaussian on images of 2^22 pixels and more: the streamed passes win from
-  // W = 13 on (measured on 4096^2: W = 9 tile 9.4 vs streamed 14.0 ms, W = 15
-  // 18.5 vs 15.6 ms, sigma_r = 10), earlier than the cost model says.
+  // The streamed path launches kernels per block of 16 orders.  Box: the column
+  // strips beat the fused tiles from W = 16 on images of 2^20 pixels and more
+  // (measured on 4096^2: W = 10 fused 1.7 vs strips 1.9 ps per pixel and order,
+  // W = 30 4.4 vs 2.2).  Gaussian: the split matrix-core passes win from about
+  // W = 14 at every size measured, 64 x 64 to 4096^2 (on 256 images of 64..1024
+  // x 64..768 with sigma_s in [2, 15]: 166.6 ms fused, 75.7 ms taking the faster
+  // engine per image, 76.1 ms from W = 16 on); W = 15 on 512^2 is still faster
+  // fused (0.21 vs 0.23 ms), hence W >= 16; from W = 13 on 2^22 pixels and more
+  // (4096^2: W = 9 tile 9.4 vs streamed 14.0 ms, W = 15 18.5 vs 15.6 ms).
   const int64_t npx = (int64_t)H * Wd;
-  if (allow_streamed && npx >= (1 << 20) && ls_supported(W)) {
-    const bool gauss_wide = bestc > streamed_cost(kernel, W) || (npx >= (1 << 22) && W >= 13);
-    if (kernel == BF_BOX ? (W >= 16 && ls_box_strip_supported(W)) : gauss_wide)
-      return fail(BF_EUNSUPPORTED, "streamed path is cheaper at this support");
+  if (allow_streamed && ls_supported(W)) {
+    const bool gauss_wide = W >= 16 || (npx >= (1 << 22) && W >= 13) ||
+                            (npx >= (1 << 20) && bestc > streamed_cost(kernel, W));
+    const bool box_wide = npx >= (1 << 20) && W >= 16 && ls_box_strip_supported(W);
+    if (kernel == BF_BOX ? box_wide : gauss_wide) return fail(BF_EUNSUPPORTED, "streamed path is cheaper at this support");
   }
   *variant = best;
   *TY = 4 * forward_variant(best).opt;

@@ -200,13 +200,25 @@ def test_wide_range_image_reported():
     assert batch.image_status[0] >= 0 and batch.image_status[1] == L.BF_EUNSUPPORTED
 
 
+def _own_plan(spec):
+    # whether the batch's plain forward runs this image on its own plan's streamed passes
+    import paper_1603_08109_amd as P
+    from paper_1603_08109_amd import _lib as L
+    kw = {k: v for k, v in spec.items() if k not in ("kernel", "sigma_r", "grad")}
+    return P.bf_order(spec["kernel"], spec["sigma_r"], **kw).path == L.BF_PATH_STREAMED
+
+
 def test_batch_saved_state_pair():
     # bf_batch_forward_saved / bf_batch_backward_saved: the same outputs as the
-    # graphed forward and, from the same forward state (the same kernel writes
-    # it), exactly the recomputing adjoint's gradients; the W = 30 box image
-    # takes the streamed adjoint from the saved planes as well
+    # graphed forward (to rounding where the graphed forward takes the image's own
+    # streamed plan and the saved form the fused tiles: both within the oracle
+    # tolerance) and, from the same forward state (the same kernel writes it),
+    # exactly the recomputing adjoint's gradients; the W = 30 box image takes the
+    # streamed adjoint from the saved planes as well
     torch, P = _mods()
     specs = _grad_batch(33)
+    tol = [1e-3 if _own_plan(s) else 1e-5 for s in specs]
+    assert 1e-3 in tol and 1e-5 in tol
     batch = P.Batch(specs)
     assert all(s >= 0 for s in batch.image_status)
     imgs = [torch.tensor(synthimg.gen2(s["height"], s["width"], 900 + i), dtype=torch.float32, device="cuda")
@@ -223,7 +235,7 @@ def test_batch_saved_state_pair():
         gin, gs = batch.backward(imgs, gouts, saved=saved)
         torch.cuda.synchronize()
         for i in range(len(specs)):
-            assert torch.abs(out[i] - ref_out[i]).max().item() <= 1e-5, (rep, i)
+            assert torch.abs(out[i] - ref_out[i]).max().item() <= tol[i], (rep, i)
             assert torch.equal(gin[i], ref_gin[i]), (rep, i)
         assert torch.equal(torch.nan_to_num(gs, nan=7.0), torch.nan_to_num(ref_gs, nan=7.0)), rep
 
