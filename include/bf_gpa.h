@@ -254,7 +254,11 @@ int bf_backward(const bf_plan_t* plan, const float* in, int64_t in_pitch,
  * per image and a work list of tiles ordered by decreasing cost; the
  * forward runs as ONE persistent kernel launch whose workgroups claim tiles
  * from a device counter.  The launch sequence is captured in a hipGraph on
- * the first bf_batch_forward and replayed afterwards.  Image pointer
+ * the first bf_batch_forward and replayed afterwards.  Images that a
+ * single-image plan would run on the streamed passes (Gaussian W >= 16, wide
+ * box supports on large images) get such a plan of their own instead: their
+ * launches run on four side streams of the batch, forked from and joined back
+ * into `stream`, concurrently with the persistent launch.  Image pointer
  * arrays are host arrays of `count` DEVICE pointers, copied at call time.
  * Per-image plan problems are reported by bf_batch_status. */
 int bf_batch_plan(int32_t count, const bf_params* per_image, bf_batch_t** out);
