@@ -249,3 +249,33 @@ def test_batch_saved_state_errors():
     g = P.Batch([dict(kernel="gauss", sigma_s=2.0, sigma_r=30.0, height=20, width=30, grad=True)])
     with pytest.raises(ValueError):
         g.forward(x, saved=[torch.empty(10, device="cuda")])           # too small
+
+
+def test_side_streams_on_a_caller_stream():
+    # images with Gaussian W >= 16 take their own streamed plans on the batch's side streams (more
+    # of them than side streams), the others the persistent launch; three graph replays with new
+    # inputs on a non-default caller stream, each image against the oracle, and the stream's order
+    # kept: a kernel queued behind the call on the same stream sees the finished outputs
+    torch, P = _mods()
+    specs = [dict(kernel="gauss", sigma_s=ss, sigma_r=sr, height=H, width=Wd)
+             for ss, sr, H, Wd in [(6.0, 30.0, 90, 130), (2.0, 25.0, 70, 64), (10.0, 40.0, 120, 75),
+                                   (15.0, 30.0, 80, 200), (7.0, 20.0, 64, 64), (1.5, 50.0, 33, 170),
+                                   (12.0, 35.0, 100, 100), (8.5, 45.0, 66, 140)]]
+    batch = P.Batch(specs)
+    assert all(s >= 0 for s in batch.image_status)
+    stream = torch.cuda.Stream()
+    for rep in range(3):
+        imgs = [torch.tensor(synthimg.gen2(s["height"], s["width"], 700 + 10 * rep + i), dtype=torch.float32,
+                             device="cuda") for i, s in enumerate(specs)]
+        torch.cuda.synchronize()
+        with torch.cuda.stream(stream):
+            outs = batch.forward(imgs, stream=stream)
+            sums = torch.stack([o.double().sum() for o in outs])  # queued behind the call on `stream`
+        torch.cuda.synchronize()
+        for i, s in enumerate(specs):
+            W = K.support("gauss", sigma_s=s["sigma_s"])
+            f32 = imgs[i].cpu().numpy().astype(np.float64)
+            ref = _oracle(f32, s, batch.N[i], W)
+            got = outs[i].cpu().numpy().astype(np.float64)
+            assert np.abs(got - ref).max() <= TOL, (rep, i)
+            assert abs(sums[i].item() - got.sum()) <= 1e-6 * abs(got.sum()), (rep, i)
