@@ -112,6 +112,19 @@ def test_ragged_and_tiny(shape):
         assert np.abs(out - ref).max() <= TOL, (kind, shape)
 
 
+@pytest.mark.parametrize("shape", [(1, 1), (1, 200), (200, 1), (3, 3), (5, 64), (64, 5), (65, 129)])
+def test_ragged_and_tiny_wide_gaussian(shape):
+    # Gaussians from W = 16 on take the streamed passes at every image size: W = 18 (matrix-core
+    # column pass) and W = 45 (split column pass), supports far beyond the image
+    f = synthimg.gen1(*shape, 33)
+    for ss in (6.0, 15.0):
+        out, plan, f32 = _gpu_forward(f, "gauss", 25.0, sigma_s=ss)
+        assert plan.info.tile_rows == 0, (ss, shape)
+        w1, _ = _taps("gauss", dict(sigma_s=ss))
+        ref = G.gpa_alg2(f32, w1, 25.0, plan.info.N, 127.5)
+        assert np.abs(out - ref).max() <= TOL, (ss, shape)
+
+
 def test_support_zero_is_identity():
     f = synthimg.gen2(50, 70, 41)
     out, plan, f32 = _gpu_forward(f, "box", 30.0, W=0)
