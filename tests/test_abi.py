@@ -111,6 +111,14 @@ def test_engine_selection():
     s = P.bf_order("gauss", 30.0, sigma_s=3.0, engine="streamed", **kw)
     assert s.path == L.BF_PATH_STREAMED
     assert P.bf_order("gauss", 30.0, sigma_s=25.0, **kw).path == L.BF_PATH_STREAMED  # W = 75
+    # the Gaussian takes the streamed passes from W = 16 at every size (W = 15 stays fused below 2^22
+    # pixels, W = 13 goes streamed from 2^22 pixels); the box keeps its fused tiles below 2^20 pixels
+    for H, Wd in ((1, 1), (64, 64), (512, 512), (768, 1024)):
+        assert P.bf_order("gauss", 30.0, sigma_s=5.0, height=H, width=Wd).path == L.BF_PATH_TILE  # W = 15
+        assert P.bf_order("gauss", 30.0, sigma_s=5.1, height=H, width=Wd).path == L.BF_PATH_STREAMED  # W = 16
+        assert P.bf_order("box", 30.0, W=40, height=H, width=Wd).path == L.BF_PATH_TILE
+    assert P.bf_order("gauss", 30.0, sigma_s=4.3, height=2048, width=2048).path == L.BF_PATH_STREAMED  # W = 13
+    assert P.bf_order("box", 30.0, W=40, height=1024, width=1024).path == L.BF_PATH_STREAMED
     for bad, code in [(dict(kernel="box", W=3), L.BF_EUNSUPPORTED),             # Gaussian only
                       (dict(kernel="gauss", sigma_s=15.4), L.BF_EUNSUPPORTED),  # W = 47 > 45
                       (dict(kernel="gauss", sigma_s=3.0, joint=True), L.BF_EUNSUPPORTED)]:
