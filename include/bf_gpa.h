@@ -278,9 +278,11 @@ int bf_batch_tune(bf_batch_t* batch, const float* const* in, const int64_t* in_p
  * persistent batch launch; the adjoint tiles of all images whose support
  * fits the fused adjoint run as one more persistent launch over a
  * cost-ordered work list, and wider supports run the streamed adjoint image
- * by image.  Images with BF_FLAG_MIRROR run bf_backward of a plan of their
- * own (built at bf_batch_plan, on the image extended by reflection), image
- * by image, recomputing their state.  Arguments are host arrays of `count` entries:
+ * by image.  Images on a streamed plan of their own (see bf_batch_plan) run
+ * that plan's bf_backward on the batch's side streams, concurrently.  Images
+ * with BF_FLAG_MIRROR run bf_backward of a plan of their own (built at
+ * bf_batch_plan, on the image extended by reflection), image by image,
+ * recomputing their state.  Arguments are host arrays of `count` entries:
  *   in, in_pitch          the images and row pitches (device pointers)
  *   grad_out, gout_pitch  dL/d(out_i)
  *   grad_in, gin_pitch    NULL, or receives dL/d(in_i) (an entry may be NULL)

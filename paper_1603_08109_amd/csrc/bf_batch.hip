@@ -235,6 +235,7 @@ struct bf_batch {
   void* d_bls = nullptr;              // streamed adjoint state, reused image by image
   double* d_bls_partials = nullptr;
   std::vector<int> mirrored;          // images with the reflecting border: adjoint through their own plan
+  std::vector<bool> own_adj;          // images whose adjoint runs on their own streamed plan (fplans)
   std::vector<bf_plan_t*> mplans;     // those plans (per image, null elsewhere)
 };
 
@@ -369,18 +370,32 @@ static int stage(bf_batch* b, int k, const float* const* in, const int64_t* in_p
   return BF_OK;
 }
 
-// save: the staged params carry per-image saved planes, written as well, for
-// every image; otherwise only the tiles of images without a plan of their own
+// The tiles of images without a plan of their own; save: the staged params
+// carry per-image saved planes, written as well.
 static int run_direct(bf_batch* b, int k, hipStream_t s, int grid, bool save = false) {
   const BatchShape& sh = b->cands[b->chosen];
   if (hipMemcpyAsync(b->d_params, b->h_stage[k], b->count * sizeof(TileParams), hipMemcpyHostToDevice,
                      s) != hipSuccess)
     return fail(BF_EHIP, "hipMemcpyAsync batch params");
   hipLaunchKernelGGL(batch_reset_kernel, dim3(1), dim3(64), 0, s, b->d_counter);
-  hipError_t e = launch_batch_v(sh.variant, b->d_params, save ? b->d_tiles : b->d_ftiles,
-                                save ? b->ntiles : b->nftiles, b->d_counter, grid, sh.lds, b->acc64, save, s);
+  hipError_t e = launch_batch_v(sh.variant, b->d_params, b->d_ftiles, b->nftiles, b->d_counter, grid, sh.lds,
+                                b->acc64, save, s);
   if (e != hipSuccess) return fail(BF_EHIP, std::string("batch launch: ") + hipGetErrorString(e));
   return BF_OK;
+}
+
+// Side streams: fork them from `s` (they start after the work queued on `s` so far) and join
+// them back into it (work queued on `s` afterwards waits for theirs).
+static void fork_side(bf_batch* b, hipStream_t s) {
+  hipEventRecord(b->fork_ev, s);
+  for (int j = 0; j < bf_batch::kAux; ++j) hipStreamWaitEvent(b->aux[j], b->fork_ev, 0);
+}
+
+static void join_side(bf_batch* b, hipStream_t s) {
+  for (int j = 0; j < bf_batch::kAux; ++j) {
+    hipEventRecord(b->join_ev[j], b->aux[j]);
+    hipStreamWaitEvent(s, b->join_ev[j], 0);
+  }
 }
 
 // Adjoint planning: images whose support fits the fused adjoint tiles get
@@ -403,12 +418,15 @@ static int plan_batch_adjoint(bf_batch* b) {
       return fail(BF_EINVAL, "batch mirror adjoint: order or support differs from the batch plan");
     b->mirrored.push_back(i);
   }
+  b->own_adj.assign(count, false);
+  for (int i = 0; i < count; ++i)
+    b->own_adj[i] = b->status[i] >= 0 && b->fplans[i] && !b->mplans[i];
   int best = -1, best_n = -1;
   for (int v = 0; v < backward_variant_count(); ++v) {
     const Variant vv = backward_variant(v);
     int n = 0;
     for (int i = 0; i < count; ++i) {
-      if (b->status[i] < 0 || b->mplans[i]) continue;
+      if (b->status[i] < 0 || b->mplans[i] || b->own_adj[i]) continue;
       const int TY = 4 * vv.opt, W = b->prm[i].W;
       const bool sigs = b->prm[i].kernel == BF_GAUSS;
       if (region_floats_bwd(TY, W) <= (int64_t)kThreads * vv.mreg &&
@@ -434,7 +452,7 @@ static int plan_batch_adjoint(bf_batch* b) {
     const bool sigs = p.kernel == BF_GAUSS;
     b->saved_off[i] = saved;
     saved += 3 * (int64_t)p.height * p.width;
-    if (b->mplans[i]) continue;
+    if (b->mplans[i] || b->own_adj[i]) continue;
     const int TY = 4 * vv.opt;
     if (region_floats_bwd(TY, p.W) <= (int64_t)kThreads * vv.mreg &&
         backward_lds_bytes(TY, p.W, sigs) + 2 * kThreads * 8 + 64 <= max_lds_bytes()) {
@@ -569,7 +587,9 @@ int bf_batch_plan(int32_t count, const bf_params* per_image, bf_batch_t** out) {
   b->fplans.assign(count, nullptr);
   for (int i = 0; i < count; ++i) {
     if (b->status[i] < 0 || b->info[i].path != BF_PATH_STREAMED) continue;
-    const int st = bf_plan(&b->prm[i], &b->fplans[i]);
+    bf_params q = b->prm[i];
+    if (b->grad && !(q.flags & BF_FLAG_MIRROR)) q.flags |= BF_FLAG_GRAD;  // its adjoint runs on it too
+    const int st = bf_plan(&q, &b->fplans[i]);
     if (st < 0) {
       bf_batch_destroy(b);
       return st;
@@ -756,11 +776,24 @@ int bf_batch_forward_saved(bf_batch_t* b, const float* const* in, const int64_t*
     if (!saved[i]) return fail(BF_EINVAL, "NULL saved pointer in batch");
     b->h_stage[k][i].saved = saved[i];
   }
-  st = run_direct(b, k, s, grid_of(b), true);
+  // images on their own streamed plans run it on the side streams (keeping their state there
+  // unless their adjoint is the mirror plan's, which recomputes)
+  const bool side = b->fork_ev != nullptr;
+  if (side) fork_side(b, s);
+  st = run_direct(b, k, s, grid_of(b, false), true);
   if (st < 0) return st;
+  int fst = BF_OK;
+  if (side) {
+    for (int j = 0; j < bf_batch::kAux; ++j)
+      for (int i : b->aux_imgs[j])
+        if (fst >= 0)
+          fst = bf_forward(b->fplans[i], in[i], in_pitch[i], out[i], out_pitch[i], b->own_adj[i] ? saved[i] : nullptr,
+                           b->aux[j]);
+    join_side(b, s);
+  }
   hipEventRecord(b->ev[k], s);
   b->ev_used[k] = true;
-  return BF_OK;
+  return fst < 0 ? fst : BF_OK;
 }
 
 }  // extern "C"
@@ -802,11 +835,15 @@ static int batch_backward(bf_batch_t* b, const float* const* in, const int64_t* 
   if (hipMemcpyAsync(b->d_bparams, b->h_bstage, 2 * (size_t)n * sizeof(TileParams), hipMemcpyHostToDevice, s) !=
       hipSuccess)
     return fail(BF_EHIP, "hipMemcpyAsync batch adjoint params");
+  // the side streams start here (their work is queued after the persistent launches below, and
+  // runs concurrently with them)
+  const bool side = b->fork_ev != nullptr;
+  if (side) fork_side(b, s);
   hipLaunchKernelGGL(batch_reset_kernel, dim3(1), dim3(64), 0, s, b->d_counter);
   hipError_t e = hipSuccess;
   if (!saved) {
-    e = launch_batch_v(sh.variant, b->d_bparams, b->d_tiles, b->ntiles, b->d_counter, grid_of(b), sh.lds, b->acc64,
-                       true, s);
+    e = launch_batch_v(sh.variant, b->d_bparams, b->d_ftiles, b->nftiles, b->d_counter, grid_of(b, false), sh.lds,
+                       b->acc64, true, s);
     if (e != hipSuccess) return fail(BF_EHIP, std::string("batch forward-state launch: ") + hipGetErrorString(e));
   }
   if (b->nbtiles > 0) {
@@ -839,9 +876,21 @@ static int batch_backward(bf_batch_t* b, const float* const* in, const int64_t* 
                                grad_sigma ? grad_sigma + 2 * i : nullptr, stream);
     if (st < 0) return st;
   }
+  // images on their own streamed plans: their whole adjoint on the side streams (the state
+  // recomputed by that plan unless saved); sigma gradients written by that plan only
+  int ost = BF_OK;
+  if (side) {
+    for (int j = 0; j < bf_batch::kAux; ++j)
+      for (int i : b->aux_imgs[j])
+        if (b->own_adj[i] && ost >= 0)
+          ost = bf_backward(b->fplans[i], in[i], in_pitch[i], grad_out[i], gout_pitch[i], saved ? saved[i] : nullptr,
+                            grad_in ? grad_in[i] : nullptr, (grad_in && grad_in[i]) ? gin_pitch[i] : 0,
+                            grad_sigma ? grad_sigma + 2 * i : nullptr, b->aux[j]);
+    join_side(b, s);
+  }
   hipEventRecord(b->bev, s);
   b->bev_used = true;
-  return BF_OK;
+  return ost < 0 ? ost : BF_OK;
 }
 
 extern "C" {
