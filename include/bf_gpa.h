@@ -300,7 +300,8 @@ int bf_batch_backward(bf_batch_t* batch, const float* const* in, const int64_t* 
 /* The batch pair with the forward state kept by the caller (as bf_forward /
  * bf_backward with `saved`), so the adjoint skips its recompute launch.
  * bf_batch_forward_saved runs the persistent forward directly (not from the
- * captured graph) and also writes, for image i, three planes of
+ * captured graph; images on their own streamed plans run those on the side
+ * streams) and also writes, for image i, three planes of
  * height*width float32 (dense pitch = width) to the DEVICE buffer saved[i];
  * bf_batch_backward_saved takes the same arrays and reads them.  `saved` is
  * a host array of `count` device pointers; entries of images whose plan
