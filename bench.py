@@ -426,8 +426,27 @@ def main():
                             "recompute_ms": round(ms_fr, 3), "recompute_mpix_s": round(px5 / ms_fr / 1e3, 1),
                             "mirror_recompute_ms": round(ms_fm, 3),
                             "mirror_recompute_mpix_s": round(px5 / ms_fm / 1e3, 1)}
+        # a wide support (sigma_s = 10, W = 30): per image the streamed forward and the streamed
+        # adjoint; in the batch each image's own plan on the side streams
+        plan10 = P.Plan("gauss", 30.0, 512, 512, sigma_s=10.0, grad=True)
+        wbatch = P.Batch([dict(kernel="gauss", sigma_s=10.0, sigma_r=30.0, height=512, width=512, grad=True)
+                          for _ in range(32)])
+        gw = [(outs[b] - tgts[b]) * (2.0 / outs[b].numel()) for b in range(32)]
+
+        def fwd_bwd_wide():
+            for b in range(32):
+                plan10.forward(imgs[b], out=outs[b])
+                plan10.backward(imgs[b], gw[b], grad_in=gins[b])
+
+        def fwd_bwd_wide_batched():
+            wbatch.forward(imgs, outs)
+            wbatch.backward(imgs, gw, grad_ins=bgins)
+
+        ms_w = time_launches(fwd_bwd_wide, stream, 1, max(1, a.steps // 2), torch)
+        ms_wb = time_launches(fwd_bwd_wide_batched, stream, 1, max(1, a.steps // 2), torch)
+        extra["fwd_bwd"].update({"wide_sigma_s10_ms": round(ms_w, 3), "wide_sigma_s10_batched_ms": round(ms_wb, 3)})
         print(f"# fwd_bwd {extra['fwd_bwd']}", file=sys.stderr, flush=True)
-        del imgs, tgts, saved, outs, gins, bgins, ref_gins, gbatch, bsaved
+        del imgs, tgts, saved, outs, gins, bgins, ref_gins, gbatch, bsaved, wbatch, plan10, gw
 
         # batched workload: 256 uneven images, one persistent launch vs per-image launches
         specs = synthimg.batch_params(256, 4000)
