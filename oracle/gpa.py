@@ -9,11 +9,12 @@ Two independent evaluations of the same filter are given:
   (t, tau) = (h(i-j), h(i)) on the centred image h = f - c (Sec. 2:
   t = f(i-j), tau = f(i); Sec. 3, eq. shift: the intensities are centred
   before the expansion, and the centre is added back at the end).
-* ``gpa_alg2`` follows Algorithm 2 (Sec. 3) step by step: the N+1
+* ``gpa_alg2`` evaluates the form Algorithm 2 (Sec. 3) computes: the N+1
   auxiliary images F_n = exp(-h^2/2 sigma_r^2) (h/sigma_r)^n of
-  eq. (intImg) are produced recursively, each is filtered with the spatial
-  kernel (eq. spatialFiltering), and the numerator P and denominator Q of
-  eqs. (P), (Q) are accumulated with the recursively updated G_n/n!.
+  eq. (intImg), each filtered with the spatial kernel (eq.
+  spatialFiltering), and the numerator P and denominator Q of eqs. (P),
+  (Q) summed over n with the weights G_n/n! (``gpa_sums``; the other
+  modules pass their own spatial filter to it).
 
 Appendix B shows the two agree in exact arithmetic; the tests pin that.
 "Order N" is the number of Taylor terms n = 0..N-1 of eq. (approx), so
@@ -145,26 +146,50 @@ def spatial_filter(F: np.ndarray, w1: np.ndarray) -> np.ndarray:
     return out
 
 
-def gpa_alg2(f: np.ndarray, w1: np.ndarray, sigma_r: float, N: int, T: float,
-             return_pq: bool = False):
-    """Algorithm 2 (Sec. 3) in float64.  T is the centre of the dynamic range
-    [0, 2T] (the paper centres with t_c = T)."""
+def power_over_factorial(u: np.ndarray, N: int):
+    """The weights u^n / n! of eqs. (P) and (Q) for n = 0 .. N-1 (G_n(i)/n!
+    with G_n = u^n of eq. intImg), each the product of the n factors u/k,
+    k = 1 .. n, so that no power or factorial leaves the float64 range."""
+    c = np.ones_like(u)
+    for n in range(N):
+        yield n, c
+        c = c * (u / (n + 1))
+
+
+def gpa_sums(f: np.ndarray, filt, sigma_r: float, N: int, T: float):
+    """Eqs. (intImg), (spatialFiltering), (P), (Q) and (PbyQ) of Sec. 3 for
+    the image centred by eq. (shift) with t_c = T, h = f - T, u = h/sigma_r:
+
+        F_n = exp(-u^2/2) u^n,   Fbar_n = filt(F_n)            n = 0 .. N
+        Q   = sum_{n<N} u^n/n! Fbar_n
+        P   = sigma_r sum_{n<N} u^n/n! Fbar_{n+1}
+        out = P / Q + T
+
+    `filt` is the spatial filtering of eq. (spatialFiltering) (any border
+    rule and any number of axes).  Every F_n is formed from its definition and
+    filtered once, N + 1 filterings in all.  Returns (out, P, Q)."""
     f = np.asarray(f, dtype=np.float64)
-    # initialisation loop over pixels
-    h = f - T
-    F = np.exp(-(h * h) / (2.0 * sigma_r * sigma_r))
-    G = np.ones_like(f)
+    u = (f - T) / sigma_r
+    E = np.exp(-0.5 * u * u)
     P = np.zeros_like(f)
     Q = np.zeros_like(f)
-    Hh = h / sigma_r
-    Fbar = spatial_filter(F, w1)
-    for n in range(1, N + 1):
-        Q = Q + G * Fbar
-        F = Hh * F
-        Fbar = spatial_filter(F, w1)
-        P = P + G * Fbar
-        G = Hh * G / n
-    out = sigma_r * (P / Q) + T
+    Fbar_n = filt(E)
+    for n, c in power_over_factorial(u, N):
+        Fbar_next = filt(E * u ** (n + 1))
+        Q += c * Fbar_n
+        P += c * Fbar_next
+        Fbar_n = Fbar_next
+    P *= sigma_r
+    return P / Q + T, P, Q
+
+
+def gpa_alg2(f: np.ndarray, w1: np.ndarray, sigma_r: float, N: int, T: float,
+             return_pq: bool = False):
+    """The N + 1 filtering form of eq. (GPA) (eqs. P, Q, PbyQ; Algorithm 2
+    computes the same sums) with the separable zero-extension filter
+    ``spatial_filter``.  T is the centre of the dynamic range [0, 2T] (the
+    paper centres with t_c = T).  return_pq: also P and Q."""
+    out, P, Q = gpa_sums(f, lambda F: spatial_filter(F, w1), sigma_r, N, T)
     if return_pq:
         return out, P, Q
     return out

@@ -8,11 +8,12 @@ gbar = dL/d(out), the quantities checked are the vector-Jacobian products
 
 with N and the support W held fixed.
 
-* ``vjp_autograd`` builds the GPA of Algorithm 2 (Sec. 3) from plain torch
-  CPU float64 operations (the separable zero-padded spatial filter is a
-  pair of 1-D convolutions) and lets torch.autograd differentiate it.
+* ``vjp_autograd`` builds the N + 1 filtering form of the GPA (eqs. P, Q,
+  PbyQ of Sec. 3) from plain torch CPU float64 operations (the separable
+  zero-padded spatial filter is a pair of 1-D convolutions) and lets
+  torch.autograd differentiate it.
 * ``vjp_fd`` takes central finite differences of L = sum(gbar * out) with
-  the numpy Algorithm 2 of ``oracle.gpa`` (a separate code path).
+  the numpy filtering form of ``oracle.gpa`` (a separate code path).
 * ``mirror=True`` on either: the same with the reflecting
   border (image extended by reflection about its edges, edge samples
   repeated); autograd differentiates the reflection as the gather it is, the
@@ -45,21 +46,25 @@ def _filter_torch(F: torch.Tensor, w1: torch.Tensor) -> torch.Tensor:
 
 def gpa_torch(f: torch.Tensor, sigma_r: torch.Tensor, sigma_s, kind: str, W: int,
               N: int, T: float) -> torch.Tensor:
-    """Algorithm 2 (Sec. 3) in differentiable torch float64."""
+    """Eqs. (intImg), (spatialFiltering), (P), (Q), (PbyQ) (Sec. 3) in
+    differentiable torch float64, with the centring of eq. (shift), t_c = T:
+    F_n = exp(-u^2/2) u^n with u = (f - T)/sigma_r, each filtered once, and
+    the sums of eqs. (P), (Q) with the weights u^n/n!."""
     w1 = _taps_torch(kind, sigma_s, W)
-    h = f - T
-    F = torch.exp(-(h * h) / (2.0 * sigma_r * sigma_r))
-    G = torch.ones_like(f)
+    u = (f - T) / sigma_r
+    E = torch.exp(-0.5 * u * u)
     P = torch.zeros_like(f)
     Q = torch.zeros_like(f)
-    Hh = h / sigma_r
-    Fbar = _filter_torch(F, w1)
-    for n in range(1, N + 1):
-        Q = Q + G * Fbar
-        F = Hh * F
-        Fbar = _filter_torch(F, w1)
-        P = P + G * Fbar
-        G = Hh * G / n
+    c = torch.ones_like(f)          # u^n / n!, the product of the factors u/k
+    Fbar_n = _filter_torch(E, w1)
+    un = torch.ones_like(f)         # u^n
+    for n in range(N):
+        un = un * u
+        Fbar_next = _filter_torch(E * un, w1)
+        Q = Q + c * Fbar_n
+        P = P + c * Fbar_next
+        Fbar_n = Fbar_next
+        c = c * (u / (n + 1))
     return sigma_r * (P / Q) + T
 
 

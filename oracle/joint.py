@@ -27,7 +27,7 @@ from __future__ import annotations
 import numpy as np
 
 from .bf import range_kernel
-from .gpa import phi, spatial_filter
+from .gpa import phi, power_over_factorial, spatial_filter
 
 
 def direct_joint_bf(f: np.ndarray, h: np.ndarray, w2: np.ndarray, sigma_r: float) -> np.ndarray:
@@ -117,19 +117,16 @@ def gpa_joint_pairwise_at(f: np.ndarray, h: np.ndarray, pixels: np.ndarray, w2: 
 
 def gpa_joint_alg2(f: np.ndarray, h: np.ndarray, w1: np.ndarray, sigma_r: float, N: int,
                    T: float) -> np.ndarray:
-    """The Algorithm-2 form of the cross filter: F_n from the guide by the
-    recursion of eq. (intImg), 2N spatial filterings (F_n and F_n f), and
-    the G_n/n! recursion of Algorithm 2 for the weights."""
+    """The filtering form of the cross filter written above: F_n = exp(-x^2/2)
+    x^n of the centred guide (eq. intImg), 2N spatial filterings (of F_n and of
+    F_n f), weights x^n/n! at the centre pixel, out = P / Q."""
     f = np.asarray(f, dtype=np.float64)
-    hc = np.asarray(h, dtype=np.float64) - T
-    F = np.exp(-(hc * hc) / (2.0 * sigma_r * sigma_r))
-    G = np.ones_like(f)
+    x = (np.asarray(h, dtype=np.float64) - T) / sigma_r
+    E = np.exp(-0.5 * x * x)
     P = np.zeros_like(f)
     Q = np.zeros_like(f)
-    Hh = hc / sigma_r
-    for n in range(N):
-        Q = Q + G * spatial_filter(F, w1)
-        P = P + G * spatial_filter(F * f, w1)
-        F = Hh * F
-        G = Hh * G / (n + 1)
+    for n, c in power_over_factorial(x, N):
+        Fn = E * x ** n
+        Q += c * spatial_filter(Fn, w1)
+        P += c * spatial_filter(Fn * f, w1)
     return P / Q

@@ -102,23 +102,9 @@ def gpa_pairwise(f: np.ndarray, sigma_s: float, sigma_r: float, N: int, center: 
 
 
 def gpa_alg2(f: np.ndarray, sigma_s: float, sigma_r: float, N: int, T: float) -> np.ndarray:
-    """Algorithm 2 (Sec. 3) with ``spatial_filter`` above as step (spatialFiltering):
-    F_n by the recursion of eq. (intImg), N+1 filterings, G_n/n! recursively."""
-    f = np.asarray(f, dtype=np.float64)
-    h = f - T
-    F = np.exp(-(h * h) / (2.0 * sigma_r * sigma_r))
-    G = np.ones_like(f)
-    P = np.zeros_like(f)
-    Q = np.zeros_like(f)
-    Hh = h / sigma_r
-    Fbar = spatial_filter(F, sigma_s)
-    for n in range(1, N + 1):
-        Q = Q + G * Fbar
-        F = Hh * F
-        Fbar = spatial_filter(F, sigma_s)
-        P = P + G * Fbar
-        G = Hh * G / n
-    return sigma_r * (P / Q) + T
+    """Eqs. (P), (Q), (PbyQ) (the sums of ``oracle.gpa.gpa_sums``) with
+    ``spatial_filter`` above as eq. (spatialFiltering): N+1 filterings."""
+    return _gpa.gpa_sums(f, lambda F: spatial_filter(F, sigma_s), sigma_r, N, T)[0]
 
 
 def gpa_alg2_at(f: np.ndarray, pixels: np.ndarray, sigma_s: float, sigma_r: float, N: int,
@@ -131,25 +117,21 @@ def gpa_alg2_at(f: np.ndarray, pixels: np.ndarray, sigma_s: float, sigma_r: floa
     rr, cc = px[:, 0], px[:, 1]
     Kr = kernel(rr[:, None] - np.arange(H)[None, :], sigma_s)
     Kc = kernel(cc[:, None] - np.arange(Wd)[None, :], sigma_s)
-    h = f - T
-    Hh = h / sigma_r
-    F = np.exp(-(h * h) / (2.0 * sigma_r * sigma_r))
-    hp = Hh[rr, cc]
-    G = np.ones(len(px))
-    P = np.zeros(len(px))
-    Q = np.zeros(len(px))
+    u = (f - T) / sigma_r
+    E = np.exp(-0.5 * u * u)
 
     def at(F):
         return ((Kr @ F) * Kc).sum(axis=1)
 
-    Fbar = at(F)
-    for n in range(1, N + 1):
-        Q = Q + G * Fbar
-        F = Hh * F
-        Fbar = at(F)
-        P = P + G * Fbar
-        G = hp * G / n
-    return sigma_r * (P / Q) + T
+    P = np.zeros(len(px))
+    Q = np.zeros(len(px))
+    Fbar_n = at(E)
+    for n, c in _gpa.power_over_factorial(u[rr, cc], N):
+        Fbar_next = at(E * u ** (n + 1))
+        Q += c * Fbar_n
+        P += c * Fbar_next
+        Fbar_n = Fbar_next
+    return sigma_r * P / Q + T
 
 
 def iir_sections(sigma_s: float):

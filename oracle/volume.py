@@ -19,6 +19,7 @@ from __future__ import annotations
 import numpy as np
 
 from .bf import range_kernel
+from . import gpa as _gpa
 from .gpa import phi, phi_wide
 
 
@@ -90,23 +91,9 @@ def spatial_filter(F: np.ndarray, w1: np.ndarray) -> np.ndarray:
 
 
 def gpa_alg2(f: np.ndarray, w1: np.ndarray, sigma_r: float, N: int, T: float) -> np.ndarray:
-    """Algorithm 2 (Sec. 3) on a volume: the same recursions, filtering over
-    three axes."""
-    f = np.asarray(f, dtype=np.float64)
-    h = f - T
-    F = np.exp(-(h * h) / (2.0 * sigma_r * sigma_r))
-    G = np.ones_like(f)
-    P = np.zeros_like(f)
-    Q = np.zeros_like(f)
-    Hh = h / sigma_r
-    Fbar = spatial_filter(F, w1)
-    for n in range(1, N + 1):
-        Q = Q + G * Fbar
-        F = Hh * F
-        Fbar = spatial_filter(F, w1)
-        P = P + G * Fbar
-        G = Hh * G / n
-    return sigma_r * (P / Q) + T
+    """Eqs. (P), (Q), (PbyQ) on a volume: the sums of ``oracle.gpa.gpa_sums``
+    with ``spatial_filter`` above (three axes) as eq. (spatialFiltering)."""
+    return _gpa.gpa_sums(f, lambda F: spatial_filter(F, w1), sigma_r, N, T)[0]
 
 
 def _reflect_pad(f: np.ndarray, W: int) -> np.ndarray:
