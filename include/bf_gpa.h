@@ -251,21 +251,38 @@ int bf_backward(const bf_plan_t* plan, const float* in, int64_t in_pitch,
 
 /* Batched forward over many images of uneven size, each with its own
  * parameters (an extension beyond the paper).  bf_batch_plan builds one plan
- * per image and a work list of tiles ordered by decreasing cost; the
- * forward runs as ONE persistent kernel launch whose workgroups claim tiles
- * from a device counter.  The launch sequence is captured in a hipGraph on
- * the first bf_batch_forward and replayed afterwards.  Images that a
- * single-image plan would run on the streamed passes (Gaussian W >= 16, wide
- * box supports on large images) get such a plan of their own instead: their
- * launches run on four side streams of the batch, forked from and joined back
- * into `stream`, concurrently with the persistent launch.  Image pointer
- * arrays are host arrays of `count` DEVICE pointers, copied at call time.
- * Per-image plan problems are reported by bf_batch_status. */
+ * per image and a work list of tiles ordered by decreasing cost; the images
+ * that fit the fused tiles run as ONE persistent kernel launch whose
+ * workgroups claim tiles from a device counter.  Images that a single-image
+ * plan would run on the streamed passes (Gaussian W >= 16, wide box supports
+ * on large images) get such a plan of their own instead; their launches run
+ * on four side streams of the batch, forked from the persistent launch's
+ * stream and joined back, concurrently with it, and read their image
+ * pointers from the batch's device copy of the call's parameters.  The whole
+ * sequence (parameter copy, fork, persistent launch, side-stream launches,
+ * join) is captured in a hipGraph on the first bf_batch_forward of each of two
+ * staging slots, and every call is then ONE hipGraphLaunch on `stream`
+ * (bf_batch_get_info counts them).  Image pointer arrays are host arrays of
+ * `count` DEVICE pointers, copied at call time into pinned staging that the
+ * graph copies to the device.  Per-image plan problems are reported by
+ * bf_batch_status. */
 int bf_batch_plan(int32_t count, const bf_params* per_image, bf_batch_t** out);
 int bf_batch_forward(bf_batch_t* batch, const float* const* in, const int64_t* in_pitch,
                      float* const* out, const int64_t* out_pitch, void* stream);
 /* Per-image N and status codes (host arrays of `count`, either may be NULL). */
 int bf_batch_status(const bf_batch_t* batch, int32_t* per_image_status, int32_t* per_image_N);
+
+/* How a batch runs (an extension beyond the paper; a pure query). */
+typedef struct bf_batch_info {
+  int32_t images_persistent;       /* images whose tiles the persistent launch claims */
+  int32_t images_streamed;         /* images on a streamed plan of their own (side streams) */
+  int64_t persistent_lds_bytes;    /* dynamic LDS per workgroup of the chosen persistent shape,
+                                      sized for the persistent images only */
+  int64_t workspace_bytes;         /* device bytes held by the batch and its images' plans */
+  int64_t forward_graph_launches;  /* hipGraphLaunch calls bf_batch_forward has made */
+  int64_t forward_direct_launches; /* launch sequences bf_batch_forward issued outside its graph */
+} bf_batch_info;
+int bf_batch_get_info(const bf_batch_t* batch, bf_batch_info* out);
 /* Time the candidate launch shapes for this batch on `stream` (inputs as
  * for bf_batch_forward) and keep the fastest; the choice is cached in the
  * file named by BF_TUNE_CACHE (if set), keyed by the batch's shape summary.

@@ -61,6 +61,17 @@ class bf_params(C.Structure):
     ]
 
 
+class bf_batch_info(C.Structure):
+    _fields_ = [
+        ("images_persistent", C.c_int32),
+        ("images_streamed", C.c_int32),
+        ("persistent_lds_bytes", C.c_int64),
+        ("workspace_bytes", C.c_int64),
+        ("forward_graph_launches", C.c_int64),
+        ("forward_direct_launches", C.c_int64),
+    ]
+
+
 class bf_plan_info(C.Structure):
     _fields_ = [
         ("N", C.c_int32),
@@ -97,6 +108,7 @@ SIGNATURES = {
     "bf_batch_forward": (C.c_int, [C.c_void_p, C.POINTER(C.c_void_p), C.POINTER(C.c_int64),
                                    C.POINTER(C.c_void_p), C.POINTER(C.c_int64), C.c_void_p]),
     "bf_batch_status": (C.c_int, [C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
+    "bf_batch_get_info": (C.c_int, [C.c_void_p, C.POINTER(bf_batch_info)]),
     "bf_batch_tune": (C.c_int, [C.c_void_p, C.POINTER(C.c_void_p), C.POINTER(C.c_int64),
                                 C.POINTER(C.c_void_p), C.POINTER(C.c_int64), C.c_void_p,
                                 C.POINTER(C.c_int32)]),

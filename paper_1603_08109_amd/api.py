@@ -326,6 +326,13 @@ class Batch:
                                                       gsp, _stream_handle(stream)), "bf_batch_backward_saved")
         return grad_ins, gs
 
+    def get_info(self) -> dict:
+        """bf_batch_get_info: how the batch runs (persistent / streamed images, LDS,
+        workspace, graph launches of the forward)."""
+        i = L.bf_batch_info()
+        L.check(self._lib.bf_batch_get_info(self._h, C.byref(i)), "bf_batch_get_info")
+        return {k: getattr(i, k) for k, _ in L.bf_batch_info._fields_}
+
     def tune(self, inputs, outputs, stream=None) -> int:
         ip, ipt, op, opt = self._arrays(inputs, outputs)
         ch = C.c_int32(-1)

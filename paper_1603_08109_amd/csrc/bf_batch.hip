@@ -180,10 +180,9 @@ using namespace bfgpa;
 struct BatchShape {
   int variant;                 // kBatchVariants index
   int wg_per_cu;               // persistent grid = CUs * wg_per_cu
-  std::vector<int> TY;         // per-image tile rows
-  std::vector<BatchTile> tiles;
-  std::vector<BatchTile> ftiles;  // the plain forward's tiles: those of images not on their own plan
-  size_t lds;                  // dynamic LDS bytes
+  std::vector<int> TY;         // per-image tile rows (0: the image runs a streamed plan of its own)
+  std::vector<BatchTile> tiles;  // the persistent launch's tiles, cost-ordered
+  size_t lds;                  // dynamic LDS bytes (the largest need of the persistent images)
 };
 
 struct bf_batch {
@@ -199,10 +198,11 @@ struct bf_batch {
   int chosen = 0;
   float* d_const = nullptr;
   TileParams* d_params = nullptr;
-  BatchTile* d_tiles = nullptr;       // tiles of the chosen shape
-  int ntiles = 0;
-  BatchTile* d_ftiles = nullptr;      // its plain-forward subset
+  BatchTile* d_ftiles = nullptr;      // the chosen shape's tiles (images not on a plan of their own)
   int nftiles = 0;
+  int64_t graph_launches = 0;         // hipGraphLaunch calls made by bf_batch_forward
+  int64_t direct_launches = 0;        // launch sequences bf_batch_forward issued outside its graph
+  int64_t own_bytes = 0;              // device bytes of the batch's own buffers
   std::vector<bf_plan_t*> fplans;     // images whose plain forward runs the streamed passes of a plan of their own
   static constexpr int kAux = 4;      // side streams for those images, concurrent with the persistent launch
   std::vector<int> aux_imgs[kAux];    // images per side stream (longest first, least-loaded stream)
@@ -249,6 +249,10 @@ static double tile_cost(const bf_params& p, const bf_plan_info& inf, int TY) {
   return (inf.N + 1.0) * per_n;
 }
 
+// A launch shape of the persistent kernel over the images that run no
+// streamed plan of their own: every such image must fit the variant's
+// register and LDS budget; the images on their own plans are left out of the
+// fit test and of the LDS size.
 static bool build_shape(bf_batch* b, int v, int wg_per_cu, BatchShape* out) {
   const Variant vv = kBatchVariants[v];
   out->variant = v;
@@ -258,7 +262,7 @@ static bool build_shape(bf_batch* b, int v, int wg_per_cu, BatchShape* out) {
   int64_t lds = 0;
   std::vector<std::pair<double, BatchTile>> list;
   for (int i = 0; i < b->count; ++i) {
-    if (b->status[i] < 0) continue;
+    if (b->status[i] < 0 || b->fplans[i]) continue;
     const bf_params& p = b->prm[i];
     const int TY = 4 * vv.opt;
     if (region_floats(TY, p.W) > (int64_t)kThreads * vv.mreg) return false;
@@ -273,10 +277,7 @@ static bool build_shape(bf_batch* b, int v, int wg_per_cu, BatchShape* out) {
                    [](const std::pair<double, BatchTile>& a, const std::pair<double, BatchTile>& b2) {
                      return a.first > b2.first;
                    });
-  for (auto& e : list) {
-    out->tiles.push_back(e.second);
-    if (b->fplans.empty() || !b->fplans[e.second.image]) out->ftiles.push_back(e.second);
-  }
+  for (auto& e : list) out->tiles.push_back(e.second);
   out->lds = (size_t)lds;
   return true;
 }
@@ -325,17 +326,14 @@ static void destroy_graphs(bf_batch* b) {
 
 static int select_shape(bf_batch* b, int c) {
   const BatchShape& sh = b->cands[c];
-  if (b->d_tiles) hipFree(b->d_tiles);
   if (b->d_ftiles) hipFree(b->d_ftiles);
-  b->d_tiles = b->d_ftiles = nullptr;
-  b->ntiles = (int)sh.tiles.size();
-  b->nftiles = (int)sh.ftiles.size();
-  for (int f = 0; f < 2; ++f) {
-    const std::vector<BatchTile>& t = f ? sh.ftiles : sh.tiles;
-    BatchTile** d = f ? &b->d_ftiles : &b->d_tiles;
-    if (t.empty()) continue;
-    if (hipMalloc(d, t.size() * sizeof(BatchTile)) != hipSuccess) return fail(BF_ENOMEM, "hipMalloc batch tiles failed");
-    if (hipMemcpy(*d, t.data(), t.size() * sizeof(BatchTile), hipMemcpyHostToDevice) != hipSuccess)
+  b->d_ftiles = nullptr;
+  b->nftiles = (int)sh.tiles.size();
+  if (!sh.tiles.empty()) {
+    if (hipMalloc(&b->d_ftiles, sh.tiles.size() * sizeof(BatchTile)) != hipSuccess)
+      return fail(BF_ENOMEM, "hipMalloc batch tiles failed");
+    if (hipMemcpy(b->d_ftiles, sh.tiles.data(), sh.tiles.size() * sizeof(BatchTile), hipMemcpyHostToDevice) !=
+        hipSuccess)
       return fail(BF_EHIP, "hipMemcpy batch tiles failed");
   }
   for (int i = 0; i < b->count; ++i) {
@@ -377,6 +375,7 @@ static int run_direct(bf_batch* b, int k, hipStream_t s, int grid, bool save = f
   if (hipMemcpyAsync(b->d_params, b->h_stage[k], b->count * sizeof(TileParams), hipMemcpyHostToDevice,
                      s) != hipSuccess)
     return fail(BF_EHIP, "hipMemcpyAsync batch params");
+  if (b->nftiles == 0) return BF_OK;
   hipLaunchKernelGGL(batch_reset_kernel, dim3(1), dim3(64), 0, s, b->d_counter);
   hipError_t e = launch_batch_v(sh.variant, b->d_params, b->d_ftiles, b->nftiles, b->d_counter, grid, sh.lds,
                                 b->acc64, save, s);
@@ -479,7 +478,10 @@ static int plan_batch_adjoint(bf_batch* b) {
   for (auto& e : list) tiles.push_back(e.second);
   b->nbtiles = (int)tiles.size();
   b->blds = (size_t)lds;
-  auto dev_alloc = [&](void** ptr, size_t bytes) { return hipMalloc(ptr, std::max<size_t>(bytes, 16)) == hipSuccess; };
+  auto dev_alloc = [&](void** ptr, size_t bytes) {
+    b->own_bytes += (int64_t)std::max<size_t>(bytes, 16);
+    return hipMalloc(ptr, std::max<size_t>(bytes, 16)) == hipSuccess;
+  };
   if (!dev_alloc((void**)&b->d_btiles, tiles.size() * sizeof(BatchTile)) ||
       !dev_alloc((void**)&b->d_bpartials, 2 * (size_t)slots * sizeof(double)) ||
       !dev_alloc((void**)&b->d_bred, count * sizeof(BatchRed)) ||
@@ -502,10 +504,43 @@ static int plan_batch_adjoint(bf_batch* b) {
   return BF_OK;
 }
 
-static int grid_of(const bf_batch* b, bool save = true) {
+static int grid_of(const bf_batch* b) {
   const BatchShape& sh = b->cands[b->chosen];
   int g = b->num_cu * sh.wg_per_cu;
-  return std::max(1, std::min(g, std::max(1, save ? b->ntiles : b->nftiles)));
+  return std::max(1, std::min(g, std::max(1, b->nftiles)));
+}
+
+// The whole plain forward on `s`: the copy of this call's parameters from
+// staging slot k, the fork of the side streams, the persistent launch, each
+// routed image's streamed plan on its side stream (reading its image
+// pointers from the copied parameters), and the join.  Recorded once into
+// the slot's graph, so that one hipGraphLaunch replays all of it.
+static int record_forward(bf_batch* b, int k, hipStream_t s) {
+  const bool side = b->fork_ev != nullptr;
+  if (side) {
+    // the copy comes first, so the side streams fork after it
+    if (hipMemcpyAsync(b->d_params, b->h_stage[k], b->count * sizeof(TileParams), hipMemcpyHostToDevice, s) !=
+        hipSuccess)
+      return fail(BF_EHIP, "hipMemcpyAsync batch params");
+    fork_side(b, s);
+    int st = BF_OK;
+    for (int j = 0; j < bf_batch::kAux; ++j)
+      for (int i : b->aux_imgs[j]) {
+        if (st < 0) break;
+        const hipError_t e = plan_forward_streamed_dyn(b->fplans[i], b->d_params + i, false, b->aux[j]);
+        if (e != hipSuccess) st = fail(BF_EHIP, std::string("batch streamed image: ") + hipGetErrorString(e));
+      }
+    if (st >= 0 && b->nftiles > 0) {
+      hipLaunchKernelGGL(batch_reset_kernel, dim3(1), dim3(64), 0, s, b->d_counter);
+      const BatchShape& sh = b->cands[b->chosen];
+      const hipError_t e = launch_batch_v(sh.variant, b->d_params, b->d_ftiles, b->nftiles, b->d_counter,
+                                          grid_of(b), sh.lds, b->acc64, false, s);
+      if (e != hipSuccess) st = fail(BF_EHIP, std::string("batch launch: ") + hipGetErrorString(e));
+    }
+    join_side(b, s);  // joined even after an error, so the capture ends with every stream rejoined
+    return st;
+  }
+  return run_direct(b, k, s, grid_of(b));
 }
 
 }  // namespace bfgpa
@@ -574,6 +609,7 @@ int bf_batch_plan(int32_t count, const bf_params* per_image, bf_batch_t** out) {
     t.saved_plane = (int64_t)pi.height * pi.width;
     t.mirror = (pi.flags & BF_FLAG_MIRROR) ? 1 : 0;
   }
+  b->own_bytes += std::max<int64_t>(total, 1) * (int64_t)sizeof(float) + count * (int64_t)sizeof(TileParams) + 8;
   if (hipMalloc(&b->d_const, std::max<int64_t>(total, 1) * sizeof(float)) != hipSuccess) {
     delete b;
     return fail(BF_ENOMEM, "hipMalloc batch tables failed");
@@ -660,6 +696,27 @@ int bf_batch_plan(int32_t count, const bf_params* per_image, bf_batch_t** out) {
   return warn;
 }
 
+int bf_batch_get_info(const bf_batch_t* b, bf_batch_info* out) {
+  if (!b || !out) return fail(BF_EINVAL, "NULL argument");
+  std::memset(out, 0, sizeof(*out));
+  for (int i = 0; i < b->count; ++i) {
+    if (b->status[i] < 0) continue;
+    if (b->fplans[i])
+      out->images_streamed++;
+    else
+      out->images_persistent++;
+  }
+  out->persistent_lds_bytes = (int64_t)b->cands[b->chosen].lds;
+  out->workspace_bytes = b->own_bytes + (int64_t)b->nftiles * (int64_t)sizeof(BatchTile);
+  for (const bf_plan_t* pl : b->fplans)
+    if (pl) out->workspace_bytes += pl->info.workspace_bytes;
+  for (const bf_plan_t* pl : b->mplans)
+    if (pl) out->workspace_bytes += pl->info.workspace_bytes;
+  out->forward_graph_launches = b->graph_launches;
+  out->forward_direct_launches = b->direct_launches;
+  return BF_OK;
+}
+
 int bf_batch_status(const bf_batch_t* b, int32_t* per_image_status, int32_t* per_image_N) {
   if (!b) return fail(BF_EINVAL, "NULL batch");
   for (int i = 0; i < b->count; ++i) {
@@ -678,48 +735,34 @@ int bf_batch_forward(bf_batch_t* b, const float* const* in, const int64_t* in_pi
   int st = stage(b, k, in, in_pitch, out, out_pitch);
   if (st < 0) return st;
   if (!b->gexec[k]) {
-    // capture: params copy from this slot, counter reset, persistent kernel
+    // capture the whole forward (parameter copy, side-stream fork, persistent
+    // launch, the routed images' streamed plans, join) from this slot
     hipStream_t cap;
     if (hipStreamCreateWithFlags(&cap, hipStreamNonBlocking) != hipSuccess)
       return fail(BF_EHIP, "hipStreamCreate");
     hipGraph_t graph = nullptr;
-    hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+    hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeRelaxed);
+    int rs = BF_OK;
     if (e == hipSuccess) {
-      int rs = run_direct(b, k, cap, grid_of(b, false));
-      e = hipStreamEndCapture(cap, &graph);
-      if (rs < 0) {
-        if (graph) hipGraphDestroy(graph);
-        hipStreamDestroy(cap);
-        return rs;
-      }
+      rs = record_forward(b, k, cap);
+      const hipError_t e2 = hipStreamEndCapture(cap, &graph);
+      if (e == hipSuccess) e = e2;
     }
-    if (e == hipSuccess) e = hipGraphInstantiate(&b->gexec[k], graph, nullptr, nullptr, 0);
+    if (rs >= 0 && e == hipSuccess) e = hipGraphInstantiate(&b->gexec[k], graph, nullptr, nullptr, 0);
     if (graph) hipGraphDestroy(graph);
     hipStreamDestroy(cap);
-    if (e != hipSuccess) return fail(BF_EHIP, std::string("batch graph capture: ") + hipGetErrorString(e));
-  }
-  // images on the streamed passes: their own plan's launches on the side streams, forked from
-  // `s` before the persistent launch and joined back into it
-  const bool side = b->fork_ev != nullptr;
-  if (side) {
-    hipEventRecord(b->fork_ev, s);
-    for (int j = 0; j < bf_batch::kAux; ++j) hipStreamWaitEvent(b->aux[j], b->fork_ev, 0);
+    if (rs < 0) return rs;
+    if (e != hipSuccess) {
+      b->gexec[k] = nullptr;
+      return fail(BF_EHIP, std::string("batch graph capture: ") + hipGetErrorString(e));
+    }
   }
   hipError_t e = hipGraphLaunch(b->gexec[k], s);
   if (e != hipSuccess) return fail(BF_EHIP, std::string("hipGraphLaunch: ") + hipGetErrorString(e));
-  int fst = BF_OK;
-  if (side) {
-    for (int j = 0; j < bf_batch::kAux; ++j) {
-      for (int i : b->aux_imgs[j]) {
-        if (fst >= 0) fst = bf_forward(b->fplans[i], in[i], in_pitch[i], out[i], out_pitch[i], nullptr, b->aux[j]);
-      }
-      hipEventRecord(b->join_ev[j], b->aux[j]);  // joined even after an error, so `s` never waits on a stale fork
-      hipStreamWaitEvent(s, b->join_ev[j], 0);
-    }
-  }
+  b->graph_launches++;
   hipEventRecord(b->ev[k], s);
   b->ev_used[k] = true;
-  return fst < 0 ? fst : BF_OK;
+  return BF_OK;
 }
 
 int bf_batch_tune(bf_batch_t* b, const float* const* in, const int64_t* in_pitch, float* const* out,
@@ -739,9 +782,9 @@ int bf_batch_tune(bf_batch_t* b, const float* const* in, const int64_t* in_pitch
     st = stage(b, k, in, in_pitch, out, out_pitch);
     if (st < 0) return st;
     // one warm-up, then three timed launches (direct, not graphed)
-    run_direct(b, k, s, grid_of(b, false));
+    run_direct(b, k, s, grid_of(b));
     hipEventRecord(e0, s);
-    for (int rep = 0; rep < 3; ++rep) run_direct(b, k, s, grid_of(b, false));
+    for (int rep = 0; rep < 3; ++rep) run_direct(b, k, s, grid_of(b));
     hipEventRecord(e1, s);
     hipEventRecord(b->ev[k], s);
     b->ev_used[k] = true;
@@ -780,7 +823,7 @@ int bf_batch_forward_saved(bf_batch_t* b, const float* const* in, const int64_t*
   // unless their adjoint is the mirror plan's, which recomputes)
   const bool side = b->fork_ev != nullptr;
   if (side) fork_side(b, s);
-  st = run_direct(b, k, s, grid_of(b, false), true);
+  st = run_direct(b, k, s, grid_of(b), true);
   if (st < 0) return st;
   int fst = BF_OK;
   if (side) {
@@ -841,8 +884,8 @@ static int batch_backward(bf_batch_t* b, const float* const* in, const int64_t* 
   if (side) fork_side(b, s);
   hipLaunchKernelGGL(batch_reset_kernel, dim3(1), dim3(64), 0, s, b->d_counter);
   hipError_t e = hipSuccess;
-  if (!saved) {
-    e = launch_batch_v(sh.variant, b->d_bparams, b->d_ftiles, b->nftiles, b->d_counter, grid_of(b, false), sh.lds,
+  if (!saved && b->nftiles > 0) {
+    e = launch_batch_v(sh.variant, b->d_bparams, b->d_ftiles, b->nftiles, b->d_counter, grid_of(b), sh.lds,
                        b->acc64, true, s);
     if (e != hipSuccess) return fail(BF_EHIP, std::string("batch forward-state launch: ") + hipGetErrorString(e));
   }
@@ -925,7 +968,6 @@ int bf_batch_destroy(bf_batch_t* b) {
   }
   if (b->d_const) hipFree(b->d_const);
   if (b->d_params) hipFree(b->d_params);
-  if (b->d_tiles) hipFree(b->d_tiles);
   if (b->d_counter) hipFree(b->d_counter);
   if (b->d_ftiles) hipFree(b->d_ftiles);
   for (int j = 0; j < bf_batch::kAux; ++j) {

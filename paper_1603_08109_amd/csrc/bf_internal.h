@@ -61,6 +61,12 @@ struct TileParams {
   int wide;             // wide range (T / sigma_r above 13): float64 per-pixel states, out = sigma_r P / Q + c
   const double* isq;    // 1 / sqrt(n), n = 0 .. N+1 (isq_0 = 0)
   const double* sq;     // sqrt(n), n = 0 .. N+1
+  // Streamed forward launched from a captured graph: when set, the lift and
+  // the final pass read in / in_pitch / out / out_pitch (and, with dyn_save,
+  // saved) from this device copy of the call's parameters instead of the
+  // by-value fields above, so one capture serves every call.
+  const TileParams* dyn;
+  int dyn_save;
 };
 
 // lambda = (T / sigma_r)^2 limits: exp(-x^2/2) stays a normal float32 for
@@ -196,6 +202,9 @@ bool ls_mirror_supported(int kernel, int W);
 int64_t ls_state_bytes(int H, int Wd, int W, bool save, bool wide = false);
 LsState ls_layout(void* base, int H, int Wd, int W, bool save, bool wide = false);
 hipError_t launch_forward_ls(const TileParams& p, const LsState& st, bool save, hipStream_t s);
+// plan-level helpers of the batch (bf_plan.cpp): the streamed forward of a
+// single-image plan with the image pointers read from `dyn` (device memory)
+hipError_t plan_forward_streamed_dyn(const bf_plan_t* pl, const TileParams* dyn, bool save, hipStream_t s);
 // streamed adjoint (bf_large_bwd.hip)
 bool bls_supported(int W, bool sigs);
 int64_t bls_state_bytes(int H, int Wd, int W, bool sigs);

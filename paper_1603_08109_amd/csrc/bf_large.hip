@@ -41,10 +41,12 @@ static int num_cus() {
 
 __global__ __launch_bounds__(kThreads) void ls_init_kernel(TileParams p, LsState st) {
   const int64_t npx = (int64_t)p.H * p.Wd;
+  const float* in = p.dyn ? p.dyn->in : p.in;
+  const int64_t in_pitch = p.dyn ? p.dyn->in_pitch : p.in_pitch;
   for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < npx;
        i += (int64_t)gridDim.x * kThreads) {
     const int r = (int)(i / p.Wd), c = (int)(i - (int64_t)r * p.Wd);
-    const float f = p.in[(int64_t)r * p.in_pitch + c];
+    const float f = in[(int64_t)r * in_pitch + c];
     const float x = (f - p.center) / p.sigma_r;
     const float E = expf(-0.5f * x * x);
     const int64_t j = (int64_t)r * st.pitch + c;
@@ -764,16 +766,19 @@ bool ls_mirror_supported(int kernel, int W) {
 __global__ __launch_bounds__(kThreads) void ls_final_kernel(TileParams p, LsState st) {
   const int64_t npx = (int64_t)p.H * p.Wd;
   const double X = p.wide ? 1.0 : (double)p.X;  // the wide-range sums carry no 1/X
+  float* out = p.dyn ? p.dyn->out : p.out;
+  const int64_t out_pitch = p.dyn ? p.dyn->out_pitch : p.out_pitch;
+  float* saved = p.dyn ? (p.dyn_save ? p.dyn->saved : nullptr) : p.saved;
   for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < npx;
        i += (int64_t)gridDim.x * kThreads) {
     const int r = (int)(i / p.Wd), c = (int)(i - (int64_t)r * p.Wd);
     const double q = st.Q[i];
     const double ratio = X * st.P[i] / q;
-    if (p.out) p.out[(int64_t)r * p.out_pitch + c] = (float)((double)p.sigma_r * ratio + (double)p.center);
-    if (p.saved && st.DP) {
-      p.saved[i] = (float)q;
-      p.saved[p.saved_plane + i] = (float)ratio;
-      p.saved[2 * p.saved_plane + i] = (float)(X * X * st.DP[i] - ratio * X * st.DQ[i]);
+    if (out) out[(int64_t)r * out_pitch + c] = (float)((double)p.sigma_r * ratio + (double)p.center);
+    if (saved && st.DP) {
+      saved[i] = (float)q;
+      saved[p.saved_plane + i] = (float)ratio;
+      saved[2 * p.saved_plane + i] = (float)(X * X * st.DP[i] - ratio * X * st.DQ[i]);
     }
   }
 }

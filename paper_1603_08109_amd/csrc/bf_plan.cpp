@@ -83,24 +83,38 @@ double poisson_tail(int N, double lam) {
   return std::max(0.0, 1.0 - head);
 }
 
+// p = 1 + log lambda and q = -lambda - log eps of Prop. (LambW).
+struct ChernoffPQ {
+  double p, q;
+};
+static ChernoffPQ chernoff_pq(double lam, double eps) { return {1.0 + std::log(lam), -lam - std::log(eps)}; }
+
+// theta = q / W0(q e^{-p}), the root above lambda of nu(x) = x log x - p x - q
+// (Prop. LambW); the order is its ceiling.
 static int chernoff_order(double lam, double eps) {
-  double p = 1.0 + std::log(lam);
-  double q = -lam - std::log(eps);
-  double w = lambert_w0(q * std::exp(-p));
-  double theta = q / w;
-  return (int)std::ceil(theta - 1e-12);
+  const ChernoffPQ c = chernoff_pq(lam, eps);
+  return (int)std::ceil(c.q / lambert_w0(c.q * std::exp(-c.p)) - 1e-12);
 }
 
+// The four-term Lambert-W series of eq. (series), W0(t) ~ t - t^2 + 3t^3/2 - 8t^4/3.
+static double lambert_w0_series(double t) { return t * (1.0 - t * (1.0 - t * (1.5 - t * (8.0 / 3.0)))); }
+
+// One Newton step on nu(x) = x log x - p x - q, eq. (Newton_method).
+static double nu_newton_step(double x, const ChernoffPQ& c) {
+  return x - (x * std::log(x) - c.p * x - c.q) / (std::log(x) + 1.0 - c.p);
+}
+
+// The order rule of Algorithm 1: the root of Prop. (LambW) with W0 taken from
+// the series (note q e^{-p} = q / (e lambda)), refined by three Newton steps
+// when sigma_r < 30, and the fixed order 10 for sigma_r >= 70 (which carries
+// no guarantee).  Returns -1 when the series gives no finite root.
 static int alg1_order(double sigma_r, double eps, double T) {
   if (sigma_r >= 70.0) return 10;
-  double lam = (T / sigma_r) * (T / sigma_r);
-  double p = 1.0 + std::log(lam);
-  double q = -lam - std::log(eps);
-  double t = q / (M_E * lam);
-  double w = t - t * t + 1.5 * t * t * t - (8.0 / 3.0) * t * t * t * t;
-  double x = q / w;
-  if (sigma_r < 30.0)
-    for (int k = 0; k < 3; ++k) x = x - (x * std::log(x) - p * x - q) / (std::log(x) + 1.0 - p);
+  const double lam = (T / sigma_r) * (T / sigma_r);
+  const ChernoffPQ c = chernoff_pq(lam, eps);
+  double x = c.q / lambert_w0_series(c.q / (M_E * lam));
+  const int newton_steps = sigma_r < 30.0 ? 3 : 0;
+  for (int k = 0; k < newton_steps; ++k) x = nu_newton_step(x, c);
   if (!std::isfinite(x)) return -1;
   return (int)std::ceil(x - 1e-12);
 }
@@ -184,6 +198,14 @@ static int plan_order(const bf_params* p, bf_plan_info* info, int dims = 2) {
   info->guaranteed_delta = (info->kernel_bound < info->w0)
       ? 2.0 * p->T * info->kernel_bound / (info->w0 - info->kernel_bound)
       : std::numeric_limits<double>::infinity();
+  if (p->kernel == BF_GAUSS_REC) {
+    // Prop. (accuracy) assumes w >= 0; the recursive fit has small negative
+    // lobes, so N is chosen by the same rule but no +-delta bound is claimed
+    info->guaranteed_delta = std::numeric_limits<double>::infinity();
+    status = BF_WNOGUARANTEE;
+    set_error("recursive Gaussian: the kernel has negative lobes, Prop. (accuracy) gives no +-delta bound");
+    return status;
+  }
   if (status == BF_WNOGUARANTEE) set_error("order below the bound: no +-delta guarantee");
   return status;
 }
@@ -756,6 +778,22 @@ static void fill_common(const bf_plan_t* pl, TileParams& tp) {
   tp.mirror = (p.flags & BF_FLAG_MIRROR) ? 1 : 0;
   tp.mfma_x3 = (p.flags & BF_FLAG_MFMA_FP32) ? 0 : 1;
   tp.wide = pl->wide ? 1 : 0;
+}
+
+// The streamed forward of a plan, reading the image pointers (and, with
+// save, the saved-state pointer) from the device copy `dyn` of the call's
+// parameters when the kernels run: the batch captures these launches once
+// into its graph and replays them for every call.
+hipError_t plan_forward_streamed_dyn(const bf_plan_t* pl, const TileParams* dyn, bool save, hipStream_t s) {
+  if (!pl || !dyn || !pl->ls || pl->wide || (save && !pl->ls_state.DP)) return hipErrorInvalidValue;
+  TileParams tp;
+  std::memset(&tp, 0, sizeof(tp));
+  fill_common(pl, tp);
+  tp.dyn = dyn;
+  tp.dyn_save = save ? 1 : 0;
+  tp.TY = pl->TY;
+  tp.tiles_x = (pl->p.width + kTileCols - 1) / kTileCols;
+  return launch_forward_ls(tp, pl->ls_state, save, s);
 }
 }  // namespace bfgpa
 

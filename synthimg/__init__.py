@@ -104,3 +104,25 @@ def sample_pixels(H: int, W: int, count: int, border: int, border_count: int,
     mask[0, 0] = mask[0, -1] = mask[-1, 0] = mask[-1, -1] = True
     rr, cc = np.nonzero(mask)
     return np.stack([rr, cc], axis=1).astype(np.int64)
+
+
+def grad_patches(H: int, W: int, size: int, which=("centre", "edge", "corner")) -> list:
+    """Top-left (row, col) of square `size` x `size` patches of an H x W image:
+    'centre' (middle of the image), 'edge' (on the top edge, a quarter of the
+    way across) and 'corner' (the bottom-right corner)."""
+    pos = {"centre": ((H - size) // 2, (W - size) // 2),
+           "edge": (0, max(0, W // 4 - size // 2)),
+           "corner": (H - size, W - size)}
+    return [pos[k] for k in which]
+
+
+def patch_gbar(H: int, W: int, patches, size: int, seed: int) -> np.ndarray:
+    """Output gradient that is zero except on the listed size x size patches,
+    where it takes seeded values in [-0.5, 0.5] (gen2 levels / 255 - 0.5).
+    With such a gradient, dL/d(input) and the parameter gradients of a filter
+    with support W depend only on the patches grown by W, so a reference can
+    be computed on crops of that size."""
+    g = np.zeros((H, W))
+    for k, (r, c) in enumerate(patches):
+        g[r:r + size, c:c + size] = gen2(size, size, seed + k) / 255.0 - 0.5
+    return g

@@ -5,6 +5,8 @@ import math
 import os
 import re
 
+import numpy as np
+
 import pytest
 
 from oracle import kernels as K
@@ -194,3 +196,19 @@ def test_volume_planning_weight():
     assert V.w0(w1) == pytest.approx((w1[len(w1) // 2] / w1.sum()) ** 3, rel=1e-12)
     assert O.order_for_delta(1e-3, V.w0(w1), 127.5, 30.0) >= O.order_for_delta(1e-3, K.w0("gauss", sigma_s=2.0),
                                                                                   127.5, 30.0)
+
+
+def test_recursive_gaussian_claims_no_guarantee():
+    # Prop. (accuracy) assumes w >= 0; Deriche's fit has small negative lobes, so a
+    # recursive-Gaussian plan reports the warning and an infinite guaranteed delta
+    # (N still follows Cor. eps with the fit's normalised centre weight)
+    import paper_1603_08109_amd as P
+    from paper_1603_08109_amd import _lib as L
+    from oracle import recursive as R
+    for ss, sr in [(3.0, 30.0), (25.0, 10.0)]:
+        info = P.bf_order("gauss_rec", sr, sigma_s=ss, height=256, width=256)
+        assert info.status == L.BF_WNOGUARANTEE
+        assert math.isinf(info.guaranteed_delta)
+        assert R.kernel(np.arange(0, 8 * int(ss) + 8), ss).min() < 0.0  # the lobes that void the bound
+        assert info.w0 == pytest.approx(R.w0(ss), rel=1e-9)
+        assert info.N == O.chernoff_order(O.lam_of(127.5, sr), O.eps_from_delta(1e-3, R.w0(ss), 127.5))

@@ -279,3 +279,52 @@ def test_side_streams_on_a_caller_stream():
             got = outs[i].cpu().numpy().astype(np.float64)
             assert np.abs(got - ref).max() <= TOL, (rep, i)
             assert abs(sums[i].item() - got.sum()) <= 1e-6 * abs(got.sum()), (rep, i)
+
+
+def test_forward_is_one_graph_launch():
+    # wide supports (Gaussian sigma_s = 25, box W = 75 on 2^20 pixels) next to narrow ones: the wide
+    # images run their own streamed plans, and the whole forward (parameter copy, persistent tiles,
+    # side-stream launches) replays as ONE graph launch per call with no other launch; the persistent
+    # launch is planned for the narrow images only (its LDS is that of W = 9, not W = 75)
+    torch, P = _mods()
+    specs = [dict(kernel="gauss", sigma_s=25.0, sigma_r=30.0, height=300, width=280),
+             dict(kernel="box", W=75, sigma_r=30.0, height=1024, width=1024),
+             dict(kernel="gauss", sigma_s=2.0, sigma_r=25.0, height=90, width=130),
+             dict(kernel="box", W=4, sigma_r=40.0, height=70, width=64),
+             dict(kernel="gauss", sigma_s=3.0, sigma_r=30.0, height=64, width=200)]
+    batch = P.Batch(specs)
+    assert all(s >= 0 for s in batch.image_status)
+    info = batch.get_info()
+    assert info["images_streamed"] == 2 and info["images_persistent"] == 3
+    # largest fused-tile LDS of a W <= 9 image (32-row tiles): region (32 + 18) x 83 floats plus
+    # the row-pass buffer (32 + 18) x 65 floats
+    assert 0 < info["persistent_lds_bytes"] <= 4 * (50 * 83 + 4 + 50 * 65)
+    plans = []
+    for s in specs:
+        d = dict(s)
+        plans.append(P.Plan(d.pop("kernel"), d.pop("sigma_r"), **d))
+    stream = torch.cuda.Stream()
+    for rep in range(3):
+        imgs = [torch.tensor(synthimg.gen2(s["height"], s["width"], 900 + 10 * rep + i), dtype=torch.float32,
+                             device="cuda") for i, s in enumerate(specs)]
+        torch.cuda.synchronize()
+        before = batch.get_info()
+        with torch.cuda.stream(stream):
+            outs = batch.forward(imgs, stream=stream)
+        after = batch.get_info()
+        assert after["forward_graph_launches"] == before["forward_graph_launches"] + 1
+        assert after["forward_direct_launches"] == 0
+        torch.cuda.synchronize()
+        for i, s in enumerate(specs):
+            ref = plans[i].forward(imgs[i])
+            torch.cuda.synchronize()
+            assert (outs[i] - ref).abs().max().item() <= 1e-4, (rep, i)
+        if rep == 0:
+            for i, s in enumerate(specs):
+                f32 = imgs[i].cpu().numpy().astype(np.float64)
+                got = outs[i].cpu().numpy().astype(np.float64)
+                W = s["W"] if s["kernel"] == "box" else K.support("gauss", sigma_s=s["sigma_s"])
+                px = synthimg.sample_pixels(s["height"], s["width"], 40, W, 20, 910 + i)
+                w2 = K.taps2d(s["kernel"], s.get("sigma_s"), W if s["kernel"] == "box" else None)
+                ref = G.gpa_pairwise_at(f32, px, w2, s["sigma_r"], batch.N[i], 127.5)
+                assert np.abs(got[px[:, 0], px[:, 1]] - ref).max() <= TOL, i
