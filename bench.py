@@ -7,15 +7,22 @@ Workload (the large-support configuration): one 4096x4096 float32 image
     Gaussian sigma_s in {3, 10, 25}  x  sigma_r in {10, 30, 50}
     box W in {10, 30, 75}            x  sigma_r in {10, 30, 50}
 with N from the accuracy bound for delta = 1e-3.  One step = one forward
-pass per setting; `value` = total pixels filtered / total kernel time
-(Mpix/s), inputs resident in HBM.  Also reported: per-setting results, the
-differentiable fwd+bwd workload (32 x 512^2, Gaussian sigma_s = 5,
-sigma_r = 30, N = 49) and the batched workload (256 uneven images, one
-persistent launch) against per-image launches.
+pass per setting; `value` = total pixels filtered / total time (Mpix/s),
+inputs resident in HBM, times from HIP events on the launching stream.
 
-The cpu_baseline leg times the FP64 numpy oracle (Algorithm 2) on a
-256x256 crop of the same image for every setting, on this host, and
-reports the GPU's max error against it on that crop.
+Also reported: per setting the binding roofline and (from the CPU-baseline
+leg) the max and RMS error of the TIMED 4096^2 output against the float64
+oracle; fwd+bwd on the 4096^2 image (fused and streamed adjoints) and on the
+differentiable workload (32 x 512^2); the batched workload (256 uneven
+images, one graph launch) against per-image launches; the cross filter, the
+recursive Gaussian, the wide range and volumes.
+
+The cpu_baseline leg runs before anything touches the GPU: the float64
+numpy oracle (the N + 1 filtering form of eq. GPA) on the 256x256 top-left
+crop of the sweep image for every setting, on one core and on all the
+host's cores (one process per setting).  After the GPU legs it checks the
+timed outputs against the oracle (oracle evaluations only happen in this
+leg).
 """
 from __future__ import annotations
 
@@ -43,9 +50,16 @@ MFMA_F32_PEAK_TFLOPS = 157.3
 MFMA_BF16_PEAK_TFLOPS = 2500.0
 SPLIT_PRODUCTS = 6
 SPLIT_MIN_W = 40  # from this support both streamed passes use the split arithmetic
+LDS_BYTES = 160 * 1024
+NUM_CU = 256
 
 SWEEP = ([("gauss", dict(sigma_s=s), r) for s in (3.0, 10.0, 25.0) for r in (10.0, 30.0, 50.0)]
          + [("box", dict(W=w), r) for w in (10, 30, 75) for r in (10.0, 30.0, 50.0)])
+# fwd+bwd on the sweep image: the fused adjoint tile and the streamed adjoint
+FWD_BWD_4096 = [("gauss", dict(sigma_s=3.0), 30.0), ("gauss", dict(sigma_s=3.0), 10.0),
+                ("gauss", dict(sigma_s=25.0), 30.0), ("gauss", dict(sigma_s=25.0), 10.0),
+                ("box", dict(W=75), 30.0), ("box", dict(W=75), 10.0)]
+GRAD_PATCH = 32  # the fwd+bwd accuracy check: output gradient on one corner patch
 
 
 def setting_name(kind, kw, sr):
@@ -54,12 +68,22 @@ def setting_name(kind, kw, sr):
 
 
 def alg_flops_per_px_n(kind, W):
-    """Algorithmic flops of Algorithm 2 per pixel per filtering: F <- H F (1),
-    spatial filter (box: two O(1) running sums, 2 adds each = 4; Gaussian:
-    two separable passes of 2W+1 multiply-adds = 4(2W+1)), Q and P updates
-    (2 FMA = 4) and G <- H G / n (2)."""
+    """Algorithmic flops of the filtering form per pixel per filtering: F_n
+    from F_{n-1} (1), spatial filter (box: two O(1) running sums, 2 adds each
+    = 4; Gaussian: two separable passes of 2W+1 multiply-adds = 4(2W+1)), the
+    Q and P terms (2 FMA = 4) and the next weight u^n/n! (2)."""
     filt = 4.0 if kind == "box" else 4.0 * (2 * W + 1)
     return 1.0 + filt + 4.0 + 2.0
+
+
+def fwd_bwd_flops_per_px(kind, W, N):
+    """Algorithmic flops per pixel of one forward plus its adjoint with the
+    sigma gradients (the forward state saved): box ~ 37 N; Gaussian
+    ~ 25 N + 18 (2W + 1)(N + 1) (the adjoint filters the adjoint images with
+    the taps and, for d/d sigma_s, the d^2 taps)."""
+    if kind == "box":
+        return 37.0 * N
+    return 25.0 * N + 18.0 * (2 * W + 1) * (N + 1)
 
 
 def source_sha():
@@ -115,15 +139,65 @@ def time_launches(fn, stream, warmup, steps, torch):
     return e0.elapsed_time(e1) / steps  # ms per launch
 
 
+# --- engines and their seams ----------------------------------------------------
+
+def engine_of(kind, W, tile_rows):
+    """The forward engine a 4096^2 plan runs (as the planner picks it)."""
+    if tile_rows > 0:
+        return "fused_valu_tile"
+    if kind == "box":
+        return "box_strips_512" if W >= 56 else "box_strips_256"
+    return "rows_x3+cols_x3" if W >= SPLIT_MIN_W else "rows_x3+cols_mfma"
+
+
+def seams(kind, W, tile_rows, H, Wd):
+    """(row, column) of a seam of the engine's work decomposition: fused tiles
+    of 64 columns x tile_rows; box strips of 256 - 2W (512 - 2W) output
+    columns cut into row segments that fill one wave of resident workgroups;
+    streamed Gaussian passes on 16 x 256 row tiles and 64 x 64 column tiles."""
+    if tile_rows > 0:
+        return tile_rows, 64
+    if kind == "box":
+        oc, per = (512 - 2 * W, 16 * 548 * 8) if W >= 56 else (256 - 2 * W, 16 * 276 * 8)
+        nstrips = -(-Wd // oc)
+        nseg = max(1, min((H + 31) // 32, (NUM_CU * max(1, LDS_BYTES // per)) // nstrips))
+        return -(-H // nseg), oc
+    return 64, 256
+
+
+def setting_roof(kind, W, N, ms, tile_rows, H, Wd):
+    flops = H * Wd * (N + 1) * alg_flops_per_px_n(kind, W)
+    achieved = flops / (ms * 1e-3) / 1e12
+    eng = engine_of(kind, W, tile_rows)
+    extra = {}
+    if eng == "rows_x3+cols_x3":
+        # the FIR products run as split-BF16 matrix-core products: priced at the
+        # FP32-product ceiling of that arithmetic, with the FP32 matrix-core ratio beside
+        bound, peak = "mfma", MFMA_BF16_PEAK_TFLOPS / SPLIT_PRODUCTS
+        extra = {"peak_basis": f"BF16 dense {MFMA_BF16_PEAK_TFLOPS:g} TFLOP/s / {SPLIT_PRODUCTS} products "
+                               "per FP32 product",
+                 "frac_of_fp32_mfma_peak": round(achieved / MFMA_F32_PEAK_TFLOPS, 4)}
+    elif eng == "rows_x3+cols_mfma":
+        bound, peak = "mfma", MFMA_F32_PEAK_TFLOPS
+    else:
+        bound, peak = "alu", ALU_PEAK_TFLOPS
+    return flops, {"bound": bound, "achieved": round(achieved, 3), "peak": round(peak, 1), "unit": "TFLOP/s",
+                   "frac": round(achieved / peak, 4), **extra}
+
+
 # rocprofv3 runs whose summaries are committed under profiles/ (run from the
 # repository root; DIR is the output folder, then `bench.py --summarize DIR`).
+# The counter runs take one setting per forward engine (sweep indices 0, 3, 6,
+# 9, 12, 15: fused Gaussian tile, rows_x3 + cols_mfma, rows_x3 + cols_x3, fused
+# box tile, 256-column box strips, 512-column box strips, all at sigma_r = 10).
+TRAFFIC_SETTINGS = [0, 3, 6, 9, 12, 15]
 PROFILE_RUNS = {
     "trace": "rocprofv3 --kernel-trace --stats --output-format csv -d DIR/trace -o t -- "
              "python3 bench.py --steps 2 --warmup 1 --no-cpu-baseline --no-extra",
     "fetch": "rocprofv3 --pmc FETCH_SIZE --output-format csv -d DIR/fetch -o c -- "
-             "python3 bench.py --only 0,6 --steps 1 --warmup 0 --no-cpu-baseline --no-extra",
+             "python3 bench.py --only 0,3,6,9,12,15 --steps 1 --warmup 0 --no-cpu-baseline --no-extra",
     "write": "rocprofv3 --pmc WRITE_SIZE --output-format csv -d DIR/write -o c -- "
-             "python3 bench.py --only 0,6 --steps 1 --warmup 0 --no-cpu-baseline --no-extra",
+             "python3 bench.py --only 0,3,6,9,12,15 --steps 1 --warmup 0 --no-cpu-baseline --no-extra",
     "fetch_copy": "rocprofv3 --pmc FETCH_SIZE --output-format csv -d DIR/fetch_copy -o c -- "
                   "python3 bench.py --copy-probe 512",
     "write_copy": "rocprofv3 --pmc WRITE_SIZE --output-format csv -d DIR/write_copy -o c -- "
@@ -219,7 +293,7 @@ def summarize(dirpath, sweep_settings):
     wscale = probe / (copy_kib("write_copy") * 1024.0)
     fcalls, _ = counter_calls("fetch")
     wcalls, _ = counter_calls("write")
-    names = [sweep_settings[0], sweep_settings[6]]
+    names = [sweep_settings[i] for i in TRAFFIC_SETTINGS]
     settings = {}
     for s, fc, wc in zip(names, fcalls, wcalls):
         kern = collections.OrderedDict()
@@ -246,13 +320,132 @@ def summarize(dirpath, sweep_settings):
     print(f"wrote {out_md} and profiles/traffic.json")
 
 
+# --- CPU baseline leg (the only place the oracle runs) ------------------------------
+
+CROP = 256
+
+
+def _cpu_task(args):
+    """One setting of the oracle on the crop (a worker process, or in-process)."""
+    kind, kw, sr, N, fc = args
+    from oracle import gpa as G
+    from oracle import kernels as K
+    w1 = K.taps1d(kind, kw.get("sigma_s"), kw.get("W"))
+    t0 = time.perf_counter()
+    G.gpa_alg2(fc, w1, sr, N, 127.5)
+    return time.perf_counter() - t0
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def cpu_timing(sweep):
+    """The oracle's filtering form (float64 numpy) on the 256^2 top-left crop of
+    the sweep image, every setting once: on one core, then one process per
+    setting on all the host's cores (run before the GPU is touched)."""
+    import multiprocessing as mp
+    from oracle import kernels as K
+    from oracle import order as O
+    import synthimg
+    fc = np.asarray(synthimg.gen2(4096, 4096, 3000)[:CROP, :CROP], np.float32).astype(np.float64)
+    tasks = []
+    for _, (kind, kw, sr) in sweep:
+        W = K.support(kind, kw.get("sigma_s"), kw.get("W"))
+        N = O.order_for_delta(1e-3, K.w0(kind, kw.get("sigma_s"), W), 127.5, sr)
+        tasks.append((kind, kw, sr, N, fc))
+    t1 = sum(_cpu_task(t) for t in tasks)
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count() or 1
+    # at most 16 worker processes (the host share of one GPU), one per setting
+    cores = max(1, min(16, avail, len(tasks)))
+    order = sorted(tasks, key=lambda t: -t[3] * (1 if t[0] == "box" else (2 * K.support("gauss", t[1]["sigma_s"]) + 1)))
+    t0 = time.perf_counter()
+    with mp.get_context("fork").Pool(cores) as pool:
+        list(pool.imap_unordered(_cpu_task, order, chunksize=1))
+    tall = time.perf_counter() - t0
+    px = len(tasks) * CROP * CROP
+    return {"value": round(px / tall / 1e6, 4), "unit": "Mpix/s", "cores": cores, "kind": "oracle",
+            "sample": f"float64 numpy filtering form (oracle.gpa.gpa_alg2) on the {CROP}x{CROP} top-left crop "
+                      f"of the sweep image, each of the {len(tasks)} settings once, one process per setting "
+                      f"on {cores} cores ({tall:.1f} s wall)",
+            "single_core": {"value": round(px / t1 / 1e6, 4), "unit": "Mpix/s", "cores": 1,
+                            "seconds": round(t1, 2)},
+            "host_cpu_count": os.cpu_count(), "host_cpus_available": avail, "host_cpu_model": cpu_model()}
+
+
+def _err(d):
+    d = np.asarray(d, np.float64)
+    return {"max": float(np.abs(d).max()), "rms": float(np.sqrt(np.mean(d * d))), "n": int(d.size)}
+
+
+def accuracy_checks(checks, fb_checks, f64):
+    """Errors of the timed outputs against the float64 oracle: per sweep
+    setting, at a seeded pixel sample (eq. GPA pair by pair, O2, and eq. BF,
+    O1) and on a band across the engine's seams (the filtering form on the
+    crop grown by W, exact on the band, O3); per fwd+bwd setting, dL/df and the
+    sigma gradients for an output gradient on the corner patch (float64
+    autograd on the patch grown by W)."""
+    from oracle import bf as B
+    from oracle import gpa as G
+    from oracle import grad as GR
+    from oracle import kernels as K
+    import synthimg
+    H, Wd = f64.shape
+    out = {}
+    for c in checks:
+        kind, kw, sr, N, W = c["kind"], c["kw"], c["sigma_r"], c["N"], c["W"]
+        w1 = K.taps1d(kind, kw.get("sigma_s"), kw.get("W"))
+        w2 = K.taps2d(kind, kw.get("sigma_s"), kw.get("W"))
+        px = c["pixels"]
+        o2 = G.gpa_pairwise_at(f64, px, w2, sr, N, 127.5)
+        o1 = B.direct_bf_at(f64, px, w2, sr)
+        r0, r1, c0, c1 = c["band"]
+        R0, R1, C0, C1 = max(0, r0 - W), min(H, r1 + W), max(0, c0 - W), min(Wd, c1 + W)
+        o3 = G.gpa_alg2(f64[R0:R1, C0:C1], w1, sr, N, 127.5)[r0 - R0:r1 - R0, c0 - C0:c1 - C0]
+        out[c["setting"]] = {"vs_gpa_pairwise_sample": _err(c["sample_vals"] - o2),
+                             "vs_direct_bf_sample": _err(c["sample_vals"] - o1),
+                             "vs_filtering_form_band": _err(c["band_vals"] - o3),
+                             "band": [r0, r1, c0, c1]}
+        print(f"# accuracy {c['setting']}: {out[c['setting']]}", file=sys.stderr, flush=True)
+    fb = {}
+    for c in fb_checks:
+        kind, kw, sr, N, W = c["kind"], c["kw"], c["sigma_r"], c["N"], c["W"]
+        (pr, pc) = c["patch"]
+        R0, R1, C0, C1 = max(0, pr - W), min(H, pr + GRAD_PATCH + W), max(0, pc - W), min(Wd, pc + GRAD_PATCH + W)
+        gbar = synthimg.patch_gbar(H, Wd, [c["patch"]], GRAD_PATCH, c["seed"])[R0:R1, C0:C1]
+        gbar = np.asarray(gbar, np.float32).astype(np.float64)
+        df, dsr, dss = GR.vjp_autograd(f64[R0:R1, C0:C1], gbar, kind, kw.get("sigma_s"), W, sr, N, 127.5)
+        d = c["gin_crop"] - df
+        scale = float(np.abs(df).max())
+        e = {"dfdin_max_rel": float(np.abs(d).max()) / scale, "dfdin_rms_rel": float(np.sqrt(np.mean(d * d))) / scale,
+             "dfdin_zero_outside_crop": bool(c["zero_outside"]),
+             "dsigma_r_rel": abs(c["gs"][0] - dsr) / abs(dsr)}
+        if kind == "gauss":
+            e["dsigma_s_rel"] = abs(c["gs"][1] - dss) / abs(dss)
+        fb[c["setting"]] = e
+        print(f"# accuracy fwd+bwd {c['setting']}: {e}", file=sys.stderr, flush=True)
+    return out, fb
+
+
+# --- main -------------------------------------------------------------------------------
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-extra", action="store_true", help="skip the fwd+bwd and batch legs")
+    ap.add_argument("--no-extra", action="store_true", help="skip every leg but the sweep")
     ap.add_argument("--only", default="", help="comma list of sweep indices to run")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (counter calibration)")
@@ -265,6 +458,16 @@ def main():
     if a.gpus != 1:
         print(json.dumps({"error": "this benchmark measures one GPU (the sharding design is documented, not run); --gpus must be 1"}))
         sys.exit(2)
+
+    sweep = list(enumerate(SWEEP))
+    if a.only:
+        keep = {int(i) for i in a.only.split(",")}
+        sweep = [s for s in sweep if s[0] in keep]
+
+    cpu = None
+    if not a.no_cpu_baseline and not a.copy_probe:
+        cpu = cpu_timing(sweep)
+        print(f"# cpu {cpu}", file=sys.stderr, flush=True)
 
     import torch
     import paper_1603_08109_amd as P
@@ -279,12 +482,8 @@ def main():
     H = Wd = 4096
     f = synthimg.gen2(H, Wd, 3000)
     x = torch.tensor(f, dtype=torch.float32, device=dev)
+    f64 = x.cpu().numpy().astype(np.float64)  # the float32 input the GPU sees
     out = torch.empty_like(x)
-
-    sweep = list(enumerate(SWEEP))
-    if a.only:
-        keep = {int(i) for i in a.only.split(",")}
-        sweep = [s for s in sweep if s[0] in keep]
 
     results, skipped = [], []
     plans = {}
@@ -298,58 +497,98 @@ def main():
     torch.cuda.synchronize()
     total_ms = 0.0
     total_px = 0.0
+    checks = []
     for idx, (kind, kw, sr) in sweep:
         if idx not in plans:
             continue
         plan = plans[idx]
         ms = time_launches(lambda: plan.forward(x, out=out), stream, a.warmup, a.steps, torch)
-        N, W = plan.info.N, plan.info.W
-        flops = H * Wd * (N + 1) * alg_flops_per_px_n(kind, W)
-        r = dict(setting=setting_name(kind, kw, sr), N=N, W=W, tile_rows=plan.info.tile_rows,
+        N, W, TY = plan.info.N, plan.info.W, plan.info.tile_rows
+        flops, roof = setting_roof(kind, W, N, ms, TY, H, Wd)
+        r = dict(setting=setting_name(kind, kw, sr), N=N, W=W, tile_rows=TY, engine=engine_of(kind, W, TY),
                  ms=round(ms, 4), mpix_s=round(H * Wd / ms / 1e3, 1),
                  alg_tflops=round(flops / ms / 1e9, 2),
-                 hbm_gbs=round(8.0 * H * Wd / ms / 1e6, 1))
+                 hbm_gbs=round(8.0 * H * Wd / ms / 1e6, 1), roof=roof)
         results.append(r)
         total_ms += ms
         total_px += H * Wd
         print(f"# {r}", file=sys.stderr, flush=True)
-
-    def roof(r):
-        kind = "box" if r["setting"].startswith("box") else "gauss"
-        flops = H * Wd * (r["N"] + 1) * alg_flops_per_px_n(kind, r["W"])
-        achieved = flops / (r["ms"] * 1e-3) / 1e12
-        streamed_fir = r["tile_rows"] == 0 and kind == "gauss"
-        split = streamed_fir and r["W"] >= SPLIT_MIN_W
-        kern = ("gpa_forward_kernel (one launch)" if r["tile_rows"] > 0 else
-                "ls_rows_x3 + ls_cols_x3 per block of 16 orders" if split else
-                "ls_rows_x3 + ls_cols_mfma per block of 16 orders" if streamed_fir else
-                "ls_box_strip per block of 16 orders")
-        extra = {}
-        if split:
-            # the FIR products run as split-BF16 matrix-core products: priced at the
-            # FP32-product ceiling of that arithmetic, with the FP32 matrix-core ratio beside
-            bound, peak = "mfma", MFMA_BF16_PEAK_TFLOPS / SPLIT_PRODUCTS
-            extra = {"peak_basis": f"BF16 dense {MFMA_BF16_PEAK_TFLOPS:g} TFLOP/s / {SPLIT_PRODUCTS} products "
-                                   "per FP32 product",
-                     "frac_of_fp32_mfma_peak": round(achieved / MFMA_F32_PEAK_TFLOPS, 4)}
-        elif streamed_fir:
-            bound, peak = "mfma", MFMA_F32_PEAK_TFLOPS
-        else:
-            bound, peak = "alu", ALU_PEAK_TFLOPS
-        return {"bound": bound, "achieved": round(achieved, 3), "peak": round(peak, 1),
-                "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
-                "traffic": measured_traffic(r["setting"]),
-                "kernel": kern, "setting": r["setting"], "ms_per_call": r["ms"],
-                "alg_flops_per_call": flops, "hbm_frac_alg_bytes": round(r["hbm_gbs"] / HBM_PEAK_GBS, 5),
-                **extra}
+        if cpu is not None:
+            # keep what the accuracy check needs from the last timed output
+            sr_seam, sc_seam = seams(kind, W, TY, H, Wd)
+            wide = W <= 10
+            band = (sr_seam - 1, sr_seam + 1, 0 if wide else max(0, sc_seam - 150), Wd if wide else min(Wd, sc_seam + 150))
+            n = 48 if W > 40 else 96 if W > 10 else 192
+            px = synthimg.sample_pixels(H, Wd, n, W, n // 3, 3001 + idx)
+            o = out.cpu().numpy().astype(np.float64)
+            checks.append(dict(setting=r["setting"], kind=kind, kw=kw, sigma_r=sr, N=N, W=W, pixels=px,
+                               sample_vals=o[px[:, 0], px[:, 1]], band=band,
+                               band_vals=o[band[0]:band[1], band[2]:band[3]].copy()))
 
     dom = max(results, key=lambda r: r["ms"])
-    roofline = roof(dom)
+    roofline = dict(dom["roof"])
+    roofline.update({"traffic": measured_traffic(dom["setting"]), "kernel": dom["engine"], "setting": dom["setting"],
+                     "ms_per_call": dom["ms"], "alg_flops_per_call": H * Wd * (dom["N"] + 1) * alg_flops_per_px_n(
+                         "box" if dom["setting"].startswith("box") else "gauss", dom["W"]),
+                     "hbm_frac_alg_bytes": round(dom["hbm_gbs"] / HBM_PEAK_GBS, 5)})
     fused = [r for r in results if r["tile_rows"] > 0]
-    roofline_fused = roof(max(fused, key=lambda r: r["ms"])) if fused else None
+    roofline_fused = None
+    if fused:
+        fd = max(fused, key=lambda r: r["ms"])
+        roofline_fused = dict(fd["roof"], setting=fd["setting"], kernel="gpa_forward_kernel (one launch)",
+                              ms_per_call=fd["ms"], traffic=measured_traffic(fd["setting"]))
 
     extra = {}
+    fb_checks = []
     if not a.no_extra:
+        # fwd+bwd on the sweep image: forward keeping its state, then the adjoint with both sigma
+        # gradients; loss = MSE against the noise-free image
+        clean = torch.tensor(synthimg.clean2(H, Wd, 3000), dtype=torch.float32, device=dev)
+        fbl = {}
+        for kind, kw, sr in FWD_BWD_4096:
+            plan = P.Plan(kind, sr, H, Wd, grad=True, **kw)
+            N, W = plan.info.N, plan.info.W
+            saved = plan.new_saved()
+            gin = torch.empty_like(x)
+
+            def fwd_bwd():
+                plan.forward(x, out=out, saved=saved)
+                g = (out - clean) * (2.0 / out.numel())
+                plan.backward(x, g, saved=saved, grad_in=gin)
+
+            ms = time_launches(fwd_bwd, stream, 1, max(1, a.steps // 4), torch)
+            flops = H * Wd * fwd_bwd_flops_per_px(kind, W, N)
+            tf = flops / (ms * 1e-3) / 1e12
+            fused_adj = W <= 26
+            bound, peak = ("alu", ALU_PEAK_TFLOPS) if (fused_adj or kind == "box") else ("mfma", MFMA_F32_PEAK_TFLOPS)
+            name = setting_name(kind, kw, sr)
+            fbl[name] = {"N": N, "W": W, "adjoint": "fused tile" if fused_adj else "streamed",
+                         "ms": round(ms, 3), "mpix_s": round(H * Wd / ms / 1e3, 1), "alg_tflops": round(tf, 2),
+                         "roof": {"bound": bound, "peak": round(peak, 1), "unit": "TFLOP/s",
+                                  "frac": round(tf / peak, 4)},
+                         "hbm_gbs_alg_bytes": round(36.0 * H * Wd / ms / 1e6, 1)}
+            print(f"# fwd_bwd_4096 {name} {fbl[name]}", file=sys.stderr, flush=True)
+            if cpu is not None:
+                # an (untimed) adjoint for an output gradient on the corner patch, for the check
+                pr, pc = synthimg.grad_patches(H, Wd, GRAD_PATCH, ("corner",))[0]
+                seed = 7400 + len(fb_checks)
+                g = torch.tensor(synthimg.patch_gbar(H, Wd, [(pr, pc)], GRAD_PATCH, seed), dtype=torch.float32,
+                                 device=dev)
+                gin2, gs = plan.backward(x, g, saved=saved)
+                torch.cuda.synchronize()
+                R0, C0 = max(0, pr - W), max(0, pc - W)
+                gi = gin2.cpu().numpy().astype(np.float64)
+                zero = np.count_nonzero(gi[:R0, :]) == 0 and np.count_nonzero(gi[:, :C0]) == 0
+                fb_checks.append(dict(setting=name, kind=kind, kw=kw, sigma_r=sr, N=N, W=W, patch=(pr, pc),
+                                      seed=seed, gin_crop=gi[R0:, C0:].copy(), gs=gs.cpu().numpy(),
+                                      zero_outside=zero))
+                del g, gin2, gi
+            del plan, saved, gin
+        extra["fwd_bwd_4096"] = {"workload": "4096x4096 gen2, forward with saved state + adjoint (dL/df, "
+                                             "dL/dsigma_r, dL/dsigma_s), MSE loss against the noise-free image",
+                                 "per_setting": fbl}
+        del clean
+
         # differentiable workload: 32 x 512^2, Gaussian sigma_s = 5, sigma_r = 30
         imgs = [torch.tensor(synthimg.gen1(512, 512, 5000 + b), dtype=torch.float32, device=dev)
                 for b in range(32)]
@@ -359,7 +598,6 @@ def main():
         saved = [plan5.new_saved() for _ in range(32)]
         outs = [torch.empty_like(imgs[0]) for _ in range(32)]
         gins = [torch.empty_like(imgs[0]) for _ in range(32)]
-        gs = torch.empty(2, dtype=torch.float64, device=dev)
 
         def fwd_bwd():
             for b in range(32):
@@ -416,13 +654,19 @@ def main():
         torch.cuda.synchronize()
         rel_s = max(float((bgins[b] - ref_gins[b]).abs().max() / ref_gins[b].abs().max()) for b in range(32))
         px5 = 32 * 512 * 512
-        extra["fwd_bwd"] = {"workload": "32x512^2 gauss(sigma_s=5,sigma_r=30) N=%d, MSE loss" % plan5.info.N,
+        N5, W5 = plan5.info.N, plan5.info.W
+        tf5 = px5 * fwd_bwd_flops_per_px("gauss", W5, N5) / (ms_fbs * 1e-3) / 1e12
+        extra["fwd_bwd"] = {"workload": "32x512^2 gauss(sigma_s=5,sigma_r=30) N=%d, MSE loss" % N5,
                             "ms": round(ms_fb, 3), "mpix_s": round(px5 / ms_fb / 1e3, 1),
                             "fwd_ms": round(ms_f, 3), "fwd_mpix_s": round(px5 / ms_f / 1e3, 1),
                             "batched_ms": round(ms_fbb, 3), "batched_mpix_s": round(px5 / ms_fbb / 1e3, 1),
                             "batched_vs_per_image_max_rel_dfdin": rel,
                             "batched_saved_ms": round(ms_fbs, 3), "batched_saved_mpix_s": round(px5 / ms_fbs / 1e3, 1),
                             "batched_saved_vs_per_image_max_rel_dfdin": rel_s,
+                            "batched_saved_roof": {"bound": "alu", "achieved": round(tf5, 2),
+                                                   "peak": round(ALU_PEAK_TFLOPS, 1), "unit": "TFLOP/s",
+                                                   "frac": round(tf5 / ALU_PEAK_TFLOPS, 4),
+                                                   "alg_flops_per_px": fwd_bwd_flops_per_px("gauss", W5, N5)},
                             "recompute_ms": round(ms_fr, 3), "recompute_mpix_s": round(px5 / ms_fr / 1e3, 1),
                             "mirror_recompute_ms": round(ms_fm, 3),
                             "mirror_recompute_mpix_s": round(px5 / ms_fm / 1e3, 1)}
@@ -448,7 +692,7 @@ def main():
         print(f"# fwd_bwd {extra['fwd_bwd']}", file=sys.stderr, flush=True)
         del imgs, tgts, saved, outs, gins, bgins, ref_gins, gbatch, bsaved, wbatch, plan10, gw
 
-        # batched workload: 256 uneven images, one persistent launch vs per-image launches
+        # batched workload: 256 uneven images, one graph launch vs per-image launches
         specs = synthimg.batch_params(256, 4000)
         per = [dict(kernel="gauss", sigma_s=s["sigma_s"], sigma_r=s["sigma_r"], height=s["height"],
                     width=s["width"]) for s in specs]
@@ -457,7 +701,9 @@ def main():
         bouts = [torch.empty_like(t) for t in bimgs]
         batch = P.Batch(per)
         chosen = batch.tune(bimgs, bouts)
+        g0 = batch.get_info()["forward_graph_launches"]
         ms_b = time_launches(lambda: batch.forward(bimgs, bouts), stream, 1, a.steps, torch)
+        binfo = batch.get_info()
         plans4 = []
         for s in per:
             d = dict(s)
@@ -473,7 +719,12 @@ def main():
                                       "sigma_r U[10,60]", "mpx": round(bpx / 1e6, 2),
                           "batched_ms": round(ms_b, 3), "per_image_ms": round(ms_p, 3),
                           "batched_mpix_s": round(bpx / ms_b / 1e3, 1),
-                          "speedup": round(ms_p / ms_b, 3), "tuned_candidate": chosen}
+                          "speedup": round(ms_p / ms_b, 3), "tuned_candidate": chosen,
+                          "graph_launches_per_call": (binfo["forward_graph_launches"] - g0) / (1 + a.steps),
+                          "direct_launches": binfo["forward_direct_launches"],
+                          "images_persistent": binfo["images_persistent"],
+                          "images_streamed": binfo["images_streamed"],
+                          "workspace_gb": round(binfo["workspace_bytes"] / 1e9, 3)}
         print(f"# batch {extra['batch']}", file=sys.stderr, flush=True)
         del bimgs, bouts, batch, plans4
 
@@ -529,34 +780,17 @@ def main():
         print(f"# volume {extra['volume']}", file=sys.stderr, flush=True)
         del vx, vout
 
-    cpu = None
-    if not a.no_cpu_baseline:
-        from oracle import gpa as G
-        from oracle import kernels as K
-        crop = 256
-        fc = x[:crop, :crop].double().cpu().numpy()
-        t_cpu = 0.0
-        n_set = 0
-        worst = 0.0
-        for idx, (kind, kw, sr) in sweep:
-            if idx not in plans:
-                continue
-            plan = plans[idx]
-            sub = P.Plan(kind, sr, crop, crop, **kw)
-            gpu_crop = sub.forward(x[:crop, :crop].contiguous())
-            w1 = K.taps1d(kind, kw.get("sigma_s"), kw.get("W"))
-            t0 = time.perf_counter()
-            ref = G.gpa_alg2(fc, w1, sr, plan.info.N, 127.5)
-            t_cpu += time.perf_counter() - t0
-            n_set += 1
-            torch.cuda.synchronize()
-            worst = max(worst, float(np.abs(gpu_crop.cpu().numpy().astype(np.float64) - ref).max()))
-        cpu = {"value": round(n_set * crop * crop / t_cpu / 1e6, 4), "unit": "Mpix/s", "cores": 1,
-               "kind": "oracle",
-               "sample": f"numpy float64 Algorithm 2 on the {crop}x{crop} top-left crop, each of the "
-                         f"{n_set} settings once ({t_cpu:.1f} s)",
-               "gpu_max_err_on_sample": worst}
-        print(f"# cpu {cpu}", file=sys.stderr, flush=True)
+    if cpu is not None:
+        acc, fb_acc = accuracy_checks(checks, fb_checks, f64)
+        for r in results:
+            r["accuracy"] = acc.get(r["setting"])
+        if "fwd_bwd_4096" in extra:
+            for name, e in fb_acc.items():
+                extra["fwd_bwd_4096"]["per_setting"][name]["accuracy"] = e
+        worst = max(max(v["vs_gpa_pairwise_sample"]["max"], v["vs_filtering_form_band"]["max"])
+                    for v in acc.values())
+        cpu["gpu_max_err_vs_oracle"] = worst
+        cpu["gpu_max_err_vs_direct_bf"] = max(v["vs_direct_bf_sample"]["max"] for v in acc.values())
 
     value = total_px / (total_ms * 1e-3) / 1e6
     line = {

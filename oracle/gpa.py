@@ -174,8 +174,10 @@ def gpa_sums(f: np.ndarray, filt, sigma_r: float, N: int, T: float):
     P = np.zeros_like(f)
     Q = np.zeros_like(f)
     Fbar_n = filt(E)
+    un = np.ones_like(u)   # u^(n+1) below, one factor u per order
     for n, c in power_over_factorial(u, N):
-        Fbar_next = filt(E * u ** (n + 1))
+        un = un * u
+        Fbar_next = filt(E * un)
         Q += c * Fbar_n
         P += c * Fbar_next
         Fbar_n = Fbar_next

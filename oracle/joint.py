@@ -125,8 +125,10 @@ def gpa_joint_alg2(f: np.ndarray, h: np.ndarray, w1: np.ndarray, sigma_r: float,
     E = np.exp(-0.5 * x * x)
     P = np.zeros_like(f)
     Q = np.zeros_like(f)
+    xn = np.ones_like(x)   # x^n, one factor x per order
     for n, c in power_over_factorial(x, N):
-        Fn = E * x ** n
+        Fn = E * xn
         Q += c * spatial_filter(Fn, w1)
         P += c * spatial_filter(Fn * f, w1)
+        xn = xn * x
     return P / Q

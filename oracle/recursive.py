@@ -126,8 +126,10 @@ def gpa_alg2_at(f: np.ndarray, pixels: np.ndarray, sigma_s: float, sigma_r: floa
     P = np.zeros(len(px))
     Q = np.zeros(len(px))
     Fbar_n = at(E)
+    un = np.ones_like(u)   # u^(n+1) below, one factor u per order
     for n, c in _gpa.power_over_factorial(u[rr, cc], N):
-        Fbar_next = at(E * u ** (n + 1))
+        un = un * u
+        Fbar_next = at(E * un)
         Q += c * Fbar_n
         P += c * Fbar_next
         Fbar_n = Fbar_next

@@ -23,6 +23,12 @@ batch_params(count, seed)
 clean_blocks(H, W, seed)
     The noise-free block image that gen1(H, W, seed) starts from (the
     regression target of the differentiable workload).
+clean2(H, W, seed)
+    The noise-free image (blocks plus ramp, clipped) that gen2(H, W, seed)
+    starts from.
+grad_patches, patch_gbar
+    Patches of an image and an output gradient supported on them (checks of
+    the adjoint on crops of large images).
 
 Seeds: workload k, image b uses ``seed = 1000*k + b``.
 """
@@ -59,6 +65,12 @@ def ramp(H: int, W: int) -> np.ndarray:
     i = np.arange(H, dtype=np.float64)[:, None]
     j = np.arange(W, dtype=np.float64)[None, :]
     return RAMP_AMPLITUDE * np.sin(2.0 * np.pi * (i / H + j / W))
+
+
+def clean2(H: int, W: int, seed: int) -> np.ndarray:
+    """Noise-free image underlying gen2(H, W, seed): blocks plus ramp, clipped."""
+    rng = np.random.default_rng(seed)
+    return np.clip(_levels(rng, H, W) + ramp(H, W), 0.0, 255.0)
 
 
 def gen2(H: int, W: int, seed: int) -> np.ndarray:
