@@ -176,6 +176,33 @@ int bf_plan_clone_workspace(const bf_plan_t* plan, bf_plan_t** out);
 int bf_forward(const bf_plan_t* plan, const float* in, int64_t in_pitch,
                float* out, int64_t out_pitch, float* saved, void* stream);
 
+/* Allocation-free forward, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  The same filter and the same fused-tile kernel as bf_plan +
+ * bf_forward, without a plan: the parameters are normalised and N, W and the
+ * engine chosen exactly as bf_plan does, and the constant tables that a plan
+ * keeps in its own workspace go to one static device array of the library
+ * instead (64 KiB per device, held until the process ends), written by small
+ * kernels on `stream` whose arguments carry the values.  The call makes no
+ * device allocation and frees nothing.
+ *   p       as for bf_plan; BF_FLAG_GRAD, JOINT, STREAMED and TILE_MFMA are
+ *           refused (BF_EUNSUPPORTED); BF_FLAG_MIRROR, FP32_ACCUM and
+ *           TILE_VALU are honoured
+ *   in      device, height x width float32, row pitch in_pitch (elements)
+ *   out     device, height x width float32, row pitch out_pitch; must not
+ *           alias `in`
+ * Limits: only parameters for which bf_plan picks the fused tile
+ * (BF_PATH_TILE: small supports, or any support on small images) run here;
+ * others return BF_EUNSUPPORTED.  Tables beyond the static array (16384
+ * floats, an order N of about 2000) return BF_EINVAL.
+ * Every call on one device shares the static array and leaves its tables
+ * there: calls that overlap on one device (other streams or threads) race;
+ * calls in order on one stream do not.
+ * Returns BF_OK, BF_WNOGUARANTEE as bf_plan does, or BF_EINVAL / BF_EUNSUPPORTED
+ * / BF_EHIP. */
+int bf_forward_noalloc(const bf_params* p, const float* in, int64_t in_pitch, float* out,
+                       int64_t out_pitch, void* stream);
+
 /* Video and volume data, the extension named in Sec. 1 and Sec. 5: D slices
  * of height x width (p->height, p->width), the kernel w1 x w1 x w1 on the cube
  * [-W, W]^3 (box or truncated Gaussian, W <= 32), zero extension or, with

@@ -7,5 +7,6 @@ a thin ctypes binding plus a torch.autograd wrapper.
 """
 from ._lib import (BF_PATH_RECURSIVE, BF_PATH_STREAMED, BF_PATH_TILE, BF_PATH_TILE_MFMA,  # noqa: F401
                    BF_PATH_VOLUME, BF_PATH_WIDE, BFError)
-from .api import Batch, Plan, PlanInfo, VolumePlan, bf_order, image_range, range_params, version  # noqa: F401
+from .api import (Batch, Plan, PlanInfo, VolumePlan, bf_order, forward_noalloc, image_range,  # noqa: F401
+                  range_params, version)
 from .autograd import BilateralGPA  # noqa: F401

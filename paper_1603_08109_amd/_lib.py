@@ -99,6 +99,8 @@ SIGNATURES = {
     "bf_forward_volume": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_int64, C.c_void_p]),
     "bf_forward": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_int64, C.c_void_p,
                              C.c_void_p]),
+    "bf_forward_noalloc": (C.c_int, [C.POINTER(bf_params), C.c_void_p, C.c_int64, C.c_void_p, C.c_int64,
+                                     C.c_void_p]),
     "bf_forward_joint": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_int64, C.c_void_p,
                                    C.c_int64, C.c_void_p]),
     "bf_image_range": (C.c_int, [C.c_void_p, C.c_int64, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p]),

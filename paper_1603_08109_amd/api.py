@@ -341,6 +341,24 @@ class Batch:
         return ch.value
 
 
+def forward_noalloc(kernel: str, sigma_r: float, inp: torch.Tensor, out: torch.Tensor | None = None,
+                    stream=None, **kw) -> torch.Tensor:
+    """bf_forward_noalloc: the plain forward without a plan; the library keeps
+    the constant tables in its static device array (no device allocation in the
+    call; pass `out` to avoid torch allocating one)."""
+    H, Wd = inp.shape
+    _check_image(inp, H, Wd, "inp")
+    if out is None:
+        out = torch.empty_like(inp)
+    _check_image(out, H, Wd, "out")
+    p = make_params(kernel, sigma_r, height=H, width=Wd, **kw)
+    lib = L.load()
+    L.check(lib.bf_forward_noalloc(C.byref(p), C.c_void_p(inp.data_ptr()), inp.stride(0),
+                                   C.c_void_p(out.data_ptr()), out.stride(0), _stream_handle(stream)),
+            "bf_forward_noalloc")
+    return out
+
+
 def image_range(img: torch.Tensor, stream=None) -> torch.Tensor:
     """Device float32 tensor [min, max] of a 2-D float32 image (bf_image_range)."""
     if not isinstance(img, torch.Tensor) or img.device.type != "cuda" or img.dtype != torch.float32:

@@ -231,6 +231,13 @@ hipError_t launch_batch_forward(const TileParams* d_params, const BatchTile* d_t
 int batch_variant_mreg();
 int batch_variant_opt();
 
+// Allocation-free forward (bf_noalloc.hip): the device address of the static
+// table array on the current device, its capacity, and a fill of it from host
+// values carried in kernel arguments.
+int noalloc_capacity_floats();
+hipError_t noalloc_scratch(float** out);
+hipError_t noalloc_fill(float* dst, const float* h, int64_t n, hipStream_t s);
+
 // errors
 void set_error(const std::string& msg);
 int fail(int code, const std::string& msg);

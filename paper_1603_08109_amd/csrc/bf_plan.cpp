@@ -758,12 +758,12 @@ int bf_destroy(bf_plan_t* plan) {
 }  // extern "C"
 
 namespace bfgpa {
-static void fill_common(const bf_plan_t* pl, TileParams& tp) {
-  const bf_params& p = pl->p;
+static void fill_common_tables(const bf_params& p, const bf_plan_info& info, const float* d_const,
+                               int64_t tab_stride, bool wide, TileParams& tp) {
   tp.H = p.height;
   tp.Wd = p.width;
   tp.W = p.W;
-  tp.N = pl->info.N;
+  tp.N = info.N;
   tp.kt = p.kernel;
   tp.sigma_r = (float)p.sigma_r;
   tp.inv_sigma_r = (float)(1.0 / p.sigma_r);
@@ -772,12 +772,16 @@ static void fill_common(const bf_plan_t* pl, TileParams& tp) {
   tp.X = (float)(p.T / p.sigma_r);
   tp.inv_sigma_s3 = p.kernel == BF_GAUSS ? (float)(1.0 / (p.sigma_s * p.sigma_s * p.sigma_s)) : 0.0f;
   const int64_t ntapr = ((2 * p.W + 1 + 2 * kTapPad + 63) / 64) * 64;
-  bind_tables(tp, pl->d_const, pl->tab_stride, ntapr);
-  tp.rg_tab = p.kernel == BF_GAUSS_REC ? pl->d_const + 7 * pl->tab_stride + 2 * ntapr : nullptr;
+  bind_tables(tp, d_const, tab_stride, ntapr);
+  tp.rg_tab = p.kernel == BF_GAUSS_REC ? d_const + 7 * tab_stride + 2 * ntapr : nullptr;
   tp.saved_plane = (int64_t)p.height * p.width;
   tp.mirror = (p.flags & BF_FLAG_MIRROR) ? 1 : 0;
   tp.mfma_x3 = (p.flags & BF_FLAG_MFMA_FP32) ? 0 : 1;
-  tp.wide = pl->wide ? 1 : 0;
+  tp.wide = wide ? 1 : 0;
+}
+
+static void fill_common(const bf_plan_t* pl, TileParams& tp) {
+  fill_common_tables(pl->p, pl->info, pl->d_const, pl->tab_stride, pl->wide, tp);
 }
 
 // The streamed forward of a plan, reading the image pointers (and, with
@@ -835,6 +839,54 @@ int bf_forward(const bf_plan_t* pl, const float* in, int64_t in_pitch, float* ou
   }
   if (e != hipSuccess) return hip_fail(e, "forward launch");
   return BF_OK;
+}
+
+int bf_forward_noalloc(const bf_params* in_p, const float* in, int64_t in_pitch, float* out,
+                       int64_t out_pitch, void* stream) {
+  if (!in_p || !in || !out) return fail(BF_EINVAL, "NULL parameter or image pointer");
+  bf_params p;
+  int st = normalise(in_p, &p);
+  if (st < 0) return st;
+  if (p.height <= 0 || p.width <= 0) return fail(BF_EINVAL, "height and width must be > 0");
+  if (in_pitch < p.width || out_pitch < p.width) return fail(BF_EINVAL, "pitch smaller than width");
+  if ((const void*)in == (const void*)out) return fail(BF_EINVAL, "in and out must not alias");
+  if (p.flags & (BF_FLAG_GRAD | BF_FLAG_JOINT | BF_FLAG_STREAMED | BF_FLAG_TILE_MFMA))
+    return fail(BF_EUNSUPPORTED, "the allocation-free forward is the plain fused-tile forward "
+                                 "(no adjoint, cross filter, streamed or matrix-core engine)");
+  bf_plan_info info;
+  const int ost = plan_order(&p, &info);
+  if (ost < 0) return ost;
+  ForwardPath fpath;
+  st = choose_forward_path(p, &fpath);
+  if (st < 0) return st;
+  if (fpath.engine != BF_PATH_TILE)
+    return fail(BF_EUNSUPPORTED, "the allocation-free forward serves the fused-tile engine only; this image "
+                                 "size and support take an engine whose per-pixel state needs bf_plan's workspace");
+  int64_t stride = 0, ntapr = 0;
+  const std::vector<float> h = const_tables(p, info, &stride, &ntapr);
+  if ((int64_t)h.size() > noalloc_capacity_floats())
+    return fail(BF_EINVAL, "constant tables of " + std::to_string(h.size()) + " floats exceed the static buffer of " +
+                               std::to_string(noalloc_capacity_floats()) + " (order N too large)");
+  float* d = nullptr;
+  hipError_t e = noalloc_scratch(&d);
+  if (e != hipSuccess) return hip_fail(e, "static table buffer address");
+  const hipStream_t s = (hipStream_t)stream;
+  e = noalloc_fill(d, h.data(), (int64_t)h.size(), s);
+  if (e != hipSuccess) return hip_fail(e, "static table fill");
+  TileParams tp;
+  std::memset(&tp, 0, sizeof(tp));
+  fill_common_tables(p, info, d, stride, false, tp);
+  tp.in = in;
+  tp.in_pitch = in_pitch;
+  tp.out = out;
+  tp.out_pitch = out_pitch;
+  tp.TY = fpath.TY;
+  tp.tiles_x = (p.width + kTileCols - 1) / kTileCols;
+  const bool acc64 = (p.flags & BF_FLAG_FP32_ACCUM) == 0;
+  e = launch_forward(tp, fpath.variant, acc64, false, s);
+  if (e != hipSuccess) return hip_fail(e, "forward launch");
+  if (ost == BF_WNOGUARANTEE) set_error("order below the bound: no +-delta guarantee");
+  return ost;
 }
 
 int bf_plan_volume(const bf_params* in, int32_t depth, bf_plan_t** out) {
