@@ -50,8 +50,6 @@ MFMA_F32_PEAK_TFLOPS = 157.3
 MFMA_BF16_PEAK_TFLOPS = 2500.0
 SPLIT_PRODUCTS = 6
 SPLIT_MIN_W = 40  # from this support both streamed passes use the split arithmetic
-LDS_BYTES = 160 * 1024
-NUM_CU = 256
 
 SWEEP = ([("gauss", dict(sigma_s=s), r) for s in (3.0, 10.0, 25.0) for r in (10.0, 30.0, 50.0)]
          + [("box", dict(W=w), r) for w in (10, 30, 75) for r in (10.0, 30.0, 50.0)])
@@ -141,34 +139,31 @@ def time_launches(fn, stream, warmup, steps, torch):
 
 # --- engines and their seams ----------------------------------------------------
 
-def engine_of(kind, W, tile_rows):
-    """The forward engine a 4096^2 plan runs (as the planner picks it)."""
-    if tile_rows > 0:
+def engine_of(kind, W, info):
+    """The forward engine a 4096^2 plan runs (as the planner reports it)."""
+    if info.path == 0:
         return "fused_valu_tile"
     if kind == "box":
-        return "box_strips_512" if W >= 56 else "box_strips_256"
+        return f"box_strips_{info.tile_cols + 2 * W}"
     return "rows_x3+cols_x3" if W >= SPLIT_MIN_W else "rows_x3+cols_mfma"
 
 
-def seams(kind, W, tile_rows, H, Wd):
+def seams(kind, W, info):
     """(row, column) of a seam of the engine's work decomposition: fused tiles
-    of 64 columns x tile_rows; box strips of 256 - 2W (512 - 2W) output
-    columns cut into row segments that fill one wave of resident workgroups;
-    streamed Gaussian passes on 16 x 256 row tiles and 64 x 64 column tiles."""
-    if tile_rows > 0:
-        return tile_rows, 64
+    of 64 columns x tile_rows; box strips of tile_cols output columns cut into
+    row segments of tile_rows (the plan reports both); streamed Gaussian passes
+    on 16 x 256 row tiles and 64 x 64 column tiles."""
+    if info.path == 0:
+        return info.tile_rows, 64
     if kind == "box":
-        oc, per = (512 - 2 * W, 16 * 548 * 8) if W >= 56 else (256 - 2 * W, 16 * 276 * 8)
-        nstrips = -(-Wd // oc)
-        nseg = max(1, min((H + 31) // 32, (NUM_CU * max(1, LDS_BYTES // per)) // nstrips))
-        return -(-H // nseg), oc
+        return info.tile_rows, info.tile_cols
     return 64, 256
 
 
-def setting_roof(kind, W, N, ms, tile_rows, H, Wd):
+def setting_roof(kind, W, N, ms, info, H, Wd):
     flops = H * Wd * (N + 1) * alg_flops_per_px_n(kind, W)
     achieved = flops / (ms * 1e-3) / 1e12
-    eng = engine_of(kind, W, tile_rows)
+    eng = engine_of(kind, W, info)
     extra = {}
     if eng == "rows_x3+cols_x3":
         # the FIR products run as split-BF16 matrix-core products: priced at the
@@ -504,8 +499,8 @@ def main():
         plan = plans[idx]
         ms = time_launches(lambda: plan.forward(x, out=out), stream, a.warmup, a.steps, torch)
         N, W, TY = plan.info.N, plan.info.W, plan.info.tile_rows
-        flops, roof = setting_roof(kind, W, N, ms, TY, H, Wd)
-        r = dict(setting=setting_name(kind, kw, sr), N=N, W=W, tile_rows=TY, engine=engine_of(kind, W, TY),
+        flops, roof = setting_roof(kind, W, N, ms, plan.info, H, Wd)
+        r = dict(setting=setting_name(kind, kw, sr), N=N, W=W, tile_rows=TY, engine=engine_of(kind, W, plan.info),
                  ms=round(ms, 4), mpix_s=round(H * Wd / ms / 1e3, 1),
                  alg_tflops=round(flops / ms / 1e9, 2),
                  hbm_gbs=round(8.0 * H * Wd / ms / 1e6, 1), roof=roof)
@@ -515,7 +510,7 @@ def main():
         print(f"# {r}", file=sys.stderr, flush=True)
         if cpu is not None:
             # keep what the accuracy check needs from the last timed output
-            sr_seam, sc_seam = seams(kind, W, TY, H, Wd)
+            sr_seam, sc_seam = seams(kind, W, plan.info)
             wide = W <= 10
             band = (sr_seam - 1, sr_seam + 1, 0 if wide else max(0, sc_seam - 150), Wd if wide else min(Wd, sc_seam + 150))
             n = 48 if W > 40 else 96 if W > 10 else 192
@@ -531,7 +526,7 @@ def main():
                      "ms_per_call": dom["ms"], "alg_flops_per_call": H * Wd * (dom["N"] + 1) * alg_flops_per_px_n(
                          "box" if dom["setting"].startswith("box") else "gauss", dom["W"]),
                      "hbm_frac_alg_bytes": round(dom["hbm_gbs"] / HBM_PEAK_GBS, 5)})
-    fused = [r for r in results if r["tile_rows"] > 0]
+    fused = [r for r in results if r["engine"] == "fused_valu_tile"]
     roofline_fused = None
     if fused:
         fd = max(fused, key=lambda r: r["ms"])

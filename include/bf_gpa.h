@@ -120,8 +120,10 @@ typedef struct bf_plan_info {
   double  lambda;            /* T^2 / sigma_r^2 */
   double  kernel_bound;      /* Poisson tail at N, Prop. upperBound */
   double  guaranteed_delta;  /* 2 T bound / (w0 - bound), Prop. accuracy (inf if none) */
-  int32_t tile_rows;         /* tile height the forward kernel uses */
-  int32_t tile_cols;         /* tile width */
+  int32_t tile_rows;         /* tile height the fused forward kernel uses; for the
+                                box column strips of the streamed engine (bf_plan
+                                only), the row-segment length of the plain forward */
+  int32_t tile_cols;         /* tile width; for the box strips, output columns per strip */
   int64_t workspace_bytes;   /* device bytes owned by the plan */
   int32_t path;              /* BF_PATH_* the forward runs (bf_order: the one it would run) */
 } bf_plan_info;

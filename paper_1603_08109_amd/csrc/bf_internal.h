@@ -198,6 +198,13 @@ int max_lds_bytes();
 // large-support path (bf_large.hip)
 bool ls_supported(int W);
 bool ls_box_strip_supported(int W);
+// box column strips: columns per thread, output columns per strip, row-segment
+// length, grid and LDS bytes on an H x Wd image
+struct StripShape {
+  int cpt, oc, seg_rows, grid;
+  int64_t lds;
+};
+StripShape ls_box_strip_shape(int H, int Wd, int W, bool save);
 bool ls_mirror_supported(int kernel, int W);
 int64_t ls_state_bytes(int H, int Wd, int W, bool save, bool wide = false);
 LsState ls_layout(void* base, int H, int Wd, int W, bool save, bool wide = false);

@@ -407,15 +407,7 @@ __global__ __launch_bounds__(kThreads) void ls_cols_fir_kernel(TileParams p, LsS
 // ---------------------------------------------------------------------------
 // Box kernel in column strips.  With C_n(r, c) = sum_{|dr| <= W} F^_n(r + dr, c)
 // (zero outside the image), the box sum is F_bar_n(r, c) = sum_{|dc| <= W}
-// C_n(r, c + dc).  A workgroup owns a strip of OC = 256 - 2W output columns
-// (one strip column per thread, halo included) and a segment of rows.  It
-// keeps C_n for the block's orders in float64 registers and slides them down
-// the segment (add the entering row, subtract the leaving one; each row's
-// F^_n follow from F^_{n0} and y by the power recursion), takes each order's
-// row window as a difference of float64 prefix sums (one wave scan per
-// order), and folds the K values of every output pixel into eqs. (P), (Q).
-// The segment's rows advance the F^ state image as they enter.  Waves share
-// only LDS, so the barriers leave global loads and stores in flight.
+// C_n(r, c + dc).
 // ---------------------------------------------------------------------------
 // Inclusive prefix sum of a double over the 64 lanes of a wave: row_shr
 // steps inside each 16-lane row, then row_bcast:15 and row_bcast:31 carry the
@@ -445,315 +437,265 @@ __device__ __forceinline__ double wave_scan_incl(double v) {
 }
 
 constexpr int kStripThreads = 256;
-constexpr int kStripPitch = 276;  // doubles per order: 256 columns swizzled, the total, 16-byte rows
 
-// Column s of a 256-column prefix row sits at s + 2 (s / 32): the 16-byte
-// reads of lanes 8 apart (32 bytes per lane) no longer share banks.
-__device__ __forceinline__ int sw1(int s) { return s + 2 * (s >> 5); }
+// ---------------------------------------------------------------------------
+// Box kernel in column strips, single-pass form used for every box support
+// from 16 on large images.  A workgroup owns a strip of SC = 256 CPT columns
+// (CPT per thread, halo included; OC = SC - 2W outputs) and a segment of
+// rows, and processes the kLsBlock orders n0 .. n0 + kLsBlock - 1 of one
+// launch.  Per output row r:
+//   1. every thread writes the column sums C_n(r, c) of its columns (float64
+//      registers, rounded to float32) for the block's orders into LDS;
+//   2. (barrier) wave w takes orders w, w + 4, w + 8, w + 12.  For each,
+//      lane l sums strip columns 4 CPT l .. 4 CPT l + 4 CPT - 1 into a float64
+//      prefix, a DPP wave scan joins the lanes, the inclusive prefix S goes to
+//      the wave's own LDS row (read back by the same wave: no barrier), and
+//      the window sums S(c + W) - S(c - W - 1) of the output columns
+//      overwrite that order's column sums in LDS (float32);
+//   3. (barrier) each thread folds the window sums of its output columns into
+//      eqs. (P), (Q) (float32 partials added to the float64 totals every 8
+//      orders) and slides its column sums down one row: the entering and
+//      leaving rows' F^_n follow from F^_{n0} and y by the power recursion,
+//      in float64.
+// The fold has no per-order tests: the factor 1/(n + 1) that advances a_n is
+// taken as 0 where n + 1 >= N, so a_n = 0 for every n >= N, and the orders
+// past N in the last block add nothing (eq. (Q) stops at n = N - 1 and eq.
+// (P) at n = N).  The rows entering the segment advance the F^ state image.
+// ---------------------------------------------------------------------------
+template <int CPT>
+struct StripGeom {
+  static constexpr int SC = 256 * CPT;              // strip columns
+  static constexpr int CPL = 4 * CPT;               // columns per lane in the row scan
+  static constexpr int CPITCH = SC + 4 * (SC / 64);  // float32 row: 4 floats of padding per 64 columns
+  static constexpr int SPITCH = SC + 4 + 2 * ((SC + 2) / 32);  // float64 prefix row (slots 0 .. SC + 1)
+  static constexpr int LDS_BYTES = kLsBlock * CPITCH * 4 + 4 * SPITCH * 8;
+};
+// float32 column c of a row: the 16-byte reads of lanes 8 apart (32 bytes
+// per lane) fall on distinct banks
+__device__ __forceinline__ int strip_cpos(int c) { return c + 4 * (c >> 6); }
+// float64 prefix slot s (S(c) at slot c + 2, S(-1) = 0 at slot 1): the
+// 16-byte writes of lanes 4 apart (64 bytes per lane) fall on distinct banks
+__device__ __forceinline__ int strip_spos(int s) { return s + 2 * (s >> 5); }
 
-__host__ __device__ inline int strip_cols(int W) { return kStripThreads - 2 * W; }
-
-template <bool SAVE>
-__global__ __launch_bounds__(kStripThreads) void ls_box_strip_kernel(TileParams p, LsState st, int n0, int K,
-                                                                     int src, int seg_rows) {
+template <int CPT, bool SAVE>
+__global__ __launch_bounds__(kStripThreads) void ls_box_strip_kernel(TileParams p, LsState st, int n0, int src,
+                                                                      int seg_rows) {
+  using G = StripGeom<CPT>;
+  constexpr int SC = G::SC, CPL = G::CPL;
   extern __shared__ double dlds[];
-  double* Cs = dlds;  // kLsBlock x kStripPitch; order k's window sums then overwrite its row
-  const int W = p.W, L = 2 * W + 1;
-  const int OC = strip_cols(W);
-  const int nstrips = (p.Wd + OC - 1) / OC;
-  const int strip = blockIdx.x % nstrips, seg = blockIdx.x / nstrips;
-  const int c0 = strip * OC;
-  const int r_lo = seg * seg_rows, r_hi = min(r_lo + seg_rows, p.H);
-  const int t = threadIdx.x;
-  const int gc = c0 - W + t;
-  // mirror border: strip columns and rows outside the image read their reflections
-  const bool col_ok = p.mirror || (gc >= 0 && gc < p.Wd);
-  const int gcs = p.mirror ? reflect_index(gc, p.Wd) : gc;
-  const bool central = t >= W && t < W + OC && gc < p.Wd;
-  const int lane = t & 63, wv = t >> 6;
-  const int oc = t;  // output column c0 + oc (idle lanes cost nothing once a wave has none)
-  const bool pix = oc < OC && c0 + oc < p.Wd;
-  const float* Fin = st.F[src];
-  float* Fout = st.F[src ^ 1];
-  double C[kLsBlock];
-  float in1[kLsBlock];  // 1/(n+1) of the block's orders, read once
-#pragma unroll
-  for (int k = 0; k < kLsBlock; ++k) {
-    C[k] = 0.0;
-    in1[k] = p.inv_tab[n0 + min(k, K - 1) + 1];
-  }
-  // row q of F^_{n0 .. n0+K-1} at this column enters (+) or leaves (-) the window
-  auto load_row = [&](int q, float& f, float& y) {
-    f = 0.f;
-    y = 0.f;
-    if (p.mirror) q = reflect_index(q, p.H);
-    if (col_ok && q >= 0 && q < p.H) {
-      const int64_t j = (int64_t)q * st.pitch + gcs;
-      f = Fin[j];
-      y = st.Y[j];
-    }
-  };
-  for (int q = r_lo - W; q <= r_lo + W; ++q) {
-    float f, y;
-    load_row(q, f, y);
-#pragma unroll
-    for (int k = 0; k < kLsBlock; ++k)
-      if (k < K) {
-        C[k] += (double)f;
-        f *= y;
-      }
-    if (central && q >= r_lo && q < r_hi) Fout[(int64_t)q * st.pitch + gc] = f;
-  }
-  for (int r = r_lo; r < r_hi; ++r) {
-#pragma unroll
-    for (int k = 0; k < kLsBlock; ++k)
-      if (k < K) Cs[k * kStripPitch + sw1(t)] = C[k];
-    LsPix<1, SAVE> px;
-    const int64_t pi = (int64_t)r * p.Wd + c0 + oc;
-    px.load(st, pi, 0, pix ? 1 : 0);
-    float fe, ye, fl, yl;  // rows entering and leaving after this output row
-    load_row(r + W + 1, fe, ye);
-    load_row(r - W, fl, yl);
-    lds_barrier();
-    // per order: prefix S over the 256 strip columns (float64), then the
-    // window sums S(c + 2W + 1) - S(c) of the OC output columns.  Wave w
-    // takes orders w, w+4, w+8, w+12 (straight-line, so the four scans
-    // interleave; rows past K hold stale values that nobody reads).  Lane l
-    // scans columns 4l .. 4l+3 (DPP across lanes), writes S back in place,
-    // then reads S at columns l + 64i and l + 64i + L (conflict-free).
-#pragma unroll
-    for (int j = 0; j < kLsBlock / 4; ++j) {
-      double* row = Cs + (wv + 4 * j) * kStripPitch;
-      const double2 u = *(const double2*)(row + sw1(4 * lane));
-      const double2 w = *(const double2*)(row + sw1(4 * lane) + 2);
-      const double s1 = u.x + u.y, s2 = s1 + w.x, s3 = s2 + w.y;
-      const double incl = wave_scan_incl(s3);
-      const double ex = incl - s3;
-      *(double2*)(row + sw1(4 * lane)) = make_double2(ex, ex + u.x);
-      *(double2*)(row + sw1(4 * lane) + 2) = make_double2(ex + s1, ex + s2);
-      if (lane == 63) row[sw1(256)] = incl;
-      float ov[4];
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int c = lane + 64 * i;
-        ov[i] = (float)(row[sw1(min(c + L, 256))] - row[sw1(c)]);
-      }
-      // all of the wave's reads of S precede these writes into the same row
-      float* o = (float*)row;
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-        if (lane + 64 * i < OC) o[lane + 64 * i] = ov[i];
-    }
-    lds_barrier();
-    // this pixel's window sums, then a barrier: the next row's column sums
-    // overwrite the rows they sit in
-    float v[kLsBlock];
-#pragma unroll
-    for (int k = 0; k < kLsBlock; ++k) v[k] = ((const float*)(Cs + k * kStripPitch))[oc];
-    lds_barrier();
-    if (pix) {
-#pragma unroll
-      for (int k = 0; k < kLsBlock; ++k)
-        if (k < K) px.fold(0, n0 + k, p.N, v[k], in1[k]);
-      px.store(st, pi, 0, 1);
-    }
-    // slide the window to r + 1
-#pragma unroll
-    for (int k = 0; k < kLsBlock; ++k)
-      if (k < K) {
-        C[k] += (double)fe - (double)fl;
-        fe *= ye;
-        fl *= yl;
-      }
-    const int qe = r + W + 1;
-    if (central && qe >= r_lo && qe < r_hi) Fout[(int64_t)qe * st.pitch + gc] = fe;
-  }
-}
-
-// Wider strips for the forward without saved state: 512 strip columns, two
-// per thread, so the 2W halo columns are shared by 512 - 2W outputs instead
-// of 256 - 2W.  The same float64 column sums and prefix windows; the fold
-// keeps float32 partial sums of eqs. (P), (Q) and adds them into the float64
-// totals every 8 orders, as the fused tiles do.
-constexpr int kStrip2Cols = 512;
-constexpr int kStrip2Pitch = 548;  // doubles per order: 512 columns swizzled, the total, 16-byte rows
-
-__host__ __device__ inline int strip2_cols(int W) { return kStrip2Cols - 2 * W; }
-
-// Column s of a prefix row sits at s + 2 (s / 32): a lane's 8 consecutive
-// columns stay contiguous, and the 16 lanes of a 16-byte read phase land on
-// distinct banks.
-__device__ __forceinline__ int sw2(int s) { return s + 2 * (s >> 5); }
-
-__global__ __launch_bounds__(kStripThreads) void ls_box_strip2_kernel(TileParams p, LsState st, int n0, int K,
-                                                                      int src, int seg_rows) {
-  extern __shared__ double dlds[];
-  double* Cs = dlds;  // kLsBlock x kStrip2Pitch; order k's window sums then overwrite its row
-  const int W = p.W, L = 2 * W + 1;
-  const int OC = strip2_cols(W);
+  float* Cb = (float*)dlds;                        // kLsBlock x CPITCH
+  double* Sb = dlds + (kLsBlock * G::CPITCH) / 2;  // 4 x SPITCH
+  const int W = p.W;
+  const int OC = SC - 2 * W;
   const int nstrips = (p.Wd + OC - 1) / OC;
   const int strip = blockIdx.x % nstrips, seg = blockIdx.x / nstrips;
   const int c0 = strip * OC;
   const int r_lo = seg * seg_rows, r_hi = min(r_lo + seg_rows, p.H);
   const int t = threadIdx.x;
   const int lane = t & 63, wv = t >> 6;
-  // this thread's strip columns 2t, 2t + 1 (image columns c0 - W + 2t + j)
-  int gcs[2];
-  bool col_ok[2], central[2], pix[2];
-  int64_t pio[2];
+  // this thread's strip columns CPT t + j (image columns c0 - W + CPT t + j)
+  int gcs[CPT];
+  bool col_ok[CPT], central[CPT];
+  int gcol[CPT];
 #pragma unroll
-  for (int j = 0; j < 2; ++j) {
-    const int sc = 2 * t + j, gc = c0 - W + sc;
+  for (int j = 0; j < CPT; ++j) {
+    const int sc = CPT * t + j, gc = c0 - W + sc;
     col_ok[j] = p.mirror || (gc >= 0 && gc < p.Wd);
     gcs[j] = p.mirror ? reflect_index(gc, p.Wd) : gc;
-    central[j] = sc >= W && sc < W + OC && gc < p.Wd;
-    pix[j] = central[j];
-    pio[j] = gc;  // output column of this strip column when central
+    central[j] = sc >= W && sc < W + OC && gc < p.Wd;  // an output column of this strip
+    gcol[j] = gc;
   }
   const float* Fin = st.F[src];
   float* Fout = st.F[src ^ 1];
-  double C[kLsBlock][2];
+  // 1/(n + 1) for the block's orders, 0 from n + 1 = N on (wave-uniform)
   float in1[kLsBlock];
+  float dqm[kLsBlock], dpm[kLsBlock];  // adjoint sums: eq. (Q)'s derivative stops at N - 1, (P)'s at N
 #pragma unroll
   for (int k = 0; k < kLsBlock; ++k) {
-    C[k][0] = C[k][1] = 0.0;
-    in1[k] = p.inv_tab[n0 + min(k, K - 1) + 1];
+    const int n = n0 + k;
+    in1[k] = (n + 1 < p.N) ? p.inv_tab[n + 1] : 0.f;
+    dqm[k] = (n == p.N) ? 0.f : 1.f;
+    dpm[k] = (n == p.N + 1) ? 0.f : 1.f;
   }
-  auto load_row = [&](int q, float (&f)[2], float (&y)[2]) {
-    if (p.mirror) q = reflect_index(q, p.H);
+  double* srow = Sb + wv * G::SPITCH;
+  if (lane == 0) {
+    srow[strip_spos(0)] = 0.0;
+    srow[strip_spos(1)] = 0.0;  // S(-1)
+  }
+  double C[kLsBlock][CPT];
 #pragma unroll
-    for (int j = 0; j < 2; ++j) {
-      f[j] = 0.f;
-      y[j] = 0.f;
-      if (col_ok[j] && q >= 0 && q < p.H) {
-        const int64_t i = (int64_t)q * st.pitch + gcs[j];
-        f[j] = Fin[i];
-        y[j] = st.Y[i];
-      }
+  for (int k = 0; k < kLsBlock; ++k)
+#pragma unroll
+    for (int j = 0; j < CPT; ++j) C[k][j] = 0.0;
+  // clamped (always in bounds) load addresses; samples off the image read 0
+#pragma unroll
+  for (int j = 0; j < CPT; ++j) gcs[j] = min(max(gcs[j], 0), p.Wd - 1);
+  auto load_row = [&](int q, float (&f)[CPT], float (&y)[CPT]) {
+    const bool in_rows = p.mirror || (q >= 0 && q < p.H);
+    q = p.mirror ? reflect_index(q, p.H) : min(max(q, 0), p.H - 1);
+#pragma unroll
+    for (int j = 0; j < CPT; ++j) {
+      const int64_t i = (int64_t)q * st.pitch + gcs[j];
+      const float fv = Fin[i], yv = st.Y[i];
+      const bool ok = col_ok[j] && in_rows;
+      f[j] = ok ? fv : 0.f;
+      y[j] = ok ? yv : 0.f;
     }
   };
+  // warm-up: the window of rows r_lo - W .. r_lo + W
   for (int q = r_lo - W; q <= r_lo + W; ++q) {
-    float f[2], y[2];
+    float f[CPT], y[CPT];
     load_row(q, f, y);
 #pragma unroll
-    for (int k = 0; k < kLsBlock; ++k)
-      if (k < K) {
-#pragma unroll
-        for (int j = 0; j < 2; ++j) {
-          C[k][j] += (double)f[j];
-          f[j] *= y[j];
-        }
-      }
-#pragma unroll
-    for (int j = 0; j < 2; ++j)
-      if (central[j] && q >= r_lo && q < r_hi) Fout[(int64_t)q * st.pitch + pio[j]] = f[j];
-  }
-  for (int r = r_lo; r < r_hi; ++r) {
-#pragma unroll
-    for (int k = 0; k < kLsBlock; ++k)
-      if (k < K) *(double2*)(Cs + k * kStrip2Pitch + sw2(2 * t)) = make_double2(C[k][0], C[k][1]);
-    float fe[2], ye[2], fl[2], yl[2];  // rows entering and leaving after this output row
-    load_row(r + W + 1, fe, ye);
-    load_row(r - W, fl, yl);
-    lds_barrier();
-    // per order: float64 prefix over the 512 strip columns (lane l scans
-    // columns 8l .. 8l + 7, a DPP wave scan joins the lanes), then the window
-    // sums S(c + 2W + 1) - S(c) of the OC output columns; wave w takes orders
-    // w, w + 4, w + 8, w + 12
-#pragma unroll
-    for (int jj = 0; jj < kLsBlock / 4; ++jj) {
-      double* row = Cs + (wv + 4 * jj) * kStrip2Pitch;
-      double x[8];
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const double2 v2 = *(const double2*)(row + sw2(8 * lane) + 2 * u);
-        x[2 * u] = v2.x;
-        x[2 * u + 1] = v2.y;
-      }
-      double pre[8];
-      pre[0] = 0.0;
-#pragma unroll
-      for (int u = 1; u < 8; ++u) pre[u] = pre[u - 1] + x[u - 1];
-      const double tot = pre[7] + x[7];
-      const double incl = wave_scan_incl(tot);
-      const double ex = incl - tot;
-#pragma unroll
-      for (int u = 0; u < 4; ++u)
-        *(double2*)(row + sw2(8 * lane) + 2 * u) = make_double2(ex + pre[2 * u], ex + pre[2 * u + 1]);
-      if (lane == 63) row[sw2(kStrip2Cols)] = incl;
-      float ov[8];
-#pragma unroll
-      for (int i = 0; i < 8; ++i) {
-        const int c = lane + 64 * i;
-        ov[i] = (float)(row[sw2(min(c + L, kStrip2Cols))] - row[sw2(c)]);
-      }
-      // all of the wave's reads of S precede these writes into the same row
-      float* o = (float*)row;
-#pragma unroll
-      for (int i = 0; i < 8; ++i)
-        if (lane + 64 * i < OC) o[lane + 64 * i] = ov[i];
-    }
-    lds_barrier();
-    // this thread's pixels: output columns 2t + j - W
-    float v[kLsBlock][2];
-#pragma unroll
-    for (int k = 0; k < kLsBlock; ++k)
-#pragma unroll
-      for (int j = 0; j < 2; ++j) v[k][j] = pix[j] ? ((const float*)(Cs + k * kStrip2Pitch))[2 * t + j - W] : 0.f;
-    lds_barrier();
-#pragma unroll
-    for (int j = 0; j < 2; ++j) {
-      if (!pix[j]) continue;
-      const int64_t pi = (int64_t)r * p.Wd + pio[j];
-      float a = st.a[pi], ap = st.ap[pi];
-      const float z = st.z[pi];
-      double P = st.P[pi], Q = st.Q[pi];
-      float p32 = 0.f, q32 = 0.f;
+    for (int j = 0; j < CPT; ++j) {
+      double fd = (double)f[j];
+      const double yd = (double)y[j];
 #pragma unroll
       for (int k = 0; k < kLsBlock; ++k) {
-        if (k < K) {
-          const int n = n0 + k;
-          if (n < p.N) q32 = fmaf(a, v[k][j], q32);
-          if (n >= 1) p32 = fmaf(ap, v[k][j], p32);
-          ap = a;
-          a *= z * in1[k];
+        C[k][j] += fd;
+        fd *= yd;
+      }
+      if (central[j] && q >= r_lo && q < r_hi) Fout[(int64_t)q * st.pitch + gcol[j]] = (float)fd;
+    }
+  }
+  for (int r = r_lo; r < r_hi; ++r) {
+    // column sums of row r into LDS
+#pragma unroll
+    for (int k = 0; k < kLsBlock; ++k) {
+      float* row = Cb + k * G::CPITCH + strip_cpos(CPT * t);
+#pragma unroll
+      for (int j = 0; j < CPT; ++j) row[j] = (float)C[k][j];
+    }
+    // rows entering and leaving after this one, and this row's pixel state
+    float fe[CPT], ye[CPT], fl[CPT], yl[CPT];
+    load_row(r + W + 1, fe, ye);
+    load_row(r - W, fl, yl);
+    float a[CPT], ap[CPT], app[CPT], z[CPT];
+    double P[CPT], Q[CPT], DP[CPT], DQ[CPT];
+#pragma unroll
+    for (int j = 0; j < CPT; ++j) {  // non-output columns read pixel (r, 0) and store nothing
+      const int64_t pi = (int64_t)r * p.Wd + (central[j] ? gcol[j] : 0);
+      a[j] = st.a[pi];
+      ap[j] = st.ap[pi];
+      z[j] = st.z[pi];
+      P[j] = st.P[pi];
+      Q[j] = st.Q[pi];
+      if (SAVE) {
+        app[j] = st.app[pi];
+        DP[j] = st.DP[pi];
+        DQ[j] = st.DQ[pi];
+      }
+    }
+    lds_barrier();
+    // row windows of orders wv, wv + 4, wv + 8, wv + 12
+#pragma unroll
+    for (int jj = 0; jj < kLsBlock / 4; ++jj) {
+      float* crow = Cb + (wv + 4 * jj) * G::CPITCH;
+      float x[CPL];
+#pragma unroll
+      for (int u = 0; u < CPL; u += 4) {
+        const float4 v4 = *(const float4*)(crow + strip_cpos(CPL * lane + u));
+        x[u] = v4.x;
+        x[u + 1] = v4.y;
+        x[u + 2] = v4.z;
+        x[u + 3] = v4.w;
+      }
+      double pre[CPL];
+      pre[0] = (double)x[0];
+#pragma unroll
+      for (int u = 1; u < CPL; ++u) pre[u] = pre[u - 1] + (double)x[u];
+      const double incl = wave_scan_incl(pre[CPL - 1]);
+      const double ex = incl - pre[CPL - 1];
+#pragma unroll
+      for (int u = 0; u < CPL; u += 2)
+        *(double2*)(srow + strip_spos(CPL * lane + 2 + u)) = make_double2(ex + pre[u], ex + pre[u + 1]);
+      // window sums of the columns c = lane + 64 i (this wave's prefix row,
+      // written above by its own lanes); the slots are clamped, so columns
+      // within W of the strip edge get values that no output reads
+#pragma unroll
+      for (int i = 0; i < SC / 64; ++i) {
+        const int c = lane + 64 * i;
+        crow[strip_cpos(c)] = (float)(srow[strip_spos(min(c + W + 2, SC + 1))] - srow[strip_spos(max(c - W + 1, 1))]);
+      }
+    }
+    lds_barrier();
+    // fold this thread's output pixels: float64 products and sums (the terms
+    // of eqs. (P), (Q) cancel heavily at small sigma_r; float32 partial sums
+    // cost about 5e-4 there); a_n advances in float32
+#pragma unroll
+    for (int j = 0; j < CPT; ++j) {
+      double ad = (double)a[j], apd = (double)ap[j], appd = SAVE ? (double)app[j] : 0.0;
+      float af = a[j];
+#pragma unroll
+      for (int k = 0; k < kLsBlock; ++k) {
+        const double vd = (double)Cb[k * G::CPITCH + strip_cpos(CPT * t) + j];
+        Q[j] = fma(ad, vd, Q[j]);
+        P[j] = fma(apd, vd, P[j]);
+        if (SAVE) {
+          DQ[j] = fma((double)(ap[j] * dqm[k]), vd, DQ[j]);
+          DP[j] = fma((double)(app[j] * dpm[k]), vd, DP[j]);
+          app[j] = ap[j];
+          appd = apd;
         }
-        if ((k & 7) == 7) {
-          Q += (double)q32;
-          P += (double)p32;
-          q32 = p32 = 0.f;
+        ap[j] = af;
+        apd = ad;
+        af *= z[j] * in1[k];
+        ad = (double)af;
+      }
+      if (central[j]) {
+        const int64_t pi = (int64_t)r * p.Wd + gcol[j];
+        st.a[pi] = af;
+        st.ap[pi] = ap[j];
+        st.P[pi] = P[j];
+        st.Q[pi] = Q[j];
+        if (SAVE) {
+          st.app[pi] = app[j];
+          st.DP[pi] = DP[j];
+          st.DQ[pi] = DQ[j];
         }
       }
-      st.a[pi] = a;
-      st.ap[pi] = ap;
-      st.P[pi] = P;
-      st.Q[pi] = Q;
     }
     // slide the window to r + 1
-#pragma unroll
-    for (int k = 0; k < kLsBlock; ++k)
-      if (k < K) {
-#pragma unroll
-        for (int j = 0; j < 2; ++j) {
-          C[k][j] += (double)fe[j] - (double)fl[j];
-          fe[j] *= ye[j];
-          fl[j] *= yl[j];
-        }
-      }
     const int qe = r + W + 1;
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
-      if (central[j] && qe >= r_lo && qe < r_hi) Fout[(int64_t)qe * st.pitch + pio[j]] = fe[j];
+    for (int j = 0; j < CPT; ++j) {
+      double fed = (double)fe[j], fld = (double)fl[j];
+      const double yed = (double)ye[j], yld = (double)yl[j];
+#pragma unroll
+      for (int k = 0; k < kLsBlock; ++k) {
+        C[k][j] = (C[k][j] + fed) - fld;
+        fed *= yed;
+        fld *= yld;
+      }
+      if (central[j] && qe >= r_lo && qe < r_hi) Fout[(int64_t)qe * st.pitch + gcol[j]] = (float)fed;
+    }
   }
 }
 
-int64_t ls_box_strip2_lds_bytes() { return (int64_t)kLsBlock * kStrip2Pitch * 8; }
+template <int CPT>
+int64_t ls_box_strip_lds_bytes() { return StripGeom<CPT>::LDS_BYTES; }
 
-bool ls_box_strip2_supported(int W) { return strip2_cols(W) >= 128; }
+bool ls_box_strip_supported(int W) { return 256 - 2 * W >= 64; }
 
-int64_t ls_box_strip_lds_bytes() { return (int64_t)kLsBlock * kStripPitch * 8; }
-
-bool ls_box_strip_supported(int W) { return strip_cols(W) >= 64; }
+// Shape of the box strips on an H x Wd image: the 512-column form for the
+// plain forward from W = 48 (its halo is shared by more outputs, at two
+// resident workgroups per compute unit; 4096^2, sigma_r = 10: W = 75 10.8 ms
+// against 13.4 for the 256-column form, W = 30 8.1 against 7.6), else 256
+// columns (three resident workgroups; two with the saved state, whose sums
+// need more registers).  Row segments: one wave of resident workgroups, so
+// none trails; each pays a 2W + 1 row warm-up.
+StripShape ls_box_strip_shape(int H, int Wd, int W, bool save) {
+  StripShape sh;
+  sh.cpt = (!save && W >= 48) ? 2 : 1;
+  const int resident = (sh.cpt == 2 || save) ? 2 : 3;
+  sh.oc = 256 * sh.cpt - 2 * W;
+  const int nstrips = (Wd + sh.oc - 1) / sh.oc;
+  const int nseg = std::max(1, std::min((H + 31) / 32, num_cus() * resident / nstrips));
+  sh.seg_rows = (H + nseg - 1) / nseg;
+  sh.grid = nstrips * ((H + sh.seg_rows - 1) / sh.seg_rows);
+  sh.lds = sh.cpt == 2 ? ls_box_strip_lds_bytes<2>() : ls_box_strip_lds_bytes<1>();
+  return sh;
+}
 
 // The streamed kernels that implement the mirror border: box strips, and the
 // matrix-core row and column passes of the Gaussian.
@@ -875,35 +817,14 @@ hipError_t launch_forward_ls(const TileParams& p, const LsState& st, bool save, 
   const int gfir16 = ((p.H + 63) / 64) * tiles_x;
   const size_t fl8 = (size_t)(32 + 2 * p.W) * kLsColPitch * 4;
   const size_t fl16 = (size_t)(64 + 2 * p.W) * kLsColPitch * 4;
-  // box: column strips (running float64 column sums, prefix-sum row windows)
+  // box: column strips (float64 running column sums, float64 prefix-sum row windows)
   const bool box_strip = p.kt == BF_BOX && ls_box_strip_supported(p.W);
-  const int nstrips = box_strip ? (p.Wd + strip_cols(p.W) - 1) / strip_cols(p.W) : 1;
-  // segments: one wave of workgroups (as many as fit on the chip at once, so
-  // none trails); each segment pays a 2W + 1 row warm-up
-  const int slots = num_cus() * (int)std::max<int64_t>(1, max_lds_bytes() / ls_box_strip_lds_bytes());
-  const int nseg = std::max(1, std::min((p.H + 31) / 32, slots / nstrips));
-  const int strip_seg = (p.H + nseg - 1) / nseg;
-  const int gstrip = nstrips * ((p.H + strip_seg - 1) / strip_seg);
-  // forward without saved state and W >= 56: the 512-column strips (the halo
-  // is shared by more outputs, at half the occupancy; 4096^2, sigma_r = 10:
-  // W = 75 15.7 -> 14.4 ms, W = 30 9.3 -> 10.9 ms, crossover near W = 54)
-  const bool strip2 = box_strip && !save && p.W >= 56 && ls_box_strip2_supported(p.W);
-  const int nstrips2 = strip2 ? (p.Wd + strip2_cols(p.W) - 1) / strip2_cols(p.W) : 1;
-  const int slots2 = num_cus() * (int)std::max<int64_t>(1, max_lds_bytes() / ls_box_strip2_lds_bytes());
-  const int nseg2 = std::max(1, std::min((p.H + 31) / 32, slots2 / nstrips2));
-  const int strip2_seg = (p.H + nseg2 - 1) / nseg2;
-  const int gstrip2 = nstrips2 * ((p.H + strip2_seg - 1) / strip2_seg);
-  if (strip2) {
-    e = hipFuncSetAttribute((const void*)ls_box_strip2_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)ls_box_strip2_lds_bytes());
-    if (e != hipSuccess) return e;
-  }
+  const StripShape sh = box_strip ? ls_box_strip_shape(p.H, p.Wd, p.W, save) : StripShape{};
+  const void* strip_kern = nullptr;
   if (box_strip) {
-    e = hipFuncSetAttribute((const void*)ls_box_strip_kernel<false>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)ls_box_strip_lds_bytes());
-    if (e == hipSuccess)
-      e = hipFuncSetAttribute((const void*)ls_box_strip_kernel<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              (int)ls_box_strip_lds_bytes());
+    strip_kern = sh.cpt == 2 ? (save ? (const void*)ls_box_strip_kernel<2, true> : (const void*)ls_box_strip_kernel<2, false>)
+                             : (save ? (const void*)ls_box_strip_kernel<1, true> : (const void*)ls_box_strip_kernel<1, false>);
+    e = hipFuncSetAttribute(strip_kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh.lds);
     if (e != hipSuccess) return e;
   }
   // Gaussian: FIR passes on the matrix cores where the staged windows fit
@@ -938,22 +859,12 @@ hipError_t launch_forward_ls(const TileParams& p, const LsState& st, bool save, 
   int src = 0;
   for (int n0 = 0; n0 <= p.N; n0 += kLsBlock) {
     const int K = std::min(kLsBlock, p.N + 1 - n0);
-    if (strip2) {
-      hipLaunchKernelGGL(ls_box_strip2_kernel, dim3(gstrip2), dim3(kStripThreads), (size_t)ls_box_strip2_lds_bytes(),
-                         s, p, st, n0, K, src, strip2_seg);
-      e = hipGetLastError();
-      if (e != hipSuccess) return e;
-      src ^= 1;
-      continue;
-    }
     if (box_strip) {
-      if (save)
-        hipLaunchKernelGGL((ls_box_strip_kernel<true>), dim3(gstrip), dim3(kStripThreads), (size_t)ls_box_strip_lds_bytes(),
-                           s, p, st, n0, K, src, strip_seg);
-      else
-        hipLaunchKernelGGL((ls_box_strip_kernel<false>), dim3(gstrip), dim3(kStripThreads), (size_t)ls_box_strip_lds_bytes(),
-                           s, p, st, n0, K, src, strip_seg);
-      e = hipGetLastError();
+      int n0v = n0, srcv = src, segv = sh.seg_rows;
+      TileParams pv = p;
+      LsState sv = st;
+      void* args[] = {(void*)&pv, (void*)&sv, (void*)&n0v, (void*)&srcv, (void*)&segv};
+      e = hipLaunchKernel(strip_kern, dim3(sh.grid), dim3(kStripThreads), args, (size_t)sh.lds, s);
       if (e != hipSuccess) return e;
       src ^= 1;
       continue;

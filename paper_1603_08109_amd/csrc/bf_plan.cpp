@@ -627,6 +627,11 @@ int bf_plan(const bf_params* in, bf_plan_t** out) {
   pl->info.path = fpath.engine;
   pl->info.tile_rows = TY;
   pl->info.tile_cols = (ls || fpath.engine == BF_PATH_RECURSIVE) ? 0 : fpath.engine == BF_PATH_TILE_MFMA ? 64 : kTileCols;
+  if (ls && !wide && p.kernel == BF_BOX && ls_box_strip_supported(p.W)) {
+    const StripShape sh = ls_box_strip_shape(p.height, p.width, p.W, false);
+    pl->info.tile_rows = sh.seg_rows;
+    pl->info.tile_cols = sh.oc;
+  }
   pl->mfma = fpath.engine == BF_PATH_TILE_MFMA;
   pl->rec = fpath.engine == BF_PATH_RECURSIVE;
   pl->wide = wide;

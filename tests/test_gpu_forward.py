@@ -119,7 +119,7 @@ def test_ragged_and_tiny_wide_gaussian(shape):
     f = synthimg.gen1(*shape, 33)
     for ss in (6.0, 15.0):
         out, plan, f32 = _gpu_forward(f, "gauss", 25.0, sigma_s=ss)
-        assert plan.info.tile_rows == 0, (ss, shape)
+        assert plan.info.path == 1, (ss, shape)  # streamed
         w1, _ = _taps("gauss", dict(sigma_s=ss))
         ref = G.gpa_alg2(f32, w1, 25.0, plan.info.N, 127.5)
         assert np.abs(out - ref).max() <= TOL, (ss, shape)
@@ -184,7 +184,7 @@ def test_explicit_order_and_rules():
 def test_large_support(kind, kw, sr, shape):
     f = synthimg.gen2(*shape, 77)
     out, plan, f32 = _gpu_forward(f, kind, sr, **kw)
-    assert plan.info.tile_rows == 0  # streamed path
+    assert plan.info.path == 1  # streamed path
     kw = {k: v for k, v in kw.items() if k != "streamed"}
     w1, _ = _taps(kind, kw)
     ref = G.gpa_alg2(f32, w1, sr, plan.info.N, 127.5)
@@ -202,7 +202,7 @@ def test_streamed_matches_fused(kind, kw, sr):
     ps = P.Plan(kind, sr, 150, 210, streamed=True, **kw)
     b = ps.forward(x)
     torch.cuda.synchronize()
-    assert ps.info.tile_rows == 0
+    assert ps.info.path == 1
     assert (a - b).abs().max().item() <= 1e-4
     w1, _ = _taps(kind, kw)
     ref = G.gpa_alg2(x.cpu().numpy().astype(np.float64), w1, sr, ps.info.N, 127.5)
@@ -234,7 +234,7 @@ def test_streamed_saved_state_matches_fused(kind, kw, sr):
     x = torch.tensor(f, dtype=torch.float32, device="cuda")
     pf = P.Plan(kind, sr, 140, 200, grad=True, **kw)
     ps = P.Plan(kind, sr, 140, 200, grad=True, streamed=True, **kw)
-    assert ps.info.tile_rows == 0 and pf.info.tile_rows > 0
+    assert ps.info.path == 1 and pf.info.path == 0
     sf, ss = pf.new_saved(), ps.new_saved()
     a = pf.forward(x, saved=sf)
     b = ps.forward(x, saved=ss)
@@ -269,9 +269,9 @@ def test_clone_workspace_on_two_streams():
 @pytest.mark.parametrize("W,sr,shape", [(16, 10.0, (150, 700)), (56, 30.0, (120, 1100)), (75, 20.0, (90, 900)),
                                         (190, 30.0, (60, 500))])
 def test_box_strip_widths_agree(W, sr, shape):
-    # the forward-only strips (512 columns from W = 56, float32 partial sums
-    # flushed every 8 orders) against the 256-column strips that also write the
-    # saved state, and both against the oracle; several strips, a ragged last one
+    # the forward-only strips (512 columns from W = 48) against the
+    # 256-column strips that also write the saved state, and both against the
+    # oracle; several strips, a ragged last one
     torch, P = _mods()
     f = synthimg.gen2(*shape, 80 + W)
     x = torch.tensor(f, dtype=torch.float32, device="cuda")

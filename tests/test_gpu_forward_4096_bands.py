@@ -4,8 +4,8 @@ bands that cross the seams of each engine's work decomposition.
 Each engine that the planner picks at 4096^2 is checked on its own shape:
   * the fused tile on the vector ALUs (Gaussian sigma_s = 3 and box W = 10):
     tiles of 64 columns x tile_rows rows;
-  * the box column strips (256 columns, W = 30) and the wide strips (512
-    columns, W = 75), cut into row segments;
+  * the box column strips (256 columns at W = 30, 512 columns at W = 75),
+    cut into row segments (the plan reports both);
   * the split-bfloat16 row pass with the float32 matrix-core column pass
     (Gaussian sigma_s = 10) and with the split column pass (sigma_s = 25):
     16 x 256 row tiles, 64 x 64 column tiles.
@@ -36,24 +36,11 @@ def _image():
     return synthimg.gen2(H, Wd, 3000)
 
 
-def _strip_segment_rows(W):
-    """Row-segment length of the box column strips at 4096^2 (256 compute units,
-    160 KiB of LDS per unit): segments fill one wave of resident workgroups."""
-    lds = 160 * 1024
-    if W >= 56:
-        oc, per = 512 - 2 * W, 16 * 548 * 8
-    else:
-        oc, per = 256 - 2 * W, 16 * 276 * 8
-    nstrips = -(-Wd // oc)
-    nseg = max(1, min((H + 31) // 32, (256 * max(1, lds // per)) // nstrips))
-    return -(-H // nseg), oc
-
-
-def _bands(kind, W, tile_rows):
-    if tile_rows > 0:  # fused tile: seam between the first two tile rows, full width
-        seam_r, seam_c = tile_rows, 64
-    elif kind == "box":
-        seam_r, seam_c = _strip_segment_rows(W)
+def _bands(kind, W, info):
+    if info.path == 0:  # fused tile: seam between the first two tile rows, full width
+        seam_r, seam_c = info.tile_rows, 64
+    elif kind == "box":  # column strips: row segments and output columns per strip, as the plan reports them
+        seam_r, seam_c = info.tile_rows, info.tile_cols
     else:  # streamed Gaussian: 16-row row-pass tiles, 64-row column-pass tiles
         seam_r, seam_c = 64, 256
     # narrow supports: full-width bands; wide ones: 3+ column seams (cost)
@@ -82,15 +69,18 @@ def test_band_parity_4096(kind, kw, sr, engine):
     x = torch.tensor(f, dtype=torch.float32, device="cuda")
     plan = P.Plan(kind, sr, H, Wd, **kw)
     W, N = plan.info.W, plan.info.N
-    print(f"# {kind} {kw} sigma_r={sr} W={W} N={N} tile_rows={plan.info.tile_rows}", flush=True)
-    assert (plan.info.tile_rows > 0) == (engine == "tile")
+    print(f"# {kind} {kw} sigma_r={sr} W={W} N={N} path={plan.info.path} tile_rows={plan.info.tile_rows} "
+          f"tile_cols={plan.info.tile_cols}", flush=True)
+    assert (plan.info.path == 0) == (engine == "tile")
+    if kind == "box" and engine == "streamed":  # the strip decomposition is reported
+        assert plan.info.tile_rows > 0 and plan.info.tile_cols == (512 if W >= 48 else 256) - 2 * W
     out = plan.forward(x)
     torch.cuda.synchronize()
     out = out.cpu().numpy().astype(np.float64)
     del x
     f32 = np.asarray(f, np.float32).astype(np.float64)
     w1 = K.taps1d(kind, kw.get("sigma_s"), kw.get("W"))
-    for (r0, r1, c0, c1) in _bands(kind, W, plan.info.tile_rows):
+    for (r0, r1, c0, c1) in _bands(kind, W, plan.info):
         R0, R1, C0, C1 = max(0, r0 - W), min(H, r1 + W), max(0, c0 - W), min(Wd, c1 + W)
         ref = G.gpa_alg2(f32[R0:R1, C0:C1], w1, sr, N, 127.5)[r0 - R0:r1 - R0, c0 - C0:c1 - C0]
         d = out[r0:r1, c0:c1] - ref

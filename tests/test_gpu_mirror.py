@@ -43,7 +43,7 @@ def _run(f, kind, sr, **kw):
 def test_fused_mirror(kind, kw, sr, shape):
     f = synthimg.gen2(*shape, 61)
     out, plan, f32 = _run(f, kind, sr, **kw)
-    assert plan.info.tile_rows > 0
+    assert plan.info.path == 0
     ref = M.gpa_alg2(f32, _w1(kind, kw), sr, plan.info.N, 127.5)
     print(f"{kind} {kw} {shape}: max {np.abs(out - ref).max():.3e}", flush=True)
     assert np.abs(out - ref).max() <= TOL
@@ -55,7 +55,7 @@ def test_fused_mirror(kind, kw, sr, shape):
 def test_streamed_mirror(kind, kw, sr, shape):
     f = synthimg.gen2(*shape, 62)
     out, plan, f32 = _run(f, kind, sr, streamed=True, **kw)
-    assert plan.info.tile_rows == 0
+    assert plan.info.path == 1
     ref = M.gpa_alg2(f32, _w1(kind, kw), sr, plan.info.N, 127.5)
     print(f"{kind} {kw} {shape}: max {np.abs(out - ref).max():.3e}", flush=True)
     assert np.abs(out - ref).max() <= TOL
