@@ -145,7 +145,7 @@ def engine_of(kind, W, info):
         return "fused_valu_tile"
     if kind == "box":
         return f"box_strips_{info.tile_cols + 2 * W}"
-    return "rows_x3+cols_x3" if W >= SPLIT_MIN_W else "rows_x3+cols_mfma"
+    return "rows_x3+cols_x3s" if W >= SPLIT_MIN_W else "rows_x3+cols_mfma"
 
 
 def seams(kind, W, info):
@@ -165,7 +165,7 @@ def setting_roof(kind, W, N, ms, info, H, Wd):
     achieved = flops / (ms * 1e-3) / 1e12
     eng = engine_of(kind, W, info)
     extra = {}
-    if eng == "rows_x3+cols_x3":
+    if eng == "rows_x3+cols_x3s":
         # the FIR products run as split-BF16 matrix-core products: priced at the
         # FP32-product ceiling of that arithmetic, with the FP32 matrix-core ratio beside
         bound, peak = "mfma", MFMA_BF16_PEAK_TFLOPS / SPLIT_PRODUCTS

@@ -874,7 +874,14 @@ hipError_t launch_forward_ls(const TileParams& p, const LsState& st, bool save, 
       // ms per call, rows+cols float32 / split rows / both split: W = 30 4.40 / 4.00 /
       // 4.14, W = 51 5.82 / 4.95 / 4.78, W = 75 7.40 / 6.09 / 5.93)
       e = launch_rows_x3(p, st, n0, K, src, grow, s);
-      if (e == hipSuccess) {
+      // from W = 40 the column pass splits its window once per workgroup
+      // (ls_cols_x3s) where its registers allow (up to 6 k-steps, plain
+      // forward); 4096^2, sigma_r = 10, W = 75: 25.1 -> 23.6 ms per call.  Below
+      // W = 40 the float32 matrix-core column pass stays faster.
+      const bool x3s = !save && p.W >= 40 && (16 + 2 * p.W + 31) / 32 <= 6 && st.hbytes < (1LL << 31);
+      if (e == hipSuccess && x3s) {
+        e = launch_cols_x3s(p, st, n0, K, false, s);
+      } else if (e == hipSuccess) {
         if (p.W >= 40) {
           e = launch_cols_x3(p, st, n0, K, save, gfir16, s);
         } else {
