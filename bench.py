@@ -58,6 +58,7 @@ FWD_BWD_4096 = [("gauss", dict(sigma_s=3.0), 30.0), ("gauss", dict(sigma_s=3.0),
                 ("gauss", dict(sigma_s=25.0), 30.0), ("gauss", dict(sigma_s=25.0), 10.0),
                 ("box", dict(W=75), 30.0), ("box", dict(W=75), 10.0)]
 GRAD_PATCH = 32  # the fwd+bwd accuracy check: output gradient on one corner patch
+EXTRA_LEGS = ("fwd_bwd_4096", "fwd_bwd", "batch", "joint", "recursive", "wide_range", "volume")
 
 
 def setting_name(kind, kw, sr):
@@ -251,7 +252,7 @@ def summarize(dirpath, sweep_settings):
              PROFILE_RUNS["trace"], "python3 bench.py --summarize DIR", "```", "",
              f"Each setting runs {per_call} forward calls (1 warm-up + 2 timed). A call is one fused "
              "`gpa_forward_kernel` launch, or the streamed sequence `ls_init`, per block of 16 orders "
-             "(`ls_rows_x3` + `ls_cols_x3` for the Gaussian from W = 40, `ls_rows_x3` + `ls_cols_mfma` below, "
+             "(`ls_rows_x3` + `ls_cols_x3s` for the Gaussian from W = 40, `ls_rows_x3` + `ls_cols_mfma` below, "
              "`ls_box_strip` for the box), `ls_final`.",
              "", "| kernel | calls | total ms | avg us | % |", "|---|---|---|---|---|"]
     for k, v in sorted(per_kernel.items(), key=lambda kv: -sum(kv[1])):
@@ -332,6 +333,15 @@ def _cpu_task(args):
 
 
 def cpu_model():
+    """The host CPU model as `lscpu` prints it (else /proc/cpuinfo's model name)."""
+    import subprocess
+    try:
+        r = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10)
+        for line in r.stdout.splitlines():
+            if line.strip().lower().startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except (OSError, subprocess.SubprocessError):
+        pass
     try:
         with open("/proc/cpuinfo") as fh:
             for line in fh:
@@ -441,12 +451,18 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true", help="skip every leg but the sweep")
+    ap.add_argument("--legs", default=",".join(EXTRA_LEGS),
+                    help="comma list of the extra legs to run (default: all of " + ", ".join(EXTRA_LEGS) + ")")
     ap.add_argument("--only", default="", help="comma list of sweep indices to run")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (counter calibration)")
     ap.add_argument("--summarize", default="", metavar="DIR",
                     help="write profiles/ summaries from the rocprofv3 outputs of PROFILE_RUNS in DIR")
     a = ap.parse_args()
+    legs = set() if a.no_extra else {l for l in a.legs.split(",") if l}
+    unknown = legs - set(EXTRA_LEGS)
+    if unknown:
+        raise SystemExit(f"bench.py: unknown legs {sorted(unknown)}; known: {', '.join(EXTRA_LEGS)}")
     if a.summarize:
         summarize(a.summarize, [setting_name(k, kw, sr) for k, kw, sr in SWEEP])
         return
@@ -535,7 +551,7 @@ def main():
 
     extra = {}
     fb_checks = []
-    if not a.no_extra:
+    if "fwd_bwd_4096" in legs:
         # fwd+bwd on the sweep image: forward keeping its state, then the adjoint with both sigma
         # gradients; loss = MSE against the noise-free image
         clean = torch.tensor(synthimg.clean2(H, Wd, 3000), dtype=torch.float32, device=dev)
@@ -584,6 +600,7 @@ def main():
                                  "per_setting": fbl}
         del clean
 
+    if "fwd_bwd" in legs:
         # differentiable workload: 32 x 512^2, Gaussian sigma_s = 5, sigma_r = 30
         imgs = [torch.tensor(synthimg.gen1(512, 512, 5000 + b), dtype=torch.float32, device=dev)
                 for b in range(32)]
@@ -687,6 +704,7 @@ def main():
         print(f"# fwd_bwd {extra['fwd_bwd']}", file=sys.stderr, flush=True)
         del imgs, tgts, saved, outs, gins, bgins, ref_gins, gbatch, bsaved, wbatch, plan10, gw
 
+    if "batch" in legs:
         # batched workload: 256 uneven images, one graph launch vs per-image launches
         specs = synthimg.batch_params(256, 4000)
         per = [dict(kernel="gauss", sigma_s=s["sigma_s"], sigma_r=s["sigma_r"], height=s["height"],
@@ -723,6 +741,7 @@ def main():
         print(f"# batch {extra['batch']}", file=sys.stderr, flush=True)
         del bimgs, bouts, batch, plans4
 
+    if "joint" in legs:
         # cross (joint) filter on the sweep image with a second synthetic image as guide
         guide = torch.tensor(synthimg.gen1(H, Wd, 3100), dtype=torch.float32, device=dev)
         jl = {}
@@ -736,6 +755,7 @@ def main():
         print(f"# joint {extra['joint']}", file=sys.stderr, flush=True)
         del guide
 
+    if "recursive" in legs:
         # recursive (Deriche) Gaussian: cost flat in sigma_s, next to the exact FIR of the sweep
         rl = {}
         for ss, sr in [(3.0, 30.0), (10.0, 30.0), (25.0, 30.0), (25.0, 10.0), (60.0, 30.0)]:
@@ -748,6 +768,7 @@ def main():
                               "per_setting": rl}
         print(f"# recursive {extra['recursive']}", file=sys.stderr, flush=True)
 
+    if "wide_range" in legs:
         # wide range (T / sigma_r above 13): the streamed Gaussian with float64 per-pixel states
         wl = {}
         for ss, sr in [(3.0, 8.0), (3.0, 5.0), (25.0, 5.0), (25.0, 3.5)]:
@@ -760,6 +781,7 @@ def main():
                                "per_setting": wl}
         print(f"# wide_range {extra['wide_range']}", file=sys.stderr, flush=True)
 
+    if "volume" in legs:
         # video/volume extension: 64 frames of 1024^2 (67 Mvoxels), box W = 3 and Gaussian sigma_s = 1.5
         vd, vh, vw = 64, 1024, 1024
         vx = torch.tensor(np.stack([synthimg.gen2(vh, vw, 3200 + d) for d in range(vd)]), dtype=torch.float32,
