@@ -290,9 +290,11 @@ struct Accum<false> {
   __device__ __forceinline__ double value() const { return (double)part; }
 };
 
-template <int KT, int OPT, int MREG, bool ACC64, bool SAVE>
+template <int KT, int OPT, int MREG, bool ACC64, bool SAVE, int WC = 0>
 __device__ __forceinline__ void forward_tile(const TileParams& p, int r0, int c0, float* lds) {
-  const int W = p.W;
+  // WC > 0: the support is a compile-time constant (the FIR and box loops
+  // unroll completely and the taps stay in scalar registers across orders)
+  const int W = WC > 0 ? WC : p.W;
   const int N = p.N;
   const RegionGeom g = region_geom(4 * OPT, W);
   float* Fs = lds;

@@ -139,6 +139,9 @@ inline int64_t region_floats_bwd(int TY, int W) {
 // Launchers (bf_kernels.hip).  Return hipError_t.
 hipError_t launch_forward(const TileParams& p, int variant, bool acc64, bool save,
                           hipStream_t s);
+// the plain fused forward compiled for a fixed support W = 1 .. 21 (bf_fused_w.hip)
+bool fixed_w_available(int W, int variant);
+hipError_t launch_forward_fixed_w(const TileParams& p, hipStream_t s);
 hipError_t launch_backward(const TileParams& p, int variant, bool sigs, double* partials,
                            double* grad_sigma, hipStream_t s);
 hipError_t launch_joint(const TileParams& p, int variant, hipStream_t s);
