@@ -78,11 +78,9 @@ extern "C" {
                                    Gaussian W <= 124; with BF_FLAG_GRAD the adjoint runs on
                                    the image extended by W on each side (see bf_backward) */
 #define BF_FLAG_TILE_VALU   32  /* force the fused tile on the vector ALUs (the planner's
-                                   choice otherwise); BF_EUNSUPPORTED if W does not fit */
-#define BF_FLAG_TILE_MFMA   64  /* force the fused 64 x 64 tile with both FIR passes on the
-                                   matrix cores (Gaussian, W <= 45, float64 sums whatever
-                                   BF_FLAG_FP32_ACCUM says); at most one of STREAMED,
-                                   TILE_VALU, TILE_MFMA may be set */
+                                   choice otherwise); BF_EUNSUPPORTED if W does not fit; not
+                                   together with BF_FLAG_STREAMED (BF_EINVAL).  Other flag bits
+                                   than the BF_FLAG_* here return BF_EINVAL. */
 #define BF_FLAG_MFMA_FP32  128  /* streamed Gaussian passes: plain float32 matrix-core products
                                    instead of float32 emulated by three-way bfloat16 splits
                                    (six bf16 products per float32 product, about 2.3x fewer
@@ -91,7 +89,6 @@ extern "C" {
 /* forward engines (bf_plan_info.path) */
 #define BF_PATH_TILE       0  /* one fused launch, tile on the vector ALUs */
 #define BF_PATH_STREAMED   1  /* blocks of orders through device memory */
-#define BF_PATH_TILE_MFMA  2  /* one fused launch, FIR passes on the matrix cores */
 #define BF_PATH_RECURSIVE  3  /* BF_GAUSS_REC: row and column recursions per block of orders */
 #define BF_PATH_VOLUME     4  /* bf_plan_volume: row, column and depth passes per block of orders */
 #define BF_PATH_WIDE       5  /* T/sigma_r in (13, 37.4]: the streamed Gaussian with float64
@@ -187,7 +184,7 @@ int bf_forward(const bf_plan_t* plan, const float* in, int64_t in_pitch,
  * instead (64 KiB per device, held until the process ends), written by small
  * kernels on `stream` whose arguments carry the values.  The call makes no
  * device allocation and frees nothing.
- *   p       as for bf_plan; BF_FLAG_GRAD, JOINT, STREAMED and TILE_MFMA are
+ *   p       as for bf_plan; BF_FLAG_GRAD, JOINT and STREAMED are
  *           refused (BF_EUNSUPPORTED); BF_FLAG_MIRROR, FP32_ACCUM and
  *           TILE_VALU are honoured
  *   in      device, height x width float32, row pitch in_pitch (elements)
@@ -210,8 +207,8 @@ int bf_forward_noalloc(const bf_params* p, const float* in, int64_t in_pitch, fl
  * [-W, W]^3 (box or truncated Gaussian, W <= 32), zero extension or, with
  * BF_FLAG_MIRROR, reflection about every face (edge samples repeated), Algorithm
  * 2 with three-axis filtering; N from the rule of bf_plan with the centre weight
- * (w1(0) / sum w1)^3.  Forward filter only: BF_FLAG_GRAD, JOINT, TILE_VALU and
- * TILE_MFMA return BF_EUNSUPPORTED, as does BF_GAUSS_REC.  T/sigma_r above 13
+ * (w1(0) / sum w1)^3.  Forward filter only: BF_FLAG_GRAD, JOINT and TILE_VALU
+ * return BF_EUNSUPPORTED, as does BF_GAUSS_REC.  T/sigma_r above 13
  * (lambda in (170, 1400]) takes the Gaussian only, on the float64-state passes
  * of BF_PATH_WIDE (not with BF_FLAG_MFMA_FP32).
  * Allocates about 80 bytes per voxel.  *out is owned by the caller

@@ -34,11 +34,9 @@ BF_FLAG_STREAMED = 4
 BF_FLAG_JOINT = 8
 BF_FLAG_MIRROR = 16
 BF_FLAG_TILE_VALU = 32
-BF_FLAG_TILE_MFMA = 64
 BF_FLAG_MFMA_FP32 = 128
 BF_PATH_TILE = 0
 BF_PATH_STREAMED = 1
-BF_PATH_TILE_MFMA = 2
 BF_PATH_RECURSIVE = 3
 BF_PATH_VOLUME = 4
 BF_PATH_WIDE = 5

@@ -17,9 +17,9 @@ from . import _lib as L
 
 _RULES = {"lambertw": L.BF_NRULE_LAMBERTW, "alg1": L.BF_NRULE_ALG1, "poisson": L.BF_NRULE_POISSON}
 _KERNELS = {"box": L.BF_BOX, "gauss": L.BF_GAUSS, "gaussian": L.BF_GAUSS, "gauss_rec": L.BF_GAUSS_REC}
-_ENGINES = {None: 0, "auto": 0, "valu": L.BF_FLAG_TILE_VALU, "mfma": L.BF_FLAG_TILE_MFMA,
+_ENGINES = {None: 0, "auto": 0, "valu": L.BF_FLAG_TILE_VALU,
             "streamed": L.BF_FLAG_STREAMED}
-PATHS = {L.BF_PATH_TILE: "valu", L.BF_PATH_STREAMED: "streamed", L.BF_PATH_TILE_MFMA: "mfma",
+PATHS = {L.BF_PATH_TILE: "valu", L.BF_PATH_STREAMED: "streamed",
          L.BF_PATH_RECURSIVE: "recursive", L.BF_PATH_VOLUME: "volume", L.BF_PATH_WIDE: "wide"}
 
 
@@ -46,7 +46,7 @@ def make_params(kernel: str, sigma_r: float, *, sigma_s: float | None = None, W:
                 joint: bool = False, mirror: bool = False, engine: str | None = None,
                 mfma_fp32: bool = False) -> L.bf_params:
     """bf_params; `engine` forces the forward engine: "valu" (fused tile on the
-    vector ALUs), "mfma" (fused tile on the matrix cores) or "streamed"; `mfma_fp32`
+    vector ALUs) or "streamed"; `mfma_fp32`
     keeps the streamed Gaussian passes on plain float32 matrix-core products."""
     p = L.bf_params()
     p.kernel = _KERNELS[kernel]

@@ -185,10 +185,6 @@ int64_t vol_state_bytes(int D, int Hs, int Wd, int W, bool wide = false);
 LsState vol_layout(void* base, int D, int Hs, int Wd, int W, VolBufs* g, bool wide = false);
 hipError_t launch_forward_vol(const TileParams& p, const LsState& st, const VolBufs& g, int D, int Hs, hipStream_t s);
 
-// fused Gaussian tile with both FIR passes on the matrix cores (W <= 45)
-hipError_t launch_fused_mfma(const TileParams& p, bool save, hipStream_t s);
-bool fused_mfma_supported(int W);
-int64_t fused_mfma_lds_bytes(int W);
 hipError_t launch_range(const float* in, int64_t pitch, int H, int Wd, float* mm, hipStream_t s);
 int joint_variant_count();
 Variant joint_variant(int v);
@@ -278,7 +274,6 @@ struct bf_plan {
   double* d_partials;   // per-workgroup sigma-gradient partials
   int ntiles_b;         // backward tiles
   bool ls;              // large-support path (support too wide for the fused tiles)
-  bool mfma;            // fused matrix-core tile (Gaussian)
   bool rec;             // recursive Gaussian (its state in d_ls / ls_state)
   bool wide;            // wide-range streamed Gaussian (its state in d_ls / ls_state)
   int depth;            // > 0: a volume plan of depth slices (its state in d_ls / ls_state, vol)

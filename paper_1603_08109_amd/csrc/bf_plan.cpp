@@ -139,6 +139,9 @@ static int normalise(const bf_params* in, bf_params* p) {
   *p = *in;
   if (p->kernel != BF_BOX && p->kernel != BF_GAUSS && p->kernel != BF_GAUSS_REC)
     return fail(BF_EINVAL, "kernel must be BF_BOX, BF_GAUSS or BF_GAUSS_REC");
+  constexpr int kKnownFlags = BF_FLAG_FP32_ACCUM | BF_FLAG_GRAD | BF_FLAG_STREAMED | BF_FLAG_JOINT |
+                              BF_FLAG_MIRROR | BF_FLAG_TILE_VALU | BF_FLAG_MFMA_FP32;
+  if (p->flags & ~kKnownFlags) return fail(BF_EINVAL, "unknown flag bits");
   if (p->kernel == BF_GAUSS) {
     if (!(p->sigma_s > 0.0) || !std::isfinite(p->sigma_s)) return fail(BF_EINVAL, "sigma_s must be > 0");
     if (p->W <= 0) p->W = (int)std::ceil(3.0 * p->sigma_s - 1e-12);
@@ -427,15 +430,15 @@ struct ForwardPath {
 };
 
 static int choose_forward_path(const bf_params& p, ForwardPath* fp) {
-  const int force = p.flags & (BF_FLAG_STREAMED | BF_FLAG_TILE_VALU | BF_FLAG_TILE_MFMA);
-  if (force & (force - 1)) return fail(BF_EINVAL, "at most one of the STREAMED / TILE_VALU / TILE_MFMA flags");
+  if ((p.flags & BF_FLAG_STREAMED) && (p.flags & BF_FLAG_TILE_VALU))
+    return fail(BF_EINVAL, "at most one of the STREAMED / TILE_VALU flags");
   const bool mirror = (p.flags & BF_FLAG_MIRROR) != 0;
   fp->variant = -1;
   fp->TY = 0;
   if ((p.T / p.sigma_r) * (p.T / p.sigma_r) > kLambdaF32) {
     // float32 exp(-x^2/2) underflows: the streamed Gaussian with float64 states
     if (p.kernel != BF_GAUSS ||
-        (p.flags & (BF_FLAG_JOINT | BF_FLAG_GRAD | BF_FLAG_TILE_VALU | BF_FLAG_TILE_MFMA | BF_FLAG_MFMA_FP32)))
+        (p.flags & (BF_FLAG_JOINT | BF_FLAG_GRAD | BF_FLAG_TILE_VALU | BF_FLAG_MFMA_FP32)))
       return fail(BF_EUNSUPPORTED,
                   "sigma_r too small for float32: T/sigma_r above 13 runs only the plain forward Gaussian "
                   "(no adjoint or cross filter, split-bfloat16 streamed passes)");
@@ -444,7 +447,7 @@ static int choose_forward_path(const bf_params& p, ForwardPath* fp) {
     return BF_OK;
   }
   if (p.kernel == BF_GAUSS_REC) {
-    if (p.flags & (BF_FLAG_JOINT | BF_FLAG_MIRROR | BF_FLAG_TILE_VALU | BF_FLAG_TILE_MFMA))
+    if (p.flags & (BF_FLAG_JOINT | BF_FLAG_MIRROR | BF_FLAG_TILE_VALU))
       return fail(BF_EUNSUPPORTED, "the recursive Gaussian runs the plain filter, zero border, own engine");
     if (p.height > 0 && p.width > 0 && !rg_supported(p.height, p.width))
       return fail(BF_EUNSUPPORTED, "recursive Gaussian: width and height <= 8192");
@@ -452,17 +455,10 @@ static int choose_forward_path(const bf_params& p, ForwardPath* fp) {
     return BF_OK;
   }
   if (p.flags & BF_FLAG_JOINT) {
-    if (p.flags & (BF_FLAG_GRAD | BF_FLAG_STREAMED | BF_FLAG_TILE_MFMA))
-      return fail(BF_EUNSUPPORTED, "the cross filter has no adjoint, streamed or matrix-core path");
+    if (p.flags & (BF_FLAG_GRAD | BF_FLAG_STREAMED))
+      return fail(BF_EUNSUPPORTED, "the cross filter has no adjoint or streamed path");
     fp->engine = BF_PATH_TILE;
     return choose_joint_tile(p.kernel, p.W, p.height, p.width, &fp->variant, &fp->TY);
-  }
-  if (p.flags & BF_FLAG_TILE_MFMA) {
-    if (p.kernel != BF_GAUSS) return fail(BF_EUNSUPPORTED, "the matrix-core tile serves the Gaussian kernel only");
-    if (!fused_mfma_supported(p.W)) return fail(BF_EUNSUPPORTED, "support W too large for the matrix-core tile");
-    fp->engine = BF_PATH_TILE_MFMA;
-    fp->TY = 64;
-    return BF_OK;
   }
   if (p.flags & BF_FLAG_TILE_VALU) {
     fp->engine = BF_PATH_TILE;
@@ -539,8 +535,7 @@ int bf_order(const bf_params* in, bf_plan_info* out) {
     out->path = fp.engine;
     out->tile_rows = fp.TY;
     out->tile_cols = (fp.engine == BF_PATH_STREAMED || fp.engine == BF_PATH_RECURSIVE || fp.engine == BF_PATH_WIDE) ? 0
-                     : fp.engine == BF_PATH_TILE_MFMA                                  ? 64
-                                                                                       : kTileCols;
+                                                                                                                : kTileCols;
   }
   return st;
 }
@@ -626,13 +621,12 @@ int bf_plan(const bf_params* in, bf_plan_t** out) {
   pl->info = info;
   pl->info.path = fpath.engine;
   pl->info.tile_rows = TY;
-  pl->info.tile_cols = (ls || fpath.engine == BF_PATH_RECURSIVE) ? 0 : fpath.engine == BF_PATH_TILE_MFMA ? 64 : kTileCols;
+  pl->info.tile_cols = (ls || fpath.engine == BF_PATH_RECURSIVE) ? 0 : kTileCols;
   if (ls && !wide && p.kernel == BF_BOX && ls_box_strip_supported(p.W)) {
     const StripShape sh = ls_box_strip_shape(p.height, p.width, p.W, false);
     pl->info.tile_rows = sh.seg_rows;
     pl->info.tile_cols = sh.oc;
   }
-  pl->mfma = fpath.engine == BF_PATH_TILE_MFMA;
   pl->rec = fpath.engine == BF_PATH_RECURSIVE;
   pl->wide = wide;
   pl->variant = variant;
@@ -834,8 +828,6 @@ int bf_forward(const bf_plan_t* pl, const float* in, int64_t in_pitch, float* ou
       return fail(BF_EINVAL, "saved state needs a plan built with BF_FLAG_GRAD");
     e = pl->wide ? launch_forward_wide(tp, pl->ls_state, (hipStream_t)stream)
                  : launch_forward_ls(tp, pl->ls_state, saved != nullptr, (hipStream_t)stream);
-  } else if (pl->mfma) {
-    e = launch_fused_mfma(tp, saved != nullptr, (hipStream_t)stream);
   } else if (pl->rec) {
     if (saved) return fail(BF_EINVAL, "the recursive Gaussian keeps no adjoint state");
     e = launch_forward_rg(tp, pl->ls_state, (hipStream_t)stream);
@@ -855,9 +847,9 @@ int bf_forward_noalloc(const bf_params* in_p, const float* in, int64_t in_pitch,
   if (p.height <= 0 || p.width <= 0) return fail(BF_EINVAL, "height and width must be > 0");
   if (in_pitch < p.width || out_pitch < p.width) return fail(BF_EINVAL, "pitch smaller than width");
   if ((const void*)in == (const void*)out) return fail(BF_EINVAL, "in and out must not alias");
-  if (p.flags & (BF_FLAG_GRAD | BF_FLAG_JOINT | BF_FLAG_STREAMED | BF_FLAG_TILE_MFMA))
+  if (p.flags & (BF_FLAG_GRAD | BF_FLAG_JOINT | BF_FLAG_STREAMED))
     return fail(BF_EUNSUPPORTED, "the allocation-free forward is the plain fused-tile forward "
-                                 "(no adjoint, cross filter, streamed or matrix-core engine)");
+                                 "(no adjoint, cross filter or streamed engine)");
   bf_plan_info info;
   const int ost = plan_order(&p, &info);
   if (ost < 0) return ost;
@@ -903,7 +895,7 @@ int bf_plan_volume(const bf_params* in, int32_t depth, bf_plan_t** out) {
   if (st < 0) return st;
   if (p.height <= 0 || p.width <= 0) return fail(BF_EINVAL, "height and width must be > 0");
   if (p.kernel == BF_GAUSS_REC) return fail(BF_EUNSUPPORTED, "volumes take the box or the truncated Gaussian");
-  if (p.flags & (BF_FLAG_GRAD | BF_FLAG_JOINT | BF_FLAG_TILE_VALU | BF_FLAG_TILE_MFMA))
+  if (p.flags & (BF_FLAG_GRAD | BF_FLAG_JOINT | BF_FLAG_TILE_VALU))
     return fail(BF_EUNSUPPORTED, "volumes: forward filter (zero or mirror border), streamed engine only");
   if (p.W > kVolMaxW) return fail(BF_EUNSUPPORTED, "volumes: W <= 32");
   if ((int64_t)depth * p.height > (1 << 30) / std::max(1, p.width))
@@ -1046,7 +1038,6 @@ int bf_backward(const bf_plan_t* pl, const float* in, int64_t in_pitch, const fl
     fp.TY = pl->TY;
     fp.tiles_x = (pl->p.width + kTileCols - 1) / kTileCols;
     hipError_t e = pl->ls     ? launch_forward_ls(fp, pl->ls_state, true, s)
-                   : pl->mfma ? launch_fused_mfma(fp, true, s)
                               : launch_forward(fp, pl->variant, acc64, true, s);
     if (e != hipSuccess) return hip_fail(e, "forward (recompute) launch");
     saved = pl->d_work;

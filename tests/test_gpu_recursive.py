@@ -108,7 +108,7 @@ def test_full_size_sampled(ss, sr):
 
 def test_unsupported_combinations():
     torch, P = _mods()
-    for kw in (dict(grad=True), dict(mirror=True), dict(joint=True), dict(engine="mfma"), dict(engine="valu")):
+    for kw in (dict(grad=True), dict(mirror=True), dict(joint=True), dict(engine="valu")):
         with pytest.raises(P.BFError):
             P.Plan("gauss_rec", 30.0, 64, 64, sigma_s=2.0, **kw)
     plan = P.Plan("gauss_rec", 30.0, 32, 32, sigma_s=2.0)
