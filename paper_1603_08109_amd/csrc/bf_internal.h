@@ -203,7 +203,8 @@ bool ls_box_strip_supported(int W);
 // length, grid and LDS bytes on an H x Wd image
 struct StripShape {
   int cpt, oc, seg_rows, grid;
-  int64_t lds;
+  int kb;        // orders per launch (a tail block of at most 16 orders takes 16)
+  int64_t lds;   // LDS bytes of the full block's kernel
 };
 StripShape ls_box_strip_shape(int H, int Wd, int W, bool save);
 bool ls_mirror_supported(int kernel, int W);

@@ -436,55 +436,81 @@ __device__ __forceinline__ double wave_scan_incl(double v) {
   return v;
 }
 
+// G independent inclusive wave scans, step by step, so that each step's DPP
+// moves of one value fill the wait states of the others
+template <int G>
+__device__ __forceinline__ void wave_scan_incl_n(double (&v)[G]) {
+#pragma unroll
+  for (int g = 0; g < G; ++g) v[g] += dpp_shr<0x111>(v[g]);
+#pragma unroll
+  for (int g = 0; g < G; ++g) v[g] += dpp_shr<0x112>(v[g]);
+#pragma unroll
+  for (int g = 0; g < G; ++g) v[g] += dpp_shr<0x114>(v[g]);
+#pragma unroll
+  for (int g = 0; g < G; ++g) v[g] += dpp_shr<0x118>(v[g]);
+#pragma unroll
+  for (int g = 0; g < G; ++g) v[g] += dpp_d<0x142, 0xA>(v[g]);
+#pragma unroll
+  for (int g = 0; g < G; ++g) v[g] += dpp_d<0x143, 0xC>(v[g]);
+}
+
 constexpr int kStripThreads = 256;
 
 // ---------------------------------------------------------------------------
 // Box kernel in column strips, single-pass form used for every box support
 // from 16 on large images.  A workgroup owns a strip of SC = 256 CPT columns
 // (CPT per thread, halo included; OC = SC - 2W outputs) and a segment of
-// rows, and processes the kLsBlock orders n0 .. n0 + kLsBlock - 1 of one
-// launch.  Per output row r:
-//   1. every thread writes the column sums C_n(r, c) of its columns (float64
-//      registers, rounded to float32) for the block's orders into LDS;
-//   2. (barrier) wave w takes orders w, w + 4, w + 8, w + 12.  For each,
+// rows, and processes the KB orders n0 .. n0 + KB - 1 of one launch; their
+// column sums C_n(r, c) stay in float64 registers down the rows.  Per output
+// row:
+//   1. every thread writes the column sums of its columns for the KB orders
+//      into LDS (rounded to float32);
+//   2. (barrier) wave w takes the orders w, w + 4, ...  For each,
 //      lane l sums strip columns 4 CPT l .. 4 CPT l + 4 CPT - 1 into a float64
 //      prefix, a DPP wave scan joins the lanes, the inclusive prefix S goes to
 //      the wave's own LDS row (read back by the same wave: no barrier), and
 //      the window sums S(c + W) - S(c - W - 1) of the output columns
 //      overwrite that order's column sums in LDS (float32);
 //   3. (barrier) each thread folds the window sums of its output columns into
-//      eqs. (P), (Q) (float32 partials added to the float64 totals every 8
-//      orders) and slides its column sums down one row: the entering and
-//      leaving rows' F^_n follow from F^_{n0} and y by the power recursion,
-//      in float64.
-// The fold has no per-order tests: the factor 1/(n + 1) that advances a_n is
-// taken as 0 where n + 1 >= N, so a_n = 0 for every n >= N, and the orders
-// past N in the last block add nothing (eq. (Q) stops at n = N - 1 and eq.
-// (P) at n = N).  The rows entering the segment advance the F^ state image.
+//      eqs. (P), (Q) in float64.
+// Then every thread slides its column sums down one row: the entering and
+// leaving rows' F^_n follow from F^_{n0} and y by the power recursion, in
+// float64.  The fold has no per-order tests: the factor 1/(n + 1) that
+// advances a_n is taken as 0 where n + 1 >= N, so a_n = 0 for every n >= N,
+// and the orders past N in the last block add nothing (eq. (Q) stops at
+// n = N - 1 and eq. (P) at n = N).  The per-pixel state between launches is
+// a_{n0 - 1}, z and the two sums: a_{n0} = a_{n0 - 1} (z / n0) is recomputed
+// with the rounding the chain itself applied, so it is the same float.  Each wave scans SG
+// orders together, one LDS prefix row each, so their scans and LDS round
+// trips overlap.  The rows entering the segment advance the F^ state image.
 // ---------------------------------------------------------------------------
-template <int CPT>
+template <int CPT, int KB>
 struct StripGeom {
   static constexpr int SC = 256 * CPT;              // strip columns
   static constexpr int CPL = 4 * CPT;               // columns per lane in the row scan
-  static constexpr int CPITCH = SC + 4 * (SC / 64);  // float32 row: 4 floats of padding per 64 columns
+  static constexpr int CPITCH = SC + 4 * (SC / 32);  // float32 row: 4 floats of padding per 32 columns
   static constexpr int SPITCH = SC + 4 + 2 * ((SC + 2) / 32);  // float64 prefix row (slots 0 .. SC + 1)
-  static constexpr int LDS_BYTES = kLsBlock * CPITCH * 4 + 4 * SPITCH * 8;
+  static constexpr int SG = CPT == 1 ? 4 : 2;       // orders a wave scans together (one prefix row each)
+  static constexpr int LDS_BYTES = KB * CPITCH * 4 + 4 * SG * SPITCH * 8;
 };
-// float32 column c of a row: the 16-byte reads of lanes 8 apart (32 bytes
-// per lane) fall on distinct banks
-__device__ __forceinline__ int strip_cpos(int c) { return c + 4 * (c >> 6); }
+// float32 column c of a row, 4 floats of padding after every 32: the 16-byte
+// reads of 8 lanes (one LDS cycle) fall on distinct banks for runs of 16 or
+// 32 bytes per lane, and 32 consecutive columns stay contiguous for the
+// 4- and 8-byte accesses
+__device__ __forceinline__ int strip_cpos(int c) { return c + 4 * (c >> 5); }
 // float64 prefix slot s (S(c) at slot c + 2, S(-1) = 0 at slot 1): the
 // 16-byte writes of lanes 4 apart (64 bytes per lane) fall on distinct banks
 __device__ __forceinline__ int strip_spos(int s) { return s + 2 * (s >> 5); }
 
-template <int CPT, bool SAVE>
+template <int CPT, bool SAVE, int KB>
 __global__ __launch_bounds__(kStripThreads) void ls_box_strip_kernel(TileParams p, LsState st, int n0, int src,
                                                                       int seg_rows) {
-  using G = StripGeom<CPT>;
-  constexpr int SC = G::SC, CPL = G::CPL;
+  using G = StripGeom<CPT, KB>;
+  constexpr int SC = G::SC, CPL = G::CPL, SG = G::SG;
+  static_assert((KB / 4) % SG == 0, "a wave's orders: whole scan groups");
   extern __shared__ double dlds[];
-  float* Cb = (float*)dlds;                        // kLsBlock x CPITCH
-  double* Sb = dlds + (kLsBlock * G::CPITCH) / 2;  // 4 x SPITCH
+  float* Cb = (float*)dlds;                  // KB x CPITCH
+  double* Sb = dlds + (KB * G::CPITCH) / 2;  // 4 SG x SPITCH
   const int W = p.W;
   const int OC = SC - 2 * W;
   const int nstrips = (p.Wd + OC - 1) / OC;
@@ -508,23 +534,25 @@ __global__ __launch_bounds__(kStripThreads) void ls_box_strip_kernel(TileParams 
   const float* Fin = st.F[src];
   float* Fout = st.F[src ^ 1];
   // 1/(n + 1) for the block's orders, 0 from n + 1 = N on (wave-uniform)
-  float in1[kLsBlock];
-  float dqm[kLsBlock], dpm[kLsBlock];  // adjoint sums: eq. (Q)'s derivative stops at N - 1, (P)'s at N
+  float in1[KB];
+  float dqm[KB], dpm[KB];  // adjoint sums: eq. (Q)'s derivative stops at N - 1, (P)'s at N
 #pragma unroll
-  for (int k = 0; k < kLsBlock; ++k) {
+  for (int k = 0; k < KB; ++k) {
     const int n = n0 + k;
     in1[k] = (n + 1 < p.N) ? p.inv_tab[n + 1] : 0.f;
     dqm[k] = (n == p.N) ? 0.f : 1.f;
     dpm[k] = (n == p.N + 1) ? 0.f : 1.f;
   }
-  double* srow = Sb + wv * G::SPITCH;
-  if (lane == 0) {
-    srow[strip_spos(0)] = 0.0;
-    srow[strip_spos(1)] = 0.0;  // S(-1)
+  // the factor that took a_{n0 - 1} to a_{n0} at the end of the previous block
+  const float in1_prev = (n0 >= 1 && n0 < p.N) ? p.inv_tab[n0] : 0.f;
+  double* srow = Sb + wv * SG * G::SPITCH;  // this wave's SG prefix rows
+  if (lane < SG) {
+    srow[lane * G::SPITCH + strip_spos(0)] = 0.0;
+    srow[lane * G::SPITCH + strip_spos(1)] = 0.0;  // S(-1)
   }
-  double C[kLsBlock][CPT];
+  double C[KB][CPT];
 #pragma unroll
-  for (int k = 0; k < kLsBlock; ++k)
+  for (int k = 0; k < KB; ++k)
 #pragma unroll
     for (int j = 0; j < CPT; ++j) C[k][j] = 0.0;
   // clamped (always in bounds) load addresses; samples off the image read 0
@@ -551,7 +579,7 @@ __global__ __launch_bounds__(kStripThreads) void ls_box_strip_kernel(TileParams 
       double fd = (double)f[j];
       const double yd = (double)y[j];
 #pragma unroll
-      for (int k = 0; k < kLsBlock; ++k) {
+      for (int k = 0; k < KB; ++k) {
         C[k][j] += fd;
         fd *= yd;
       }
@@ -559,95 +587,130 @@ __global__ __launch_bounds__(kStripThreads) void ls_box_strip_kernel(TileParams 
     }
   }
   for (int r = r_lo; r < r_hi; ++r) {
-    // column sums of row r into LDS
-#pragma unroll
-    for (int k = 0; k < kLsBlock; ++k) {
-      float* row = Cb + k * G::CPITCH + strip_cpos(CPT * t);
-#pragma unroll
-      for (int j = 0; j < CPT; ++j) row[j] = (float)C[k][j];
-    }
     // rows entering and leaving after this one, and this row's pixel state
     float fe[CPT], ye[CPT], fl[CPT], yl[CPT];
     load_row(r + W + 1, fe, ye);
     load_row(r - W, fl, yl);
-    float a[CPT], ap[CPT], app[CPT], z[CPT];
-    double P[CPT], Q[CPT], DP[CPT], DQ[CPT];
+    // the sums of even and odd orders are kept apart (two shorter dependency
+    // chains); a_n advances in float32
+    float af[CPT], ap[CPT], app[CPT], z[CPT];
+    double P[CPT], Q[CPT], P1[CPT], Q1[CPT], DP[CPT], DQ[CPT];
 #pragma unroll
     for (int j = 0; j < CPT; ++j) {  // non-output columns read pixel (r, 0) and store nothing
       const int64_t pi = (int64_t)r * p.Wd + (central[j] ? gcol[j] : 0);
-      a[j] = st.a[pi];
       ap[j] = st.ap[pi];
       z[j] = st.z[pi];
       P[j] = st.P[pi];
       Q[j] = st.Q[pi];
+      P1[j] = 0.0;
+      Q1[j] = 0.0;
+      if (n0 == 0)
+        af[j] = st.a[pi];
+      else
+        af[j] = ap[j] * (z[j] * in1_prev);
       if (SAVE) {
         app[j] = st.app[pi];
         DP[j] = st.DP[pi];
         DQ[j] = st.DQ[pi];
       }
     }
+    double ad[CPT], apd[CPT];
+#pragma unroll
+    for (int j = 0; j < CPT; ++j) {
+      ad[j] = (double)af[j];
+      apd[j] = (double)ap[j];
+    }
+    // column sums of row r into LDS
+#pragma unroll
+    for (int k = 0; k < KB; ++k) {
+      float* row = Cb + k * G::CPITCH + strip_cpos(CPT * t);
+#pragma unroll
+      for (int j = 0; j < CPT; ++j) row[j] = (float)C[k][j];
+    }
     lds_barrier();
-    // row windows of orders wv, wv + 4, wv + 8, wv + 12
+    // row windows of the orders wv, wv + 4, ..., SG at a time
 #pragma unroll
-    for (int jj = 0; jj < kLsBlock / 4; ++jj) {
-      float* crow = Cb + (wv + 4 * jj) * G::CPITCH;
-      float x[CPL];
+    for (int jg = 0; jg < KB / 4; jg += SG) {
+      float x[SG][CPL];
 #pragma unroll
-      for (int u = 0; u < CPL; u += 4) {
-        const float4 v4 = *(const float4*)(crow + strip_cpos(CPL * lane + u));
-        x[u] = v4.x;
-        x[u + 1] = v4.y;
-        x[u + 2] = v4.z;
-        x[u + 3] = v4.w;
+      for (int g = 0; g < SG; ++g) {
+        const float* crow = Cb + (wv + 4 * (jg + g)) * G::CPITCH;
+#pragma unroll
+        for (int u = 0; u < CPL; u += 4) {
+          const float4 v4 = *(const float4*)(crow + strip_cpos(CPL * lane + u));
+          x[g][u] = v4.x;
+          x[g][u + 1] = v4.y;
+          x[g][u + 2] = v4.z;
+          x[g][u + 3] = v4.w;
+        }
       }
-      double pre[CPL];
-      pre[0] = (double)x[0];
+      double pre[SG][CPL], v[SG];
 #pragma unroll
-      for (int u = 1; u < CPL; ++u) pre[u] = pre[u - 1] + (double)x[u];
-      const double incl = wave_scan_incl(pre[CPL - 1]);
-      const double ex = incl - pre[CPL - 1];
+      for (int g = 0; g < SG; ++g) {
+        pre[g][0] = (double)x[g][0];
 #pragma unroll
-      for (int u = 0; u < CPL; u += 2)
-        *(double2*)(srow + strip_spos(CPL * lane + 2 + u)) = make_double2(ex + pre[u], ex + pre[u + 1]);
-      // window sums of the columns c = lane + 64 i (this wave's prefix row,
+        for (int u = 1; u < CPL; ++u) pre[g][u] = pre[g][u - 1] + (double)x[g][u];
+        v[g] = pre[g][CPL - 1];
+      }
+      wave_scan_incl_n<SG>(v);
+#pragma unroll
+      for (int g = 0; g < SG; ++g) {
+        const double ex = v[g] - pre[g][CPL - 1];
+        double* sg = srow + g * G::SPITCH;
+#pragma unroll
+        for (int u = 0; u < CPL; u += 2)
+          *(double2*)(sg + strip_spos(CPL * lane + 2 + u)) = make_double2(ex + pre[g][u], ex + pre[g][u + 1]);
+      }
+      // window sums of the columns c = lane + 64 i (this wave's prefix rows,
       // written above by its own lanes); the slots are clamped, so columns
       // within W of the strip edge get values that no output reads
 #pragma unroll
-      for (int i = 0; i < SC / 64; ++i) {
-        const int c = lane + 64 * i;
-        crow[strip_cpos(c)] = (float)(srow[strip_spos(min(c + W + 2, SC + 1))] - srow[strip_spos(max(c - W + 1, 1))]);
+      for (int g = 0; g < SG; ++g) {
+        float* crow = Cb + (wv + 4 * (jg + g)) * G::CPITCH;
+        const double* sg = srow + g * G::SPITCH;
+#pragma unroll
+        for (int i = 0; i < SC / 64; ++i) {
+          const int c = lane + 64 * i;
+          crow[strip_cpos(c)] =
+              (float)(sg[strip_spos(min(c + W + 2, SC + 1))] - sg[strip_spos(max(c - W + 1, 1))]);
+        }
       }
     }
     lds_barrier();
     // fold this thread's output pixels: float64 products and sums (the terms
     // of eqs. (P), (Q) cancel heavily at small sigma_r; float32 partial sums
-    // cost about 5e-4 there); a_n advances in float32
+    // cost about 5e-4 there).  The next row writes only this thread's own
+    // columns before its barrier, so no barrier is needed after the fold.
 #pragma unroll
     for (int j = 0; j < CPT; ++j) {
-      double ad = (double)a[j], apd = (double)ap[j], appd = SAVE ? (double)app[j] : 0.0;
-      float af = a[j];
 #pragma unroll
-      for (int k = 0; k < kLsBlock; ++k) {
+      for (int k = 0; k < KB; ++k) {
         const double vd = (double)Cb[k * G::CPITCH + strip_cpos(CPT * t) + j];
-        Q[j] = fma(ad, vd, Q[j]);
-        P[j] = fma(apd, vd, P[j]);
+        if (k & 1) {
+          Q1[j] = fma(ad[j], vd, Q1[j]);
+          P1[j] = fma(apd[j], vd, P1[j]);
+        } else {
+          Q[j] = fma(ad[j], vd, Q[j]);
+          P[j] = fma(apd[j], vd, P[j]);
+        }
         if (SAVE) {
           DQ[j] = fma((double)(ap[j] * dqm[k]), vd, DQ[j]);
           DP[j] = fma((double)(app[j] * dpm[k]), vd, DP[j]);
           app[j] = ap[j];
-          appd = apd;
         }
-        ap[j] = af;
-        apd = ad;
-        af *= z[j] * in1[k];
-        ad = (double)af;
+        ap[j] = af[j];
+        apd[j] = ad[j];
+        af[j] *= z[j] * in1[k];
+        ad[j] = (double)af[j];
       }
+    }
+#pragma unroll
+    for (int j = 0; j < CPT; ++j) {
       if (central[j]) {
         const int64_t pi = (int64_t)r * p.Wd + gcol[j];
-        st.a[pi] = af;
         st.ap[pi] = ap[j];
-        st.P[pi] = P[j];
-        st.Q[pi] = Q[j];
+        st.P[pi] = P[j] + P1[j];
+        st.Q[pi] = Q[j] + Q1[j];
         if (SAVE) {
           st.app[pi] = app[j];
           st.DP[pi] = DP[j];
@@ -662,7 +725,7 @@ __global__ __launch_bounds__(kStripThreads) void ls_box_strip_kernel(TileParams 
       double fed = (double)fe[j], fld = (double)fl[j];
       const double yed = (double)ye[j], yld = (double)yl[j];
 #pragma unroll
-      for (int k = 0; k < kLsBlock; ++k) {
+      for (int k = 0; k < KB; ++k) {
         C[k][j] = (C[k][j] + fed) - fld;
         fed *= yed;
         fld *= yld;
@@ -672,28 +735,43 @@ __global__ __launch_bounds__(kStripThreads) void ls_box_strip_kernel(TileParams 
   }
 }
 
-template <int CPT>
-int64_t ls_box_strip_lds_bytes() { return StripGeom<CPT>::LDS_BYTES; }
-
 bool ls_box_strip_supported(int W) { return 256 - 2 * W >= 64; }
+
+// The strip kernel for a launch of kb orders (the shape's block, or 16 at
+// the tail), and its LDS bytes.
+static const void* box_strip_kernel(int cpt, bool save, int kb) {
+  if (save) return (const void*)ls_box_strip_kernel<1, true, 16>;  // the saved state runs 256-column strips
+  if (cpt == 2) return (const void*)ls_box_strip_kernel<2, false, 16>;
+  return kb == 32 ? (const void*)ls_box_strip_kernel<1, false, 32> : (const void*)ls_box_strip_kernel<1, false, 16>;
+}
+static int64_t box_strip_lds(int cpt, int kb) {
+  if (cpt == 2) return StripGeom<2, 16>::LDS_BYTES;
+  return kb == 32 ? StripGeom<1, 32>::LDS_BYTES : StripGeom<1, 16>::LDS_BYTES;
+}
+// orders of the launch that starts at n0: the shape's block, or 16 where the
+// orders left (n0 .. N) fit in 16
+static int box_strip_block(const StripShape& sh, int n0, int N) { return N + 1 - n0 <= 16 ? 16 : sh.kb; }
 
 // Shape of the box strips on an H x Wd image: the 512-column form for the
 // plain forward from W = 48 (its halo is shared by more outputs, at two
-// resident workgroups per compute unit; 4096^2, sigma_r = 10: W = 75 10.8 ms
-// against 13.4 for the 256-column form, W = 30 8.1 against 7.6), else 256
-// columns (three resident workgroups; two with the saved state, whose sums
-// need more registers).  Row segments: one wave of resident workgroups, so
-// none trails; each pays a 2W + 1 row warm-up.
+// resident workgroups per compute unit; 4096^2, sigma_r = 10: W = 75 11.0 ms
+// against 13.5 for the 256-column form), else 256 columns.  The plain
+// 256-column form takes 32 orders per launch (two resident workgroups: the
+// per-pixel state crosses HBM half as often; W = 30, sigma_r = 10: 7.3 ms
+// against 7.9 with 16 orders and three resident workgroups); the others 16.
+// Row segments: one wave of resident workgroups, so none trails; each pays a
+// 2W + 1 row warm-up.
 StripShape ls_box_strip_shape(int H, int Wd, int W, bool save) {
   StripShape sh;
   sh.cpt = (!save && W >= 48) ? 2 : 1;
-  const int resident = (sh.cpt == 2 || save) ? 2 : 3;
+  sh.kb = (save || sh.cpt == 2) ? 16 : 32;
+  const int resident = (sh.cpt == 1 && sh.kb == 16 && !save) ? 3 : 2;
   sh.oc = 256 * sh.cpt - 2 * W;
   const int nstrips = (Wd + sh.oc - 1) / sh.oc;
   const int nseg = std::max(1, std::min((H + 31) / 32, num_cus() * resident / nstrips));
   sh.seg_rows = (H + nseg - 1) / nseg;
   sh.grid = nstrips * ((H + sh.seg_rows - 1) / sh.seg_rows);
-  sh.lds = sh.cpt == 2 ? ls_box_strip_lds_bytes<2>() : ls_box_strip_lds_bytes<1>();
+  sh.lds = box_strip_lds(sh.cpt, sh.kb);
   return sh;
 }
 
@@ -820,12 +898,12 @@ hipError_t launch_forward_ls(const TileParams& p, const LsState& st, bool save, 
   // box: column strips (float64 running column sums, float64 prefix-sum row windows)
   const bool box_strip = p.kt == BF_BOX && ls_box_strip_supported(p.W);
   const StripShape sh = box_strip ? ls_box_strip_shape(p.H, p.Wd, p.W, save) : StripShape{};
-  const void* strip_kern = nullptr;
   if (box_strip) {
-    strip_kern = sh.cpt == 2 ? (save ? (const void*)ls_box_strip_kernel<2, true> : (const void*)ls_box_strip_kernel<2, false>)
-                             : (save ? (const void*)ls_box_strip_kernel<1, true> : (const void*)ls_box_strip_kernel<1, false>);
-    e = hipFuncSetAttribute(strip_kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh.lds);
-    if (e != hipSuccess) return e;
+    for (int kb = sh.kb; kb >= 16; kb /= 2) {
+      e = hipFuncSetAttribute(box_strip_kernel(sh.cpt, save, kb), hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)box_strip_lds(sh.cpt, kb));
+      if (e != hipSuccess) return e;
+    }
   }
   // Gaussian: FIR passes on the matrix cores where the staged windows fit
   const size_t rlm = (size_t)ls_rows_mfma_lds_bytes(p.W);
@@ -857,66 +935,75 @@ hipError_t launch_forward_ls(const TileParams& p, const LsState& st, bool save, 
     if (e != hipSuccess) return e;
   }
   int src = 0;
-  for (int n0 = 0; n0 <= p.N; n0 += kLsBlock) {
-    const int K = std::min(kLsBlock, p.N + 1 - n0);
-    if (box_strip) {
+  if (box_strip) {
+    for (int n0 = 0; n0 <= p.N;) {
+      const int kb = box_strip_block(sh, n0, p.N);
       int n0v = n0, srcv = src, segv = sh.seg_rows;
       TileParams pv = p;
       LsState sv = st;
       void* args[] = {(void*)&pv, (void*)&sv, (void*)&n0v, (void*)&srcv, (void*)&segv};
-      e = hipLaunchKernel(strip_kern, dim3(sh.grid), dim3(kStripThreads), args, (size_t)sh.lds, s);
+      e = hipLaunchKernel(box_strip_kernel(sh.cpt, save, kb), dim3(sh.grid), dim3(kStripThreads), args,
+                          (size_t)box_strip_lds(sh.cpt, kb), s);
       if (e != hipSuccess) return e;
       src ^= 1;
-      continue;
+      n0 += kb;
     }
+  }
+  // two passes per block of orders (every other path)
+  for (int n0 = 0; !box_strip && n0 <= p.N; n0 += kLsBlock) {
+    const int K = std::min(kLsBlock, p.N + 1 - n0);
+    // row pass
     if (x3) {
       // split row pass always; split column pass from W = 40 (4096^2, sigma_r = 30,
       // ms per call, rows+cols float32 / split rows / both split: W = 30 4.40 / 4.00 /
       // 4.14, W = 51 5.82 / 4.95 / 4.78, W = 75 7.40 / 6.09 / 5.93)
       e = launch_rows_x3(p, st, n0, K, src, grow, s);
+    } else {
+      if (rows_mfma)
+        hipLaunchKernelGGL(ls_rows_mfma_kernel, dim3(grow), dim3(kThreads), (size_t)rlm, s, p, st, n0, K, src);
+      else
+        hipLaunchKernelGGL(rk, dim3(grow), dim3(kThreads), (size_t)rl, s, p, st, n0, K, src);
+      e = hipGetLastError();
+    }
+    if (e != hipSuccess) return e;
+    // column pass
+    if (x3) {
       // from W = 40 the column pass splits its window once per workgroup
       // (ls_cols_x3s) where its registers allow (up to 6 k-steps, plain
       // forward); 4096^2, sigma_r = 10, W = 75: 25.1 -> 23.6 ms per call.  Below
-      // W = 40 the float32 matrix-core column pass stays faster.
+      // W = 40 the float32 matrix-core column pass stays faster (W = 30: 3%;
+      // at W = 39 the split-once pass is 4% faster).
       const bool x3s = !save && p.W >= 40 && (16 + 2 * p.W + 31) / 32 <= 6 && st.hbytes < (1LL << 31);
-      if (e == hipSuccess && x3s) {
+      if (x3s) {
         e = launch_cols_x3s(p, st, n0, K, false, s);
-      } else if (e == hipSuccess) {
-        if (p.W >= 40) {
-          e = launch_cols_x3(p, st, n0, K, save, gfir16, s);
-        } else {
-          if (save)
-            hipLaunchKernelGGL((ls_cols_mfma_kernel<true>), dim3(gfir16), dim3(kColsThreads), clm, s, p, st, n0, K);
-          else
-            hipLaunchKernelGGL((ls_cols_mfma_kernel<false>), dim3(gfir16), dim3(kColsThreads), clm, s, p, st, n0, K);
-          e = hipGetLastError();
-        }
+      } else if (p.W >= 40) {
+        e = launch_cols_x3(p, st, n0, K, save, gfir16, s);
+      } else {
+        if (save)
+          hipLaunchKernelGGL((ls_cols_mfma_kernel<true>), dim3(gfir16), dim3(kColsThreads), clm, s, p, st, n0, K);
+        else
+          hipLaunchKernelGGL((ls_cols_mfma_kernel<false>), dim3(gfir16), dim3(kColsThreads), clm, s, p, st, n0, K);
+        e = hipGetLastError();
       }
-      if (e != hipSuccess) return e;
-      src ^= 1;
-      continue;
-    }
-    if (rows_mfma)
-      hipLaunchKernelGGL(ls_rows_mfma_kernel, dim3(grow), dim3(kThreads), (size_t)rlm, s, p, st, n0, K, src);
-    else
-      hipLaunchKernelGGL(rk, dim3(grow), dim3(kThreads), (size_t)rl, s, p, st, n0, K, src);
-    if (p.kt == BF_BOX) {
-      if (save)
-        hipLaunchKernelGGL((ls_cols_box_kernel<true>), gbox, dim3(kThreads), 0, s, p, st, n0, K, seg_rows);
-      else
-        hipLaunchKernelGGL((ls_cols_box_kernel<false>), gbox, dim3(kThreads), 0, s, p, st, n0, K, seg_rows);
-    } else if (cols_mfma) {
-      if (save)
-        hipLaunchKernelGGL((ls_cols_mfma_kernel<true>), dim3(gfir16), dim3(kColsThreads), clm, s, p, st, n0, K);
-      else
-        hipLaunchKernelGGL((ls_cols_mfma_kernel<false>), dim3(gfir16), dim3(kColsThreads), clm, s, p, st, n0, K);
     } else {
-      if (save)
-        hipLaunchKernelGGL((ls_cols_fir_kernel<8, true>), dim3(gfir8), dim3(kThreads), fl8, s, p, st, n0, K);
-      else
-        hipLaunchKernelGGL((ls_cols_fir_kernel<16, false>), dim3(gfir16), dim3(kThreads), fl16, s, p, st, n0, K);
+      if (p.kt == BF_BOX) {
+        if (save)
+          hipLaunchKernelGGL((ls_cols_box_kernel<true>), gbox, dim3(kThreads), 0, s, p, st, n0, K, seg_rows);
+        else
+          hipLaunchKernelGGL((ls_cols_box_kernel<false>), gbox, dim3(kThreads), 0, s, p, st, n0, K, seg_rows);
+      } else if (cols_mfma) {
+        if (save)
+          hipLaunchKernelGGL((ls_cols_mfma_kernel<true>), dim3(gfir16), dim3(kColsThreads), clm, s, p, st, n0, K);
+        else
+          hipLaunchKernelGGL((ls_cols_mfma_kernel<false>), dim3(gfir16), dim3(kColsThreads), clm, s, p, st, n0, K);
+      } else {
+        if (save)
+          hipLaunchKernelGGL((ls_cols_fir_kernel<8, true>), dim3(gfir8), dim3(kThreads), fl8, s, p, st, n0, K);
+        else
+          hipLaunchKernelGGL((ls_cols_fir_kernel<16, false>), dim3(gfir16), dim3(kThreads), fl16, s, p, st, n0, K);
+      }
+      e = hipGetLastError();
     }
-    e = hipGetLastError();
     if (e != hipSuccess) return e;
     src ^= 1;
   }

@@ -267,11 +267,12 @@ def test_clone_workspace_on_two_streams():
 
 
 @pytest.mark.parametrize("W,sr,shape", [(16, 10.0, (150, 700)), (56, 30.0, (120, 1100)), (75, 20.0, (90, 900)),
-                                        (190, 30.0, (60, 500))])
+                                        (190, 30.0, (60, 500)), (20, 15.0, (140, 900)), (40, 25.0, (100, 1300))])
 def test_box_strip_widths_agree(W, sr, shape):
     # the forward-only strips (512 columns from W = 48) against the
     # 256-column strips that also write the saved state, and both against the
-    # oracle; several strips, a ragged last one
+    # oracle; several strips, a ragged last one.  W = 20 (N = 133) and W = 40
+    # (N = 66) end their 32-order launches with a 16-order one.
     torch, P = _mods()
     f = synthimg.gen2(*shape, 80 + W)
     x = torch.tensor(f, dtype=torch.float32, device="cuda")
