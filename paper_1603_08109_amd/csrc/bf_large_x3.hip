@@ -84,6 +84,20 @@ __device__ __forceinline__ void split3(float f, __bf16& h, __bf16& m, __bf16& l)
   l = (__bf16)(r - (float)m);
 }
 
+// split3 of two values at once, each plane's pair packed in one 32-bit word
+// (first value in the low half): one packed conversion per plane, and the
+// bfloat16 halves widened back by a shift or a mask.  The steps and their
+// rounding are those of split3, so the pieces are the same.
+typedef float f2v __attribute__((ext_vector_type(2)));
+typedef __bf16 b2v __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ void split3_pair(float f0, float f1, uint32_t& H, uint32_t& M, uint32_t& L) {
+  H = __builtin_bit_cast(uint32_t, __builtin_convertvector((f2v){f0, f1}, b2v));
+  const float r0 = f0 - __uint_as_float(H << 16), r1 = f1 - __uint_as_float(H & 0xffff0000u);
+  M = __builtin_bit_cast(uint32_t, __builtin_convertvector((f2v){r0, r1}, b2v));
+  const float s0 = r0 - __uint_as_float(M << 16), s1 = r1 - __uint_as_float(M & 0xffff0000u);
+  L = __builtin_bit_cast(uint32_t, __builtin_convertvector((f2v){s0, s1}, b2v));
+}
+
 // the three planes of the Toeplitz operand, [s][plane][lane] x 8
 template <int NT>
 __device__ __forceinline__ void fill_toeplitz_x3(__bf16* Tb, int W, const float* __restrict__ tz) {
@@ -170,13 +184,11 @@ int64_t ls_cols_x3_lds_bytes(int W) {
 template <typename FT>
 __device__ __forceinline__ void x3_split_pair(FT f0, FT f1, __bf16* P, int plane, int jj) {
   const int q = 2 * (threadIdx.x + jj * kX3RowsThreads);
-  __bf16 h0, m0, l0, h1, m1, l1;
-  split3((float)f0, h0, m0, l0);
-  split3((float)f1, h1, m1, l1);
-  typedef __bf16 bf2 __attribute__((ext_vector_type(2)));
-  *(bf2*)(P + q) = bf2{h0, h1};
-  *(bf2*)(P + plane + q) = bf2{m0, m1};
-  *(bf2*)(P + 2 * plane + q) = bf2{l0, l1};
+  uint32_t h, m, l;
+  split3_pair((float)f0, (float)f1, h, m, l);
+  *(uint32_t*)(P + q) = h;
+  *(uint32_t*)(P + plane + q) = m;
+  *(uint32_t*)(P + 2 * plane + q) = l;
 }
 
 // F^_n -> F^_{n+1} = F^_n y; wide range: F~_n -> F~_{n+1} = F~_n x / sqrt(n + 1)
@@ -376,15 +388,14 @@ __global__ __launch_bounds__(kX3ColsThreads) void ls_cols_x3_kernel(TileParams p
     for (int q = 0; q <= S; ++q) {
       X3 bv;
       const float* src = cur + lbase + 8 * q * kX3GroupFloats;
+      uint32_t h[4], m[4], l[4];
 #pragma unroll
-      for (int i = 0; i < 8; ++i) {
-        const float f = src[(i >> 2) * kX3GroupFloats + (i & 3) * 64];
-        __bf16 h, m, l;
-        split3(f, h, m, l);
-        bv.h[i] = h;
-        bv.m[i] = m;
-        bv.l[i] = l;
-      }
+      for (int i = 0; i < 8; i += 2)
+        split3_pair(src[(i >> 2) * kX3GroupFloats + (i & 3) * 64], src[(i >> 2) * kX3GroupFloats + ((i + 1) & 3) * 64],
+                    h[i / 2], m[i / 2], l[i / 2]);
+      bv.h = __builtin_bit_cast(bf8, h);
+      bv.m = __builtin_bit_cast(bf8, m);
+      bv.l = __builtin_bit_cast(bf8, l);
       // block rb at step q, block rb + 2 at step q - 1
       if (q >= 1 && q < S)
         mfma_x3_pair(T[q < S ? q : 0], bv, acc[0], T[q >= 1 ? q - 1 : 0], bv, acc[1]);
@@ -544,19 +555,14 @@ __device__ __forceinline__ void x3s_split(const float (&reg)[X3sGeom<S>::ITEMS][
   for (int i = 0; i < G::ITEMS; ++i) {
     const int grp = g0 + (kX3sThreads / kX3sCols) * i;
     if (grp < G::GROUPS) {
-      bf8 h, m, l;
-#pragma unroll
-      for (int j = 0; j < 8; ++j) {
-        __bf16 a, b, c;
-        split3(reg[i][j], a, b, c);
-        h[j] = a;
-        m[j] = b;
-        l[j] = c;
-      }
-      bf8* d = (bf8*)(Pl + col * G::RP + 8 * grp);
-      d[0] = h;
-      *(bf8*)(Pl + PS + col * G::RP + 8 * grp) = m;
-      *(bf8*)(Pl + 2 * PS + col * G::RP + 8 * grp) = l;
+      uint4 h, m, l;
+      split3_pair(reg[i][0], reg[i][1], h.x, m.x, l.x);
+      split3_pair(reg[i][2], reg[i][3], h.y, m.y, l.y);
+      split3_pair(reg[i][4], reg[i][5], h.z, m.z, l.z);
+      split3_pair(reg[i][6], reg[i][7], h.w, m.w, l.w);
+      *(uint4*)(Pl + col * G::RP + 8 * grp) = h;
+      *(uint4*)(Pl + PS + col * G::RP + 8 * grp) = m;
+      *(uint4*)(Pl + 2 * PS + col * G::RP + 8 * grp) = l;
     }
   }
 }
