@@ -221,7 +221,7 @@ def _calls(dispatches):
         n = _short(d["name"])
         if n.startswith("__amd_rocclr") or not n.replace("<", " ").split()[0].endswith("kernel"):
             continue
-        if n.startswith("gpa_forward_kernel"):
+        if n.startswith("gpa_forward_kernel") or n.startswith("gpa_forward_w_kernel"):
             calls.append([d])
         elif n.startswith("ls_init_kernel"):
             cur = [d]
@@ -251,9 +251,10 @@ def summarize(dirpath, sweep_settings):
              "Command (from the repository root, DIR = an output folder):", "", "```",
              PROFILE_RUNS["trace"], "python3 bench.py --summarize DIR", "```", "",
              f"Each setting runs {per_call} forward calls (1 warm-up + 2 timed). A call is one fused "
-             "`gpa_forward_kernel` launch, or the streamed sequence `ls_init`, per block of 16 orders "
-             "(`ls_rows_x3` + `ls_cols_x3s` for the Gaussian from W = 40, `ls_rows_x3` + `ls_cols_mfma` below, "
-             "`ls_box_strip` for the box), `ls_final`.",
+             "launch (`gpa_forward_w_kernel`, the tile compiled for its support W <= 21, else "
+             "`gpa_forward_kernel`), or the streamed sequence `ls_init`, per block of orders (16 orders: "
+             "`ls_rows_x3` + `ls_cols_x3s` for the Gaussian from W = 40, `ls_rows_x3` + `ls_cols_mfma` below; "
+             "32 or 16 orders: `ls_box_strip` for the box), `ls_final`.",
              "", "| kernel | calls | total ms | avg us | % |", "|---|---|---|---|---|"]
     for k, v in sorted(per_kernel.items(), key=lambda kv: -sum(kv[1])):
         lines.append(f"| `{k}` | {len(v)} | {sum(v) / 1e3:.2f} | {sum(v) / len(v):.1f} | "
@@ -546,7 +547,7 @@ def main():
     roofline_fused = None
     if fused:
         fd = max(fused, key=lambda r: r["ms"])
-        roofline_fused = dict(fd["roof"], setting=fd["setting"], kernel="gpa_forward_kernel (one launch)",
+        roofline_fused = dict(fd["roof"], setting=fd["setting"], kernel="fused tile (one launch)",
                               ms_per_call=fd["ms"], traffic=measured_traffic(fd["setting"]))
 
     extra = {}
