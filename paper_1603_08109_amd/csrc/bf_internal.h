@@ -168,7 +168,7 @@ int64_t ls_rows_x3_lds_bytes(int W);
 int64_t ls_cols_x3_lds_bytes(int W);
 hipError_t launch_rows_x3(const TileParams& p, const LsState& st, int n0, int K, int src, int grid, hipStream_t s);
 hipError_t launch_cols_x3(const TileParams& p, const LsState& st, int n0, int K, bool save, int grid, hipStream_t s);
-hipError_t launch_cols_x3s(const TileParams& p, const LsState& st, int n0, int K, bool save, hipStream_t s);
+hipError_t launch_cols_x3s(const TileParams& p, const LsState& st, int n0, int K, hipStream_t s);
 int64_t ls_cols_x3s_lds_bytes(int W);
 
 // pieces of the streamed sequence (an image of p.H rows)

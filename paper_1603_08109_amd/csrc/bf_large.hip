@@ -975,7 +975,7 @@ hipError_t launch_forward_ls(const TileParams& p, const LsState& st, bool save, 
       // at W = 39 the split-once pass is 4% faster).
       const bool x3s = !save && p.W >= 40 && (16 + 2 * p.W + 31) / 32 <= 6 && st.hbytes < (1LL << 31);
       if (x3s) {
-        e = launch_cols_x3s(p, st, n0, K, false, s);
+        e = launch_cols_x3s(p, st, n0, K, s);
       } else if (p.W >= 40) {
         e = launch_cols_x3(p, st, n0, K, save, gfir16, s);
       } else {

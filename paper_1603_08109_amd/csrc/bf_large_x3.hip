@@ -29,10 +29,10 @@
 // (operand reads of step q + 1 under the products of step q), with one
 // barrier per order.
 // Column pass (ls_cols_x3s, the plain forward up to 6 k-steps): tiles of 32
-// columns x 64 rows; each order's window is loaded into registers while the
-// previous order multiplies and split once per workgroup into three
-// column-major bfloat16 planes in LDS, from which a lane's operand is one
-// 16-byte read per plane.  Column pass with saved state or 7-8 k-steps
+// columns x 128 rows; each order's window is loaded into registers while the
+// previous order multiplies and split once per workgroup into one of two
+// sets of three column-major bfloat16 planes in LDS, from which a lane's
+// operand is one 16-byte read per plane.  Column pass with saved state or 7-8 k-steps
 // (ls_cols_x3): 64 x 64 tiles, the float32 window staged by direct-to-LDS
 // loads, each lane splitting its 8 rows of one column in registers.  In every
 // pass a wave's blocks that read the same data slice one k-step apart share
@@ -483,89 +483,7 @@ static hipError_t cols_x3_t(const TileParams& p, const LsState& st, int n0, int 
   }
 }
 
-// Column pass, split-once form.  Tiles of 32 columns x 64 output rows, four
-// waves: wave w takes column block cb = w >> 1 (16 columns) and the row
-// blocks rb = w & 1 and rb + 2, which read the same 32-row window slice one
-// k-step apart, as in ls_cols_x3_kernel.  The window of order k (rows tr0 ..
-// tr0 + R - 1 of the padded row-filtered image, R = x3_cols_rows(W)) is
-// loaded into registers, a thread owning items of 8 consecutive rows of one
-// column, and split ONCE into three bfloat16 planes in LDS, column-major:
-// plane[column][row] with column stride RP = R + 8 elements (8 mod 16), so
-// the 16-byte operand reads of 16 lanes on consecutive columns fall on
-// distinct banks, and a lane's B operand (8 consecutive rows of one column)
-// is one 16-byte read per plane.  The loads of order k + 1 are in flight
-// while order k multiplies; two workgroups share a compute unit, so one's
-// splits overlap the other's matrix-core steps.
-constexpr int kX3sThreads = 256;
-constexpr int kX3sCols = 32;
-
-__host__ __device__ inline int x3s_rp(int W) { return x3_cols_rows(W) + 8; }
-
-int64_t ls_cols_x3s_lds_bytes(int W) {
-  const int64_t planes = 3LL * kX3sCols * x3s_rp(W) * 2;
-  const int64_t table = (int64_t)x3_steps(W) * 3 * 64 * 16;
-  return planes > table ? planes : table;
-}
-
-template <int S>
-struct X3sGeom {
-  static constexpr int R = 32 * S + 48;                       // window rows
-  static constexpr int RP = R + 8;                            // column stride of a plane
-  static constexpr int GROUPS = R / 8;                        // items of 8 rows per column
-  static constexpr int ITEMS = (GROUPS * kX3sCols + kX3sThreads - 1) / kX3sThreads;  // per thread
-};
-
-// The window of one order into registers: buffer loads with one VGPR offset
-// per item and the row step in the scalar offset (a per-load 64-bit address
-// for 32 loads in flight costs 64 VGPRs).  The buffer spans one row-filtered
-// image (its padded rows), and loads past it return 0.
-template <int S, bool MIRROR>
-__device__ __forceinline__ void x3s_load(const float* __restrict__ Hk, int64_t hbytes, int64_t pitch, int tr0,
-                                         int c0, int W, int H, float (&reg)[X3sGeom<S>::ITEMS][8]) {
-  using G = X3sGeom<S>;
-  const __amdgpu_buffer_rsrc_t rs =
-      __builtin_amdgcn_make_buffer_rsrc((void*)Hk, (short)0, (int)hbytes, 0x00020000);
-  const int col = threadIdx.x & (kX3sCols - 1);
-  const int g0 = threadIdx.x / kX3sCols;
-  const int rstep = (int)(pitch * 4);
-#pragma unroll
-  for (int i = 0; i < G::ITEMS; ++i) {
-    const int grp = min(g0 + (kX3sThreads / kX3sCols) * i, G::GROUPS - 1);  // idle items reload a valid group
-    if (MIRROR) {
-#pragma unroll
-      for (int j = 0; j < 8; ++j) {
-        const int R = reflect_index(tr0 + 8 * grp + j - W, H) + W;  // padded row: image row R - W
-        reg[i][j] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, (R * (int)pitch + c0 + col) * 4, 0, 0));
-      }
-    } else {
-      const int vo = ((tr0 + 8 * grp) * (int)pitch + c0 + col) * 4;
-#pragma unroll
-      for (int j = 0; j < 8; ++j) reg[i][j] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, vo, j * rstep, 0));
-    }
-  }
-}
-
-template <int S>
-__device__ __forceinline__ void x3s_split(const float (&reg)[X3sGeom<S>::ITEMS][8], __bf16* Pl) {
-  using G = X3sGeom<S>;
-  constexpr int PS = kX3sCols * G::RP;  // elements per plane
-  const int col = threadIdx.x & (kX3sCols - 1);
-  const int g0 = threadIdx.x / kX3sCols;
-#pragma unroll
-  for (int i = 0; i < G::ITEMS; ++i) {
-    const int grp = g0 + (kX3sThreads / kX3sCols) * i;
-    if (grp < G::GROUPS) {
-      uint4 h, m, l;
-      split3_pair(reg[i][0], reg[i][1], h.x, m.x, l.x);
-      split3_pair(reg[i][2], reg[i][3], h.y, m.y, l.y);
-      split3_pair(reg[i][4], reg[i][5], h.z, m.z, l.z);
-      split3_pair(reg[i][6], reg[i][7], h.w, m.w, l.w);
-      *(uint4*)(Pl + col * G::RP + 8 * grp) = h;
-      *(uint4*)(Pl + PS + col * G::RP + 8 * grp) = m;
-      *(uint4*)(Pl + 2 * PS + col * G::RP + 8 * grp) = l;
-    }
-  }
-}
+constexpr int kX3sCols = 32;  // columns of a split-once column-pass tile
 
 // a lane's B operand at element offset o of the planes (8 rows of one column)
 template <int RP>
@@ -578,35 +496,120 @@ __device__ __forceinline__ X3 x3s_operand(const __bf16* Pl, int o) {
   return r;
 }
 
-template <int S, bool SAVE, bool WIDE>
-__global__ __launch_bounds__(kX3sThreads, 2) void ls_cols_x3s_kernel(TileParams p, LsState st, int n0, int K) {
+
+// Column pass, split-once form: tiles of 32 columns x 128 output rows, eight
+// waves, one workgroup per compute unit.  Wave w takes column block
+// cb = w >> 2 (16 columns) and the row blocks rb = (w & 1) + 4 ((w >> 1) & 1)
+// and rb + 2, which read the same 32-row window slice one k-step apart, as in
+// ls_cols_x3_kernel.  An order's window (R = 32 S + 112 rows of the padded
+// row-filtered image) is loaded into registers, a thread owning items of 8
+// consecutive rows of one column, and split ONCE into three bfloat16 planes
+// in LDS, column-major: plane[column][row] with column stride RP = R + 8
+// elements (8 mod 16), so the 16-byte operand reads of lanes on consecutive
+// columns fall on distinct banks, and a lane's B operand (8 consecutive rows
+// of one column) is one 16-byte read per plane.  Two sets of planes
+// alternate between orders: one barrier per order, and each wave splits its
+// share of order k + 1 into the other set between its matrix-core steps on
+// order k, issuing the loads of order k + 2 as each item's registers free
+// up.  The arithmetic and its order are those of ls_cols_x3, so the outputs
+// are bit-identical.
+constexpr int kX3sThreads = 512;
+constexpr int kX3sRows = 128;
+
+template <int S>
+struct X3sGeom {
+  static constexpr int R = 32 * S + 112;                                       // window rows
+  static constexpr int RP = R + 8;                                             // column stride, 8 mod 16
+  static constexpr int GROUPS = R / 8;                                         // items of 8 rows per column
+  static constexpr int ITEMS = (GROUPS * kX3sCols + kX3sThreads - 1) / kX3sThreads;  // per thread
+  static constexpr int PS = kX3sCols * RP;                                     // elements per plane
+  static constexpr int BUF = 3 * PS;                                           // elements per set of planes
+};
+
+int64_t ls_cols_x3s_lds_bytes(int W) {
+  const int64_t rp = 32LL * x3_steps(W) + 120;
+  return 2 * 3 * kX3sCols * rp * 2;  // two sets of planes (the Toeplitz table, smaller, passes through the second)
+}
+
+// item i (8 rows of one column) of an order's window into registers; past the
+// buffer (the padded rows of one row-filtered image) loads return 0
+template <int S, bool MIRROR>
+__device__ __forceinline__ void x3s_load_item(__amdgpu_buffer_rsrc_t rs, int pitch, int tr0, int c0, int W, int H,
+                                              int i, float (&r)[8]) {
   using G = X3sGeom<S>;
-  constexpr int PS = kX3sCols * G::RP;
+  const int col = threadIdx.x & (kX3sCols - 1);
+  const int g0 = threadIdx.x / kX3sCols;
+  const int grp = min(g0 + (kX3sThreads / kX3sCols) * i, G::GROUPS - 1);  // idle items reload a valid group
+  if (MIRROR) {
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int Rr = reflect_index(tr0 + 8 * grp + j - W, H) + W;  // padded row: image row Rr - W
+      r[j] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, (Rr * pitch + c0 + col) * 4, 0, 0));
+    }
+  } else {
+    const int vo = ((tr0 + 8 * grp) * pitch + c0 + col) * 4;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) r[j] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, vo, j * pitch * 4, 0));
+  }
+}
+
+template <int S>
+__device__ __forceinline__ void x3s_split_item(const float (&r)[8], int i, __bf16* Pl) {
+  using G = X3sGeom<S>;
+  const int col = threadIdx.x & (kX3sCols - 1);
+  const int grp = threadIdx.x / kX3sCols + (kX3sThreads / kX3sCols) * i;
+  if (grp < G::GROUPS) {
+    uint4 h, m, l;
+    split3_pair(r[0], r[1], h.x, m.x, l.x);
+    split3_pair(r[2], r[3], h.y, m.y, l.y);
+    split3_pair(r[4], r[5], h.z, m.z, l.z);
+    split3_pair(r[6], r[7], h.w, m.w, l.w);
+    *(uint4*)(Pl + col * G::RP + 8 * grp) = h;
+    *(uint4*)(Pl + G::PS + col * G::RP + 8 * grp) = m;
+    *(uint4*)(Pl + 2 * G::PS + col * G::RP + 8 * grp) = l;
+  }
+}
+
+template <int S, bool MIRROR>
+__global__ __launch_bounds__(kX3sThreads) void ls_cols_x3s_kernel(TileParams p, LsState st, int n0, int K) {
+  using G = X3sGeom<S>;
   extern __shared__ float lds[];
-  __bf16* Pl = (__bf16*)lds;
+  __bf16* Pl = (__bf16*)lds;  // two sets of G::BUF elements
   const int tiles_x = (p.Wd + kX3sCols - 1) / kX3sCols;
-  const int tiles_y = (p.H + 63) / 64;
+  const int tiles_y = (p.H + kX3sRows - 1) / kX3sRows;
   int ty, tx;
   band_tile(xcd_remap(blockIdx.x, gridDim.x), tiles_x, tiles_y, ty, tx);
   const int lane = threadIdx.x & 63;
   const int wv = threadIdx.x >> 6;
-  const int rb = wv & 1, cb = wv >> 1;
-  const int tr0 = ty * 64, c0 = tx * kX3sCols;
+  const int cb = wv >> 2, rb = (wv & 1) + 4 * ((wv >> 1) & 1);
+  const int tr0 = ty * kX3sRows, c0 = tx * kX3sCols;
   const int W = p.W;
+  const int pitch = (int)st.pitch;
+  auto rsrc = [&](int k) {
+    return __builtin_amdgcn_make_buffer_rsrc((void*)st.H[k], (short)0, (int)st.hbytes, 0x00020000);
+  };
   float reg[G::ITEMS][8];
-  if (p.mirror)
-    x3s_load<S, true>(st.H[0], st.hbytes, st.pitch, tr0, c0, W, p.H, reg);
-  else
-    x3s_load<S, false>(st.H[0], st.hbytes, st.pitch, tr0, c0, W, p.H, reg);
-  // the Toeplitz operands pass through the plane area into registers
-  fill_toeplitz_x3<kX3sThreads>(Pl, W, p.taps + kTapPad);
+  {
+    const __amdgpu_buffer_rsrc_t rs = rsrc(0);
+#pragma unroll
+    for (int i = 0; i < G::ITEMS; ++i) x3s_load_item<S, MIRROR>(rs, pitch, tr0, c0, W, p.H, i, reg[i]);
+  }
+  // the Toeplitz operands pass through the second set of planes into registers
+  fill_toeplitz_x3<kX3sThreads>(Pl + G::BUF, W, p.taps + kTapPad);
   __syncthreads();
   X3 T[S];
 #pragma unroll
-  for (int q = 0; q < S; ++q) T[q] = x3_table(Pl, q, lane);
+  for (int q = 0; q < S; ++q) T[q] = x3_table(Pl + G::BUF, q, lane);
+#pragma unroll
+  for (int i = 0; i < G::ITEMS; ++i) x3s_split_item<S>(reg[i], i, Pl);
+  if (K > 1) {
+    const __amdgpu_buffer_rsrc_t rs = rsrc(1);
+#pragma unroll
+    for (int i = 0; i < G::ITEMS; ++i) x3s_load_item<S, MIRROR>(rs, pitch, tr0, c0, W, p.H, i, reg[i]);
+  }
   const int pr0 = tr0 + 16 * rb + 4 * (lane >> 4);
   const int pc = c0 + 16 * cb + (lane & 15);
-  typename std::conditional<WIDE, WidePix<8>, LsPix<8, SAVE>>::type px;
+  LsPix<8, false> px;
 #pragma unroll
   for (int b = 0; b < 2; ++b) {
     const int nr = pc < p.Wd ? max(0, min(4, p.H - (pr0 + 32 * b))) : 0;
@@ -616,23 +619,19 @@ __global__ __launch_bounds__(kX3sThreads, 2) void ls_cols_x3s_kernel(TileParams 
   const int obase = (16 * cb + (lane & 15)) * G::RP + 16 * rb + 8 * (lane >> 4);
   for (int k = 0; k < K; ++k) {
     const int n = n0 + k;
-    __syncthreads();  // every wave has read order k - 1's planes (and the table)
-    x3s_split<S>(reg, Pl);
-    __syncthreads();  // order k's planes are written
-    if (k + 1 < K) {
-      if (p.mirror)
-        x3s_load<S, true>(st.H[k + 1], st.hbytes, st.pitch, tr0, c0, W, p.H, reg);
-      else
-        x3s_load<S, false>(st.H[k + 1], st.hbytes, st.pitch, tr0, c0, W, p.H, reg);
-    }
+    // order k's planes are written, and every wave has read order k - 1's (the set written next)
+    __syncthreads();
+    const __bf16* cur = Pl + (k & 1) * G::BUF;
+    __bf16* nxt = Pl + ((k + 1) & 1) * G::BUF;
+    const bool split_next = k + 1 < K;
+    const bool load_next = k + 2 < K;
+    const __amdgpu_buffer_rsrc_t rs = rsrc(load_next ? k + 2 : k);
     mf4 acc[2] = {mf4{0.f, 0.f, 0.f, 0.f}, mf4{0.f, 0.f, 0.f, 0.f}};
-    // operands one step ahead of the products; the compiler fence keeps the
-    // reads of later steps below (hoisting them all costs registers: spills)
-    X3 bv = x3s_operand<G::RP>(Pl, obase);
+    X3 bv = x3s_operand<G::RP>(cur, obase);
 #pragma unroll
     for (int q = 0; q <= S; ++q) {
       X3 bn;
-      if (q < S) bn = x3s_operand<G::RP>(Pl, obase + 32 * (q + 1));
+      if (q < S) bn = x3s_operand<G::RP>(cur, obase + 32 * (q + 1));
       // block rb at step q, block rb + 2 at step q - 1
       if (q >= 1 && q < S)
         mfma_x3_pair(T[q < S ? q : 0], bv, acc[0], T[q >= 1 ? q - 1 : 0], bv, acc[1]);
@@ -640,22 +639,19 @@ __global__ __launch_bounds__(kX3sThreads, 2) void ls_cols_x3s_kernel(TileParams 
         acc[0] = mfma_x3(T[q], bv, acc[0]);
       else
         acc[1] = mfma_x3(T[q >= 1 ? q - 1 : 0], bv, acc[1]);
+      // item q of order k + 1 into the other set, then its registers take order k + 2
+      if (q < G::ITEMS) {
+        if (split_next) x3s_split_item<S>(reg[q], q, nxt);
+        if (load_next) x3s_load_item<S, MIRROR>(rs, pitch, tr0, c0, W, p.H, q, reg[q]);
+      }
       asm volatile("" ::: "memory");
       bv = bn;
     }
-    if constexpr (WIDE) {
-      const double g1 = p.isq[n + 1], sn = p.sq[n];
+    const float in1 = p.inv_tab[n + 1];
 #pragma unroll
-      for (int b = 0; b < 2; ++b)
+    for (int b = 0; b < 2; ++b)
 #pragma unroll
-        for (int v = 0; v < 4; ++v) px.fold(4 * b + v, n, p.N, acc[b][v], g1, sn);
-    } else {
-      const float in1 = p.inv_tab[n + 1];
-#pragma unroll
-      for (int b = 0; b < 2; ++b)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) px.fold(4 * b + v, n, p.N, acc[b][v], in1);
-    }
+      for (int v = 0; v < 4; ++v) px.fold(4 * b + v, n, p.N, acc[b][v], in1);
   }
 #pragma unroll
   for (int b = 0; b < 2; ++b) {
@@ -664,38 +660,37 @@ __global__ __launch_bounds__(kX3sThreads, 2) void ls_cols_x3s_kernel(TileParams 
   }
 }
 
-template <int S, bool SAVE, bool WIDE>
+template <int S, bool MIRROR>
 static hipError_t cols_x3s_s(const TileParams& p, const LsState& st, int n0, int K, hipStream_t s) {
   static bool attr = false;
+  const int64_t lb = ls_cols_x3s_lds_bytes(p.W);
   if (!attr) {
-    hipError_t e = hipFuncSetAttribute((const void*)ls_cols_x3s_kernel<S, SAVE, WIDE>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)ls_cols_x3s_lds_bytes(p.W));
+    hipError_t e = hipFuncSetAttribute((const void*)ls_cols_x3s_kernel<S, MIRROR>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lb);
     if (e != hipSuccess) return e;
     attr = true;
   }
-  const int grid = ((p.H + 63) / 64) * ((p.Wd + kX3sCols - 1) / kX3sCols);
-  hipLaunchKernelGGL((ls_cols_x3s_kernel<S, SAVE, WIDE>), dim3(grid), dim3(kX3sThreads),
-                     (size_t)ls_cols_x3s_lds_bytes(p.W), s, p, st, n0, K);
+  const int grid = ((p.H + kX3sRows - 1) / kX3sRows) * ((p.Wd + kX3sCols - 1) / kX3sCols);
+  hipLaunchKernelGGL((ls_cols_x3s_kernel<S, MIRROR>), dim3(grid), dim3(kX3sThreads), (size_t)lb, s, p, st, n0, K);
   return hipGetLastError();
 }
 
-template <bool SAVE, bool WIDE>
-static hipError_t cols_x3s_t(const TileParams& p, const LsState& st, int n0, int K, hipStream_t s) {
+template <bool MIRROR>
+static hipError_t cols_x3s_m(const TileParams& p, const LsState& st, int n0, int K, hipStream_t s) {
   switch (x3_steps(p.W)) {
-    case 1: return cols_x3s_s<1, SAVE, WIDE>(p, st, n0, K, s);
-    case 2: return cols_x3s_s<2, SAVE, WIDE>(p, st, n0, K, s);
-    case 3: return cols_x3s_s<3, SAVE, WIDE>(p, st, n0, K, s);
-    case 4: return cols_x3s_s<4, SAVE, WIDE>(p, st, n0, K, s);
-    case 5: return cols_x3s_s<5, SAVE, WIDE>(p, st, n0, K, s);
-    case 6: return cols_x3s_s<6, SAVE, WIDE>(p, st, n0, K, s);
-    case 7: return cols_x3s_s<7, SAVE, WIDE>(p, st, n0, K, s);
-    case 8: return cols_x3s_s<8, SAVE, WIDE>(p, st, n0, K, s);
+    case 1: return cols_x3s_s<1, MIRROR>(p, st, n0, K, s);
+    case 2: return cols_x3s_s<2, MIRROR>(p, st, n0, K, s);
+    case 3: return cols_x3s_s<3, MIRROR>(p, st, n0, K, s);
+    case 4: return cols_x3s_s<4, MIRROR>(p, st, n0, K, s);
+    case 5: return cols_x3s_s<5, MIRROR>(p, st, n0, K, s);
+    case 6: return cols_x3s_s<6, MIRROR>(p, st, n0, K, s);
     default: return hipErrorInvalidValue;
   }
 }
 
-hipError_t launch_cols_x3s(const TileParams& p, const LsState& st, int n0, int K, bool save, hipStream_t s) {
-  return save ? cols_x3s_t<true, false>(p, st, n0, K, s) : cols_x3s_t<false, false>(p, st, n0, K, s);
+hipError_t launch_cols_x3s(const TileParams& p, const LsState& st, int n0, int K, hipStream_t s) {
+  if (ls_cols_x3s_lds_bytes(p.W) > max_lds_bytes() || st.hbytes >= (1LL << 31)) return hipErrorInvalidValue;
+  return p.mirror ? cols_x3s_m<true>(p, st, n0, K, s) : cols_x3s_m<false>(p, st, n0, K, s);
 }
 
 // one kernel per k-step count S = x3_steps(W) (W <= 120: S <= 8), the Toeplitz operands in registers
