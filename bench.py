@@ -49,7 +49,7 @@ MFMA_F32_PEAK_TFLOPS = 157.3
 # FP32-product ceiling of that arithmetic is a sixth of it.
 MFMA_BF16_PEAK_TFLOPS = 2500.0
 SPLIT_PRODUCTS = 6
-SPLIT_MIN_W = 40  # from this support both streamed passes use the split arithmetic
+SPLIT_MIN_W = 31  # from this support both streamed passes use the split arithmetic
 
 SWEEP = ([("gauss", dict(sigma_s=s), r) for s in (3.0, 10.0, 25.0) for r in (10.0, 30.0, 50.0)]
          + [("box", dict(W=w), r) for w in (10, 30, 75) for r in (10.0, 30.0, 50.0)])
@@ -253,7 +253,7 @@ def summarize(dirpath, sweep_settings):
              f"Each setting runs {per_call} forward calls (1 warm-up + 2 timed). A call is one fused "
              "launch (`gpa_forward_w_kernel`, the tile compiled for its support W <= 21, else "
              "`gpa_forward_kernel`), or the streamed sequence `ls_init`, per block of orders (16 orders: "
-             "`ls_rows_x3` + `ls_cols_x3s` for the Gaussian from W = 40, `ls_rows_x3` + `ls_cols_mfma` below; "
+             "`ls_rows_x3` + `ls_cols_x3s` for the Gaussian from W = 31, `ls_rows_x3` + `ls_cols_mfma` below; "
              "32 or 16 orders: `ls_box_strip` for the box), `ls_final`.",
              "", "| kernel | calls | total ms | avg us | % |", "|---|---|---|---|---|"]
     for k, v in sorted(per_kernel.items(), key=lambda kv: -sum(kv[1])):

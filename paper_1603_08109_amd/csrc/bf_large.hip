@@ -954,9 +954,9 @@ hipError_t launch_forward_ls(const TileParams& p, const LsState& st, bool save, 
     const int K = std::min(kLsBlock, p.N + 1 - n0);
     // row pass
     if (x3) {
-      // split row pass always; split column pass from W = 40 (4096^2, sigma_r = 30,
-      // ms per call, rows+cols float32 / split rows / both split: W = 30 4.40 / 4.00 /
-      // 4.14, W = 51 5.82 / 4.95 / 4.78, W = 75 7.40 / 6.09 / 5.93)
+      // split row pass always (4096^2, sigma_r = 30, ms per call, rows+cols
+      // float32 / split rows / both split by the two-wave column pass: W = 30
+      // 4.40 / 4.00 / 4.14, W = 51 5.82 / 4.95 / 4.78, W = 75 7.40 / 6.09 / 5.93)
       e = launch_rows_x3(p, st, n0, K, src, grow, s);
     } else {
       if (rows_mfma)
@@ -968,12 +968,12 @@ hipError_t launch_forward_ls(const TileParams& p, const LsState& st, bool save, 
     if (e != hipSuccess) return e;
     // column pass
     if (x3) {
-      // from W = 40 the column pass splits its window once per workgroup
+      // from W = 31 the column pass splits its window once per workgroup
       // (ls_cols_x3s) where its registers allow (up to 6 k-steps, plain
-      // forward); 4096^2, sigma_r = 10, W = 75: 25.1 -> 23.6 ms per call.  Below
-      // W = 40 the float32 matrix-core column pass stays faster (W = 30: 3%;
-      // at W = 39 the split-once pass is 4% faster).
-      const bool x3s = !save && p.W >= 40 && (16 + 2 * p.W + 31) / 32 <= 6 && st.hbytes < (1LL << 31);
+      // forward).  4096^2, sigma_r = 10, ms per call with the float32
+      // matrix-core column pass / the split-once pass: W = 26 16.7 / 17.1,
+      // W = 30 17.24 / 17.17, W = 33 17.9 / 17.3, W = 39 18.8 / 17.3.
+      const bool x3s = !save && p.W >= 31 && (16 + 2 * p.W + 31) / 32 <= 6 && st.hbytes < (1LL << 31);
       if (x3s) {
         e = launch_cols_x3s(p, st, n0, K, s);
       } else if (p.W >= 40) {

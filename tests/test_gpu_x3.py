@@ -92,10 +92,11 @@ def test_split_saved_state():
 
 
 @pytest.mark.parametrize("ss,shape", [(2.0, (70, 300)), (15.0, (130, 270)), (21.3, (140, 200)),
-                                      (33.3, (230, 150))])
+                                      (33.3, (230, 150)), (11.0, (300, 170))])
 def test_split_every_step_count(ss, shape):
     # the passes are compiled per k-step count S = ceil((16 + 2W) / 32): W = 6 (S = 1), 45 (S = 4,
-    # split columns), 64 (S = 5), 100 (S = 7); the other counts are covered above
+    # split columns), 64 (S = 5), 100 (S = 7), 33 (S = 3, the split-once column pass from W = 31:
+    # three 128-row tiles, the last ragged); the other counts are covered above
     f = synthimg.gen1(*shape, 94)
     x3, f32, plan, fx = _pair(f, ss, 30.0)
     ref = G.gpa_alg2(fx, K.taps1d("gauss", ss), 30.0, plan.info.N, 127.5)
