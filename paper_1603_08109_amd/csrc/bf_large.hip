@@ -409,49 +409,36 @@ __global__ __launch_bounds__(kThreads) void ls_cols_fir_kernel(TileParams p, LsS
 // (zero outside the image), the box sum is F_bar_n(r, c) = sum_{|dc| <= W}
 // C_n(r, c + dc).
 // ---------------------------------------------------------------------------
-// Inclusive prefix sum of a double over the 64 lanes of a wave: row_shr
-// steps inside each 16-lane row, then row_bcast:15 and row_bcast:31 carry the
-// row totals (DPP moves of both 32-bit halves; no LDS traffic).
+// Segmented inclusive prefix sum of a float over the 64 lanes of a wave, in
+// chunks of CH = 16, 32 or 64 lanes: row_shr steps inside each 16-lane row,
+// then row_bcast:15 into rows 1 and 3 (chunks of 32) and row_bcast:31 into
+// rows 2 and 3 (one chunk of 64).  Source lanes outside the row (or rows the
+// mask leaves out) contribute 0.
 template <int CTRL, int ROW_MASK>
-__device__ __forceinline__ double dpp_d(double v) {  // lanes of disabled rows read 0
-  const int lo = __double2loint(v), hi = __double2hiint(v);
-  const int l2 = __builtin_amdgcn_update_dpp(0, lo, CTRL, ROW_MASK, 0xF, true);
-  const int h2 = __builtin_amdgcn_update_dpp(0, hi, CTRL, ROW_MASK, 0xF, true);
-  return __hiloint2double(h2, l2);
-}
-template <int CTRL>
-__device__ __forceinline__ double dpp_shr(double v) {  // all rows; lanes shifted in from outside the row read 0
-  const int lo = __double2loint(v), hi = __double2hiint(v);
-  const int l2 = __builtin_amdgcn_mov_dpp(lo, CTRL, 0xF, 0xF, true);
-  const int h2 = __builtin_amdgcn_mov_dpp(hi, CTRL, 0xF, 0xF, true);
-  return __hiloint2double(h2, l2);
-}
-__device__ __forceinline__ double wave_scan_incl(double v) {
-  v += dpp_shr<0x111>(v);     // row_shr:1
-  v += dpp_shr<0x112>(v);     // row_shr:2
-  v += dpp_shr<0x114>(v);     // row_shr:4
-  v += dpp_shr<0x118>(v);     // row_shr:8
-  v += dpp_d<0x142, 0xA>(v);  // row_bcast:15 into rows 1, 3
-  v += dpp_d<0x143, 0xC>(v);  // row_bcast:31 into rows 2, 3
-  return v;
+__device__ __forceinline__ float dpp_f(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROW_MASK, 0xF, true));
 }
 
-// G independent inclusive wave scans, step by step, so that each step's DPP
-// moves of one value fill the wait states of the others
+// G independent segmented scans, step by step, so that each step's DPP
+// operand of one value fills the wait states of the others
 template <int G>
-__device__ __forceinline__ void wave_scan_incl_n(double (&v)[G]) {
+__device__ __forceinline__ void wave_scan_seg_n(float (&v)[G], int ch) {
 #pragma unroll
-  for (int g = 0; g < G; ++g) v[g] += dpp_shr<0x111>(v[g]);
+  for (int g = 0; g < G; ++g) v[g] += dpp_f<0x111, 0xF>(v[g]);  // row_shr:1
 #pragma unroll
-  for (int g = 0; g < G; ++g) v[g] += dpp_shr<0x112>(v[g]);
+  for (int g = 0; g < G; ++g) v[g] += dpp_f<0x112, 0xF>(v[g]);  // row_shr:2
 #pragma unroll
-  for (int g = 0; g < G; ++g) v[g] += dpp_shr<0x114>(v[g]);
+  for (int g = 0; g < G; ++g) v[g] += dpp_f<0x114, 0xF>(v[g]);  // row_shr:4
 #pragma unroll
-  for (int g = 0; g < G; ++g) v[g] += dpp_shr<0x118>(v[g]);
+  for (int g = 0; g < G; ++g) v[g] += dpp_f<0x118, 0xF>(v[g]);  // row_shr:8
+  if (ch >= 32) {
 #pragma unroll
-  for (int g = 0; g < G; ++g) v[g] += dpp_d<0x142, 0xA>(v[g]);
+    for (int g = 0; g < G; ++g) v[g] += dpp_f<0x142, 0xA>(v[g]);  // row_bcast:15 into rows 1, 3
+  }
+  if (ch >= 64) {
 #pragma unroll
-  for (int g = 0; g < G; ++g) v[g] += dpp_d<0x143, 0xC>(v[g]);
+    for (int g = 0; g < G; ++g) v[g] += dpp_f<0x143, 0xC>(v[g]);  // row_bcast:31 into rows 2, 3
+  }
 }
 
 constexpr int kStripThreads = 256;
@@ -465,14 +452,18 @@ constexpr int kStripThreads = 256;
 // row:
 //   1. every thread writes the column sums of its columns for the KB orders
 //      into LDS (rounded to float32);
-//   2. (barrier) wave w takes the orders w, w + 4, ...  For each,
-//      lane l sums strip columns 4 CPT l .. 4 CPT l + 4 CPT - 1 into a float64
-//      prefix, a DPP wave scan joins the lanes, the inclusive prefix S goes to
-//      the wave's own LDS row (read back by the same wave: no barrier), and
-//      the window sums S(c + W) - S(c - W - 1) of the output columns
-//      overwrite that order's column sums in LDS (float32);
-//   3. (barrier) each thread folds the window sums of its output columns into
-//      eqs. (P), (Q) in float64.
+//   2. (barrier) wave w takes the orders w, w + 4, ...  The strip row is cut
+//      into chunks of L = CH CPL >= 2W + 1 columns (CH lanes of CPL = 4 CPT
+//      columns each).  Lane l sums its CPL columns, a segmented DPP scan
+//      joins the lanes of each chunk, and the prefix S within the chunk
+//      overwrites the column sums in place (float32);
+//   3. (barrier) each thread forms the window sums of its output columns c
+//      from S and folds them into eqs. (P), (Q) in float64.  With a = c - W -
+//      1 and b = c + W: S(b) - S(a) when both lie in one chunk, else S(b) +
+//      (T - S(a)) with T the total of a's chunk (a window of 2W + 1 <= L
+//      columns meets at most two chunks).  Every partial sum is therefore
+//      bounded by two chunk sums, so the float32 rounding is that of a direct
+//      sum over two windows, not of a prefix over the whole strip.
 // Then every thread slides its column sums down one row: the entering and
 // leaving rows' F^_n follow from F^_{n0} and y by the power recursion, in
 // float64.  The fold has no per-order tests: the factor 1/(n + 1) that
@@ -480,37 +471,35 @@ constexpr int kStripThreads = 256;
 // and the orders past N in the last block add nothing (eq. (Q) stops at
 // n = N - 1 and eq. (P) at n = N).  The per-pixel state between launches is
 // a_{n0 - 1}, z and the two sums: a_{n0} = a_{n0 - 1} (z / n0) is recomputed
-// with the rounding the chain itself applied, so it is the same float.  Each wave scans SG
-// orders together, one LDS prefix row each, so their scans and LDS round
-// trips overlap.  The rows entering the segment advance the F^ state image.
+// with the rounding the chain itself applied, so it is the same float.  The
+// rows entering the segment advance the F^ state image.
 // ---------------------------------------------------------------------------
 template <int CPT, int KB>
 struct StripGeom {
   static constexpr int SC = 256 * CPT;              // strip columns
   static constexpr int CPL = 4 * CPT;               // columns per lane in the row scan
   static constexpr int CPITCH = SC + 4 * (SC / 32);  // float32 row: 4 floats of padding per 32 columns
-  static constexpr int SPITCH = SC + 4 + 2 * ((SC + 2) / 32);  // float64 prefix row (slots 0 .. SC + 1)
-  static constexpr int SG = CPT == 1 ? 4 : 2;       // orders a wave scans together (one prefix row each)
-  static constexpr int LDS_BYTES = KB * CPITCH * 4 + 4 * SG * SPITCH * 8;
+  static constexpr int LDS_BYTES = 2 * KB * CPITCH * 4;  // two sets of rows, used by alternate image rows
 };
 // float32 column c of a row, 4 floats of padding after every 32: the 16-byte
 // reads of 8 lanes (one LDS cycle) fall on distinct banks for runs of 16 or
 // 32 bytes per lane, and 32 consecutive columns stay contiguous for the
 // 4- and 8-byte accesses
 __device__ __forceinline__ int strip_cpos(int c) { return c + 4 * (c >> 5); }
-// float64 prefix slot s (S(c) at slot c + 2, S(-1) = 0 at slot 1): the
-// 16-byte writes of lanes 4 apart (64 bytes per lane) fall on distinct banks
-__device__ __forceinline__ int strip_spos(int s) { return s + 2 * (s >> 5); }
+
+// lanes per scan chunk: the smallest of 16, 32, 64 whose CPL-column chunks
+// hold a whole window of 2W + 1 columns
+__host__ __device__ inline int strip_chunk_lanes(int cpl, int W) {
+  return 16 * cpl >= 2 * W + 1 ? 16 : (32 * cpl >= 2 * W + 1 ? 32 : 64);
+}
 
 template <int CPT, bool SAVE, int KB>
-__global__ __launch_bounds__(kStripThreads) void ls_box_strip_kernel(TileParams p, LsState st, int n0, int src,
+__global__ __launch_bounds__(kStripThreads, 2) void ls_box_strip_kernel(TileParams p, LsState st, int n0, int src,
                                                                       int seg_rows) {
   using G = StripGeom<CPT, KB>;
-  constexpr int SC = G::SC, CPL = G::CPL, SG = G::SG;
-  static_assert((KB / 4) % SG == 0, "a wave's orders: whole scan groups");
-  extern __shared__ double dlds[];
-  float* Cb = (float*)dlds;                  // KB x CPITCH
-  double* Sb = dlds + (KB * G::CPITCH) / 2;  // 4 SG x SPITCH
+  constexpr int SC = G::SC, CPL = G::CPL, NW = KB / 4;
+  constexpr int SG = CPT == 1 ? NW : 2;  // orders a wave scans together
+  extern __shared__ float Cbuf[];  // 2 x KB x CPITCH
   const int W = p.W;
   const int OC = SC - 2 * W;
   const int nstrips = (p.Wd + OC - 1) / OC;
@@ -519,6 +508,8 @@ __global__ __launch_bounds__(kStripThreads) void ls_box_strip_kernel(TileParams 
   const int r_lo = seg * seg_rows, r_hi = min(r_lo + seg_rows, p.H);
   const int t = threadIdx.x;
   const int lane = t & 63, wv = t >> 6;
+  const int ch = strip_chunk_lanes(CPL, W);
+  const int L = ch * CPL;  // columns per scan chunk
   // this thread's strip columns CPT t + j (image columns c0 - W + CPT t + j)
   int gcs[CPT];
   bool col_ok[CPT], central[CPT];
@@ -530,6 +521,16 @@ __global__ __launch_bounds__(kStripThreads) void ls_box_strip_kernel(TileParams 
     gcs[j] = p.mirror ? reflect_index(gc, p.Wd) : gc;
     central[j] = sc >= W && sc < W + OC && gc < p.Wd;  // an output column of this strip
     gcol[j] = gc;
+  }
+  // the fold's columns: strip columns t + 256 j (consecutive lanes, consecutive
+  // columns)
+  int fcol[CPT];
+  bool fout[CPT];
+#pragma unroll
+  for (int j = 0; j < CPT; ++j) {
+    const int sc = t + 256 * j, gc = c0 - W + sc;
+    fout[j] = sc >= W && sc < W + OC && gc < p.Wd;
+    fcol[j] = gc;
   }
   const float* Fin = st.F[src];
   float* Fout = st.F[src ^ 1];
@@ -545,11 +546,6 @@ __global__ __launch_bounds__(kStripThreads) void ls_box_strip_kernel(TileParams 
   }
   // the factor that took a_{n0 - 1} to a_{n0} at the end of the previous block
   const float in1_prev = (n0 >= 1 && n0 < p.N) ? p.inv_tab[n0] : 0.f;
-  double* srow = Sb + wv * SG * G::SPITCH;  // this wave's SG prefix rows
-  if (lane < SG) {
-    srow[lane * G::SPITCH + strip_spos(0)] = 0.0;
-    srow[lane * G::SPITCH + strip_spos(1)] = 0.0;  // S(-1)
-  }
   double C[KB][CPT];
 #pragma unroll
   for (int k = 0; k < KB; ++k)
@@ -597,7 +593,7 @@ __global__ __launch_bounds__(kStripThreads) void ls_box_strip_kernel(TileParams 
     double P[CPT], Q[CPT], P1[CPT], Q1[CPT], DP[CPT], DQ[CPT];
 #pragma unroll
     for (int j = 0; j < CPT; ++j) {  // non-output columns read pixel (r, 0) and store nothing
-      const int64_t pi = (int64_t)r * p.Wd + (central[j] ? gcol[j] : 0);
+      const int64_t pi = (int64_t)r * p.Wd + (fout[j] ? fcol[j] : 0);
       ap[j] = st.ap[pi];
       z[j] = st.z[pi];
       P[j] = st.P[pi];
@@ -620,7 +616,9 @@ __global__ __launch_bounds__(kStripThreads) void ls_box_strip_kernel(TileParams 
       ad[j] = (double)af[j];
       apd[j] = (double)ap[j];
     }
-    // column sums of row r into LDS
+    // column sums of row r into LDS (the set of this row's parity: the fold
+    // of row r - 1 may still read the other set)
+    float* Cb = Cbuf + (r & 1) * KB * G::CPITCH;
 #pragma unroll
     for (int k = 0; k < KB; ++k) {
       float* row = Cb + k * G::CPITCH + strip_cpos(CPT * t);
@@ -628,9 +626,10 @@ __global__ __launch_bounds__(kStripThreads) void ls_box_strip_kernel(TileParams 
       for (int j = 0; j < CPT; ++j) row[j] = (float)C[k][j];
     }
     lds_barrier();
-    // row windows of the orders wv, wv + 4, ..., SG at a time
+    // chunk prefixes of the orders wv, wv + 4, ..., SG of them together; each
+    // lane rewrites its own CPL columns in place
 #pragma unroll
-    for (int jg = 0; jg < KB / 4; jg += SG) {
+    for (int jg = 0; jg < NW; jg += SG) {
       float x[SG][CPL];
 #pragma unroll
       for (int g = 0; g < SG; ++g) {
@@ -644,48 +643,45 @@ __global__ __launch_bounds__(kStripThreads) void ls_box_strip_kernel(TileParams 
           x[g][u + 3] = v4.w;
         }
       }
-      double pre[SG][CPL], v[SG];
+      float v[SG];
 #pragma unroll
       for (int g = 0; g < SG; ++g) {
-        pre[g][0] = (double)x[g][0];
 #pragma unroll
-        for (int u = 1; u < CPL; ++u) pre[g][u] = pre[g][u - 1] + (double)x[g][u];
-        v[g] = pre[g][CPL - 1];
+        for (int u = 1; u < CPL; ++u) x[g][u] += x[g][u - 1];
+        v[g] = x[g][CPL - 1];
       }
-      wave_scan_incl_n<SG>(v);
+      wave_scan_seg_n<SG>(v, ch);
 #pragma unroll
       for (int g = 0; g < SG; ++g) {
-        const double ex = v[g] - pre[g][CPL - 1];
-        double* sg = srow + g * G::SPITCH;
-#pragma unroll
-        for (int u = 0; u < CPL; u += 2)
-          *(double2*)(sg + strip_spos(CPL * lane + 2 + u)) = make_double2(ex + pre[g][u], ex + pre[g][u + 1]);
-      }
-      // window sums of the columns c = lane + 64 i (this wave's prefix rows,
-      // written above by its own lanes); the slots are clamped, so columns
-      // within W of the strip edge get values that no output reads
-#pragma unroll
-      for (int g = 0; g < SG; ++g) {
+        const float ex = v[g] - x[g][CPL - 1];
         float* crow = Cb + (wv + 4 * (jg + g)) * G::CPITCH;
-        const double* sg = srow + g * G::SPITCH;
 #pragma unroll
-        for (int i = 0; i < SC / 64; ++i) {
-          const int c = lane + 64 * i;
-          crow[strip_cpos(c)] =
-              (float)(sg[strip_spos(min(c + W + 2, SC + 1))] - sg[strip_spos(max(c - W + 1, 1))]);
-        }
+        for (int u = 0; u < CPL; u += 4)
+          *(float4*)(crow + strip_cpos(CPL * lane + u)) =
+              make_float4(ex + x[g][u], ex + x[g][u + 1], ex + x[g][u + 2], ex + x[g][u + 3]);
       }
     }
     lds_barrier();
-    // fold this thread's output pixels: float64 products and sums (the terms
-    // of eqs. (P), (Q) cancel heavily at small sigma_r; float32 partial sums
-    // cost about 5e-4 there).  The next row writes only this thread's own
-    // columns before its barrier, so no barrier is needed after the fold.
+    // window sums and the fold of this thread's output pixels: float64
+    // products and sums (the terms of eqs. (P), (Q) cancel heavily at small
+    // sigma_r; float32 partial sums cost about 5e-4 there).  The fold reads
+    // other threads' columns; row r + 1 writes the other set, and row r + 2
+    // writes this one only after the barrier of row r + 1, which every
+    // thread reaches after this fold.
 #pragma unroll
     for (int j = 0; j < CPT; ++j) {
+      // window ends b = c + W, a = c - W - 1, and the last column of a's chunk
+      const int sc = t + 256 * j;
+      const int b = min(sc + W, SC - 1), a = sc - W - 1;
+      const int ac = max(a, 0);
+      const int pb = strip_cpos(b), pa = strip_cpos(ac), pt = strip_cpos((ac / L) * L + L - 1);
+      const float fa = a >= 0 ? 1.f : 0.f;
+      const float ft = (a >= 0 && ac / L != b / L) ? 1.f : 0.f;
 #pragma unroll
       for (int k = 0; k < KB; ++k) {
-        const double vd = (double)Cb[k * G::CPITCH + strip_cpos(CPT * t) + j];
+        const float* row = Cb + k * G::CPITCH;
+        const float wsum = fmaf(-fa, row[pa], fmaf(ft, row[pt], row[pb]));
+        const double vd = (double)wsum;
         if (k & 1) {
           Q1[j] = fma(ad[j], vd, Q1[j]);
           P1[j] = fma(apd[j], vd, P1[j]);
@@ -706,8 +702,8 @@ __global__ __launch_bounds__(kStripThreads) void ls_box_strip_kernel(TileParams 
     }
 #pragma unroll
     for (int j = 0; j < CPT; ++j) {
-      if (central[j]) {
-        const int64_t pi = (int64_t)r * p.Wd + gcol[j];
+      if (fout[j]) {
+        const int64_t pi = (int64_t)r * p.Wd + fcol[j];
         st.ap[pi] = ap[j];
         st.P[pi] = P[j] + P1[j];
         st.Q[pi] = Q[j] + Q1[j];
