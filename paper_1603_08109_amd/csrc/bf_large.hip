@@ -522,14 +522,15 @@ __global__ __launch_bounds__(kStripThreads, 2) void ls_box_strip_kernel(TilePara
     central[j] = sc >= W && sc < W + OC && gc < p.Wd;  // an output column of this strip
     gcol[j] = gc;
   }
-  // the fold's columns: strip columns t + 256 j (consecutive lanes, consecutive
-  // columns)
+  // the fold's columns: output o = t + 256 j of the strip, strip column W + o
+  // (consecutive lanes, consecutive columns; a wave whose lanes hold no output
+  // skips that fold)
   int fcol[CPT];
   bool fout[CPT];
 #pragma unroll
   for (int j = 0; j < CPT; ++j) {
-    const int sc = t + 256 * j, gc = c0 - W + sc;
-    fout[j] = sc >= W && sc < W + OC && gc < p.Wd;
+    const int o = t + 256 * j, gc = c0 + o;
+    fout[j] = o < OC && gc < p.Wd;
     fcol[j] = gc;
   }
   const float* Fin = st.F[src];
@@ -582,26 +583,54 @@ __global__ __launch_bounds__(kStripThreads, 2) void ls_box_strip_kernel(TilePara
       if (central[j] && q >= r_lo && q < r_hi) Fout[(int64_t)q * st.pitch + gcol[j]] = (float)fd;
     }
   }
+  // per-pixel state of a row (non-output columns read pixel (r, 0) and store
+  // nothing); with one column per thread the next row's is loaded a row ahead
+  constexpr bool PF = CPT == 1 && !SAVE;
+  struct PixState {
+    float ap, z, a;
+    double P, Q;
+  };
+  auto load_state = [&](int r, PixState (&ps)[CPT]) {
+#pragma unroll
+    for (int j = 0; j < CPT; ++j) {
+      const int64_t pi = (int64_t)r * p.Wd + (fout[j] ? fcol[j] : 0);
+      ps[j].ap = st.ap[pi];
+      ps[j].z = st.z[pi];
+      ps[j].P = st.P[pi];
+      ps[j].Q = st.Q[pi];
+      ps[j].a = n0 == 0 ? st.a[pi] : 0.f;
+    }
+  };
+  PixState nxt[CPT];
+  if (PF && r_lo < r_hi) load_state(r_lo, nxt);
   for (int r = r_lo; r < r_hi; ++r) {
     // rows entering and leaving after this one, and this row's pixel state
     float fe[CPT], ye[CPT], fl[CPT], yl[CPT];
     load_row(r + W + 1, fe, ye);
     load_row(r - W, fl, yl);
+    PixState cur[CPT];
+    if (PF) {
+#pragma unroll
+      for (int j = 0; j < CPT; ++j) cur[j] = nxt[j];
+      load_state(min(r + 1, r_hi - 1), nxt);
+    } else {
+      load_state(r, cur);
+    }
     // the sums of even and odd orders are kept apart (two shorter dependency
     // chains); a_n advances in float32
     float af[CPT], ap[CPT], app[CPT], z[CPT];
     double P[CPT], Q[CPT], P1[CPT], Q1[CPT], DP[CPT], DQ[CPT];
 #pragma unroll
-    for (int j = 0; j < CPT; ++j) {  // non-output columns read pixel (r, 0) and store nothing
+    for (int j = 0; j < CPT; ++j) {
       const int64_t pi = (int64_t)r * p.Wd + (fout[j] ? fcol[j] : 0);
-      ap[j] = st.ap[pi];
-      z[j] = st.z[pi];
-      P[j] = st.P[pi];
-      Q[j] = st.Q[pi];
+      ap[j] = cur[j].ap;
+      z[j] = cur[j].z;
+      P[j] = cur[j].P;
+      Q[j] = cur[j].Q;
       P1[j] = 0.0;
       Q1[j] = 0.0;
       if (n0 == 0)
-        af[j] = st.a[pi];
+        af[j] = cur[j].a;
       else
         af[j] = ap[j] * (z[j] * in1_prev);
       if (SAVE) {
@@ -670,10 +699,11 @@ __global__ __launch_bounds__(kStripThreads, 2) void ls_box_strip_kernel(TilePara
     // thread reaches after this fold.
 #pragma unroll
     for (int j = 0; j < CPT; ++j) {
+      if (j > 0 && __builtin_amdgcn_ballot_w64(fout[j]) == 0) continue;  // wave-uniform
       // window ends b = c + W, a = c - W - 1, and the last column of a's chunk
-      const int sc = t + 256 * j;
+      const int sc = W + t + 256 * j;
       const int b = min(sc + W, SC - 1), a = sc - W - 1;
-      const int ac = max(a, 0);
+      const int ac = min(max(a, 0), SC - 1);
       const int pb = strip_cpos(b), pa = strip_cpos(ac), pt = strip_cpos((ac / L) * L + L - 1);
       const float fa = a >= 0 ? 1.f : 0.f;
       const float ft = (a >= 0 && ac / L != b / L) ? 1.f : 0.f;
