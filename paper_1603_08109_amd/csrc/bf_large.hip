@@ -767,26 +767,35 @@ bool ls_box_strip_supported(int W) { return 256 - 2 * W >= 64; }
 // the tail), and its LDS bytes.
 static const void* box_strip_kernel(int cpt, bool save, int kb) {
   if (save) return (const void*)ls_box_strip_kernel<1, true, 16>;  // the saved state runs 256-column strips
-  if (cpt == 2) return (const void*)ls_box_strip_kernel<2, false, 16>;
+  if (cpt == 2) return kb == 8 ? (const void*)ls_box_strip_kernel<2, false, 8> : (const void*)ls_box_strip_kernel<2, false, 16>;
+  if (kb == 8) return (const void*)ls_box_strip_kernel<1, false, 8>;
   return kb == 32 ? (const void*)ls_box_strip_kernel<1, false, 32> : (const void*)ls_box_strip_kernel<1, false, 16>;
 }
 static int64_t box_strip_lds(int cpt, int kb) {
-  if (cpt == 2) return StripGeom<2, 16>::LDS_BYTES;
+  if (cpt == 2) return kb == 8 ? StripGeom<2, 8>::LDS_BYTES : StripGeom<2, 16>::LDS_BYTES;
+  if (kb == 8) return StripGeom<1, 8>::LDS_BYTES;
   return kb == 32 ? StripGeom<1, 32>::LDS_BYTES : StripGeom<1, 16>::LDS_BYTES;
 }
-// orders of the launch that starts at n0: the shape's block, or 16 where the
-// orders left (n0 .. N) fit in 16
-static int box_strip_block(const StripShape& sh, int n0, int N) { return N + 1 - n0 <= 16 ? 16 : sh.kb; }
+// orders of the launch that starts at n0 (orders n0 .. N are left): the
+// 32-order form runs 16 where they fit in 16 (splitting a 32-order tail costs
+// more launches than its idle orders: 4096^2, W = 30, sigma_r = 30, 53
+// orders: 1.46 ms as 32 + 32 against 1.55 as 32 + 16 + 8); the 512-column
+// form runs 8 where they fit in 8 (W = 75, sigma_r = 30, 55 orders: 1.97 ms
+// against 2.10 with 16 for the last 7); the saved state always 16.
+static int box_strip_block(const StripShape& sh, bool save, int n0, int N) {
+  const int left = N + 1 - n0;
+  if (save) return 16;
+  if (sh.kb == 32) return left <= 16 ? 16 : 32;
+  return left <= 8 ? 8 : 16;
+}
 
 // Shape of the box strips on an H x Wd image: the 512-column form for the
-// plain forward from W = 48 (its halo is shared by more outputs, at two
-// resident workgroups per compute unit; 4096^2, sigma_r = 10: W = 75 11.0 ms
-// against 13.5 for the 256-column form), else 256 columns.  The plain
-// 256-column form takes 32 orders per launch (two resident workgroups: the
-// per-pixel state crosses HBM half as often; W = 30, sigma_r = 10: 7.3 ms
-// against 7.9 with 16 orders and three resident workgroups); the others 16.
-// Row segments: one wave of resident workgroups, so none trails; each pays a
-// 2W + 1 row warm-up.
+// plain forward from W = 48 (its halo is shared by more outputs), else 256
+// columns (4096^2, sigma_r = 10, W = 30: 5.3 ms against 6.2 for 512
+// columns).  The plain 256-column form takes 32 orders per launch (the
+// per-pixel state crosses HBM half as often; W = 30: 5.4 ms against 6.1 with
+// 16 orders); the others 16.  Row segments: one wave of resident
+// workgroups, so none trails; each pays a 2W + 1 row warm-up.
 StripShape ls_box_strip_shape(int H, int Wd, int W, bool save) {
   StripShape sh;
   sh.cpt = (!save && W >= 48) ? 2 : 1;
@@ -925,7 +934,7 @@ hipError_t launch_forward_ls(const TileParams& p, const LsState& st, bool save, 
   const bool box_strip = p.kt == BF_BOX && ls_box_strip_supported(p.W);
   const StripShape sh = box_strip ? ls_box_strip_shape(p.H, p.Wd, p.W, save) : StripShape{};
   if (box_strip) {
-    for (int kb = sh.kb; kb >= 16; kb /= 2) {
+    for (int kb = sh.kb; kb >= (save || sh.kb == 32 ? 16 : 8); kb /= 2) {
       e = hipFuncSetAttribute(box_strip_kernel(sh.cpt, save, kb), hipFuncAttributeMaxDynamicSharedMemorySize,
                               (int)box_strip_lds(sh.cpt, kb));
       if (e != hipSuccess) return e;
@@ -963,7 +972,7 @@ hipError_t launch_forward_ls(const TileParams& p, const LsState& st, bool save, 
   int src = 0;
   if (box_strip) {
     for (int n0 = 0; n0 <= p.N;) {
-      const int kb = box_strip_block(sh, n0, p.N);
+      const int kb = box_strip_block(sh, save, n0, p.N);
       int n0v = n0, srcv = src, segv = sh.seg_rows;
       TileParams pv = p;
       LsState sv = st;
