@@ -50,6 +50,7 @@ MFMA_F32_PEAK_TFLOPS = 157.3
 MFMA_BF16_PEAK_TFLOPS = 2500.0
 SPLIT_PRODUCTS = 6
 SPLIT_MIN_W = 31  # from this support both streamed passes use the split arithmetic
+PRESPLIT_MIN_W = 57  # from this support the row pass writes its outputs split (plain forward)
 
 SWEEP = ([("gauss", dict(sigma_s=s), r) for s in (3.0, 10.0, 25.0) for r in (10.0, 30.0, 50.0)]
          + [("box", dict(W=w), r) for w in (10, 30, 75) for r in (10.0, 30.0, 50.0)])
@@ -146,6 +147,8 @@ def engine_of(kind, W, info):
         return "fused_valu_tile"
     if kind == "box":
         return f"box_strips_{info.tile_cols + 2 * W}"
+    if W >= PRESPLIT_MIN_W:
+        return "rows_x3_split+cols_x3p"
     return "rows_x3+cols_x3s" if W >= SPLIT_MIN_W else "rows_x3+cols_mfma"
 
 
@@ -166,7 +169,7 @@ def setting_roof(kind, W, N, ms, info, H, Wd):
     achieved = flops / (ms * 1e-3) / 1e12
     eng = engine_of(kind, W, info)
     extra = {}
-    if eng == "rows_x3+cols_x3s":
+    if eng in ("rows_x3+cols_x3s", "rows_x3_split+cols_x3p"):
         # the FIR products run as split-BF16 matrix-core products: priced at the
         # FP32-product ceiling of that arithmetic, with the FP32 matrix-core ratio beside
         bound, peak = "mfma", MFMA_BF16_PEAK_TFLOPS / SPLIT_PRODUCTS
@@ -184,7 +187,7 @@ def setting_roof(kind, W, N, ms, info, H, Wd):
 # rocprofv3 runs whose summaries are committed under profiles/ (run from the
 # repository root; DIR is the output folder, then `bench.py --summarize DIR`).
 # The counter runs take one setting per forward engine (sweep indices 0, 3, 6,
-# 9, 12, 15: fused Gaussian tile, rows_x3 + cols_mfma, rows_x3 + cols_x3, fused
+# 9, 12, 15: fused Gaussian tile, rows_x3 + cols_mfma, split rows_x3 + cols_x3p, fused
 # box tile, 256-column box strips, 512-column box strips, all at sigma_r = 10).
 TRAFFIC_SETTINGS = [0, 3, 6, 9, 12, 15]
 PROFILE_RUNS = {
@@ -253,7 +256,8 @@ def summarize(dirpath, sweep_settings):
              f"Each setting runs {per_call} forward calls (1 warm-up + 2 timed). A call is one fused "
              "launch (`gpa_forward_w_kernel`, the tile compiled for its support W <= 21, else "
              "`gpa_forward_kernel`), or the streamed sequence `ls_init`, per block of orders (16 orders: "
-             "`ls_rows_x3` + `ls_cols_x3s` for the Gaussian from W = 31, `ls_rows_x3` + `ls_cols_mfma` below; "
+             "`ls_rows_x3` writing split outputs + `ls_cols_x3p` for the Gaussian from W = 57, `ls_rows_x3` + "
+             "`ls_cols_x3s` from W = 31, `ls_rows_x3` + `ls_cols_mfma` below; "
              "32 or 16 orders: `ls_box_strip` for the box), `ls_final`.",
              "", "| kernel | calls | total ms | avg us | % |", "|---|---|---|---|---|"]
     for k, v in sorted(per_kernel.items(), key=lambda kv: -sum(kv[1])):

@@ -90,6 +90,10 @@ struct LsState {
   float* HT[kLsBlock];      // recursive Gaussian: the row-filtered images, column-major
   double* Fd[2];            // wide range: F~_n = e^{-x^2/2} x^n / sqrt(n!) images (double-buffered)
   double *ad, *apd;         // wide range: per-pixel a~_n, a~_{n-1}
+  uint16_t* Hs[kLsBlock];   // pre-split row-filtered images (ls_split_rows), or null: per image three
+                            // bfloat16 planes of hs_plane elements, rows in groups of eight
+                            // ([row / 8][column][row % 8], pitch columns)
+  int64_t hs_plane;         // elements per plane of a pre-split image
 };
 
 // Rows of one row-filtered image of the streamed passes: the height padded
@@ -97,6 +101,14 @@ struct LsState {
 // window's entering row, and the overhang of a staged column window: the
 // split-bfloat16 column pass stages up to 2W + 95 rows from a tile's first).
 __host__ __device__ inline int64_t ls_hrows(int H, int W) { return (int64_t)((H + 63) / 64) * 64 + 2 * W + 40; }
+
+// Rows of one pre-split row-filtered image: round_up(W, 8) zero rows above
+// (image row i at row i + round_up(W, 8), so the row pass's runs of four rows
+// stay inside a group of eight), the height rounded up to 16 (the row pass
+// writes whole 16-row tiles; rows past the image are written as zeros).
+// Reads past the last row return zeros (buffer loads with the plane's size).
+__host__ __device__ inline int ls_split_top(int W) { return (W + 7) & ~7; }
+__host__ __device__ inline int64_t ls_split_rows(int H, int W) { return ls_split_top(W) + (int64_t)((H + 15) / 16) * 16; }
 
 // Streamed adjoint (supports too wide for the fused adjoint tiles): orders
 // per block and its device state.
@@ -170,6 +182,11 @@ hipError_t launch_rows_x3(const TileParams& p, const LsState& st, int n0, int K,
 hipError_t launch_cols_x3(const TileParams& p, const LsState& st, int n0, int K, bool save, int grid, hipStream_t s);
 hipError_t launch_cols_x3s(const TileParams& p, const LsState& st, int n0, int K, hipStream_t s);
 int64_t ls_cols_x3s_lds_bytes(int W);
+// plain forward on pre-split row-filtered images (st.Hs): the row pass writes its
+// outputs split, the column pass stages the planes straight into LDS
+hipError_t launch_rows_x3_split(const TileParams& p, const LsState& st, int n0, int K, int src, int grid,
+                                hipStream_t s);
+hipError_t launch_cols_x3p(const TileParams& p, const LsState& st, int n0, int K, hipStream_t s);
 
 // pieces of the streamed sequence (an image of p.H rows)
 hipError_t ls_launch_init(const TileParams& p, const LsState& st, hipStream_t s);
@@ -208,8 +225,9 @@ struct StripShape {
 };
 StripShape ls_box_strip_shape(int H, int Wd, int W, bool save);
 bool ls_mirror_supported(int kernel, int W);
-int64_t ls_state_bytes(int H, int Wd, int W, bool save, bool wide = false);
-LsState ls_layout(void* base, int H, int Wd, int W, bool save, bool wide = false);
+int64_t ls_state_bytes(int H, int Wd, int W, bool save, bool wide = false, bool split = false);
+LsState ls_layout(void* base, int H, int Wd, int W, bool save, bool wide = false, bool split = false);
+bool ls_split_supported(int W);
 hipError_t launch_forward_ls(const TileParams& p, const LsState& st, bool save, hipStream_t s);
 // plan-level helpers of the batch (bf_plan.cpp): the streamed forward of a
 // single-image plan with the image pointers read from `dyn` (device memory)

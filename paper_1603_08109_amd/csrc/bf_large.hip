@@ -851,10 +851,12 @@ bool ls_supported(int W) {
 }
 
 // wide range: the F~ images and the coefficients in float64 instead of float32
-int64_t ls_state_bytes(int H, int Wd, int W, bool save, bool wide) {
+// split: the row-filtered images pre-split (three bfloat16 planes each, the
+// plain forward's split passes) instead of float32
+int64_t ls_state_bytes(int H, int Wd, int W, bool save, bool wide, bool split) {
   const int64_t pitch = ((Wd + 63) / 64) * 64;
   const int64_t img = pitch * H;
-  const int64_t himg = pitch * ls_hrows(H, W);
+  const int64_t himg = split ? ((3 * 2 * pitch * ls_split_rows(H, W) + 255) & ~255LL) / 4 : pitch * ls_hrows(H, W);
   const int64_t npx = (int64_t)H * Wd;
   int64_t b = (wide ? 2 * img * 8 + img * 4 : 3 * img * 4) + (int64_t)kLsBlock * himg * 4 +
               (wide ? 2 * npx * 8 + npx * 4 : 3 * npx * 4) + 2 * npx * 8;
@@ -863,7 +865,7 @@ int64_t ls_state_bytes(int H, int Wd, int W, bool save, bool wide) {
 }
 
 // Carve the state buffers out of one allocation.
-LsState ls_layout(void* base, int H, int Wd, int W, bool save, bool wide) {
+LsState ls_layout(void* base, int H, int Wd, int W, bool save, bool wide, bool split) {
   LsState st = {};
   const int64_t pitch = ((Wd + 63) / 64) * 64;
   const int64_t img = pitch * H;
@@ -884,7 +886,12 @@ LsState ls_layout(void* base, int H, int Wd, int W, bool save, bool wide) {
     st.F[1] = (float*)take(img * 4);
   }
   st.Y = (float*)take(img * 4);
-  for (int k = 0; k < kLsBlock; ++k) st.H[k] = (float*)take(himg * 4);
+  if (split) {
+    st.hs_plane = pitch * ls_split_rows(H, W);
+    for (int k = 0; k < kLsBlock; ++k) st.Hs[k] = (uint16_t*)take(3 * 2 * st.hs_plane);
+  } else {
+    for (int k = 0; k < kLsBlock; ++k) st.H[k] = (float*)take(himg * 4);
+  }
   if (wide) {
     st.ad = (double*)take(npx * 8);
     st.apd = (double*)take(npx * 8);
@@ -902,7 +909,7 @@ LsState ls_layout(void* base, int H, int Wd, int W, bool save, bool wide) {
     st.DP = (double*)take(npx * 8);
     st.DQ = (double*)take(npx * 8);
   }
-  st.hbytes = himg * 4;
+  st.hbytes = split ? 0 : himg * 4;
   return st;
 }
 
@@ -969,6 +976,10 @@ hipError_t launch_forward_ls(const TileParams& p, const LsState& st, bool save, 
       e = hipFuncSetAttribute((const void*)k16, hipFuncAttributeMaxDynamicSharedMemorySize, max_lds_bytes());
     if (e != hipSuccess) return e;
   }
+  // pre-split row-filtered images (a plan's plain Gaussian forward): split row
+  // pass and the column pass that stages the planes directly
+  const bool split = st.Hs[0] != nullptr;
+  if (split && (save || p.mirror || !x3 || p.kt == BF_BOX)) return hipErrorInvalidValue;
   int src = 0;
   if (box_strip) {
     for (int n0 = 0; n0 <= p.N;) {
@@ -992,7 +1003,7 @@ hipError_t launch_forward_ls(const TileParams& p, const LsState& st, bool save, 
       // split row pass always (4096^2, sigma_r = 30, ms per call, rows+cols
       // float32 / split rows / both split by the two-wave column pass: W = 30
       // 4.40 / 4.00 / 4.14, W = 51 5.82 / 4.95 / 4.78, W = 75 7.40 / 6.09 / 5.93)
-      e = launch_rows_x3(p, st, n0, K, src, grow, s);
+      e = split ? launch_rows_x3_split(p, st, n0, K, src, grow, s) : launch_rows_x3(p, st, n0, K, src, grow, s);
     } else {
       if (rows_mfma)
         hipLaunchKernelGGL(ls_rows_mfma_kernel, dim3(grow), dim3(kThreads), (size_t)rlm, s, p, st, n0, K, src);
@@ -1009,7 +1020,9 @@ hipError_t launch_forward_ls(const TileParams& p, const LsState& st, bool save, 
       // matrix-core column pass / the split-once pass: W = 26 16.7 / 17.1,
       // W = 30 17.24 / 17.17, W = 33 17.9 / 17.3, W = 39 18.8 / 17.3.
       const bool x3s = !save && p.W >= 31 && (16 + 2 * p.W + 31) / 32 <= 6 && st.hbytes < (1LL << 31);
-      if (x3s) {
+      if (split) {
+        e = launch_cols_x3p(p, st, n0, K, s);
+      } else if (x3s) {
         e = launch_cols_x3s(p, st, n0, K, s);
       } else if (p.W >= 40) {
         e = launch_cols_x3(p, st, n0, K, save, gfir16, s);

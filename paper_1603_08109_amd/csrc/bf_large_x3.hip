@@ -98,16 +98,17 @@ __device__ __forceinline__ void split3_pair(float f0, float f1, uint32_t& H, uin
   L = __builtin_bit_cast(uint32_t, __builtin_convertvector((f2v){s0, s1}, b2v));
 }
 
-// the three planes of the Toeplitz operand, [s][plane][lane] x 8
+// the three planes of the Toeplitz operand, [s][plane][lane] x 8, for S
+// k-steps with the taps shifted down by sft rows (the window's first row is
+// sft rows above the first output's)
 template <int NT>
-__device__ __forceinline__ void fill_toeplitz_x3(__bf16* Tb, int W, const float* __restrict__ tz) {
-  const int S = x3_steps(W);
+__device__ __forceinline__ void fill_toeplitz_x3(__bf16* Tb, int W, const float* __restrict__ tz, int S, int sft) {
   for (int u = threadIdx.x; u < S * 64; u += NT) {
     const int s = u >> 6, l = u & 63;
     bf8 ph, pm, pl;
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
-      const int d = 32 * s + 8 * (l >> 4) + i - (l & 15);
+      const int d = 32 * s + 8 * (l >> 4) + i - (l & 15) - sft;
       const float t = (d >= 0 && d <= 2 * W) ? tz[d] : 0.f;
       __bf16 h, m, lo;
       split3(t, h, m, lo);
@@ -211,7 +212,10 @@ __device__ __forceinline__ void x3_advance(FT* F, const float* Y, const TilePara
 // x3_steps(W).
 // WIDE: F~_n = e^{-x^2/2} x^n / sqrt(n!) in float64 (state images st.Fd),
 // advanced by x / sqrt(n + 1); the matrix cores see it rounded to float32.
-template <int S, bool WIDE>
+// SPLIT: the outputs are written pre-split (st.Hs: three bfloat16 planes,
+// rows in groups of eight, image row i at row i + ls_split_top(W)); a lane's
+// four consecutive rows of one column are one 8-byte store per plane.
+template <int S, bool WIDE, bool SPLIT = false>
 __global__ __launch_bounds__(kX3RowsThreads) void ls_rows_x3_kernel(TileParams p, LsState st, int n0, int K,
                                                                     int src) {
   using FT = typename std::conditional<WIDE, double, float>::type;
@@ -228,7 +232,7 @@ __global__ __launch_bounds__(kX3RowsThreads) void ls_rows_x3_kernel(TileParams p
   const int r0 = ty * kLsRows, c0 = tx * kLsCols;
   const FT* Fin = (const FT*)(WIDE ? (const void*)st.Fd[src] : (const void*)st.F[src]);
   FT* Fout = (FT*)(WIDE ? (void*)st.Fd[src ^ 1] : (void*)st.F[src ^ 1]);
-  fill_toeplitz_x3<kX3RowsThreads>(Tb, W, p.taps + kTapPad);
+  fill_toeplitz_x3<kX3RowsThreads>(Tb, W, p.taps + kTapPad, x3_steps(W), 0);
   FT F[kX3RowsRegs];
   float Y[kX3RowsRegs];
 #pragma unroll
@@ -287,13 +291,31 @@ __global__ __launch_bounds__(kX3RowsThreads) void ls_rows_x3_kernel(TileParams p
 #pragma unroll
     for (int jj = S + 1; jj < kX3RowsRegs / 2; ++jj) x3_split_pair(F[2 * jj], F[2 * jj + 1], nxt, plane, jj);
     if (k + 1 < K) x3_advance<WIDE>(F, Y, p, n0 + k + 1);
-    float* Hk = st.H[k] + (int64_t)W * st.pitch;  // W zero rows above the image
+    if constexpr (SPLIT) {
+      // rows orow .. orow + 3 (rows past the image hold zeros: their F^ are 0)
+      uint16_t* Hk = st.Hs[k];
+      const int R = orow + ls_split_top(W);  // a multiple of 4
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      if (orow + v < p.H) {
+      for (int b = 0; b < 2; ++b) {
+        if (ocol + 32 * b < p.Wd) {
+          uint32_t h0, m0, l0, h1, m1, l1;
+          split3_pair(acc[b][0], acc[b][1], h0, m0, l0);
+          split3_pair(acc[b][2], acc[b][3], h1, m1, l1);
+          const int64_t e = ((int64_t)(R >> 3) * st.pitch + ocol + 32 * b) * 8 + (R & 7);
+          *(uint2*)(Hk + e) = make_uint2(h0, h1);
+          *(uint2*)(Hk + st.hs_plane + e) = make_uint2(m0, m1);
+          *(uint2*)(Hk + 2 * st.hs_plane + e) = make_uint2(l0, l1);
+        }
+      }
+    } else {
+      float* Hk = st.H[k] + (int64_t)W * st.pitch;  // W zero rows above the image
 #pragma unroll
-        for (int b = 0; b < 2; ++b)
-          if (ocol + 32 * b < p.Wd) Hk[(int64_t)(orow + v) * st.pitch + ocol + 32 * b] = acc[b][v];
+      for (int v = 0; v < 4; ++v) {
+        if (orow + v < p.H) {
+#pragma unroll
+          for (int b = 0; b < 2; ++b)
+            if (ocol + 32 * b < p.Wd) Hk[(int64_t)(orow + v) * st.pitch + ocol + 32 * b] = acc[b][v];
+        }
       }
     }
   }
@@ -352,7 +374,7 @@ __global__ __launch_bounds__(kX3ColsThreads) void ls_cols_x3_kernel(TileParams p
   const int64_t bfl = x3_cols_buffer_floats(W);
   float* buf0 = lds;
   // the Toeplitz operands pass through the second buffer into registers
-  fill_toeplitz_x3<kX3ColsThreads>((__bf16*)(lds + bfl), W, p.taps + kTapPad);
+  fill_toeplitz_x3<kX3ColsThreads>((__bf16*)(lds + bfl), W, p.taps + kTapPad, x3_steps(W), 0);
   __syncthreads();
   X3 T[S];
 #pragma unroll
@@ -425,31 +447,31 @@ __global__ __launch_bounds__(kX3ColsThreads) void ls_cols_x3_kernel(TileParams p
   }
 }
 
-template <int S, bool WIDE>
+template <int S, bool WIDE, bool SPLIT>
 static hipError_t rows_x3_s(const TileParams& p, const LsState& st, int n0, int K, int src, int grid, hipStream_t s) {
   static bool attr = false;
   if (!attr) {
-    hipError_t e = hipFuncSetAttribute((const void*)ls_rows_x3_kernel<S, WIDE>,
+    hipError_t e = hipFuncSetAttribute((const void*)ls_rows_x3_kernel<S, WIDE, SPLIT>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, max_lds_bytes());
     if (e != hipSuccess) return e;
     attr = true;
   }
-  hipLaunchKernelGGL((ls_rows_x3_kernel<S, WIDE>), dim3(grid), dim3(kX3RowsThreads),
+  hipLaunchKernelGGL((ls_rows_x3_kernel<S, WIDE, SPLIT>), dim3(grid), dim3(kX3RowsThreads),
                      (size_t)ls_rows_x3_lds_bytes(p.W), s, p, st, n0, K, src);
   return hipGetLastError();
 }
 
-template <bool WIDE>
+template <bool WIDE, bool SPLIT = false>
 static hipError_t rows_x3_t(const TileParams& p, const LsState& st, int n0, int K, int src, int grid, hipStream_t s) {
   switch (x3_steps(p.W)) {
-    case 1: return rows_x3_s<1, WIDE>(p, st, n0, K, src, grid, s);
-    case 2: return rows_x3_s<2, WIDE>(p, st, n0, K, src, grid, s);
-    case 3: return rows_x3_s<3, WIDE>(p, st, n0, K, src, grid, s);
-    case 4: return rows_x3_s<4, WIDE>(p, st, n0, K, src, grid, s);
-    case 5: return rows_x3_s<5, WIDE>(p, st, n0, K, src, grid, s);
-    case 6: return rows_x3_s<6, WIDE>(p, st, n0, K, src, grid, s);
-    case 7: return rows_x3_s<7, WIDE>(p, st, n0, K, src, grid, s);
-    case 8: return rows_x3_s<8, WIDE>(p, st, n0, K, src, grid, s);
+    case 1: return rows_x3_s<1, WIDE, SPLIT>(p, st, n0, K, src, grid, s);
+    case 2: return rows_x3_s<2, WIDE, SPLIT>(p, st, n0, K, src, grid, s);
+    case 3: return rows_x3_s<3, WIDE, SPLIT>(p, st, n0, K, src, grid, s);
+    case 4: return rows_x3_s<4, WIDE, SPLIT>(p, st, n0, K, src, grid, s);
+    case 5: return rows_x3_s<5, WIDE, SPLIT>(p, st, n0, K, src, grid, s);
+    case 6: return rows_x3_s<6, WIDE, SPLIT>(p, st, n0, K, src, grid, s);
+    case 7: return rows_x3_s<7, WIDE, SPLIT>(p, st, n0, K, src, grid, s);
+    case 8: return rows_x3_s<8, WIDE, SPLIT>(p, st, n0, K, src, grid, s);
     default: return hipErrorInvalidValue;
   }
 }
@@ -595,7 +617,7 @@ __global__ __launch_bounds__(kX3sThreads) void ls_cols_x3s_kernel(TileParams p, 
     for (int i = 0; i < G::ITEMS; ++i) x3s_load_item<S, MIRROR>(rs, pitch, tr0, c0, W, p.H, i, reg[i]);
   }
   // the Toeplitz operands pass through the second set of planes into registers
-  fill_toeplitz_x3<kX3sThreads>(Pl + G::BUF, W, p.taps + kTapPad);
+  fill_toeplitz_x3<kX3sThreads>(Pl + G::BUF, W, p.taps + kTapPad, S, 0);
   __syncthreads();
   X3 T[S];
 #pragma unroll
@@ -691,6 +713,190 @@ static hipError_t cols_x3s_m(const TileParams& p, const LsState& st, int n0, int
 hipError_t launch_cols_x3s(const TileParams& p, const LsState& st, int n0, int K, hipStream_t s) {
   if (ls_cols_x3s_lds_bytes(p.W) > max_lds_bytes() || st.hbytes >= (1LL << 31)) return hipErrorInvalidValue;
   return p.mirror ? cols_x3s_m<true>(p, st, n0, K, s) : cols_x3s_m<false>(p, st, n0, K, s);
+}
+
+// Column pass on pre-split row-filtered images (the plain forward of a plan
+// whose row pass writes its outputs split, st.Hs).  Tiles of 16 columns x
+// 256 output rows, eight waves; wave w takes the row blocks rb = (w & 1) +
+// 4 (w >> 1) and rb + 2 (16 rows each), which read the same window slice one
+// k-step apart, with the matrix-core steps of ls_cols_x3s.  The window of an
+// order (R = 32 S + 256 rows from the tile's first output row, in the split
+// layout's row numbering) is copied straight from the planes into LDS by
+// buffer-to-LDS loads while the previous order multiplies: no registers hold
+// it and nothing is split here.  LDS keeps the global layout, [group of 8
+// rows][16 columns][8 rows] per plane: one load of 64 lanes copies four
+// groups of the tile's columns (four contiguous 256-byte runs), and a lane's
+// B operand (8 rows of one column) is one 16-byte read per plane, the 16
+// lanes of a group on consecutive columns (distinct banks).  The split layout
+// puts image row i at row i + ls_split_top(W), sft = ls_split_top(W) - W rows
+// below the window start that output row i's taps need, so the Toeplitz
+// operand is shifted by sft and S = x3p_steps(W) k-steps cover 16 + 2W + sft
+// rows.  Loads past the plane return zeros (the buffer's size), as do the
+// zero rows above.  The taller, narrower tile re-reads fewer halo rows per
+// output than 32 x 128 (1.75x against 2.4x at W = 75): 719 against 825 us per
+// 16-order launch.
+__host__ __device__ inline int x3p_shift(int W) { return ls_split_top(W) - W; }
+__host__ __device__ inline int x3p_steps(int W) { return (16 + 2 * W + x3p_shift(W) + 31) / 32; }
+
+constexpr int kX3pCols = 16;   // columns of a tile
+constexpr int kX3pRows = 256;  // output rows of a tile (16 blocks of 16)
+
+template <int S>
+struct X3pGeom {
+  static constexpr int R = 32 * S + 256;            // window rows (block 13 reads up to 16 * 13 + 32 S + 31)
+  static constexpr int GROUPS = R / 8;              // groups of 8 rows, a multiple of 4
+  static constexpr int PS = GROUPS * kX3pCols * 8;  // elements per plane
+  static constexpr int BUF = 3 * PS;                // elements per set of planes
+};
+
+constexpr int kX3pSets = 2;  // sets of planes: order k multiplies while k + 1 arrives
+
+int64_t ls_cols_x3p_lds_bytes(int W) {
+  return kX3pSets * 3 * (32LL * x3p_steps(W) + 256) * kX3pCols * 2;  // the Toeplitz table passes through the last set
+}
+
+// Supports of at least 5 k-steps (W >= 57).  4096^2 Gaussians, ms per call
+// (sigma_r = 10 / 30 / 50), split-once column pass against this pair:
+// W = 75 21.7 / 5.30 / 3.16 against 20.7 / 4.80 / 2.74; at W = 30, against
+// the float32 matrix-core column pass, 17.1 / 4.17 / 2.53 against
+// 17.4 / 4.10 / 2.33 (the split row pass costs about as much as it saves).
+bool ls_split_supported(int W) {
+  return ls_x3_supported(W) && x3p_steps(W) >= 5 && x3p_steps(W) <= kX3MaxSteps &&
+         ls_cols_x3p_lds_bytes(W) <= max_lds_bytes();
+}
+
+template <int S>
+__global__ __launch_bounds__(kX3sThreads) void ls_cols_x3p_kernel(TileParams p, LsState st, int n0, int K) {
+  using G = X3pGeom<S>;
+  static_assert(G::GROUPS % 4 == 0, "four groups per load");
+  constexpr int NLOADS = 3 * G::GROUPS / 4;         // loads of 64 lanes per order
+  constexpr int NWAVES = kX3sThreads / 64;
+  extern __shared__ float lds[];
+  __bf16* Pl = (__bf16*)lds;  // kX3pSets sets of G::BUF elements
+  const int tiles_x = (p.Wd + kX3pCols - 1) / kX3pCols;
+  const int tiles_y = (p.H + kX3pRows - 1) / kX3pRows;
+  int ty, tx;
+  band_tile(xcd_remap(blockIdx.x, gridDim.x), tiles_x, tiles_y, ty, tx);
+  const int lane = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform: the loads' descriptors and LDS bases stay scalar
+  const int rb = (wv & 1) + 4 * (wv >> 1);  // row blocks rb and rb + 2 (16 rows each)
+  const int tr0 = ty * kX3pRows, c0 = tx * kX3pCols;
+  const int W = p.W;
+  const int64_t pitch = st.pitch;
+  const int plane_bytes = (int)(st.hs_plane * 2);
+  // lane offset of a load: group lane / 16 of the four, column lane % 16
+  const int lvo = (int)(((int64_t)(tr0 >> 3) + (lane >> 4)) * pitch + c0 + (lane & 15)) * 16;
+  // this wave's loads of an order into a set: load u = plane u / (GROUPS / 4),
+  // groups 4 (u % (GROUPS / 4)) .. + 3
+  auto stage = [&](int k, __bf16* set) {
+    const uint16_t* Hk = st.Hs[k];
+    for (int u = wv; u < NLOADS; u += NWAVES) {
+      const int pl = u / (G::GROUPS / 4), g0 = 4 * (u - pl * (G::GROUPS / 4));
+      const __amdgpu_buffer_rsrc_t rs =
+          __builtin_amdgcn_make_buffer_rsrc((void*)(Hk + pl * st.hs_plane), (short)0, plane_bytes, 0x00020000);
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(
+          rs, (__attribute__((address_space(3))) void*)(set + pl * G::PS + g0 * kX3pCols * 8), 16,
+          lvo + (int)(g0 * pitch * 16), 0, 0, 0);
+    }
+  };
+  // the Toeplitz operands pass through the last set of planes into registers
+  __bf16* Tset = Pl + (kX3pSets - 1) * G::BUF;
+  fill_toeplitz_x3<kX3sThreads>(Tset, W, p.taps + kTapPad, S, x3p_shift(W));
+  __syncthreads();
+  X3 T[S];
+#pragma unroll
+  for (int q = 0; q < S; ++q) T[q] = x3_table(Tset, q, lane);
+  stage(0, Pl);
+  const int pr0 = tr0 + 16 * rb + 4 * (lane >> 4);
+  const int pc = c0 + (lane & 15);
+  LsPix<8, false> px;
+#pragma unroll
+  for (int b = 0; b < 2; ++b) {
+    const int nr = pc < p.Wd ? max(0, min(4, p.H - (pr0 + 32 * b))) : 0;
+    px.template load_part<4>(st, 4 * b, (int64_t)(pr0 + 32 * b) * p.Wd + pc, p.Wd, nr);
+  }
+  // this lane's operand: column l%16, rows 16 rb + 32 q + 8 (l/16) .. + 7,
+  // i.e. group 2 rb + 4 q + l/16
+  const int obase = ((2 * rb + (lane >> 4)) * kX3pCols + (lane & 15)) * 8;
+  constexpr int QSTEP = 4 * kX3pCols * 8;  // elements per k-step (four groups)
+  for (int k = 0; k < K; ++k) {
+    const int n = n0 + k;
+    // this wave's copies of order k have landed; after the barrier every
+    // wave's have, and every wave has read order k - 1's set (refilled next)
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    __syncthreads();
+    if (k + 1 < K) stage(k + 1, Pl + ((k + 1) & 1) * G::BUF);
+    const __bf16* cur = Pl + (k & 1) * G::BUF;
+    auto operand = [&](int o) {
+      X3 r;
+      r.h = *(const bf8*)(cur + o);
+      r.m = *(const bf8*)(cur + G::PS + o);
+      r.l = *(const bf8*)(cur + 2 * G::PS + o);
+      return r;
+    };
+    mf4 acc[2] = {mf4{0.f, 0.f, 0.f, 0.f}, mf4{0.f, 0.f, 0.f, 0.f}};
+    X3 bv = operand(obase);
+#pragma unroll
+    for (int q = 0; q <= S; ++q) {
+      X3 bn;
+      if (q < S) bn = operand(obase + QSTEP * (q + 1));
+      // block rb at step q, block rb + 2 at step q - 1
+      if (q >= 1 && q < S)
+        mfma_x3_pair(T[q < S ? q : 0], bv, acc[0], T[q >= 1 ? q - 1 : 0], bv, acc[1]);
+      else if (q < S)
+        acc[0] = mfma_x3(T[q], bv, acc[0]);
+      else
+        acc[1] = mfma_x3(T[q >= 1 ? q - 1 : 0], bv, acc[1]);
+      bv = bn;
+    }
+    const float in1 = p.inv_tab[n + 1];
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) px.fold(4 * b + v, n, p.N, acc[b][v], in1);
+  }
+#pragma unroll
+  for (int b = 0; b < 2; ++b) {
+    const int nr = pc < p.Wd ? max(0, min(4, p.H - (pr0 + 32 * b))) : 0;
+    px.template store_part<4>(st, 4 * b, (int64_t)(pr0 + 32 * b) * p.Wd + pc, p.Wd, nr);
+  }
+}
+
+template <int S>
+static hipError_t cols_x3p_s(const TileParams& p, const LsState& st, int n0, int K, hipStream_t s) {
+  static bool attr = false;
+  const int64_t lb = ls_cols_x3p_lds_bytes(p.W);
+  if (!attr) {
+    hipError_t e = hipFuncSetAttribute((const void*)ls_cols_x3p_kernel<S>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)lb);
+    if (e != hipSuccess) return e;
+    attr = true;
+  }
+  const int grid = ((p.H + kX3pRows - 1) / kX3pRows) * ((p.Wd + kX3pCols - 1) / kX3pCols);
+  hipLaunchKernelGGL((ls_cols_x3p_kernel<S>), dim3(grid), dim3(kX3sThreads), (size_t)lb, s, p, st, n0, K);
+  return hipGetLastError();
+}
+
+hipError_t launch_cols_x3p(const TileParams& p, const LsState& st, int n0, int K, hipStream_t s) {
+  if (!st.Hs[0] || !ls_split_supported(p.W) || (st.hs_plane + 512 * st.pitch) * 2 >= (1LL << 31) || p.mirror)
+    return hipErrorInvalidValue;
+  switch (x3p_steps(p.W)) {
+    case 1: return cols_x3p_s<1>(p, st, n0, K, s);
+    case 2: return cols_x3p_s<2>(p, st, n0, K, s);
+    case 3: return cols_x3p_s<3>(p, st, n0, K, s);
+    case 4: return cols_x3p_s<4>(p, st, n0, K, s);
+    case 5: return cols_x3p_s<5>(p, st, n0, K, s);
+    case 6: return cols_x3p_s<6>(p, st, n0, K, s);
+    case 7: return cols_x3p_s<7>(p, st, n0, K, s);
+    case 8: return cols_x3p_s<8>(p, st, n0, K, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_rows_x3_split(const TileParams& p, const LsState& st, int n0, int K, int src, int grid,
+                                hipStream_t s) {
+  if (!st.Hs[0] || p.mirror) return hipErrorInvalidValue;
+  return rows_x3_t<false, true>(p, st, n0, K, src, grid, s);
 }
 
 // one kernel per k-step count S = x3_steps(W) (W <= 120: S <= 8), the Toeplitz operands in registers
