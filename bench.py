@@ -156,12 +156,13 @@ def seams(kind, W, info):
     """(row, column) of a seam of the engine's work decomposition: fused tiles
     of 64 columns x tile_rows; box strips of tile_cols output columns cut into
     row segments of tile_rows (the plan reports both); streamed Gaussian passes
-    on 16 x 256 row tiles and 64 x 64 column tiles."""
+    on 16 x 256 row tiles and 64 x 64 column tiles (32 x 128 from W = 31,
+    16 x 256 from W = 57)."""
     if info.path == 0:
         return info.tile_rows, 64
     if kind == "box":
         return info.tile_rows, info.tile_cols
-    return 64, 256
+    return (256 if W >= PRESPLIT_MIN_W else 128 if W >= SPLIT_MIN_W else 64), 256
 
 
 def setting_roof(kind, W, N, ms, info, H, Wd):
