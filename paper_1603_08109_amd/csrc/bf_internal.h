@@ -75,7 +75,8 @@ constexpr double kLambdaF32 = 170.0;
 constexpr double kLambdaF64 = 1400.0;
 
 // Large-support path: orders per block and its device state.
-constexpr int kLsBlock = 16;
+constexpr int kLsBlock = 64;       // most orders per block of the streamed passes (row-filtered images per state)
+constexpr int kLsBlockSmall = 16;  // orders per block below 4 Mpx, for the box and the volume and recursive paths
 constexpr int kLsRows = 16;   // image rows per streamed row-pass workgroup
 constexpr int kLsCols = 256;  // output columns per streamed row-pass workgroup
 struct LsState {
@@ -94,6 +95,7 @@ struct LsState {
                             // bfloat16 planes of hs_plane elements, rows in groups of eight
                             // ([row / 8][column][row % 8], pitch columns)
   int64_t hs_plane;         // elements per plane of a pre-split image
+  int block;                // orders per block: row-filtered images allocated (0: none, box strips)
 };
 
 // Rows of one row-filtered image of the streamed passes: the height padded
@@ -225,8 +227,12 @@ struct StripShape {
 };
 StripShape ls_box_strip_shape(int H, int Wd, int W, bool save);
 bool ls_mirror_supported(int kernel, int W);
-int64_t ls_state_bytes(int H, int Wd, int W, bool save, bool wide = false, bool split = false);
-LsState ls_layout(void* base, int H, int Wd, int W, bool save, bool wide = false, bool split = false);
+// nblock: orders per block (row-filtered images in the state), ls_block_orders
+int64_t ls_state_bytes(int H, int Wd, int W, bool save, bool wide = false, bool split = false,
+                       int nblock = kLsBlockSmall);
+LsState ls_layout(void* base, int H, int Wd, int W, bool save, bool wide = false, bool split = false,
+                  int nblock = kLsBlockSmall);
+int ls_block_orders(int H, int Wd, int kernel, int W);
 bool ls_split_supported(int W);
 hipError_t launch_forward_ls(const TileParams& p, const LsState& st, bool save, hipStream_t s);
 // plan-level helpers of the batch (bf_plan.cpp): the streamed forward of a

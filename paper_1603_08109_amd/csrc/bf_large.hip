@@ -1,11 +1,11 @@
 // Large-support forward: Algorithm 2 for supports W too wide for one tile's
 // region to stay on chip (the fused kernels hold (TY + 2W) x (64 + 2W) region
-// values per workgroup).  The N+1 filterings run in blocks of up to kLsBlock
+// values per workgroup).  The N+1 filterings run in blocks of st.block orders
 // orders through device memory:
 //   ls_init  : F^_0 = e^{-x^2/2}, y, and the per-pixel coefficient state;
 //   ls_rows  : per block, F^_n for the block's orders and the row pass of
 //              each (rows staged in LDS with their W-column halo), written to
-//              kLsBlock row-filtered images; the state image advances by the
+//              st.block row-filtered images; the state image advances by the
 //              block length (double-buffered);
 //   ls_cols  : the column pass of each row-filtered image (read straight
 //              from device memory, coalesced along rows) folded into the
@@ -319,16 +319,16 @@ __global__ __launch_bounds__(kThreads) void ls_cols_box_kernel(TileParams p, LsS
   const int re = min(rs + seg_rows, p.H);
   const int L = 2 * p.W + 1;
   const int64_t pitch = st.pitch;
-  float V[kLsBlock];
+  float V[kLsBlockSmall];
 #pragma unroll
-  for (int k = 0; k < kLsBlock; ++k)
+  for (int k = 0; k < kLsBlockSmall; ++k)
     V[k] = (k < K) ? strided_sum(st.H[k] + (int64_t)rs * pitch + c, (int)pitch, 0, L) : 0.f;
   LsPix<CH, SAVE> px;
   for (int r = rs; r < re; r += CH) {
     const int nr = min(CH, re - r);
     px.load(st, (int64_t)r * p.Wd + c, p.Wd, nr);
 #pragma unroll
-    for (int k = 0; k < kLsBlock; ++k) {
+    for (int k = 0; k < kLsBlockSmall; ++k) {
       if (k < K) {
         const int n = n0 + k;
         const float in1 = p.inv_tab[n + 1];
@@ -851,21 +851,33 @@ bool ls_supported(int W) {
 }
 
 // wide range: the F~ images and the coefficients in float64 instead of float32
+// Orders per block of the streamed passes on an H x Wd image: 64 from 4 Mpx
+// (the per-pixel state and the F^ image cross HBM once per block; 4096^2,
+// sigma_r = 10: Gaussian W = 30 17.2 -> 15.4 -> 14.9 ms with 16 -> 32 -> 64
+// orders, W = 75 20.7 -> 18.8 -> 18.1 ms), else 16, which bounds the
+// row-filtered images of smaller images (a batch routes many of them to plans
+// of their own).  The box strips keep their state in registers and need none;
+// the box column pass of narrow supports walks at most 16 orders.
+int ls_block_orders(int H, int Wd, int kernel, int W) {
+  if (kernel == BF_BOX) return ls_box_strip_supported(W) ? 0 : kLsBlockSmall;
+  return (int64_t)H * Wd >= (int64_t)4 << 20 ? kLsBlock : kLsBlockSmall;
+}
+
 // split: the row-filtered images pre-split (three bfloat16 planes each, the
 // plain forward's split passes) instead of float32
-int64_t ls_state_bytes(int H, int Wd, int W, bool save, bool wide, bool split) {
+int64_t ls_state_bytes(int H, int Wd, int W, bool save, bool wide, bool split, int nblock) {
   const int64_t pitch = ((Wd + 63) / 64) * 64;
   const int64_t img = pitch * H;
   const int64_t himg = split ? ((3 * 2 * pitch * ls_split_rows(H, W) + 255) & ~255LL) / 4 : pitch * ls_hrows(H, W);
   const int64_t npx = (int64_t)H * Wd;
-  int64_t b = (wide ? 2 * img * 8 + img * 4 : 3 * img * 4) + (int64_t)kLsBlock * himg * 4 +
+  int64_t b = (wide ? 2 * img * 8 + img * 4 : 3 * img * 4) + (int64_t)nblock * himg * 4 +
               (wide ? 2 * npx * 8 + npx * 4 : 3 * npx * 4) + 2 * npx * 8;
   if (save) b += npx * 4 + 2 * npx * 8;
   return b + 256 * 32;
 }
 
 // Carve the state buffers out of one allocation.
-LsState ls_layout(void* base, int H, int Wd, int W, bool save, bool wide, bool split) {
+LsState ls_layout(void* base, int H, int Wd, int W, bool save, bool wide, bool split, int nblock) {
   LsState st = {};
   const int64_t pitch = ((Wd + 63) / 64) * 64;
   const int64_t img = pitch * H;
@@ -888,9 +900,9 @@ LsState ls_layout(void* base, int H, int Wd, int W, bool save, bool wide, bool s
   st.Y = (float*)take(img * 4);
   if (split) {
     st.hs_plane = pitch * ls_split_rows(H, W);
-    for (int k = 0; k < kLsBlock; ++k) st.Hs[k] = (uint16_t*)take(3 * 2 * st.hs_plane);
+    for (int k = 0; k < nblock; ++k) st.Hs[k] = (uint16_t*)take(3 * 2 * st.hs_plane);
   } else {
-    for (int k = 0; k < kLsBlock; ++k) st.H[k] = (float*)take(himg * 4);
+    for (int k = 0; k < nblock; ++k) st.H[k] = (float*)take(himg * 4);
   }
   if (wide) {
     st.ad = (double*)take(npx * 8);
@@ -910,6 +922,7 @@ LsState ls_layout(void* base, int H, int Wd, int W, bool save, bool wide, bool s
     st.DQ = (double*)take(npx * 8);
   }
   st.hbytes = split ? 0 : himg * 4;
+  st.block = nblock;
   return st;
 }
 
@@ -980,6 +993,8 @@ hipError_t launch_forward_ls(const TileParams& p, const LsState& st, bool save, 
   // pass and the column pass that stages the planes directly
   const bool split = st.Hs[0] != nullptr;
   if (split && (save || p.mirror || !x3 || p.kt == BF_BOX)) return hipErrorInvalidValue;
+  if (!box_strip && (st.block <= 0 || st.block > kLsBlock || (p.kt == BF_BOX && st.block > kLsBlockSmall)))
+    return hipErrorInvalidValue;
   int src = 0;
   if (box_strip) {
     for (int n0 = 0; n0 <= p.N;) {
@@ -996,8 +1011,8 @@ hipError_t launch_forward_ls(const TileParams& p, const LsState& st, bool save, 
     }
   }
   // two passes per block of orders (every other path)
-  for (int n0 = 0; !box_strip && n0 <= p.N; n0 += kLsBlock) {
-    const int K = std::min(kLsBlock, p.N + 1 - n0);
+  for (int n0 = 0; !box_strip && n0 <= p.N; n0 += st.block) {
+    const int K = std::min(st.block, p.N + 1 - n0);
     // row pass
     if (x3) {
       // split row pass always (4096^2, sigma_r = 30, ms per call, rows+cols

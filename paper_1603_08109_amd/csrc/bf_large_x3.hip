@@ -957,8 +957,8 @@ hipError_t launch_forward_wide(const TileParams& p, const LsState& st, hipStream
   const int grow = ((p.H + kLsRows - 1) / kLsRows) * ((p.Wd + kLsCols - 1) / kLsCols);
   const int gcols = ((p.H + 63) / 64) * ((p.Wd + kTileCols - 1) / kTileCols);
   int src = 0;
-  for (int n0 = 0; n0 <= p.N; n0 += kLsBlock) {
-    const int K = std::min(kLsBlock, p.N + 1 - n0);
+  for (int n0 = 0; n0 <= p.N; n0 += st.block) {
+    const int K = std::min(st.block, p.N + 1 - n0);
     e = rows_x3_t<true>(p, st, n0, K, src, grow, s);
     if (e == hipSuccess)
       e = cols_x3_t<false, true>(p, st, n0, K, gcols, s);

@@ -672,7 +672,8 @@ int bf_plan(const bf_params* in, bf_plan_t** out) {
     // keeps its row-filtered images pre-split
     const bool split = !wide && !grad && p.kernel == BF_GAUSS && !(p.flags & (BF_FLAG_MIRROR | BF_FLAG_MFMA_FP32)) &&
                        ls_split_supported(p.W);
-    const int64_t lb = ls_state_bytes(p.height, p.width, p.W, grad, wide, split);
+    const int nblock = ls_block_orders(p.height, p.width, p.kernel, p.W);
+    const int64_t lb = ls_state_bytes(p.height, p.width, p.W, grad, wide, split, nblock);
     e = hipMalloc(&pl->d_ls, lb);
     if (e != hipSuccess) {
       if (pl->d_work) hipFree(pl->d_work);
@@ -688,7 +689,7 @@ int bf_plan(const bf_params* in, bf_plan_t** out) {
       delete pl;
       return hip_fail(e, "hipMemset large-support state");
     }
-    pl->ls_state = ls_layout(pl->d_ls, p.height, p.width, p.W, grad, wide, split);
+    pl->ls_state = ls_layout(pl->d_ls, p.height, p.width, p.W, grad, wide, split, nblock);
     ws += lb;
   }
   if (pl->rec) {

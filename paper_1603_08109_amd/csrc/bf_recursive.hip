@@ -419,13 +419,14 @@ int64_t rg_state_bytes(int H, int Wd) {
   const int64_t pitch = ((Wd + 63) / 64) * 64;
   const int64_t tpitch = ((H + 15) / 16) * 16;
   const int64_t npx = (int64_t)H * Wd;
-  return 3 * (pitch * H * 4 + 256) + kLsBlock * (pitch * H * 4 + 256) + kLsBlock * ((int64_t)Wd * tpitch * 4 + 256) +
+  return 3 * (pitch * H * 4 + 256) + kLsBlockSmall * (pitch * H * 4 + 256) + kLsBlockSmall * ((int64_t)Wd * tpitch * 4 + 256) +
          3 * (npx * 4 + 256) + 2 * (npx * 8 + 256);
 }
 
 LsState rg_layout(void* base, int H, int Wd) {
   LsState st;
   std::memset(&st, 0, sizeof(st));
+  st.block = kLsBlockSmall;
   const int64_t pitch = ((Wd + 63) / 64) * 64;
   const int64_t tpitch = ((H + 15) / 16) * 16;
   const int64_t npx = (int64_t)H * Wd;
@@ -440,8 +441,8 @@ LsState rg_layout(void* base, int H, int Wd) {
   st.F[0] = (float*)take(pitch * H * 4);
   st.F[1] = (float*)take(pitch * H * 4);
   st.Y = (float*)take(pitch * H * 4);
-  for (int k = 0; k < kLsBlock; ++k) st.H[k] = (float*)take(pitch * H * 4);
-  for (int k = 0; k < kLsBlock; ++k) st.HT[k] = (float*)take((int64_t)Wd * tpitch * 4);
+  for (int k = 0; k < kLsBlockSmall; ++k) st.H[k] = (float*)take(pitch * H * 4);
+  for (int k = 0; k < kLsBlockSmall; ++k) st.HT[k] = (float*)take((int64_t)Wd * tpitch * 4);
   st.a = (float*)take(npx * 4);
   st.ap = (float*)take(npx * 4);
   st.z = (float*)take(npx * 4);
@@ -472,8 +473,8 @@ hipError_t launch_forward_rg(const TileParams& p, const LsState& st, hipStream_t
   const dim3 tiles((p.Wd + 31) / 32, (p.H + 31) / 32);
   hipLaunchKernelGGL(rg_init_kernel, tiles, dim3(256), 0, s, p, st);
   int src = 0;
-  for (int n0 = 0; n0 <= p.N; n0 += kLsBlock) {
-    const int K = std::min(kLsBlock, p.N + 1 - n0);
+  for (int n0 = 0; n0 <= p.N; n0 += kLsBlockSmall) {
+    const int K = std::min(kLsBlockSmall, p.N + 1 - n0);
     hipLaunchKernelGGL(rg_first_kernel, dim3((p.H + R1 - 1) / R1), dim3(R1 * Trp1), lds1, s, p, st, K, src, R1, Tr1,
                        Trp1);
     hipLaunchKernelGGL(rg_transpose_kernel, dim3((p.Wd + 63) / 64, (p.H + 63) / 64, K), dim3(256), 0, s, st, p.H,

@@ -112,14 +112,14 @@ __global__ __launch_bounds__(256) void vol_depth_kernel(TileParams p, LsState st
 
 int64_t vol_state_bytes(int D, int Hs, int Wd, int W, bool wide) {
   const int64_t H = (int64_t)D * Hs;
-  return ls_state_bytes((int)H, Wd, W, false, wide) + kLsBlock * (H * Wd * 4 + 256);
+  return ls_state_bytes((int)H, Wd, W, false, wide) + kLsBlockSmall * (H * Wd * 4 + 256);
 }
 
 LsState vol_layout(void* base, int D, int Hs, int Wd, int W, VolBufs* g, bool wide) {
   const int H = D * Hs;
   LsState st = ls_layout(base, H, Wd, W, false, wide);
   char* q = (char*)base + ls_state_bytes(H, Wd, W, false, wide);
-  for (int k = 0; k < kLsBlock; ++k) {
+  for (int k = 0; k < kLsBlockSmall; ++k) {
     g->G[k] = (float*)q;
     q += ((int64_t)H * Wd * 4 + 255) & ~255LL;
   }
@@ -137,8 +137,8 @@ hipError_t launch_forward_vol(const TileParams& p, const LsState& st, const VolB
   const size_t clds = (size_t)(kVolTile + 2 * p.W) * kVolTile * 4;
   const dim3 gdep((unsigned)((int64_t)Hs * p.Wd + 255) / 256, (D + kVolDepth - 1) / kVolDepth);
   int src = 0;
-  for (int n0 = 0; n0 <= p.N; n0 += kLsBlock) {
-    const int K = std::min(kLsBlock, p.N + 1 - n0);
+  for (int n0 = 0; n0 <= p.N; n0 += kLsBlockSmall) {
+    const int K = std::min(kLsBlockSmall, p.N + 1 - n0);
     e = p.wide ? launch_rows_x3_wide(p, st, n0, K, src, s) : ls_launch_rows(p, st, n0, K, src, s);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(vol_cols_kernel, dim3(tiles), dim3(256), clds, s, p, st, g, K, Hs);
