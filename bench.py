@@ -49,8 +49,8 @@ MFMA_F32_PEAK_TFLOPS = 157.3
 # FP32-product ceiling of that arithmetic is a sixth of it.
 MFMA_BF16_PEAK_TFLOPS = 2500.0
 SPLIT_PRODUCTS = 6
-SPLIT_MIN_W = 31  # from this support both streamed passes use the split arithmetic
-PRESPLIT_MIN_W = 57  # from this support the row pass writes its outputs split (plain forward)
+# 4096^2 plans run 64 orders per block, and every streamed Gaussian support
+# then writes its row-filtered images pre-split (rows_x3_split + cols_x3p)
 
 SWEEP = ([("gauss", dict(sigma_s=s), r) for s in (3.0, 10.0, 25.0) for r in (10.0, 30.0, 50.0)]
          + [("box", dict(W=w), r) for w in (10, 30, 75) for r in (10.0, 30.0, 50.0)])
@@ -147,22 +147,19 @@ def engine_of(kind, W, info):
         return "fused_valu_tile"
     if kind == "box":
         return f"box_strips_{info.tile_cols + 2 * W}"
-    if W >= PRESPLIT_MIN_W:
-        return "rows_x3_split+cols_x3p"
-    return "rows_x3+cols_x3s" if W >= SPLIT_MIN_W else "rows_x3+cols_mfma"
+    return "rows_x3_split+cols_x3p"
 
 
 def seams(kind, W, info):
     """(row, column) of a seam of the engine's work decomposition: fused tiles
     of 64 columns x tile_rows; box strips of tile_cols output columns cut into
     row segments of tile_rows (the plan reports both); streamed Gaussian passes
-    on 16 x 256 row tiles and 64 x 64 column tiles (32 x 128 from W = 31,
-    16 x 256 from W = 57)."""
+    on 16 x 256 row tiles and 16-column x 256-row column tiles."""
     if info.path == 0:
         return info.tile_rows, 64
     if kind == "box":
         return info.tile_rows, info.tile_cols
-    return (256 if W >= PRESPLIT_MIN_W else 128 if W >= SPLIT_MIN_W else 64), 256
+    return 256, 256
 
 
 def setting_roof(kind, W, N, ms, info, H, Wd):
@@ -170,15 +167,13 @@ def setting_roof(kind, W, N, ms, info, H, Wd):
     achieved = flops / (ms * 1e-3) / 1e12
     eng = engine_of(kind, W, info)
     extra = {}
-    if eng in ("rows_x3+cols_x3s", "rows_x3_split+cols_x3p"):
+    if eng == "rows_x3_split+cols_x3p":
         # the FIR products run as split-BF16 matrix-core products: priced at the
         # FP32-product ceiling of that arithmetic, with the FP32 matrix-core ratio beside
         bound, peak = "mfma", MFMA_BF16_PEAK_TFLOPS / SPLIT_PRODUCTS
         extra = {"peak_basis": f"BF16 dense {MFMA_BF16_PEAK_TFLOPS:g} TFLOP/s / {SPLIT_PRODUCTS} products "
                                "per FP32 product",
                  "frac_of_fp32_mfma_peak": round(achieved / MFMA_F32_PEAK_TFLOPS, 4)}
-    elif eng == "rows_x3+cols_mfma":
-        bound, peak = "mfma", MFMA_F32_PEAK_TFLOPS
     else:
         bound, peak = "alu", ALU_PEAK_TFLOPS
     return flops, {"bound": bound, "achieved": round(achieved, 3), "peak": round(peak, 1), "unit": "TFLOP/s",
@@ -188,7 +183,7 @@ def setting_roof(kind, W, N, ms, info, H, Wd):
 # rocprofv3 runs whose summaries are committed under profiles/ (run from the
 # repository root; DIR is the output folder, then `bench.py --summarize DIR`).
 # The counter runs take one setting per forward engine (sweep indices 0, 3, 6,
-# 9, 12, 15: fused Gaussian tile, rows_x3 + cols_mfma, split rows_x3 + cols_x3p, fused
+# 9, 12, 15: fused Gaussian tile, split rows_x3 + cols_x3p at W = 30 and 75, fused
 # box tile, 256-column box strips, 512-column box strips, all at sigma_r = 10).
 TRAFFIC_SETTINGS = [0, 3, 6, 9, 12, 15]
 PROFILE_RUNS = {
@@ -256,10 +251,9 @@ def summarize(dirpath, sweep_settings):
              PROFILE_RUNS["trace"], "python3 bench.py --summarize DIR", "```", "",
              f"Each setting runs {per_call} forward calls (1 warm-up + 2 timed). A call is one fused "
              "launch (`gpa_forward_w_kernel`, the tile compiled for its support W <= 21, else "
-             "`gpa_forward_kernel`), or the streamed sequence `ls_init`, per block of orders (16 orders: "
-             "`ls_rows_x3` writing split outputs + `ls_cols_x3p` for the Gaussian from W = 57, `ls_rows_x3` + "
-             "`ls_cols_x3s` from W = 31, `ls_rows_x3` + `ls_cols_mfma` below; "
-             "32 or 16 orders: `ls_box_strip` for the box), `ls_final`.",
+             "`gpa_forward_kernel`), or the streamed sequence `ls_init`, per block of orders (64 orders: "
+             "`ls_rows_x3` writing split outputs + `ls_cols_x3p` for the Gaussian; "
+             "32, 16 or 8 orders: `ls_box_strip` for the box), `ls_final`.",
              "", "| kernel | calls | total ms | avg us | % |", "|---|---|---|---|---|"]
     for k, v in sorted(per_kernel.items(), key=lambda kv: -sum(kv[1])):
         lines.append(f"| `{k}` | {len(v)} | {sum(v) / 1e3:.2f} | {sum(v) / len(v):.1f} | "

@@ -233,7 +233,7 @@ int64_t ls_state_bytes(int H, int Wd, int W, bool save, bool wide = false, bool 
 LsState ls_layout(void* base, int H, int Wd, int W, bool save, bool wide = false, bool split = false,
                   int nblock = kLsBlockSmall);
 int ls_block_orders(int H, int Wd, int kernel, int W);
-bool ls_split_supported(int W);
+bool ls_split_supported(int W, int nblock);
 hipError_t launch_forward_ls(const TileParams& p, const LsState& st, bool save, hipStream_t s);
 // plan-level helpers of the batch (bf_plan.cpp): the streamed forward of a
 // single-image plan with the image pointers read from `dyn` (device memory)

@@ -755,13 +755,16 @@ int64_t ls_cols_x3p_lds_bytes(int W) {
   return kX3pSets * 3 * (32LL * x3p_steps(W) + 256) * kX3pCols * 2;  // the Toeplitz table passes through the last set
 }
 
-// Supports of at least 5 k-steps (W >= 57).  4096^2 Gaussians, ms per call
-// (sigma_r = 10 / 30 / 50), split-once column pass against this pair:
-// W = 75 21.7 / 5.30 / 3.16 against 20.7 / 4.80 / 2.74; at W = 30, against
-// the float32 matrix-core column pass, 17.1 / 4.17 / 2.53 against
-// 17.4 / 4.10 / 2.33 (the split row pass costs about as much as it saves).
-bool ls_split_supported(int W) {
-  return ls_x3_supported(W) && x3p_steps(W) >= 5 && x3p_steps(W) <= kX3MaxSteps &&
+// With blocks of 64 orders every support; with 16 those of at least 5
+// k-steps (W >= 57).  4096^2 Gaussians, ms per call (sigma_r = 10 / 30 / 50),
+// 16 orders per block, split-once column pass against this pair: W = 75
+// 21.7 / 5.30 / 3.16 against 20.7 / 4.80 / 2.74; at W = 30, against the
+// float32 matrix-core column pass, 17.1 / 4.17 / 2.53 against 17.4 / 4.10 /
+// 2.33 (the split row pass costs about as much as it saves).  With 64 orders
+// per block, W = 30: 14.9 / 3.27 / 2.03 against 13.7 / 3.12 / 1.99 (and
+// 14.3 / 3.17 / 1.97 for the split-once column pass).
+bool ls_split_supported(int W, int nblock) {
+  return ls_x3_supported(W) && x3p_steps(W) >= (nblock >= kLsBlock ? 1 : 5) && x3p_steps(W) <= kX3MaxSteps &&
          ls_cols_x3p_lds_bytes(W) <= max_lds_bytes();
 }
 
@@ -878,7 +881,8 @@ static hipError_t cols_x3p_s(const TileParams& p, const LsState& st, int n0, int
 }
 
 hipError_t launch_cols_x3p(const TileParams& p, const LsState& st, int n0, int K, hipStream_t s) {
-  if (!st.Hs[0] || !ls_split_supported(p.W) || (st.hs_plane + 512 * st.pitch) * 2 >= (1LL << 31) || p.mirror)
+  if (!st.Hs[0] || !ls_split_supported(p.W, st.block) || (st.hs_plane + 512 * st.pitch) * 2 >= (1LL << 31) ||
+      p.mirror)
     return hipErrorInvalidValue;
   switch (x3p_steps(p.W)) {
     case 1: return cols_x3p_s<1>(p, st, n0, K, s);

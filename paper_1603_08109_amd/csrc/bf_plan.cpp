@@ -670,9 +670,9 @@ int bf_plan(const bf_params* in, bf_plan_t** out) {
   if (ls) {
     // the plain Gaussian forward (no adjoint state, zero border, split passes)
     // keeps its row-filtered images pre-split
-    const bool split = !wide && !grad && p.kernel == BF_GAUSS && !(p.flags & (BF_FLAG_MIRROR | BF_FLAG_MFMA_FP32)) &&
-                       ls_split_supported(p.W);
     const int nblock = ls_block_orders(p.height, p.width, p.kernel, p.W);
+    const bool split = !wide && !grad && p.kernel == BF_GAUSS && !(p.flags & (BF_FLAG_MIRROR | BF_FLAG_MFMA_FP32)) &&
+                       ls_split_supported(p.W, nblock);
     const int64_t lb = ls_state_bytes(p.height, p.width, p.W, grad, wide, split, nblock);
     e = hipMalloc(&pl->d_ls, lb);
     if (e != hipSuccess) {

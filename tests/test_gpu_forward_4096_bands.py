@@ -6,10 +6,9 @@ Each engine that the planner picks at 4096^2 is checked on its own shape:
     tiles of 64 columns x tile_rows rows;
   * the box column strips (256 columns at W = 30, 512 columns at W = 75),
     cut into row segments (the plan reports both);
-  * the split-bfloat16 row pass with the float32 matrix-core column pass
-    (Gaussian sigma_s = 10: 16 x 256 row tiles, 64 x 64 column tiles), and
-    from W = 57 the row pass writing its outputs split with the column pass
-    on them (sigma_s = 25: column tiles of 16 columns x 256 rows).
+  * the split-bfloat16 row pass writing its outputs split, with the column
+    pass on them (Gaussian sigma_s = 10 and 25; 4096^2 plans run 64 orders
+    per block): 16 x 256 row tiles, column tiles of 16 columns x 256 rows.
 A band of rows [r0, r1) and columns [c0, c1) is compared with Algorithm 2
 (oracle.gpa.gpa_alg2) evaluated on the crop grown by W on every side (clipped
 to the image).  Every output of the band has its whole window inside that crop
@@ -42,8 +41,8 @@ def _bands(kind, W, info):
         seam_r, seam_c = info.tile_rows, 64
     elif kind == "box":  # column strips: row segments and output columns per strip, as the plan reports them
         seam_r, seam_c = info.tile_rows, info.tile_cols
-    else:  # streamed Gaussian: 16-row row-pass tiles; 64-row column-pass tiles, 256 rows from W = 57
-        seam_r, seam_c = (256 if W >= 57 else 64), 256
+    else:  # streamed Gaussian: 16-row row-pass tiles, 256-row column-pass tiles
+        seam_r, seam_c = 256, 256
     # narrow supports: full-width bands; wide ones: 3+ column seams (cost)
     width = Wd if W <= 30 else 3 * seam_c + 40
     return [(seam_r - 2, seam_r + 2, 0, width),

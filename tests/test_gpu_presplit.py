@@ -1,5 +1,6 @@
 """The plain streamed Gaussian forward with pre-split row-filtered images
-(supports W >= 57): the row pass writes its outputs as three bfloat16
+(supports W >= 57, and every support on images of 4 Mpx or more, which run
+64 orders per block): the row pass writes its outputs as three bfloat16
 planes in groups of eight rows, round_up(W, 8) zero rows above the image,
 and the column pass copies them into LDS with its taps shifted by
 round_up(W, 8) - W rows.
@@ -86,3 +87,28 @@ def test_presplit_two_calls_and_constant():
     fx = x.cpu().numpy().astype(np.float64)
     ref = G.gpa_alg2(fx, K.taps1d("gauss", 25.0), 30.0, plan.info.N, 127.5)
     assert np.abs(y.cpu().numpy().astype(np.float64) - ref).max() <= TOL
+
+
+@pytest.mark.parametrize("W", [13, 30, 41])
+def test_presplit_small_supports_4mpx(W):
+    # images of 4 Mpx and more run 64 orders per block and pre-split planes at
+    # every support: a band across the first 256-row column-tile seam and the
+    # last rows, against the oracle on the band grown by W (exact there)
+    import torch
+    import paper_1603_08109_amd as P
+    H = Wd = 2048
+    f = synthimg.gen2(H, Wd, 700 + W)
+    x = torch.tensor(f, dtype=torch.float32, device="cuda")
+    ss = W / 3.0
+    plan = P.Plan("gauss", 30.0, H, Wd, sigma_s=ss, W=W, engine="streamed")
+    y = plan.forward(x)
+    torch.cuda.synchronize()
+    out = y.cpu().numpy().astype(np.float64)
+    fx = x.cpu().numpy().astype(np.float64)
+    w1 = K.taps1d("gauss", ss, W)
+    for r0, r1, c0, c1 in [(254, 258, 0, Wd), (H - 3, H, Wd - 600, Wd)]:
+        R0, R1, C0, C1 = max(0, r0 - W), min(H, r1 + W), max(0, c0 - W), min(Wd, c1 + W)
+        ref = G.gpa_alg2(fx[R0:R1, C0:C1], w1, 30.0, plan.info.N, 127.5)[r0 - R0:r1 - R0, c0 - C0:c1 - C0]
+        d = np.abs(out[r0:r1, c0:c1] - ref).max()
+        print(f"W={W} band {r0}:{r1} x {c0}:{c1}: max {d:.3e}", flush=True)
+        assert d <= TOL
