@@ -356,8 +356,8 @@ static double streamed_cost(int kernel, int W) {
   return (256.0 + 2 * W) / 256.0 * (L + 4.0) + (L + 4.0) + 5.0 + 100.0;
 }
 
-static int choose_forward_tile(int kernel, int W, int H, int Wd, bool allow_streamed, int* variant, int* TY,
-                               double* cost = nullptr) {
+static int choose_forward_tile(int kernel, int W, int H, int Wd, int N, bool allow_streamed, int* variant,
+                               int* TY, double* cost = nullptr) {
   const int nv = forward_variant_count();
   int best = -1;
   double bestc = 0.0;
@@ -376,20 +376,28 @@ static int choose_forward_tile(int kernel, int W, int H, int Wd, bool allow_stre
     }
   }
   if (best < 0) return fail(BF_EUNSUPPORTED, "support W too large for the fused tile kernels");
-  // The streamed path launches kernels per block of 16 orders.  Box: the column
-  // strips beat the fused tiles from W = 16 on images of 2^20 pixels and more
-  // (measured on 4096^2: W = 10 fused 1.7 vs strips 1.9 ps per pixel and order,
-  // W = 30 4.4 vs 2.2).  Gaussian: the split matrix-core passes win from about
-  // W = 14 at every size measured, 64 x 64 to 4096^2 (on 256 images of 64..1024
-  // x 64..768 with sigma_s in [2, 15]: 166.6 ms fused, 75.7 ms taking the faster
-  // engine per image, 76.1 ms from W = 16 on); W = 15 on 512^2 is still faster
-  // fused (0.21 vs 0.23 ms), hence W >= 16; from W = 13 on 2^22 pixels and more
-  // (4096^2: W = 9 tile 9.4 vs streamed 14.0 ms, W = 15 18.5 vs 15.6 ms).
+  // The streamed engines pay a fixed cost per call and per block of orders
+  // (the lift, the final ratio, launch ramps, the box strips' warm-up rows)
+  // for a lower cost per order at wide supports, so the crossover falls with
+  // the order N.  Measured on 4096^2 (ms, fused / streamed, sigma_r = 10 / 30
+  // / 50, N = 250 / 50 / 30): box W = 13 5.11 / 4.44, 1.15 / 1.28; W = 16
+  // 5.25 / 4.52, 1.17 / 1.30, 0.72 / 0.76; W = 20 8.38 / 4.71, 1.84 / 1.35,
+  // 1.11 / 0.79.  Gaussian W = 14 11.5 / 13.0, 2.46 / 3.00; W = 15 13.6 /
+  // 13.1, 2.90 / 3.00, 1.71 / 1.90; W = 16 13.1 / 13.1, 2.84 / 3.00; W = 18
+  // 18.6 / 13.4, 3.93 / 3.04, 2.31 / 1.92.  Box strips therefore from W = 18,
+  // and from W = 13 with 150 orders or more, on images of 2^20 pixels and
+  // more; the Gaussian from W = 17, and from W = 15 with 150 orders or more,
+  // on images of 2^22 pixels and more (64 orders per block).  Below 2^22
+  // pixels (16 orders per block) the Gaussian's split passes win from about
+  // W = 14 at every size measured, 64 x 64 to 2048^2 (on 256 images of
+  // 64..1024 x 64..768 with sigma_s in [2, 15]: 166.6 ms fused, 75.7 ms taking
+  // the faster engine per image, 76.1 ms from W = 16 on); W = 15 on 512^2 is
+  // still faster fused (0.21 vs 0.23 ms), hence W >= 16.
   const int64_t npx = (int64_t)H * Wd;
   if (allow_streamed && ls_supported(W)) {
-    const bool gauss_wide = W >= 16 || (npx >= (1 << 22) && W >= 13) ||
-                            (npx >= (1 << 20) && bestc > streamed_cost(kernel, W));
-    const bool box_wide = npx >= (1 << 20) && W >= 16 && ls_box_strip_supported(W);
+    const bool gauss_wide = npx >= (1 << 22) ? (W >= 17 || (W >= 15 && N >= 150))
+                                             : (W >= 16 || (npx >= (1 << 20) && bestc > streamed_cost(kernel, W)));
+    const bool box_wide = npx >= (1 << 20) && ls_box_strip_supported(W) && (W >= 18 || (W >= 13 && N >= 150));
     if (kernel == BF_BOX ? box_wide : gauss_wide) return fail(BF_EUNSUPPORTED, "streamed path is cheaper at this support");
   }
   *variant = best;
@@ -429,7 +437,8 @@ struct ForwardPath {
   int TY;       // tile rows (0 on the streamed path)
 };
 
-static int choose_forward_path(const bf_params& p, ForwardPath* fp) {
+// N: the order the plan takes (the engines' crossover depends on it).
+static int choose_forward_path(const bf_params& p, int N, ForwardPath* fp) {
   if ((p.flags & BF_FLAG_STREAMED) && (p.flags & BF_FLAG_TILE_VALU))
     return fail(BF_EINVAL, "at most one of the STREAMED / TILE_VALU flags");
   const bool mirror = (p.flags & BF_FLAG_MIRROR) != 0;
@@ -462,11 +471,11 @@ static int choose_forward_path(const bf_params& p, ForwardPath* fp) {
   }
   if (p.flags & BF_FLAG_TILE_VALU) {
     fp->engine = BF_PATH_TILE;
-    return choose_forward_tile(p.kernel, p.W, p.height, p.width, false, &fp->variant, &fp->TY);
+    return choose_forward_tile(p.kernel, p.W, p.height, p.width, N, false, &fp->variant, &fp->TY);
   }
   if (!(p.flags & BF_FLAG_STREAMED)) {
     double c = 0.0;
-    if (choose_forward_tile(p.kernel, p.W, p.height, p.width, true, &fp->variant, &fp->TY, &c) == BF_OK) {
+    if (choose_forward_tile(p.kernel, p.W, p.height, p.width, N, true, &fp->variant, &fp->TY, &c) == BF_OK) {
       fp->engine = BF_PATH_TILE;
       return BF_OK;
     }
@@ -530,7 +539,7 @@ int bf_order(const bf_params* in, bf_plan_info* out) {
   // the engine needs the image size, except that lambda above 170 admits one engine whatever the size
   if ((p.height > 0 && p.width > 0) || out->lambda > kLambdaF32) {
     ForwardPath fp;
-    const int pst = choose_forward_path(p, &fp);
+    const int pst = choose_forward_path(p, out->N, &fp);
     if (pst < 0) return pst;
     out->path = fp.engine;
     out->tile_rows = fp.TY;
@@ -596,7 +605,7 @@ int bf_plan(const bf_params* in, bf_plan_t** out) {
     return fail(BF_EUNSUPPORTED, "the recursive Gaussian has no adjoint");
   if ((p.flags & BF_FLAG_MIRROR) && (p.flags & BF_FLAG_GRAD)) return plan_mirror_adjoint(p, out);
   ForwardPath fpath;
-  st = choose_forward_path(p, &fpath);
+  st = choose_forward_path(p, info.N, &fpath);
   if (st < 0) return st;
   const bool wide = fpath.engine == BF_PATH_WIDE;
   const bool ls = fpath.engine == BF_PATH_STREAMED || wide;  // streamed orders through device memory
@@ -859,7 +868,7 @@ int bf_forward_noalloc(const bf_params* in_p, const float* in, int64_t in_pitch,
   const int ost = plan_order(&p, &info);
   if (ost < 0) return ost;
   ForwardPath fpath;
-  st = choose_forward_path(p, &fpath);
+  st = choose_forward_path(p, info.N, &fpath);
   if (st < 0) return st;
   if (fpath.engine != BF_PATH_TILE)
     return fail(BF_EUNSUPPORTED, "the allocation-free forward serves the fused-tile engine only; this image "

@@ -110,14 +110,27 @@ def test_engine_selection():
     s = P.bf_order("gauss", 30.0, sigma_s=3.0, engine="streamed", **kw)
     assert s.path == L.BF_PATH_STREAMED
     assert P.bf_order("gauss", 30.0, sigma_s=25.0, **kw).path == L.BF_PATH_STREAMED  # W = 75
-    # the Gaussian takes the streamed passes from W = 16 at every size (W = 15 stays fused below 2^22
-    # pixels, W = 13 goes streamed from 2^22 pixels); the box keeps its fused tiles below 2^20 pixels
+    # the Gaussian takes the streamed passes from W = 16 below 2^22 pixels (W = 15 stays fused); the box
+    # keeps its fused tiles below 2^20 pixels
     for H, Wd in ((1, 1), (64, 64), (512, 512), (768, 1024)):
         assert P.bf_order("gauss", 30.0, sigma_s=5.0, height=H, width=Wd).path == L.BF_PATH_TILE  # W = 15
         assert P.bf_order("gauss", 30.0, sigma_s=5.1, height=H, width=Wd).path == L.BF_PATH_STREAMED  # W = 16
         assert P.bf_order("box", 30.0, W=40, height=H, width=Wd).path == L.BF_PATH_TILE
-    assert P.bf_order("gauss", 30.0, sigma_s=4.3, height=2048, width=2048).path == L.BF_PATH_STREAMED  # W = 13
-    assert P.bf_order("box", 30.0, W=40, height=1024, width=1024).path == L.BF_PATH_STREAMED
+    # from 2^22 pixels the Gaussian goes streamed from W = 17, and from W = 15 with 150 orders or more
+    # (sigma_r = 30: N = 49, sigma_r = 10: N = 250)
+    big = dict(height=2048, width=2048)
+    assert P.bf_order("gauss", 30.0, sigma_s=4.3, **big).path == L.BF_PATH_TILE  # W = 13
+    assert P.bf_order("gauss", 10.0, sigma_s=4.3, **big).path == L.BF_PATH_TILE  # W = 13
+    assert P.bf_order("gauss", 30.0, W=16, sigma_s=5.2, **big).path == L.BF_PATH_TILE
+    assert P.bf_order("gauss", 10.0, W=15, sigma_s=5.0, **big).path == L.BF_PATH_STREAMED
+    assert P.bf_order("gauss", 30.0, W=17, sigma_s=5.6, **big).path == L.BF_PATH_STREAMED
+    # box strips from 2^20 pixels: from W = 18, and from W = 13 with 150 orders or more
+    mid = dict(height=1024, width=1024)
+    assert P.bf_order("box", 30.0, W=40, **mid).path == L.BF_PATH_STREAMED
+    assert P.bf_order("box", 30.0, W=18, **mid).path == L.BF_PATH_STREAMED
+    assert P.bf_order("box", 30.0, W=16, **mid).path == L.BF_PATH_TILE
+    assert P.bf_order("box", 10.0, W=13, **mid).path == L.BF_PATH_STREAMED
+    assert P.bf_order("box", 10.0, W=12, **mid).path == L.BF_PATH_TILE
     with pytest.raises(L.BFError) as e:
         P.bf_order("gauss", 30.0, sigma_s=3.0, engine="valu", streamed=True, **kw)
     assert e.value.code == L.BF_EINVAL
