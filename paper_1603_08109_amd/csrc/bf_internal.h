@@ -113,16 +113,18 @@ __host__ __device__ inline int ls_split_top(int W) { return (W + 7) & ~7; }
 __host__ __device__ inline int64_t ls_split_rows(int H, int W) { return ls_split_top(W) + (int64_t)((H + 15) / 16) * 16; }
 
 // Streamed adjoint (supports too wide for the fused adjoint tiles): orders
-// per block and its device state.
-constexpr int kBlsBlock = 8;
+// per block (kBlsBlock from 4 Mpx, kBlsBlockSmall below) and its device state.
+constexpr int kBlsBlock = 32;
+constexpr int kBlsBlockSmall = 8;
 constexpr int kBlsPartials = 1024;  // workgroups of the final reduction pass
 struct BlsState {
   int64_t pitch;               // row pitch (floats) of the image-shaped buffers
   float* A[2];                 // scaled coefficients a_m (double-buffered)
   float* B[2];                 // b_m = a_{m-1} r_m (double-buffered)
-  float* R[2 * kBlsBlock];     // row-filtered adjoint images: taps, then d^2 taps
+  float* R[2 * kBlsBlock];     // row-filtered adjoint images: taps (R[k]), then d^2 taps (R[kBlsBlock + k])
   float *fc, *fp;              // F~_m and F~_{m-1} at each pixel
   double *dx, *dss;            // per-pixel sums of the image and sigma_s gradients
+  int block;                   // orders per block (row-filtered images allocated per tap set)
 };
 
 // Kernel-shape variants (compile-time register budgets).
@@ -240,8 +242,9 @@ hipError_t launch_forward_ls(const TileParams& p, const LsState& st, bool save, 
 hipError_t plan_forward_streamed_dyn(const bf_plan_t* pl, const TileParams* dyn, bool save, hipStream_t s);
 // streamed adjoint (bf_large_bwd.hip)
 bool bls_supported(int W, bool sigs);
-int64_t bls_state_bytes(int H, int Wd, int W, bool sigs);
-BlsState bls_layout(void* base, int H, int Wd, int W, bool sigs);
+int64_t bls_state_bytes(int H, int Wd, int W, bool sigs, int nblock = kBlsBlockSmall);
+BlsState bls_layout(void* base, int H, int Wd, int W, bool sigs, int nblock = kBlsBlockSmall);
+int bls_block_orders(int H, int Wd);
 hipError_t launch_backward_ls(const TileParams& p, const BlsState& st, bool sigs, double* partials,
                               double* grad_sigma, hipStream_t s);
 hipError_t launch_sigma_reduce(const double* partials, int n, bool has_ss, double* out, hipStream_t s);

@@ -2,7 +2,7 @@
 // supports too wide for the fused adjoint tiles.  It computes what the fused
 // adjoint kernel does (same scaled recursions, same float64 sums), with the
 // N + 1 filterings of the adjoint images adj_m moved through device memory in
-// blocks of kBlsBlock orders, as in the streamed forward:
+// blocks of st.block orders, as in the streamed forward:
 //   bls_init  : a_0 = (g sigma_r / Q) E and b_0 = 0 on the image, F~_0 = E and
 //               zeroed sums at each pixel;
 //   bls_rows  : per block, adj_m = b_m [m >= 1] - rho a_m [m <= N - 1] on a
@@ -279,18 +279,24 @@ bool bls_supported(int W, bool sigs) {
          bls_rows_lds_bytes(W, sigs) <= max_lds_bytes() && bls_cols_lds_bytes(W, sigs) <= max_lds_bytes();
 }
 
-int64_t bls_state_bytes(int H, int Wd, int W, bool sigs) {
+// Orders per block of the streamed adjoint: 32 from 4 Mpx (the per-pixel
+// state crosses HBM once per block), else 8, which bounds the row-filtered
+// images of smaller images (the batch shares one state among its images).
+int bls_block_orders(int H, int Wd) { return (int64_t)H * Wd >= (int64_t)4 << 20 ? kBlsBlock : kBlsBlockSmall; }
+
+int64_t bls_state_bytes(int H, int Wd, int W, bool sigs, int nblock) {
   const int64_t pitch = ((Wd + 63) / 64) * 64;
   const int64_t img = pitch * H;
   const int64_t himg = pitch * ls_hrows(H, W);
   const int64_t npx = (int64_t)H * Wd;
-  const int64_t nr = (sigs ? 2 : 1) * kBlsBlock;
+  const int64_t nr = (sigs ? 2 : 1) * nblock;
   const int64_t b = 4 * img * 4 + nr * himg * 4 + 2 * npx * 4 + 2 * npx * 8;
   return b + 256 * (4 + nr + 4);  // alignment of each buffer
 }
 
-BlsState bls_layout(void* base, int H, int Wd, int W, bool sigs) {
-  BlsState st;
+BlsState bls_layout(void* base, int H, int Wd, int W, bool sigs, int nblock) {
+  BlsState st = {};
+  st.block = nblock;
   const int64_t pitch = ((Wd + 63) / 64) * 64;
   const int64_t img = pitch * H;
   const int64_t himg = pitch * ls_hrows(H, W);
@@ -304,7 +310,8 @@ BlsState bls_layout(void* base, int H, int Wd, int W, bool sigs) {
   st.pitch = pitch;
   for (int i = 0; i < 2; ++i) st.A[i] = (float*)take(img * 4);
   for (int i = 0; i < 2; ++i) st.B[i] = (float*)take(img * 4);
-  for (int k = 0; k < 2 * kBlsBlock; ++k) st.R[k] = (k < kBlsBlock || sigs) ? (float*)take(himg * 4) : nullptr;
+  for (int k = 0; k < nblock; ++k) st.R[k] = (float*)take(himg * 4);
+  for (int k = 0; sigs && k < nblock; ++k) st.R[kBlsBlock + k] = (float*)take(himg * 4);
   st.fc = (float*)take(npx * 4);
   st.fp = (float*)take(npx * 4);
   st.dx = (double*)take(npx * 8);
@@ -315,7 +322,7 @@ BlsState bls_layout(void* base, int H, int Wd, int W, bool sigs) {
 hipError_t launch_backward_ls(const TileParams& p, const BlsState& st, bool sigs, double* partials,
                               double* grad_sigma, hipStream_t s) {
   if (p.H <= 0 || p.Wd <= 0) return hipSuccess;
-  if (sigs && !st.R[kBlsBlock]) return hipErrorInvalidValue;
+  if (st.block <= 0 || st.block > kBlsBlock || (sigs && !st.R[kBlsBlock])) return hipErrorInvalidValue;
   if (!bls_supported(p.W, sigs)) return hipErrorInvalidValue;
   const int64_t npx = (int64_t)p.H * p.Wd;
   const int g1 = (int)std::min<int64_t>((npx + kThreads - 1) / kThreads, 4096);
@@ -333,8 +340,8 @@ hipError_t launch_backward_ls(const TileParams& p, const BlsState& st, bool sigs
   const int grow = ((p.H + kBlsRows - 1) / kBlsRows) * ((p.Wd + kBlsCols - 1) / kBlsCols);
   const int gcol = ((p.H + 63) / 64) * ((p.Wd + kTileCols - 1) / kTileCols);
   int src = 0;
-  for (int n0 = 0; n0 <= p.N; n0 += kBlsBlock) {
-    const int K = std::min(kBlsBlock, p.N + 1 - n0);
+  for (int n0 = 0; n0 <= p.N; n0 += st.block) {
+    const int K = std::min(st.block, p.N + 1 - n0);
     hipLaunchKernelGGL(rk, dim3(grow), dim3(kBlsThreads), rl, s, p, st, n0, K, src);
     hipLaunchKernelGGL(ck, dim3(gcol), dim3(kBlsThreads), cl, s, p, st, n0, K);
     e = hipGetLastError();

@@ -713,7 +713,8 @@ int bf_plan(const bf_params* in, bf_plan_t** out) {
     ws += rb;
   }
   if (bls) {
-    const int64_t bb = bls_state_bytes(p.height, p.width, p.W, sigs);
+    const int bblock = bls_block_orders(p.height, p.width);
+    const int64_t bb = bls_state_bytes(p.height, p.width, p.W, sigs, bblock);
     e = hipMalloc(&pl->d_bls, bb);
     if (e == hipSuccess) {
       e = hipMemset(pl->d_bls, 0, bb);  // zero rows around the row-filtered images
@@ -728,7 +729,7 @@ int bf_plan(const bf_params* in, bf_plan_t** out) {
       return e == hipErrorOutOfMemory ? fail(BF_ENOMEM, "hipMalloc streamed adjoint state failed")
                                       : hip_fail(e, "streamed adjoint state");
     }
-    pl->bls_state = bls_layout(pl->d_bls, p.height, p.width, p.W, sigs);
+    pl->bls_state = bls_layout(pl->d_bls, p.height, p.width, p.W, sigs, bblock);
     ws += bb;
   }
   pl->info.workspace_bytes = ws;
