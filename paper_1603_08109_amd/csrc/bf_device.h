@@ -662,46 +662,51 @@ __device__ __forceinline__ void backward_tile(const TileParams& p, int r0, int c
 // Per-pixel coefficient state (a_n, a_{n-1}, a_{n-2}, z = x X) and float64
 // sums of eqs. (P), (Q) (and the adjoint's D_P, D_Q) for CH output pixels,
 // held in registers while orders are folded in; load/store move it to and
-// from the streamed path's state images.
+// from the streamed path's state images.  At the first block (first: n0 = 0)
+// a_{-1}, a_{-2} and the sums start at zero and are not read: the lift
+// writes only a_0 and z.
 template <int CH, bool SAVE>
 struct LsPix {
   float a[CH], ap[CH], app[CH], z[CH];
   double P[CH], Q[CH], DP[CH], DQ[CH];
 
-  __device__ __forceinline__ void load(const LsState& st, int64_t i0, int64_t stride, int n_ok) {
+  __device__ __forceinline__ void load(const LsState& st, int64_t i0, int64_t stride, int n_ok, bool first) {
 #pragma unroll
     for (int s = 0; s < CH; ++s) {
       const bool ok = s < n_ok;
+      const bool rd = ok && !first;
       const int64_t i = i0 + s * stride;
       a[s] = ok ? st.a[i] : 0.f;
-      ap[s] = ok ? st.ap[i] : 0.f;
+      ap[s] = rd ? st.ap[i] : 0.f;
       z[s] = ok ? st.z[i] : 0.f;
-      P[s] = ok ? st.P[i] : 0.0;
-      Q[s] = ok ? st.Q[i] : 0.0;
+      P[s] = rd ? st.P[i] : 0.0;
+      Q[s] = rd ? st.Q[i] : 0.0;
       if (SAVE) {
-        app[s] = ok ? st.app[i] : 0.f;
-        DP[s] = ok ? st.DP[i] : 0.0;
-        DQ[s] = ok ? st.DQ[i] : 0.0;
+        app[s] = rd ? st.app[i] : 0.f;
+        DP[s] = rd ? st.DP[i] : 0.0;
+        DQ[s] = rd ? st.DQ[i] : 0.0;
       }
     }
   }
   // pixels s0 .. s0 + M - 1 at i0 + (s - s0) * stride, the first n_ok of them inside the image
   template <int M>
-  __device__ __forceinline__ void load_part(const LsState& st, int s0, int64_t i0, int64_t stride, int n_ok) {
+  __device__ __forceinline__ void load_part(const LsState& st, int s0, int64_t i0, int64_t stride, int n_ok,
+                                            bool first) {
 #pragma unroll
     for (int u = 0; u < M; ++u) {
       const int s = s0 + u;
       const bool ok = u < n_ok;
+      const bool rd = ok && !first;
       const int64_t i = ok ? i0 + u * stride : 0;
       a[s] = ok ? st.a[i] : 0.f;
-      ap[s] = ok ? st.ap[i] : 0.f;
+      ap[s] = rd ? st.ap[i] : 0.f;
       z[s] = ok ? st.z[i] : 0.f;
-      P[s] = ok ? st.P[i] : 0.0;
-      Q[s] = ok ? st.Q[i] : 0.0;
+      P[s] = rd ? st.P[i] : 0.0;
+      Q[s] = rd ? st.Q[i] : 0.0;
       if (SAVE) {
-        app[s] = ok ? st.app[i] : 0.f;
-        DP[s] = ok ? st.DP[i] : 0.0;
-        DQ[s] = ok ? st.DQ[i] : 0.0;
+        app[s] = rd ? st.app[i] : 0.f;
+        DP[s] = rd ? st.DP[i] : 0.0;
+        DQ[s] = rd ? st.DQ[i] : 0.0;
       }
     }
   }
@@ -763,24 +768,27 @@ template <int CH>
 struct WidePix {
   double a[CH], ap[CH], P[CH], Q[CH];
   float z[CH];
-  __device__ __forceinline__ void load(const LsState& st, int64_t i0, int64_t stride, int n_ok) {
-    load_part<CH>(st, 0, i0, stride, n_ok);
+  // first: as for LsPix (the wide lift writes a~_0 and z only)
+  __device__ __forceinline__ void load(const LsState& st, int64_t i0, int64_t stride, int n_ok, bool first) {
+    load_part<CH>(st, 0, i0, stride, n_ok, first);
   }
   __device__ __forceinline__ void store(const LsState& st, int64_t i0, int64_t stride, int n_ok) const {
     store_part<CH>(st, 0, i0, stride, n_ok);
   }
   template <int M>
-  __device__ __forceinline__ void load_part(const LsState& st, int s0, int64_t i0, int64_t stride, int n_ok) {
+  __device__ __forceinline__ void load_part(const LsState& st, int s0, int64_t i0, int64_t stride, int n_ok,
+                                            bool first) {
 #pragma unroll
     for (int u = 0; u < M; ++u) {
       const int s = s0 + u;
       const bool ok = u < n_ok;
+      const bool rd = ok && !first;
       const int64_t i = ok ? i0 + u * stride : 0;
       a[s] = ok ? st.ad[i] : 0.0;
-      ap[s] = ok ? st.apd[i] : 0.0;
+      ap[s] = rd ? st.apd[i] : 0.0;
       z[s] = ok ? st.z[i] : 0.f;
-      P[s] = ok ? st.P[i] : 0.0;
-      Q[s] = ok ? st.Q[i] : 0.0;
+      P[s] = rd ? st.P[i] : 0.0;
+      Q[s] = rd ? st.Q[i] : 0.0;
     }
   }
   template <int M>

@@ -52,16 +52,8 @@ __global__ __launch_bounds__(kThreads) void ls_init_kernel(TileParams p, LsState
     const int64_t j = (int64_t)r * st.pitch + c;
     st.F[0][j] = E;
     st.Y[j] = (f - p.center) * p.inv_T;
-    st.a[i] = E;
-    st.ap[i] = 0.f;
+    st.a[i] = E;  // a_{-1}, a_{-2} and the sums start at zero in the first block's column pass
     st.z[i] = x * p.X;
-    st.P[i] = 0.0;
-    st.Q[i] = 0.0;
-    if (st.DP) {
-      st.app[i] = 0.f;
-      st.DP[i] = 0.0;
-      st.DQ[i] = 0.0;
-    }
   }
 }
 
@@ -273,7 +265,7 @@ __global__ __launch_bounds__(kColsThreads) void ls_cols_mfma_kernel(TileParams p
 #pragma unroll
   for (int j = 0; j < 2; ++j) {
     const int nr = (pc0 + 16 * j < p.Wd) ? max(0, min(4, p.H - pr0)) : 0;
-    px.template load_part<4>(st, j * 4, (int64_t)pr0 * p.Wd + pc0 + 16 * j, p.Wd, nr);
+    px.template load_part<4>(st, j * 4, (int64_t)pr0 * p.Wd + pc0 + 16 * j, p.Wd, nr, n0 == 0);
   }
   for (int k = 0; k < K; ++k) {
     const int n = n0 + k;
@@ -326,7 +318,7 @@ __global__ __launch_bounds__(kThreads) void ls_cols_box_kernel(TileParams p, LsS
   LsPix<CH, SAVE> px;
   for (int r = rs; r < re; r += CH) {
     const int nr = min(CH, re - r);
-    px.load(st, (int64_t)r * p.Wd + c, p.Wd, nr);
+    px.load(st, (int64_t)r * p.Wd + c, p.Wd, nr, n0 == 0);
 #pragma unroll
     for (int k = 0; k < kLsBlockSmall; ++k) {
       if (k < K) {
@@ -373,7 +365,7 @@ __global__ __launch_bounds__(kThreads) void ls_cols_fir_kernel(TileParams p, LsS
   const float* tz = p.taps + kTapPad;
   const int nr = max(0, min(OPT, p.H - (tr0 + orow)));
   LsPix<OPT, SAVE> px;
-  if (c < p.Wd) px.load(st, (int64_t)(tr0 + orow) * p.Wd + c, p.Wd, nr);
+  if (c < p.Wd) px.load(st, (int64_t)(tr0 + orow) * p.Wd + c, p.Wd, nr, n0 == 0);
   for (int k = 0; k < K; ++k) {
     const int n = n0 + k;
     __syncthreads();
@@ -590,14 +582,15 @@ __global__ __launch_bounds__(kStripThreads, 2) void ls_box_strip_kernel(TilePara
     float ap, z, a;
     double P, Q;
   };
+  // (the first block starts a_{-1} and the sums at zero: the lift writes a_0 and z only)
   auto load_state = [&](int r, PixState (&ps)[CPT]) {
 #pragma unroll
     for (int j = 0; j < CPT; ++j) {
       const int64_t pi = (int64_t)r * p.Wd + (fout[j] ? fcol[j] : 0);
-      ps[j].ap = st.ap[pi];
+      ps[j].ap = n0 == 0 ? 0.f : st.ap[pi];
       ps[j].z = st.z[pi];
-      ps[j].P = st.P[pi];
-      ps[j].Q = st.Q[pi];
+      ps[j].P = n0 == 0 ? 0.0 : st.P[pi];
+      ps[j].Q = n0 == 0 ? 0.0 : st.Q[pi];
       ps[j].a = n0 == 0 ? st.a[pi] : 0.f;
     }
   };
@@ -634,9 +627,9 @@ __global__ __launch_bounds__(kStripThreads, 2) void ls_box_strip_kernel(TilePara
       else
         af[j] = ap[j] * (z[j] * in1_prev);
       if (SAVE) {
-        app[j] = st.app[pi];
-        DP[j] = st.DP[pi];
-        DQ[j] = st.DQ[pi];
+        app[j] = n0 == 0 ? 0.f : st.app[pi];
+        DP[j] = n0 == 0 ? 0.0 : st.DP[pi];
+        DQ[j] = n0 == 0 ? 0.0 : st.DQ[pi];
       }
     }
     double ad[CPT], apd[CPT];

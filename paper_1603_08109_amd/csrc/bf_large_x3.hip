@@ -385,7 +385,7 @@ __global__ __launch_bounds__(kX3ColsThreads) void ls_cols_x3_kernel(TileParams p
 #pragma unroll
   for (int b = 0; b < 2; ++b) {
     const int nr = pc < p.Wd ? max(0, min(4, p.H - (pr0 + 32 * b))) : 0;
-    px.template load_part<4>(st, 4 * b, (int64_t)(pr0 + 32 * b) * p.Wd + pc, p.Wd, nr);
+    px.template load_part<4>(st, 4 * b, (int64_t)(pr0 + 32 * b) * p.Wd + pc, p.Wd, nr, n0 == 0);
   }
   if (p.mirror)
     x3_stage<true>(st.H[0], st.pitch, tr0, c0, W, p.H, groups, buf0);
@@ -635,7 +635,7 @@ __global__ __launch_bounds__(kX3sThreads) void ls_cols_x3s_kernel(TileParams p, 
 #pragma unroll
   for (int b = 0; b < 2; ++b) {
     const int nr = pc < p.Wd ? max(0, min(4, p.H - (pr0 + 32 * b))) : 0;
-    px.template load_part<4>(st, 4 * b, (int64_t)(pr0 + 32 * b) * p.Wd + pc, p.Wd, nr);
+    px.template load_part<4>(st, 4 * b, (int64_t)(pr0 + 32 * b) * p.Wd + pc, p.Wd, nr, n0 == 0);
   }
   // this lane's operand: column 16 cb + l%16, rows 16 rb + 32 q + 8 (l/16) ..
   const int obase = (16 * cb + (lane & 15)) * G::RP + 16 * rb + 8 * (lane >> 4);
@@ -816,7 +816,7 @@ __global__ __launch_bounds__(kX3sThreads) void ls_cols_x3p_kernel(TileParams p, 
 #pragma unroll
   for (int b = 0; b < 2; ++b) {
     const int nr = pc < p.Wd ? max(0, min(4, p.H - (pr0 + 32 * b))) : 0;
-    px.template load_part<4>(st, 4 * b, (int64_t)(pr0 + 32 * b) * p.Wd + pc, p.Wd, nr);
+    px.template load_part<4>(st, 4 * b, (int64_t)(pr0 + 32 * b) * p.Wd + pc, p.Wd, nr, n0 == 0);
   }
   // this lane's operand: column l%16, rows 16 rb + 32 q + 8 (l/16) .. + 7,
   // i.e. group 2 rb + 4 q + l/16
@@ -925,11 +925,8 @@ __global__ __launch_bounds__(256) void wide_init_kernel(TileParams p, LsState st
     const int64_t j = (int64_t)r * st.pitch + c;
     st.Fd[0][j] = E;
     st.Y[j] = x;
-    st.ad[i] = E;
-    st.apd[i] = 0.0;
+    st.ad[i] = E;  // a~_{-1} and the sums start at zero in the first block's column pass
     st.z[i] = x;
-    st.P[i] = 0.0;
-    st.Q[i] = 0.0;
   }
 }
 

@@ -334,7 +334,7 @@ __global__ __launch_bounds__(kRgSecondThreads) void rg_second_kernel(TileParams 
   const RgCoef cf = rg_coef(p.rg_tab);
   const RgLane ln = rg_lane<C>(p.rg_tab, t & 63);
   LsPix<C, false> px;
-  px.load(st, nok > 0 ? i0 : 0, 1, nok);
+  px.load(st, nok > 0 ? i0 : 0, 1, nok, n0 == 0);
   const int64_t hoff = (int64_t)(live ? c : 0) * st.tpitch + r0;
   float xn[C];
   float nn = 0.f;
@@ -380,11 +380,8 @@ __global__ __launch_bounds__(256) void rg_init_kernel(TileParams p, LsState st) 
     const int c = c0 + j, r = r0 + tx;
     if (r < p.H && c < p.Wd) {
       const int64_t i = (int64_t)c * p.H + r;
-      st.a[i] = Ta[tx][j];
-      st.ap[i] = 0.f;
+      st.a[i] = Ta[tx][j];  // a_{-1} and the sums start at zero in the first block
       st.z[i] = Tz[tx][j];
-      st.P[i] = 0.0;
-      st.Q[i] = 0.0;
     }
   }
 }

@@ -83,7 +83,7 @@ __global__ __launch_bounds__(256) void vol_depth_kernel(TileParams p, LsState st
   const float* tz = p.taps + kTapPad;
   typename std::conditional<WIDE, WidePix<kVolDepth>, LsPix<kVolDepth, false>>::type px;
   const int64_t i0 = (int64_t)d0 * plane + (live ? q : 0);
-  px.load(st, i0, plane, nok);
+  px.load(st, i0, plane, nok, n0 == 0);
   for (int k = 0; k < K; ++k) {
     const float* Gk = g.G[k] + (live ? q : 0);
     const int n = n0 + k;
