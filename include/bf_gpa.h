@@ -307,6 +307,8 @@ typedef struct bf_batch_info {
   int64_t workspace_bytes;         /* device bytes held by the batch and its images' plans */
   int64_t forward_graph_launches;  /* hipGraphLaunch calls bf_batch_forward has made */
   int64_t forward_direct_launches; /* launch sequences bf_batch_forward issued outside its graph */
+  int64_t backward_graph_launches; /* hipGraphLaunch calls bf_batch_backward(_saved) has made */
+  int64_t backward_direct_launches;/* adjoint calls issued launch by launch (images with BF_FLAG_MIRROR) */
 } bf_batch_info;
 int bf_batch_get_info(const bf_batch_t* batch, bf_batch_info* out);
 /* Time the candidate launch shapes for this batch on `stream` (inputs as
@@ -322,10 +324,15 @@ int bf_batch_tune(bf_batch_t* batch, const float* const* in, const int64_t* in_p
  * fits the fused adjoint run as one more persistent launch over a
  * cost-ordered work list, and wider supports run the streamed adjoint image
  * by image.  Images on a streamed plan of their own (see bf_batch_plan) run
- * that plan's bf_backward on the batch's side streams, concurrently.  Images
- * with BF_FLAG_MIRROR run bf_backward of a plan of their own (built at
+ * that plan's adjoint on the batch's side streams, concurrently, reading
+ * their pointers from the batch's device copy of the call's parameters.
+ * The whole sequence is captured in a hipGraph on the first call of each
+ * combination of (saved given, grad_sigma given), and every call is then ONE
+ * hipGraphLaunch on `stream` (bf_batch_get_info counts them).  Images with
+ * BF_FLAG_MIRROR run bf_backward of a plan of their own (built at
  * bf_batch_plan, on the image extended by reflection), image by image,
- * recomputing their state.  Arguments are host arrays of `count` entries:
+ * recomputing their state; a batch holding one issues its adjoint launch by
+ * launch.  Arguments are host arrays of `count` entries:
  *   in, in_pitch          the images and row pitches (device pointers)
  *   grad_out, gout_pitch  dL/d(out_i)
  *   grad_in, gin_pitch    NULL, or receives dL/d(in_i) (an entry may be NULL)

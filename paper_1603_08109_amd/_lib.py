@@ -67,6 +67,8 @@ class bf_batch_info(C.Structure):
         ("workspace_bytes", C.c_int64),
         ("forward_graph_launches", C.c_int64),
         ("forward_direct_launches", C.c_int64),
+        ("backward_graph_launches", C.c_int64),
+        ("backward_direct_launches", C.c_int64),
     ]
 
 

@@ -83,10 +83,11 @@ struct BatchRed {
 };
 
 __global__ __launch_bounds__(kThreads) void batch_sigma_reduce_kernel(const double* partials,
-                                                                      const BatchRed* info, double* out) {
+                                                                      const BatchRed* info, const TileParams* gp) {
   __shared__ double red[2][kThreads];
   const BatchRed bi = info[blockIdx.x];
-  if (bi.n < 0) return;  // uniform per workgroup
+  double* out = gp[blockIdx.x].gsig;  // this call's destination of image blockIdx.x (or null)
+  if (bi.n < 0 || !out) return;       // uniform per workgroup
   double a = 0.0, b = 0.0;
   for (int i = threadIdx.x; i < bi.n; i += kThreads) {
     a += partials[2 * (int64_t)(bi.off + i)];
@@ -103,8 +104,8 @@ __global__ __launch_bounds__(kThreads) void batch_sigma_reduce_kernel(const doub
     __syncthreads();
   }
   if (threadIdx.x == 0) {
-    out[2 * blockIdx.x] = red[0][0];
-    out[2 * blockIdx.x + 1] = bi.has_ss ? red[1][0] : __builtin_nan("");
+    out[0] = red[0][0];
+    out[1] = bi.has_ss ? red[1][0] : __builtin_nan("");
   }
 }
 
@@ -232,6 +233,9 @@ struct bf_batch {
   TileParams* h_bstage = nullptr;     // pinned staging of d_bparams
   hipEvent_t bev = nullptr;
   bool bev_used = false;
+  hipGraphExec_t bgexec[4] = {};      // captured adjoints: [saved given | 2 * sigma gradients asked]
+  int64_t bgraph_launches = 0;        // hipGraphLaunch calls made by the batch adjoint
+  int64_t bdirect_launches = 0;       // adjoint sequences issued outside a graph
   void* d_bls = nullptr;              // streamed adjoint state, reused image by image
   double* d_bls_partials = nullptr;
   std::vector<int> mirrored;          // images with the reflecting border: adjoint through their own plan
@@ -321,6 +325,10 @@ static void destroy_graphs(bf_batch* b) {
   for (int k = 0; k < 2; ++k) {
     if (b->gexec[k]) hipGraphExecDestroy(b->gexec[k]);
     b->gexec[k] = nullptr;
+  }
+  for (int k = 0; k < 4; ++k) {
+    if (b->bgexec[k]) hipGraphExecDestroy(b->bgexec[k]);
+    b->bgexec[k] = nullptr;
   }
 }
 
@@ -714,6 +722,8 @@ int bf_batch_get_info(const bf_batch_t* b, bf_batch_info* out) {
     if (pl) out->workspace_bytes += pl->info.workspace_bytes;
   out->forward_graph_launches = b->graph_launches;
   out->forward_direct_launches = b->direct_launches;
+  out->backward_graph_launches = b->bgraph_launches;
+  out->backward_direct_launches = b->bdirect_launches;
   return BF_OK;
 }
 
@@ -841,6 +851,57 @@ int bf_batch_forward_saved(bf_batch_t* b, const float* const* in, const int64_t*
 
 }  // extern "C"
 
+// The adjoint's launches from the staged parameters (h_bstage, copied to
+// the device here): the forward state of the persistent images (unless
+// saved), their adjoint tiles as one persistent launch and the sigma
+// reductions on `s`, and the images on streamed plans of their own on the
+// side streams, forked after the copy and joined back into `s`.  Every
+// launch reads its image pointers from the device copy, so the batch records
+// this once per (saved, sigma) combination into a graph.
+static int record_backward(bf_batch* b, bool have_saved, bool sig, hipStream_t s) {
+  const int n = b->count;
+  const BatchShape& sh = b->cands[b->chosen];
+  if (hipMemcpyAsync(b->d_bparams, b->h_bstage, 2 * (size_t)n * sizeof(TileParams), hipMemcpyHostToDevice, s) !=
+      hipSuccess)
+    return fail(BF_EHIP, "hipMemcpyAsync batch adjoint params");
+  const bool side = b->fork_ev != nullptr;
+  if (side) fork_side(b, s);
+  int st = BF_OK;
+  // images on their own streamed plans: their whole adjoint on the side streams, the state
+  // recomputed into the batch's planes of that image unless saved
+  if (side)
+    for (int j = 0; j < bf_batch::kAux; ++j)
+      for (int i : b->aux_imgs[j]) {
+        if (!b->own_adj[i] || st < 0) continue;
+        const hipError_t e = plan_backward_streamed_dyn(b->fplans[i], b->d_bparams + i, b->d_bparams + n + i,
+                                                        !have_saved, sig, b->aux[j]);
+        if (e != hipSuccess) st = fail(BF_EHIP, std::string("batch streamed-plan adjoint: ") + hipGetErrorString(e));
+      }
+  if (st >= 0) {
+    hipLaunchKernelGGL(batch_reset_kernel, dim3(1), dim3(64), 0, s, b->d_counter);
+    hipError_t e = hipSuccess;
+    if (!have_saved && b->nftiles > 0) {
+      e = launch_batch_v(sh.variant, b->d_bparams, b->d_ftiles, b->nftiles, b->d_counter, grid_of(b), sh.lds,
+                         b->acc64, true, s);
+      if (e != hipSuccess) st = fail(BF_EHIP, std::string("batch forward-state launch: ") + hipGetErrorString(e));
+    }
+    if (st >= 0 && b->nbtiles > 0) {
+      const int grid = std::max(1, std::min(2 * b->num_cu, b->nbtiles));
+      e = launch_batch_bwd(b->bvariant, b->d_bparams + n, b->d_btiles, b->nbtiles, b->d_counter + 1,
+                           b->d_bpartials, grid, b->blds, s);
+      if (e != hipSuccess) st = fail(BF_EHIP, std::string("batch adjoint launch: ") + hipGetErrorString(e));
+    }
+    if (st >= 0 && sig) {
+      hipLaunchKernelGGL(batch_sigma_reduce_kernel, dim3(n), dim3(kThreads), 0, s, (const double*)b->d_bpartials,
+                         (const BatchRed*)b->d_bred, (const TileParams*)(b->d_bparams + n));
+      e = hipGetLastError();
+      if (e != hipSuccess) st = fail(BF_EHIP, std::string("batch sigma reduction: ") + hipGetErrorString(e));
+    }
+  }
+  if (side) join_side(b, s);  // joined even after an error, so a capture ends with every stream rejoined
+  return st;
+}
+
 // saved: NULL (recompute the forward state into the batch workspace) or the
 // per-image planes bf_batch_forward_saved wrote
 static int batch_backward(bf_batch_t* b, const float* const* in, const int64_t* in_pitch,
@@ -852,10 +913,11 @@ static int batch_backward(bf_batch_t* b, const float* const* in, const int64_t* 
   hipStream_t s = (hipStream_t)stream;
   if (b->bev_used && hipEventSynchronize(b->bev) != hipSuccess) return fail(BF_EHIP, "hipEventSynchronize");
   const int n = b->count;
-  const BatchShape& sh = b->cands[b->chosen];
   for (int i = 0; i < n; ++i) {
     TileParams f = b->hp[i];  // forward with state
     TileParams g = b->hp[i];  // adjoint
+    f.dyn = g.dyn = nullptr;
+    f.gsig = g.gsig = nullptr;
     if (b->status[i] >= 0) {
       const int Wd = b->prm[i].width;
       if (!in[i] || !grad_out[i]) return fail(BF_EINVAL, "NULL image pointer in batch");
@@ -864,6 +926,7 @@ static int batch_backward(bf_batch_t* b, const float* const* in, const int64_t* 
       f.in = g.in = in[i];
       f.in_pitch = g.in_pitch = in_pitch[i];
       f.out = nullptr;
+      f.out_pitch = 0;
       if (saved && !saved[i]) return fail(BF_EINVAL, "NULL saved pointer in batch");
       f.saved = g.saved = saved ? const_cast<float*>(saved[i]) : b->d_saved + b->saved_off[i];
       g.gout = grad_out[i];
@@ -871,69 +934,73 @@ static int batch_backward(bf_batch_t* b, const float* const* in, const int64_t* 
       g.out = grad_in ? grad_in[i] : nullptr;
       g.out_pitch = (grad_in && grad_in[i]) ? gin_pitch[i] : 0;
       g.TY = b->bTY[i];
+      g.gsig = grad_sigma ? grad_sigma + 2 * i : nullptr;
     }
     b->h_bstage[i] = f;
     b->h_bstage[n + i] = g;
   }
-  if (hipMemcpyAsync(b->d_bparams, b->h_bstage, 2 * (size_t)n * sizeof(TileParams), hipMemcpyHostToDevice, s) !=
-      hipSuccess)
-    return fail(BF_EHIP, "hipMemcpyAsync batch adjoint params");
-  // the side streams start here (their work is queued after the persistent launches below, and
-  // runs concurrently with them)
-  const bool side = b->fork_ev != nullptr;
-  if (side) fork_side(b, s);
-  hipLaunchKernelGGL(batch_reset_kernel, dim3(1), dim3(64), 0, s, b->d_counter);
+  const bool have_saved = saved != nullptr, sig = grad_sigma != nullptr;
+  // images on the shared streamed-adjoint state (its clear is a memset) and
+  // images with the reflecting border (their own plan's padding launches
+  // take host pointers) keep the call issued launch by launch
+  if (b->streamed.empty() && b->mirrored.empty()) {
+    const int key = (have_saved ? 1 : 0) | (sig ? 2 : 0);
+    if (!b->bgexec[key]) {
+      hipStream_t cap;
+      if (hipStreamCreateWithFlags(&cap, hipStreamNonBlocking) != hipSuccess)
+        return fail(BF_EHIP, "hipStreamCreate");
+      hipGraph_t graph = nullptr;
+      hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeRelaxed);
+      int rs = BF_OK;
+      if (e == hipSuccess) {
+        rs = record_backward(b, have_saved, sig, cap);
+        const hipError_t e2 = hipStreamEndCapture(cap, &graph);
+        if (e == hipSuccess) e = e2;
+      }
+      if (rs >= 0 && e == hipSuccess) e = hipGraphInstantiate(&b->bgexec[key], graph, nullptr, nullptr, 0);
+      if (graph) hipGraphDestroy(graph);
+      hipStreamDestroy(cap);
+      if (rs < 0) return rs;
+      if (e != hipSuccess) {
+        b->bgexec[key] = nullptr;
+        return fail(BF_EHIP, std::string("batch adjoint graph capture: ") + hipGetErrorString(e));
+      }
+    }
+    const hipError_t e = hipGraphLaunch(b->bgexec[key], s);
+    if (e != hipSuccess) return fail(BF_EHIP, std::string("hipGraphLaunch: ") + hipGetErrorString(e));
+    b->bgraph_launches++;
+    hipEventRecord(b->bev, s);
+    b->bev_used = true;
+    return BF_OK;
+  }
+  int st = record_backward(b, have_saved, sig, s);
+  b->bdirect_launches++;
   hipError_t e = hipSuccess;
-  if (!saved && b->nftiles > 0) {
-    e = launch_batch_v(sh.variant, b->d_bparams, b->d_ftiles, b->nftiles, b->d_counter, grid_of(b), sh.lds,
-                       b->acc64, true, s);
-    if (e != hipSuccess) return fail(BF_EHIP, std::string("batch forward-state launch: ") + hipGetErrorString(e));
-  }
-  if (b->nbtiles > 0) {
-    const int grid = std::max(1, std::min(2 * b->num_cu, b->nbtiles));
-    e = launch_batch_bwd(b->bvariant, b->d_bparams + n, b->d_btiles, b->nbtiles, b->d_counter + 1,
-                         b->d_bpartials, grid, b->blds, s);
-    if (e != hipSuccess) return fail(BF_EHIP, std::string("batch adjoint launch: ") + hipGetErrorString(e));
-  }
-  if (grad_sigma) {
-    hipLaunchKernelGGL(batch_sigma_reduce_kernel, dim3(n), dim3(kThreads), 0, s, (const double*)b->d_bpartials,
-                       (const BatchRed*)b->d_bred, grad_sigma);
-    e = hipGetLastError();
-    if (e != hipSuccess) return fail(BF_EHIP, std::string("batch sigma reduction: ") + hipGetErrorString(e));
-  }
   for (int i : b->streamed) {
+    if (st < 0) break;
     const bf_params& p = b->prm[i];
-    const bool sigs = p.kernel == BF_GAUSS && grad_sigma != nullptr;
+    const bool sigs = p.kernel == BF_GAUSS && sig;
     const bool gauss = p.kernel == BF_GAUSS;
     // the zero rows of this image's layout must be zero: clear the shared state
     e = hipMemsetAsync(b->d_bls, 0, (size_t)bls_state_bytes(p.height, p.width, p.W, gauss), s);
-    if (e != hipSuccess) return fail(BF_EHIP, "hipMemsetAsync streamed adjoint state");
-    const BlsState st = bls_layout(b->d_bls, p.height, p.width, p.W, gauss);
-    e = launch_backward_ls(b->h_bstage[n + i], st, sigs, b->d_bls_partials, grad_sigma ? grad_sigma + 2 * i : nullptr, s);
-    if (e != hipSuccess) return fail(BF_EHIP, std::string("batch streamed adjoint: ") + hipGetErrorString(e));
+    if (e != hipSuccess) {
+      st = fail(BF_EHIP, "hipMemsetAsync streamed adjoint state");
+      break;
+    }
+    const BlsState bst = bls_layout(b->d_bls, p.height, p.width, p.W, gauss);
+    e = launch_backward_ls(b->h_bstage[n + i], bst, sigs, b->d_bls_partials, b->h_bstage[n + i].gsig, s);
+    if (e != hipSuccess) st = fail(BF_EHIP, std::string("batch streamed adjoint: ") + hipGetErrorString(e));
   }
   for (int i : b->mirrored) {
+    if (st < 0) break;
     // recomputes its own state (the batch's saved planes of this image go unread)
-    const int st = bf_backward(b->mplans[i], in[i], in_pitch[i], grad_out[i], gout_pitch[i], nullptr,
-                               grad_in ? grad_in[i] : nullptr, grad_in ? gin_pitch[i] : 0,
-                               grad_sigma ? grad_sigma + 2 * i : nullptr, stream);
-    if (st < 0) return st;
-  }
-  // images on their own streamed plans: their whole adjoint on the side streams (the state
-  // recomputed by that plan unless saved); sigma gradients written by that plan only
-  int ost = BF_OK;
-  if (side) {
-    for (int j = 0; j < bf_batch::kAux; ++j)
-      for (int i : b->aux_imgs[j])
-        if (b->own_adj[i] && ost >= 0)
-          ost = bf_backward(b->fplans[i], in[i], in_pitch[i], grad_out[i], gout_pitch[i], saved ? saved[i] : nullptr,
-                            grad_in ? grad_in[i] : nullptr, (grad_in && grad_in[i]) ? gin_pitch[i] : 0,
-                            grad_sigma ? grad_sigma + 2 * i : nullptr, b->aux[j]);
-    join_side(b, s);
+    st = bf_backward(b->mplans[i], in[i], in_pitch[i], grad_out[i], gout_pitch[i], nullptr,
+                     grad_in ? grad_in[i] : nullptr, grad_in ? gin_pitch[i] : 0,
+                     grad_sigma ? grad_sigma + 2 * i : nullptr, stream);
   }
   hipEventRecord(b->bev, s);
   b->bev_used = true;
-  return ost < 0 ? ost : BF_OK;
+  return st < 0 ? st : BF_OK;
 }
 
 extern "C" {

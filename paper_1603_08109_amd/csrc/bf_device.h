@@ -38,6 +38,25 @@ __device__ __forceinline__ int xcd_remap(int b, int nblk) {
 
 __device__ __forceinline__ int align4(int n) { return (n + 3) & ~3; }
 
+// The adjoint kernels' parameters with the call's image pointers (and the
+// sigma-gradient destination) taken from the device copy p.dyn when set: a
+// launch recorded once into a graph then reads each call's pointers.
+__device__ __forceinline__ TileParams with_dyn(const TileParams& p) {
+  TileParams q = p;
+  if (p.dyn) {
+    const TileParams& d = *p.dyn;
+    q.in = d.in;
+    q.in_pitch = d.in_pitch;
+    q.gout = d.gout;
+    q.gout_pitch = d.gout_pitch;
+    q.out = d.out;
+    q.out_pitch = d.out_pitch;
+    q.saved = d.saved;
+    q.gsig = d.gsig;
+  }
+  return q;
+}
+
 // Workgroup barrier that orders LDS accesses only: global loads and stores
 // issued before it stay in flight (a full __syncthreads waits for them).
 // For kernels whose waves exchange data through LDS alone.

@@ -61,12 +61,14 @@ struct TileParams {
   int wide;             // wide range (T / sigma_r above 13): float64 per-pixel states, out = sigma_r P / Q + c
   const double* isq;    // 1 / sqrt(n), n = 0 .. N+1 (isq_0 = 0)
   const double* sq;     // sqrt(n), n = 0 .. N+1
-  // Streamed forward launched from a captured graph: when set, the lift and
-  // the final pass read in / in_pitch / out / out_pitch (and, with dyn_save,
-  // saved) from this device copy of the call's parameters instead of the
-  // by-value fields above, so one capture serves every call.
+  // Launches recorded once into a graph: when set, the streamed forward's
+  // lift and final pass read in / in_pitch / out / out_pitch (and, with
+  // dyn_save, saved) from this device copy of the call's parameters instead
+  // of the by-value fields above, and the adjoint kernels read every image
+  // pointer and gsig from it (with_dyn), so one capture serves every call.
   const TileParams* dyn;
   int dyn_save;
+  double* gsig;         // adjoint through dyn: {dL/d sigma_r, dL/d sigma_s} of the call (device), or null
 };
 
 // lambda = (T / sigma_r)^2 limits: exp(-x^2/2) stays a normal float32 for
@@ -240,6 +242,12 @@ hipError_t launch_forward_ls(const TileParams& p, const LsState& st, bool save, 
 // plan-level helpers of the batch (bf_plan.cpp): the streamed forward of a
 // single-image plan with the image pointers read from `dyn` (device memory)
 hipError_t plan_forward_streamed_dyn(const bf_plan_t* pl, const TileParams* dyn, bool save, hipStream_t s);
+// The adjoint of a single-image streamed plan with every pointer read from
+// device parameters: fdyn (in, and saved as the recomputed state's
+// destination; out null) for the forward recompute when `recompute`, adyn
+// (in, gout, saved, out = dL/din or null, gsig or null) for the adjoint.
+hipError_t plan_backward_streamed_dyn(const bf_plan_t* pl, const TileParams* fdyn, const TileParams* adyn,
+                                      bool recompute, bool sigs, hipStream_t s);
 // streamed adjoint (bf_large_bwd.hip)
 bool bls_supported(int W, bool sigs);
 int64_t bls_state_bytes(int H, int Wd, int W, bool sigs, int nblock = kBlsBlockSmall);
@@ -247,7 +255,9 @@ BlsState bls_layout(void* base, int H, int Wd, int W, bool sigs, int nblock = kB
 int bls_block_orders(int H, int Wd);
 hipError_t launch_backward_ls(const TileParams& p, const BlsState& st, bool sigs, double* partials,
                               double* grad_sigma, hipStream_t s);
-hipError_t launch_sigma_reduce(const double* partials, int n, bool has_ss, double* out, hipStream_t s);
+// out: the two sigma gradients, or (dyn set) dyn->gsig read when the kernel runs (null: nothing written)
+hipError_t launch_sigma_reduce(const double* partials, int n, bool has_ss, double* out, const TileParams* dyn,
+                               hipStream_t s);
 // reflecting-border adjoint: extend (image by reflection, output gradient by zeros) by W on each
 // side, and fold the extension's gradient back onto the image (bf_kernels.hip)
 hipError_t launch_mirror_pad(const float* in, int64_t in_pitch, const float* gout, int64_t gout_pitch, int H, int Wd,

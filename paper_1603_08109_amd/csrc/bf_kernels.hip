@@ -215,7 +215,8 @@ hipError_t launch_joint(const TileParams& p, int variant, hipStream_t s) {
 // Adjoint kernels (the per-tile arithmetic, backward_tile, is in bf_device.h).
 // ---------------------------------------------------------------------------
 template <int KT, int OPT, int MREG, bool SIGS>
-__global__ __launch_bounds__(kThreads, (OPT * MREG <= 256 ? 2 : 1)) void gpa_backward_kernel(TileParams p, double* partials) {
+__global__ __launch_bounds__(kThreads, (OPT * MREG <= 256 ? 2 : 1)) void gpa_backward_kernel(TileParams pk, double* partials) {
+  const TileParams p = with_dyn(pk);
   extern __shared__ float lds[];
   __shared__ double red[2 * kThreads];
   const int tile = xcd_remap(blockIdx.x, gridDim.x);
@@ -226,8 +227,10 @@ __global__ __launch_bounds__(kThreads, (OPT * MREG <= 256 ? 2 : 1)) void gpa_bac
 
 // Fixed-order sum of the per-tile partials.
 __global__ __launch_bounds__(kThreads) void sigma_reduce_kernel(const double* partials, int ntiles,
-                                                                 int has_ss, double* out) {
+                                                                 int has_ss, double* out, const TileParams* dyn) {
   __shared__ double red[2][kThreads];
+  if (dyn) out = dyn->gsig;  // uniform
+  if (!out) return;
   double a = 0.0, b = 0.0;
   for (int i = threadIdx.x; i < ntiles; i += kThreads) {
     a += partials[2 * (int64_t)i];
@@ -249,8 +252,9 @@ __global__ __launch_bounds__(kThreads) void sigma_reduce_kernel(const double* pa
   }
 }
 
-hipError_t launch_sigma_reduce(const double* partials, int n, bool has_ss, double* out, hipStream_t s) {
-  hipLaunchKernelGGL(sigma_reduce_kernel, dim3(1), dim3(kThreads), 0, s, partials, n, has_ss ? 1 : 0, out);
+hipError_t launch_sigma_reduce(const double* partials, int n, bool has_ss, double* out, const TileParams* dyn,
+                               hipStream_t s) {
+  hipLaunchKernelGGL(sigma_reduce_kernel, dim3(1), dim3(kThreads), 0, s, partials, n, has_ss ? 1 : 0, out, dyn);
   return hipGetLastError();
 }
 
@@ -302,10 +306,10 @@ hipError_t launch_backward(const TileParams& p, int variant, bool sigs, double* 
   else
     e = sigs ? launch_bwd_k<BF_GAUSS, true>(p, variant, partials, s)
              : launch_bwd_k<BF_GAUSS, false>(p, variant, partials, s);
-  if (e != hipSuccess || !grad_sigma) return e;
+  if (e != hipSuccess || (!grad_sigma && !p.dyn)) return e;
   const int tiles = ((p.H + p.TY - 1) / p.TY) * p.tiles_x;
   hipLaunchKernelGGL(sigma_reduce_kernel, dim3(1), dim3(kThreads), 0, s, (const double*)partials,
-                     tiles, (p.kt == BF_GAUSS && sigs) ? 1 : 0, grad_sigma);
+                     tiles, (p.kt == BF_GAUSS && sigs) ? 1 : 0, grad_sigma, p.dyn);
   return hipGetLastError();
 }
 

@@ -33,7 +33,8 @@ constexpr int kBlsRows = 16;      // window rows per row-pass workgroup
 constexpr int kBlsCols = 256;     // output columns per row-pass workgroup
 constexpr int kBlsRegs = 16;      // window values per thread: 16 (256 + 2W) <= 16 x 512
 
-__global__ __launch_bounds__(kThreads) void bls_init_kernel(TileParams p, BlsState st) {
+__global__ __launch_bounds__(kThreads) void bls_init_kernel(TileParams pk, BlsState st) {
+  const TileParams p = with_dyn(pk);
   const int64_t npx = (int64_t)p.H * p.Wd;
   for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < npx;
        i += (int64_t)gridDim.x * kThreads) {
@@ -58,8 +59,9 @@ __global__ __launch_bounds__(kThreads) void bls_init_kernel(TileParams p, BlsSta
 // columns 32w .. 32w + 31 of the 16 rows as two 16x16 Toeplitz products per
 // tap set and stores them from the accumulators.
 template <bool SIGS>
-__global__ __launch_bounds__(kBlsThreads) void bls_rows_kernel(TileParams p, BlsState st, int n0, int K,
+__global__ __launch_bounds__(kBlsThreads) void bls_rows_kernel(TileParams pk, BlsState st, int n0, int K,
                                                                int src) {
+  const TileParams p = with_dyn(pk);
   extern __shared__ float lds[];
   const int W = p.W, N = p.N;
   const int RW = kBlsCols + 2 * W;
@@ -151,7 +153,8 @@ int64_t bls_rows_lds_bytes(int W, bool sigs) {
 // Column passes and folds for a 64 x 64 tile: wave w covers rows
 // 16 (w % 4) .. + 15 and columns 32 (w / 4) .. + 31, 8 pixels per lane.
 template <bool SIGS>
-__global__ __launch_bounds__(kBlsThreads) void bls_cols_kernel(TileParams p, BlsState st, int n0, int K) {
+__global__ __launch_bounds__(kBlsThreads) void bls_cols_kernel(TileParams pk, BlsState st, int n0, int K) {
+  const TileParams p = with_dyn(pk);
   extern __shared__ float lds[];
   const int tiles_x = (p.Wd + kTileCols - 1) / kTileCols;
   const int tiles_y = (p.H + 63) / 64;
@@ -240,7 +243,8 @@ int64_t bls_cols_lds_bytes(int W, bool sigs) {
 }
 
 // dL/df and the per-workgroup partials of the sigma gradients.
-__global__ __launch_bounds__(kThreads) void bls_final_kernel(TileParams p, BlsState st, double* partials) {
+__global__ __launch_bounds__(kThreads) void bls_final_kernel(TileParams pk, BlsState st, double* partials) {
+  const TileParams p = with_dyn(pk);
   __shared__ double red[2][kThreads];
   const int64_t npx = (int64_t)p.H * p.Wd;
   double dsr = 0.0, dss = 0.0;
@@ -350,8 +354,8 @@ hipError_t launch_backward_ls(const TileParams& p, const BlsState& st, bool sigs
   }
   hipLaunchKernelGGL(bls_final_kernel, dim3(kBlsPartials), dim3(kThreads), 0, s, p, st, partials);
   e = hipGetLastError();
-  if (e != hipSuccess || !grad_sigma) return e;
-  return launch_sigma_reduce(partials, kBlsPartials, p.kt == BF_GAUSS && sigs, grad_sigma, s);
+  if (e != hipSuccess || (!grad_sigma && !p.dyn)) return e;
+  return launch_sigma_reduce(partials, kBlsPartials, p.kt == BF_GAUSS && sigs, grad_sigma, p.dyn, s);
 }
 
 }  // namespace bfgpa

@@ -813,6 +813,35 @@ hipError_t plan_forward_streamed_dyn(const bf_plan_t* pl, const TileParams* dyn,
   tp.tiles_x = (pl->p.width + kTileCols - 1) / kTileCols;
   return launch_forward_ls(tp, pl->ls_state, save, s);
 }
+
+// The adjoint of bf_backward for a streamed plan, every pointer read from
+// device parameters when the kernels run (the batch records it once into its
+// adjoint graph): the recompute writes the forward state to fdyn->saved, and
+// the adjoint reads in, gout and saved from adyn and writes adyn->out and
+// adyn->gsig where they are set.
+hipError_t plan_backward_streamed_dyn(const bf_plan_t* pl, const TileParams* fdyn, const TileParams* adyn,
+                                      bool recompute, bool sigs, hipStream_t s) {
+  if (!pl || !fdyn || !adyn || !pl->ls || pl->wide || pl->mirror_adj || !(pl->p.flags & BF_FLAG_GRAD) ||
+      (pl->bvariant < 0 && !pl->bls) || !pl->ls_state.DP)
+    return hipErrorInvalidValue;
+  TileParams tp;
+  std::memset(&tp, 0, sizeof(tp));
+  fill_common(pl, tp);
+  tp.tiles_x = (pl->p.width + kTileCols - 1) / kTileCols;
+  if (recompute) {
+    TileParams fp = tp;
+    fp.dyn = fdyn;
+    fp.dyn_save = 1;
+    fp.TY = pl->TY;
+    const hipError_t e = launch_forward_ls(fp, pl->ls_state, true, s);
+    if (e != hipSuccess) return e;
+  }
+  tp.dyn = adyn;
+  tp.TY = pl->bTY;
+  sigs = sigs && pl->p.kernel == BF_GAUSS;
+  return pl->bls ? launch_backward_ls(tp, pl->bls_state, sigs, pl->d_partials, nullptr, s)
+                 : launch_backward(tp, pl->bvariant, sigs, pl->d_partials, nullptr, s);
+}
 }  // namespace bfgpa
 
 extern "C" {

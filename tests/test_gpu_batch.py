@@ -328,3 +328,62 @@ def test_forward_is_one_graph_launch():
                 w2 = K.taps2d(s["kernel"], s.get("sigma_s"), W if s["kernel"] == "box" else None)
                 ref = G.gpa_pairwise_at(f32, px, w2, s["sigma_r"], batch.N[i], 127.5)
                 assert np.abs(got[px[:, 0], px[:, 1]] - ref).max() <= TOL, i
+
+
+def test_backward_is_one_graph_launch():
+    # images on streamed plans of their own (Gaussian W = 30 and W = 18, box W = 40 on 2^20 pixels)
+    # next to narrow ones, none on the shared streamed adjoint or with the reflecting border: every
+    # adjoint call, recomputing or from saved state, with or without the sigma gradients, is ONE graph
+    # launch (one capture per combination), and each replay, on other inputs and output gradients,
+    # matches the per-image plans' adjoints
+    torch, P = _mods()
+    specs = [dict(kernel="gauss", sigma_s=10.0, sigma_r=30.0, height=150, width=170, grad=True),
+             dict(kernel="gauss", sigma_s=6.0, sigma_r=25.0, height=120, width=90, grad=True),
+             dict(kernel="box", W=40, sigma_r=40.0, height=1024, width=1024, grad=True),
+             dict(kernel="gauss", sigma_s=2.0, sigma_r=35.0, height=80, width=100, grad=True),
+             dict(kernel="box", W=3, sigma_r=20.0, height=60, width=70, grad=True)]
+    batch = P.Batch(specs)
+    assert all(s >= 0 for s in batch.image_status)
+    info = batch.get_info()
+    assert info["images_streamed"] == 3 and info["images_persistent"] == 2
+    plans = []
+    for s in specs:
+        d = dict(s)
+        plans.append(P.Plan(d.pop("kernel"), d.pop("sigma_r"), **d))
+    stream = torch.cuda.Stream()
+    saved = batch.new_saved()
+    # (from saved state, sigma gradients asked)
+    cases = [(False, True), (False, False), (True, True), (False, True), (True, False), (True, True)]
+    for rep, (use_saved, want_sigma) in enumerate(cases):
+        imgs = [torch.tensor(synthimg.gen2(s["height"], s["width"], 1200 + 10 * rep + i), dtype=torch.float32,
+                             device="cuda") for i, s in enumerate(specs)]
+        gouts = [torch.tensor(synthimg.gen1(s["height"], s["width"], 1300 + 10 * rep + i) / 255.0 - 0.5,
+                              dtype=torch.float32, device="cuda") for i, s in enumerate(specs)]
+        torch.cuda.synchronize()
+        with torch.cuda.stream(stream):
+            if use_saved:
+                batch.forward(imgs, saved=saved, stream=stream)
+            before = batch.get_info()
+            gins, gs = batch.backward(imgs, gouts, want_sigma=want_sigma, saved=saved if use_saved else None,
+                                      stream=stream)
+            after = batch.get_info()
+        assert after["backward_graph_launches"] == before["backward_graph_launches"] + 1, rep
+        assert after["backward_direct_launches"] == 0, rep
+        torch.cuda.synchronize()
+        assert (gs is not None) == want_sigma
+        g = gs.cpu().numpy() if want_sigma else None
+        for i, s in enumerate(specs):
+            ref, rs = plans[i].backward(imgs[i], gouts[i])
+            torch.cuda.synchronize()
+            ref, rs = ref.cpu().numpy().astype(np.float64), rs.cpu().numpy()
+            got = gins[i].cpu().numpy().astype(np.float64)
+            err = np.abs(got - ref).max() / np.abs(ref).max()
+            print(f"rep {rep} saved={use_saved} sigma={want_sigma} image {i} {s['kernel']} W={plans[i].info.W} "
+                  f"N={plans[i].info.N}: df rel {err:.2e}", flush=True)
+            assert err <= 1e-4, (rep, i)
+            if want_sigma:
+                assert abs(g[i, 0] - rs[0]) <= 1e-4 * abs(rs[0]), (rep, i)
+                if s["kernel"] == "gauss":
+                    assert abs(g[i, 1] - rs[1]) <= 1e-4 * abs(rs[1]), (rep, i)
+                else:
+                    assert np.isnan(g[i, 1]), (rep, i)
