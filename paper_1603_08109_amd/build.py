@@ -20,7 +20,7 @@ CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libbfgpa.so")
 
-SOURCES = ["bf_plan.cpp", "bf_kernels.hip", "bf_batch.hip", "bf_large.hip", "bf_large_bwd.hip", "bf_recursive.hip", "bf_large_x3.hip", "bf_volume.hip", "bf_noalloc.hip", "bf_fused_w.hip"]
+SOURCES = ["bf_plan.cpp", "bf_kernels.hip", "bf_batch.hip", "bf_large.hip", "bf_large_bwd.hip", "bf_recursive.hip", "bf_large_x3.hip", "bf_volume.hip", "bf_noalloc.hip", "bf_fused_w.hip", "bf_fused_w_bwd.hip"]
 HEADERS = ["bf_internal.h", "bf_device.h", "bf_toeplitz.h", os.path.join("..", "..", "include", "bf_gpa.h")]
 
 

@@ -539,11 +539,12 @@ __device__ __forceinline__ void joint_tile(const TileParams& p, int r0, int c0, 
 // ---------------------------------------------------------------------------
 // One 64 x 4*OPT tile of the adjoint: writes dL/df for its pixels and the
 // tile's two sigma-gradient sums to part[0], part[1] (deterministic
-// workgroup reduction in red, 2 x kThreads doubles of LDS).
-template <int KT, int OPT, int MREG, bool SIGS>
+// workgroup reduction in red, 2 x kThreads doubles of LDS).  WC > 0: the
+// support is a compile-time constant, as in forward_tile.
+template <int KT, int OPT, int MREG, bool SIGS, int WC = 0>
 __device__ __forceinline__ void backward_tile(const TileParams& p, int r0, int c0, float* lds, double* red,
                                               double* part) {
-  const int W = p.W, N = p.N;
+  const int W = WC > 0 ? WC : p.W, N = p.N;
   const RegionGeom g = region_geom(4 * OPT, W, true);
   const int np4 = align4(g.npx);
   float* As = lds;

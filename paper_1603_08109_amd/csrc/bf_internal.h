@@ -160,6 +160,10 @@ hipError_t launch_forward(const TileParams& p, int variant, bool acc64, bool sav
 // the plain fused forward compiled for a fixed support W = 1 .. 21 (bf_fused_w.hip)
 bool fixed_w_available(int W, int variant);
 hipError_t launch_forward_fixed_w(const TileParams& p, hipStream_t s);
+// the fused adjoint tile compiled for a fixed support W = 1 .. 17 (its
+// 16-row variant, the one the planner picks there; bf_fused_w_bwd.hip)
+bool fixed_w_bwd_available(int W, int variant);
+hipError_t launch_backward_fixed_w(const TileParams& p, bool sigs, double* partials, hipStream_t s);
 hipError_t launch_backward(const TileParams& p, int variant, bool sigs, double* partials,
                            double* grad_sigma, hipStream_t s);
 hipError_t launch_joint(const TileParams& p, int variant, hipStream_t s);

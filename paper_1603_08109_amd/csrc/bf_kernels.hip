@@ -301,7 +301,9 @@ hipError_t launch_backward(const TileParams& p, int variant, bool sigs, double* 
   if (backward_lds_bytes(p.TY, p.W, sigs) + 2 * kThreads * 8 > max_lds_bytes()) return hipErrorInvalidValue;
   if (p.H <= 0 || p.Wd <= 0) return hipSuccess;
   hipError_t e;
-  if (p.kt == BF_BOX)
+  if (fixed_w_bwd_available(p.W, variant))
+    e = launch_backward_fixed_w(p, sigs, partials, s);
+  else if (p.kt == BF_BOX)
     e = launch_bwd_k<BF_BOX, false>(p, variant, partials, s);
   else
     e = sigs ? launch_bwd_k<BF_GAUSS, true>(p, variant, partials, s)
