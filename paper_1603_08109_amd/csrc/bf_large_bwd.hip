@@ -57,10 +57,14 @@ __global__ __launch_bounds__(kThreads) void bls_init_kernel(TileParams pk, BlsSt
 // values q = t + 512 j and keeps x, rho, a, b for them in registers; adj_m
 // goes to one of two LDS buffers (one barrier per order); wave w computes
 // columns 32w .. 32w + 31 of the 16 rows as two 16x16 Toeplitz products per
-// tap set and stores them from the accumulators.
-template <bool SIGS>
+// tap set and stores them from the accumulators.  BOX: the box kernel's
+// unit taps as running sums on the VALU instead (thread t: row t % 16, eight
+// consecutive output columns 8 (t / 16) .. + 7, prefix differences over its
+// LDS row; no matrix-core product and no Toeplitz table).
+template <bool SIGS, bool BOX = false>
 __global__ __launch_bounds__(kBlsThreads) void bls_rows_kernel(TileParams pk, BlsState st, int n0, int K,
                                                                int src) {
+  static_assert(!(SIGS && BOX), "the box kernel has no sigma_s gradient");
   const TileParams p = with_dyn(pk);
   extern __shared__ float lds[];
   const int W = p.W, N = p.N;
@@ -75,7 +79,7 @@ __global__ __launch_bounds__(kBlsThreads) void bls_rows_kernel(TileParams pk, Bl
   const int tiles_x = (p.Wd + kBlsCols - 1) / kBlsCols;
   const int ty = blockIdx.x / tiles_x, tx = blockIdx.x - (blockIdx.x / tiles_x) * tiles_x;
   const int r0 = ty * kBlsRows, c0 = tx * kBlsCols;
-  fill_toeplitz<kBlsThreads>(Tt, W, p.taps + kTapPad);
+  if (!BOX) fill_toeplitz<kBlsThreads>(Tt, W, p.taps + kTapPad);
   if (SIGS) fill_toeplitz<kBlsThreads>(Tt2, W, p.taps2 + kTapPad);
   float x[kBlsRegs], rho[kBlsRegs], a[kBlsRegs], b[kBlsRegs];
 #pragma unroll
@@ -111,6 +115,25 @@ __global__ __launch_bounds__(kBlsThreads) void bls_rows_kernel(TileParams pk, Bl
       b[j] = bn;
     }
     __syncthreads();
+    if constexpr (BOX) {
+      // 16 rows x 32 runs of 8 columns, one per thread (kBlsThreads = 512)
+      const int r = threadIdx.x & 15, c8 = 8 * (threadIdx.x >> 4);
+      float o[8];
+      box1d<8>(Lc + r * RWp + c8, 1, 2 * W + 1, o);
+      const int gr = r0 + r, gc = c0 + c8;
+      if (gr < p.H && gc < p.Wd) {
+        float* d = st.R[k] + (int64_t)(W + gr) * st.pitch + gc;  // W zero rows above the image
+        if (gc + 8 <= p.Wd) {
+          *(float4*)d = make_float4(o[0], o[1], o[2], o[3]);
+          *(float4*)(d + 4) = make_float4(o[4], o[5], o[6], o[7]);
+        } else {
+#pragma unroll
+          for (int s = 0; s < 8; ++s)
+            if (gc + s < p.Wd) d[s] = o[s];
+        }
+      }
+      continue;
+    }
     mf4 acc[2], acc2[2];
 #pragma unroll
     for (int bb = 0; bb < 2; ++bb) acc[bb] = acc2[bb] = mf4{0.f, 0.f, 0.f, 0.f};
@@ -237,6 +260,65 @@ __global__ __launch_bounds__(kBlsThreads) void bls_cols_kernel(TileParams pk, Bl
     }
 }
 
+// The box kernel's column pass and fold on the VALU: thread t owns column
+// t % 64 of a 64 x 64 tile and its output rows 8 (t / 64) .. + 7, and sums
+// each staged column window by prefix differences (box1d); the fold is that
+// of bls_cols_kernel (the box has no sigma_s gradient: dss stays zero).
+__global__ __launch_bounds__(kBlsThreads) void bls_cols_box_kernel(TileParams pk, BlsState st, int n0, int K) {
+  const TileParams p = with_dyn(pk);
+  extern __shared__ float lds[];
+  const int tiles_x = (p.Wd + kTileCols - 1) / kTileCols;
+  const int tiles_y = (p.H + 63) / 64;
+  int ty, tx;
+  band_tile(xcd_remap(blockIdx.x, gridDim.x), tiles_x, tiles_y, ty, tx);
+  const int c = threadIdx.x & 63, g = threadIdx.x >> 6;
+  const int tr0 = ty * 64, c0 = tx * kTileCols;
+  const int W = p.W;
+  const int rows = ls_cols_rows(W);
+  float* S1 = lds;  // rows x 64
+  const int pc = c0 + c, pr0 = tr0 + 8 * g;
+  float x[8], fc[8], fp[8];
+  double dx[8];
+#pragma unroll
+  for (int v = 0; v < 8; ++v) {
+    const int r = pr0 + v;
+    const bool ok = r < p.H && pc < p.Wd;
+    const int64_t i = ok ? (int64_t)r * p.Wd + pc : 0;
+    x[v] = ok ? (p.in[(int64_t)r * p.in_pitch + pc] - p.center) / p.sigma_r : 0.f;
+    fc[v] = ok ? st.fc[i] : 0.f;
+    fp[v] = ok ? st.fp[i] : 0.f;
+    dx[v] = ok ? st.dx[i] : 0.0;
+  }
+  for (int k = 0; k < K; ++k) {
+    const int m = n0 + k;
+    __syncthreads();
+    stage_rows_lds<kBlsThreads>(st.R[k] + (int64_t)tr0 * st.pitch + c0, st.pitch, S1, rows);
+    __syncthreads();
+    float fa[8];
+    box1d<8>(S1 + 8 * g * 64 + c, 64, 2 * W + 1, fa);  // rows 8g + v .. 8g + v + 2W of the window
+    const float sm = p.s_tab[m];
+    const float sm1 = p.s_tab[m + 1];
+    const float fm = (float)m * sm;
+#pragma unroll
+    for (int v = 0; v < 8; ++v) {
+      const float factor = fmaf(fm, fp[v], -x[v] * fc[v]);  // dF~_m/dx
+      dx[v] = fma((double)fa[v], (double)factor, dx[v]);
+      fp[v] = fc[v];
+      fc[v] *= x[v] * sm1;
+    }
+  }
+#pragma unroll
+  for (int v = 0; v < 8; ++v) {
+    const int r = pr0 + v;
+    if (r < p.H && pc < p.Wd) {
+      const int64_t i = (int64_t)r * p.Wd + pc;
+      st.fc[i] = fc[v];
+      st.fp[i] = fp[v];
+      st.dx[i] = dx[v];
+    }
+  }
+}
+
 int64_t bls_cols_lds_bytes(int W, bool sigs) {
   const int64_t n = sigs ? 2 : 1;
   return 4 * n * ((int64_t)ls_cols_rows(W) * 64 + (int64_t)ls_kk(W) * 64);
@@ -333,8 +415,10 @@ hipError_t launch_backward_ls(const TileParams& p, const BlsState& st, bool sigs
   hipLaunchKernelGGL(bls_init_kernel, dim3(g1), dim3(kThreads), 0, s, p, st);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  auto rk = sigs ? bls_rows_kernel<true> : bls_rows_kernel<false>;
-  auto ck = sigs ? bls_cols_kernel<true> : bls_cols_kernel<false>;
+  // the box kernel (no sigma_s gradient) filters with running sums on the VALU
+  const bool box = p.kt == BF_BOX && !sigs;
+  auto rk = sigs ? bls_rows_kernel<true> : box ? bls_rows_kernel<false, true> : bls_rows_kernel<false>;
+  auto ck = sigs ? bls_cols_kernel<true> : box ? bls_cols_box_kernel : bls_cols_kernel<false>;
   e = hipFuncSetAttribute((const void*)rk, hipFuncAttributeMaxDynamicSharedMemorySize, max_lds_bytes());
   if (e == hipSuccess)
     e = hipFuncSetAttribute((const void*)ck, hipFuncAttributeMaxDynamicSharedMemorySize, max_lds_bytes());
