@@ -53,6 +53,60 @@ __global__ __launch_bounds__(kThreads) void bls_init_kernel(TileParams pk, BlsSt
   }
 }
 
+// box1d on a contiguous, 8-byte aligned run, read in pairs (half the LDS
+// instructions): out[s] = src[s] + ... + src[s + L - 1], s < S, for an odd
+// L >= S + 1 and even S.  The window sum is that of src[0 .. L - 1], then
+// advanced by one entering and one leaving value per output.
+template <int S>
+__device__ __forceinline__ void box1d_pairs(const float* __restrict__ src, int L, float (&out)[S]) {
+  static_assert(S % 2 == 0, "pairs");
+  const float2* p2 = (const float2*)src;
+  float a[S];
+#pragma unroll
+  for (int i = 0; i < S / 2; ++i) {
+    const float2 v = p2[i];
+    a[2 * i] = v.x;
+    a[2 * i + 1] = v.y;
+  }
+  float start[S];
+  float acc = 0.f;
+#pragma unroll
+  for (int s = 0; s < S; ++s) {
+    start[s] = acc;
+    acc += a[s];
+  }
+  // src[S .. L - 2]: pairs S / 2 .. (L - 1) / 2 - 1
+  float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f;
+  const int iend = (L - 1) / 2;
+  int i = S / 2;
+  for (; i + 2 <= iend; i += 2) {
+    const float2 u = p2[i], w = p2[i + 1];
+    s0 += u.x;
+    s1 += u.y;
+    s2 += w.x;
+    s3 += w.y;
+  }
+  for (; i < iend; ++i) {
+    const float2 u = p2[i];
+    s0 += u.x;
+    s1 += u.y;
+  }
+  // e[t] = src[L - 1 + t], t < S
+  float e[S];
+#pragma unroll
+  for (int j = 0; j < S / 2; ++j) {
+    const float2 v = p2[iend + j];
+    e[2 * j] = v.x;
+    e[2 * j + 1] = v.y;
+  }
+  float lead = (acc + ((s0 + s1) + (s2 + s3))) + e[0];
+#pragma unroll
+  for (int s = 0; s < S; ++s) {
+    out[s] = lead - start[s];
+    if (s + 1 < S) lead += e[s + 1];
+  }
+}
+
 // Row pass of adj_m for orders n0 .. n0 + K - 1.  Thread t owns the window
 // values q = t + 512 j and keeps x, rho, a, b for them in registers; adj_m
 // goes to one of two LDS buffers (one barrier per order); wave w computes
@@ -119,7 +173,10 @@ __global__ __launch_bounds__(kBlsThreads) void bls_rows_kernel(TileParams pk, Bl
       // 16 rows x 32 runs of 8 columns, one per thread (kBlsThreads = 512)
       const int r = threadIdx.x & 15, c8 = 8 * (threadIdx.x >> 4);
       float o[8];
-      box1d<8>(Lc + r * RWp + c8, 1, 2 * W + 1, o);
+      if (2 * W + 1 >= 9)
+        box1d_pairs<8>(Lc + r * RWp + c8, 2 * W + 1, o);  // RWp and c8 even: 8-byte aligned
+      else
+        box1d<8>(Lc + r * RWp + c8, 1, 2 * W + 1, o);
       const int gr = r0 + r, gc = c0 + c8;
       if (gr < p.H && gc < p.Wd) {
         float* d = st.R[k] + (int64_t)(W + gr) * st.pitch + gc;  // W zero rows above the image
