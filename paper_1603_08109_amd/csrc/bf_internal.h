@@ -98,6 +98,11 @@ struct LsState {
                             // ([row / 8][column][row % 8], pitch columns)
   int64_t hs_plane;         // elements per plane of a pre-split image
   int block;                // orders per block: row-filtered images allocated (0: none, box strips)
+  // A device copy of this struct, which the kernels take by address: passed
+  // by value its 200-odd pointers made every launch's arguments about 1.7 KB,
+  // which slowed graphs of many short launches (256-image batch 24.5 ->
+  // 30.4 ms).  Set when the plan uploads it; the layout never changes after.
+  const LsState* dev;
 };
 
 // Rows of one row-filtered image of the streamed passes: the height padded

@@ -39,7 +39,8 @@ static int num_cus() {
   return cached[dev];
 }
 
-__global__ __launch_bounds__(kThreads) void ls_init_kernel(TileParams p, LsState st) {
+__global__ __launch_bounds__(kThreads) void ls_init_kernel(TileParams p, const LsState* __restrict__ stp) {
+  const LsState& st = *stp;
   const int64_t npx = (int64_t)p.H * p.Wd;
   const float* in = p.dyn ? p.dyn->in : p.in;
   const int64_t in_pitch = p.dyn ? p.dyn->in_pitch : p.in_pitch;
@@ -61,8 +62,9 @@ __global__ __launch_bounds__(kThreads) void ls_init_kernel(TileParams p, LsState
 // (kLsCols + 2W) columns (pitch = region_pitch-style), and the row-pass
 // output of one order (kLsRows x kLsCols) staged for a coalesced store.
 template <int KT>
-__global__ __launch_bounds__(kThreads) void ls_rows_kernel(TileParams p, LsState st, int n0, int K,
+__global__ __launch_bounds__(kThreads) void ls_rows_kernel(TileParams p, const LsState* __restrict__ stp, int n0, int K,
                                                            int src) {
+  const LsState& st = *stp;
   extern __shared__ float lds[];
   const int W = p.W;
   const int RW = kLsCols + 2 * W;
@@ -153,8 +155,9 @@ constexpr int kLsRowsRegs = 32;  // staged values per thread: 16 (256 + 2W) <= 3
 
 bool ls_rows_mfma_fits(int W) { return kLsRows * ls_rows_pitch_mfma(W) <= kLsRowsRegs * kThreads; }
 
-__global__ __launch_bounds__(kThreads) void ls_rows_mfma_kernel(TileParams p, LsState st, int n0, int K,
+__global__ __launch_bounds__(kThreads) void ls_rows_mfma_kernel(TileParams p, const LsState* __restrict__ stp, int n0, int K,
                                                                 int src) {
+  const LsState& st = *stp;
   extern __shared__ float lds[];
   const int W = p.W;
   const int RW = kLsCols + 2 * W;
@@ -242,7 +245,8 @@ int64_t ls_rows_mfma_lds_bytes(int W) {
 constexpr int kColsThreads = 512;
 
 template <bool SAVE>
-__global__ __launch_bounds__(kColsThreads) void ls_cols_mfma_kernel(TileParams p, LsState st, int n0, int K) {
+__global__ __launch_bounds__(kColsThreads) void ls_cols_mfma_kernel(TileParams p, const LsState* __restrict__ stp, int n0, int K) {
+  const LsState& st = *stp;
   extern __shared__ float lds[];
   const int tiles_x = (p.Wd + kTileCols - 1) / kTileCols;
   const int tiles_y = (p.H + 63) / 64;
@@ -302,8 +306,9 @@ int64_t ls_cols_mfma_lds_bytes(int W) {
 // CH pixels at a time.  Row-filtered images carry W zero rows above and
 // below the image, so the window never leaves the buffer.
 template <bool SAVE>
-__global__ __launch_bounds__(kThreads) void ls_cols_box_kernel(TileParams p, LsState st, int n0, int K,
+__global__ __launch_bounds__(kThreads) void ls_cols_box_kernel(TileParams p, const LsState* __restrict__ stp, int n0, int K,
                                                                int seg_rows) {
+  const LsState& st = *stp;
   constexpr int CH = 8;
   const int c = blockIdx.x * kTileCols + (threadIdx.x & 63);
   const int rs = (blockIdx.y * 4 + (threadIdx.x >> 6)) * seg_rows;
@@ -350,7 +355,8 @@ __global__ __launch_bounds__(kThreads) void ls_cols_box_kernel(TileParams p, LsS
 // reads of adjacent rows conflict-free.
 
 template <int OPT, bool SAVE>
-__global__ __launch_bounds__(kThreads) void ls_cols_fir_kernel(TileParams p, LsState st, int n0, int K) {
+__global__ __launch_bounds__(kThreads) void ls_cols_fir_kernel(TileParams p, const LsState* __restrict__ stp, int n0, int K) {
+  const LsState& st = *stp;
   extern __shared__ float lds[];
   const int tiles_x = (p.Wd + kTileCols - 1) / kTileCols;
   const int tile = xcd_remap(blockIdx.x, gridDim.x);
@@ -486,8 +492,9 @@ __host__ __device__ inline int strip_chunk_lanes(int cpl, int W) {
 }
 
 template <int CPT, bool SAVE, int KB>
-__global__ __launch_bounds__(kStripThreads, 2) void ls_box_strip_kernel(TileParams p, LsState st, int n0, int src,
+__global__ __launch_bounds__(kStripThreads, 2) void ls_box_strip_kernel(TileParams p, const LsState* __restrict__ stp, int n0, int src,
                                                                       int seg_rows) {
+  const LsState& st = *stp;
   using G = StripGeom<CPT, KB>;
   constexpr int SC = G::SC, CPL = G::CPL, NW = KB / 4;
   constexpr int SG = CPT == 1 ? NW : 2;  // orders a wave scans together
@@ -811,7 +818,8 @@ bool ls_mirror_supported(int kernel, int W) {
          ls_cols_mfma_lds_bytes(W) <= max_lds_bytes();
 }
 
-__global__ __launch_bounds__(kThreads) void ls_final_kernel(TileParams p, LsState st) {
+__global__ __launch_bounds__(kThreads) void ls_final_kernel(TileParams p, const LsState* __restrict__ stp) {
+  const LsState& st = *stp;
   const int64_t npx = (int64_t)p.H * p.Wd;
   const double X = p.wide ? 1.0 : (double)p.X;  // the wide-range sums carry no 1/X
   float* out = p.dyn ? p.dyn->out : p.out;
@@ -925,7 +933,7 @@ hipError_t launch_forward_ls(const TileParams& p, const LsState& st, bool save, 
   if (save && !st.DP) return hipErrorInvalidValue;  // saved planes need the adjoint sums
   const int64_t npx = (int64_t)p.H * p.Wd;
   const int g1 = (int)std::min<int64_t>((npx + kThreads - 1) / kThreads, 4096);
-  hipLaunchKernelGGL(ls_init_kernel, dim3(g1), dim3(kThreads), 0, s, p, st);
+  hipLaunchKernelGGL(ls_init_kernel, dim3(g1), dim3(kThreads), 0, s, p, st.dev);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const int64_t rl = ls_rows_lds_bytes(p.W);
@@ -994,7 +1002,7 @@ hipError_t launch_forward_ls(const TileParams& p, const LsState& st, bool save, 
       const int kb = box_strip_block(sh, save, n0, p.N);
       int n0v = n0, srcv = src, segv = sh.seg_rows;
       TileParams pv = p;
-      LsState sv = st;
+      const LsState* sv = st.dev;
       void* args[] = {(void*)&pv, (void*)&sv, (void*)&n0v, (void*)&srcv, (void*)&segv};
       e = hipLaunchKernel(box_strip_kernel(sh.cpt, save, kb), dim3(sh.grid), dim3(kStripThreads), args,
                           (size_t)box_strip_lds(sh.cpt, kb), s);
@@ -1014,9 +1022,9 @@ hipError_t launch_forward_ls(const TileParams& p, const LsState& st, bool save, 
       e = split ? launch_rows_x3_split(p, st, n0, K, src, grow, s) : launch_rows_x3(p, st, n0, K, src, grow, s);
     } else {
       if (rows_mfma)
-        hipLaunchKernelGGL(ls_rows_mfma_kernel, dim3(grow), dim3(kThreads), (size_t)rlm, s, p, st, n0, K, src);
+        hipLaunchKernelGGL(ls_rows_mfma_kernel, dim3(grow), dim3(kThreads), (size_t)rlm, s, p, st.dev, n0, K, src);
       else
-        hipLaunchKernelGGL(rk, dim3(grow), dim3(kThreads), (size_t)rl, s, p, st, n0, K, src);
+        hipLaunchKernelGGL(rk, dim3(grow), dim3(kThreads), (size_t)rl, s, p, st.dev, n0, K, src);
       e = hipGetLastError();
     }
     if (e != hipSuccess) return e;
@@ -1036,34 +1044,34 @@ hipError_t launch_forward_ls(const TileParams& p, const LsState& st, bool save, 
         e = launch_cols_x3(p, st, n0, K, save, gfir16, s);
       } else {
         if (save)
-          hipLaunchKernelGGL((ls_cols_mfma_kernel<true>), dim3(gfir16), dim3(kColsThreads), clm, s, p, st, n0, K);
+          hipLaunchKernelGGL((ls_cols_mfma_kernel<true>), dim3(gfir16), dim3(kColsThreads), clm, s, p, st.dev, n0, K);
         else
-          hipLaunchKernelGGL((ls_cols_mfma_kernel<false>), dim3(gfir16), dim3(kColsThreads), clm, s, p, st, n0, K);
+          hipLaunchKernelGGL((ls_cols_mfma_kernel<false>), dim3(gfir16), dim3(kColsThreads), clm, s, p, st.dev, n0, K);
         e = hipGetLastError();
       }
     } else {
       if (p.kt == BF_BOX) {
         if (save)
-          hipLaunchKernelGGL((ls_cols_box_kernel<true>), gbox, dim3(kThreads), 0, s, p, st, n0, K, seg_rows);
+          hipLaunchKernelGGL((ls_cols_box_kernel<true>), gbox, dim3(kThreads), 0, s, p, st.dev, n0, K, seg_rows);
         else
-          hipLaunchKernelGGL((ls_cols_box_kernel<false>), gbox, dim3(kThreads), 0, s, p, st, n0, K, seg_rows);
+          hipLaunchKernelGGL((ls_cols_box_kernel<false>), gbox, dim3(kThreads), 0, s, p, st.dev, n0, K, seg_rows);
       } else if (cols_mfma) {
         if (save)
-          hipLaunchKernelGGL((ls_cols_mfma_kernel<true>), dim3(gfir16), dim3(kColsThreads), clm, s, p, st, n0, K);
+          hipLaunchKernelGGL((ls_cols_mfma_kernel<true>), dim3(gfir16), dim3(kColsThreads), clm, s, p, st.dev, n0, K);
         else
-          hipLaunchKernelGGL((ls_cols_mfma_kernel<false>), dim3(gfir16), dim3(kColsThreads), clm, s, p, st, n0, K);
+          hipLaunchKernelGGL((ls_cols_mfma_kernel<false>), dim3(gfir16), dim3(kColsThreads), clm, s, p, st.dev, n0, K);
       } else {
         if (save)
-          hipLaunchKernelGGL((ls_cols_fir_kernel<8, true>), dim3(gfir8), dim3(kThreads), fl8, s, p, st, n0, K);
+          hipLaunchKernelGGL((ls_cols_fir_kernel<8, true>), dim3(gfir8), dim3(kThreads), fl8, s, p, st.dev, n0, K);
         else
-          hipLaunchKernelGGL((ls_cols_fir_kernel<16, false>), dim3(gfir16), dim3(kThreads), fl16, s, p, st, n0, K);
+          hipLaunchKernelGGL((ls_cols_fir_kernel<16, false>), dim3(gfir16), dim3(kThreads), fl16, s, p, st.dev, n0, K);
       }
       e = hipGetLastError();
     }
     if (e != hipSuccess) return e;
     src ^= 1;
   }
-  hipLaunchKernelGGL(ls_final_kernel, dim3(g1), dim3(kThreads), 0, s, p, st);
+  hipLaunchKernelGGL(ls_final_kernel, dim3(g1), dim3(kThreads), 0, s, p, st.dev);
   return hipGetLastError();
 }
 
@@ -1072,7 +1080,7 @@ hipError_t launch_forward_ls(const TileParams& p, const LsState& st, bool save, 
 hipError_t ls_launch_init(const TileParams& p, const LsState& st, hipStream_t s) {
   const int64_t npx = (int64_t)p.H * p.Wd;
   const int g1 = (int)std::min<int64_t>((npx + kThreads - 1) / kThreads, 4096);
-  hipLaunchKernelGGL(ls_init_kernel, dim3(g1), dim3(kThreads), 0, s, p, st);
+  hipLaunchKernelGGL(ls_init_kernel, dim3(g1), dim3(kThreads), 0, s, p, st.dev);
   return hipGetLastError();
 }
 
@@ -1085,20 +1093,20 @@ hipError_t ls_launch_rows(const TileParams& p, const LsState& st, int n0, int K,
     hipError_t e = hipFuncSetAttribute((const void*)ls_rows_mfma_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
                                        max_lds_bytes());
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(ls_rows_mfma_kernel, dim3(grow), dim3(kThreads), rlm, s, p, st, n0, K, src);
+    hipLaunchKernelGGL(ls_rows_mfma_kernel, dim3(grow), dim3(kThreads), rlm, s, p, st.dev, n0, K, src);
     return hipGetLastError();
   }
   auto rk = p.kt == BF_BOX ? ls_rows_kernel<BF_BOX> : ls_rows_kernel<BF_GAUSS>;
   hipError_t e = hipFuncSetAttribute((const void*)rk, hipFuncAttributeMaxDynamicSharedMemorySize, max_lds_bytes());
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(rk, dim3(grow), dim3(kThreads), (size_t)ls_rows_lds_bytes(p.W), s, p, st, n0, K, src);
+  hipLaunchKernelGGL(rk, dim3(grow), dim3(kThreads), (size_t)ls_rows_lds_bytes(p.W), s, p, st.dev, n0, K, src);
   return hipGetLastError();
 }
 
 hipError_t ls_launch_final(const TileParams& p, const LsState& st, hipStream_t s) {
   const int64_t npx = (int64_t)p.H * p.Wd;
   const int g1 = (int)std::min<int64_t>((npx + kThreads - 1) / kThreads, 4096);
-  hipLaunchKernelGGL(ls_final_kernel, dim3(g1), dim3(kThreads), 0, s, p, st);
+  hipLaunchKernelGGL(ls_final_kernel, dim3(g1), dim3(kThreads), 0, s, p, st.dev);
   return hipGetLastError();
 }
 

@@ -216,8 +216,9 @@ __device__ __forceinline__ void x3_advance(FT* F, const float* Y, const TilePara
 // rows in groups of eight, image row i at row i + ls_split_top(W)); a lane's
 // four consecutive rows of one column are one 8-byte store per plane.
 template <int S, bool WIDE, bool SPLIT = false>
-__global__ __launch_bounds__(kX3RowsThreads) void ls_rows_x3_kernel(TileParams p, LsState st, int n0, int K,
+__global__ __launch_bounds__(kX3RowsThreads) void ls_rows_x3_kernel(TileParams p, const LsState* __restrict__ stp, int n0, int K,
                                                                     int src) {
+  const LsState& st = *stp;
   using FT = typename std::conditional<WIDE, double, float>::type;
   extern __shared__ float lds[];
   const int W = p.W;
@@ -359,7 +360,8 @@ __device__ __forceinline__ void x3_stage(const float* __restrict__ Hk, int64_t p
 
 
 template <int S, bool SAVE, bool WIDE>
-__global__ __launch_bounds__(kX3ColsThreads) void ls_cols_x3_kernel(TileParams p, LsState st, int n0, int K) {
+__global__ __launch_bounds__(kX3ColsThreads) void ls_cols_x3_kernel(TileParams p, const LsState* __restrict__ stp, int n0, int K) {
+  const LsState& st = *stp;
   extern __shared__ float lds[];
   const int tiles_x = (p.Wd + kTileCols - 1) / kTileCols;
   const int tiles_y = (p.H + 63) / 64;
@@ -457,7 +459,7 @@ static hipError_t rows_x3_s(const TileParams& p, const LsState& st, int n0, int 
     attr = true;
   }
   hipLaunchKernelGGL((ls_rows_x3_kernel<S, WIDE, SPLIT>), dim3(grid), dim3(kX3RowsThreads),
-                     (size_t)ls_rows_x3_lds_bytes(p.W), s, p, st, n0, K, src);
+                     (size_t)ls_rows_x3_lds_bytes(p.W), s, p, st.dev, n0, K, src);
   return hipGetLastError();
 }
 
@@ -486,7 +488,7 @@ static hipError_t cols_x3_s(const TileParams& p, const LsState& st, int n0, int 
     attr = true;
   }
   hipLaunchKernelGGL((ls_cols_x3_kernel<S, SAVE, WIDE>), dim3(grid), dim3(kX3ColsThreads),
-                     (size_t)ls_cols_x3_lds_bytes(p.W), s, p, st, n0, K);
+                     (size_t)ls_cols_x3_lds_bytes(p.W), s, p, st.dev, n0, K);
   return hipGetLastError();
 }
 
@@ -593,7 +595,8 @@ __device__ __forceinline__ void x3s_split_item(const float (&r)[8], int i, __bf1
 }
 
 template <int S, bool MIRROR>
-__global__ __launch_bounds__(kX3sThreads) void ls_cols_x3s_kernel(TileParams p, LsState st, int n0, int K) {
+__global__ __launch_bounds__(kX3sThreads) void ls_cols_x3s_kernel(TileParams p, const LsState* __restrict__ stp, int n0, int K) {
+  const LsState& st = *stp;
   using G = X3sGeom<S>;
   extern __shared__ float lds[];
   __bf16* Pl = (__bf16*)lds;  // two sets of G::BUF elements
@@ -693,7 +696,7 @@ static hipError_t cols_x3s_s(const TileParams& p, const LsState& st, int n0, int
     attr = true;
   }
   const int grid = ((p.H + kX3sRows - 1) / kX3sRows) * ((p.Wd + kX3sCols - 1) / kX3sCols);
-  hipLaunchKernelGGL((ls_cols_x3s_kernel<S, MIRROR>), dim3(grid), dim3(kX3sThreads), (size_t)lb, s, p, st, n0, K);
+  hipLaunchKernelGGL((ls_cols_x3s_kernel<S, MIRROR>), dim3(grid), dim3(kX3sThreads), (size_t)lb, s, p, st.dev, n0, K);
   return hipGetLastError();
 }
 
@@ -769,7 +772,8 @@ bool ls_split_supported(int W, int nblock) {
 }
 
 template <int S>
-__global__ __launch_bounds__(kX3sThreads) void ls_cols_x3p_kernel(TileParams p, LsState st, int n0, int K) {
+__global__ __launch_bounds__(kX3sThreads) void ls_cols_x3p_kernel(TileParams p, const LsState* __restrict__ stp, int n0, int K) {
+  const LsState& st = *stp;
   using G = X3pGeom<S>;
   static_assert(G::GROUPS % 4 == 0, "four groups per load");
   constexpr int NLOADS = 3 * G::GROUPS / 4;         // loads of 64 lanes per order
@@ -876,7 +880,7 @@ static hipError_t cols_x3p_s(const TileParams& p, const LsState& st, int n0, int
     attr = true;
   }
   const int grid = ((p.H + kX3pRows - 1) / kX3pRows) * ((p.Wd + kX3pCols - 1) / kX3pCols);
-  hipLaunchKernelGGL((ls_cols_x3p_kernel<S>), dim3(grid), dim3(kX3sThreads), (size_t)lb, s, p, st, n0, K);
+  hipLaunchKernelGGL((ls_cols_x3p_kernel<S>), dim3(grid), dim3(kX3sThreads), (size_t)lb, s, p, st.dev, n0, K);
   return hipGetLastError();
 }
 
@@ -915,7 +919,8 @@ hipError_t launch_cols_x3(const TileParams& p, const LsState& st, int n0, int K,
 // Wide range (lambda = (T / sigma_r)^2 in (170, 1400]): the lift in float64
 // (F~_0 = a~_0 = e^{-x^2/2}, x = (f - center) / sigma_r as in float32), the
 // split passes with float64 states, and eq. (PbyQ) without the factor X.
-__global__ __launch_bounds__(256) void wide_init_kernel(TileParams p, LsState st) {
+__global__ __launch_bounds__(256) void wide_init_kernel(TileParams p, const LsState* __restrict__ stp) {
+  const LsState& st = *stp;
   const int64_t npx = (int64_t)p.H * p.Wd;
   for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < npx; i += (int64_t)gridDim.x * 256) {
     const int r = (int)(i / p.Wd), c = (int)(i - (int64_t)r * p.Wd);
@@ -933,7 +938,7 @@ __global__ __launch_bounds__(256) void wide_init_kernel(TileParams p, LsState st
 hipError_t wide_launch_init(const TileParams& p, const LsState& st, hipStream_t s) {
   const int64_t npx = (int64_t)p.H * p.Wd;
   const int g1 = (int)std::min<int64_t>((npx + 255) / 256, 4096);
-  hipLaunchKernelGGL(wide_init_kernel, dim3(g1), dim3(256), 0, s, p, st);
+  hipLaunchKernelGGL(wide_init_kernel, dim3(g1), dim3(256), 0, s, p, st.dev);
   return hipGetLastError();
 }
 
@@ -952,7 +957,7 @@ hipError_t launch_forward_wide(const TileParams& p, const LsState& st, hipStream
     return hipErrorInvalidValue;
   const int64_t npx = (int64_t)p.H * p.Wd;
   const int g1 = (int)std::min<int64_t>((npx + 255) / 256, 4096);
-  hipLaunchKernelGGL(wide_init_kernel, dim3(g1), dim3(256), 0, s, p, st);
+  hipLaunchKernelGGL(wide_init_kernel, dim3(g1), dim3(256), 0, s, p, st.dev);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const int grow = ((p.H + kLsRows - 1) / kLsRows) * ((p.Wd + kLsCols - 1) / kLsCols);

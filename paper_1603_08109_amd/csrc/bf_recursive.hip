@@ -251,8 +251,9 @@ __device__ __forceinline__ void rg_load(const float* __restrict__ p, int n, floa
 
 // Row pass for orders n0 .. n0 + K - 1 of R image rows (blockDim = R * Trp,
 // Tr = ceil(width / 16)); stores the row-filtered images row-major.
-__global__ __launch_bounds__(kRgFirstThreads) void rg_first_kernel(TileParams p, LsState st, int K, int src, int R,
+__global__ __launch_bounds__(kRgFirstThreads) void rg_first_kernel(TileParams p, const LsState* __restrict__ stp, int K, int src, int R,
                                                                    int Tr, int Trp) {
+  const LsState& st = *stp;
   extern __shared__ float lds[];
   const int nW = Trp > 64 ? Trp >> 6 : 1;
   float* tot = lds;  // 2 (parity) x R x nW x 8
@@ -296,7 +297,8 @@ __global__ __launch_bounds__(kRgFirstThreads) void rg_first_kernel(TileParams p,
 }
 
 // H[z] (row-major) -> HT[z] (column-major), 64 x 64 tiles through LDS.
-__global__ __launch_bounds__(256) void rg_transpose_kernel(LsState st, int H, int Wd) {
+__global__ __launch_bounds__(256) void rg_transpose_kernel(const LsState* __restrict__ stp, int H, int Wd) {
+  const LsState& st = *stp;
   __shared__ float T[64][65];
   const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
   const int r0 = blockIdx.y * 64, c0 = blockIdx.x * 64;
@@ -317,8 +319,9 @@ __global__ __launch_bounds__(256) void rg_transpose_kernel(LsState st, int H, in
 // of R image columns (blockDim = R * Trp, Tr = ceil(height / 8)), folded
 // into the per-pixel sums (column-major state).  Chunks of 8 samples keep
 // the float64 sums of a thread's pixels within 128 VGPRs.
-__global__ __launch_bounds__(kRgSecondThreads) void rg_second_kernel(TileParams p, LsState st, int n0, int K, int R,
+__global__ __launch_bounds__(kRgSecondThreads) void rg_second_kernel(TileParams p, const LsState* __restrict__ stp, int n0, int K, int R,
                                                                      int Tr, int Trp) {
+  const LsState& st = *stp;
   constexpr int C = kRgChunk2;
   extern __shared__ float lds[];
   const int nW = Trp > 64 ? Trp >> 6 : 1;
@@ -359,7 +362,8 @@ __global__ __launch_bounds__(kRgSecondThreads) void rg_second_kernel(TileParams 
 }
 
 // F^_0 = e^{-x^2/2} and y (row-major), a_0, z and zero sums (column-major).
-__global__ __launch_bounds__(256) void rg_init_kernel(TileParams p, LsState st) {
+__global__ __launch_bounds__(256) void rg_init_kernel(TileParams p, const LsState* __restrict__ stp) {
+  const LsState& st = *stp;
   __shared__ float Ta[32][33], Tz[32][33];
   const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
   const int r0 = blockIdx.y * 32, c0 = blockIdx.x * 32;
@@ -387,7 +391,8 @@ __global__ __launch_bounds__(256) void rg_init_kernel(TileParams p, LsState st) 
 }
 
 // eq. (PbyQ) from the column-major sums, stored row-major.
-__global__ __launch_bounds__(256) void rg_final_kernel(TileParams p, LsState st) {
+__global__ __launch_bounds__(256) void rg_final_kernel(TileParams p, const LsState* __restrict__ stp) {
+  const LsState& st = *stp;
   __shared__ float To[32][33];
   const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
   const int r0 = blockIdx.y * 32, c0 = blockIdx.x * 32;
@@ -468,19 +473,19 @@ hipError_t launch_forward_rg(const TileParams& p, const LsState& st, hipStream_t
   const size_t lds1 = (size_t)(16 * R1 * nW1) * 4;
   const size_t lds2 = (size_t)(16 * R2 * nW2) * 4;
   const dim3 tiles((p.Wd + 31) / 32, (p.H + 31) / 32);
-  hipLaunchKernelGGL(rg_init_kernel, tiles, dim3(256), 0, s, p, st);
+  hipLaunchKernelGGL(rg_init_kernel, tiles, dim3(256), 0, s, p, st.dev);
   int src = 0;
   for (int n0 = 0; n0 <= p.N; n0 += kLsBlockSmall) {
     const int K = std::min(kLsBlockSmall, p.N + 1 - n0);
-    hipLaunchKernelGGL(rg_first_kernel, dim3((p.H + R1 - 1) / R1), dim3(R1 * Trp1), lds1, s, p, st, K, src, R1, Tr1,
+    hipLaunchKernelGGL(rg_first_kernel, dim3((p.H + R1 - 1) / R1), dim3(R1 * Trp1), lds1, s, p, st.dev, K, src, R1, Tr1,
                        Trp1);
-    hipLaunchKernelGGL(rg_transpose_kernel, dim3((p.Wd + 63) / 64, (p.H + 63) / 64, K), dim3(256), 0, s, st, p.H,
+    hipLaunchKernelGGL(rg_transpose_kernel, dim3((p.Wd + 63) / 64, (p.H + 63) / 64, K), dim3(256), 0, s, st.dev, p.H,
                        p.Wd);
-    hipLaunchKernelGGL(rg_second_kernel, dim3((p.Wd + R2 - 1) / R2), dim3(R2 * Trp2), lds2, s, p, st, n0, K, R2, Tr2,
+    hipLaunchKernelGGL(rg_second_kernel, dim3((p.Wd + R2 - 1) / R2), dim3(R2 * Trp2), lds2, s, p, st.dev, n0, K, R2, Tr2,
                        Trp2);
     src ^= 1;
   }
-  hipLaunchKernelGGL(rg_final_kernel, tiles, dim3(256), 0, s, p, st);
+  hipLaunchKernelGGL(rg_final_kernel, tiles, dim3(256), 0, s, p, st.dev);
   return hipGetLastError();
 }
 
