@@ -85,24 +85,29 @@ struct LsState {
   int64_t pitch;            // row pitch (floats) of the image-shaped buffers
   float* F[2];              // F^ state images (double-buffered)
   float* Y;                 // y = (f - center) / T
-  float* H[kLsBlock];       // row-filtered images, W zero rows above and below
+  float* H0;                // row-filtered images (W zero rows above and below), image k at h(k)
+  int64_t h_stride;         // floats from one row-filtered image to the next
   float *a, *ap, *app, *z;  // per-pixel coefficient recursion
   double *P, *Q, *DP, *DQ;  // per-pixel sums
   int64_t hbytes;           // bytes of one row-filtered image
   int64_t tpitch;           // recursive Gaussian: row pitch of the column-major filtered images
-  float* HT[kLsBlock];      // recursive Gaussian: the row-filtered images, column-major
+  float* HT0;               // recursive Gaussian: the row-filtered images, column-major, image k at ht(k)
+  int64_t ht_stride;
   double* Fd[2];            // wide range: F~_n = e^{-x^2/2} x^n / sqrt(n!) images (double-buffered)
   double *ad, *apd;         // wide range: per-pixel a~_n, a~_{n-1}
-  uint16_t* Hs[kLsBlock];   // pre-split row-filtered images (ls_split_rows), or null: per image three
+  uint16_t* Hs0;            // pre-split row-filtered images (ls_split_rows), or null: per image three
                             // bfloat16 planes of hs_plane elements, rows in groups of eight
-                            // ([row / 8][column][row % 8], pitch columns)
+                            // ([row / 8][column][row % 8], pitch columns); image k at hs(k)
+  int64_t hs_stride;
   int64_t hs_plane;         // elements per plane of a pre-split image
   int block;                // orders per block: row-filtered images allocated (0: none, box strips)
-  // A device copy of this struct, which the kernels take by address: passed
-  // by value its 200-odd pointers made every launch's arguments about 1.7 KB,
-  // which slowed graphs of many short launches (256-image batch 24.5 ->
-  // 30.4 ms).  Set when the plan uploads it; the layout never changes after.
-  const LsState* dev;
+  // The images of a block are equal-sized and consecutive, so base and stride
+  // describe them: the struct stays small (about 200 bytes) as every streamed
+  // launch takes it by value, and its pointers stay kernel-argument (global)
+  // pointers to the compiler.
+  __host__ __device__ float* h(int k) const { return H0 + k * h_stride; }
+  __host__ __device__ float* ht(int k) const { return HT0 + k * ht_stride; }
+  __host__ __device__ uint16_t* hs(int k) const { return Hs0 + k * hs_stride; }
 };
 
 // Rows of one row-filtered image of the streamed passes: the height padded

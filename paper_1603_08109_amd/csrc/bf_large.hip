@@ -39,8 +39,7 @@ static int num_cus() {
   return cached[dev];
 }
 
-__global__ __launch_bounds__(kThreads) void ls_init_kernel(TileParams p, const LsState* __restrict__ stp) {
-  const LsState& st = *stp;
+__global__ __launch_bounds__(kThreads) void ls_init_kernel(TileParams p, LsState st) {
   const int64_t npx = (int64_t)p.H * p.Wd;
   const float* in = p.dyn ? p.dyn->in : p.in;
   const int64_t in_pitch = p.dyn ? p.dyn->in_pitch : p.in_pitch;
@@ -62,9 +61,8 @@ __global__ __launch_bounds__(kThreads) void ls_init_kernel(TileParams p, const L
 // (kLsCols + 2W) columns (pitch = region_pitch-style), and the row-pass
 // output of one order (kLsRows x kLsCols) staged for a coalesced store.
 template <int KT>
-__global__ __launch_bounds__(kThreads) void ls_rows_kernel(TileParams p, const LsState* __restrict__ stp, int n0, int K,
+__global__ __launch_bounds__(kThreads) void ls_rows_kernel(TileParams p, LsState st, int n0, int K,
                                                            int src) {
-  const LsState& st = *stp;
   extern __shared__ float lds[];
   const int W = p.W;
   const int RW = kLsCols + 2 * W;
@@ -124,7 +122,7 @@ __global__ __launch_bounds__(kThreads) void ls_rows_kernel(TileParams p, const L
     }
     __syncthreads();
     // coalesced store of this order's row-filtered rows; advance F^ by one power
-    float* Hk = st.H[k] + (int64_t)W * st.pitch;  // W zero rows above the image
+    float* Hk = st.h(k) + (int64_t)W * st.pitch;  // W zero rows above the image
     for (int q = threadIdx.x; q < kLsRows * kLsCols; q += kThreads) {
       const int row = q / kLsCols, col = q - row * kLsCols;
       const int gr = r0 + row, gc = c0 + col;
@@ -155,9 +153,8 @@ constexpr int kLsRowsRegs = 32;  // staged values per thread: 16 (256 + 2W) <= 3
 
 bool ls_rows_mfma_fits(int W) { return kLsRows * ls_rows_pitch_mfma(W) <= kLsRowsRegs * kThreads; }
 
-__global__ __launch_bounds__(kThreads) void ls_rows_mfma_kernel(TileParams p, const LsState* __restrict__ stp, int n0, int K,
+__global__ __launch_bounds__(kThreads) void ls_rows_mfma_kernel(TileParams p, LsState st, int n0, int K,
                                                                 int src) {
-  const LsState& st = *stp;
   extern __shared__ float lds[];
   const int W = p.W;
   const int RW = kLsCols + 2 * W;
@@ -207,7 +204,7 @@ __global__ __launch_bounds__(kThreads) void ls_rows_mfma_kernel(TileParams p, co
 #pragma unroll
     for (int bb = 0; bb < 4; ++bb) acc[bb] = mf4{0.f, 0.f, 0.f, 0.f};
     toeplitz_rows<4>(Fc, RWp, cbase, Tt, KK, acc);
-    float* Hk = st.H[k] + (int64_t)W * st.pitch;  // W zero rows above the image
+    float* Hk = st.h(k) + (int64_t)W * st.pitch;  // W zero rows above the image
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       if (orow + v < p.H) {
@@ -245,8 +242,7 @@ int64_t ls_rows_mfma_lds_bytes(int W) {
 constexpr int kColsThreads = 512;
 
 template <bool SAVE>
-__global__ __launch_bounds__(kColsThreads) void ls_cols_mfma_kernel(TileParams p, const LsState* __restrict__ stp, int n0, int K) {
-  const LsState& st = *stp;
+__global__ __launch_bounds__(kColsThreads) void ls_cols_mfma_kernel(TileParams p, LsState st, int n0, int K) {
   extern __shared__ float lds[];
   const int tiles_x = (p.Wd + kTileCols - 1) / kTileCols;
   const int tiles_y = (p.H + 63) / 64;
@@ -275,9 +271,9 @@ __global__ __launch_bounds__(kColsThreads) void ls_cols_mfma_kernel(TileParams p
     const int n = n0 + k;
     __syncthreads();
     if (p.mirror)
-      stage_rows_lds_mirror<kColsThreads>(st.H[k], st.pitch, tr0, c0, W, p.H, Sl, rows);
+      stage_rows_lds_mirror<kColsThreads>(st.h(k), st.pitch, tr0, c0, W, p.H, Sl, rows);
     else
-      stage_rows_lds<kColsThreads>(st.H[k] + (int64_t)tr0 * st.pitch + c0, st.pitch, Sl, rows);
+      stage_rows_lds<kColsThreads>(st.h(k) + (int64_t)tr0 * st.pitch + c0, st.pitch, Sl, rows);
     __syncthreads();
     mf4 acc[2];
 #pragma unroll
@@ -306,9 +302,8 @@ int64_t ls_cols_mfma_lds_bytes(int W) {
 // CH pixels at a time.  Row-filtered images carry W zero rows above and
 // below the image, so the window never leaves the buffer.
 template <bool SAVE>
-__global__ __launch_bounds__(kThreads) void ls_cols_box_kernel(TileParams p, const LsState* __restrict__ stp, int n0, int K,
+__global__ __launch_bounds__(kThreads) void ls_cols_box_kernel(TileParams p, LsState st, int n0, int K,
                                                                int seg_rows) {
-  const LsState& st = *stp;
   constexpr int CH = 8;
   const int c = blockIdx.x * kTileCols + (threadIdx.x & 63);
   const int rs = (blockIdx.y * 4 + (threadIdx.x >> 6)) * seg_rows;
@@ -319,7 +314,7 @@ __global__ __launch_bounds__(kThreads) void ls_cols_box_kernel(TileParams p, con
   float V[kLsBlockSmall];
 #pragma unroll
   for (int k = 0; k < kLsBlockSmall; ++k)
-    V[k] = (k < K) ? strided_sum(st.H[k] + (int64_t)rs * pitch + c, (int)pitch, 0, L) : 0.f;
+    V[k] = (k < K) ? strided_sum(st.h(k) + (int64_t)rs * pitch + c, (int)pitch, 0, L) : 0.f;
   LsPix<CH, SAVE> px;
   for (int r = rs; r < re; r += CH) {
     const int nr = min(CH, re - r);
@@ -329,7 +324,7 @@ __global__ __launch_bounds__(kThreads) void ls_cols_box_kernel(TileParams p, con
       if (k < K) {
         const int n = n0 + k;
         const float in1 = p.inv_tab[n + 1];
-        const float* hk = st.H[k] + c;
+        const float* hk = st.h(k) + c;
         float enter[CH], leave[CH];
 #pragma unroll
         for (int s = 0; s < CH; ++s) {
@@ -355,8 +350,7 @@ __global__ __launch_bounds__(kThreads) void ls_cols_box_kernel(TileParams p, con
 // reads of adjacent rows conflict-free.
 
 template <int OPT, bool SAVE>
-__global__ __launch_bounds__(kThreads) void ls_cols_fir_kernel(TileParams p, const LsState* __restrict__ stp, int n0, int K) {
-  const LsState& st = *stp;
+__global__ __launch_bounds__(kThreads) void ls_cols_fir_kernel(TileParams p, LsState st, int n0, int K) {
   extern __shared__ float lds[];
   const int tiles_x = (p.Wd + kTileCols - 1) / kTileCols;
   const int tile = xcd_remap(blockIdx.x, gridDim.x);
@@ -375,7 +369,7 @@ __global__ __launch_bounds__(kThreads) void ls_cols_fir_kernel(TileParams p, con
   for (int k = 0; k < K; ++k) {
     const int n = n0 + k;
     __syncthreads();
-    const float* hk = st.H[k] + (int64_t)tr0 * st.pitch + c0;  // padded row tr0 = image row tr0 - W
+    const float* hk = st.h(k) + (int64_t)tr0 * st.pitch + c0;  // padded row tr0 = image row tr0 - W
     // eight loads in flight per thread before any LDS store
     const int total = rows * kTileCols;
     const bool col_ok = (c0 + (threadIdx.x & 63)) < p.Wd;  // q & 63 == threadIdx.x & 63 below
@@ -492,9 +486,8 @@ __host__ __device__ inline int strip_chunk_lanes(int cpl, int W) {
 }
 
 template <int CPT, bool SAVE, int KB>
-__global__ __launch_bounds__(kStripThreads, 2) void ls_box_strip_kernel(TileParams p, const LsState* __restrict__ stp, int n0, int src,
+__global__ __launch_bounds__(kStripThreads, 2) void ls_box_strip_kernel(TileParams p, LsState st, int n0, int src,
                                                                       int seg_rows) {
-  const LsState& st = *stp;
   using G = StripGeom<CPT, KB>;
   constexpr int SC = G::SC, CPL = G::CPL, NW = KB / 4;
   constexpr int SG = CPT == 1 ? NW : 2;  // orders a wave scans together
@@ -818,8 +811,7 @@ bool ls_mirror_supported(int kernel, int W) {
          ls_cols_mfma_lds_bytes(W) <= max_lds_bytes();
 }
 
-__global__ __launch_bounds__(kThreads) void ls_final_kernel(TileParams p, const LsState* __restrict__ stp) {
-  const LsState& st = *stp;
+__global__ __launch_bounds__(kThreads) void ls_final_kernel(TileParams p, LsState st) {
   const int64_t npx = (int64_t)p.H * p.Wd;
   const double X = p.wide ? 1.0 : (double)p.X;  // the wide-range sums carry no 1/X
   float* out = p.dyn ? p.dyn->out : p.out;
@@ -901,9 +893,11 @@ LsState ls_layout(void* base, int H, int Wd, int W, bool save, bool wide, bool s
   st.Y = (float*)take(img * 4);
   if (split) {
     st.hs_plane = pitch * ls_split_rows(H, W);
-    for (int k = 0; k < nblock; ++k) st.Hs[k] = (uint16_t*)take(3 * 2 * st.hs_plane);
+    st.hs_stride = ((3 * 2 * st.hs_plane + 255) & ~255LL) / 2;  // take()'s rounding
+    st.Hs0 = (uint16_t*)take(nblock * 2 * st.hs_stride);
   } else {
-    for (int k = 0; k < nblock; ++k) st.H[k] = (float*)take(himg * 4);
+    st.h_stride = ((himg * 4 + 255) & ~255LL) / 4;
+    st.H0 = nblock > 0 ? (float*)take(nblock * 4 * st.h_stride) : nullptr;
   }
   if (wide) {
     st.ad = (double*)take(npx * 8);
@@ -933,7 +927,7 @@ hipError_t launch_forward_ls(const TileParams& p, const LsState& st, bool save, 
   if (save && !st.DP) return hipErrorInvalidValue;  // saved planes need the adjoint sums
   const int64_t npx = (int64_t)p.H * p.Wd;
   const int g1 = (int)std::min<int64_t>((npx + kThreads - 1) / kThreads, 4096);
-  hipLaunchKernelGGL(ls_init_kernel, dim3(g1), dim3(kThreads), 0, s, p, st.dev);
+  hipLaunchKernelGGL(ls_init_kernel, dim3(g1), dim3(kThreads), 0, s, p, st);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const int64_t rl = ls_rows_lds_bytes(p.W);
@@ -992,7 +986,7 @@ hipError_t launch_forward_ls(const TileParams& p, const LsState& st, bool save, 
   }
   // pre-split row-filtered images (a plan's plain Gaussian forward): split row
   // pass and the column pass that stages the planes directly
-  const bool split = st.Hs[0] != nullptr;
+  const bool split = st.Hs0 != nullptr;
   if (split && (save || p.mirror || !x3 || p.kt == BF_BOX)) return hipErrorInvalidValue;
   if (!box_strip && (st.block <= 0 || st.block > kLsBlock || (p.kt == BF_BOX && st.block > kLsBlockSmall)))
     return hipErrorInvalidValue;
@@ -1002,7 +996,7 @@ hipError_t launch_forward_ls(const TileParams& p, const LsState& st, bool save, 
       const int kb = box_strip_block(sh, save, n0, p.N);
       int n0v = n0, srcv = src, segv = sh.seg_rows;
       TileParams pv = p;
-      const LsState* sv = st.dev;
+      LsState sv = st;
       void* args[] = {(void*)&pv, (void*)&sv, (void*)&n0v, (void*)&srcv, (void*)&segv};
       e = hipLaunchKernel(box_strip_kernel(sh.cpt, save, kb), dim3(sh.grid), dim3(kStripThreads), args,
                           (size_t)box_strip_lds(sh.cpt, kb), s);
@@ -1022,9 +1016,9 @@ hipError_t launch_forward_ls(const TileParams& p, const LsState& st, bool save, 
       e = split ? launch_rows_x3_split(p, st, n0, K, src, grow, s) : launch_rows_x3(p, st, n0, K, src, grow, s);
     } else {
       if (rows_mfma)
-        hipLaunchKernelGGL(ls_rows_mfma_kernel, dim3(grow), dim3(kThreads), (size_t)rlm, s, p, st.dev, n0, K, src);
+        hipLaunchKernelGGL(ls_rows_mfma_kernel, dim3(grow), dim3(kThreads), (size_t)rlm, s, p, st, n0, K, src);
       else
-        hipLaunchKernelGGL(rk, dim3(grow), dim3(kThreads), (size_t)rl, s, p, st.dev, n0, K, src);
+        hipLaunchKernelGGL(rk, dim3(grow), dim3(kThreads), (size_t)rl, s, p, st, n0, K, src);
       e = hipGetLastError();
     }
     if (e != hipSuccess) return e;
@@ -1044,34 +1038,34 @@ hipError_t launch_forward_ls(const TileParams& p, const LsState& st, bool save, 
         e = launch_cols_x3(p, st, n0, K, save, gfir16, s);
       } else {
         if (save)
-          hipLaunchKernelGGL((ls_cols_mfma_kernel<true>), dim3(gfir16), dim3(kColsThreads), clm, s, p, st.dev, n0, K);
+          hipLaunchKernelGGL((ls_cols_mfma_kernel<true>), dim3(gfir16), dim3(kColsThreads), clm, s, p, st, n0, K);
         else
-          hipLaunchKernelGGL((ls_cols_mfma_kernel<false>), dim3(gfir16), dim3(kColsThreads), clm, s, p, st.dev, n0, K);
+          hipLaunchKernelGGL((ls_cols_mfma_kernel<false>), dim3(gfir16), dim3(kColsThreads), clm, s, p, st, n0, K);
         e = hipGetLastError();
       }
     } else {
       if (p.kt == BF_BOX) {
         if (save)
-          hipLaunchKernelGGL((ls_cols_box_kernel<true>), gbox, dim3(kThreads), 0, s, p, st.dev, n0, K, seg_rows);
+          hipLaunchKernelGGL((ls_cols_box_kernel<true>), gbox, dim3(kThreads), 0, s, p, st, n0, K, seg_rows);
         else
-          hipLaunchKernelGGL((ls_cols_box_kernel<false>), gbox, dim3(kThreads), 0, s, p, st.dev, n0, K, seg_rows);
+          hipLaunchKernelGGL((ls_cols_box_kernel<false>), gbox, dim3(kThreads), 0, s, p, st, n0, K, seg_rows);
       } else if (cols_mfma) {
         if (save)
-          hipLaunchKernelGGL((ls_cols_mfma_kernel<true>), dim3(gfir16), dim3(kColsThreads), clm, s, p, st.dev, n0, K);
+          hipLaunchKernelGGL((ls_cols_mfma_kernel<true>), dim3(gfir16), dim3(kColsThreads), clm, s, p, st, n0, K);
         else
-          hipLaunchKernelGGL((ls_cols_mfma_kernel<false>), dim3(gfir16), dim3(kColsThreads), clm, s, p, st.dev, n0, K);
+          hipLaunchKernelGGL((ls_cols_mfma_kernel<false>), dim3(gfir16), dim3(kColsThreads), clm, s, p, st, n0, K);
       } else {
         if (save)
-          hipLaunchKernelGGL((ls_cols_fir_kernel<8, true>), dim3(gfir8), dim3(kThreads), fl8, s, p, st.dev, n0, K);
+          hipLaunchKernelGGL((ls_cols_fir_kernel<8, true>), dim3(gfir8), dim3(kThreads), fl8, s, p, st, n0, K);
         else
-          hipLaunchKernelGGL((ls_cols_fir_kernel<16, false>), dim3(gfir16), dim3(kThreads), fl16, s, p, st.dev, n0, K);
+          hipLaunchKernelGGL((ls_cols_fir_kernel<16, false>), dim3(gfir16), dim3(kThreads), fl16, s, p, st, n0, K);
       }
       e = hipGetLastError();
     }
     if (e != hipSuccess) return e;
     src ^= 1;
   }
-  hipLaunchKernelGGL(ls_final_kernel, dim3(g1), dim3(kThreads), 0, s, p, st.dev);
+  hipLaunchKernelGGL(ls_final_kernel, dim3(g1), dim3(kThreads), 0, s, p, st);
   return hipGetLastError();
 }
 
@@ -1080,7 +1074,7 @@ hipError_t launch_forward_ls(const TileParams& p, const LsState& st, bool save, 
 hipError_t ls_launch_init(const TileParams& p, const LsState& st, hipStream_t s) {
   const int64_t npx = (int64_t)p.H * p.Wd;
   const int g1 = (int)std::min<int64_t>((npx + kThreads - 1) / kThreads, 4096);
-  hipLaunchKernelGGL(ls_init_kernel, dim3(g1), dim3(kThreads), 0, s, p, st.dev);
+  hipLaunchKernelGGL(ls_init_kernel, dim3(g1), dim3(kThreads), 0, s, p, st);
   return hipGetLastError();
 }
 
@@ -1093,20 +1087,20 @@ hipError_t ls_launch_rows(const TileParams& p, const LsState& st, int n0, int K,
     hipError_t e = hipFuncSetAttribute((const void*)ls_rows_mfma_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
                                        max_lds_bytes());
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(ls_rows_mfma_kernel, dim3(grow), dim3(kThreads), rlm, s, p, st.dev, n0, K, src);
+    hipLaunchKernelGGL(ls_rows_mfma_kernel, dim3(grow), dim3(kThreads), rlm, s, p, st, n0, K, src);
     return hipGetLastError();
   }
   auto rk = p.kt == BF_BOX ? ls_rows_kernel<BF_BOX> : ls_rows_kernel<BF_GAUSS>;
   hipError_t e = hipFuncSetAttribute((const void*)rk, hipFuncAttributeMaxDynamicSharedMemorySize, max_lds_bytes());
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(rk, dim3(grow), dim3(kThreads), (size_t)ls_rows_lds_bytes(p.W), s, p, st.dev, n0, K, src);
+  hipLaunchKernelGGL(rk, dim3(grow), dim3(kThreads), (size_t)ls_rows_lds_bytes(p.W), s, p, st, n0, K, src);
   return hipGetLastError();
 }
 
 hipError_t ls_launch_final(const TileParams& p, const LsState& st, hipStream_t s) {
   const int64_t npx = (int64_t)p.H * p.Wd;
   const int g1 = (int)std::min<int64_t>((npx + kThreads - 1) / kThreads, 4096);
-  hipLaunchKernelGGL(ls_final_kernel, dim3(g1), dim3(kThreads), 0, s, p, st.dev);
+  hipLaunchKernelGGL(ls_final_kernel, dim3(g1), dim3(kThreads), 0, s, p, st);
   return hipGetLastError();
 }
 

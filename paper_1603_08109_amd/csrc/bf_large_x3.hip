@@ -216,9 +216,8 @@ __device__ __forceinline__ void x3_advance(FT* F, const float* Y, const TilePara
 // rows in groups of eight, image row i at row i + ls_split_top(W)); a lane's
 // four consecutive rows of one column are one 8-byte store per plane.
 template <int S, bool WIDE, bool SPLIT = false>
-__global__ __launch_bounds__(kX3RowsThreads) void ls_rows_x3_kernel(TileParams p, const LsState* __restrict__ stp, int n0, int K,
+__global__ __launch_bounds__(kX3RowsThreads) void ls_rows_x3_kernel(TileParams p, LsState st, int n0, int K,
                                                                     int src) {
-  const LsState& st = *stp;
   using FT = typename std::conditional<WIDE, double, float>::type;
   extern __shared__ float lds[];
   const int W = p.W;
@@ -294,7 +293,7 @@ __global__ __launch_bounds__(kX3RowsThreads) void ls_rows_x3_kernel(TileParams p
     if (k + 1 < K) x3_advance<WIDE>(F, Y, p, n0 + k + 1);
     if constexpr (SPLIT) {
       // rows orow .. orow + 3 (rows past the image hold zeros: their F^ are 0)
-      uint16_t* Hk = st.Hs[k];
+      uint16_t* Hk = st.hs(k);
       const int R = orow + ls_split_top(W);  // a multiple of 4
 #pragma unroll
       for (int b = 0; b < 2; ++b) {
@@ -309,7 +308,7 @@ __global__ __launch_bounds__(kX3RowsThreads) void ls_rows_x3_kernel(TileParams p
         }
       }
     } else {
-      float* Hk = st.H[k] + (int64_t)W * st.pitch;  // W zero rows above the image
+      float* Hk = st.h(k) + (int64_t)W * st.pitch;  // W zero rows above the image
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         if (orow + v < p.H) {
@@ -360,8 +359,7 @@ __device__ __forceinline__ void x3_stage(const float* __restrict__ Hk, int64_t p
 
 
 template <int S, bool SAVE, bool WIDE>
-__global__ __launch_bounds__(kX3ColsThreads) void ls_cols_x3_kernel(TileParams p, const LsState* __restrict__ stp, int n0, int K) {
-  const LsState& st = *stp;
+__global__ __launch_bounds__(kX3ColsThreads) void ls_cols_x3_kernel(TileParams p, LsState st, int n0, int K) {
   extern __shared__ float lds[];
   const int tiles_x = (p.Wd + kTileCols - 1) / kTileCols;
   const int tiles_y = (p.H + 63) / 64;
@@ -390,9 +388,9 @@ __global__ __launch_bounds__(kX3ColsThreads) void ls_cols_x3_kernel(TileParams p
     px.template load_part<4>(st, 4 * b, (int64_t)(pr0 + 32 * b) * p.Wd + pc, p.Wd, nr, n0 == 0);
   }
   if (p.mirror)
-    x3_stage<true>(st.H[0], st.pitch, tr0, c0, W, p.H, groups, buf0);
+    x3_stage<true>(st.h(0), st.pitch, tr0, c0, W, p.H, groups, buf0);
   else
-    x3_stage<false>(st.H[0], st.pitch, tr0, c0, W, p.H, groups, buf0);
+    x3_stage<false>(st.h(0), st.pitch, tr0, c0, W, p.H, groups, buf0);
   // this lane's column and first row of slice 0 (16 rb + 8 (l/16), a multiple
   // of 4: row r of a slice sits at group r / 4, offsets are compile-time)
   const int lbase = (4 * rb + 2 * (lane >> 4)) * kX3GroupFloats + 16 * cb + (lane & 15);
@@ -403,9 +401,9 @@ __global__ __launch_bounds__(kX3ColsThreads) void ls_cols_x3_kernel(TileParams p
     if (k + 1 < K) {
       float* nxt = lds + ((k + 1) & 1) * bfl;
       if (p.mirror)
-        x3_stage<true>(st.H[k + 1], st.pitch, tr0, c0, W, p.H, groups, nxt);
+        x3_stage<true>(st.h(k + 1), st.pitch, tr0, c0, W, p.H, groups, nxt);
       else
-        x3_stage<false>(st.H[k + 1], st.pitch, tr0, c0, W, p.H, groups, nxt);
+        x3_stage<false>(st.h(k + 1), st.pitch, tr0, c0, W, p.H, groups, nxt);
     }
     mf4 acc[2] = {mf4{0.f, 0.f, 0.f, 0.f}, mf4{0.f, 0.f, 0.f, 0.f}};
 #pragma unroll
@@ -459,7 +457,7 @@ static hipError_t rows_x3_s(const TileParams& p, const LsState& st, int n0, int 
     attr = true;
   }
   hipLaunchKernelGGL((ls_rows_x3_kernel<S, WIDE, SPLIT>), dim3(grid), dim3(kX3RowsThreads),
-                     (size_t)ls_rows_x3_lds_bytes(p.W), s, p, st.dev, n0, K, src);
+                     (size_t)ls_rows_x3_lds_bytes(p.W), s, p, st, n0, K, src);
   return hipGetLastError();
 }
 
@@ -488,7 +486,7 @@ static hipError_t cols_x3_s(const TileParams& p, const LsState& st, int n0, int 
     attr = true;
   }
   hipLaunchKernelGGL((ls_cols_x3_kernel<S, SAVE, WIDE>), dim3(grid), dim3(kX3ColsThreads),
-                     (size_t)ls_cols_x3_lds_bytes(p.W), s, p, st.dev, n0, K);
+                     (size_t)ls_cols_x3_lds_bytes(p.W), s, p, st, n0, K);
   return hipGetLastError();
 }
 
@@ -595,8 +593,7 @@ __device__ __forceinline__ void x3s_split_item(const float (&r)[8], int i, __bf1
 }
 
 template <int S, bool MIRROR>
-__global__ __launch_bounds__(kX3sThreads) void ls_cols_x3s_kernel(TileParams p, const LsState* __restrict__ stp, int n0, int K) {
-  const LsState& st = *stp;
+__global__ __launch_bounds__(kX3sThreads) void ls_cols_x3s_kernel(TileParams p, LsState st, int n0, int K) {
   using G = X3sGeom<S>;
   extern __shared__ float lds[];
   __bf16* Pl = (__bf16*)lds;  // two sets of G::BUF elements
@@ -611,7 +608,7 @@ __global__ __launch_bounds__(kX3sThreads) void ls_cols_x3s_kernel(TileParams p, 
   const int W = p.W;
   const int pitch = (int)st.pitch;
   auto rsrc = [&](int k) {
-    return __builtin_amdgcn_make_buffer_rsrc((void*)st.H[k], (short)0, (int)st.hbytes, 0x00020000);
+    return __builtin_amdgcn_make_buffer_rsrc((void*)st.h(k), (short)0, (int)st.hbytes, 0x00020000);
   };
   float reg[G::ITEMS][8];
   {
@@ -696,7 +693,7 @@ static hipError_t cols_x3s_s(const TileParams& p, const LsState& st, int n0, int
     attr = true;
   }
   const int grid = ((p.H + kX3sRows - 1) / kX3sRows) * ((p.Wd + kX3sCols - 1) / kX3sCols);
-  hipLaunchKernelGGL((ls_cols_x3s_kernel<S, MIRROR>), dim3(grid), dim3(kX3sThreads), (size_t)lb, s, p, st.dev, n0, K);
+  hipLaunchKernelGGL((ls_cols_x3s_kernel<S, MIRROR>), dim3(grid), dim3(kX3sThreads), (size_t)lb, s, p, st, n0, K);
   return hipGetLastError();
 }
 
@@ -772,8 +769,7 @@ bool ls_split_supported(int W, int nblock) {
 }
 
 template <int S>
-__global__ __launch_bounds__(kX3sThreads) void ls_cols_x3p_kernel(TileParams p, const LsState* __restrict__ stp, int n0, int K) {
-  const LsState& st = *stp;
+__global__ __launch_bounds__(kX3sThreads) void ls_cols_x3p_kernel(TileParams p, LsState st, int n0, int K) {
   using G = X3pGeom<S>;
   static_assert(G::GROUPS % 4 == 0, "four groups per load");
   constexpr int NLOADS = 3 * G::GROUPS / 4;         // loads of 64 lanes per order
@@ -796,7 +792,7 @@ __global__ __launch_bounds__(kX3sThreads) void ls_cols_x3p_kernel(TileParams p, 
   // this wave's loads of an order into a set: load u = plane u / (GROUPS / 4),
   // groups 4 (u % (GROUPS / 4)) .. + 3
   auto stage = [&](int k, __bf16* set) {
-    const uint16_t* Hk = st.Hs[k];
+    const uint16_t* Hk = st.hs(k);
     for (int u = wv; u < NLOADS; u += NWAVES) {
       const int pl = u / (G::GROUPS / 4), g0 = 4 * (u - pl * (G::GROUPS / 4));
       const __amdgpu_buffer_rsrc_t rs =
@@ -880,12 +876,12 @@ static hipError_t cols_x3p_s(const TileParams& p, const LsState& st, int n0, int
     attr = true;
   }
   const int grid = ((p.H + kX3pRows - 1) / kX3pRows) * ((p.Wd + kX3pCols - 1) / kX3pCols);
-  hipLaunchKernelGGL((ls_cols_x3p_kernel<S>), dim3(grid), dim3(kX3sThreads), (size_t)lb, s, p, st.dev, n0, K);
+  hipLaunchKernelGGL((ls_cols_x3p_kernel<S>), dim3(grid), dim3(kX3sThreads), (size_t)lb, s, p, st, n0, K);
   return hipGetLastError();
 }
 
 hipError_t launch_cols_x3p(const TileParams& p, const LsState& st, int n0, int K, hipStream_t s) {
-  if (!st.Hs[0] || !ls_split_supported(p.W, st.block) || (st.hs_plane + 512 * st.pitch) * 2 >= (1LL << 31) ||
+  if (!st.Hs0 || !ls_split_supported(p.W, st.block) || (st.hs_plane + 512 * st.pitch) * 2 >= (1LL << 31) ||
       p.mirror)
     return hipErrorInvalidValue;
   switch (x3p_steps(p.W)) {
@@ -903,7 +899,7 @@ hipError_t launch_cols_x3p(const TileParams& p, const LsState& st, int n0, int K
 
 hipError_t launch_rows_x3_split(const TileParams& p, const LsState& st, int n0, int K, int src, int grid,
                                 hipStream_t s) {
-  if (!st.Hs[0] || p.mirror) return hipErrorInvalidValue;
+  if (!st.Hs0 || p.mirror) return hipErrorInvalidValue;
   return rows_x3_t<false, true>(p, st, n0, K, src, grid, s);
 }
 
@@ -919,8 +915,7 @@ hipError_t launch_cols_x3(const TileParams& p, const LsState& st, int n0, int K,
 // Wide range (lambda = (T / sigma_r)^2 in (170, 1400]): the lift in float64
 // (F~_0 = a~_0 = e^{-x^2/2}, x = (f - center) / sigma_r as in float32), the
 // split passes with float64 states, and eq. (PbyQ) without the factor X.
-__global__ __launch_bounds__(256) void wide_init_kernel(TileParams p, const LsState* __restrict__ stp) {
-  const LsState& st = *stp;
+__global__ __launch_bounds__(256) void wide_init_kernel(TileParams p, LsState st) {
   const int64_t npx = (int64_t)p.H * p.Wd;
   for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < npx; i += (int64_t)gridDim.x * 256) {
     const int r = (int)(i / p.Wd), c = (int)(i - (int64_t)r * p.Wd);
@@ -938,7 +933,7 @@ __global__ __launch_bounds__(256) void wide_init_kernel(TileParams p, const LsSt
 hipError_t wide_launch_init(const TileParams& p, const LsState& st, hipStream_t s) {
   const int64_t npx = (int64_t)p.H * p.Wd;
   const int g1 = (int)std::min<int64_t>((npx + 255) / 256, 4096);
-  hipLaunchKernelGGL(wide_init_kernel, dim3(g1), dim3(256), 0, s, p, st.dev);
+  hipLaunchKernelGGL(wide_init_kernel, dim3(g1), dim3(256), 0, s, p, st);
   return hipGetLastError();
 }
 
@@ -957,7 +952,7 @@ hipError_t launch_forward_wide(const TileParams& p, const LsState& st, hipStream
     return hipErrorInvalidValue;
   const int64_t npx = (int64_t)p.H * p.Wd;
   const int g1 = (int)std::min<int64_t>((npx + 255) / 256, 4096);
-  hipLaunchKernelGGL(wide_init_kernel, dim3(g1), dim3(256), 0, s, p, st.dev);
+  hipLaunchKernelGGL(wide_init_kernel, dim3(g1), dim3(256), 0, s, p, st);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const int grow = ((p.H + kLsRows - 1) / kLsRows) * ((p.Wd + kLsCols - 1) / kLsCols);

@@ -507,14 +507,6 @@ static int hip_fail(hipError_t e, const char* what) {
   return fail(BF_EHIP, std::string(what) + ": " + hipGetErrorString(e));
 }
 
-// The streamed kernels read a plan's state layout from device memory
-// (LsState::dev): a copy kept after the state buffer's last byte, `at`.
-constexpr int64_t kStateCopyBytes = ((int64_t)sizeof(LsState) + 255) & ~255LL;
-static hipError_t upload_state(LsState& st, void* base, int64_t at) {
-  st.dev = (const LsState*)((char*)base + at);
-  return hipMemcpy((char*)base + at, &st, sizeof(LsState), hipMemcpyHostToDevice);
-}
-
 }  // namespace bfgpa
 
 using namespace bfgpa;
@@ -691,7 +683,7 @@ int bf_plan(const bf_params* in, bf_plan_t** out) {
     const bool split = !wide && !grad && p.kernel == BF_GAUSS && !(p.flags & (BF_FLAG_MIRROR | BF_FLAG_MFMA_FP32)) &&
                        ls_split_supported(p.W, nblock);
     const int64_t lb = ls_state_bytes(p.height, p.width, p.W, grad, wide, split, nblock);
-    e = hipMalloc(&pl->d_ls, lb + kStateCopyBytes);
+    e = hipMalloc(&pl->d_ls, lb);
     if (e != hipSuccess) {
       if (pl->d_work) hipFree(pl->d_work);
       if (pl->d_partials) hipFree(pl->d_partials);
@@ -707,31 +699,17 @@ int bf_plan(const bf_params* in, bf_plan_t** out) {
       return hip_fail(e, "hipMemset large-support state");
     }
     pl->ls_state = ls_layout(pl->d_ls, p.height, p.width, p.W, grad, wide, split, nblock);
-    e = upload_state(pl->ls_state, pl->d_ls, lb);
-    if (e != hipSuccess) {
-      hipFree(pl->d_ls);
-      hipFree(pl->d_const);
-      delete pl;
-      return hip_fail(e, "hipMemcpy large-support state layout");
-    }
     ws += lb;
   }
   if (pl->rec) {
     const int64_t rb = rg_state_bytes(p.height, p.width);
-    e = hipMalloc(&pl->d_ls, rb + kStateCopyBytes);
+    e = hipMalloc(&pl->d_ls, rb);
     if (e != hipSuccess) {
       hipFree(pl->d_const);
       delete pl;
       return fail(BF_ENOMEM, "hipMalloc recursive-Gaussian state failed");
     }
     pl->ls_state = rg_layout(pl->d_ls, p.height, p.width);
-    e = upload_state(pl->ls_state, pl->d_ls, rb);
-    if (e != hipSuccess) {
-      hipFree(pl->d_ls);
-      hipFree(pl->d_const);
-      delete pl;
-      return hip_fail(e, "hipMemcpy recursive-Gaussian state layout");
-    }
     ws += rb;
   }
   if (bls) {
@@ -993,7 +971,7 @@ int bf_plan_volume(const bf_params* in, int32_t depth, bf_plan_t** out) {
   e = hipMemcpy(pl->d_const, h.data(), bytes, hipMemcpyHostToDevice);
   if (e != hipSuccess) { hipFree(pl->d_const); delete pl; return hip_fail(e, "hipMemcpy tables"); }
   const int64_t vb = vol_state_bytes(depth, p.height, p.width, p.W, wide);
-  e = hipMalloc(&pl->d_ls, vb + kStateCopyBytes);
+  e = hipMalloc(&pl->d_ls, vb);
   if (e == hipSuccess) {
     e = hipMemset(pl->d_ls, 0, vb);  // zero rows around the row-filtered images
     if (e != hipSuccess) hipFree(pl->d_ls);
@@ -1004,13 +982,6 @@ int bf_plan_volume(const bf_params* in, int32_t depth, bf_plan_t** out) {
     return e == hipErrorOutOfMemory ? fail(BF_ENOMEM, "hipMalloc volume state failed") : hip_fail(e, "volume state");
   }
   pl->ls_state = vol_layout(pl->d_ls, depth, p.height, p.width, p.W, &pl->vol, wide);
-  e = upload_state(pl->ls_state, pl->d_ls, vb);
-  if (e != hipSuccess) {
-    hipFree(pl->d_ls);
-    hipFree(pl->d_const);
-    delete pl;
-    return hip_fail(e, "hipMemcpy volume state layout");
-  }
   pl->info.workspace_bytes = (int64_t)bytes + vb;
   *out = pl;
   if (ost == BF_WNOGUARANTEE) set_error("order below the bound: no +-delta guarantee");

@@ -251,9 +251,8 @@ __device__ __forceinline__ void rg_load(const float* __restrict__ p, int n, floa
 
 // Row pass for orders n0 .. n0 + K - 1 of R image rows (blockDim = R * Trp,
 // Tr = ceil(width / 16)); stores the row-filtered images row-major.
-__global__ __launch_bounds__(kRgFirstThreads) void rg_first_kernel(TileParams p, const LsState* __restrict__ stp, int K, int src, int R,
+__global__ __launch_bounds__(kRgFirstThreads) void rg_first_kernel(TileParams p, LsState st, int K, int src, int R,
                                                                    int Tr, int Trp) {
-  const LsState& st = *stp;
   extern __shared__ float lds[];
   const int nW = Trp > 64 ? Trp >> 6 : 1;
   float* tot = lds;  // 2 (parity) x R x nW x 8
@@ -277,7 +276,7 @@ __global__ __launch_bounds__(kRgFirstThreads) void rg_first_kernel(TileParams p,
   for (int k = 0; k < K; ++k) {
     float y[kRgChunk];
     rg_filter_chunk<kRgChunk>(Fh, Fn, y, t, Trp, cf, ln, p.rg_tab, tot + (k & 1) * 8 * R * nW + 8 * nW * rr);
-    float* Hk = st.H[k] + g0;
+    float* Hk = st.h(k) + g0;
     if (nok == kRgChunk) {
 #pragma unroll
       for (int g = 0; g < 4; ++g) ((rg_f4*)Hk)[g] = rg_f4{y[4 * g], y[4 * g + 1], y[4 * g + 2], y[4 * g + 3]};
@@ -297,13 +296,12 @@ __global__ __launch_bounds__(kRgFirstThreads) void rg_first_kernel(TileParams p,
 }
 
 // H[z] (row-major) -> HT[z] (column-major), 64 x 64 tiles through LDS.
-__global__ __launch_bounds__(256) void rg_transpose_kernel(const LsState* __restrict__ stp, int H, int Wd) {
-  const LsState& st = *stp;
+__global__ __launch_bounds__(256) void rg_transpose_kernel(LsState st, int H, int Wd) {
   __shared__ float T[64][65];
   const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
   const int r0 = blockIdx.y * 64, c0 = blockIdx.x * 64;
-  const float* src = st.H[blockIdx.z];
-  float* dst = st.HT[blockIdx.z];
+  const float* src = st.h(blockIdx.z);
+  float* dst = st.ht(blockIdx.z);
   for (int j = ty; j < 64; j += 4) {
     const int r = r0 + j, c = c0 + tx;
     if (r < H && c < Wd) T[j][tx] = src[(int64_t)r * st.pitch + c];
@@ -319,9 +317,8 @@ __global__ __launch_bounds__(256) void rg_transpose_kernel(const LsState* __rest
 // of R image columns (blockDim = R * Trp, Tr = ceil(height / 8)), folded
 // into the per-pixel sums (column-major state).  Chunks of 8 samples keep
 // the float64 sums of a thread's pixels within 128 VGPRs.
-__global__ __launch_bounds__(kRgSecondThreads) void rg_second_kernel(TileParams p, const LsState* __restrict__ stp, int n0, int K, int R,
+__global__ __launch_bounds__(kRgSecondThreads) void rg_second_kernel(TileParams p, LsState st, int n0, int K, int R,
                                                                      int Tr, int Trp) {
-  const LsState& st = *stp;
   constexpr int C = kRgChunk2;
   extern __shared__ float lds[];
   const int nW = Trp > 64 ? Trp >> 6 : 1;
@@ -341,16 +338,16 @@ __global__ __launch_bounds__(kRgSecondThreads) void rg_second_kernel(TileParams 
   const int64_t hoff = (int64_t)(live ? c : 0) * st.tpitch + r0;
   float xn[C];
   float nn = 0.f;
-  rg_load<C>(st.HT[0] + hoff, nok, xn);
-  if (nxt) nn = st.HT[0][hoff + C];
+  rg_load<C>(st.ht(0) + hoff, nok, xn);
+  if (nxt) nn = st.ht(0)[hoff + C];
   for (int k = 0; k < K; ++k) {
     float x[C], y[C];
 #pragma unroll
     for (int i = 0; i < C; ++i) x[i] = xn[i];
     const float xnext = nn;
     if (k + 1 < K) {
-      rg_load<C>(st.HT[k + 1] + hoff, nok, xn);
-      if (nxt) nn = st.HT[k + 1][hoff + C];
+      rg_load<C>(st.ht(k + 1) + hoff, nok, xn);
+      if (nxt) nn = st.ht(k + 1)[hoff + C];
     }
     rg_filter_chunk<C>(x, xnext, y, t, Trp, cf, ln, p.rg_tab, tot + (k & 1) * 8 * R * nW + 8 * nW * rr);
     const int n = n0 + k;
@@ -362,8 +359,7 @@ __global__ __launch_bounds__(kRgSecondThreads) void rg_second_kernel(TileParams 
 }
 
 // F^_0 = e^{-x^2/2} and y (row-major), a_0, z and zero sums (column-major).
-__global__ __launch_bounds__(256) void rg_init_kernel(TileParams p, const LsState* __restrict__ stp) {
-  const LsState& st = *stp;
+__global__ __launch_bounds__(256) void rg_init_kernel(TileParams p, LsState st) {
   __shared__ float Ta[32][33], Tz[32][33];
   const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
   const int r0 = blockIdx.y * 32, c0 = blockIdx.x * 32;
@@ -391,8 +387,7 @@ __global__ __launch_bounds__(256) void rg_init_kernel(TileParams p, const LsStat
 }
 
 // eq. (PbyQ) from the column-major sums, stored row-major.
-__global__ __launch_bounds__(256) void rg_final_kernel(TileParams p, const LsState* __restrict__ stp) {
-  const LsState& st = *stp;
+__global__ __launch_bounds__(256) void rg_final_kernel(TileParams p, LsState st) {
   __shared__ float To[32][33];
   const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
   const int r0 = blockIdx.y * 32, c0 = blockIdx.x * 32;
@@ -443,8 +438,10 @@ LsState rg_layout(void* base, int H, int Wd) {
   st.F[0] = (float*)take(pitch * H * 4);
   st.F[1] = (float*)take(pitch * H * 4);
   st.Y = (float*)take(pitch * H * 4);
-  for (int k = 0; k < kLsBlockSmall; ++k) st.H[k] = (float*)take(pitch * H * 4);
-  for (int k = 0; k < kLsBlockSmall; ++k) st.HT[k] = (float*)take((int64_t)Wd * tpitch * 4);
+  st.h_stride = ((pitch * H * 4 + 255) & ~255LL) / 4;
+  st.H0 = (float*)take(kLsBlockSmall * 4 * st.h_stride);
+  st.ht_stride = (((int64_t)Wd * tpitch * 4 + 255) & ~255LL) / 4;
+  st.HT0 = (float*)take(kLsBlockSmall * 4 * st.ht_stride);
   st.a = (float*)take(npx * 4);
   st.ap = (float*)take(npx * 4);
   st.z = (float*)take(npx * 4);
@@ -473,19 +470,19 @@ hipError_t launch_forward_rg(const TileParams& p, const LsState& st, hipStream_t
   const size_t lds1 = (size_t)(16 * R1 * nW1) * 4;
   const size_t lds2 = (size_t)(16 * R2 * nW2) * 4;
   const dim3 tiles((p.Wd + 31) / 32, (p.H + 31) / 32);
-  hipLaunchKernelGGL(rg_init_kernel, tiles, dim3(256), 0, s, p, st.dev);
+  hipLaunchKernelGGL(rg_init_kernel, tiles, dim3(256), 0, s, p, st);
   int src = 0;
   for (int n0 = 0; n0 <= p.N; n0 += kLsBlockSmall) {
     const int K = std::min(kLsBlockSmall, p.N + 1 - n0);
-    hipLaunchKernelGGL(rg_first_kernel, dim3((p.H + R1 - 1) / R1), dim3(R1 * Trp1), lds1, s, p, st.dev, K, src, R1, Tr1,
+    hipLaunchKernelGGL(rg_first_kernel, dim3((p.H + R1 - 1) / R1), dim3(R1 * Trp1), lds1, s, p, st, K, src, R1, Tr1,
                        Trp1);
-    hipLaunchKernelGGL(rg_transpose_kernel, dim3((p.Wd + 63) / 64, (p.H + 63) / 64, K), dim3(256), 0, s, st.dev, p.H,
+    hipLaunchKernelGGL(rg_transpose_kernel, dim3((p.Wd + 63) / 64, (p.H + 63) / 64, K), dim3(256), 0, s, st, p.H,
                        p.Wd);
-    hipLaunchKernelGGL(rg_second_kernel, dim3((p.Wd + R2 - 1) / R2), dim3(R2 * Trp2), lds2, s, p, st.dev, n0, K, R2, Tr2,
+    hipLaunchKernelGGL(rg_second_kernel, dim3((p.Wd + R2 - 1) / R2), dim3(R2 * Trp2), lds2, s, p, st, n0, K, R2, Tr2,
                        Trp2);
     src ^= 1;
   }
-  hipLaunchKernelGGL(rg_final_kernel, tiles, dim3(256), 0, s, p, st.dev);
+  hipLaunchKernelGGL(rg_final_kernel, tiles, dim3(256), 0, s, p, st);
   return hipGetLastError();
 }
 

@@ -28,8 +28,7 @@ constexpr int kVolDepth = 8;   // voxels per thread along the depth axis
 
 // Column FIR inside each slice for orders n0 .. n0 + K - 1.  Thread: column
 // c = tid % 64 of the tile, output rows 16 (tid / 64) .. + 15.
-__global__ __launch_bounds__(256) void vol_cols_kernel(TileParams p, const LsState* __restrict__ stp, VolBufs g, int K, int Hs) {
-  const LsState& st = *stp;
+__global__ __launch_bounds__(256) void vol_cols_kernel(TileParams p, LsState st, VolBufs g, int K, int Hs) {
   extern __shared__ float lds[];
   const int W = p.W;
   const int rows = kVolTile + 2 * W;
@@ -42,7 +41,7 @@ __global__ __launch_bounds__(256) void vol_cols_kernel(TileParams p, const LsSta
   for (int k = 0; k < K; ++k) {
     __syncthreads();  // the previous order's reads are done
     // stage rows R0 - W .. R0 + 63 + W (row-filtered images carry W zero rows above)
-    const float* Hk = st.H[k];
+    const float* Hk = st.h(k);
     for (int i = rg; i < rows; i += 4) {
       const int Rp = R0 + i;  // padded row = stacked row R0 - W + i, plus W
       lds[i * kVolTile + c] = (c0 + c < p.Wd) ? Hk[(int64_t)Rp * st.pitch + c0 + c] : 0.f;
@@ -73,9 +72,8 @@ __global__ __launch_bounds__(256) void vol_cols_kernel(TileParams p, const LsSta
 // plane, voxels at depths d0 .. d0 + kVolDepth - 1.
 // WIDE: the wide-range float64 states (see ls_rows_x3_kernel), folded without the X of eq. (P)
 template <bool WIDE>
-__global__ __launch_bounds__(256) void vol_depth_kernel(TileParams p, const LsState* __restrict__ stp, VolBufs g, int n0, int K, int Hs,
+__global__ __launch_bounds__(256) void vol_depth_kernel(TileParams p, LsState st, VolBufs g, int n0, int K, int Hs,
                                                         int D) {
-  const LsState& st = *stp;
   const int64_t plane = (int64_t)Hs * p.Wd;
   const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
   const int d0 = blockIdx.y * kVolDepth;
@@ -143,11 +141,11 @@ hipError_t launch_forward_vol(const TileParams& p, const LsState& st, const VolB
     const int K = std::min(kLsBlockSmall, p.N + 1 - n0);
     e = p.wide ? launch_rows_x3_wide(p, st, n0, K, src, s) : ls_launch_rows(p, st, n0, K, src, s);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(vol_cols_kernel, dim3(tiles), dim3(256), clds, s, p, st.dev, g, K, Hs);
+    hipLaunchKernelGGL(vol_cols_kernel, dim3(tiles), dim3(256), clds, s, p, st, g, K, Hs);
     if (p.wide)
-      hipLaunchKernelGGL(vol_depth_kernel<true>, gdep, dim3(256), 0, s, p, st.dev, g, n0, K, Hs, D);
+      hipLaunchKernelGGL(vol_depth_kernel<true>, gdep, dim3(256), 0, s, p, st, g, n0, K, Hs, D);
     else
-      hipLaunchKernelGGL(vol_depth_kernel<false>, gdep, dim3(256), 0, s, p, st.dev, g, n0, K, Hs, D);
+      hipLaunchKernelGGL(vol_depth_kernel<false>, gdep, dim3(256), 0, s, p, st, g, n0, K, Hs, D);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     src ^= 1;
