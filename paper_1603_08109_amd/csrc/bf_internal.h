@@ -133,10 +133,14 @@ struct BlsState {
   int64_t pitch;               // row pitch (floats) of the image-shaped buffers
   float* A[2];                 // scaled coefficients a_m (double-buffered)
   float* B[2];                 // b_m = a_{m-1} r_m (double-buffered)
-  float* R[2 * kBlsBlock];     // row-filtered adjoint images: taps (R[k]), then d^2 taps (R[kBlsBlock + k])
+  float* R0;                   // row-filtered adjoint images with the taps, image k at r(k)
+  float* R20;                  // with the d^2 taps (sigma_s gradient), image k at r2(k), or null
+  int64_t r_stride;            // floats from one image to the next (equal-sized, consecutive)
   float *fc, *fp;              // F~_m and F~_{m-1} at each pixel
   double *dx, *dss;            // per-pixel sums of the image and sigma_s gradients
   int block;                   // orders per block (row-filtered images allocated per tap set)
+  __host__ __device__ float* r(int k) const { return R0 + k * r_stride; }
+  __host__ __device__ float* r2(int k) const { return R20 + k * r_stride; }
 };
 
 // Kernel-shape variants (compile-time register budgets).

@@ -179,7 +179,7 @@ __global__ __launch_bounds__(kBlsThreads) void bls_rows_kernel(TileParams pk, Bl
         box1d<8>(Lc + r * RWp + c8, 1, 2 * W + 1, o);
       const int gr = r0 + r, gc = c0 + c8;
       if (gr < p.H && gc < p.Wd) {
-        float* d = st.R[k] + (int64_t)(W + gr) * st.pitch + gc;  // W zero rows above the image
+        float* d = st.r(k) + (int64_t)(W + gr) * st.pitch + gc;  // W zero rows above the image
         if (gc + 8 <= p.Wd) {
           *(float4*)d = make_float4(o[0], o[1], o[2], o[3]);
           *(float4*)(d + 4) = make_float4(o[4], o[5], o[6], o[7]);
@@ -196,8 +196,8 @@ __global__ __launch_bounds__(kBlsThreads) void bls_rows_kernel(TileParams pk, Bl
     for (int bb = 0; bb < 2; ++bb) acc[bb] = acc2[bb] = mf4{0.f, 0.f, 0.f, 0.f};
     toeplitz_rows<2>(Lc, RWp, cbase, Tt, KK, acc);
     if (SIGS) toeplitz_rows<2>(Lc, RWp, cbase, Tt2, KK, acc2);
-    float* R1 = st.R[k] + (int64_t)W * st.pitch;  // W zero rows above the image
-    float* R2 = st.R[kBlsBlock + k] + (int64_t)W * st.pitch;
+    float* R1 = st.r(k) + (int64_t)W * st.pitch;  // W zero rows above the image
+    float* R2 = st.r2(k) + (int64_t)W * st.pitch;
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       if (orow + v < p.H) {
@@ -275,8 +275,8 @@ __global__ __launch_bounds__(kBlsThreads) void bls_cols_kernel(TileParams pk, Bl
   for (int k = 0; k < K; ++k) {
     const int m = n0 + k;
     __syncthreads();
-    stage_rows_lds<kBlsThreads>(st.R[k] + (int64_t)tr0 * st.pitch + c0, st.pitch, S1, rows);
-    if (SIGS) stage_rows_lds<kBlsThreads>(st.R[kBlsBlock + k] + (int64_t)tr0 * st.pitch + c0, st.pitch, S2, rows);
+    stage_rows_lds<kBlsThreads>(st.r(k) + (int64_t)tr0 * st.pitch + c0, st.pitch, S1, rows);
+    if (SIGS) stage_rows_lds<kBlsThreads>(st.r2(k) + (int64_t)tr0 * st.pitch + c0, st.pitch, S2, rows);
     __syncthreads();
     mf4 fa[2], gs[2];
 #pragma unroll
@@ -349,7 +349,7 @@ __global__ __launch_bounds__(kBlsThreads) void bls_cols_box_kernel(TileParams pk
   for (int k = 0; k < K; ++k) {
     const int m = n0 + k;
     __syncthreads();
-    stage_rows_lds<kBlsThreads>(st.R[k] + (int64_t)tr0 * st.pitch + c0, st.pitch, S1, rows);
+    stage_rows_lds<kBlsThreads>(st.r(k) + (int64_t)tr0 * st.pitch + c0, st.pitch, S1, rows);
     __syncthreads();
     float fa[8];
     box1d<8>(S1 + 8 * g * 64 + c, 64, 2 * W + 1, fa);  // rows 8g + v .. 8g + v + 2W of the window
@@ -453,8 +453,9 @@ BlsState bls_layout(void* base, int H, int Wd, int W, bool sigs, int nblock) {
   st.pitch = pitch;
   for (int i = 0; i < 2; ++i) st.A[i] = (float*)take(img * 4);
   for (int i = 0; i < 2; ++i) st.B[i] = (float*)take(img * 4);
-  for (int k = 0; k < nblock; ++k) st.R[k] = (float*)take(himg * 4);
-  for (int k = 0; sigs && k < nblock; ++k) st.R[kBlsBlock + k] = (float*)take(himg * 4);
+  st.r_stride = ((himg * 4 + 255) & ~255LL) / 4;  // take()'s rounding
+  st.R0 = (float*)take(nblock * 4 * st.r_stride);
+  st.R20 = sigs ? (float*)take(nblock * 4 * st.r_stride) : nullptr;
   st.fc = (float*)take(npx * 4);
   st.fp = (float*)take(npx * 4);
   st.dx = (double*)take(npx * 8);
@@ -465,7 +466,7 @@ BlsState bls_layout(void* base, int H, int Wd, int W, bool sigs, int nblock) {
 hipError_t launch_backward_ls(const TileParams& p, const BlsState& st, bool sigs, double* partials,
                               double* grad_sigma, hipStream_t s) {
   if (p.H <= 0 || p.Wd <= 0) return hipSuccess;
-  if (st.block <= 0 || st.block > kBlsBlock || (sigs && !st.R[kBlsBlock])) return hipErrorInvalidValue;
+  if (st.block <= 0 || st.block > kBlsBlock || (sigs && !st.R20)) return hipErrorInvalidValue;
   if (!bls_supported(p.W, sigs)) return hipErrorInvalidValue;
   const int64_t npx = (int64_t)p.H * p.Wd;
   const int g1 = (int)std::min<int64_t>((npx + kThreads - 1) / kThreads, 4096);
