@@ -109,6 +109,7 @@ struct LsState {
   __host__ __device__ float* ht(int k) const { return HT0 + k * ht_stride; }
   __host__ __device__ uint16_t* hs(int k) const { return Hs0 + k * hs_stride; }
 };
+static_assert(sizeof(LsState) <= 256, "every streamed launch takes the state by value");
 
 // Rows of one row-filtered image of the streamed passes: the height padded
 // to a multiple of 64, W zero rows above, and W + 40 zero rows below (a box
@@ -142,6 +143,7 @@ struct BlsState {
   __host__ __device__ float* r(int k) const { return R0 + k * r_stride; }
   __host__ __device__ float* r2(int k) const { return R20 + k * r_stride; }
 };
+static_assert(sizeof(BlsState) <= 256, "every streamed adjoint launch takes the state by value");
 
 // Kernel-shape variants (compile-time register budgets).
 struct Variant {
@@ -171,9 +173,10 @@ inline int64_t region_floats_bwd(int TY, int W) {
 // Launchers (bf_kernels.hip).  Return hipError_t.
 hipError_t launch_forward(const TileParams& p, int variant, bool acc64, bool save,
                           hipStream_t s);
-// the plain fused forward compiled for a fixed support W = 1 .. 21 (bf_fused_w.hip)
+// the fused forward (plain, or keeping the adjoint's state) compiled for a
+// fixed support W = 1 .. 21 (bf_fused_w.hip)
 bool fixed_w_available(int W, int variant);
-hipError_t launch_forward_fixed_w(const TileParams& p, hipStream_t s);
+hipError_t launch_forward_fixed_w(const TileParams& p, bool save, hipStream_t s);
 // the fused adjoint tile compiled for a fixed support W = 1 .. 17 (its
 // 16-row variant, the one the planner picks there; bf_fused_w_bwd.hip)
 bool fixed_w_bwd_available(int W, int variant);

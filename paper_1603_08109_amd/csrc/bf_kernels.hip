@@ -84,8 +84,8 @@ hipError_t launch_forward(const TileParams& p, int variant, bool acc64, bool sav
   if (region_floats(p.TY, p.W) > (int64_t)kThreads * v.mreg) return hipErrorInvalidValue;
   if (forward_lds_bytes(p.TY, p.W) > max_lds_bytes()) return hipErrorInvalidValue;
   if (p.H <= 0 || p.Wd <= 0) return hipSuccess;
-  // the plain forward at a support compiled as a constant (bf_fused_w.hip)
-  if (acc64 && !save && fixed_w_available(p.W, variant)) return launch_forward_fixed_w(p, s);
+  // the float64-sum forward at a support compiled as a constant (bf_fused_w.hip)
+  if (acc64 && fixed_w_available(p.W, variant)) return launch_forward_fixed_w(p, save, s);
   return p.kt == BF_BOX ? launch_fwd_k<BF_BOX>(p, variant, acc64, save, s)
                         : launch_fwd_k<BF_GAUSS>(p, variant, acc64, save, s);
 }
