@@ -223,7 +223,7 @@ hipError_t ls_launch_final(const TileParams& p, const LsState& st, hipStream_t s
 // Video / volume data: D slices of Hs x Wd stacked as one image of D Hs rows.
 constexpr int kVolMaxW = 32;
 struct VolBufs {
-  float* G[kLsBlock];  // per order of a block: the row- and column-filtered volume
+  float* G[kLsBlockSmall];  // per order of a block (16 orders): the row- and column-filtered volume
 };
 int64_t vol_state_bytes(int D, int Hs, int Wd, int W, bool wide = false);
 LsState vol_layout(void* base, int D, int Hs, int Wd, int W, VolBufs* g, bool wide = false);

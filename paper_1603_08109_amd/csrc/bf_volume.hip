@@ -71,7 +71,11 @@ __global__ __launch_bounds__(256) void vol_cols_kernel(TileParams p, LsState st,
 // FIR across slices and the fold into eqs. (P), (Q): thread q of the slice
 // plane, voxels at depths d0 .. d0 + kVolDepth - 1.
 // WIDE: the wide-range float64 states (see ls_rows_x3_kernel), folded without the X of eq. (P)
-template <bool WIDE>
+// WC > 0: the support W = WC with zero extension, compiled as a constant: the
+// kVolDepth + 2W samples of the thread's column are loaded once per order
+// into registers (zeros outside the volume) and every output sums its 2W + 1
+// of them in the same order as the runtime-W loop, so the sums are the same.
+template <bool WIDE, int WC = 0>
 __global__ __launch_bounds__(256) void vol_depth_kernel(TileParams p, LsState st, VolBufs g, int n0, int K, int Hs,
                                                         int D) {
   const int64_t plane = (int64_t)Hs * p.Wd;
@@ -89,6 +93,25 @@ __global__ __launch_bounds__(256) void vol_depth_kernel(TileParams p, LsState st
     const int n = n0 + k;
     const float in1 = p.inv_tab[n + 1];
     const double g1 = WIDE ? p.isq[n + 1] : 0.0, sn = WIDE ? p.sq[n] : 0.0;
+    if constexpr (WC > 0) {
+      float win[kVolDepth + 2 * WC];
+#pragma unroll
+      for (int i = 0; i < kVolDepth + 2 * WC; ++i) {
+        const int d = d0 - WC + i;
+        win[i] = (live && d >= 0 && d < D) ? Gk[(int64_t)d * plane] : 0.f;
+      }
+#pragma unroll
+      for (int t = 0; t < kVolDepth; ++t) {
+        float acc = 0.f;
+#pragma unroll
+        for (int a = 0; a <= 2 * WC; ++a) acc += tz[a] * win[t + a];
+        if constexpr (WIDE)
+          px.fold(t, n, p.N, acc, g1, sn);
+        else
+          px.fold(t, n, p.N, acc, in1);
+      }
+      continue;
+    }
 #pragma unroll
     for (int t = 0; t < kVolDepth; ++t) {
       const int d = d0 + t;
@@ -126,6 +149,29 @@ LsState vol_layout(void* base, int D, int Hs, int Wd, int W, VolBufs* g, bool wi
   return st;
 }
 
+template <bool WIDE>
+static hipError_t launch_vol_depth_w(const TileParams& p, const LsState& st, const VolBufs& g, int n0, int K,
+                                     int Hs, int D, dim3 grid, hipStream_t s) {
+  if (!p.mirror) {
+    switch (p.W) {
+#define BF_VD_CASE(w) \
+  case w: hipLaunchKernelGGL((vol_depth_kernel<WIDE, w>), grid, dim3(256), 0, s, p, st, g, n0, K, Hs, D); return hipSuccess;
+      BF_VD_CASE(1) BF_VD_CASE(2) BF_VD_CASE(3) BF_VD_CASE(4) BF_VD_CASE(5) BF_VD_CASE(6) BF_VD_CASE(7) BF_VD_CASE(8)
+#undef BF_VD_CASE
+      default: break;
+    }
+  }
+  hipLaunchKernelGGL((vol_depth_kernel<WIDE, 0>), grid, dim3(256), 0, s, p, st, g, n0, K, Hs, D);
+  return hipSuccess;
+}
+
+// the depth pass: compiled for W = 1 .. 8 with zero extension, else the runtime-W loop
+static hipError_t launch_vol_depth(const TileParams& p, const LsState& st, const VolBufs& g, int n0, int K, int Hs,
+                                   int D, dim3 grid, hipStream_t s) {
+  return p.wide ? launch_vol_depth_w<true>(p, st, g, n0, K, Hs, D, grid, s)
+                : launch_vol_depth_w<false>(p, st, g, n0, K, Hs, D, grid, s);
+}
+
 hipError_t launch_forward_vol(const TileParams& p, const LsState& st, const VolBufs& g, int D, int Hs,
                               hipStream_t s) {
   if (p.H <= 0 || p.Wd <= 0) return hipSuccess;
@@ -142,10 +188,8 @@ hipError_t launch_forward_vol(const TileParams& p, const LsState& st, const VolB
     e = p.wide ? launch_rows_x3_wide(p, st, n0, K, src, s) : ls_launch_rows(p, st, n0, K, src, s);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(vol_cols_kernel, dim3(tiles), dim3(256), clds, s, p, st, g, K, Hs);
-    if (p.wide)
-      hipLaunchKernelGGL(vol_depth_kernel<true>, gdep, dim3(256), 0, s, p, st, g, n0, K, Hs, D);
-    else
-      hipLaunchKernelGGL(vol_depth_kernel<false>, gdep, dim3(256), 0, s, p, st, g, n0, K, Hs, D);
+    e = launch_vol_depth(p, st, g, n0, K, Hs, D, gdep, s);
+    if (e != hipSuccess) return e;
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     src ^= 1;
