@@ -20,6 +20,7 @@
 
 #include "bf_device.h"
 #include "bf_internal.h"
+#include "bf_toeplitz.h"
 
 namespace bfgpa {
 
@@ -38,21 +39,26 @@ __global__ __launch_bounds__(256) void vol_cols_kernel(TileParams p, LsState st,
   const int c = threadIdx.x & 63;
   const int rg = threadIdx.x >> 6;
   const float* tz = p.taps + kTapPad;  // tz[a + W] = w1(a)
+  // the first row of the slice that holds this thread's first output row (its
+  // rows advance one at a time, so each step starts the next slice at most once)
+  const int Rt = R0 + 16 * rg;
+  const int dfirst = (Rt / Hs) * Hs;
   for (int k = 0; k < K; ++k) {
     __syncthreads();  // the previous order's reads are done
-    // stage rows R0 - W .. R0 + 63 + W (row-filtered images carry W zero rows above)
-    const float* Hk = st.h(k);
-    for (int i = rg; i < rows; i += 4) {
-      const int Rp = R0 + i;  // padded row = stacked row R0 - W + i, plus W
-      lds[i * kVolTile + c] = (c0 + c < p.Wd) ? Hk[(int64_t)Rp * st.pitch + c0 + c] : 0.f;
-    }
+    // stage rows R0 - W .. R0 + 63 + W (row-filtered images carry W zero rows
+    // above; padded row R0 + i is stacked row R0 - W + i), rounded up to whole
+    // groups of four by direct-to-LDS loads (the zero rows below cover them;
+    // columns past the image are never written by the row pass and stay zero)
+    stage_rows_lds<256>(st.h(k) + (int64_t)R0 * st.pitch + c0, st.pitch, lds, (rows + 3) & ~3);
     __syncthreads();
     float* Gk = g.G[k];
+    int dcur = dfirst;
 #pragma unroll 4
     for (int j = 0; j < 16; ++j) {
-      const int R = R0 + 16 * rg + j;  // stacked row
+      const int R = Rt + j;  // stacked row
+      if (R >= dcur + Hs) dcur += Hs;
       if (R >= p.H || c0 + c >= p.Wd) continue;
-      const int d0 = (R / Hs) * Hs;  // first row of this slice
+      const int d0 = dcur;  // first row of this slice
       float acc = 0.f;
       if (p.mirror) {
         // reflected rows stay in this slice and within W of R: inside the staged window
@@ -180,7 +186,7 @@ hipError_t launch_forward_vol(const TileParams& p, const LsState& st, const VolB
   hipError_t e = p.wide ? wide_launch_init(p, st, s) : ls_launch_init(p, st, s);
   if (e != hipSuccess) return e;
   const int tiles = ((p.H + kVolTile - 1) / kVolTile) * ((p.Wd + kVolTile - 1) / kVolTile);
-  const size_t clds = (size_t)(kVolTile + 2 * p.W) * kVolTile * 4;
+  const size_t clds = (size_t)((kVolTile + 2 * p.W + 3) & ~3) * kVolTile * 4;
   const dim3 gdep((unsigned)((int64_t)Hs * p.Wd + 255) / 256, (D + kVolDepth - 1) / kVolDepth);
   int src = 0;
   for (int n0 = 0; n0 <= p.N; n0 += kLsBlockSmall) {
