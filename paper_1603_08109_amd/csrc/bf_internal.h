@@ -213,7 +213,8 @@ int64_t ls_cols_x3s_lds_bytes(int W);
 // outputs split, the column pass stages the planes straight into LDS
 hipError_t launch_rows_x3_split(const TileParams& p, const LsState& st, int n0, int K, int src, int grid,
                                 hipStream_t s);
-hipError_t launch_cols_x3p(const TileParams& p, const LsState& st, int n0, int K, hipStream_t s);
+// fin: the block holds order N, and the pass writes eq. (PbyQ) in place of the state
+hipError_t launch_cols_x3p(const TileParams& p, const LsState& st, int n0, int K, bool fin, hipStream_t s);
 
 // pieces of the streamed sequence (an image of p.H rows)
 hipError_t ls_launch_init(const TileParams& p, const LsState& st, hipStream_t s);

@@ -1031,7 +1031,7 @@ hipError_t launch_forward_ls(const TileParams& p, const LsState& st, bool save, 
       // W = 30 17.24 / 17.17, W = 33 17.9 / 17.3, W = 39 18.8 / 17.3.
       const bool x3s = !save && p.W >= 31 && (16 + 2 * p.W + 31) / 32 <= 6 && st.hbytes < (1LL << 31);
       if (split) {
-        e = launch_cols_x3p(p, st, n0, K, s);
+        e = launch_cols_x3p(p, st, n0, K, n0 + K > p.N, s);  // the last block writes eq. (PbyQ) itself
       } else if (x3s) {
         e = launch_cols_x3s(p, st, n0, K, s);
       } else if (p.W >= 40) {
@@ -1065,6 +1065,7 @@ hipError_t launch_forward_ls(const TileParams& p, const LsState& st, bool save, 
     if (e != hipSuccess) return e;
     src ^= 1;
   }
+  if (split && !box_strip) return hipSuccess;
   hipLaunchKernelGGL(ls_final_kernel, dim3(g1), dim3(kThreads), 0, s, p, st);
   return hipGetLastError();
 }

@@ -768,8 +768,10 @@ bool ls_split_supported(int W, int nblock) {
          ls_cols_x3p_lds_bytes(W) <= max_lds_bytes();
 }
 
+// fin: the block holds order N, so instead of the per-pixel state the kernel
+// writes eq. (PbyQ), out = sigma_r X P / Q + c (in float64, as ls_final_kernel).
 template <int S>
-__global__ __launch_bounds__(kX3sThreads) void ls_cols_x3p_kernel(TileParams p, LsState st, int n0, int K) {
+__global__ __launch_bounds__(kX3sThreads) void ls_cols_x3p_kernel(TileParams p, LsState st, int n0, int K, int fin) {
   using G = X3pGeom<S>;
   static_assert(G::GROUPS % 4 == 0, "four groups per load");
   constexpr int NLOADS = 3 * G::GROUPS / 4;         // loads of 64 lanes per order
@@ -858,6 +860,22 @@ __global__ __launch_bounds__(kX3sThreads) void ls_cols_x3p_kernel(TileParams p, 
 #pragma unroll
       for (int v = 0; v < 4; ++v) px.fold(4 * b + v, n, p.N, acc[b][v], in1);
   }
+  if (fin) {
+    float* out = p.dyn ? p.dyn->out : p.out;
+    const int64_t out_pitch = p.dyn ? p.dyn->out_pitch : p.out_pitch;
+    const double X = (double)p.X;
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int r = pr0 + 32 * b + v;
+        if (out && r < p.H && pc < p.Wd) {
+          const double ratio = X * px.P[4 * b + v] / px.Q[4 * b + v];
+          out[(int64_t)r * out_pitch + pc] = (float)((double)p.sigma_r * ratio + (double)p.center);
+        }
+      }
+    return;
+  }
 #pragma unroll
   for (int b = 0; b < 2; ++b) {
     const int nr = pc < p.Wd ? max(0, min(4, p.H - (pr0 + 32 * b))) : 0;
@@ -866,7 +884,7 @@ __global__ __launch_bounds__(kX3sThreads) void ls_cols_x3p_kernel(TileParams p, 
 }
 
 template <int S>
-static hipError_t cols_x3p_s(const TileParams& p, const LsState& st, int n0, int K, hipStream_t s) {
+static hipError_t cols_x3p_s(const TileParams& p, const LsState& st, int n0, int K, bool fin, hipStream_t s) {
   static bool attr = false;
   const int64_t lb = ls_cols_x3p_lds_bytes(p.W);
   if (!attr) {
@@ -876,23 +894,24 @@ static hipError_t cols_x3p_s(const TileParams& p, const LsState& st, int n0, int
     attr = true;
   }
   const int grid = ((p.H + kX3pRows - 1) / kX3pRows) * ((p.Wd + kX3pCols - 1) / kX3pCols);
-  hipLaunchKernelGGL((ls_cols_x3p_kernel<S>), dim3(grid), dim3(kX3sThreads), (size_t)lb, s, p, st, n0, K);
+  hipLaunchKernelGGL((ls_cols_x3p_kernel<S>), dim3(grid), dim3(kX3sThreads), (size_t)lb, s, p, st, n0, K,
+                     fin ? 1 : 0);
   return hipGetLastError();
 }
 
-hipError_t launch_cols_x3p(const TileParams& p, const LsState& st, int n0, int K, hipStream_t s) {
+hipError_t launch_cols_x3p(const TileParams& p, const LsState& st, int n0, int K, bool fin, hipStream_t s) {
   if (!st.Hs0 || !ls_split_supported(p.W, st.block) || (st.hs_plane + 512 * st.pitch) * 2 >= (1LL << 31) ||
       p.mirror)
     return hipErrorInvalidValue;
   switch (x3p_steps(p.W)) {
-    case 1: return cols_x3p_s<1>(p, st, n0, K, s);
-    case 2: return cols_x3p_s<2>(p, st, n0, K, s);
-    case 3: return cols_x3p_s<3>(p, st, n0, K, s);
-    case 4: return cols_x3p_s<4>(p, st, n0, K, s);
-    case 5: return cols_x3p_s<5>(p, st, n0, K, s);
-    case 6: return cols_x3p_s<6>(p, st, n0, K, s);
-    case 7: return cols_x3p_s<7>(p, st, n0, K, s);
-    case 8: return cols_x3p_s<8>(p, st, n0, K, s);
+    case 1: return cols_x3p_s<1>(p, st, n0, K, fin, s);
+    case 2: return cols_x3p_s<2>(p, st, n0, K, fin, s);
+    case 3: return cols_x3p_s<3>(p, st, n0, K, fin, s);
+    case 4: return cols_x3p_s<4>(p, st, n0, K, fin, s);
+    case 5: return cols_x3p_s<5>(p, st, n0, K, fin, s);
+    case 6: return cols_x3p_s<6>(p, st, n0, K, fin, s);
+    case 7: return cols_x3p_s<7>(p, st, n0, K, fin, s);
+    case 8: return cols_x3p_s<8>(p, st, n0, K, fin, s);
     default: return hipErrorInvalidValue;
   }
 }
