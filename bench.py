@@ -253,7 +253,8 @@ def summarize(dirpath, sweep_settings):
              "launch (`gpa_forward_w_kernel`, the tile compiled for its support W <= 21, else "
              "`gpa_forward_kernel`), or the streamed sequence `ls_init`, per block of orders (64 orders: "
              "`ls_rows_x3` writing split outputs + `ls_cols_x3p` for the Gaussian; "
-             "32, 16 or 8 orders: `ls_box_strip` for the box), `ls_final`.",
+             "32, 16 or 8 orders: `ls_box_strip` for the box), and `ls_final` for the box (the Gaussian's "
+             "last column pass writes eq. (PbyQ) itself).",
              "", "| kernel | calls | total ms | avg us | % |", "|---|---|---|---|---|"]
     for k, v in sorted(per_kernel.items(), key=lambda kv: -sum(kv[1])):
         lines.append(f"| `{k}` | {len(v)} | {sum(v) / 1e3:.2f} | {sum(v) / len(v):.1f} | "
