@@ -214,21 +214,30 @@ def _short(name):
 
 def _calls(dispatches):
     """Group time-ordered library dispatches into forward calls: one fused
-    launch, or the streamed sequence from ls_init to ls_final."""
+    launch, or the streamed sequence from ls_init up to ls_final (the box) or
+    to the next call's first launch (the Gaussian, whose last column pass
+    writes the output itself)."""
     calls, cur = [], None
     for d in dispatches:
         n = _short(d["name"])
         if n.startswith("__amd_rocclr") or not n.replace("<", " ").split()[0].endswith("kernel"):
             continue
         if n.startswith("gpa_forward_kernel") or n.startswith("gpa_forward_w_kernel"):
+            if cur is not None:
+                calls.append(cur)
+                cur = None
             calls.append([d])
         elif n.startswith("ls_init_kernel"):
+            if cur is not None:
+                calls.append(cur)
             cur = [d]
         elif cur is not None:
             cur.append(d)
             if n.startswith("ls_final_kernel"):
                 calls.append(cur)
                 cur = None
+    if cur is not None:
+        calls.append(cur)
     return calls
 
 
