@@ -17,8 +17,12 @@
 
 namespace bfgpa {
 
+// The plain forward of the smaller register shapes asks for three waves per
+// SIMD (its registers then fit in 168 without spills; the form keeping the
+// adjoint's state would spill there and keeps two): 4096^2, sigma_r = 30,
+// Gaussian W = 9 1.81 -> 1.72 ms, box W = 10 0.93 -> 0.85 ms.
 template <int KT, int OPT, int MREG, int WC, bool SAVE>
-__global__ __launch_bounds__(kThreads, (OPT * MREG <= 256 ? 2 : 1)) void gpa_forward_w_kernel(TileParams p) {
+__global__ __launch_bounds__(kThreads, (!SAVE && OPT * MREG <= 160 ? 3 : OPT * MREG <= 256 ? 2 : 1)) void gpa_forward_w_kernel(TileParams p) {
   extern __shared__ float lds[];
   const int tile = xcd_remap(blockIdx.x, gridDim.x);
   const int ty = tile / p.tiles_x;
